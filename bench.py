@@ -1,0 +1,150 @@
+#!/usr/bin/env python3
+"""Benchmark: adaptive sampled betweenness (time to epsilon) on one MI355X.
+
+One step = one whole adaptive run through the C ABI (kad_run): vertex-diameter rule,
+pilot samples, computeDelta, then batches of sampled shortest paths (balanced
+bidirectional BFS, uniform path, interior hits) with the stopping rule checked every
+interval, on a graph already resident in HBM.
+
+Workload (default): undirected Chung-Lu graph, n = 1,000,000, power-law exponent 2.3,
+mean degree 20 (2.0e7 arcs), uint32 CSR; all-nodes task, epsilon = 0.005, delta = 0.1,
+seed 1, 65,536 samples per sampler launch.
+
+Prints one JSON line.  value = sampled shortest paths per second over the timed steps
+(pilot + main-phase samples that enter the result; samples computed past the stopping
+point of the last batch are not counted).  roofline = the sampler kernel's algorithmic
+bytes per launch over its event-timed average launch duration, against 8 TB/s.
+cpu_baseline = the CPU oracle on a bounded sample of the same workload.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(arcs, nodes, hits):
+    """Bytes the method must touch: 4 B neighbour id + 1 bit visited probe per scanned
+    arc, 26 B per reached node (8 B row bounds, 16 B path count, 2 B level), 4 B per hit."""
+    return 4.125 * arcs + 26.0 * nodes + 4.0 * hits
+
+
+def cpu_baseline(csr, samples, seed):
+    import oracle
+    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    t0 = time.perf_counter()
+    S = oracle.sample_paths(csr, seed, 1, 0, samples, threads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": samples / dt, "unit": "sampled shortest paths/s", "cores": threads,
+            "kind": "oracle", "gteps": float(S.arcs.sum()) / dt / 1e9,
+            "sample": f"oracle sample_paths: main-phase ids 0..{samples - 1}, seed {seed}, "
+                      f"same graph ({dt:.1f} s)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="cl1m")
+    ap.add_argument("--epsilon", type=float, default=0.005)
+    ap.add_argument("--delta", type=float, default=0.1)
+    ap.add_argument("--seed", type=int, default=1)
+    ap.add_argument("--kernel-batch", type=int, default=65536)
+    ap.add_argument("--check-interval", type=int, default=0)
+    ap.add_argument("--cpu-samples", type=int, default=20000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path "
+              "(samples would shard across GPUs with one all-reduce of the counters per "
+              "check interval; not built)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import graphgen as gg
+    import paper_1604_08553_amd as kad
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    t0 = time.perf_counter()
+    csr = gg.workload(args.workload)
+    gen_s = time.perf_counter() - t0
+    print(f"[bench] graph {csr.name}: n={csr.n} arcs={csr.arcs} ({gen_s:.1f} s)", file=sys.stderr,
+          flush=True)
+    ctx = kad.Context(0)
+    G = kad.Graph(ctx, csr)
+    kw = dict(epsilon=args.epsilon, delta=args.delta, seed=args.seed,
+              kernel_batch=args.kernel_batch, check_interval=args.check_interval)
+    for w in range(args.warmup):
+        r = kad.run(ctx, G, **kw)
+        print(f"[bench] warmup {w}: tau={r['tau']} {r['seconds']:.3f} s", file=sys.stderr, flush=True)
+
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    runs = []
+    for s in range(args.steps):
+        r = kad.run(ctx, G, **kw)
+        runs.append(r)
+        print(f"[bench] step {s}: tau={r['tau']} omega={r['omega']} stop={r['stop_reason']} "
+              f"{r['seconds']:.3f} s", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = ctx.timing()
+    ctx.set_timing(False)
+
+    paths = sum(r["alpha"] + r["tau"] for r in runs)
+    arcs = sum(r["arcs_scanned"] + r["pilot_arcs_scanned"] for r in runs)
+    r0 = runs[0]
+    alg = algorithmic_bytes(tm["arcs"], tm["nodes"], tm["hits"])
+    per_launch_bytes = alg / max(tm["launches"], 1)
+    avg_launch_s = tm["seconds"] / max(tm["launches"], 1)
+    achieved = per_launch_bytes / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+
+    out = {
+        "metric": "sampled shortest paths/sec",
+        "value": paths / elapsed,
+        "unit": "paths/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u128",
+        "data": "synthetic",
+        "config": {
+            "workload": f"undirected Chung-Lu n={csr.n} beta=2.3 mean degree 20 ({csr.arcs} arcs), "
+                        f"all-nodes, epsilon={args.epsilon}, delta={args.delta}, seed {args.seed}, "
+                        f"{args.kernel_batch} samples per sampler launch",
+            "graph_sha256": csr.sha256(),
+        },
+        "gteps": arcs / elapsed / 1e9,
+        "time_to_epsilon_s": elapsed / args.steps,
+        "tau": r0["tau"], "omega": r0["omega"], "alpha": r0["alpha"], "vd": r0["vd"],
+        "check_interval": r0["interval"], "stop": "rule" if r0["stop_reason"] else "omega",
+        "sampler": {"launches": tm["launches"], "samples": tm["samples"],
+                    "avg_launch_ms": avg_launch_s * 1e3,
+                    "arcs_per_sample": tm["arcs"] / max(tm["samples"], 1),
+                    "nodes_per_sample": tm["nodes"] / max(tm["samples"], 1),
+                    "gteps_in_kernel": tm["arcs"] / max(tm["seconds"], 1e-12) / 1e9},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sampler_kernel",
+                     "alg_bytes_per_launch": per_launch_bytes},
+    }
+    G.close()
+    ctx.close()
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(csr, args.cpu_samples, args.seed)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

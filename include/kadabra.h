@@ -1,0 +1,227 @@
+/*
+ * kadabra.h -- C ABI of the MI355X sampled-betweenness library.
+ *
+ * The library approximates the normalised betweenness centrality
+ *     bc(v) = 1/(n(n-1)) * sum over ordered pairs s != t, v not in {s,t}, of sigma_st(v)/sigma_st
+ * (paper section 2, "Algorithm Overview") with the adaptive sampling algorithm of
+ * Borassi & Natale (Algorithm 1): random pairs (s,t), one uniformly random shortest
+ * s-t path per pair found by a balanced bidirectional BFS (section 4), hits on the
+ * path's interior nodes, and a stopping rule built on the bounds f and g of
+ * Theorem azuma-borassi with per-node failure probabilities chosen by computeDelta
+ * (Algorithm 2).  Two tasks are offered: every centrality within +-epsilon
+ * (section 2) and the top-k ranking (section 5, Algorithm 3).
+ *
+ * Conventions for every call:
+ *   - All calls return a kad_status (0 = success, negative = error); none aborts.
+ *     kad_last_error() gives a thread-local description of the last failure.
+ *   - Pointers marked "host" are ordinary CPU memory; "device" pointers are HIP
+ *     device memory of the context's GPU.  The caller owns every buffer it passes;
+ *     the library never frees them.
+ *   - Results depend only on the graph and the parameters (kernel_batch excluded):
+ *     all randomness is a counter-based Philox4x64-10 stream keyed by (seed,
+ *     phase, sample id), so the output is identical for any launch shape.
+ *   - hip_stream may be NULL (the library's own stream) or a hipStream_t of the
+ *     context's device; calls are synchronous with respect to the host.
+ */
+#ifndef KADABRA_H
+#define KADABRA_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KAD_OK = 0,
+  KAD_EINVAL = -1,    /* bad argument or malformed graph */
+  KAD_ENOMEM = -2,    /* host or device allocation failed, or over the HBM budget */
+  KAD_EDEVICE = -3,   /* HIP runtime error, or no usable GPU */
+  KAD_EBUSY = -4,     /* reserved */
+  KAD_ETOOSMALL = -5, /* an output buffer is too small; the needed size is reported */
+  KAD_EOVERFLOW = -6, /* a result does not fit the library's fixed-width arithmetic */
+  KAD_ERNG = -7       /* a bounded random draw was rejected 64 times (probability < 2^-64) */
+} kad_status;
+
+enum { KAD_MEM_HOST = 0, KAD_MEM_DEVICE = 1 };
+enum { KAD_ALL_NODES = 0, KAD_TOPK = 1 };
+enum { KAD_STOP_OMEGA = 0, KAD_STOP_RULE = 1 };
+
+/* per-sample flag bits reported by kad_sample_paths */
+enum {
+  KAD_SAMPLE_OVERFLOW = 1u, /* a path count or the candidate-edge total reached 2^128 */
+  KAD_SAMPLE_CAPACITY = 2u, /* the candidate-edge list or the path outgrew its buffer */
+  KAD_SAMPLE_RNG = 4u       /* a bounded draw exhausted its attempts */
+};
+
+typedef struct kad_ctx kad_ctx;
+typedef struct kad_graph kad_graph;
+
+/* ---------------------------------------------------------------- context */
+
+/* Open HIP device `hip_device`.  hbm_budget_bytes caps the library's device memory
+ * (graphs + per-sample working state); 0 means 90% of the free memory at creation.
+ * Fails with KAD_EDEVICE when the device does not exist. */
+kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **out);
+kad_status kad_ctx_destroy(kad_ctx *ctx);
+
+/* ---------------------------------------------------------------- graphs */
+
+/* Register an unweighted graph in CSR form (paper section 2: G = (V,E), directed or
+ * undirected; section 4 uses out-arcs forward from s and in-arcs backward from t).
+ *   n        : number of nodes, 2 <= n < 2^32; nodes are 0..n-1.
+ *   arcs     : number of CSR entries, < 2^32 (an undirected edge is two arcs).
+ *   row_ptr  : uint32[n+1], row_ptr[0] = 0, row_ptr[n] = arcs, non-decreasing.
+ *   col      : uint32[arcs]; row v lists the heads of v's out-arcs, strictly
+ *              ascending (no duplicates), no self-loops.
+ *   rrow_ptr, rcol : the in-rows (transpose) in the same form.  Ignored for an
+ *              undirected graph (which must be symmetric).  For a directed graph
+ *              NULL means "build the transpose"; if given it must be the exact
+ *              transpose.
+ *   mem      : KAD_MEM_HOST (the library copies the arrays to the device) or
+ *              KAD_MEM_DEVICE (the arrays are device pointers that the library
+ *              borrows; the caller keeps them alive and unchanged until
+ *              kad_graph_destroy; the library also keeps a host copy for the
+ *              host-side vertex-diameter pass).
+ * Every property above is validated; violations return KAD_EINVAL. */
+kad_status kad_graph_create(kad_ctx *ctx, uint32_t n, uint64_t arcs, int directed,
+                            const uint32_t *row_ptr, const uint32_t *col,
+                            const uint32_t *rrow_ptr, const uint32_t *rcol, int mem,
+                            kad_graph **out);
+kad_status kad_graph_destroy(kad_graph *g);
+
+/* ---------------------------------------------------------------- the adaptive run */
+
+typedef struct {
+  double epsilon;          /* lambda of the paper, in (0,1) */
+  double delta;            /* failure probability, in (0,1) */
+  uint32_t mode;           /* KAD_ALL_NODES or KAD_TOPK */
+  uint32_t k;              /* top-k: 1 <= k <= n */
+  uint64_t seed;           /* Philox key word 0 */
+  uint32_t check_interval; /* samples between stopping checks; 0 = 2^floor(log2(omega/16))
+                              clamped to [1024, 65536].  Part of the result contract. */
+  uint32_t kernel_batch;   /* samples per sampler launch (rounded up to a multiple of the
+                              check interval); 0 = library choice.  Performance only. */
+  uint32_t vd_override;    /* 0 = library vertex-diameter rule (exact when n*arcs <= 1e9,
+                              else a strongly-connected-component bound) */
+  uint32_t reserved;       /* must be 0 */
+  double c;                /* constant of the sample cap omega; 0 = 0.5 */
+  double balance_eps;      /* epsilon of computeDelta (Algorithm 2); 0 = 0.001 */
+} kad_params;
+
+typedef struct {
+  /* scalar outputs */
+  uint64_t tau;            /* samples taken in the main phase */
+  uint64_t omega;          /* cap: ceil(c/eps^2 (floor(log2(max(VD-2,1))) + 1 + ln(2/delta))) */
+  uint64_t alpha;          /* pilot samples: max(1, floor(omega/100)) */
+  uint64_t interval;       /* check interval used */
+  uint64_t arcs_scanned;   /* arcs scanned by the main phase's level expansions */
+  uint64_t pilot_arcs_scanned;
+  uint64_t overflow_samples; /* samples recomputed with wide path counts */
+  uint32_t vd, vd_exact;   /* vertex diameter used, and whether it is exact */
+  uint32_t stop_reason;    /* KAD_STOP_RULE or KAD_STOP_OMEGA */
+  uint32_t n;
+  double seconds;          /* wall time of the call */
+  double C;                /* the constant found by computeDelta's bisection */
+  /* caller-owned host arrays of length n; any may be NULL */
+  uint64_t *count;         /* main-phase hits per node */
+  double *bc;              /* count / tau */
+  double *lower, *upper;   /* [bc - f, bc + g] after a rule stop, [bc - eps, bc + eps] at omega */
+  /* top-k output (caller-owned, capacity topk_cap): nodes with rank_lo <= k in order of
+     decreasing estimate (ties by id), with rank_lo = 1 + #{w != v: lower(w) >= upper(v)}
+     and rank_hi = #{w: upper(w) > lower(v)}.  If more than topk_cap nodes qualify the call
+     returns KAD_ETOOSMALL with topk_len set to the number needed. */
+  uint32_t topk_cap, topk_len;
+  uint32_t *topk_node, *rank_lo, *rank_hi;
+} kad_result;
+
+/* Run the adaptive algorithm (Algorithm 1) on the GPU: vertex diameter (host), omega,
+ * pilot of alpha samples (phase 0) and computeDelta (host, binary64), then the main
+ * phase (phase 1) in batches of samples with the stopping rule checked every
+ * check_interval samples (host, binary64).  Fills `r`. */
+kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_result *r,
+                   void *hip_stream);
+
+/* ---------------------------------------------------------------- sampling primitives */
+
+/* Exact per-sample trace of sample ids [first, first+count) of `phase` (0 pilot, 1 main)
+ * (section 4: pair, balanced bidirectional BFS, uniform shortest path).  Host outputs:
+ *   s[count], t[count]          : the pair
+ *   path_off[count+1]           : sample k's path is path_nodes[path_off[k] .. path_off[k+1]),
+ *                                 from s to t inclusive; empty when s and t are disconnected
+ *   path_nodes[path_cap]        : KAD_ETOOSMALL (path_off[count] = needed) when short
+ *   arcs_scanned[count]         : arcs scanned by the level expansions
+ *   flags[count]                : KAD_SAMPLE_* bits (0 for a valid sample)
+ * Any output pointer may be NULL except path_off when path_nodes is given. */
+kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                            uint64_t first, uint32_t count, uint32_t *s, uint32_t *t,
+                            uint64_t *path_off, uint32_t *path_nodes, uint64_t path_cap,
+                            uint64_t *arcs_scanned, uint32_t *flags, void *hip_stream);
+
+/* Hit counts of sample ids [first, first+count) of `phase`: count_out[v] (host, length n)
+ * is incremented by the number of sampled paths with v as an interior node (section 2:
+ * X_i(v) = 1 iff v lies on path i and differs from its ends).  *arcs_scanned (may be
+ * NULL) receives the total arcs scanned. */
+kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                          uint64_t first, uint64_t count, uint64_t *count_out,
+                          uint64_t *arcs_scanned, void *hip_stream);
+
+/* ---------------------------------------------------------------- host statistics */
+/* These run on the CPU only (no device needed); binary64, no FMA contraction. */
+
+/* Sample cap of Algorithm 1: ceil(c/eps^2 * (floor(log2(max(vd-2,1))) + 1 + ln(2/delta))). */
+uint64_t kad_omega(double epsilon, double delta, uint32_t vd, double c);
+/* Pilot size of Algorithm 2: max(1, floor(omega/100)). */
+uint64_t kad_alpha(uint64_t omega);
+/* Default check interval: 2^floor(log2(omega/16)) clamped to [1024, 65536]. */
+uint64_t kad_default_interval(uint64_t omega);
+
+/* Vertex diameter (largest number of nodes on a shortest path) of a host CSR (same layout
+ * rules as kad_graph_create; rrow/rcol required for directed graphs).  Exact by a BFS from
+ * every node when n*arcs <= exact_limit; otherwise the bound: heaviest path of the
+ * strongly-connected-component DAG where component C weighs ecc_out_C(r) + ecc_in_C(r) + 1,
+ * r = C's node of largest in+out degree (lowest id on ties). */
+kad_status kad_vertex_diameter(uint32_t n, uint64_t arcs, int directed, const uint32_t *row_ptr,
+                               const uint32_t *col, const uint32_t *rrow_ptr,
+                               const uint32_t *rcol, double exact_limit, uint32_t *vd,
+                               uint32_t *exact);
+
+/* f and g of Theorem azuma-borassi, L = ln(1/delta_L) or ln(1/delta_U), btilde = count/tau. */
+double kad_bound_f(double btilde, double L, double omega, double tau);
+double kad_bound_g(double btilde, double L, double omega, double tau);
+
+/* computeDelta (Algorithm 2): L_l[v] = -ln(delta_L(v)), L_u[v] = -ln(delta_U(v)) from the
+ * pilot counts count0 (alpha samples) and the wanted half-widths lambda_l/lambda_u (host
+ * arrays of length n); *C receives the bisection's constant (may be NULL). */
+kad_status kad_compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
+                             const double *lambda_l, const double *lambda_u, double delta,
+                             double balance_eps, double *L_l, double *L_u, double *C);
+
+/* Wanted half-widths for the top-k task (section 5) from the pilot counts. */
+kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha,
+                            double epsilon, double *lambda_l, double *lambda_u);
+
+/* Stopping conditions: all-nodes (every f <= eps and g <= eps) and top-k (Algorithm 3).
+ * Return 1 (stop), 0 (continue) or a negative kad_status. */
+int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *count, uint64_t tau,
+                     uint64_t omega, double epsilon, const double *L_l, const double *L_u);
+
+/* ---------------------------------------------------------------- measurement hooks */
+
+/* Time every sampler launch of this context with HIP events recorded on the launch
+ * stream (enable != 0; this also resets the totals).  Adds one event synchronisation
+ * per launch. */
+kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable);
+/* Totals over the timed sampler launches since timing was enabled: launches, samples,
+ * seconds (sum of the event-measured launch durations), arcs scanned, nodes reached by
+ * the two searches, and hits (interior path nodes).  Any pointer may be NULL. */
+kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *samples,
+                              double *seconds, uint64_t *arcs, uint64_t *nodes, uint64_t *hits);
+
+const char *kad_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KADABRA_H */

@@ -1,0 +1,351 @@
+"""MI355X sampled betweenness centrality (the KADABRA hot path) -- Python binding.
+
+Thin ctypes marshalling over ``libkadabra.so`` (C ABI in ``include/kadabra.h``):
+every step of the sampling path runs in the library's HIP kernels, the stopping
+statistics in its C++ host code.  PyTorch is optional and only used to hand over
+device tensors and HIP streams.  The binding fails loudly when the library has not
+been built; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import re
+
+import numpy as np
+
+__all__ = ["Context", "Graph", "run", "sample_paths", "hit_counts", "KadError", "lib",
+           "library_path", "declared_symbols", "omega", "alpha", "default_interval",
+           "vertex_diameter", "bound_f", "bound_g", "compute_delta", "topk_lambdas",
+           "have_to_stop"]
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_LIB_PATH = os.path.join(_HERE, "libkadabra.so")
+_HEADER = os.path.join(os.path.dirname(_HERE), "include", "kadabra.h")
+
+ALL_NODES, TOPK = 0, 1
+MEM_HOST, MEM_DEVICE = 0, 1
+STOP_OMEGA, STOP_RULE = 0, 1
+SAMPLE_OVERFLOW, SAMPLE_CAPACITY, SAMPLE_RNG = 1, 2, 4
+
+_STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
+           -4: "busy", -5: "buffer too small", -6: "overflow", -7: "random draw rejected"}
+
+
+class KadError(RuntimeError):
+    def __init__(self, status, message):
+        super().__init__(f"{_STATUS.get(status, status)}: {message}")
+        self.status = status
+
+
+class _Params(C.Structure):
+    _fields_ = [("epsilon", C.c_double), ("delta", C.c_double), ("mode", C.c_uint32),
+                ("k", C.c_uint32), ("seed", C.c_uint64), ("check_interval", C.c_uint32),
+                ("kernel_batch", C.c_uint32), ("vd_override", C.c_uint32),
+                ("reserved", C.c_uint32), ("c", C.c_double), ("balance_eps", C.c_double)]
+
+
+class _Result(C.Structure):
+    _fields_ = [("tau", C.c_uint64), ("omega", C.c_uint64), ("alpha", C.c_uint64),
+                ("interval", C.c_uint64), ("arcs_scanned", C.c_uint64),
+                ("pilot_arcs_scanned", C.c_uint64), ("overflow_samples", C.c_uint64),
+                ("vd", C.c_uint32), ("vd_exact", C.c_uint32), ("stop_reason", C.c_uint32),
+                ("n", C.c_uint32), ("seconds", C.c_double), ("C", C.c_double),
+                ("count", C.c_void_p), ("bc", C.c_void_p), ("lower", C.c_void_p),
+                ("upper", C.c_void_p), ("topk_cap", C.c_uint32), ("topk_len", C.c_uint32),
+                ("topk_node", C.c_void_p), ("rank_lo", C.c_void_p), ("rank_hi", C.c_void_p)]
+
+
+_lib = None
+
+
+def library_path() -> str:
+    return _LIB_PATH
+
+
+def lib():
+    """Load libkadabra.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError(f"{_LIB_PATH} is missing: build it with "
+                          "`python -m paper_1604_08553_amd.build`")
+    L = C.CDLL(_LIB_PATH)
+    vp, u32, u64, i32, dbl, st = C.c_void_p, C.c_uint32, C.c_uint64, C.c_int, C.c_double, C.c_int
+    sig = {
+        "kad_ctx_create": ([i32, u64, vp], st),
+        "kad_ctx_destroy": ([vp], st),
+        "kad_graph_create": ([vp, u32, u64, i32, vp, vp, vp, vp, i32, vp], st),
+        "kad_graph_destroy": ([vp], st),
+        "kad_run": ([vp, vp, C.POINTER(_Params), C.POINTER(_Result), vp], st),
+        "kad_sample_paths": ([vp, vp, u64, u32, u64, u32, vp, vp, vp, vp, u64, vp, vp, vp], st),
+        "kad_hit_counts": ([vp, vp, u64, u32, u64, u64, vp, vp, vp], st),
+        "kad_omega": ([dbl, dbl, u32, dbl], u64),
+        "kad_alpha": ([u64], u64),
+        "kad_default_interval": ([u64], u64),
+        "kad_vertex_diameter": ([u32, u64, i32, vp, vp, vp, vp, dbl, vp, vp], st),
+        "kad_bound_f": ([dbl, dbl, dbl, dbl], dbl),
+        "kad_bound_g": ([dbl, dbl, dbl, dbl], dbl),
+        "kad_compute_delta": ([u32, vp, u64, u64, vp, vp, dbl, dbl, vp, vp, vp], st),
+        "kad_topk_lambdas": ([u32, u32, vp, u64, dbl, vp, vp], st),
+        "kad_have_to_stop": ([u32, u32, u32, vp, u64, u64, dbl, vp, vp], st),
+        "kad_ctx_set_timing": ([vp, i32], st),
+        "kad_ctx_get_timing": ([vp, vp, vp, vp, vp, vp, vp], st),
+        "kad_last_error": ([], C.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(L, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = L
+    return L
+
+
+def declared_symbols() -> list:
+    """Function names declared in include/kadabra.h."""
+    text = open(_HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(kad_[a-z0-9_]+)\s*\(", text)))
+
+
+def _check(rc):
+    if rc != 0:
+        msg = lib().kad_last_error()
+        raise KadError(rc, msg.decode() if msg else "")
+
+
+def _p(a):
+    return None if a is None else a.ctypes.data
+
+
+def _u32(a):
+    return np.ascontiguousarray(a, dtype=np.uint32)
+
+
+# ----------------------------------------------------------------------------- objects
+
+
+class Context:
+    """A HIP device with the library's working memory (``hbm_budget`` bytes, 0 = 90%
+    of the free memory)."""
+
+    def __init__(self, device: int = 0, hbm_budget: int = 0):
+        h = C.c_void_p()
+        _check(lib().kad_ctx_create(device, hbm_budget, C.byref(h)))
+        self.handle = h
+        self.device = device
+
+    def close(self):
+        if self.handle:
+            lib().kad_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_timing(self, enable: bool = True):
+        _check(lib().kad_ctx_set_timing(self.handle, 1 if enable else 0))
+
+    def timing(self) -> dict:
+        """Totals over the event-timed sampler launches (see kad_ctx_get_timing)."""
+        v = [C.c_uint64() for _ in range(5)]
+        sec = C.c_double()
+        _check(lib().kad_ctx_get_timing(self.handle, C.byref(v[0]), C.byref(v[1]), C.byref(sec),
+                                        C.byref(v[2]), C.byref(v[3]), C.byref(v[4])))
+        return {"launches": v[0].value, "samples": v[1].value, "seconds": sec.value,
+                "arcs": v[2].value, "nodes": v[3].value, "hits": v[4].value}
+
+
+class Graph:
+    """A CSR graph registered with a context.
+
+    ``csr`` is any object with ``n, row, col, directed`` (and ``rrow, rcol`` for
+    directed graphs), e.g. ``graphgen.CSR``.  With torch tensors on the context's GPU
+    pass ``mem="device"``: the library borrows them (keep them alive)."""
+
+    def __init__(self, ctx: Context, csr=None, *, n=None, row=None, col=None, rrow=None,
+                 rcol=None, directed=None, mem="host"):
+        if csr is not None:
+            n, row, col, directed = csr.n, csr.row, csr.col, csr.directed
+            rrow = getattr(csr, "rrow", None) if directed else None
+            rcol = getattr(csr, "rcol", None) if directed else None
+        self.ctx = ctx
+        self.n = int(n)
+        self.directed = bool(directed)
+        h = C.c_void_p()
+        if mem == "device":
+            self._keep = (row, col, rrow, rcol)
+            ptr = lambda t: None if t is None else t.data_ptr()
+            arcs = int(col.numel())
+            rc = lib().kad_graph_create(ctx.handle, self.n, arcs, 1 if self.directed else 0,
+                                        ptr(row), ptr(col), ptr(rrow), ptr(rcol), MEM_DEVICE,
+                                        C.byref(h))
+        else:
+            row, col = _u32(row), _u32(col)
+            rrow = None if rrow is None else _u32(rrow)
+            rcol = None if rcol is None else _u32(rcol)
+            self._keep = (row, col, rrow, rcol)
+            arcs = int(col.size)
+            rc = lib().kad_graph_create(ctx.handle, self.n, arcs, 1 if self.directed else 0,
+                                        _p(row), _p(col), _p(rrow), _p(rcol), MEM_HOST,
+                                        C.byref(h))
+        _check(rc)
+        self.handle = h
+        self.arcs = arcs
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kad_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if hasattr(stream, "cuda_stream"):
+        return stream.cuda_stream
+    return int(stream)
+
+
+# ----------------------------------------------------------------------------- calls
+
+
+def run(ctx: Context, graph: Graph, epsilon: float, delta: float, mode: str = "all", k: int = 0,
+        seed: int = 1, check_interval: int = 0, kernel_batch: int = 0, vd_override: int = 0,
+        c: float = 0.0, balance_eps: float = 0.0, topk_cap: int = 0, stream=None) -> dict:
+    """The adaptive run (Algorithm 1).  Returns scalars plus the per-node arrays."""
+    n = graph.n
+    p = _Params(epsilon, delta, TOPK if mode == "topk" else ALL_NODES, k, seed, check_interval,
+                kernel_batch, vd_override, 0, c, balance_eps)
+    out = {"count": np.zeros(n, dtype=np.uint64), "bc": np.zeros(n), "lower": np.zeros(n),
+           "upper": np.zeros(n)}
+    cap = topk_cap or (n if mode == "topk" else 0)
+    tk = {"topk_node": np.zeros(max(cap, 1), dtype=np.uint32),
+          "rank_lo": np.zeros(max(cap, 1), dtype=np.uint32),
+          "rank_hi": np.zeros(max(cap, 1), dtype=np.uint32)}
+    r = _Result()
+    for name, a in list(out.items()) + list(tk.items()):
+        setattr(r, name, a.ctypes.data)
+    r.topk_cap = cap
+    _check(lib().kad_run(ctx.handle, graph.handle, C.byref(p), C.byref(r), _stream(stream)))
+    for name in ("tau", "omega", "alpha", "interval", "arcs_scanned", "pilot_arcs_scanned",
+                 "overflow_samples", "vd", "vd_exact", "stop_reason", "seconds", "C"):
+        out[name] = getattr(r, name)
+    if mode == "topk":
+        m = r.topk_len
+        out["topk_node"] = tk["topk_node"][:m].copy()
+        out["rank_lo"] = tk["rank_lo"][:m].copy()
+        out["rank_hi"] = tk["rank_hi"][:m].copy()
+    return out
+
+
+def sample_paths(ctx: Context, graph: Graph, seed: int, phase: int, first: int, count: int,
+                 stream=None) -> dict:
+    """Per-sample trace of ids [first, first+count): s, t, packed paths, arcs, flags."""
+    s = np.zeros(count, dtype=np.uint32)
+    t = np.zeros(count, dtype=np.uint32)
+    off = np.zeros(count + 1, dtype=np.uint64)
+    arcs = np.zeros(count, dtype=np.uint64)
+    flags = np.zeros(count, dtype=np.uint32)
+    cap = max(16, count * 8)
+    while True:
+        nodes = np.zeros(cap, dtype=np.uint32)
+        rc = lib().kad_sample_paths(ctx.handle, graph.handle, seed, phase, first, count, _p(s),
+                                    _p(t), _p(off), _p(nodes), cap, _p(arcs), _p(flags),
+                                    _stream(stream))
+        if rc == -5:
+            cap = int(off[count]) + 16
+            continue
+        _check(rc)
+        return {"s": s, "t": t, "path_off": off, "nodes": nodes[:int(off[count])],
+                "arcs": arcs, "flags": flags}
+
+
+def hit_counts(ctx: Context, graph: Graph, seed: int, phase: int, first: int, count: int,
+               stream=None):
+    """(count[n], arcs scanned) of sample ids [first, first+count)."""
+    cnt = np.zeros(graph.n, dtype=np.uint64)
+    arcs = C.c_uint64()
+    _check(lib().kad_hit_counts(ctx.handle, graph.handle, seed, phase, first, count, _p(cnt),
+                                C.byref(arcs), _stream(stream)))
+    return cnt, arcs.value
+
+
+# ----------------------------------------------------------------------------- host statistics
+
+
+def omega(epsilon, delta, vd, c=0.5) -> int:
+    return int(lib().kad_omega(epsilon, delta, vd, c))
+
+
+def alpha(om) -> int:
+    return int(lib().kad_alpha(om))
+
+
+def default_interval(om) -> int:
+    return int(lib().kad_default_interval(om))
+
+
+def vertex_diameter(csr, exact_limit=1e9):
+    row, col = _u32(csr.row), _u32(csr.col)
+    rrow = _u32(csr.rrow) if csr.directed else None
+    rcol = _u32(csr.rcol) if csr.directed else None
+    vd, ex = C.c_uint32(), C.c_uint32()
+    _check(lib().kad_vertex_diameter(csr.n, int(col.size), 1 if csr.directed else 0, _p(row),
+                                     _p(col), _p(rrow), _p(rcol), exact_limit, C.byref(vd),
+                                     C.byref(ex)))
+    return int(vd.value), bool(ex.value)
+
+
+def bound_f(bt, L, om, tau) -> float:
+    return float(lib().kad_bound_f(bt, L, float(om), float(tau)))
+
+
+def bound_g(bt, L, om, tau) -> float:
+    return float(lib().kad_bound_g(bt, L, float(om), float(tau)))
+
+
+def compute_delta(count0, alpha_, omega_, lam_l, lam_u, delta, balance_eps=0.001):
+    count0 = np.ascontiguousarray(count0, dtype=np.uint64)
+    n = count0.size
+    ll = np.ascontiguousarray(lam_l, dtype=np.float64)
+    lu = np.ascontiguousarray(lam_u, dtype=np.float64)
+    Ll, Lu, Cv = np.zeros(n), np.zeros(n), C.c_double()
+    _check(lib().kad_compute_delta(n, _p(count0), alpha_, omega_, _p(ll), _p(lu), delta,
+                                   balance_eps, _p(Ll), _p(Lu), C.byref(Cv)))
+    return Ll, Lu, Cv.value
+
+
+def topk_lambdas(count0, k, alpha_, epsilon):
+    count0 = np.ascontiguousarray(count0, dtype=np.uint64)
+    n = count0.size
+    ll, lu = np.zeros(n), np.zeros(n)
+    _check(lib().kad_topk_lambdas(n, k, _p(count0), alpha_, epsilon, _p(ll), _p(lu)))
+    return ll, lu
+
+
+def have_to_stop(count, tau, omega_, epsilon, L_l, L_u, mode="all", k=0) -> bool:
+    count = np.ascontiguousarray(count, dtype=np.uint64)
+    Ll = np.ascontiguousarray(L_l, dtype=np.float64)
+    Lu = np.ascontiguousarray(L_u, dtype=np.float64)
+    r = lib().kad_have_to_stop(count.size, TOPK if mode == "topk" else ALL_NODES, k,
+                               _p(count), tau, omega_, epsilon, _p(Ll), _p(Lu))
+    if r < 0:
+        _check(r)
+    return bool(r)

@@ -1,0 +1,734 @@
+// HIP kernels of the sampled-betweenness hot path, written for CDNA4 (gfx950).
+//
+// sampler_kernel: one workgroup per sample (Borassi & Natale, section 4 "Balanced
+//   Bidirectional BFS"; pair and path distribution of section 2).  A persistent
+//   grid pulls sample ids from a counter; everything random is a Philox4x64-10
+//   draw keyed by (seed, phase, sample id, purpose, step), so results do not
+//   depend on which workgroup runs which sample.
+//
+//   Each level expansion is split in two scans of the frontier's rows:
+//     touch scan     -- for every arc, test its head against the other side's
+//                       frontier (an LDS bit filter, confirmed by the node's tag)
+//                       and collect the candidate edges;
+//     discovery scan -- only when the two searches did not touch: claim unseen
+//                       heads for the next level (compare-and-swap on the tag),
+//                       add the 128-bit path counts, append the new frontier with
+//                       wave ballots.
+//   The expansion that meets -- normally the largest one -- therefore costs
+//   coalesced row reads and LDS probes only.
+//
+// hit_reduce_kernel: the interior nodes of the sampled paths are counted per
+//   node-id tile in an LDS histogram and added to the global counters by the
+//   tile's owner, so the counters see no atomics.
+#include "kad_device.h"
+
+namespace kad {
+namespace {
+
+constexpr int BLOCK = SAMPLER_BLOCK;
+constexpr int WAVE = 64;
+constexpr int NWAVES = BLOCK / WAVE;
+constexpr int CHUNK = 512;  // frontier nodes staged in LDS per pass (2 per thread)
+constexpr int FILTER_LOG2 = 16;
+constexpr int FILTER_WORDS = (1 << FILTER_LOG2) / 32;
+constexpr int PI_LDS = 1024;  // candidate edges kept in LDS; more spill to the slot buffer
+constexpr uint32_t MAX_ATTEMPTS = 64;
+
+static_assert(CHUNK == 2 * BLOCK, "two staged frontier nodes per thread");
+
+// ------------------------------------------------------------------ Philox4x64-10
+// Salmon et al., SC'11: ten rounds of two 64x64->128 multiplications; the key is
+// bumped by two Weyl constants between rounds.
+constexpr uint64_t PH_M0 = 0xD2E7470EE14C6C93ULL;
+constexpr uint64_t PH_M1 = 0xCA5A826395121157ULL;
+constexpr uint64_t PH_W0 = 0x9E3779B97F4A7C15ULL;
+constexpr uint64_t PH_W1 = 0xBB67AE8584CAA73BULL;
+
+__device__ __forceinline__ void philox2(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                        uint64_t k0, uint64_t k1, uint64_t &o0, uint64_t &o1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += PH_W0;
+      k1 += PH_W1;
+    }
+    const uint64_t lo0 = PH_M0 * c0, hi0 = __umul64hi(PH_M0, c0);
+    const uint64_t lo1 = PH_M1 * c2, hi1 = __umul64hi(PH_M1, c2);
+    const uint64_t y0 = hi1 ^ c1 ^ k0;
+    const uint64_t y2 = hi0 ^ c3 ^ k1;
+    c0 = y0;
+    c1 = lo1;
+    c2 = y2;
+    c3 = lo0;
+  }
+  o0 = c0;
+  o1 = c1;
+}
+
+__device__ __forceinline__ uint64_t stream_word(uint32_t phase, uint32_t purpose, uint64_t step) {
+  return ((uint64_t)phase << 56) | ((uint64_t)purpose << 48) | (step & 0xFFFFFFFFFFFFULL);
+}
+
+enum : uint32_t { P_S = 0, P_T = 1, P_EDGE = 2, P_BACK_S = 3, P_BACK_T = 4 };
+
+// ------------------------------------------------------------------ 128-bit naturals
+struct u128 {
+  uint64_t lo, hi;
+};
+
+__device__ __forceinline__ bool lt128(u128 a, u128 b) {
+  return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+__device__ __forceinline__ u128 add128(u128 a, u128 b, bool &ovf) {
+  u128 r;
+  r.lo = a.lo + b.lo;
+  const uint64_t c = r.lo < a.lo ? 1u : 0u;
+  const uint64_t t = a.hi + b.hi;
+  ovf |= t < a.hi;
+  r.hi = t + c;
+  ovf |= r.hi < t;
+  return r;
+}
+
+__device__ __forceinline__ u128 sub128(u128 a, u128 b) {  // a >= b
+  u128 r;
+  r.lo = a.lo - b.lo;
+  r.hi = a.hi - b.hi - (a.lo < b.lo ? 1u : 0u);
+  return r;
+}
+
+__device__ __forceinline__ u128 mul128(u128 a, u128 b, bool &ovf) {
+  if (a.hi != 0 && b.hi != 0) {
+    ovf = true;
+    return u128{0, 0};
+  }
+  u128 r;
+  r.lo = a.lo * b.lo;
+  const uint64_t h = __umul64hi(a.lo, b.lo);
+  const uint64_t x1 = a.lo * b.hi, x1h = __umul64hi(a.lo, b.hi);
+  const uint64_t x2 = a.hi * b.lo, x2h = __umul64hi(a.hi, b.lo);
+  ovf |= (x1h | x2h) != 0;
+  uint64_t cross = x1 + x2;
+  ovf |= cross < x1;
+  r.hi = h + cross;
+  ovf |= r.hi < h;
+  return r;
+}
+
+__device__ __forceinline__ uint32_t bitlen128(u128 x) {
+  if (x.hi) return 128u - (uint32_t)__clzll(x.hi);
+  if (x.lo) return 64u - (uint32_t)__clzll(x.lo);
+  return 0u;
+}
+
+// An integer uniform in [0, bound), bound >= 1: W = bitlength(bound - 1); attempt a
+// takes ceil(W/64) words of block 0 of counter (i, sword, a, 0), least-significant
+// first, keeps W bits and accepts the value if it is below the bound.
+__device__ u128 uniform_below(u128 bound, uint64_t seed, uint64_t i, uint64_t sword,
+                              uint32_t &flags) {
+  if (bound.hi == 0 && bound.lo == 1) return u128{0, 0};
+  const u128 bm1 = sub128(bound, u128{1, 0});
+  const uint32_t W = bitlen128(bm1);
+  const uint32_t q = (W + 63) / 64;
+  const uint32_t top = W - 64 * (q - 1);
+  const uint64_t mask = top == 64 ? ~0ULL : ((1ULL << top) - 1);
+  for (uint32_t a = 0; a < MAX_ATTEMPTS; ++a) {
+    uint64_t o0, o1;
+    philox2(i, sword, a, 0, seed, 0, o0, o1);
+    u128 x;
+    if (q == 1) {
+      x.lo = o0 & mask;
+      x.hi = 0;
+    } else {
+      x.lo = o0;
+      x.hi = o1 & mask;
+    }
+    if (lt128(x, bound)) return x;
+  }
+  flags |= FLAG_RNG;
+  return u128{0, 0};
+}
+
+// ------------------------------------------------------------------ memory helpers
+// Tags and path counts are updated with device-scope atomics; reads that must see
+// them go through agent-scope loads so no stale vector-L1 line is used.
+__device__ __forceinline__ uint32_t ld_tag(const uint32_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ u128 ld_sig(const uint64_t *sig, uint32_t v) {
+  u128 r;
+  r.lo = __hip_atomic_load(sig + 2 * (size_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  r.hi = __hip_atomic_load(sig + 2 * (size_t)v + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return r;
+}
+
+// sigma(w) += x with exact carry into the high word; true when the sum reached 2^128.
+__device__ __forceinline__ bool atomic_add_sig(uint64_t *sig, uint32_t w, uint64_t xlo,
+                                               uint64_t xhi) {
+  uint64_t *p = sig + 2 * (size_t)w;
+  const uint64_t old = atomicAdd((unsigned long long *)p, (unsigned long long)xlo);
+  const uint64_t c = (old + xlo < old) ? 1u : 0u;
+  const uint64_t add = xhi + c;
+  bool ovf = add < xhi;
+  if (add != 0) {
+    const uint64_t oh = atomicAdd((unsigned long long *)(p + 1), (unsigned long long)add);
+    ovf |= oh + add < oh;
+  }
+  return ovf;
+}
+
+__device__ __forceinline__ uint32_t filter_bit(uint32_t w) {
+  return (w * 2654435761u) >> (32 - FILTER_LOG2);
+}
+
+// ------------------------------------------------------------------ wave / block scans
+__device__ __forceinline__ uint32_t lane_id() { return threadIdx.x & (WAVE - 1); }
+
+__device__ __forceinline__ uint32_t wave_incl_u32(uint32_t v) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint32_t o = __shfl_up(v, d, WAVE);
+    if (lane >= (uint32_t)d) v += o;
+  }
+  return v;
+}
+
+__device__ __forceinline__ uint64_t wave_sum_u64(uint64_t v) {
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, WAVE);
+  return v;
+}
+
+__device__ __forceinline__ u128 wave_incl_u128(u128 v, bool &ovf) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (int d = 1; d < WAVE; d <<= 1) {
+    const uint64_t olo = __shfl_up(v.lo, d, WAVE);
+    const uint64_t ohi = __shfl_up(v.hi, d, WAVE);
+    if (lane >= (uint32_t)d) v = add128(v, u128{olo, ohi}, ovf);
+  }
+  return v;
+}
+
+struct Lds {
+  uint32_t filter[FILTER_WORDS];
+  uint64_t pi[PI_LDS];
+  uint64_t c_sig_lo[CHUNK];
+  uint64_t c_sig_hi[CHUNK];
+  uint32_t c_node[CHUNK];
+  uint32_t c_start[CHUNK];
+  uint32_t c_pref[CHUNK + 1];
+  uint32_t red32[NWAVES + 1];
+  uint64_t red_lo[NWAVES];
+  uint64_t red_hi[NWAVES];
+  uint64_t deg[2];
+  uint64_t arcs;
+  uint64_t new_deg;
+  uint64_t r_lo, r_hi;
+  uint32_t k, s, t;
+  uint32_t fb[2], fe[2], lvl[2];
+  uint32_t nvis, pi_count, flags, win;
+  uint32_t ovf_any;
+};
+
+// Exclusive block scan of one value per thread; *total gets the block sum.
+__device__ __forceinline__ uint32_t block_excl_u32(Lds &L, uint32_t v, uint32_t &total) {
+  const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
+  const uint32_t inc = wave_incl_u32(v);
+  if (lane == WAVE - 1) L.red32[wid] = inc;
+  __syncthreads();
+  uint32_t before = 0, all = 0;
+#pragma unroll
+  for (int q = 0; q < NWAVES; ++q) {
+    const uint32_t x = L.red32[q];
+    if ((uint32_t)q < wid) before += x;
+    all += x;
+  }
+  __syncthreads();
+  total = all;
+  return before + inc - v;
+}
+
+// Inclusive block scan of 128-bit values; *total gets the block sum.
+__device__ __forceinline__ u128 block_incl_u128(Lds &L, u128 v, u128 &total, bool &ovf) {
+  const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
+  u128 inc = wave_incl_u128(v, ovf);
+  if (lane == WAVE - 1) {
+    L.red_lo[wid] = inc.lo;
+    L.red_hi[wid] = inc.hi;
+  }
+  __syncthreads();
+  u128 before{0, 0}, all{0, 0};
+#pragma unroll
+  for (int q = 0; q < NWAVES; ++q) {
+    const u128 x{L.red_lo[q], L.red_hi[q]};
+    if ((uint32_t)q < wid) before = add128(before, x, ovf);
+    all = add128(all, x, ovf);
+  }
+  __syncthreads();
+  total = all;
+  return add128(before, inc, ovf);
+}
+
+// Wave-aggregated append of the lanes with `pred` to an LDS-counted list.
+__device__ __forceinline__ uint32_t wave_reserve(bool pred, uint32_t *counter, uint32_t &rank) {
+  const uint64_t mask = __ballot(pred);
+  if (mask == 0) return 0xFFFFFFFFu;
+  const uint32_t lane = lane_id();
+  const uint32_t leader = (uint32_t)__ffsll((unsigned long long)mask) - 1;
+  uint32_t base = 0;
+  if (lane == leader) base = atomicAdd(counter, (uint32_t)__popcll(mask));
+  base = __shfl(base, leader, WAVE);
+  rank = (uint32_t)__popcll(mask & ((1ULL << lane) - 1ULL));
+  return base;
+}
+
+enum class Scan { Touch, Discover };
+
+// One pass over the rows of frontier [fb, fe) (chunked through LDS).
+template <Scan MODE>
+__device__ __forceinline__ void scan_frontier(Lds &L, const GraphDev &g, uint32_t me,
+                                              uint32_t fb, uint32_t fe, uint32_t *tag,
+                                              uint64_t *sig, uint32_t *visit, uint64_t *gpi,
+                                              uint32_t pi_cap, uint32_t other_tag,
+                                              uint32_t next_tag, bool &ovf) {
+  const uint32_t tid = threadIdx.x;
+  const uint32_t *rp = me == 0 ? g.row : g.rrow;
+  const uint32_t *cl = me == 0 ? g.col : g.rcol;
+  for (uint32_t cb = fb; cb < fe; cb += CHUNK) {
+    const uint32_t m = min((uint32_t)CHUNK, fe - cb);
+    uint32_t d[2] = {0, 0};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t j = 2 * tid + q;
+      if (j < m) {
+        const uint32_t u = visit[cb + j];
+        const uint32_t st = rp[u];
+        d[q] = rp[u + 1] - st;
+        L.c_node[j] = u;
+        L.c_start[j] = st;
+        if (MODE == Scan::Discover) {
+          const u128 su = ld_sig(sig, u);
+          L.c_sig_lo[j] = su.lo;
+          L.c_sig_hi[j] = su.hi;
+        }
+      }
+    }
+    uint32_t tot;
+    const uint32_t ex = block_excl_u32(L, d[0] + d[1], tot);
+    if (2 * tid < m) L.c_pref[2 * tid] = ex;
+    if (2 * tid + 1 < m) L.c_pref[2 * tid + 1] = ex + d[0];
+    if (tid == 0) L.c_pref[m] = tot;
+    __syncthreads();
+    // Every lane of a wave runs the same number of iterations (cross-lane ballots and
+    // shuffles below must not see inactive lanes); lanes past the end are idle.
+    uint32_t jlo = 0;
+    const uint32_t lane = lane_id();
+    for (uint32_t e0 = (tid / WAVE) * WAVE; e0 < tot; e0 += BLOCK) {
+      const uint32_t e = e0 + lane;
+      const bool valid = e < tot;
+      uint32_t u = 0, w = 0, lo = jlo;
+      if (valid) {
+        // largest j with c_pref[j] <= e (then c_pref[j+1] > e: node j owns arc e)
+        uint32_t hi = m;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
+        }
+        jlo = lo;
+        u = L.c_node[lo];
+        w = cl[L.c_start[lo] + (e - L.c_pref[lo])];
+      }
+      if (MODE == Scan::Touch) {
+        bool hit = false;
+        if (valid) {
+          const uint32_t h = filter_bit(w);
+          if ((L.filter[h >> 5] >> (h & 31)) & 1u) hit = ld_tag(tag + w) == other_tag;
+        }
+        uint32_t rank = 0;
+        const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
+        if (hit) {
+          const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+          const uint32_t idx = base + rank;
+          if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
+          else if (idx < pi_cap) gpi[idx] = key;
+        }
+      } else {
+        bool disc = false;
+        if (valid) {
+          uint32_t tg = ld_tag(tag + w);
+          if (tg == 0) {
+            const uint32_t old = atomicCAS(tag + w, 0u, next_tag);
+            disc = old == 0;
+            tg = disc ? next_tag : old;
+          }
+          if (tg == next_tag) ovf |= atomic_add_sig(sig, w, L.c_sig_lo[lo], L.c_sig_hi[lo]);
+        }
+        uint32_t rank = 0;
+        const uint32_t base = wave_reserve(disc, &L.nvis, rank);
+        if (base != 0xFFFFFFFFu) {  // uniform: some lane of this wave discovered a node
+          uint64_t dg = 0;
+          if (disc) {
+            visit[base + rank] = w;
+            dg = (uint64_t)(rp[w + 1] - rp[w]);
+          }
+          const uint64_t sum = wave_sum_u64(dg);
+          if (lane == 0) atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)sum);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// In-place ascending bitonic sort of keys[0, M), M a power of two, by the workgroup.
+__device__ void bitonic_sort(uint64_t *keys, uint32_t M) {
+  for (uint32_t k = 2; k <= M; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < M; i += BLOCK) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = keys[i], b = keys[ixj];
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            keys[i] = b;
+            keys[ixj] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// One backtracking walk of a wave (section 4, "by backtracking"): from `start` on
+// level `lev` of side `side` down to level 0, each step drawing
+// r < sigma(x) and taking the first neighbour on the level below (in row order)
+// whose running count exceeds r.  Writes the nodes to path[pos(j-1)].
+__device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint32_t lev,
+                          const uint32_t *tag, const uint64_t *sig, uint64_t seed, uint64_t i,
+                          uint32_t phase, uint32_t *path, uint32_t ls, uint32_t &flags) {
+  const uint32_t lane = lane_id();
+  // the s side looks at predecessors (in-rows), the t side at successors (out-rows)
+  const uint32_t *rp = side == 0 ? g.rrow : g.row;
+  const uint32_t *cl = side == 0 ? g.rcol : g.col;
+  uint32_t x = start;
+  for (uint32_t j = lev; j >= 1; --j) {
+    const u128 bound = ld_sig(sig, x);
+    const u128 r = uniform_below(bound, seed, i, stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j),
+                                 flags);
+    const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1, stored as (j-1)+1
+    const uint32_t beg = rp[x], end = rp[x + 1];
+    u128 carry{0, 0};
+    uint32_t pick = 0xFFFFFFFFu;
+    for (uint32_t b = beg; b < end; b += WAVE) {
+      const uint32_t idx = b + lane;
+      uint32_t u = 0;
+      u128 val{0, 0};
+      if (idx < end) {
+        u = cl[idx];
+        if (ld_tag(tag + u) == want) val = ld_sig(sig, u);
+      }
+      bool dummy = false;
+      u128 inc = wave_incl_u128(val, dummy);
+      inc = add128(inc, carry, dummy);
+      const uint64_t m = __ballot(idx < end && lt128(r, inc));
+      if (m) {
+        pick = __shfl(u, (int)__ffsll((unsigned long long)m) - 1, WAVE);
+        break;
+      }
+      carry.lo = __shfl(inc.lo, WAVE - 1, WAVE);
+      carry.hi = __shfl(inc.hi, WAVE - 1, WAVE);
+    }
+    if (pick == 0xFFFFFFFFu) {
+      flags |= FLAG_CAPACITY;  // unreachable for consistent counts
+      return;
+    }
+    x = pick;
+    if (lane == 0) path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x;
+  }
+}
+
+__global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st, uint64_t seed,
+                                                        uint32_t phase, uint64_t first,
+                                                        uint32_t count, uint32_t *work,
+                                                        SampleOut out) {
+  __shared__ Lds L;
+  const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
+  const size_t n = g.n;
+  const size_t slot = blockIdx.x;
+  uint32_t *tag = st.tag + slot * n;
+  uint64_t *sig = st.sig + slot * n * 2;
+  uint32_t *visit = st.visit + slot * n;
+  uint64_t *gpi = st.pi + slot * st.pi_cap;
+
+  for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
+
+  for (;;) {
+    if (tid == 0) L.k = atomicAdd(work, 1u);
+    __syncthreads();
+    const uint32_t k = L.k;
+    if (k >= count) break;
+    const uint64_t i = first + k;
+
+    // ---- the pair and the two initial levels
+    if (tid == 0) {
+      uint32_t fl = 0;
+      const uint32_t s = (uint32_t)uniform_below(u128{g.n, 0}, seed, i, stream_word(phase, P_S, 0), fl).lo;
+      const uint32_t tp = (uint32_t)uniform_below(u128{g.n - 1u, 0}, seed, i, stream_word(phase, P_T, 0), fl).lo;
+      const uint32_t t = tp + (tp >= s ? 1u : 0u);
+      L.s = s;
+      L.t = t;
+      tag[s] = 1u;
+      tag[t] = TAG_T | 1u;
+      sig[2 * (size_t)s] = 1;
+      sig[2 * (size_t)s + 1] = 0;
+      sig[2 * (size_t)t] = 1;
+      sig[2 * (size_t)t + 1] = 0;
+      visit[0] = s;
+      visit[1] = t;
+      L.fb[0] = 0; L.fe[0] = 1;
+      L.fb[1] = 1; L.fe[1] = 2;
+      L.lvl[0] = 0; L.lvl[1] = 0;
+      L.deg[0] = (uint64_t)(g.row[s + 1] - g.row[s]);
+      L.deg[1] = (uint64_t)(g.rrow[t + 1] - g.rrow[t]);
+      L.arcs = 0;
+      L.nvis = 2;
+      L.flags = fl;
+      L.ovf_any = 0;
+    }
+    __threadfence();
+    __syncthreads();
+
+    bool ovf = false;
+    bool met = false;
+    for (;;) {
+      const uint32_t me = L.deg[0] <= L.deg[1] ? 0u : 1u;  // ties expand the s side
+      const uint32_t ot = 1u - me;
+      const uint32_t fb = L.fb[me], fe = L.fe[me];
+      const uint32_t ob = L.fb[ot], oe = L.fe[ot];
+      const uint32_t lme = L.lvl[me], lot = L.lvl[ot];
+      const uint32_t other_tag = (ot == 0 ? 0u : TAG_T) | (lot + 1);
+      const uint32_t next_tag = (me == 0 ? 0u : TAG_T) | (lme + 2);
+      const uint64_t dme = L.deg[me];
+      __syncthreads();
+      if (tid == 0) {
+        L.arcs += dme;
+        L.pi_count = 0;
+        L.new_deg = 0;
+      }
+      for (uint32_t j = ob + tid; j < oe; j += BLOCK) {
+        const uint32_t h = filter_bit(visit[j]);
+        atomicOr(&L.filter[h >> 5], 1u << (h & 31));
+      }
+      __syncthreads();
+      scan_frontier<Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
+                                 next_tag, ovf);
+      for (uint32_t j = ob + tid; j < oe; j += BLOCK) L.filter[filter_bit(visit[j]) >> 5] = 0;
+      const uint32_t P = L.pi_count;
+      const uint32_t nb = L.nvis;
+      __syncthreads();
+      if (P > 0) {
+        met = true;
+        break;
+      }
+      scan_frontier<Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
+                                    other_tag, next_tag, ovf);
+      __threadfence();
+      __syncthreads();
+      const uint32_t ne = L.nvis;
+      const uint64_t nd = L.new_deg;
+      __syncthreads();
+      if (ne == nb) break;  // the expanded side closed: s and t are disconnected
+      if (tid == 0) {
+        L.fb[me] = nb;
+        L.fe[me] = ne;
+        L.lvl[me] = lme + 1;
+        L.deg[me] = nd;
+      }
+      __syncthreads();
+    }
+    if (ovf) atomicOr(&L.ovf_any, 1u);
+    __syncthreads();
+    if (L.ovf_any && tid == 0) L.flags |= FLAG_OVERFLOW;
+    __syncthreads();
+
+    const uint32_t ls = L.lvl[0], lt = L.lvl[1];
+    uint32_t len = 0;
+    uint32_t *path = out.path + (size_t)k * out.stride;
+    if (met && L.flags == 0) {
+      const uint32_t P = L.pi_count;
+      if (P > st.pi_cap || ls + lt + 2 > out.stride) {
+        if (tid == 0) L.flags |= FLAG_CAPACITY;
+      } else {
+        // ---- candidate edges in canonical order (v ascending, then w ascending)
+        uint32_t M = 1;
+        while (M < P) M <<= 1;
+        uint64_t *keys = L.pi;
+        if (P <= (uint32_t)PI_LDS) {
+          for (uint32_t j = P + tid; j < M; j += BLOCK) L.pi[j] = ~0ULL;
+          __syncthreads();
+          bitonic_sort(L.pi, M);
+        } else {
+          for (uint32_t j = tid; j < (uint32_t)PI_LDS; j += BLOCK) gpi[j] = L.pi[j];
+          for (uint32_t j = P + tid; j < M; j += BLOCK) gpi[j] = ~0ULL;
+          __threadfence_block();
+          __syncthreads();
+          bitonic_sort(gpi, M);
+          keys = gpi;
+        }
+        // ---- sigma_st = sum of sigma_s(v) sigma_t(w); draw r < sigma_st
+        bool wov = false;
+        u128 acc{0, 0};
+        for (uint32_t j = tid; j < P; j += BLOCK) {
+          const uint64_t key = keys[j];
+          acc = add128(acc, mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), wov), wov);
+        }
+        u128 total;
+        (void)block_incl_u128(L, acc, total, wov);
+        if (wov) atomicOr(&L.ovf_any, 2u);
+        __syncthreads();
+        if (tid == 0) {
+          if (L.ovf_any & 2u) {
+            L.flags |= FLAG_OVERFLOW;
+          } else {
+            uint32_t fl = 0;
+            const u128 r = uniform_below(total, seed, i, stream_word(phase, P_EDGE, 0), fl);
+            L.flags |= fl;
+            L.r_lo = r.lo;
+            L.r_hi = r.hi;
+          }
+          L.win = 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        if (L.flags == 0) {
+          const u128 r{L.r_lo, L.r_hi};
+          u128 carry{0, 0};
+          for (uint32_t base = 0; base < P; base += BLOCK) {
+            const uint32_t j = base + tid;
+            u128 wt{0, 0};
+            bool dm = false;
+            if (j < P) {
+              const uint64_t key = keys[j];
+              wt = mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), dm);
+            }
+            u128 chunk_total;
+            u128 inc = block_incl_u128(L, wt, chunk_total, dm);
+            inc = add128(inc, carry, dm);
+            const u128 exc = sub128(inc, wt);
+            if (j < P && !lt128(r, exc) && lt128(r, inc)) L.win = j;
+            carry = add128(carry, chunk_total, dm);
+          }
+          __syncthreads();
+          const uint32_t win = L.win;
+          const uint64_t key = keys[win < P ? win : 0];
+          const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
+          // ---- the two halves: wave 0 walks to s, wave 1 walks to t
+          uint32_t fl = 0;
+          if (wid == 0) {
+            if (lane == 0) path[ls] = v;
+            backtrack(g, 0, v, ls, tag, sig, seed, i, phase, path, ls, fl);
+          } else if (wid == 1) {
+            if (lane == 0) path[ls + 1] = w;
+            backtrack(g, 1, w, lt, tag, sig, seed, i, phase, path, ls, fl);
+          }
+          if (win >= P) fl |= FLAG_CAPACITY;
+          if (fl && lane == 0) atomicOr(&L.flags, fl);
+          __syncthreads();
+          if (L.flags == 0) len = ls + lt + 2;
+        }
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      out.s[k] = L.s;
+      out.t[k] = L.t;
+      out.len[k] = L.flags ? 0u : len;
+      out.arcs[k] = L.arcs;
+      out.flags[k] = L.flags;
+      out.nodes[k] = L.nvis;
+    }
+    // ---- restore the slot's all-zero state for the next sample
+    const uint32_t nv = L.nvis;
+    for (uint32_t j = tid; j < nv; j += BLOCK) {
+      const uint32_t v = visit[j];
+      tag[v] = 0;
+      sig[2 * (size_t)v] = 0;
+      sig[2 * (size_t)v + 1] = 0;
+    }
+    __threadfence();
+    __syncthreads();
+  }
+}
+
+// ------------------------------------------------------------------ hit reduction
+constexpr int HIT_BLOCK = 256;
+constexpr uint32_t HIT_TILE = 8192;  // node ids per workgroup (32 KB LDS histogram)
+
+__global__ __launch_bounds__(HIT_BLOCK) void hit_reduce_kernel(const uint32_t *path,
+                                                               const uint32_t *len,
+                                                               uint32_t stride, uint32_t nsamp,
+                                                               uint32_t n, uint64_t *count) {
+  __shared__ uint32_t hist[HIT_TILE];
+  const uint32_t tile0 = blockIdx.x * HIT_TILE;
+  for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) hist[b] = 0;
+  __syncthreads();
+  const uint64_t total = (uint64_t)nsamp * stride;
+  for (uint64_t e = threadIdx.x; e < total; e += HIT_BLOCK) {
+    const uint32_t k = (uint32_t)(e / stride);
+    const uint32_t j = (uint32_t)(e - (uint64_t)k * stride);
+    const uint32_t l = len[k];
+    if (j >= 1 && j + 1 < l) {
+      const uint32_t v = path[e] - tile0;
+      if (v < HIT_TILE) atomicAdd(&hist[v], 1u);
+    }
+  }
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) {
+    const uint32_t h = hist[b];
+    if (h && tile0 + b < n) count[tile0 + b] += h;
+  }
+}
+
+__global__ void zero_u32_kernel(uint32_t *p, uint32_t count) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed, uint32_t phase,
+                          uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
+                          uint32_t grid, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(sampler_kernel, dim3(grid), dim3(BLOCK), 0, stream, g, st, seed, phase,
+                     first, count, work, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t stride,
+                             uint32_t nsamp, uint32_t n, uint64_t *count, hipStream_t stream) {
+  if (nsamp == 0) return hipSuccess;
+  const uint32_t tiles = (n + HIT_TILE - 1) / HIT_TILE;
+  hipLaunchKernelGGL(hit_reduce_kernel, dim3(tiles), dim3(HIT_BLOCK), 0, stream, path, len,
+                     stride, nsamp, n, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(zero_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, stream, p, count);
+  return hipGetLastError();
+}
+
+int sampler_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel, BLOCK, 0) !=
+      hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
+}
+
+}  // namespace kad

@@ -1,0 +1,744 @@
+// C ABI of the sampled-betweenness library: contexts, graphs, the adaptive run
+// (Algorithm 1 of Borassi & Natale with a batched stopping check) and the sampling
+// primitives.  The sampling itself runs in the HIP kernels of kad_kernels.hip; this
+// file moves data, schedules launches and evaluates the binary64 statistics.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <chrono>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/kadabra.h"
+#include "kad_device.h"
+#include "kad_stats.h"
+
+namespace {
+
+thread_local std::string g_error;
+
+kad_status fail(kad_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_error = buf;
+  return st;
+}
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return fail(KAD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t count) {
+    if (count <= n) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) n = count;
+    return e;
+  }
+};
+
+template <typename T>
+struct PinBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  ~PinBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t count) {
+    if (count <= n) return hipSuccess;
+    release();
+    hipError_t e = hipHostMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T),
+                                 hipHostMallocDefault);
+    if (e == hipSuccess) n = count;
+    return e;
+  }
+};
+
+constexpr uint32_t PI_CAP = 65536;       // candidate edges per slot (power of two)
+constexpr uint32_t DEFAULT_BATCH = 65536;
+
+}  // namespace
+
+struct kad_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  uint64_t budget = 0;
+  uint64_t used_graphs = 0;
+  uint32_t cus = 0;
+  int blocks_per_cu = 1;
+  // per-slot working state
+  uint32_t slot_n = 0, slots = 0;
+  DevBuf<uint32_t> tag, visit;
+  DevBuf<uint64_t> sig, pi;
+  // per-launch outputs
+  uint32_t out_cap = 0, out_stride = 0;
+  DevBuf<uint32_t> o_s, o_t, o_len, o_flags, o_nodes, o_path, work;
+  DevBuf<uint64_t> o_arcs, count;
+  PinBuf<uint32_t> h_flags, h_len, h_nodes, h_s, h_t, h_path;
+  PinBuf<uint64_t> h_arcs, h_count;
+  // timing of the sampler launches (HIP events on the launch stream)
+  bool timing = false;
+  uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0;
+  double t_seconds = 0.0;
+};
+
+struct kad_graph {
+  kad_ctx *ctx = nullptr;
+  uint32_t n = 0;
+  uint64_t arcs = 0;
+  bool directed = false;
+  std::vector<uint32_t> row, col, rrow, rcol;  // host copies
+  uint32_t *d_row = nullptr, *d_col = nullptr, *d_rrow = nullptr, *d_rcol = nullptr;
+  bool owns_fwd = false, owns_rev = false;
+  uint64_t bytes = 0;
+  uint32_t vd = 0;
+  bool vd_exact = false, vd_known = false;
+};
+
+namespace {
+
+kad::GraphDev dev_view(const kad_graph *g) {
+  kad::GraphDev d;
+  d.n = g->n;
+  d.arcs = g->arcs;
+  d.row = g->d_row;
+  d.col = g->d_col;
+  d.rrow = g->directed ? g->d_rrow : g->d_row;
+  d.rcol = g->directed ? g->d_rcol : g->d_col;
+  return d;
+}
+
+// Rows sorted strictly ascending, heads in range, no self-loops.
+kad_status check_rows(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32_t *col,
+                      const char *what) {
+  if (row[0] != 0 || row[n] != arcs) return fail(KAD_EINVAL, "%s: row_ptr[0] must be 0 and row_ptr[n] = arcs", what);
+  for (uint32_t v = 0; v < n; ++v) {
+    if (row[v + 1] < row[v]) return fail(KAD_EINVAL, "%s: row_ptr decreases at node %u", what, v);
+    for (uint32_t e = row[v]; e < row[v + 1]; ++e) {
+      const uint32_t x = col[e];
+      if (x >= n) return fail(KAD_EINVAL, "%s: node %u has out-of-range neighbour %u", what, v, x);
+      if (x == v) return fail(KAD_EINVAL, "%s: self-loop at node %u", what, v);
+      if (e > row[v] && col[e - 1] >= x)
+        return fail(KAD_EINVAL, "%s: row %u is not strictly ascending", what, v);
+    }
+  }
+  return KAD_OK;
+}
+
+void transpose(uint32_t n, const std::vector<uint32_t> &row, const std::vector<uint32_t> &col,
+               std::vector<uint32_t> &trow, std::vector<uint32_t> &tcol) {
+  trow.assign((size_t)n + 1, 0);
+  for (uint32_t x : col) trow[x + 1]++;
+  for (uint32_t v = 0; v < n; ++v) trow[v + 1] += trow[v];
+  tcol.resize(col.size());
+  std::vector<uint32_t> fill(trow.begin(), trow.end() - 1);
+  for (uint32_t v = 0; v < n; ++v)
+    for (uint32_t e = row[v]; e < row[v + 1]; ++e) tcol[fill[col[e]]++] = v;  // v ascending
+}
+
+hipStream_t pick_stream(kad_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }
+
+// Size the slot state and output buffers for graph size n and `batch` samples of
+// path stride `stride`.
+kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t stride) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  const uint32_t want_slots = ctx->cus * (uint32_t)ctx->blocks_per_cu;
+  if (ctx->slot_n < n || ctx->slots == 0) {
+    ctx->tag.release();
+    ctx->visit.release();
+    ctx->sig.release();
+    ctx->pi.release();
+    const uint64_t per_slot = (uint64_t)n * (4 + 4 + 16) + (uint64_t)PI_CAP * 8;
+    const uint64_t avail = ctx->budget > ctx->used_graphs + (256ull << 20)
+                               ? ctx->budget - ctx->used_graphs - (256ull << 20)
+                               : 0;
+    uint64_t slots = std::min<uint64_t>(want_slots, avail / per_slot);
+    if (slots == 0)
+      return fail(KAD_ENOMEM, "HBM budget too small for one sampler slot of a %u-node graph", n);
+    ctx->slots = (uint32_t)slots;
+    ctx->slot_n = n;
+    HIP_TRY(ctx->tag.ensure((size_t)slots * n));
+    HIP_TRY(ctx->visit.ensure((size_t)slots * n));
+    HIP_TRY(ctx->sig.ensure((size_t)slots * n * 2));
+    HIP_TRY(ctx->pi.ensure((size_t)slots * PI_CAP));
+    HIP_TRY(hipMemsetAsync(ctx->tag.p, 0, (size_t)slots * n * 4, ctx->stream));
+    HIP_TRY(hipMemsetAsync(ctx->sig.p, 0, (size_t)slots * n * 16, ctx->stream));
+    HIP_TRY(hipStreamSynchronize(ctx->stream));
+  }
+  if (ctx->out_cap < batch || ctx->out_stride < stride) {
+    const uint32_t cap = std::max(batch, ctx->out_cap);
+    const uint32_t st = std::max(stride, ctx->out_stride);
+    for (auto *b : {&ctx->o_s, &ctx->o_t, &ctx->o_len, &ctx->o_flags, &ctx->o_nodes, &ctx->o_path})
+      b->release();
+    ctx->o_arcs.release();
+    HIP_TRY(ctx->o_s.ensure(cap));
+    HIP_TRY(ctx->o_t.ensure(cap));
+    HIP_TRY(ctx->o_len.ensure(cap));
+    HIP_TRY(ctx->o_flags.ensure(cap));
+    HIP_TRY(ctx->o_nodes.ensure(cap));
+    HIP_TRY(ctx->o_arcs.ensure(cap));
+    HIP_TRY(ctx->o_path.ensure((size_t)cap * st));
+    HIP_TRY(ctx->h_flags.ensure(cap));
+    HIP_TRY(ctx->h_len.ensure(cap));
+    HIP_TRY(ctx->h_nodes.ensure(cap));
+    HIP_TRY(ctx->h_arcs.ensure(cap));
+    ctx->out_cap = cap;
+    ctx->out_stride = st;
+  }
+  HIP_TRY(ctx->work.ensure(1));
+  HIP_TRY(ctx->count.ensure(n));
+  HIP_TRY(ctx->h_count.ensure(n));
+  return KAD_OK;
+}
+
+// Launch the sampler on ids [first, first+count) (count <= out_cap) with the
+// context's current stride; optional event timing.
+kad_status run_sampler(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                       uint64_t first, uint32_t count, uint32_t stride, hipStream_t stream) {
+  kad::SlotState st;
+  st.slots = ctx->slots;
+  st.n = g->n;
+  st.pi_cap = PI_CAP;
+  st.tag = ctx->tag.p;
+  st.sig = ctx->sig.p;
+  st.visit = ctx->visit.p;
+  st.pi = ctx->pi.p;
+  kad::SampleOut o;
+  o.s = ctx->o_s.p;
+  o.t = ctx->o_t.p;
+  o.len = ctx->o_len.p;
+  o.flags = ctx->o_flags.p;
+  o.nodes = ctx->o_nodes.p;
+  o.arcs = ctx->o_arcs.p;
+  o.path = ctx->o_path.p;
+  o.stride = stride;
+  HIP_TRY(kad::launch_zero_u32(ctx->work.p, 1, stream));
+  const uint32_t grid = std::min<uint32_t>(ctx->slots, count);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (ctx->timing) {
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    HIP_TRY(hipEventRecord(e0, stream));
+  }
+  HIP_TRY(kad::launch_sampler(dev_view(g), st, seed, phase, first, count, ctx->work.p, o, grid,
+                              stream));
+  if (ctx->timing) {
+    HIP_TRY(hipEventRecord(e1, stream));
+    HIP_TRY(hipEventSynchronize(e1));
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    ctx->t_launches += 1;
+    ctx->t_samples += count;
+    ctx->t_seconds += ms * 1e-3;
+    // work of the timed launch (outside the timed interval): arcs, nodes, hits
+    HIP_TRY(ctx->h_nodes.ensure(count));
+    HIP_TRY(ctx->h_len.ensure(count));
+    HIP_TRY(ctx->h_arcs.ensure(count));
+    HIP_TRY(hipMemcpyAsync(ctx->h_nodes.p, ctx->o_nodes.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_len.p, ctx->o_len.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_arcs.p, ctx->o_arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (uint32_t k = 0; k < count; ++k) {
+      ctx->t_arcs += ctx->h_arcs.p[k];
+      ctx->t_nodes += ctx->h_nodes.p[k];
+      ctx->t_hits += ctx->h_len.p[k] >= 2 ? ctx->h_len.p[k] - 2 : 0;
+    }
+  }
+  return KAD_OK;
+}
+
+// Copy the per-sample flags/arcs of the last launch and reject flagged samples.
+kad_status collect_batch(kad_ctx *ctx, uint32_t count, hipStream_t stream, bool want_nodes) {
+  HIP_TRY(hipMemcpyAsync(ctx->h_flags.p, ctx->o_flags.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(ctx->h_arcs.p, ctx->o_arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
+  if (want_nodes) {
+    HIP_TRY(hipMemcpyAsync(ctx->h_nodes.p, ctx->o_nodes.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_len.p, ctx->o_len.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+  }
+  HIP_TRY(hipStreamSynchronize(stream));
+  for (uint32_t k = 0; k < count; ++k) {
+    const uint32_t f = ctx->h_flags.p[k];
+    if (f & kad::FLAG_OVERFLOW)
+      return fail(KAD_EOVERFLOW, "a path count exceeded 128 bits (sample %u of the batch)", k);
+    if (f & kad::FLAG_RNG) return fail(KAD_ERNG, "bounded draw rejected 64 times");
+    if (f & kad::FLAG_CAPACITY)
+      return fail(KAD_EOVERFLOW, "candidate-edge list or path outgrew its buffer (sample %u)", k);
+  }
+  return KAD_OK;
+}
+
+kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact) {
+  if (!g->vd_known) {
+    bool ex = false;
+    const uint32_t *rr = g->directed ? g->rrow.data() : g->row.data();
+    const uint32_t *rc = g->directed ? g->rcol.data() : g->col.data();
+    if (kad::vertex_diameter(g->n, g->arcs, g->row.data(), g->col.data(), rr, rc, 1e9, &g->vd, &ex))
+      return fail(KAD_EINVAL, "vertex diameter: bad graph");
+    g->vd_exact = ex;
+    g->vd_known = true;
+  }
+  *vd = g->vd;
+  *exact = g->vd_exact;
+  return KAD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *kad_last_error(void) { return g_error.c_str(); }
+
+kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **out) {
+  if (!out) return fail(KAD_EINVAL, "out is NULL");
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0)
+    return fail(KAD_EDEVICE, "no HIP device available");
+  if (hip_device < 0 || hip_device >= ndev) return fail(KAD_EDEVICE, "device %d does not exist", hip_device);
+  std::unique_ptr<kad_ctx> c(new kad_ctx());
+  c->device = hip_device;
+  HIP_TRY(hipSetDevice(hip_device));
+  HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  hipDeviceProp_t prop;
+  HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
+  c->cus = (uint32_t)prop.multiProcessorCount;
+  c->blocks_per_cu = kad::sampler_blocks_per_cu();
+  size_t free_b = 0, total_b = 0;
+  HIP_TRY(hipMemGetInfo(&free_b, &total_b));
+  c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+  *out = c.release();
+  return KAD_OK;
+}
+
+kad_status kad_ctx_destroy(kad_ctx *ctx) {
+  if (!ctx) return KAD_OK;
+  (void)hipSetDevice(ctx->device);
+  if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return KAD_OK;
+}
+
+kad_status kad_graph_create(kad_ctx *ctx, uint32_t n, uint64_t arcs, int directed,
+                            const uint32_t *row_ptr, const uint32_t *col,
+                            const uint32_t *rrow_ptr, const uint32_t *rcol, int mem,
+                            kad_graph **out) {
+  if (!ctx || !out || !row_ptr || (!col && arcs)) return fail(KAD_EINVAL, "NULL argument");
+  *out = nullptr;
+  if (n < 2) return fail(KAD_EINVAL, "a graph needs at least 2 nodes");
+  if (arcs >= (1ull << 32)) return fail(KAD_EINVAL, "arcs must be below 2^32");
+  if (mem != KAD_MEM_HOST && mem != KAD_MEM_DEVICE) return fail(KAD_EINVAL, "bad mem kind");
+  HIP_TRY(hipSetDevice(ctx->device));
+  std::unique_ptr<kad_graph> g(new kad_graph());
+  g->ctx = ctx;
+  g->n = n;
+  g->arcs = arcs;
+  g->directed = directed != 0;
+  g->row.resize((size_t)n + 1);
+  g->col.resize(arcs);
+  auto fetch = [&](std::vector<uint32_t> &dst, const uint32_t *src, size_t cnt) -> hipError_t {
+    if (cnt == 0) return hipSuccess;
+    if (mem == KAD_MEM_HOST) {
+      memcpy(dst.data(), src, cnt * 4);
+      return hipSuccess;
+    }
+    return hipMemcpy(dst.data(), src, cnt * 4, hipMemcpyDeviceToHost);
+  };
+  HIP_TRY(fetch(g->row, row_ptr, (size_t)n + 1));
+  HIP_TRY(fetch(g->col, col, arcs));
+  kad_status st = check_rows(n, arcs, g->row.data(), g->col.data(), "out-rows");
+  if (st) return st;
+  std::vector<uint32_t> trow, tcol;
+  transpose(n, g->row, g->col, trow, tcol);
+  if (!g->directed) {
+    if (trow != g->row || tcol != g->col) return fail(KAD_EINVAL, "undirected graph is not symmetric");
+  } else if (rrow_ptr && rcol) {
+    g->rrow.resize((size_t)n + 1);
+    g->rcol.resize(arcs);
+    HIP_TRY(fetch(g->rrow, rrow_ptr, (size_t)n + 1));
+    HIP_TRY(fetch(g->rcol, rcol, arcs));
+    if (g->rrow != trow || g->rcol != tcol) return fail(KAD_EINVAL, "in-rows are not the transpose of the out-rows");
+  } else {
+    g->rrow.swap(trow);
+    g->rcol.swap(tcol);
+  }
+  const bool borrow = mem == KAD_MEM_DEVICE;
+  const size_t rbytes = ((size_t)n + 1) * 4, cbytes = (size_t)arcs * 4;
+  if (borrow) {
+    g->d_row = const_cast<uint32_t *>(row_ptr);
+    g->d_col = const_cast<uint32_t *>(col);
+  } else {
+    g->owns_fwd = true;
+    HIP_TRY(hipMalloc((void **)&g->d_row, rbytes));
+    HIP_TRY(hipMalloc((void **)&g->d_col, std::max<size_t>(cbytes, 4)));
+    HIP_TRY(hipMemcpy(g->d_row, g->row.data(), rbytes, hipMemcpyHostToDevice));
+    if (cbytes) HIP_TRY(hipMemcpy(g->d_col, g->col.data(), cbytes, hipMemcpyHostToDevice));
+    g->bytes += rbytes + cbytes;
+  }
+  if (g->directed) {
+    if (borrow && rrow_ptr && rcol) {
+      g->d_rrow = const_cast<uint32_t *>(rrow_ptr);
+      g->d_rcol = const_cast<uint32_t *>(rcol);
+    } else {
+      g->owns_rev = true;
+      HIP_TRY(hipMalloc((void **)&g->d_rrow, rbytes));
+      HIP_TRY(hipMalloc((void **)&g->d_rcol, std::max<size_t>(cbytes, 4)));
+      HIP_TRY(hipMemcpy(g->d_rrow, g->rrow.data(), rbytes, hipMemcpyHostToDevice));
+      if (cbytes) HIP_TRY(hipMemcpy(g->d_rcol, g->rcol.data(), cbytes, hipMemcpyHostToDevice));
+      g->bytes += rbytes + cbytes;
+    }
+  }
+  ctx->used_graphs += g->bytes;
+  *out = g.release();
+  return KAD_OK;
+}
+
+kad_status kad_graph_destroy(kad_graph *g) {
+  if (!g) return KAD_OK;
+  (void)hipSetDevice(g->ctx->device);
+  if (g->owns_fwd) {
+    (void)hipFree(g->d_row);
+    (void)hipFree(g->d_col);
+  }
+  if (g->owns_rev) {
+    (void)hipFree(g->d_rrow);
+    (void)hipFree(g->d_rcol);
+  }
+  g->ctx->used_graphs -= std::min(g->ctx->used_graphs, g->bytes);
+  delete g;
+  return KAD_OK;
+}
+
+// ---------------------------------------------------------------- host statistics
+
+uint64_t kad_omega(double epsilon, double delta, uint32_t vd, double c) {
+  return kad::omega_of(epsilon, delta, vd, c > 0 ? c : 0.5);
+}
+uint64_t kad_alpha(uint64_t omega) { return kad::alpha_of(omega); }
+uint64_t kad_default_interval(uint64_t omega) { return kad::interval_of(omega); }
+
+kad_status kad_vertex_diameter(uint32_t n, uint64_t arcs, int directed, const uint32_t *row_ptr,
+                               const uint32_t *col, const uint32_t *rrow_ptr,
+                               const uint32_t *rcol, double exact_limit, uint32_t *vd,
+                               uint32_t *exact) {
+  if (!vd || !exact || !row_ptr || (arcs && !col)) return fail(KAD_EINVAL, "NULL argument");
+  if (directed && (!rrow_ptr || !rcol)) return fail(KAD_EINVAL, "directed graph needs in-rows");
+  bool ex = false;
+  if (kad::vertex_diameter(n, arcs, row_ptr, col, directed ? rrow_ptr : row_ptr,
+                           directed ? rcol : col, exact_limit, vd, &ex))
+    return fail(KAD_EINVAL, "bad graph");
+  *exact = ex ? 1u : 0u;
+  return KAD_OK;
+}
+
+double kad_bound_f(double btilde, double L, double omega, double tau) {
+  return kad::bound_f(btilde, L, omega, tau);
+}
+double kad_bound_g(double btilde, double L, double omega, double tau) {
+  return kad::bound_g(btilde, L, omega, tau);
+}
+
+kad_status kad_compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
+                             const double *lambda_l, const double *lambda_u, double delta,
+                             double balance_eps, double *L_l, double *L_u, double *C) {
+  if (!n || !count0 || !lambda_l || !lambda_u || !L_l || !L_u || !alpha)
+    return fail(KAD_EINVAL, "bad argument");
+  if (!(delta > 0 && delta < 1) || !(balance_eps > 0 && balance_eps < 0.5))
+    return fail(KAD_EINVAL, "delta must be in (0,1) and balance_eps in (0,0.5)");
+  kad::compute_delta(n, count0, alpha, omega, lambda_l, lambda_u, delta, balance_eps, L_l, L_u, C);
+  return KAD_OK;
+}
+
+kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha,
+                            double epsilon, double *lambda_l, double *lambda_u) {
+  if (!n || k < 1 || k > n || !count0 || !lambda_l || !lambda_u || !alpha)
+    return fail(KAD_EINVAL, "bad argument");
+  kad::topk_lambdas(n, k, count0, alpha, epsilon, lambda_l, lambda_u);
+  return KAD_OK;
+}
+
+int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *count, uint64_t tau,
+                     uint64_t omega, double epsilon, const double *L_l, const double *L_u) {
+  if (!n || !count || !L_l || !L_u || tau == 0) return fail(KAD_EINVAL, "bad argument");
+  if (mode != KAD_ALL_NODES && mode != KAD_TOPK) return fail(KAD_EINVAL, "bad mode");
+  if (mode == KAD_TOPK && (k < 1 || k > n)) return fail(KAD_EINVAL, "k out of range");
+  // the same grouped evaluation that kad_run uses at every check
+  kad::StopChecker checker(n, mode, k, epsilon, omega, L_l, L_u);
+  return checker.check(count, tau) ? 1 : 0;
+}
+
+// ---------------------------------------------------------------- sampling primitives
+
+kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                            uint64_t first, uint32_t count, uint32_t *s, uint32_t *t,
+                            uint64_t *path_off, uint32_t *path_nodes, uint64_t path_cap,
+                            uint64_t *arcs_scanned, uint32_t *flags, void *hip_stream) {
+  if (!ctx || !g) return fail(KAD_EINVAL, "NULL context or graph");
+  if (path_nodes && !path_off) return fail(KAD_EINVAL, "path_nodes needs path_off");
+  if (phase > 255) return fail(KAD_EINVAL, "phase must fit 8 bits");
+  kad_graph *gm = const_cast<kad_graph *>(g);
+  uint32_t vd;
+  bool ex;
+  kad_status st = graph_vd(gm, &vd, &ex);
+  if (st) return st;
+  const uint32_t stride = std::max<uint32_t>(vd, 2);
+  const uint32_t batch = std::min<uint32_t>(std::max<uint32_t>(count, 1), DEFAULT_BATCH);
+  if ((st = ensure_capacity(ctx, g->n, batch, stride))) return st;
+  hipStream_t stream = pick_stream(ctx, hip_stream);
+  HIP_TRY(ctx->h_s.ensure(batch));
+  HIP_TRY(ctx->h_t.ensure(batch));
+  HIP_TRY(ctx->h_path.ensure((size_t)batch * stride));
+  uint64_t off = 0;
+  bool short_buf = false;
+  for (uint64_t done = 0; done < count;) {
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
+    if ((st = run_sampler(ctx, g, seed, phase, first + done, nb, stride, stream))) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->h_s.p, ctx->o_s.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_t.p, ctx->o_t.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_len.p, ctx->o_len.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_flags.p, ctx->o_flags.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_arcs.p, ctx->o_arcs.p, (size_t)nb * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_path.p, ctx->o_path.p, (size_t)nb * stride * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    for (uint32_t k = 0; k < nb; ++k) {
+      const uint64_t idx = done + k;
+      if (s) s[idx] = ctx->h_s.p[k];
+      if (t) t[idx] = ctx->h_t.p[k];
+      if (arcs_scanned) arcs_scanned[idx] = ctx->h_arcs.p[k];
+      if (flags) flags[idx] = ctx->h_flags.p[k];
+      const uint32_t len = ctx->h_len.p[k];
+      if (path_off) path_off[idx] = off;
+      if (path_nodes) {
+        if (off + len <= path_cap)
+          memcpy(path_nodes + off, ctx->h_path.p + (size_t)k * stride, (size_t)len * 4);
+        else
+          short_buf = true;
+      }
+      off += len;
+    }
+    done += nb;
+  }
+  if (path_off) path_off[count] = off;
+  if (short_buf) return fail(KAD_ETOOSMALL, "path_nodes needs %llu entries", (unsigned long long)off);
+  return KAD_OK;
+}
+
+kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                          uint64_t first, uint64_t count, uint64_t *count_out,
+                          uint64_t *arcs_scanned, void *hip_stream) {
+  if (!ctx || !g || !count_out) return fail(KAD_EINVAL, "NULL argument");
+  kad_graph *gm = const_cast<kad_graph *>(g);
+  uint32_t vd;
+  bool ex;
+  kad_status st = graph_vd(gm, &vd, &ex);
+  if (st) return st;
+  const uint32_t stride = std::max<uint32_t>(vd, 2);
+  const uint32_t batch = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(count, 1), DEFAULT_BATCH);
+  if ((st = ensure_capacity(ctx, g->n, batch, stride))) return st;
+  hipStream_t stream = pick_stream(ctx, hip_stream);
+  HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)g->n * 8, stream));
+  uint64_t arcs = 0;
+  for (uint64_t done = 0; done < count;) {
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
+    if ((st = run_sampler(ctx, g, seed, phase, first + done, nb, stride, stream))) return st;
+    if ((st = collect_batch(ctx, nb, stream, false))) return st;
+    for (uint32_t k = 0; k < nb; ++k) arcs += ctx->h_arcs.p[k];
+    HIP_TRY(kad::launch_hit_reduce(ctx->o_path.p, ctx->o_len.p, stride, nb, g->n, ctx->count.p, stream));
+    done += nb;
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)g->n * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  for (uint32_t v = 0; v < g->n; ++v) count_out[v] += ctx->h_count.p[v];
+  if (arcs_scanned) *arcs_scanned = arcs;
+  return KAD_OK;
+}
+
+// ---------------------------------------------------------------- the adaptive run
+
+kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_result *r,
+                   void *hip_stream) {
+  using clock = std::chrono::steady_clock;
+  const auto t0 = clock::now();
+  if (!ctx || !g || !p || !r) return fail(KAD_EINVAL, "NULL argument");
+  if (!(p->epsilon > 0 && p->epsilon < 1)) return fail(KAD_EINVAL, "epsilon must be in (0,1)");
+  if (!(p->delta > 0 && p->delta < 1)) return fail(KAD_EINVAL, "delta must be in (0,1)");
+  if (p->mode != KAD_ALL_NODES && p->mode != KAD_TOPK) return fail(KAD_EINVAL, "bad mode");
+  if (p->mode == KAD_TOPK && (p->k < 1 || p->k > g->n)) return fail(KAD_EINVAL, "k must be in [1, n]");
+  if (p->reserved != 0) return fail(KAD_EINVAL, "reserved must be 0");
+  const double c = p->c > 0 ? p->c : 0.5;
+  const double eb = p->balance_eps > 0 ? p->balance_eps : 0.001;
+  if (!(eb < 0.5)) return fail(KAD_EINVAL, "balance_eps must be below 0.5");
+  kad_graph *gm = const_cast<kad_graph *>(g);
+  const uint32_t n = g->n;
+  kad_status st;
+
+  uint32_t vd;
+  bool vd_exact = false;
+  if (p->vd_override) {
+    vd = p->vd_override;
+  } else if ((st = graph_vd(gm, &vd, &vd_exact))) {
+    return st;
+  }
+  const uint64_t omega = kad::omega_of(p->epsilon, p->delta, vd, c);
+  const uint64_t alpha = kad::alpha_of(omega);
+  const uint64_t B = p->check_interval ? p->check_interval : kad::interval_of(omega);
+  uint64_t K = p->kernel_batch ? p->kernel_batch : DEFAULT_BATCH;
+  K = std::max<uint64_t>(B, (K + B - 1) / B * B);
+  if (K > (1u << 30)) return fail(KAD_EINVAL, "kernel_batch too large");
+  const uint32_t stride = std::max<uint32_t>(vd, 2);
+  if ((st = ensure_capacity(ctx, n, (uint32_t)K, stride))) return st;
+  hipStream_t stream = pick_stream(ctx, hip_stream);
+
+  // ---- pilot (phase 0): alpha samples -> count0
+  std::vector<uint64_t> count0(n, 0);
+  HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, stream));
+  uint64_t pilot_arcs = 0;
+  for (uint64_t done = 0; done < alpha;) {
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->out_cap, alpha - done);
+    if ((st = run_sampler(ctx, g, p->seed, 0, done, nb, stride, stream))) return st;
+    if ((st = collect_batch(ctx, nb, stream, false))) return st;
+    for (uint32_t k = 0; k < nb; ++k) pilot_arcs += ctx->h_arcs.p[k];
+    HIP_TRY(kad::launch_hit_reduce(ctx->o_path.p, ctx->o_len.p, stride, nb, n, ctx->count.p, stream));
+    done += nb;
+  }
+  HIP_TRY(hipMemcpyAsync(count0.data(), ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+
+  // ---- computeDelta (host, binary64)
+  std::vector<double> lam_l(n, p->epsilon), lam_u(n, p->epsilon), L_l(n), L_u(n);
+  if (p->mode == KAD_TOPK) kad::topk_lambdas(n, p->k, count0.data(), alpha, p->epsilon, lam_l.data(), lam_u.data());
+  double Cb = 0;
+  kad::compute_delta(n, count0.data(), alpha, omega, lam_l.data(), lam_u.data(), p->delta, eb,
+                     L_l.data(), L_u.data(), &Cb);
+  kad::StopChecker checker(n, p->mode, p->k, p->epsilon, omega, L_l.data(), L_u.data());
+
+  // ---- main phase (phase 1): batches of K samples, a check every B samples
+  HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, stream));
+  uint64_t tau = 0, arcs = 0;
+  bool rule = false, stop = false;
+  while (!stop) {
+    // a whole number of check intervals (the last batch may end at omega)
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(K, omega - tau);
+    if ((st = run_sampler(ctx, g, p->seed, 1, tau, nb, stride, stream))) return st;
+    if ((st = collect_batch(ctx, nb, stream, false))) return st;
+    for (uint32_t c0 = 0; c0 < nb && !stop;) {
+      const uint32_t cb = (uint32_t)std::min<uint64_t>(B, nb - c0);
+      HIP_TRY(kad::launch_hit_reduce(ctx->o_path.p + (size_t)c0 * stride, ctx->o_len.p + c0, stride, cb, n,
+                                     ctx->count.p, stream));
+      HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+      HIP_TRY(hipStreamSynchronize(stream));
+      for (uint32_t k = c0; k < c0 + cb; ++k) arcs += ctx->h_arcs.p[k];
+      tau += cb;
+      c0 += cb;
+      if (tau >= omega) {
+        stop = true;
+      } else if (cb == B && checker.check(ctx->h_count.p, tau)) {
+        stop = true;
+        rule = true;
+      }
+    }
+  }
+
+  // ---- outputs (Theorem 1 intervals)
+  r->tau = tau;
+  r->omega = omega;
+  r->alpha = alpha;
+  r->interval = B;
+  r->arcs_scanned = arcs;
+  r->pilot_arcs_scanned = pilot_arcs;
+  r->overflow_samples = 0;
+  r->vd = vd;
+  r->vd_exact = vd_exact ? 1u : 0u;
+  r->stop_reason = rule ? KAD_STOP_RULE : KAD_STOP_OMEGA;
+  r->n = n;
+  r->C = Cb;
+  const uint64_t *cnt = ctx->h_count.p;
+  std::vector<double> bc(n), lo(n), hi(n);
+  const double T = (double)tau, W = (double)omega;
+  for (uint32_t v = 0; v < n; ++v) {
+    bc[v] = (double)cnt[v] / T;
+    if (rule) {
+      lo[v] = bc[v] - kad::bound_f(bc[v], L_l[v], W, T);
+      hi[v] = bc[v] + kad::bound_g(bc[v], L_u[v], W, T);
+    } else {
+      lo[v] = bc[v] - p->epsilon;
+      hi[v] = bc[v] + p->epsilon;
+    }
+  }
+  if (r->count) memcpy(r->count, cnt, (size_t)n * 8);
+  if (r->bc) memcpy(r->bc, bc.data(), (size_t)n * 8);
+  if (r->lower) memcpy(r->lower, lo.data(), (size_t)n * 8);
+  if (r->upper) memcpy(r->upper, hi.data(), (size_t)n * 8);
+  r->topk_len = 0;
+  kad_status ret = KAD_OK;
+  if (p->mode == KAD_TOPK) {
+    std::vector<uint32_t> rlo(n), rhi(n), sel;
+    kad::rank_intervals(n, lo.data(), hi.data(), rlo.data(), rhi.data());
+    for (uint32_t v = 0; v < n; ++v)
+      if (rlo[v] <= p->k) sel.push_back(v);
+    std::sort(sel.begin(), sel.end(), [cnt](uint32_t a, uint32_t b) {
+      return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b;
+    });
+    r->topk_len = (uint32_t)sel.size();
+    if (sel.size() > r->topk_cap) {
+      ret = fail(KAD_ETOOSMALL, "top-k output needs %zu entries", sel.size());
+    } else {
+      for (size_t q = 0; q < sel.size(); ++q) {
+        if (r->topk_node) r->topk_node[q] = sel[q];
+        if (r->rank_lo) r->rank_lo[q] = rlo[sel[q]];
+        if (r->rank_hi) r->rank_hi[q] = rhi[sel[q]];
+      }
+    }
+  }
+  r->seconds = std::chrono::duration<double>(clock::now() - t0).count();
+  return ret;
+}
+
+// ---------------------------------------------------------------- timing (bench support)
+
+kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  ctx->timing = enable != 0;
+  ctx->t_launches = ctx->t_samples = ctx->t_arcs = ctx->t_nodes = ctx->t_hits = 0;
+  ctx->t_seconds = 0.0;
+  return KAD_OK;
+}
+
+kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *samples,
+                              double *seconds, uint64_t *arcs, uint64_t *nodes, uint64_t *hits) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  if (launches) *launches = ctx->t_launches;
+  if (samples) *samples = ctx->t_samples;
+  if (seconds) *seconds = ctx->t_seconds;
+  if (arcs) *arcs = ctx->t_arcs;
+  if (nodes) *nodes = ctx->t_nodes;
+  if (hits) *hits = ctx->t_hits;
+  return KAD_OK;
+}
+
+}  // extern "C"

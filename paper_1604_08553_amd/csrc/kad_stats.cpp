@@ -1,0 +1,385 @@
+// Host-side statistics of the adaptive betweenness algorithm (Borassi & Natale):
+// the sample cap omega (Algorithm 1), the vertex diameter it needs, computeDelta
+// (Algorithm 2, appendix "How to choose delta_L, delta_U"), the bounds f and g of
+// Theorem azuma-borassi, the all-nodes and top-k stopping conditions (section 2,
+// Algorithm 3), the top-k half-widths (section 5) and the rank intervals of the
+// top-k output.  Binary64 throughout, no FMA contraction, glibc exp/log.
+#include "kad_stats.h"
+
+#include <math.h>
+
+#include <algorithm>
+#include <map>
+#include <thread>
+#include <utility>
+#include <vector>
+
+namespace kad {
+
+// ------------------------------------------------------------------ schedule
+
+uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c) {
+  // floor(log2(VD - 2)) + 1, with VD <= 3 giving 0 + 1
+  const uint32_t base = vd > 3 ? vd - 2 : 1u;
+  uint32_t fl = 0;
+  for (uint32_t x = base; x > 1; x >>= 1) ++fl;
+  const double bits = (double)(fl + 1);
+  const double value = c / (epsilon * epsilon) * (bits + log(2.0 / delta));
+  return (uint64_t)ceil(value);
+}
+
+uint64_t alpha_of(uint64_t omega) { return std::max<uint64_t>(1, omega / 100); }
+
+uint64_t interval_of(uint64_t omega) {
+  const uint64_t q = omega / 16;
+  uint64_t p = 1;
+  while (2 * p <= q) p *= 2;
+  return std::min<uint64_t>(65536, std::max<uint64_t>(1024, p));
+}
+
+// ------------------------------------------------------------------ f and g
+
+double bound_f(double bt, double L, double omega, double tau) {
+  // (L/tau) * (a + sqrt(a^2 + x)) with a = 1/3 - omega/tau < 0 and x = 2 bt omega / L,
+  // evaluated as (L/tau) * x / (sqrt(a^2 + x) - a), free of cancellation.
+  const double a = 1.0 / 3.0 - omega / tau;
+  const double x = 2.0 * bt * omega / L;
+  return (L / tau) * (x / (sqrt(a * a + x) - a));
+}
+
+double bound_g(double bt, double L, double omega, double tau) {
+  const double b = 1.0 / 3.0 + omega / tau;
+  const double x = 2.0 * bt * omega / L;
+  return (L / tau) * (b + sqrt(b * b + x));
+}
+
+// ------------------------------------------------------------------ vertex diameter
+
+namespace {
+
+// Distances by BFS from src over rows (rp, cl); only nodes with comp[x] == c when comp
+// is given.  Returns the eccentricity (largest finite distance).
+uint32_t bfs_farthest(const uint32_t *rp, const uint32_t *cl, uint32_t src,
+                      const std::vector<uint32_t> *comp, uint32_t c, std::vector<uint32_t> &dist,
+                      std::vector<uint32_t> &queue) {
+  size_t head = 0, tail = 0;
+  dist[src] = 0;
+  queue[tail++] = src;
+  uint32_t far = 0;
+  while (head < tail) {
+    const uint32_t u = queue[head++];
+    far = std::max(far, dist[u]);
+    for (uint32_t e = rp[u]; e < rp[u + 1]; ++e) {
+      const uint32_t x = cl[e];
+      if (dist[x] != UINT32_MAX) continue;
+      if (comp && (*comp)[x] != c) continue;
+      dist[x] = dist[u] + 1;
+      queue[tail++] = x;
+    }
+  }
+  for (size_t q = 0; q < tail; ++q) dist[queue[q]] = UINT32_MAX;
+  return far;
+}
+
+// Strongly connected components by Tarjan's algorithm (iterative).  Components are
+// numbered in the order Tarjan completes them, which is a reverse topological order
+// of the condensation: every arc u->x between components has comp[u] > comp[x].
+uint32_t tarjan_scc(uint32_t n, const uint32_t *row, const uint32_t *col,
+                    std::vector<uint32_t> &comp) {
+  std::vector<uint32_t> index(n, UINT32_MAX), low(n, 0), stack, call, edge;
+  std::vector<uint8_t> on_stack(n, 0);
+  comp.assign(n, UINT32_MAX);
+  uint32_t next_index = 0, ncomp = 0;
+  stack.reserve(n);
+  for (uint32_t root = 0; root < n; ++root) {
+    if (index[root] != UINT32_MAX) continue;
+    call.push_back(root);
+    edge.push_back(row[root]);
+    index[root] = low[root] = next_index++;
+    stack.push_back(root);
+    on_stack[root] = 1;
+    while (!call.empty()) {
+      const uint32_t u = call.back();
+      uint32_t &e = edge.back();
+      if (e < row[u + 1]) {
+        const uint32_t x = col[e++];
+        if (index[x] == UINT32_MAX) {
+          index[x] = low[x] = next_index++;
+          stack.push_back(x);
+          on_stack[x] = 1;
+          call.push_back(x);
+          edge.push_back(row[x]);
+        } else if (on_stack[x]) {
+          low[u] = std::min(low[u], index[x]);
+        }
+        continue;
+      }
+      if (low[u] == index[u]) {
+        uint32_t x;
+        do {
+          x = stack.back();
+          stack.pop_back();
+          on_stack[x] = 0;
+          comp[x] = ncomp;
+        } while (x != u);
+        ++ncomp;
+      }
+      call.pop_back();
+      edge.pop_back();
+      if (!call.empty()) low[call.back()] = std::min(low[call.back()], low[u]);
+    }
+  }
+  return ncomp;
+}
+
+}  // namespace
+
+int vertex_diameter(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32_t *col,
+                    const uint32_t *rrow, const uint32_t *rcol, double exact_limit, uint32_t *vd,
+                    bool *exact) {
+  if (n == 0 || !row || !rrow || (arcs && (!col || !rcol))) return -1;
+  if ((double)n * (double)arcs <= exact_limit) {
+    // exact: the largest BFS eccentricity over all sources, plus one node
+    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    std::vector<uint32_t> best(nt, 0);
+    std::vector<std::thread> pool;
+    for (unsigned w = 0; w < nt; ++w) {
+      pool.emplace_back([&, w]() {
+        std::vector<uint32_t> dist(n, UINT32_MAX), queue(n);
+        for (uint32_t s = w; s < n; s += nt)
+          best[w] = std::max(best[w], bfs_farthest(row, col, s, nullptr, 0, dist, queue));
+      });
+    }
+    for (auto &t : pool) t.join();
+    *vd = *std::max_element(best.begin(), best.end()) + 1;
+    *exact = true;
+    return 0;
+  }
+  // bound over the condensation: weight(C) = ecc_out_C(r) + ecc_in_C(r) + 1
+  std::vector<uint32_t> comp;
+  const uint32_t nc = tarjan_scc(n, row, col, comp);
+  std::vector<uint32_t> root(nc, UINT32_MAX);
+  std::vector<uint64_t> root_deg(nc, 0);
+  for (uint32_t v = 0; v < n; ++v) {
+    const uint64_t d = (uint64_t)(row[v + 1] - row[v]) + (rrow[v + 1] - rrow[v]);
+    const uint32_t c = comp[v];
+    if (root[c] == UINT32_MAX || d > root_deg[c]) {
+      root[c] = v;
+      root_deg[c] = d;
+    }
+  }
+  std::vector<uint32_t> dist(n, UINT32_MAX), queue(n);
+  std::vector<uint64_t> weight(nc);
+  for (uint32_t c = 0; c < nc; ++c) {
+    weight[c] = (uint64_t)bfs_farthest(row, col, root[c], &comp, c, dist, queue) +
+                bfs_farthest(rrow, rcol, root[c], &comp, c, dist, queue) + 1;
+  }
+  // Tarjan numbering is reverse topological: process components from the highest id
+  // (sources) down; heaviest[c] = weight[c] + max over arcs into c.
+  std::vector<uint64_t> heaviest(nc, 0);
+  std::vector<std::vector<uint32_t>> members(nc);
+  for (uint32_t v = 0; v < n; ++v) members[comp[v]].push_back(v);
+  uint64_t answer = 0;
+  for (uint32_t c = nc; c-- > 0;) {
+    uint64_t in_best = 0;
+    for (uint32_t v : members[c])
+      for (uint32_t e = rrow[v]; e < rrow[v + 1]; ++e) {
+        const uint32_t c2 = comp[rcol[e]];
+        if (c2 != c) in_best = std::max(in_best, heaviest[c2]);
+      }
+    heaviest[c] = in_best + weight[c];
+    answer = std::max(answer, heaviest[c]);
+  }
+  *vd = (uint32_t)std::min<uint64_t>(answer, UINT32_MAX);
+  *exact = false;
+  return 0;
+}
+
+// ------------------------------------------------------------------ computeDelta
+
+void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
+                   const double *lam_l, const double *lam_u, double delta, double eps_bal,
+                   double *L_l, double *L_u, double *C_out) {
+  std::vector<double> cl(n), cu(n), vals(2 * (size_t)n);
+  for (uint32_t v = 0; v < n; ++v) {
+    const double b0 = (double)count0[v] / (double)alpha;
+    cl[v] = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
+    cu[v] = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
+    vals[2 * (size_t)v] = cl[v];
+    vals[2 * (size_t)v + 1] = cu[v];
+  }
+  std::sort(vals.begin(), vals.end());
+  // distinct constants with multiplicities, ascending
+  std::vector<std::pair<double, double>> groups;
+  for (double x : vals) {
+    if (!groups.empty() && groups.back().first == x)
+      groups.back().second += 1.0;
+    else
+      groups.emplace_back(x, 1.0);
+  }
+  auto term = [](double C, double c) { return c == 0.0 ? 0.0 : exp(-C / c); };
+  auto total = [&](double C) {
+    double s = 0.0;
+    for (const auto &g : groups) s += g.second * term(C, g.first);
+    return s;
+  };
+  // smallest C with total(C) <= delta/2 - eps*delta (the sum decreases in C)
+  const double target = delta / 2.0 - eps_bal * delta;
+  double lo = 0.0, hi = 1.0;
+  while (total(hi) > target) hi *= 2.0;
+  for (int it = 0; it < 100; ++it) {
+    const double mid = (lo + hi) / 2.0;
+    if (total(mid) > target)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const double C = hi;
+  const double floor_add = eps_bal * delta / (2.0 * (double)n);
+  for (uint32_t v = 0; v < n; ++v) {
+    L_l[v] = -log(term(C, cl[v]) + floor_add);
+    L_u[v] = -log(term(C, cu[v]) + floor_add);
+  }
+  if (C_out) *C_out = C;
+}
+
+// ------------------------------------------------------------------ top-k half-widths
+
+namespace {
+// nodes by count descending, id ascending
+void estimate_order(uint32_t n, const uint64_t *count, std::vector<uint32_t> &ord) {
+  ord.resize(n);
+  for (uint32_t v = 0; v < n; ++v) ord[v] = v;
+  std::sort(ord.begin(), ord.end(), [count](uint32_t a, uint32_t b) {
+    return count[a] != count[b] ? count[a] > count[b] : a < b;
+  });
+}
+double clamp_unit(double x, double eps) { return std::min(1.0, std::max(eps, x)); }
+}  // namespace
+
+void topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha, double eps,
+                  double *lam_l, double *lam_u) {
+  std::vector<uint32_t> ord;
+  estimate_order(n, count0, ord);
+  const double A = (double)alpha;
+  auto b0 = [&](uint32_t pos) { return (double)count0[ord[pos]] / A; };
+  std::vector<uint8_t> tie(n, 0);
+  for (uint32_t i = 0; i < k; ++i)
+    if (i + 1 < n && b0(i) - b0(i + 1) < 2.0 * eps) tie[i] = tie[i + 1] = 1;
+  for (uint32_t i = 0; i < k; ++i) {
+    const uint32_t v = ord[i];
+    double up = i == 0 ? 1.0 : (b0(i - 1) - b0(i)) / 2.0;
+    double dn = i + 1 < n ? (b0(i) - b0(i + 1)) / 2.0 : 1.0;
+    if (tie[i]) up = dn = eps;
+    lam_u[v] = clamp_unit(up, eps);
+    lam_l[v] = clamp_unit(dn, eps);
+  }
+  const double kth_low = b0(k - 1) - lam_l[ord[k - 1]];
+  for (uint32_t i = k; i < n; ++i) {
+    const uint32_t v = ord[i];
+    if (tie[i]) {
+      lam_l[v] = lam_u[v] = eps;
+    } else {
+      lam_l[v] = 1.0;
+      lam_u[v] = clamp_unit(kth_low - b0(i), eps);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ stopping conditions
+
+StopChecker::StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
+                         const double *L_l, const double *L_u)
+    : n_(n), mode_(mode), k_(k), eps_(eps), omega_(omega), Ll_(L_l), Lu_(L_u) {
+  std::map<std::pair<double, double>, uint32_t> ids;
+  group_.resize(n);
+  for (uint32_t v = 0; v < n; ++v) {
+    auto key = std::make_pair(L_l[v], L_u[v]);
+    auto it = ids.find(key);
+    if (it == ids.end()) {
+      it = ids.emplace(key, (uint32_t)gL_l_.size()).first;
+      gL_l_.push_back(L_l[v]);
+      gL_u_.push_back(L_u[v]);
+    }
+    group_[v] = it->second;
+  }
+  gmax_.resize(gL_l_.size());
+  if (mode_ == 1) in_top_.assign(n, 0);
+}
+
+bool StopChecker::check(const uint64_t *count, uint64_t tau) {
+  const double T = (double)tau, W = (double)omega_;
+  std::fill(gmax_.begin(), gmax_.end(), 0);
+  std::vector<uint8_t> seen(gmax_.size(), 0);
+  if (mode_ == 0) {
+    for (uint32_t v = 0; v < n_; ++v) {
+      const uint32_t g = group_[v];
+      seen[g] = 1;
+      gmax_[g] = std::max(gmax_[g], count[v]);
+    }
+    for (size_t g = 0; g < gmax_.size(); ++g) {
+      if (!seen[g]) continue;
+      const double bt = (double)gmax_[g] / T;
+      if (!(bound_f(bt, gL_l_[g], W, T) <= eps_) || !(bound_g(bt, gL_u_[g], W, T) <= eps_))
+        return false;
+    }
+    return true;
+  }
+  // top-k (Algorithm 3): the k+1 largest by (count desc, id asc) are handled one by one;
+  // for the rest only the per-group maximum can decide the second loop's condition.
+  const uint32_t head = std::min(n_, k_ + 1);
+  order_.resize(n_);
+  for (uint32_t v = 0; v < n_; ++v) order_[v] = v;
+  auto cmp = [count](uint32_t a, uint32_t b) {
+    return count[a] != count[b] ? count[a] > count[b] : a < b;
+  };
+  std::nth_element(order_.begin(), order_.begin() + (head - 1), order_.end(), cmp);
+  std::sort(order_.begin(), order_.begin() + head, cmp);
+  auto bt = [&](uint32_t v) { return (double)count[v] / T; };
+  auto fv = [&](uint32_t v) { return bound_f(bt(v), Ll_[v], W, T); };
+  auto gv = [&](uint32_t v) { return bound_g(bt(v), Lu_[v], W, T); };
+  for (uint32_t i = 0; i < k_; ++i) {
+    const uint32_t v = order_[i];
+    if (fv(v) > eps_ || gv(v) > eps_) {
+      if (i > 0 && bt(order_[i - 1]) - fv(order_[i - 1]) < bt(v) + gv(v)) return false;
+      if (i + 1 < n_ && bt(v) - fv(v) < bt(order_[i + 1]) + gv(order_[i + 1])) return false;
+    }
+  }
+  const uint32_t vk = order_[k_ - 1];
+  const double kth_low = bt(vk) - fv(vk);
+  for (uint32_t i = 0; i < k_; ++i) in_top_[order_[i]] = 1;
+  for (uint32_t v = 0; v < n_; ++v) {
+    if (in_top_[v]) continue;
+    const uint32_t g = group_[v];
+    seen[g] = 1;
+    gmax_[g] = std::max(gmax_[g], count[v]);
+  }
+  for (uint32_t i = 0; i < k_; ++i) in_top_[order_[i]] = 0;
+  for (size_t g = 0; g < gmax_.size(); ++g) {
+    if (!seen[g]) continue;
+    const double b = (double)gmax_[g] / T;
+    const double f = bound_f(b, gL_l_[g], W, T), gg = bound_g(b, gL_u_[g], W, T);
+    if ((f > eps_ || gg > eps_) && kth_low < b + gg) return false;
+  }
+  return true;
+}
+
+// ------------------------------------------------------------------ rank intervals
+
+void rank_intervals(uint32_t n, const double *lower, const double *upper, uint32_t *rank_lo,
+                    uint32_t *rank_hi) {
+  std::vector<double> lo_sorted(lower, lower + n), up_sorted(upper, upper + n);
+  std::sort(lo_sorted.begin(), lo_sorted.end());
+  std::sort(up_sorted.begin(), up_sorted.end());
+  for (uint32_t v = 0; v < n; ++v) {
+    // #{w: lower(w) >= upper(v)}, minus v itself if it qualifies
+    size_t ge = lo_sorted.end() - std::lower_bound(lo_sorted.begin(), lo_sorted.end(), upper[v]);
+    if (lower[v] >= upper[v]) --ge;
+    rank_lo[v] = (uint32_t)(1 + ge);
+    // #{w: upper(w) > lower(v)}
+    rank_hi[v] = (uint32_t)(up_sorted.end() -
+                            std::upper_bound(up_sorted.begin(), up_sorted.end(), lower[v]));
+  }
+}
+
+}  // namespace kad

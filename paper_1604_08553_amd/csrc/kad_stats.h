@@ -1,0 +1,56 @@
+// Host-side statistics of the adaptive algorithm (library-internal interface).
+// All binary64, compiled without FMA contraction.
+#pragma once
+#include <stdint.h>
+
+#include <vector>
+
+namespace kad {
+
+uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c);
+uint64_t alpha_of(uint64_t omega);
+uint64_t interval_of(uint64_t omega);
+
+double bound_f(double bt, double L, double omega, double tau);
+double bound_g(double bt, double L, double omega, double tau);
+
+// Returns 0 on success, -1 on invalid arguments.
+int vertex_diameter(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32_t *col,
+                    const uint32_t *rrow, const uint32_t *rcol, double exact_limit, uint32_t *vd,
+                    bool *exact);
+
+void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
+                   const double *lam_l, const double *lam_u, double delta, double eps_bal,
+                   double *L_l, double *L_u, double *C);
+
+void topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha, double eps,
+                  double *lam_l, double *lam_u);
+
+// The stopping check used inside a run.  Nodes sharing the same (L_l, L_u) pair are
+// grouped once; f, g and b+g are non-decreasing in the count, so within a group only
+// the largest count can decide a per-node condition.  Gives exactly the booleans of
+// the plain evaluation.
+class StopChecker {
+ public:
+  StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
+              const double *L_l, const double *L_u);
+  bool check(const uint64_t *count, uint64_t tau);
+
+ private:
+  uint32_t n_, mode_, k_;
+  double eps_;
+  uint64_t omega_;
+  const double *Ll_, *Lu_;
+  std::vector<uint32_t> group_;      // node -> group
+  std::vector<double> gL_l_, gL_u_;  // group -> L values
+  std::vector<uint64_t> gmax_;       // scratch: largest count per group
+  std::vector<uint32_t> order_;      // scratch for the top-k order
+  std::vector<uint8_t> in_top_;
+};
+
+// Rank intervals of the top-k output: rank_lo = 1 + #{w != v: lower(w) >= upper(v)},
+// rank_hi = #{w: upper(w) > lower(v)}.
+void rank_intervals(uint32_t n, const double *lower, const double *upper, uint32_t *rank_lo,
+                    uint32_t *rank_hi);
+
+}  // namespace kad

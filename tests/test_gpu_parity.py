@@ -1,0 +1,196 @@
+"""GPU parity: the HIP path (through the C ABI) against the CPU oracle, bit for bit.
+
+Sampled paths (s, t, every node, arcs scanned), hit counts, and whole adaptive runs
+(tau, counts, interval bounds, top-k output) must be identical for the same seed.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def kad():
+    import torch
+    assert torch.cuda.is_available(), "no GPU"
+    import paper_1604_08553_amd as k
+    k.lib()
+    return k
+
+
+@pytest.fixture(scope="module")
+def ctx(kad):
+    c = kad.Context(0)
+    yield c
+    c.close()
+
+
+@pytest.fixture(scope="module")
+def orc():
+    import oracle
+    oracle.build(force=False)
+    return oracle
+
+
+def _compare_paths(kad, ctx, orc, csr, seed, phase, first, count, allow_flags=False):
+    G = kad.Graph(ctx, csr)
+    _say("sample_paths", csr.name, "n", csr.n, "seed", seed, "phase", phase, "ids", first, count)
+    A = kad.sample_paths(ctx, G, seed, phase, first, count)
+    B = orc.sample_paths(csr, seed, phase, first, count, threads=16)
+    ok = A["flags"] == 0
+    if not allow_flags:
+        assert ok.all(), np.unique(A["flags"])
+    assert np.array_equal(A["s"], B.s) and np.array_equal(A["t"], B.t)
+    assert np.array_equal(A["arcs"][ok], B.arcs[ok])
+    for k in np.nonzero(ok)[0]:
+        a = A["nodes"][A["path_off"][k]:A["path_off"][k + 1]]
+        b = B.path(k)
+        assert np.array_equal(a, b), (k, a, b)
+    G.close()
+    return A, B
+
+
+def test_paths_er2000_65536(kad, ctx, orc):
+    g = gg.workload("er2000")
+    _compare_paths(kad, ctx, orc, g, 1, 1, 0, 65536)
+    _compare_paths(kad, ctx, orc, g, 7, 0, 12345, 3001)
+
+
+@pytest.mark.parametrize("name", ["gnp_u", "gnp_d", "path", "star", "cycle", "grid", "union",
+                                  "K2", "empty2", "kbip"])
+def test_paths_small_graphs(kad, ctx, orc, name):
+    g = {"gnp_u": lambda: gg.gnp(60, 0.05, 3), "gnp_d": lambda: gg.gnp(60, 0.04, 4, True),
+         "path": lambda: gg.path_graph(40), "star": lambda: gg.star_graph(30),
+         "cycle": lambda: gg.cycle_graph(25, True), "grid": lambda: gg.grid(12, 17),
+         "union": lambda: gg.disjoint_union(gg.path_graph(9), gg.cycle_graph(6, True),
+                                            gg.star_graph(5)),
+         "K2": lambda: gg.path_graph(2),
+         "empty2": lambda: gg.csr_from_edges(2, [], [], False, name="empty2"),
+         "kbip": lambda: gg.complete_bipartite(30, 45)}[name]()
+    _compare_paths(kad, ctx, orc, g, 11, 1, 0, 4099)
+
+
+def test_paths_many_meeting_edges(kad, ctx, orc):
+    """K_{1500,1500}: a pair on one side meets through 1500 candidate edges (more than
+    the LDS staging holds, so the sort runs in the slot's global buffer)."""
+    g = gg.complete_bipartite(1500, 1500)
+    _compare_paths(kad, ctx, orc, g, 5, 1, 0, 300)
+
+
+def test_paths_directed_chung_lu(kad, ctx, orc):
+    g = gg.chung_lu_directed(200_000, 2.5, 2.1, 10.0, 9)
+    _compare_paths(kad, ctx, orc, g, 3, 1, 0, 4000)
+
+
+def test_paths_chung_lu_1m_sampled_ids(kad, ctx, orc):
+    """The bench workload at full size: ids drawn across the main phase's range."""
+    g = gg.workload("cl1m")
+    _compare_paths(kad, ctx, orc, g, 1, 1, 0, 3000)
+    _compare_paths(kad, ctx, orc, g, 1, 1, 150_000, 1000)
+    _compare_paths(kad, ctx, orc, g, 1, 0, 0, 1000)
+
+
+def test_paths_grid_unflagged_match(kad, ctx, orc):
+    """On a 500x500 grid the frontier path counts of distant pairs pass 2^128 (a node
+    l levels out on a diagonal has C(l, l/2) shortest paths): those samples are
+    flagged, all others must match the oracle exactly."""
+    g = gg.grid(500, 500)
+    A, B = _compare_paths(kad, ctx, orc, g, 2, 1, 0, 160, allow_flags=True)
+    flagged = A["flags"] != 0
+    assert flagged.any() and (~flagged).sum() >= 5
+    assert np.all(A["flags"][flagged] == kad.SAMPLE_OVERFLOW)
+    # a flagged sample really has a count beyond 128 bits somewhere on its frontier:
+    # at least its distance is long enough for one
+    d = np.diff(B.path_off.astype(np.int64)) - 1
+    assert np.all(d[flagged] >= 120)
+
+
+def test_hit_counts_match(kad, ctx, orc):
+    for g, cnt in [(gg.workload("er2000"), 50000), (gg.gnp(300, 0.02, 5, True), 20000)]:
+        _say("hit_counts", g.name, cnt)
+        G = kad.Graph(ctx, g)
+        a, arcs = kad.hit_counts(ctx, G, 4, 1, 100, cnt)
+        S = orc.sample_paths(g, 4, 1, 100, cnt, threads=16)
+        b = np.zeros(g.n, dtype=np.uint64)
+        for k in range(cnt):
+            p = S.path(k)
+            b[p[1:-1]] += 1
+        assert np.array_equal(a, b)
+        assert arcs == int(S.arcs.sum())
+        G.close()
+
+
+def _compare_run(kad, ctx, orc, g, **kw):
+    _say("run", g.name, kw)
+    G = kad.Graph(ctx, g)
+    a = kad.run(ctx, G, **kw)
+    okw = dict(kw)
+    okw.pop("kernel_batch", None)
+    b = orc.run(g, threads=16, **okw)
+    for key in ("tau", "omega", "alpha", "vd"):
+        assert a[key] == b[key], (key, a[key], b[key])
+    assert a["stop_reason"] == b["stop_rule"]
+    assert a["arcs_scanned"] == b["arcs"]
+    assert np.array_equal(a["count"], b["count"])
+    assert np.array_equal(a["bc"], b["bc"])
+    assert np.array_equal(a["lower"], b["lower"]) and np.array_equal(a["upper"], b["upper"])
+    G.close()
+    return a, b
+
+
+def test_run_er2000_all_nodes(kad, ctx, orc):
+    a, b = _compare_run(kad, ctx, orc, gg.workload("er2000"), epsilon=0.01, delta=0.1, seed=1)
+    assert a["omega"] == 29979 and a["alpha"] == 299 and a["stop_reason"] == 1
+
+
+def test_run_kernel_batch_does_not_change_result(kad, ctx, orc):
+    g = gg.workload("er2000")
+    G = kad.Graph(ctx, g)
+    r1 = kad.run(ctx, G, 0.01, 0.1, seed=3, kernel_batch=1024)
+    r2 = kad.run(ctx, G, 0.01, 0.1, seed=3, kernel_batch=65536)
+    assert r1["tau"] == r2["tau"] and np.array_equal(r1["count"], r2["count"])
+
+
+def test_run_directed_and_disconnected(kad, ctx, orc):
+    g = gg.disjoint_union(gg.chung_lu_directed(3000, 2.5, 2.1, 6.0, 4), gg.cycle_graph(50, True))
+    _compare_run(kad, ctx, orc, g, epsilon=0.02, delta=0.1, seed=9)
+
+
+def test_run_topk(kad, ctx, orc):
+    g = gg.chung_lu(1500, 2.3, 6.0, 42)
+    a, b = _compare_run(kad, ctx, orc, g, epsilon=0.004, delta=0.1, mode="topk", k=5, seed=2)
+    rlo, rhi = orc.rank_intervals(b["lower"], b["upper"])
+    sel = np.nonzero(rlo <= 5)[0]
+    cnt = b["count"]
+    sel = sorted(sel.tolist(), key=lambda v: (-int(cnt[v]), v))
+    assert a["topk_node"].tolist() == sel
+    assert a["rank_lo"].tolist() == [int(rlo[v]) for v in sel]
+    assert a["rank_hi"].tolist() == [int(rhi[v]) for v in sel]
+
+
+def test_run_complete_graph_g_only(kad, ctx, orc):
+    a, b = _compare_run(kad, ctx, orc, gg.complete_graph(20), epsilon=0.01, delta=0.1, seed=3)
+    assert a["count"].sum() == 0 and a["stop_reason"] == 1
+
+
+def test_device_memory_graph_and_torch_stream(kad, ctx, orc):
+    import torch
+    g = gg.workload("er2000")
+    row = torch.from_numpy(g.row.astype(np.int32)).cuda()
+    col = torch.from_numpy(g.col.astype(np.int32)).cuda()
+    G = kad.Graph(ctx, n=g.n, row=row, col=col, directed=False, mem="device")
+    s = torch.cuda.Stream()
+    A = kad.sample_paths(ctx, G, 1, 1, 0, 2000, stream=s)
+    B = orc.sample_paths(g, 1, 1, 0, 2000, threads=16)
+    assert np.array_equal(A["nodes"], B.nodes)
+    G.close()

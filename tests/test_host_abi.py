@@ -1,0 +1,138 @@
+"""CPU checks of the C-ABI library: it loads, exports every declared symbol, and its
+host-side binary64 statistics agree with the oracle (no device calls)."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+import graphgen as gg
+
+kad = pytest.importorskip("paper_1604_08553_amd")
+
+
+@pytest.fixture(scope="module")
+def klib():
+    if not os.path.exists(kad.library_path()):
+        pytest.fail("libkadabra.so is not built (python -m paper_1604_08553_amd.build)")
+    return kad.lib()
+
+
+def test_exports_every_declared_symbol(klib):
+    syms = kad.declared_symbols()
+    assert len(syms) >= 19
+    handle = ctypes.CDLL(kad.library_path())
+    for name in syms:
+        assert hasattr(handle, name), name
+
+
+def test_no_device_gives_clean_error(klib):
+    # CPU container: creating a context must fail with a status, never abort
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    if has_gpu:
+        pytest.skip("a GPU is present")
+    with pytest.raises(kad.KadError) as e:
+        kad.Context(0)
+    assert e.value.status == -3
+
+
+def test_schedule_matches_oracle(klib, oracle_lib):
+    for lam in (0.03, 0.01, 0.005, 0.002, 0.0002):
+        for delta in (0.1, 0.05, 0.2):
+            for vd in (1, 2, 3, 4, 5, 8, 11, 30, 1000, 5000):
+                om = kad.omega(lam, delta, vd)
+                assert om == oracle_lib.omega(lam, delta, vd)
+                assert kad.alpha(om) == oracle_lib.alpha(om)
+                assert kad.default_interval(om) == oracle_lib.default_interval(om)
+
+
+def _graphs():
+    out = [gg.path_graph(9), gg.star_graph(7), gg.cycle_graph(8, True), gg.grid(6, 9),
+           gg.complete_bipartite(3, 4), gg.disjoint_union(gg.path_graph(5), gg.cycle_graph(4, True)),
+           gg.workload("er2000"), gg.chung_lu(3000, 2.3, 6.0, 7),
+           gg.chung_lu_directed(3000, 2.5, 2.1, 5.0, 8)]
+    for seed in range(8):
+        out.append(gg.gnp(40, 0.06, seed))
+        out.append(gg.gnp(40, 0.05, seed, directed=True))
+    return out
+
+
+def test_vertex_diameter_matches_oracle(klib, oracle_lib):
+    for g in _graphs():
+        for limit in (1e9, 0.0):
+            assert kad.vertex_diameter(g, limit) == oracle_lib.vertex_diameter(g, limit), (g.name, limit)
+
+
+def test_f_g_bitwise_equal_to_oracle(klib, oracle_lib):
+    rng = np.random.default_rng(1)
+    for _ in range(5000):
+        om = float(rng.integers(1000, 10**8))
+        tau = float(rng.integers(1, int(om) + 1))
+        L = float(np.exp(rng.uniform(-1, 5)))
+        b = float(rng.integers(0, int(tau) + 1)) / tau
+        assert kad.bound_f(b, L, om, tau) == oracle_lib.f(b, L, om, tau)
+        assert kad.bound_g(b, L, om, tau) == oracle_lib.g(b, L, om, tau)
+
+
+def _pilot(n, alpha, seed, zero_frac=0.3):
+    rng = np.random.default_rng(seed)
+    c = rng.poisson(rng.exponential(1.5, n)).astype(np.uint64)
+    c[rng.random(n) < zero_frac] = 0
+    return np.minimum(c, alpha).astype(np.uint64)
+
+
+def test_compute_delta_matches_oracle(klib, oracle_lib):
+    for seed, n in enumerate((10, 1000, 20000)):
+        alpha, om = 299, 29979
+        c0 = _pilot(n, alpha, seed)
+        lam = np.full(n, 0.01)
+        a = kad.compute_delta(c0, alpha, om, lam, lam, 0.1, 0.001)
+        b = oracle_lib.compute_delta(c0, alpha, om, lam, lam, 0.1, 0.001)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+        ll, lu = oracle_lib.topk_lambdas(c0, 5, alpha, 0.002)
+        a = kad.compute_delta(c0, alpha, om, ll, lu, 0.1, 0.001)
+        b = oracle_lib.compute_delta(c0, alpha, om, ll, lu, 0.1, 0.001)
+        assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+
+
+def test_topk_lambdas_match_oracle(klib, oracle_lib):
+    for seed in range(6):
+        n = 500
+        c0 = _pilot(n, 300, seed, zero_frac=0.1)
+        for k in (1, 3, 10, n):
+            for lam in (0.0005, 0.002, 0.05):
+                a = kad.topk_lambdas(c0, k, 300, lam)
+                b = oracle_lib.topk_lambdas(c0, k, 300, lam)
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (seed, k, lam)
+
+
+def test_grouped_stop_check_equals_plain_oracle(klib, oracle_lib):
+    """The library groups nodes by (L_l, L_u) and tests only each group's largest count;
+    the oracle tests every node.  Sweep tau across the decision boundary."""
+    rng = np.random.default_rng(3)
+    n, alpha, om = 3000, 300, 40000
+    decisions = 0
+    for trial in range(6):
+        c0 = _pilot(n, alpha, 100 + trial)
+        lam = 0.01 if trial % 2 == 0 else 0.004
+        for mode, k in (("all", 0), ("topk", 1), ("topk", 7)):
+            if mode == "topk":
+                ll, lu = oracle_lib.topk_lambdas(c0, k, alpha, lam)
+            else:
+                ll = lu = np.full(n, lam)
+            Ll, Lu, _ = oracle_lib.compute_delta(c0, alpha, om, ll, lu, 0.1)
+            p = (c0.astype(np.float64) + 0.5) / (alpha + 1)
+            for tau in np.unique(np.geomspace(1000, om, 14).astype(np.int64)):
+                cnt = rng.binomial(int(tau), np.minimum(p, 1.0)).astype(np.uint64)
+                a = kad.have_to_stop(cnt, int(tau), om, lam, Ll, Lu, mode=mode, k=k)
+                if mode == "topk":
+                    b = oracle_lib.stop_topk(cnt, k, int(tau), om, lam, Ll, Lu)
+                else:
+                    b = oracle_lib.stop_all(cnt, int(tau), om, lam, Ll, Lu)
+                assert a == b, (trial, mode, k, tau)
+                decisions += a
+    assert decisions > 0
