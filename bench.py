@@ -129,6 +129,8 @@ def main():
         "time_to_epsilon_s": elapsed / args.steps,
         "tau": r0["tau"], "omega": r0["omega"], "alpha": r0["alpha"], "vd": r0["vd"],
         "check_interval": r0["interval"], "stop": "rule" if r0["stop_reason"] else "omega",
+        "phases_s": {k: sum(r[f"seconds_{k}"] for r in runs) / len(runs)
+                     for k in ("setup", "pilot", "delta", "main")},
         "sampler": {"launches": tm["launches"], "samples": tm["samples"],
                     "avg_launch_ms": avg_launch_s * 1e3,
                     "arcs_per_sample": tm["arcs"] / max(tm["samples"], 1),

@@ -123,6 +123,10 @@ typedef struct {
   uint32_t n;
   double seconds;          /* wall time of the call */
   double C;                /* the constant found by computeDelta's bisection */
+  double seconds_setup;    /* vertex diameter, omega, buffers */
+  double seconds_pilot;    /* pilot samples and their counts */
+  double seconds_delta;    /* computeDelta and the stopping-check setup */
+  double seconds_main;     /* main phase until the stopping check */
   /* caller-owned host arrays of length n; any may be NULL */
   uint64_t *count;         /* main-phase hits per node */
   double *bc;              /* count / tau */

@@ -51,6 +51,8 @@ class _Result(C.Structure):
                 ("pilot_arcs_scanned", C.c_uint64), ("overflow_samples", C.c_uint64),
                 ("vd", C.c_uint32), ("vd_exact", C.c_uint32), ("stop_reason", C.c_uint32),
                 ("n", C.c_uint32), ("seconds", C.c_double), ("C", C.c_double),
+                ("seconds_setup", C.c_double), ("seconds_pilot", C.c_double),
+                ("seconds_delta", C.c_double), ("seconds_main", C.c_double),
                 ("count", C.c_void_p), ("bc", C.c_void_p), ("lower", C.c_void_p),
                 ("upper", C.c_void_p), ("topk_cap", C.c_uint32), ("topk_len", C.c_uint32),
                 ("topk_node", C.c_void_p), ("rank_lo", C.c_void_p), ("rank_hi", C.c_void_p)]
@@ -245,7 +247,8 @@ def run(ctx: Context, graph: Graph, epsilon: float, delta: float, mode: str = "a
     r.topk_cap = cap
     _check(lib().kad_run(ctx.handle, graph.handle, C.byref(p), C.byref(r), _stream(stream)))
     for name in ("tau", "omega", "alpha", "interval", "arcs_scanned", "pilot_arcs_scanned",
-                 "overflow_samples", "vd", "vd_exact", "stop_reason", "seconds", "C"):
+                 "overflow_samples", "vd", "vd_exact", "stop_reason", "seconds", "C",
+                 "seconds_setup", "seconds_pilot", "seconds_delta", "seconds_main"):
         out[name] = getattr(r, name)
     if mode == "topk":
         m = r.topk_len

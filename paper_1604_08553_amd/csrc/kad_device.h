@@ -50,9 +50,12 @@ hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
                           uint32_t grid, hipStream_t stream);
 
-// count[v] += number of samples in [0, nsamp) whose path has v as an interior node.
+// count[v] += (or -=, with subtract) the number of samples in [0, nsamp) whose path has
+// v as an interior node.  With gmax != NULL also raises gmax[group[v]] to the new count
+// of every changed node.
 hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t stride,
-                             uint32_t nsamp, uint32_t n, uint64_t *count, hipStream_t stream);
+                             uint32_t nsamp, uint32_t n, uint64_t *count, bool subtract,
+                             const uint32_t *group, uint64_t *gmax, hipStream_t stream);
 
 // Zero a small device buffer with a kernel (no memset node when captured).
 hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t stream);

@@ -33,6 +33,9 @@ constexpr int FILTER_LOG2 = 16;
 constexpr int FILTER_WORDS = (1 << FILTER_LOG2) / 32;
 constexpr int PI_LDS = 1024;  // candidate edges kept in LDS; more spill to the slot buffer
 constexpr uint32_t MAX_ATTEMPTS = 64;
+constexpr int MAXLEV = 32;     // levels per side whose node lists are remembered
+constexpr int MATCH_CAP = 192; // predecessor candidates a backtracking wave keeps in LDS
+constexpr uint64_t SMALL_EXPANSION = 512;  // arcs: up to this, one combined scan per level
 
 static_assert(CHUNK == 2 * BLOCK, "two staged frontier nodes per thread");
 
@@ -151,28 +154,38 @@ __device__ u128 uniform_below(u128 bound, uint64_t seed, uint64_t i, uint64_t sw
 }
 
 // ------------------------------------------------------------------ memory helpers
-// Tags and path counts are updated with device-scope atomics; reads that must see
-// them go through agent-scope loads so no stale vector-L1 line is used.
+// A slot's tags and path counts are touched only by the workgroup that owns the slot,
+// so every atomic and every load that must observe one is workgroup-scoped: it stays
+// in the CU's XCD (no cross-XCD coherence traffic), and __syncthreads orders it.
+// Between launches the slot state is all-zero, whichever XCD ran it last.
 __device__ __forceinline__ uint32_t ld_tag(const uint32_t *p) {
-  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 __device__ __forceinline__ u128 ld_sig(const uint64_t *sig, uint32_t v) {
   u128 r;
-  r.lo = __hip_atomic_load(sig + 2 * (size_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  r.hi = __hip_atomic_load(sig + 2 * (size_t)v + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  r.lo = __hip_atomic_load(sig + 2 * (size_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  r.hi = __hip_atomic_load(sig + 2 * (size_t)v + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   return r;
+}
+__device__ __forceinline__ uint32_t cas_tag(uint32_t *p, uint32_t expect, uint32_t want) {
+  __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+  return expect;  // the value found (== the old expectation on success)
+}
+__device__ __forceinline__ uint64_t add_u64(uint64_t *p, uint64_t x) {
+  return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
 // sigma(w) += x with exact carry into the high word; true when the sum reached 2^128.
 __device__ __forceinline__ bool atomic_add_sig(uint64_t *sig, uint32_t w, uint64_t xlo,
                                                uint64_t xhi) {
   uint64_t *p = sig + 2 * (size_t)w;
-  const uint64_t old = atomicAdd((unsigned long long *)p, (unsigned long long)xlo);
+  const uint64_t old = add_u64(p, xlo);
   const uint64_t c = (old + xlo < old) ? 1u : 0u;
   const uint64_t add = xhi + c;
   bool ovf = add < xhi;
   if (add != 0) {
-    const uint64_t oh = atomicAdd((unsigned long long *)(p + 1), (unsigned long long)add);
+    const uint64_t oh = add_u64(p + 1, add);
     ovf |= oh + add < oh;
   }
   return ovf;
@@ -231,7 +244,18 @@ struct Lds {
   uint32_t fb[2], fe[2], lvl[2];
   uint32_t nvis, pi_count, flags, win;
   uint32_t ovf_any;
+  uint32_t needed;  // nodes on completed levels (the reached set the method needs)
+  uint32_t seg_lo[2][MAXLEV], seg_hi[2][MAXLEV];  // level l of a side = visit[seg_lo, seg_hi)
 };
+
+// Backtracking scratch of one wave, carved out of the candidate-edge staging area
+// (free once the meeting edge is chosen).
+struct MatchScratch {
+  uint32_t id[MATCH_CAP];
+  uint64_t lo[MATCH_CAP];
+  uint64_t hi[MATCH_CAP];
+};
+static_assert(2 * sizeof(MatchScratch) <= PI_LDS * sizeof(uint64_t), "scratch fits the staging area");
 
 // Exclusive block scan of one value per thread; *total gets the block sum.
 __device__ __forceinline__ uint32_t block_excl_u32(Lds &L, uint32_t v, uint32_t &total) {
@@ -285,7 +309,9 @@ __device__ __forceinline__ uint32_t wave_reserve(bool pred, uint32_t *counter, u
   return base;
 }
 
-enum class Scan { Touch, Discover };
+// Touch: meeting test only (filter + tag).  Discover: next-level claims and counts only.
+// Both: the meeting test by tag and the discovery in one pass (small expansions).
+enum class Scan { Touch, Discover, Both };
 
 // One pass over the rows of frontier [fb, fe) (chunked through LDS).
 template <Scan MODE>
@@ -309,7 +335,7 @@ __device__ __forceinline__ void scan_frontier(Lds &L, const GraphDev &g, uint32_
         d[q] = rp[u + 1] - st;
         L.c_node[j] = u;
         L.c_start[j] = st;
-        if (MODE == Scan::Discover) {
+        if (MODE != Scan::Touch) {
           const u128 su = ld_sig(sig, u);
           L.c_sig_lo[j] = su.lo;
           L.c_sig_hi[j] = su.hi;
@@ -322,65 +348,119 @@ __device__ __forceinline__ void scan_frontier(Lds &L, const GraphDev &g, uint32_
     if (2 * tid + 1 < m) L.c_pref[2 * tid + 1] = ex + d[0];
     if (tid == 0) L.c_pref[m] = tot;
     __syncthreads();
-    // Every lane of a wave runs the same number of iterations (cross-lane ballots and
-    // shuffles below must not see inactive lanes); lanes past the end are idle.
+    // Each lane takes U arcs per iteration (independent searches and row loads in
+    // flight); every lane of a wave runs the same number of iterations because the
+    // ballots and shuffles below must not see inactive lanes.
+    constexpr int U = MODE == Scan::Touch ? 4 : 2;  // arcs per lane per iteration
     uint32_t jlo = 0;
     const uint32_t lane = lane_id();
-    for (uint32_t e0 = (tid / WAVE) * WAVE; e0 < tot; e0 += BLOCK) {
-      const uint32_t e = e0 + lane;
-      const bool valid = e < tot;
-      uint32_t u = 0, w = 0, lo = jlo;
-      if (valid) {
-        // largest j with c_pref[j] <= e (then c_pref[j+1] > e: node j owns arc e)
-        uint32_t hi = m;
-        while (hi - lo > 1) {
-          const uint32_t mid = (lo + hi) >> 1;
-          if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
+    for (uint32_t e0 = (tid / WAVE) * (WAVE * U); e0 < tot; e0 += BLOCK * U) {
+      uint32_t uu[U], ww[U], jj[U];
+      bool vv[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const uint32_t e = e0 + q * WAVE + lane;
+        vv[q] = e < tot;
+        uint32_t lo = jlo;
+        // largest j with c_pref[j] <= e (then c_pref[j+1] > e: node j owns arc e); arcs
+        // of a long row stay in the row of the lane's previous arc, so test that first
+        if (vv[q] && L.c_pref[lo + 1] <= e) {
+          uint32_t hi = m;
+          ++lo;
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
+          }
         }
-        jlo = lo;
-        u = L.c_node[lo];
-        w = cl[L.c_start[lo] + (e - L.c_pref[lo])];
+        jj[q] = lo;
       }
-      if (MODE == Scan::Touch) {
-        bool hit = false;
-        if (valid) {
-          const uint32_t h = filter_bit(w);
-          if ((L.filter[h >> 5] >> (h & 31)) & 1u) hit = ld_tag(tag + w) == other_tag;
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const uint32_t e = e0 + q * WAVE + lane;
+        uu[q] = 0;
+        ww[q] = 0;
+        if (vv[q]) {
+          uu[q] = L.c_node[jj[q]];
+          ww[q] = cl[L.c_start[jj[q]] + (e - L.c_pref[jj[q]])];
+          jlo = jj[q];
         }
-        uint32_t rank = 0;
-        const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
-        if (hit) {
-          const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
-          const uint32_t idx = base + rank;
-          if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
-          else if (idx < pi_cap) gpi[idx] = key;
-        }
-      } else {
-        bool disc = false;
-        if (valid) {
-          uint32_t tg = ld_tag(tag + w);
-          if (tg == 0) {
-            const uint32_t old = atomicCAS(tag + w, 0u, next_tag);
-            disc = old == 0;
-            tg = disc ? next_tag : old;
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const uint32_t u = uu[q], w = ww[q];
+        const bool valid = vv[q];
+        if (MODE == Scan::Touch) {
+          bool hit = false;
+          if (valid) {
+            const uint32_t h = filter_bit(w);
+            if ((L.filter[h >> 5] >> (h & 31)) & 1u) hit = ld_tag(tag + w) == other_tag;
           }
-          if (tg == next_tag) ovf |= atomic_add_sig(sig, w, L.c_sig_lo[lo], L.c_sig_hi[lo]);
-        }
-        uint32_t rank = 0;
-        const uint32_t base = wave_reserve(disc, &L.nvis, rank);
-        if (base != 0xFFFFFFFFu) {  // uniform: some lane of this wave discovered a node
-          uint64_t dg = 0;
-          if (disc) {
-            visit[base + rank] = w;
-            dg = (uint64_t)(rp[w + 1] - rp[w]);
+          uint32_t rank = 0;
+          const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
+          if (hit) {
+            const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+            const uint32_t idx = base + rank;
+            if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
+            else if (idx < pi_cap) gpi[idx] = key;
           }
-          const uint64_t sum = wave_sum_u64(dg);
-          if (lane == 0) atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)sum);
+        } else {
+          bool disc = false, hit = false;
+          if (valid) {
+            uint32_t tg = ld_tag(tag + w);
+            if (MODE == Scan::Both) hit = tg == other_tag;
+            if (tg == 0) {
+              const uint32_t old = cas_tag(tag + w, 0u, next_tag);
+              disc = old == 0;
+              tg = disc ? next_tag : old;
+            }
+            if (tg == next_tag) {
+              const uint32_t j = jj[q];
+              ovf |= atomic_add_sig(sig, w, L.c_sig_lo[j], L.c_sig_hi[j]);
+            }
+          }
+          if (MODE == Scan::Both) {
+            uint32_t prank = 0;
+            const uint32_t pbase = wave_reserve(hit, &L.pi_count, prank);
+            if (hit) {
+              const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+              const uint32_t idx = pbase + prank;
+              if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
+              else if (idx < pi_cap) gpi[idx] = key;
+            }
+          }
+          uint32_t rank = 0;
+          const uint32_t base = wave_reserve(disc, &L.nvis, rank);
+          if (base != 0xFFFFFFFFu) {  // uniform: some lane of this wave discovered a node
+            uint64_t dg = 0;
+            if (disc) {
+              visit[base + rank] = w;
+              dg = (uint64_t)(rp[w + 1] - rp[w]);
+            }
+            const uint64_t sum = wave_sum_u64(dg);
+            if (lane == 0) atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)sum);
+          }
         }
       }
     }
     __syncthreads();
   }
+}
+
+// Ascending bitonic sort of up to 64 keys held one per lane (missing lanes hold ~0),
+// in registers by one wave.
+__device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
+  const uint32_t lane = lane_id();
+#pragma unroll
+  for (uint32_t k = 2; k <= (uint32_t)WAVE; k <<= 1) {
+#pragma unroll
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      const uint64_t other = __shfl_xor(x, (int)j, WAVE);
+      const bool up = (lane & k) == 0;
+      const bool low = (lane & j) == 0;
+      x = (low == up) ? (x < other ? x : other) : (x > other ? x : other);
+    }
+  }
+  return x;
 }
 
 // In-place ascending bitonic sort of keys[0, M), M a power of two, by the workgroup.
@@ -404,16 +484,25 @@ __device__ void bitonic_sort(uint64_t *keys, uint32_t M) {
 }
 
 // One backtracking walk of a wave (section 4, "by backtracking"): from `start` on
-// level `lev` of side `side` down to level 0, each step drawing
-// r < sigma(x) and taking the first neighbour on the level below (in row order)
-// whose running count exceeds r.  Writes the nodes to path[pos(j-1)].
+// level `lev` of side `side` down to level 0.  Each step draws r < sigma(x) and takes,
+// among x's neighbours on the level below in row order (the s side looks at
+// predecessors in x's in-row, the t side at successors in x's out-row), the first
+// whose running count exceeds r.  Rows are sorted, so "row order" is "ascending id".
+// Two equivalent ways to enumerate those neighbours:
+//   row scan  -- walk x's row, keep entries tagged with the level below;
+//   list scan -- walk the (remembered) node list of the level below and keep the
+//                entries found in x's row by binary search; prefix sums are then
+//                taken in ascending id.  Used when the list is much shorter than the
+//                row (x a hub).
 __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint32_t lev,
-                          const uint32_t *tag, const uint64_t *sig, uint64_t seed, uint64_t i,
-                          uint32_t phase, uint32_t *path, uint32_t ls, uint32_t &flags) {
+                          const uint32_t *tag, const uint64_t *sig, const uint32_t *visit,
+                          const uint32_t (*seg_lo)[MAXLEV], const uint32_t (*seg_hi)[MAXLEV],
+                          MatchScratch &M, uint64_t seed, uint64_t i, uint32_t phase,
+                          uint32_t *path, uint32_t ls, uint32_t &flags) {
   const uint32_t lane = lane_id();
-  // the s side looks at predecessors (in-rows), the t side at successors (out-rows)
   const uint32_t *rp = side == 0 ? g.rrow : g.row;
   const uint32_t *cl = side == 0 ? g.rcol : g.col;
+  const uint64_t lanes_below = (1ULL << lane) - 1ULL;
   uint32_t x = start;
   for (uint32_t j = lev; j >= 1; --j) {
     const u128 bound = ld_sig(sig, x);
@@ -421,26 +510,80 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
                                  flags);
     const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1, stored as (j-1)+1
     const uint32_t beg = rp[x], end = rp[x + 1];
-    u128 carry{0, 0};
     uint32_t pick = 0xFFFFFFFFu;
-    for (uint32_t b = beg; b < end; b += WAVE) {
-      const uint32_t idx = b + lane;
-      uint32_t u = 0;
-      u128 val{0, 0};
-      if (idx < end) {
-        u = cl[idx];
-        if (ld_tag(tag + u) == want) val = ld_sig(sig, u);
+    bool row_scan = true;
+    if (j - 1 < (uint32_t)MAXLEV) {
+      const uint32_t Lb = seg_lo[side][j - 1], Le = seg_hi[side][j - 1];
+      if ((uint64_t)(Le - Lb) * 16 < (uint64_t)(end - beg)) {
+        // ---- list scan
+        uint32_t nm = 0;
+        for (uint32_t b = Lb; b < Le; b += WAVE) {
+          const uint32_t q = b + lane;
+          uint32_t cand = 0;
+          bool match = false;
+          if (q < Le) {
+            cand = visit[q];
+            uint32_t lo = beg, hi = end;
+            while (lo < hi) {
+              const uint32_t mid = (lo + hi) >> 1;
+              if (cl[mid] < cand) lo = mid + 1; else hi = mid;
+            }
+            match = lo < end && cl[lo] == cand;
+          }
+          const uint64_t mk = __ballot(match);
+          if (match) {
+            const uint32_t pos = nm + (uint32_t)__popcll(mk & lanes_below);
+            if (pos < (uint32_t)MATCH_CAP) {
+              const u128 sv = ld_sig(sig, cand);
+              M.id[pos] = cand;
+              M.lo[pos] = sv.lo;
+              M.hi[pos] = sv.hi;
+            }
+          }
+          nm += (uint32_t)__popcll(mk);
+        }
+        if (nm <= (uint32_t)MATCH_CAP) {
+          row_scan = false;
+          // inclusive prefix of match q in id order = sum of sigma over ids <= id_q
+          uint32_t found = 0xFFFFFFFFu;
+          for (uint32_t q0 = 0; q0 < nm; q0 += WAVE) {
+            const uint32_t q = q0 + lane;
+            if (q < nm) {
+              const uint32_t me = M.id[q];
+              u128 inc{0, 0};
+              bool dm = false;
+              for (uint32_t p2 = 0; p2 < nm; ++p2)
+                if (M.id[p2] <= me) inc = add128(inc, u128{M.lo[p2], M.hi[p2]}, dm);
+              const u128 exc = sub128(inc, u128{M.lo[q], M.hi[q]});
+              if (!lt128(r, exc) && lt128(r, inc)) found = me;
+            }
+          }
+          const uint64_t mk = __ballot(found != 0xFFFFFFFFu);
+          if (mk) pick = __shfl(found, (int)__ffsll((unsigned long long)mk) - 1, WAVE);
+        }
       }
-      bool dummy = false;
-      u128 inc = wave_incl_u128(val, dummy);
-      inc = add128(inc, carry, dummy);
-      const uint64_t m = __ballot(idx < end && lt128(r, inc));
-      if (m) {
-        pick = __shfl(u, (int)__ffsll((unsigned long long)m) - 1, WAVE);
-        break;
+    }
+    if (row_scan) {
+      u128 carry{0, 0};
+      for (uint32_t b = beg; b < end; b += WAVE) {
+        const uint32_t idx = b + lane;
+        uint32_t u = 0;
+        u128 val{0, 0};
+        if (idx < end) {
+          u = cl[idx];
+          if (ld_tag(tag + u) == want) val = ld_sig(sig, u);
+        }
+        bool dummy = false;
+        u128 inc = wave_incl_u128(val, dummy);
+        inc = add128(inc, carry, dummy);
+        const uint64_t m = __ballot(idx < end && lt128(r, inc));
+        if (m) {
+          pick = __shfl(u, (int)__ffsll((unsigned long long)m) - 1, WAVE);
+          break;
+        }
+        carry.lo = __shfl(inc.lo, WAVE - 1, WAVE);
+        carry.hi = __shfl(inc.hi, WAVE - 1, WAVE);
       }
-      carry.lo = __shfl(inc.lo, WAVE - 1, WAVE);
-      carry.hi = __shfl(inc.hi, WAVE - 1, WAVE);
     }
     if (pick == 0xFFFFFFFFu) {
       flags |= FLAG_CAPACITY;  // unreachable for consistent counts
@@ -451,7 +594,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
   }
 }
 
-__global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st, uint64_t seed,
+__global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g, SlotState st, uint64_t seed,
                                                         uint32_t phase, uint64_t first,
                                                         uint32_t count, uint32_t *work,
                                                         SampleOut out) {
@@ -491,6 +634,8 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
       visit[1] = t;
       L.fb[0] = 0; L.fe[0] = 1;
       L.fb[1] = 1; L.fe[1] = 2;
+      L.seg_lo[0][0] = 0; L.seg_hi[0][0] = 1;
+      L.seg_lo[1][0] = 1; L.seg_hi[1][0] = 2;
       L.lvl[0] = 0; L.lvl[1] = 0;
       L.deg[0] = (uint64_t)(g.row[s + 1] - g.row[s]);
       L.deg[1] = (uint64_t)(g.rrow[t + 1] - g.rrow[t]);
@@ -499,11 +644,11 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
       L.flags = fl;
       L.ovf_any = 0;
     }
-    __threadfence();
     __syncthreads();
 
     bool ovf = false;
     bool met = false;
+    uint32_t needed = 0;
     for (;;) {
       const uint32_t me = L.deg[0] <= L.deg[1] ? 0u : 1u;  // ties expand the s side
       const uint32_t ot = 1u - me;
@@ -519,24 +664,38 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
         L.pi_count = 0;
         L.new_deg = 0;
       }
-      for (uint32_t j = ob + tid; j < oe; j += BLOCK) {
-        const uint32_t h = filter_bit(visit[j]);
-        atomicOr(&L.filter[h >> 5], 1u << (h & 31));
+      const uint32_t nb = L.nvis;  // the next level starts here
+      needed = nb;
+      if (dme <= SMALL_EXPANSION) {
+        // small level: meeting test by tag and discovery in one pass (the nodes it
+        // claims are never read if the two searches touched; they are reset anyway)
+        __syncthreads();
+        bool ovf_next = false;  // counts of the next level matter only if there is one
+        scan_frontier<Scan::Both>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
+                                  next_tag, ovf_next);
+        if (L.pi_count > 0) {
+          met = true;
+          break;
+        }
+        ovf |= ovf_next;
+      } else {
+        for (uint32_t j = ob + tid; j < oe; j += BLOCK) {
+          const uint32_t h = filter_bit(visit[j]);
+          atomicOr(&L.filter[h >> 5], 1u << (h & 31));
+        }
+        __syncthreads();
+        scan_frontier<Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
+                                   next_tag, ovf);
+        for (uint32_t j = ob + tid; j < oe; j += BLOCK) L.filter[filter_bit(visit[j]) >> 5] = 0;
+        const uint32_t P = L.pi_count;
+        __syncthreads();
+        if (P > 0) {
+          met = true;
+          break;
+        }
+        scan_frontier<Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
+                                      other_tag, next_tag, ovf);
       }
-      __syncthreads();
-      scan_frontier<Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
-                                 next_tag, ovf);
-      for (uint32_t j = ob + tid; j < oe; j += BLOCK) L.filter[filter_bit(visit[j]) >> 5] = 0;
-      const uint32_t P = L.pi_count;
-      const uint32_t nb = L.nvis;
-      __syncthreads();
-      if (P > 0) {
-        met = true;
-        break;
-      }
-      scan_frontier<Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
-                                    other_tag, next_tag, ovf);
-      __threadfence();
       __syncthreads();
       const uint32_t ne = L.nvis;
       const uint64_t nd = L.new_deg;
@@ -547,11 +706,16 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
         L.fe[me] = ne;
         L.lvl[me] = lme + 1;
         L.deg[me] = nd;
+        if (lme + 1 < (uint32_t)MAXLEV) {
+          L.seg_lo[me][lme + 1] = nb;
+          L.seg_hi[me][lme + 1] = ne;
+        }
       }
       __syncthreads();
     }
     if (ovf) atomicOr(&L.ovf_any, 1u);
     __syncthreads();
+    if (tid == 0) L.needed = needed;
     if (L.ovf_any && tid == 0) L.flags |= FLAG_OVERFLOW;
     __syncthreads();
 
@@ -567,14 +731,19 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
         uint32_t M = 1;
         while (M < P) M <<= 1;
         uint64_t *keys = L.pi;
-        if (P <= (uint32_t)PI_LDS) {
+        if (P <= (uint32_t)WAVE) {
+          if (wid == 0) {
+            const uint64_t x = wave_sort64(lane < P ? L.pi[lane] : ~0ULL);
+            if (lane < P) L.pi[lane] = x;
+          }
+          __syncthreads();
+        } else if (P <= (uint32_t)PI_LDS) {
           for (uint32_t j = P + tid; j < M; j += BLOCK) L.pi[j] = ~0ULL;
           __syncthreads();
           bitonic_sort(L.pi, M);
         } else {
           for (uint32_t j = tid; j < (uint32_t)PI_LDS; j += BLOCK) gpi[j] = L.pi[j];
           for (uint32_t j = P + tid; j < M; j += BLOCK) gpi[j] = ~0ULL;
-          __threadfence_block();
           __syncthreads();
           bitonic_sort(gpi, M);
           keys = gpi;
@@ -625,14 +794,18 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
           const uint32_t win = L.win;
           const uint64_t key = keys[win < P ? win : 0];
           const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
+          __syncthreads();  // the staging area becomes backtracking scratch below
           // ---- the two halves: wave 0 walks to s, wave 1 walks to t
           uint32_t fl = 0;
+          MatchScratch *scratch = reinterpret_cast<MatchScratch *>(L.pi);
           if (wid == 0) {
             if (lane == 0) path[ls] = v;
-            backtrack(g, 0, v, ls, tag, sig, seed, i, phase, path, ls, fl);
+            backtrack(g, 0, v, ls, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[0], seed, i,
+                      phase, path, ls, fl);
           } else if (wid == 1) {
             if (lane == 0) path[ls + 1] = w;
-            backtrack(g, 1, w, lt, tag, sig, seed, i, phase, path, ls, fl);
+            backtrack(g, 1, w, lt, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[1], seed, i,
+                      phase, path, ls, fl);
           }
           if (win >= P) fl |= FLAG_CAPACITY;
           if (fl && lane == 0) atomicOr(&L.flags, fl);
@@ -648,7 +821,7 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
       out.len[k] = L.flags ? 0u : len;
       out.arcs[k] = L.arcs;
       out.flags[k] = L.flags;
-      out.nodes[k] = L.nvis;
+      out.nodes[k] = L.needed;
     }
     // ---- restore the slot's all-zero state for the next sample
     const uint32_t nv = L.nvis;
@@ -658,7 +831,6 @@ __global__ __launch_bounds__(BLOCK) void sampler_kernel(GraphDev g, SlotState st
       sig[2 * (size_t)v] = 0;
       sig[2 * (size_t)v + 1] = 0;
     }
-    __threadfence();
     __syncthreads();
   }
 }
@@ -670,7 +842,10 @@ constexpr uint32_t HIT_TILE = 8192;  // node ids per workgroup (32 KB LDS histog
 __global__ __launch_bounds__(HIT_BLOCK) void hit_reduce_kernel(const uint32_t *path,
                                                                const uint32_t *len,
                                                                uint32_t stride, uint32_t nsamp,
-                                                               uint32_t n, uint64_t *count) {
+                                                               uint32_t n, uint64_t *count,
+                                                               int subtract,
+                                                               const uint32_t *group,
+                                                               uint64_t *gmax) {
   __shared__ uint32_t hist[HIT_TILE];
   const uint32_t tile0 = blockIdx.x * HIT_TILE;
   for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) hist[b] = 0;
@@ -688,7 +863,14 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_reduce_kernel(const uint32_t *p
   __syncthreads();
   for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) {
     const uint32_t h = hist[b];
-    if (h && tile0 + b < n) count[tile0 + b] += h;
+    const uint32_t v = tile0 + b;
+    if (h && v < n) {
+      const uint64_t c = subtract ? count[v] - h : count[v] + h;
+      count[v] = c;
+      // running maximum of the counts of each stopping-rule group (counts only grow
+      // while the maxima are in use)
+      if (gmax) atomicMax((unsigned long long *)&gmax[group[v]], (unsigned long long)c);
+    }
   }
 }
 
@@ -709,11 +891,12 @@ hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed,
 }
 
 hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t stride,
-                             uint32_t nsamp, uint32_t n, uint64_t *count, hipStream_t stream) {
+                             uint32_t nsamp, uint32_t n, uint64_t *count, bool subtract,
+                             const uint32_t *group, uint64_t *gmax, hipStream_t stream) {
   if (nsamp == 0) return hipSuccess;
   const uint32_t tiles = (n + HIT_TILE - 1) / HIT_TILE;
   hipLaunchKernelGGL(hit_reduce_kernel, dim3(tiles), dim3(HIT_BLOCK), 0, stream, path, len,
-                     stride, nsamp, n, count);
+                     stride, nsamp, n, count, subtract ? 1 : 0, group, gmax);
   return hipGetLastError();
 }
 

@@ -9,6 +9,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <cmath>
 #include <chrono>
 #include <memory>
 #include <string>
@@ -83,9 +84,25 @@ constexpr uint32_t DEFAULT_BATCH = 65536;
 
 }  // namespace
 
+// Device outputs of one sampler launch, with pinned host mirrors of the small ones.
+struct OutSet {
+  DevBuf<uint32_t> s, t, len, flags, nodes, path;
+  DevBuf<uint64_t> arcs;
+  PinBuf<uint32_t> h_flags, h_len, h_nodes;
+  PinBuf<uint64_t> h_arcs;
+  hipEvent_t k0 = nullptr, k1 = nullptr;  // launch start/end (timing)
+  hipEvent_t copied = nullptr;            // sampler done and mirrors landed
+  hipEvent_t reduced = nullptr;           // every reduction reading this set is done
+  ~OutSet() {
+    for (hipEvent_t e : {k0, k1, copied, reduced})
+      if (e) (void)hipEventDestroy(e);
+  }
+};
+
 struct kad_ctx {
   int device = 0;
-  hipStream_t stream = nullptr;
+  hipStream_t stream = nullptr;   // sampling (unless the caller gives one)
+  hipStream_t rstream = nullptr;  // hit reductions and check snapshots
   uint64_t budget = 0;
   uint64_t used_graphs = 0;
   uint32_t cus = 0;
@@ -94,16 +111,22 @@ struct kad_ctx {
   uint32_t slot_n = 0, slots = 0;
   DevBuf<uint32_t> tag, visit;
   DevBuf<uint64_t> sig, pi;
-  // per-launch outputs
+  // per-launch outputs, double-buffered so the next batch can be sampled while the
+  // host checks the current one
   uint32_t out_cap = 0, out_stride = 0;
-  DevBuf<uint32_t> o_s, o_t, o_len, o_flags, o_nodes, o_path, work;
-  DevBuf<uint64_t> o_arcs, count;
-  PinBuf<uint32_t> h_flags, h_len, h_nodes, h_s, h_t, h_path;
-  PinBuf<uint64_t> h_arcs, h_count;
+  OutSet outs[2];
+  DevBuf<uint32_t> work, group;
+  DevBuf<uint64_t> count, gmax;
+  PinBuf<uint32_t> h_s, h_t, h_path;
+  PinBuf<uint64_t> h_count;
+  std::vector<hipEvent_t> chunk_ev;
   // timing of the sampler launches (HIP events on the launch stream)
   bool timing = false;
   uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0;
   double t_seconds = 0.0;
+  ~kad_ctx() {
+    for (auto e : chunk_ev) (void)hipEventDestroy(e);
+  }
 };
 
 struct kad_graph {
@@ -162,7 +185,7 @@ void transpose(uint32_t n, const std::vector<uint32_t> &row, const std::vector<u
 
 hipStream_t pick_stream(kad_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }
 
-// Size the slot state and output buffers for graph size n and `batch` samples of
+// Size the slot state and both output sets for graph size n and `batch` samples of
 // path stride `stride`.
 kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t stride) {
   HIP_TRY(hipSetDevice(ctx->device));
@@ -173,8 +196,8 @@ kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t st
     ctx->sig.release();
     ctx->pi.release();
     const uint64_t per_slot = (uint64_t)n * (4 + 4 + 16) + (uint64_t)PI_CAP * 8;
-    const uint64_t avail = ctx->budget > ctx->used_graphs + (256ull << 20)
-                               ? ctx->budget - ctx->used_graphs - (256ull << 20)
+    const uint64_t avail = ctx->budget > ctx->used_graphs + (1024ull << 20)
+                               ? ctx->budget - ctx->used_graphs - (1024ull << 20)
                                : 0;
     uint64_t slots = std::min<uint64_t>(want_slots, avail / per_slot);
     if (slots == 0)
@@ -192,22 +215,32 @@ kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t st
   if (ctx->out_cap < batch || ctx->out_stride < stride) {
     const uint32_t cap = std::max(batch, ctx->out_cap);
     const uint32_t st = std::max(stride, ctx->out_stride);
-    for (auto *b : {&ctx->o_s, &ctx->o_t, &ctx->o_len, &ctx->o_flags, &ctx->o_nodes, &ctx->o_path})
-      b->release();
-    ctx->o_arcs.release();
-    HIP_TRY(ctx->o_s.ensure(cap));
-    HIP_TRY(ctx->o_t.ensure(cap));
-    HIP_TRY(ctx->o_len.ensure(cap));
-    HIP_TRY(ctx->o_flags.ensure(cap));
-    HIP_TRY(ctx->o_nodes.ensure(cap));
-    HIP_TRY(ctx->o_arcs.ensure(cap));
-    HIP_TRY(ctx->o_path.ensure((size_t)cap * st));
-    HIP_TRY(ctx->h_flags.ensure(cap));
-    HIP_TRY(ctx->h_len.ensure(cap));
-    HIP_TRY(ctx->h_nodes.ensure(cap));
-    HIP_TRY(ctx->h_arcs.ensure(cap));
+    for (OutSet &o : ctx->outs) {
+      for (auto *b : {&o.s, &o.t, &o.len, &o.flags, &o.nodes, &o.path}) b->release();
+      o.arcs.release();
+      HIP_TRY(o.s.ensure(cap));
+      HIP_TRY(o.t.ensure(cap));
+      HIP_TRY(o.len.ensure(cap));
+      HIP_TRY(o.flags.ensure(cap));
+      HIP_TRY(o.nodes.ensure(cap));
+      HIP_TRY(o.arcs.ensure(cap));
+      HIP_TRY(o.path.ensure((size_t)cap * st));
+      HIP_TRY(o.h_flags.ensure(cap));
+      HIP_TRY(o.h_len.ensure(cap));
+      HIP_TRY(o.h_nodes.ensure(cap));
+      HIP_TRY(o.h_arcs.ensure(cap));
+    }
     ctx->out_cap = cap;
     ctx->out_stride = st;
+  }
+  for (OutSet &o : ctx->outs) {
+    if (!o.k0) HIP_TRY(hipEventCreate(&o.k0));
+    if (!o.k1) HIP_TRY(hipEventCreate(&o.k1));
+    if (!o.copied) HIP_TRY(hipEventCreateWithFlags(&o.copied, hipEventDisableTiming));
+    if (!o.reduced) {
+      HIP_TRY(hipEventCreateWithFlags(&o.reduced, hipEventDisableTiming));
+      HIP_TRY(hipEventRecord(o.reduced, ctx->rstream));  // nothing pending yet
+    }
   }
   HIP_TRY(ctx->work.ensure(1));
   HIP_TRY(ctx->count.ensure(n));
@@ -215,10 +248,13 @@ kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t st
   return KAD_OK;
 }
 
-// Launch the sampler on ids [first, first+count) (count <= out_cap) with the
-// context's current stride; optional event timing.
-kad_status run_sampler(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
-                       uint64_t first, uint32_t count, uint32_t stride, hipStream_t stream) {
+// Enqueue the sampler on ids [first, first+count) into output set `set`, then the
+// copies of its flags and arcs (and, when timing, nodes and lengths) to the host
+// mirrors; nothing waits.
+kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                        uint64_t first, uint32_t count, uint32_t stride, int set,
+                        hipStream_t stream) {
+  OutSet &o = ctx->outs[set];
   kad::SlotState st;
   st.slots = ctx->slots;
   st.n = g->n;
@@ -227,63 +263,50 @@ kad_status run_sampler(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t
   st.sig = ctx->sig.p;
   st.visit = ctx->visit.p;
   st.pi = ctx->pi.p;
-  kad::SampleOut o;
-  o.s = ctx->o_s.p;
-  o.t = ctx->o_t.p;
-  o.len = ctx->o_len.p;
-  o.flags = ctx->o_flags.p;
-  o.nodes = ctx->o_nodes.p;
-  o.arcs = ctx->o_arcs.p;
-  o.path = ctx->o_path.p;
-  o.stride = stride;
+  kad::SampleOut so;
+  so.s = o.s.p;
+  so.t = o.t.p;
+  so.len = o.len.p;
+  so.flags = o.flags.p;
+  so.nodes = o.nodes.p;
+  so.arcs = o.arcs.p;
+  so.path = o.path.p;
+  so.stride = stride;
   HIP_TRY(kad::launch_zero_u32(ctx->work.p, 1, stream));
   const uint32_t grid = std::min<uint32_t>(ctx->slots, count);
-  hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (ctx->timing) {
-    HIP_TRY(hipEventCreate(&e0));
-    HIP_TRY(hipEventCreate(&e1));
-    HIP_TRY(hipEventRecord(e0, stream));
-  }
-  HIP_TRY(kad::launch_sampler(dev_view(g), st, seed, phase, first, count, ctx->work.p, o, grid,
+  if (ctx->timing) HIP_TRY(hipEventRecord(o.k0, stream));
+  HIP_TRY(kad::launch_sampler(dev_view(g), st, seed, phase, first, count, ctx->work.p, so, grid,
                               stream));
+  if (ctx->timing) HIP_TRY(hipEventRecord(o.k1, stream));
+  HIP_TRY(hipMemcpyAsync(o.h_flags.p, o.flags.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(hipMemcpyAsync(o.h_arcs.p, o.arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
   if (ctx->timing) {
-    HIP_TRY(hipEventRecord(e1, stream));
-    HIP_TRY(hipEventSynchronize(e1));
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
-    ctx->t_launches += 1;
-    ctx->t_samples += count;
-    ctx->t_seconds += ms * 1e-3;
-    // work of the timed launch (outside the timed interval): arcs, nodes, hits
-    HIP_TRY(ctx->h_nodes.ensure(count));
-    HIP_TRY(ctx->h_len.ensure(count));
-    HIP_TRY(ctx->h_arcs.ensure(count));
-    HIP_TRY(hipMemcpyAsync(ctx->h_nodes.p, ctx->o_nodes.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_len.p, ctx->o_len.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_arcs.p, ctx->o_arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipStreamSynchronize(stream));
-    for (uint32_t k = 0; k < count; ++k) {
-      ctx->t_arcs += ctx->h_arcs.p[k];
-      ctx->t_nodes += ctx->h_nodes.p[k];
-      ctx->t_hits += ctx->h_len.p[k] >= 2 ? ctx->h_len.p[k] - 2 : 0;
-    }
+    HIP_TRY(hipMemcpyAsync(o.h_nodes.p, o.nodes.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(o.h_len.p, o.len.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
   }
+  HIP_TRY(hipEventRecord(o.copied, stream));
   return KAD_OK;
 }
 
-// Copy the per-sample flags/arcs of the last launch and reject flagged samples.
-kad_status collect_batch(kad_ctx *ctx, uint32_t count, hipStream_t stream, bool want_nodes) {
-  HIP_TRY(hipMemcpyAsync(ctx->h_flags.p, ctx->o_flags.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipMemcpyAsync(ctx->h_arcs.p, ctx->o_arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
-  if (want_nodes) {
-    HIP_TRY(hipMemcpyAsync(ctx->h_nodes.p, ctx->o_nodes.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_len.p, ctx->o_len.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
+// Wait for a batch's mirrors, account its launch time, and reject flagged samples
+// among the first `used` samples (samples past a stopping point do not matter).
+kad_status finish_batch(kad_ctx *ctx, int set, uint32_t count, uint32_t used) {
+  OutSet &o = ctx->outs[set];
+  HIP_TRY(hipEventSynchronize(o.copied));
+  if (ctx->timing) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, o.k0, o.k1));
+    ctx->t_launches += 1;
+    ctx->t_samples += count;
+    ctx->t_seconds += ms * 1e-3;
+    for (uint32_t k = 0; k < count; ++k) {
+      ctx->t_arcs += o.h_arcs.p[k];
+      ctx->t_nodes += o.h_nodes.p[k];
+      ctx->t_hits += o.h_len.p[k] >= 2 ? o.h_len.p[k] - 2 : 0;
+    }
   }
-  HIP_TRY(hipStreamSynchronize(stream));
-  for (uint32_t k = 0; k < count; ++k) {
-    const uint32_t f = ctx->h_flags.p[k];
+  for (uint32_t k = 0; k < used; ++k) {
+    const uint32_t f = o.h_flags.p[k];
     if (f & kad::FLAG_OVERFLOW)
       return fail(KAD_EOVERFLOW, "a path count exceeded 128 bits (sample %u of the batch)", k);
     if (f & kad::FLAG_RNG) return fail(KAD_ERNG, "bounded draw rejected 64 times");
@@ -325,6 +348,7 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
   c->device = hip_device;
   HIP_TRY(hipSetDevice(hip_device));
   HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&c->rstream, hipStreamNonBlocking));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   c->cus = (uint32_t)prop.multiProcessorCount;
@@ -340,6 +364,7 @@ kad_status kad_ctx_destroy(kad_ctx *ctx) {
   if (!ctx) return KAD_OK;
   (void)hipSetDevice(ctx->device);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
+  if (ctx->rstream) (void)hipStreamDestroy(ctx->rstream);
   delete ctx;
   return KAD_OK;
 }
@@ -513,25 +538,25 @@ kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uin
   HIP_TRY(ctx->h_s.ensure(batch));
   HIP_TRY(ctx->h_t.ensure(batch));
   HIP_TRY(ctx->h_path.ensure((size_t)batch * stride));
+  OutSet &o = ctx->outs[0];
   uint64_t off = 0;
   bool short_buf = false;
   for (uint64_t done = 0; done < count;) {
     const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
-    if ((st = run_sampler(ctx, g, seed, phase, first + done, nb, stride, stream))) return st;
-    HIP_TRY(hipMemcpyAsync(ctx->h_s.p, ctx->o_s.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_t.p, ctx->o_t.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_len.p, ctx->o_len.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_flags.p, ctx->o_flags.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_arcs.p, ctx->o_arcs.p, (size_t)nb * 8, hipMemcpyDeviceToHost, stream));
-    HIP_TRY(hipMemcpyAsync(ctx->h_path.p, ctx->o_path.p, (size_t)nb * stride * 4, hipMemcpyDeviceToHost, stream));
+    if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream))) return st;
+    HIP_TRY(hipMemcpyAsync(ctx->h_s.p, o.s.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_t.p, o.t.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(o.h_len.p, o.len.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_path.p, o.path.p, (size_t)nb * stride * 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    if ((st = finish_batch(ctx, 0, nb, 0))) return st;  // flags are reported, not fatal
     for (uint32_t k = 0; k < nb; ++k) {
       const uint64_t idx = done + k;
       if (s) s[idx] = ctx->h_s.p[k];
       if (t) t[idx] = ctx->h_t.p[k];
-      if (arcs_scanned) arcs_scanned[idx] = ctx->h_arcs.p[k];
-      if (flags) flags[idx] = ctx->h_flags.p[k];
-      const uint32_t len = ctx->h_len.p[k];
+      if (arcs_scanned) arcs_scanned[idx] = o.h_arcs.p[k];
+      if (flags) flags[idx] = o.h_flags.p[k];
+      const uint32_t len = o.h_len.p[k];
       if (path_off) path_off[idx] = off;
       if (path_nodes) {
         if (off + len <= path_cap)
@@ -565,10 +590,11 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
   uint64_t arcs = 0;
   for (uint64_t done = 0; done < count;) {
     const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
-    if ((st = run_sampler(ctx, g, seed, phase, first + done, nb, stride, stream))) return st;
-    if ((st = collect_batch(ctx, nb, stream, false))) return st;
-    for (uint32_t k = 0; k < nb; ++k) arcs += ctx->h_arcs.p[k];
-    HIP_TRY(kad::launch_hit_reduce(ctx->o_path.p, ctx->o_len.p, stride, nb, g->n, ctx->count.p, stream));
+    if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream))) return st;
+    HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, g->n,
+                                   ctx->count.p, false, nullptr, nullptr, stream));
+    if ((st = finish_batch(ctx, 0, nb, nb))) return st;
+    for (uint32_t k = 0; k < nb; ++k) arcs += ctx->outs[0].h_arcs.p[k];
     done += nb;
   }
   HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)g->n * 8, hipMemcpyDeviceToHost, stream));
@@ -610,9 +636,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   uint64_t K = p->kernel_batch ? p->kernel_batch : DEFAULT_BATCH;
   K = std::max<uint64_t>(B, (K + B - 1) / B * B);
   if (K > (1u << 30)) return fail(KAD_EINVAL, "kernel_batch too large");
+  const uint32_t chunks_per_batch = (uint32_t)(K / B);
   const uint32_t stride = std::max<uint32_t>(vd, 2);
   if ((st = ensure_capacity(ctx, n, (uint32_t)K, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
+  const auto t_setup = clock::now();
 
   // ---- pilot (phase 0): alpha samples -> count0
   std::vector<uint64_t> count0(n, 0);
@@ -620,14 +648,16 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   uint64_t pilot_arcs = 0;
   for (uint64_t done = 0; done < alpha;) {
     const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->out_cap, alpha - done);
-    if ((st = run_sampler(ctx, g, p->seed, 0, done, nb, stride, stream))) return st;
-    if ((st = collect_batch(ctx, nb, stream, false))) return st;
-    for (uint32_t k = 0; k < nb; ++k) pilot_arcs += ctx->h_arcs.p[k];
-    HIP_TRY(kad::launch_hit_reduce(ctx->o_path.p, ctx->o_len.p, stride, nb, n, ctx->count.p, stream));
+    if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream))) return st;
+    HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
+                                   ctx->count.p, false, nullptr, nullptr, stream));
+    if ((st = finish_batch(ctx, 0, nb, nb))) return st;
+    for (uint32_t k = 0; k < nb; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
     done += nb;
   }
   HIP_TRY(hipMemcpyAsync(count0.data(), ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipStreamSynchronize(stream));
+  const auto t_pilot = clock::now();
 
   // ---- computeDelta (host, binary64)
   std::vector<double> lam_l(n, p->epsilon), lam_u(n, p->epsilon), L_l(n), L_u(n);
@@ -637,32 +667,139 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
                      L_l.data(), L_u.data(), &Cb);
   kad::StopChecker checker(n, p->mode, p->k, p->epsilon, omega, L_l.data(), L_u.data());
 
-  // ---- main phase (phase 1): batches of K samples, a check every B samples
-  HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, stream));
-  uint64_t tau = 0, arcs = 0;
+  const auto t_delta = clock::now();
+
+  // ---- main phase (phase 1): batches of samples, a check every B samples.
+  // The sampler runs on `stream`; the hit reductions and the check snapshots on the
+  // context's reduction stream, so batch b+1 is sampled while batch b is reduced and
+  // checked.  Batch b+1 is launched right after batch b's first check, sized from how
+  // far that check is from stopping; batch sizes never change the result, because the
+  // check is made at every multiple of B whatever the batches are.
+  // All-nodes: the reduction also keeps each stopping group's largest count on the
+  // device, so a check copies only those maxima.  Top-k: a check copies the counts.
+  hipStream_t rs = ctx->rstream;
+  const bool by_group = p->mode == KAD_ALL_NODES;
+  const size_t ngroups = checker.groups();
+  const size_t snap = by_group ? ngroups : (size_t)n;
+  HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, rs));
+  if (by_group) {
+    HIP_TRY(ctx->group.ensure(n));
+    HIP_TRY(ctx->gmax.ensure(ngroups));
+    HIP_TRY(hipMemcpyAsync(ctx->group.p, checker.group_of().data(), (size_t)n * 4,
+                           hipMemcpyHostToDevice, rs));
+    HIP_TRY(hipMemsetAsync(ctx->gmax.p, 0, ngroups * 8, rs));
+  }
+  PinBuf<uint64_t> snaps;  // one snapshot per check of the current batch
+  HIP_TRY(snaps.ensure(snap * chunks_per_batch));
+  while (ctx->chunk_ev.size() < chunks_per_batch) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->chunk_ev.push_back(e);
+  }
+  auto round_up = [&](double x) {
+    const double q = std::ceil(std::max(x, 1.0) / (double)B);
+    return (uint64_t)std::min<double>(q, (double)(K / B)) * B;
+  };
+  // first batch: the stopping rule evaluated on the pilot estimates (group maxima of
+  // the pilot counts scaled to tau), solved for tau by bisection over multiples of B
+  uint64_t first_nb = K;
+  if (by_group) {
+    std::vector<uint64_t> g0(ngroups, 0);
+    const auto &grp = checker.group_of();
+    for (uint32_t v = 0; v < n; ++v) g0[grp[v]] = std::max(g0[grp[v]], count0[v]);
+    std::vector<uint64_t> gs(ngroups);
+    auto passes = [&](uint64_t t) {
+      for (size_t q = 0; q < ngroups; ++q) gs[q] = (uint64_t)((double)g0[q] * (double)t / (double)alpha);
+      return checker.check_group_max(gs.data(), t);
+    };
+    uint64_t lo = 0, hi = (omega + B - 1) / B;  // in units of B
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (passes(mid * B)) hi = mid; else lo = mid;
+    }
+    first_nb = round_up(0.9 * (double)(hi * B));
+  }
+
+  uint64_t tau = 0, arcs = 0, launched = 0;
   bool rule = false, stop = false;
+  int cur = 0;
+  uint32_t cur_nb = (uint32_t)std::min<uint64_t>(first_nb, omega);
+  HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[cur].reduced, 0));
+  if ((st = launch_batch(ctx, g, p->seed, 1, 0, cur_nb, stride, cur, stream))) return st;
+  launched = cur_nb;
+  double worst = 0.0;
   while (!stop) {
-    // a whole number of check intervals (the last batch may end at omega)
-    const uint32_t nb = (uint32_t)std::min<uint64_t>(K, omega - tau);
-    if ((st = run_sampler(ctx, g, p->seed, 1, tau, nb, stride, stream))) return st;
-    if ((st = collect_batch(ctx, nb, stream, false))) return st;
-    for (uint32_t c0 = 0; c0 < nb && !stop;) {
-      const uint32_t cb = (uint32_t)std::min<uint64_t>(B, nb - c0);
-      HIP_TRY(kad::launch_hit_reduce(ctx->o_path.p + (size_t)c0 * stride, ctx->o_len.p + c0, stride, cb, n,
-                                     ctx->count.p, stream));
-      HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
-      HIP_TRY(hipStreamSynchronize(stream));
-      for (uint32_t k = c0; k < c0 + cb; ++k) arcs += ctx->h_arcs.p[k];
+    if (cur_nb == 0) return fail(KAD_EINVAL, "internal: empty batch before the stopping point");
+    const OutSet &o = ctx->outs[cur];
+    HIP_TRY(hipStreamWaitEvent(rs, o.copied, 0));
+    uint32_t nchunks = 0;
+    for (uint32_t c0 = 0; c0 < cur_nb; c0 += (uint32_t)B, ++nchunks) {
+      const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - c0);
+      HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)c0 * stride, o.len.p + c0, stride, cb, n,
+                                     ctx->count.p, false, by_group ? ctx->group.p : nullptr,
+                                     by_group ? ctx->gmax.p : nullptr, rs));
+      HIP_TRY(hipMemcpyAsync(snaps.p + (size_t)nchunks * snap, by_group ? ctx->gmax.p : ctx->count.p,
+                             snap * 8, hipMemcpyDeviceToHost, rs));
+      HIP_TRY(hipEventRecord(ctx->chunk_ev[nchunks], rs));
+    }
+    HIP_TRY(hipEventRecord(ctx->outs[cur].reduced, rs));
+    uint32_t next_nb = 0;
+    auto launch_next = [&]() -> kad_status {
+      if (launched >= omega) return KAD_OK;
+      // remaining samples predicted from the last check: the bounds shrink about as 1/tau
+      double want = (double)K;
+      if (by_group && worst > 0.0 && tau > 0) want = (double)tau * worst - (double)launched;
+      next_nb = (uint32_t)std::min<uint64_t>(round_up(want), omega - launched);
+      const int nxt = 1 - cur;
+      HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[nxt].reduced, 0));
+      kad_status s2 = launch_batch(ctx, g, p->seed, 1, launched, next_nb, stride, nxt, stream);
+      if (s2) return s2;
+      launched += next_nb;
+      return KAD_OK;
+    };
+    bool next_done = false;
+    uint32_t c = 0, c0 = 0;
+    for (; c0 < cur_nb; ++c, c0 += (uint32_t)B) {
+      const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - c0);
+      HIP_TRY(hipEventSynchronize(ctx->chunk_ev[c]));
       tau += cb;
-      c0 += cb;
+      const uint64_t *sp = snaps.p + (size_t)c * snap;
       if (tau >= omega) {
         stop = true;
-      } else if (cb == B && checker.check(ctx->h_count.p, tau)) {
+      } else if (cb == B && (by_group ? checker.check_group_max(sp, tau, &worst)
+                                      : checker.check(sp, tau))) {
         stop = true;
         rule = true;
       }
+      if (stop) break;
+      if (!next_done) {
+        if ((st = launch_next())) return st;
+        next_done = true;
+      }
     }
+    const uint32_t used = stop ? c0 + (uint32_t)std::min<uint64_t>(B, cur_nb - c0) : cur_nb;
+    if ((st = finish_batch(ctx, cur, cur_nb, used))) return st;
+    for (uint32_t k = 0; k < used; ++k) arcs += ctx->outs[cur].h_arcs.p[k];
+    if (stop) {
+      // undo the reductions of the check intervals past the stopping point
+      if (used < cur_nb)
+        HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)used * stride, o.len.p + used, stride,
+                                       cur_nb - used, n, ctx->count.p, true, nullptr, nullptr, rs));
+      if (next_done && next_nb) {
+        if ((st = finish_batch(ctx, 1 - cur, next_nb, 0))) return st;  // drain (timing only)
+      }
+      break;
+    }
+    if (!next_done) {
+      if ((st = launch_next())) return st;
+    }
+    cur = 1 - cur;
+    cur_nb = next_nb;
   }
+  HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, rs));
+  HIP_TRY(hipStreamSynchronize(rs));
+  HIP_TRY(hipStreamSynchronize(stream));
+  const auto t_main = clock::now();
 
   // ---- outputs (Theorem 1 intervals)
   r->tau = tau;
@@ -715,7 +852,15 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       }
     }
   }
-  r->seconds = std::chrono::duration<double>(clock::now() - t0).count();
+  const auto t_end = clock::now();
+  auto secs = [](clock::time_point a, clock::time_point b) {
+    return std::chrono::duration<double>(b - a).count();
+  };
+  r->seconds = secs(t0, t_end);
+  r->seconds_setup = secs(t0, t_setup);
+  r->seconds_pilot = secs(t_setup, t_pilot);
+  r->seconds_delta = secs(t_pilot, t_delta);
+  r->seconds_main = secs(t_delta, t_main);
   return ret;
 }
 

@@ -7,6 +7,7 @@
 #include "kad_stats.h"
 
 #include <math.h>
+#include <string.h>
 
 #include <algorithm>
 #include <map>
@@ -197,30 +198,104 @@ int vertex_diameter(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32
 
 // ------------------------------------------------------------------ computeDelta
 
+namespace {
+// Open-addressing map from a double's bit pattern to a slot index (values repeat a lot:
+// a node's constant depends only on its pilot count and its wanted half-widths).
+class ValueIndex {
+ public:
+  explicit ValueIndex(size_t expect) {
+    size_t cap = 1024;
+    while (cap < 2 * expect) cap *= 2;
+    keys_.assign(cap, EMPTY);
+    slot_.assign(cap, 0);
+  }
+  // index of x among the distinct values, inserting it (with the next index) if new
+  uint32_t find_or_add(double x) {
+    uint64_t k;
+    memcpy(&k, &x, 8);
+    if (k == EMPTY) k = EMPTY_ALIAS;
+    size_t h = (size_t)((k * 0x9E3779B97F4A7C15ULL) >> 17) & (keys_.size() - 1);
+    while (true) {
+      if (keys_[h] == k) return slot_[h];
+      if (keys_[h] == EMPTY) {
+        keys_[h] = k;
+        slot_[h] = (uint32_t)values.size();
+        values.push_back(x);
+        if (2 * values.size() > keys_.size()) grow();
+        return (uint32_t)values.size() - 1;
+      }
+      h = (h + 1) & (keys_.size() - 1);
+    }
+  }
+  std::vector<double> values;
+
+ private:
+  static constexpr uint64_t EMPTY = ~0ULL;                  // a NaN pattern, never a constant
+  static constexpr uint64_t EMPTY_ALIAS = 0xFFF8000000000001ULL;
+  void grow() {
+    std::vector<uint64_t> old_k;
+    std::vector<uint32_t> old_s;
+    old_k.swap(keys_);
+    old_s.swap(slot_);
+    keys_.assign(old_k.size() * 2, EMPTY);
+    slot_.assign(old_k.size() * 2, 0);
+    for (size_t q = 0; q < old_k.size(); ++q) {
+      if (old_k[q] == EMPTY) continue;
+      size_t h = (size_t)((old_k[q] * 0x9E3779B97F4A7C15ULL) >> 17) & (keys_.size() - 1);
+      while (keys_[h] != EMPTY) h = (h + 1) & (keys_.size() - 1);
+      keys_[h] = old_k[q];
+      slot_[h] = old_s[q];
+    }
+  }
+  std::vector<uint64_t> keys_;
+  std::vector<uint32_t> slot_;
+};
+}  // namespace
+
 void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
                    const double *lam_l, const double *lam_u, double delta, double eps_bal,
                    double *L_l, double *L_u, double *C_out) {
-  std::vector<double> cl(n), cu(n), vals(2 * (size_t)n);
+  // the 2n constants c_L(v), c_U(v) as indices into their distinct values
+  ValueIndex index(4096);
+  std::vector<uint32_t> il(n), iu(n);
+  std::vector<double> mult;
+  // most nodes repeat an earlier (count0, lambda_l, lambda_u): a direct-mapped memo of
+  // that triple skips recomputing the same two constants
+  struct Memo {
+    uint64_t c0, ll, lu;
+    uint32_t a, b;
+    bool used;
+  };
+  std::vector<Memo> memo(4096, Memo{0, 0, 0, 0, 0, false});
   for (uint32_t v = 0; v < n; ++v) {
-    const double b0 = (double)count0[v] / (double)alpha;
-    cl[v] = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
-    cu[v] = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
-    vals[2 * (size_t)v] = cl[v];
-    vals[2 * (size_t)v + 1] = cu[v];
+    uint64_t bl, bu;
+    memcpy(&bl, &lam_l[v], 8);
+    memcpy(&bu, &lam_u[v], 8);
+    const uint64_t h = (count0[v] * 0x9E3779B97F4A7C15ULL) ^ (bl * 0xC2B2AE3D27D4EB4FULL) ^
+                       (bu * 0x165667B19E3779F9ULL);
+    Memo &m = memo[(h >> 40) & 4095];
+    if (!(m.used && m.c0 == count0[v] && m.ll == bl && m.lu == bu)) {
+      const double b0 = (double)count0[v] / (double)alpha;
+      const double cl = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
+      const double cu = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
+      m = Memo{count0[v], bl, bu, index.find_or_add(cl), index.find_or_add(cu), true};
+      if (mult.size() < index.values.size()) mult.resize(index.values.size(), 0.0);
+    }
+    il[v] = m.a;
+    iu[v] = m.b;
+    mult[m.a] += 1.0;
+    mult[m.b] += 1.0;
   }
-  std::sort(vals.begin(), vals.end());
   // distinct constants with multiplicities, ascending
-  std::vector<std::pair<double, double>> groups;
-  for (double x : vals) {
-    if (!groups.empty() && groups.back().first == x)
-      groups.back().second += 1.0;
-    else
-      groups.emplace_back(x, 1.0);
-  }
+  const size_t nd = index.values.size();
+  std::vector<uint32_t> ord(nd);
+  for (uint32_t q = 0; q < nd; ++q) ord[q] = q;
+  std::sort(ord.begin(), ord.end(),
+            [&](uint32_t a, uint32_t b) { return index.values[a] < index.values[b]; });
   auto term = [](double C, double c) { return c == 0.0 ? 0.0 : exp(-C / c); };
   auto total = [&](double C) {
     double s = 0.0;
-    for (const auto &g : groups) s += g.second * term(C, g.first);
+    for (uint32_t q : ord) s += mult[q] * term(C, index.values[q]);
     return s;
   };
   // smallest C with total(C) <= delta/2 - eps*delta (the sum decreases in C)
@@ -236,9 +311,11 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
   }
   const double C = hi;
   const double floor_add = eps_bal * delta / (2.0 * (double)n);
+  std::vector<double> Lq(nd);
+  for (size_t q = 0; q < nd; ++q) Lq[q] = -log(term(C, index.values[q]) + floor_add);
   for (uint32_t v = 0; v < n; ++v) {
-    L_l[v] = -log(term(C, cl[v]) + floor_add);
-    L_u[v] = -log(term(C, cu[v]) + floor_add);
+    L_l[v] = Lq[il[v]];
+    L_u[v] = Lq[iu[v]];
   }
   if (C_out) *C_out = C;
 }
@@ -291,20 +368,52 @@ void topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha
 StopChecker::StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
                          const double *L_l, const double *L_u)
     : n_(n), mode_(mode), k_(k), eps_(eps), omega_(omega), Ll_(L_l), Lu_(L_u) {
-  std::map<std::pair<double, double>, uint32_t> ids;
+  // group = distinct (L_l, L_u) pair (a direct-mapped memo in front of the map: most
+  // nodes repeat an earlier pair)
+  std::map<std::pair<uint64_t, uint64_t>, uint32_t> ids;
+  struct Memo {
+    uint64_t a, b;
+    uint32_t g;
+    bool used;
+  };
+  std::vector<Memo> memo(4096, Memo{0, 0, 0, false});
   group_.resize(n);
   for (uint32_t v = 0; v < n; ++v) {
-    auto key = std::make_pair(L_l[v], L_u[v]);
-    auto it = ids.find(key);
-    if (it == ids.end()) {
-      it = ids.emplace(key, (uint32_t)gL_l_.size()).first;
-      gL_l_.push_back(L_l[v]);
-      gL_u_.push_back(L_u[v]);
+    uint64_t a, b;
+    memcpy(&a, &L_l[v], 8);
+    memcpy(&b, &L_u[v], 8);
+    Memo &m = memo[((a * 0x9E3779B97F4A7C15ULL ^ b * 0xC2B2AE3D27D4EB4FULL) >> 40) & 4095];
+    if (!(m.used && m.a == a && m.b == b)) {
+      auto key = std::make_pair(a, b);
+      auto it = ids.find(key);
+      if (it == ids.end()) {
+        it = ids.emplace(key, (uint32_t)gL_l_.size()).first;
+        gL_l_.push_back(L_l[v]);
+        gL_u_.push_back(L_u[v]);
+      }
+      m = Memo{a, b, it->second, true};
     }
-    group_[v] = it->second;
+    group_[v] = m.g;
   }
   gmax_.resize(gL_l_.size());
   if (mode_ == 1) in_top_.assign(n, 0);
+}
+
+bool StopChecker::check_group_max(const uint64_t *gmax, uint64_t tau, double *worst) const {
+  const double T = (double)tau, W = (double)omega_;
+  bool stop = true;
+  double w = 0.0;
+  for (size_t g = 0; g < gL_l_.size(); ++g) {
+    const double bt = (double)gmax[g] / T;
+    const double f = bound_f(bt, gL_l_[g], W, T), gg = bound_g(bt, gL_u_[g], W, T);
+    if (!(f <= eps_) || !(gg <= eps_)) {
+      stop = false;
+      if (!worst) return false;
+    }
+    w = std::max(w, std::max(f, gg) / eps_);
+  }
+  if (worst) *worst = w;
+  return stop;
 }
 
 bool StopChecker::check(const uint64_t *count, uint64_t tau) {

@@ -1,6 +1,7 @@
 // Host-side statistics of the adaptive algorithm (library-internal interface).
 // All binary64, compiled without FMA contraction.
 #pragma once
+#include <stddef.h>
 #include <stdint.h>
 
 #include <vector>
@@ -35,6 +36,12 @@ class StopChecker {
   StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
               const double *L_l, const double *L_u);
   bool check(const uint64_t *count, uint64_t tau);
+  // All-nodes task only: the same decision from the per-group largest counts.  *worst
+  // (optional) receives max over groups of max(f, g) / eps, how far the rule is from
+  // stopping (a scheduling hint; the decision itself is f <= eps and g <= eps).
+  bool check_group_max(const uint64_t *gmax, uint64_t tau, double *worst = nullptr) const;
+  const std::vector<uint32_t> &group_of() const { return group_; }
+  size_t groups() const { return gL_l_.size(); }
 
  private:
   uint32_t n_, mode_, k_;
