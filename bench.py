@@ -59,6 +59,8 @@ def main():
     ap.add_argument("--check-interval", type=int, default=0)
     ap.add_argument("--cpu-samples", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB (scale for HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
@@ -71,6 +73,16 @@ def main():
     import paper_1604_08553_amd as kad
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        x = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "device copy", "bytes_read": nbytes,
+                          "bytes_written": nbytes}), flush=True)
+        return
     t0 = time.perf_counter()
     csr = gg.workload(args.workload)
     gen_s = time.perf_counter() - t0
@@ -88,8 +100,10 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
+    arrays = None  # result arrays reused across steps
     for s in range(args.steps):
-        r = kad.run(ctx, G, **kw)
+        r = kad.run(ctx, G, out=arrays, **kw)
+        arrays = {k: r[k] for k in ("count", "bc", "lower", "upper")}
         runs.append(r)
         print(f"[bench] step {s}: tau={r['tau']} omega={r['omega']} stop={r['stop_reason']} "
               f"{r['seconds']:.3f} s", file=sys.stderr, flush=True)

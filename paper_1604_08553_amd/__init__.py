@@ -230,13 +230,23 @@ def _stream(stream):
 
 def run(ctx: Context, graph: Graph, epsilon: float, delta: float, mode: str = "all", k: int = 0,
         seed: int = 1, check_interval: int = 0, kernel_batch: int = 0, vd_override: int = 0,
-        c: float = 0.0, balance_eps: float = 0.0, topk_cap: int = 0, stream=None) -> dict:
-    """The adaptive run (Algorithm 1).  Returns scalars plus the per-node arrays."""
+        c: float = 0.0, balance_eps: float = 0.0, topk_cap: int = 0, stream=None,
+        out: dict = None) -> dict:
+    """The adaptive run (Algorithm 1).  Returns scalars plus the per-node arrays.
+
+    ``out`` may hold preallocated arrays "count" (uint64[n]), "bc", "lower", "upper"
+    (float64[n]) to be filled in place (saves page-faulting fresh arrays per call)."""
     n = graph.n
     p = _Params(epsilon, delta, TOPK if mode == "topk" else ALL_NODES, k, seed, check_interval,
                 kernel_batch, vd_override, 0, c, balance_eps)
-    out = {"count": np.zeros(n, dtype=np.uint64), "bc": np.zeros(n), "lower": np.zeros(n),
-           "upper": np.zeros(n)}
+    prev = out or {}
+    out = {"count": prev.get("count"), "bc": prev.get("bc"), "lower": prev.get("lower"),
+           "upper": prev.get("upper")}
+    for name, dt in (("count", np.uint64), ("bc", np.float64), ("lower", np.float64),
+                     ("upper", np.float64)):
+        a = out[name]
+        if a is None or a.shape != (n,) or a.dtype != dt or not a.flags.c_contiguous:
+            out[name] = np.empty(n, dtype=dt)
     cap = topk_cap or (n if mode == "topk" else 0)
     tk = {"topk_node": np.zeros(max(cap, 1), dtype=np.uint32),
           "rank_lo": np.zeros(max(cap, 1), dtype=np.uint32),

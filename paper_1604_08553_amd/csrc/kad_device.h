@@ -50,12 +50,26 @@ hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
                           uint32_t grid, hipStream_t stream);
 
+// Node tiles of the hit reduction: 8,192 ids each, at most this many tiles (graphs of
+// up to 2^25 nodes).
+constexpr uint32_t MAX_HIT_TILES_PUBLIC = 4096;
+constexpr uint32_t HIT_TILE_IDS = 8192;
+
+// Scratch of the hit reduction: one bin of `cap` node ids per tile (cap >= the hits of
+// one call), and the bins' fill counters (all zero between calls).
+struct HitScratch {
+  uint32_t *bins;
+  uint64_t cap;
+  uint32_t *bin_count;
+};
+
 // count[v] += (or -=, with subtract) the number of samples in [0, nsamp) whose path has
 // v as an interior node.  With gmax != NULL also raises gmax[group[v]] to the new count
 // of every changed node.
 hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t stride,
                              uint32_t nsamp, uint32_t n, uint64_t *count, bool subtract,
-                             const uint32_t *group, uint64_t *gmax, hipStream_t stream);
+                             const uint32_t *group, uint64_t *gmax, const HitScratch &hs,
+                             hipStream_t stream);
 
 // Zero a small device buffer with a kernel (no memset node when captured).
 hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t stream);

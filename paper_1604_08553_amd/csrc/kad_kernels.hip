@@ -35,7 +35,8 @@ constexpr int PI_LDS = 1024;  // candidate edges kept in LDS; more spill to the 
 constexpr uint32_t MAX_ATTEMPTS = 64;
 constexpr int MAXLEV = 32;     // levels per side whose node lists are remembered
 constexpr int MATCH_CAP = 192; // predecessor candidates a backtracking wave keeps in LDS
-constexpr uint64_t SMALL_EXPANSION = 512;  // arcs: up to this, one combined scan per level
+constexpr uint64_t SMALL_EXPANSION = 512;
+constexpr uint32_t MAX_HIT_TILES = MAX_HIT_TILES_PUBLIC;  // arcs: up to this, one combined scan per level
 
 static_assert(CHUNK == 2 * BLOCK, "two staged frontier nodes per thread");
 
@@ -836,42 +837,144 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g, SlotState
 }
 
 // ------------------------------------------------------------------ hit reduction
+// Two passes per check interval.  partition: each workgroup takes a slice of the
+// samples, counts its interior hits per node tile in LDS, reserves room in each
+// tile's bin with one atomic per (workgroup, tile) and copies the hits there.  tile:
+// one workgroup per tile builds an LDS histogram of its bin and adds it to the
+// counters of the tile -- every counter has a single owner, so the counters see no
+// atomics.
 constexpr int HIT_BLOCK = 256;
-constexpr uint32_t HIT_TILE = 8192;  // node ids per workgroup (32 KB LDS histogram)
+constexpr uint32_t HIT_TILE = 8192;   // node ids per tile (32 KB LDS histogram)
+constexpr uint32_t SAMPLES_PER_PART = 64;
 
-__global__ __launch_bounds__(HIT_BLOCK) void hit_reduce_kernel(const uint32_t *path,
-                                                               const uint32_t *len,
-                                                               uint32_t stride, uint32_t nsamp,
-                                                               uint32_t n, uint64_t *count,
-                                                               int subtract,
-                                                               const uint32_t *group,
-                                                               uint64_t *gmax) {
-  __shared__ uint32_t hist[HIT_TILE];
-  const uint32_t tile0 = blockIdx.x * HIT_TILE;
-  for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) hist[b] = 0;
+// Bin entries pack a node id (below 2^25) with a multiplicity (at most the samples of
+// one partition workgroup) in the top 7 bits.
+constexpr uint32_t ENTRY_ID_BITS = 25;
+constexpr uint32_t AGG_SLOTS = 1024;  // LDS hash of one partition workgroup's hits
+static_assert(SAMPLES_PER_PART < (1u << (32 - ENTRY_ID_BITS)), "multiplicity fits its bits");
+static_assert(AGG_SLOTS == 1024, "the probe hash takes 10 bits");
+static_assert((uint64_t)MAX_HIT_TILES * HIT_TILE <= (1ull << ENTRY_ID_BITS), "ids fit their bits");
+
+// spp samples per workgroup.  With aggregate, spp * (stride - 2) <= AGG_SLOTS / 2, so
+// the LDS hash is at most half full and every probe sequence ends; without it (paths
+// too long for the hash) every hit is its own entry of multiplicity 1.
+__global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(const uint32_t *path,
+                                                                  const uint32_t *len,
+                                                                  uint32_t stride,
+                                                                  uint32_t nsamp, uint32_t tiles,
+                                                                  uint32_t spp, int aggregate,
+                                                                  uint32_t *bins, uint64_t cap,
+                                                                  uint32_t *bin_count) {
+  __shared__ uint32_t tcount[MAX_HIT_TILES];
+  __shared__ uint32_t tbase[MAX_HIT_TILES];
+  __shared__ uint32_t akey[AGG_SLOTS];
+  __shared__ uint32_t acnt[AGG_SLOTS];
+  const uint32_t s0 = blockIdx.x * spp;
+  const uint32_t s1 = min(nsamp, s0 + spp);
+  const uint32_t entries = (s1 - s0) * stride;
+  for (uint32_t t = threadIdx.x; t < tiles; t += HIT_BLOCK) tcount[t] = 0;
+  if (!aggregate) {
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < entries; e += HIT_BLOCK) {
+      const uint32_t k = s0 + e / stride, j = e % stride;
+      if (j >= 1 && j + 1 < len[k]) atomicAdd(&tcount[path[(size_t)k * stride + j] / HIT_TILE], 1u);
+    }
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < tiles; t += HIT_BLOCK) {
+      const uint32_t c = tcount[t];
+      if (c) tbase[t] = atomicAdd(&bin_count[t], c);
+      tcount[t] = 0;
+    }
+    __syncthreads();
+    for (uint32_t e = threadIdx.x; e < entries; e += HIT_BLOCK) {
+      const uint32_t k = s0 + e / stride, j = e % stride;
+      if (j >= 1 && j + 1 < len[k]) {
+        const uint32_t v = path[(size_t)k * stride + j];
+        const uint32_t t = v / HIT_TILE;
+        const uint32_t pos = tbase[t] + atomicAdd(&tcount[t], 1u);
+        bins[(size_t)t * cap + pos] = v | (1u << ENTRY_ID_BITS);
+      }
+    }
+    return;
+  }
+  for (uint32_t q = threadIdx.x; q < AGG_SLOTS; q += HIT_BLOCK) {
+    akey[q] = 0xFFFFFFFFu;
+    acnt[q] = 0;
+  }
   __syncthreads();
-  const uint64_t total = (uint64_t)nsamp * stride;
-  for (uint64_t e = threadIdx.x; e < total; e += HIT_BLOCK) {
-    const uint32_t k = (uint32_t)(e / stride);
-    const uint32_t j = (uint32_t)(e - (uint64_t)k * stride);
-    const uint32_t l = len[k];
-    if (j >= 1 && j + 1 < l) {
-      const uint32_t v = path[e] - tile0;
-      if (v < HIT_TILE) atomicAdd(&hist[v], 1u);
+  // aggregate the slice's interior hits by node (a hub appears on many paths)
+  for (uint32_t e = threadIdx.x; e < entries; e += HIT_BLOCK) {
+    const uint32_t k = s0 + e / stride, j = e % stride;
+    if (j >= 1 && j + 1 < len[k]) {
+      const uint32_t v = path[(size_t)k * stride + j];
+      uint32_t h = (v * 2654435761u) >> 22;  // 10 bits
+      for (;;) {  // at most AGG_SLOTS / 2 keys: a free slot is always found
+        const uint32_t old = atomicCAS(&akey[h], 0xFFFFFFFFu, v);
+        if (old == 0xFFFFFFFFu || old == v) break;
+        h = (h + 1) & (AGG_SLOTS - 1);
+      }
+      atomicAdd(&acnt[h], 1u);
     }
   }
   __syncthreads();
-  for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) {
-    const uint32_t h = hist[b];
-    const uint32_t v = tile0 + b;
+  for (uint32_t q = threadIdx.x; q < AGG_SLOTS; q += HIT_BLOCK)
+    if (acnt[q]) atomicAdd(&tcount[akey[q] / HIT_TILE], 1u);
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < tiles; t += HIT_BLOCK) {
+    const uint32_t c = tcount[t];
+    if (c) tbase[t] = atomicAdd(&bin_count[t], c);
+    tcount[t] = 0;
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < AGG_SLOTS; q += HIT_BLOCK) {
+    const uint32_t c = acnt[q];
+    if (c) {
+      const uint32_t v = akey[q];
+      const uint32_t t = v / HIT_TILE;
+      const uint32_t pos = tbase[t] + atomicAdd(&tcount[t], 1u);
+      bins[(size_t)t * cap + pos] = v | (c << ENTRY_ID_BITS);  // pos < cap (see launcher)
+    }
+  }
+}
+
+__global__ __launch_bounds__(HIT_BLOCK) void hit_tile_kernel(const uint32_t *bins, uint64_t cap,
+                                                             uint32_t *bin_count, uint32_t n,
+                                                             uint64_t *count, int subtract,
+                                                             const uint32_t *group,
+                                                             uint64_t *gmax) {
+  __shared__ uint32_t hist[HIT_TILE];
+  const uint32_t t = blockIdx.x;
+  const uint32_t m = bin_count[t];
+  if (m == 0) return;  // uniform for the workgroup
+  const uint32_t tile0 = t * HIT_TILE;
+  const uint32_t *bin = bins + (size_t)t * cap;
+  constexpr uint32_t ID_MASK = (1u << ENTRY_ID_BITS) - 1u;
+  for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) hist[b] = 0;
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < m; q += HIT_BLOCK) {
+    const uint32_t x = bin[q];
+    atomicAdd(&hist[(x & ID_MASK) - tile0], x >> ENTRY_ID_BITS);
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < m; q += HIT_BLOCK) {
+    const uint32_t v = bin[q] & ID_MASK;
+    const uint32_t h = atomicExch(&hist[v - tile0], 0u);  // the first claimer owns node v
     if (h && v < n) {
       const uint64_t c = subtract ? count[v] - h : count[v] + h;
       count[v] = c;
       // running maximum of the counts of each stopping-rule group (counts only grow
       // while the maxima are in use)
-      if (gmax) atomicMax((unsigned long long *)&gmax[group[v]], (unsigned long long)c);
+      if (gmax) {
+        // most nodes of a popular group stay below its maximum: skip those atomics (a
+        // stale read only costs an unneeded atomic)
+        unsigned long long *gm = (unsigned long long *)&gmax[group[v]];
+        if (c > __hip_atomic_load(gm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+          atomicMax(gm, (unsigned long long)c);
+      }
     }
   }
+  __syncthreads();
+  if (threadIdx.x == 0) bin_count[t] = 0;  // ready for the next interval
 }
 
 __global__ void zero_u32_kernel(uint32_t *p, uint32_t count) {
@@ -892,11 +995,19 @@ hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed,
 
 hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t stride,
                              uint32_t nsamp, uint32_t n, uint64_t *count, bool subtract,
-                             const uint32_t *group, uint64_t *gmax, hipStream_t stream) {
+                             const uint32_t *group, uint64_t *gmax, const HitScratch &hs,
+                             hipStream_t stream) {
   if (nsamp == 0) return hipSuccess;
   const uint32_t tiles = (n + HIT_TILE - 1) / HIT_TILE;
-  hipLaunchKernelGGL(hit_reduce_kernel, dim3(tiles), dim3(HIT_BLOCK), 0, stream, path, len,
-                     stride, nsamp, n, count, subtract ? 1 : 0, group, gmax);
+  const uint32_t inner = stride > 2 ? stride - 2 : 1;  // most interior nodes of a path
+  if (tiles > MAX_HIT_TILES || (uint64_t)nsamp * inner > hs.cap) return hipErrorInvalidValue;
+  const bool aggregate = inner <= AGG_SLOTS / 2;
+  const uint32_t spp = aggregate ? max(1u, min(SAMPLES_PER_PART, (AGG_SLOTS / 2) / inner)) : 1u;
+  hipLaunchKernelGGL(hit_partition_kernel, dim3((nsamp + spp - 1) / spp), dim3(HIT_BLOCK), 0,
+                     stream, path, len, stride, nsamp, tiles, spp, aggregate ? 1 : 0, hs.bins,
+                     hs.cap, hs.bin_count);
+  hipLaunchKernelGGL(hit_tile_kernel, dim3(tiles), dim3(HIT_BLOCK), 0, stream, hs.bins, hs.cap,
+                     hs.bin_count, n, count, subtract ? 1 : 0, group, gmax);
   return hipGetLastError();
 }
 

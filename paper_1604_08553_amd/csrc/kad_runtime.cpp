@@ -117,9 +117,14 @@ struct kad_ctx {
   OutSet outs[2];
   DevBuf<uint32_t> work, group;
   DevBuf<uint64_t> count, gmax;
+  DevBuf<uint32_t> bins, bin_count;  // hit-reduction scratch (bin_count all zero between calls)
+  uint64_t bins_cap = 0;
   PinBuf<uint32_t> h_s, h_t, h_path;
   PinBuf<uint64_t> h_count;
   std::vector<hipEvent_t> chunk_ev;
+  // host scratch of kad_run, kept across calls (large fresh allocations fault in pages)
+  std::vector<uint64_t> h_count0;
+  std::vector<double> h_lam_l, h_lam_u, h_L_l, h_L_u, h_bc, h_lo, h_hi;
   // timing of the sampler launches (HIP events on the launch stream)
   bool timing = false;
   uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0;
@@ -245,7 +250,30 @@ kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t st
   HIP_TRY(ctx->work.ensure(1));
   HIP_TRY(ctx->count.ensure(n));
   HIP_TRY(ctx->h_count.ensure(n));
+  // hit-reduction bins: room in every tile for all the hits of one reduction call
+  const uint64_t tiles = (n + kad::HIT_TILE_IDS - 1) / kad::HIT_TILE_IDS;
+  if (tiles > kad::MAX_HIT_TILES_PUBLIC)
+    return fail(KAD_EINVAL, "graphs above %u nodes are not supported by the hit reduction",
+                kad::MAX_HIT_TILES_PUBLIC * kad::HIT_TILE_IDS);
+  const uint64_t cap = (uint64_t)ctx->out_cap * std::max<uint32_t>(ctx->out_stride - 2, 1);
+  if (cap > ctx->bins_cap || tiles * cap > ctx->bins.n) {
+    ctx->bins.release();
+    HIP_TRY(ctx->bins.ensure(tiles * cap));
+    ctx->bins_cap = cap;
+  }
+  if (ctx->bin_count.n == 0) {
+    HIP_TRY(ctx->bin_count.ensure(kad::MAX_HIT_TILES_PUBLIC));
+    HIP_TRY(hipMemset(ctx->bin_count.p, 0, kad::MAX_HIT_TILES_PUBLIC * 4));
+  }
   return KAD_OK;
+}
+
+kad::HitScratch hit_scratch(kad_ctx *ctx) {
+  kad::HitScratch h;
+  h.bins = ctx->bins.p;
+  h.cap = ctx->bins_cap;
+  h.bin_count = ctx->bin_count.p;
+  return h;
 }
 
 // Enqueue the sampler on ids [first, first+count) into output set `set`, then the
@@ -592,7 +620,7 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
     const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
     if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream))) return st;
     HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, g->n,
-                                   ctx->count.p, false, nullptr, nullptr, stream));
+                                   ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
     if ((st = finish_batch(ctx, 0, nb, nb))) return st;
     for (uint32_t k = 0; k < nb; ++k) arcs += ctx->outs[0].h_arcs.p[k];
     done += nb;
@@ -643,29 +671,58 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   const auto t_setup = clock::now();
 
   // ---- pilot (phase 0): alpha samples -> count0
-  std::vector<uint64_t> count0(n, 0);
+  std::vector<uint64_t> &count0 = ctx->h_count0;
+  count0.resize(n);
   HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, stream));
   uint64_t pilot_arcs = 0;
+  uint32_t pilot_last = 0;
   for (uint64_t done = 0; done < alpha;) {
+    if (pilot_last) {  // several pilot batches: the previous one must be read first
+      if ((st = finish_batch(ctx, 0, pilot_last, pilot_last))) return st;
+      for (uint32_t k = 0; k < pilot_last; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
+    }
     const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->out_cap, alpha - done);
     if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream))) return st;
     HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
-                                   ctx->count.p, false, nullptr, nullptr, stream));
-    if ((st = finish_batch(ctx, 0, nb, nb))) return st;
-    for (uint32_t k = 0; k < nb; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
+                                   ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
+    pilot_last = nb;
     done += nb;
   }
   HIP_TRY(hipMemcpyAsync(count0.data(), ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
-  HIP_TRY(hipStreamSynchronize(stream));
+  hipEvent_t pilot_done = nullptr;
+  HIP_TRY(hipEventCreateWithFlags(&pilot_done, hipEventDisableTiming));
+  HIP_TRY(hipEventRecord(pilot_done, stream));
+
+  // ---- the first main-phase batch (phase 1 does not depend on the pilot) is sampled
+  // while the host runs computeDelta; half the cap, in whole check intervals
+  const int first_set = 1;
+  const uint32_t first_nb = (uint32_t)std::min<uint64_t>(
+      omega, std::min<uint64_t>(K, std::max<uint64_t>(B, (omega / 2 + B - 1) / B * B)));
+  HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[first_set].reduced, 0));
+  if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream))) {
+    (void)hipEventDestroy(pilot_done);
+    return st;
+  }
+  HIP_TRY(hipEventSynchronize(pilot_done));
+  (void)hipEventDestroy(pilot_done);
+  if ((st = finish_batch(ctx, 0, pilot_last, pilot_last))) return st;
+  for (uint32_t k = 0; k < pilot_last; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
   const auto t_pilot = clock::now();
 
   // ---- computeDelta (host, binary64)
-  std::vector<double> lam_l(n, p->epsilon), lam_u(n, p->epsilon), L_l(n), L_u(n);
+  std::vector<double> &lam_l = ctx->h_lam_l, &lam_u = ctx->h_lam_u, &L_l = ctx->h_L_l,
+                      &L_u = ctx->h_L_u;
+  lam_l.assign(n, p->epsilon);
+  lam_u.assign(n, p->epsilon);
+  L_l.resize(n);
+  L_u.resize(n);
   if (p->mode == KAD_TOPK) kad::topk_lambdas(n, p->k, count0.data(), alpha, p->epsilon, lam_l.data(), lam_u.data());
   double Cb = 0;
+  kad::Groups groups;
   kad::compute_delta(n, count0.data(), alpha, omega, lam_l.data(), lam_u.data(), p->delta, eb,
-                     L_l.data(), L_u.data(), &Cb);
-  kad::StopChecker checker(n, p->mode, p->k, p->epsilon, omega, L_l.data(), L_u.data());
+                     L_l.data(), L_u.data(), &Cb, &groups);
+  kad::StopChecker checker(n, p->mode, p->k, p->epsilon, omega, L_l.data(), L_u.data(),
+                           std::move(groups));
 
   const auto t_delta = clock::now();
 
@@ -700,33 +757,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     const double q = std::ceil(std::max(x, 1.0) / (double)B);
     return (uint64_t)std::min<double>(q, (double)(K / B)) * B;
   };
-  // first batch: the stopping rule evaluated on the pilot estimates (group maxima of
-  // the pilot counts scaled to tau), solved for tau by bisection over multiples of B
-  uint64_t first_nb = K;
-  if (by_group) {
-    std::vector<uint64_t> g0(ngroups, 0);
-    const auto &grp = checker.group_of();
-    for (uint32_t v = 0; v < n; ++v) g0[grp[v]] = std::max(g0[grp[v]], count0[v]);
-    std::vector<uint64_t> gs(ngroups);
-    auto passes = [&](uint64_t t) {
-      for (size_t q = 0; q < ngroups; ++q) gs[q] = (uint64_t)((double)g0[q] * (double)t / (double)alpha);
-      return checker.check_group_max(gs.data(), t);
-    };
-    uint64_t lo = 0, hi = (omega + B - 1) / B;  // in units of B
-    while (hi - lo > 1) {
-      const uint64_t mid = (lo + hi) / 2;
-      if (passes(mid * B)) hi = mid; else lo = mid;
-    }
-    first_nb = round_up(0.9 * (double)(hi * B));
-  }
 
-  uint64_t tau = 0, arcs = 0, launched = 0;
+  uint64_t tau = 0, arcs = 0, launched = first_nb;
   bool rule = false, stop = false;
-  int cur = 0;
-  uint32_t cur_nb = (uint32_t)std::min<uint64_t>(first_nb, omega);
-  HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[cur].reduced, 0));
-  if ((st = launch_batch(ctx, g, p->seed, 1, 0, cur_nb, stride, cur, stream))) return st;
-  launched = cur_nb;
+  int cur = first_set;
+  uint32_t cur_nb = first_nb;
   double worst = 0.0;
   while (!stop) {
     if (cur_nb == 0) return fail(KAD_EINVAL, "internal: empty batch before the stopping point");
@@ -737,7 +772,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - c0);
       HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)c0 * stride, o.len.p + c0, stride, cb, n,
                                      ctx->count.p, false, by_group ? ctx->group.p : nullptr,
-                                     by_group ? ctx->gmax.p : nullptr, rs));
+                                     by_group ? ctx->gmax.p : nullptr, hit_scratch(ctx), rs));
       HIP_TRY(hipMemcpyAsync(snaps.p + (size_t)nchunks * snap, by_group ? ctx->gmax.p : ctx->count.p,
                              snap * 8, hipMemcpyDeviceToHost, rs));
       HIP_TRY(hipEventRecord(ctx->chunk_ev[nchunks], rs));
@@ -784,7 +819,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       // undo the reductions of the check intervals past the stopping point
       if (used < cur_nb)
         HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)used * stride, o.len.p + used, stride,
-                                       cur_nb - used, n, ctx->count.p, true, nullptr, nullptr, rs));
+                                       cur_nb - used, n, ctx->count.p, true, nullptr, nullptr, hit_scratch(ctx), rs));
       if (next_done && next_nb) {
         if ((st = finish_batch(ctx, 1 - cur, next_nb, 0))) return st;  // drain (timing only)
       }
@@ -815,27 +850,48 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   r->n = n;
   r->C = Cb;
   const uint64_t *cnt = ctx->h_count.p;
-  std::vector<double> bc(n), lo(n), hi(n);
+  // per-node outputs, written straight into the caller's arrays when given
+  std::vector<double> &bcs = ctx->h_bc, &los = ctx->h_lo, &his = ctx->h_hi;
+  const bool topk = p->mode == KAD_TOPK;
+  double *bc = r->bc ? r->bc : (bcs.resize(n), bcs.data());
+  double *lo = r->lower && !topk ? r->lower : (los.resize(n), los.data());
+  double *hi = r->upper && !topk ? r->upper : (his.resize(n), his.data());
   const double T = (double)tau, W = (double)omega;
-  for (uint32_t v = 0; v < n; ++v) {
-    bc[v] = (double)cnt[v] / T;
-    if (rule) {
-      lo[v] = bc[v] - kad::bound_f(bc[v], L_l[v], W, T);
-      hi[v] = bc[v] + kad::bound_g(bc[v], L_u[v], W, T);
-    } else {
-      lo[v] = bc[v] - p->epsilon;
-      hi[v] = bc[v] + p->epsilon;
+  // f and g depend on (count, L_l, L_u) only: memoise per (group, count)
+  struct Memo {
+    uint64_t c;
+    uint32_t grp;
+    bool used;
+    double f, g;
+  };
+  const auto &grp_of = checker.group_of();
+  kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+    std::vector<Memo> memo(rule ? 16384 : 0, Memo{0, 0, false, 0.0, 0.0});
+    if (r->count) memcpy(r->count + vb, cnt + vb, (size_t)(ve - vb) * 8);
+    for (uint32_t v = vb; v < ve; ++v) {
+      bc[v] = (double)cnt[v] / T;
+      if (rule) {
+        const uint32_t gv = grp_of[v];
+        Memo &m = memo[(uint32_t)((cnt[v] * 0x9E3779B97F4A7C15ULL ^ (uint64_t)gv * 0xC2B2AE3D27D4EB4FULL) >> 50)];
+        if (!(m.used && m.c == cnt[v] && m.grp == gv))
+          m = Memo{cnt[v], gv, true, kad::bound_f(bc[v], L_l[v], W, T), kad::bound_g(bc[v], L_u[v], W, T)};
+        lo[v] = bc[v] - m.f;
+        hi[v] = bc[v] + m.g;
+      } else {
+        lo[v] = bc[v] - p->epsilon;
+        hi[v] = bc[v] + p->epsilon;
+      }
     }
+  });
+  if (topk) {
+    if (r->lower) memcpy(r->lower, lo, (size_t)n * 8);
+    if (r->upper) memcpy(r->upper, hi, (size_t)n * 8);
   }
-  if (r->count) memcpy(r->count, cnt, (size_t)n * 8);
-  if (r->bc) memcpy(r->bc, bc.data(), (size_t)n * 8);
-  if (r->lower) memcpy(r->lower, lo.data(), (size_t)n * 8);
-  if (r->upper) memcpy(r->upper, hi.data(), (size_t)n * 8);
   r->topk_len = 0;
   kad_status ret = KAD_OK;
   if (p->mode == KAD_TOPK) {
     std::vector<uint32_t> rlo(n), rhi(n), sel;
-    kad::rank_intervals(n, lo.data(), hi.data(), rlo.data(), rhi.data());
+    kad::rank_intervals(n, lo, hi, rlo.data(), rhi.data());
     for (uint32_t v = 0; v < n; ++v)
       if (rlo[v] <= p->k) sel.push_back(v);
     std::sort(sel.begin(), sel.end(), [cnt](uint32_t a, uint32_t b) {

@@ -17,6 +17,25 @@
 
 namespace kad {
 
+unsigned parallel_threads(uint32_t n) {
+  const unsigned hw = std::max(1u, std::thread::hardware_concurrency());
+  return std::max(1u, std::min({16u, hw, n / 65536u + 1u}));
+}
+
+void parallel_ranges(uint32_t n, const std::function<void(uint32_t, uint32_t, unsigned)> &f) {
+  const unsigned nt = parallel_threads(n);
+  if (nt == 1) {
+    f(0, n, 0);
+    return;
+  }
+  std::vector<std::thread> pool;
+  for (unsigned w = 0; w < nt; ++w) {
+    const uint32_t b = (uint32_t)((uint64_t)n * w / nt), e = (uint32_t)((uint64_t)n * (w + 1) / nt);
+    pool.emplace_back(f, b, e, w);
+  }
+  for (auto &t : pool) t.join();
+}
+
 // ------------------------------------------------------------------ schedule
 
 uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c) {
@@ -254,37 +273,98 @@ class ValueIndex {
 
 void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
                    const double *lam_l, const double *lam_u, double delta, double eps_bal,
-                   double *L_l, double *L_u, double *C_out) {
-  // the 2n constants c_L(v), c_U(v) as indices into their distinct values
+                   double *L_l, double *L_u, double *C_out, Groups *groups) {
+  // The 2n constants c_L(v) = 2 b0(v) omega / lambda_L(v)^2 (and c_U) are handled as
+  // indices into their distinct values with multiplicities.
   ValueIndex index(4096);
-  std::vector<uint32_t> il(n), iu(n);
   std::vector<double> mult;
-  // most nodes repeat an earlier (count0, lambda_l, lambda_u): a direct-mapped memo of
-  // that triple skips recomputing the same two constants
-  struct Memo {
-    uint64_t c0, ll, lu;
-    uint32_t a, b;
-    bool used;
+  auto add_value = [&](double x, double times) {
+    const uint32_t q = index.find_or_add(x);
+    if (mult.size() < index.values.size()) mult.resize(index.values.size(), 0.0);
+    mult[q] += times;
+    return q;
   };
-  std::vector<Memo> memo(4096, Memo{0, 0, 0, 0, 0, false});
-  for (uint32_t v = 0; v < n; ++v) {
-    uint64_t bl, bu;
-    memcpy(&bl, &lam_l[v], 8);
-    memcpy(&bu, &lam_u[v], 8);
-    const uint64_t h = (count0[v] * 0x9E3779B97F4A7C15ULL) ^ (bl * 0xC2B2AE3D27D4EB4FULL) ^
-                       (bu * 0x165667B19E3779F9ULL);
-    Memo &m = memo[(h >> 40) & 4095];
-    if (!(m.used && m.c0 == count0[v] && m.ll == bl && m.lu == bu)) {
-      const double b0 = (double)count0[v] / (double)alpha;
-      const double cl = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
-      const double cu = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
-      m = Memo{count0[v], bl, bu, index.find_or_add(cl), index.find_or_add(cu), true};
-      if (mult.size() < index.values.size()) mult.resize(index.values.size(), 0.0);
+  // Uniform half-widths (the all-nodes task): a node's constants depend on its pilot
+  // count only, so they are computed once per distinct count.
+  const unsigned nt = parallel_threads(n);
+  std::vector<uint8_t> t_uniform(nt, 1);
+  std::vector<uint64_t> t_cmax(nt, 0);
+  parallel_ranges(n, [&](uint32_t b0, uint32_t e0, unsigned w) {
+    uint64_t cm = 0;
+    bool un = true;
+    for (uint32_t v = b0; v < e0; ++v) {
+      un = un && lam_l[v] == lam_l[0] && lam_u[v] == lam_u[0];
+      cm = std::max(cm, count0[v]);
     }
-    il[v] = m.a;
-    iu[v] = m.b;
-    mult[m.a] += 1.0;
-    mult[m.b] += 1.0;
+    t_uniform[w] = un;
+    t_cmax[w] = cm;
+  });
+  const bool uniform = std::all_of(t_uniform.begin(), t_uniform.end(), [](uint8_t x) { return x; });
+  const uint64_t cmax = *std::max_element(t_cmax.begin(), t_cmax.end());
+  std::vector<uint32_t> il, iu;        // general path: per-node value indices
+  std::vector<uint32_t> ca, cb, cgrp;  // uniform path: per-count value indices and group
+  if (uniform && cmax < (1u << 24)) {
+    std::vector<std::vector<uint32_t>> th(nt, std::vector<uint32_t>(cmax + 1, 0));
+    parallel_ranges(n, [&](uint32_t b0, uint32_t e0, unsigned w) {
+      for (uint32_t v = b0; v < e0; ++v) th[w][count0[v]]++;
+    });
+    ca.assign(cmax + 1, 0);
+    cb.assign(cmax + 1, 0);
+    cgrp.assign(cmax + 1, 0);
+    uint32_t ngrp = 0;
+    for (uint64_t c = 0; c <= cmax; ++c) {
+      uint64_t h = 0;
+      for (unsigned w = 0; w < nt; ++w) h += th[w][c];
+      if (!h) continue;
+      const double b0 = (double)c / (double)alpha;
+      ca[c] = add_value(2.0 * b0 * (double)omega / (lam_l[0] * lam_l[0]), (double)h);
+      cb[c] = add_value(2.0 * b0 * (double)omega / (lam_u[0] * lam_u[0]), (double)h);
+      cgrp[c] = ngrp++;
+    }
+    if (groups) {
+      groups->L_l.assign(ngrp, 0.0);
+      groups->L_u.assign(ngrp, 0.0);
+    }
+  } else {
+    // most nodes repeat an earlier (count0, lambda_l, lambda_u): a direct-mapped memo
+    // of that triple skips recomputing the same two constants
+    il.resize(n);
+    iu.resize(n);
+    struct Memo {
+      uint64_t c0, ll, lu;
+      uint32_t a, b;
+      bool used;
+    };
+    std::vector<Memo> memo(4096, Memo{0, 0, 0, 0, 0, false});
+    for (uint32_t v = 0; v < n; ++v) {
+      uint64_t bl, bu;
+      memcpy(&bl, &lam_l[v], 8);
+      memcpy(&bu, &lam_u[v], 8);
+      const uint64_t h = (count0[v] * 0x9E3779B97F4A7C15ULL) ^ (bl * 0xC2B2AE3D27D4EB4FULL) ^
+                         (bu * 0x165667B19E3779F9ULL);
+      Memo &m = memo[(h >> 40) & 4095];
+      if (!(m.used && m.c0 == count0[v] && m.ll == bl && m.lu == bu)) {
+        const double b0 = (double)count0[v] / (double)alpha;
+        const double cl = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
+        const double cu = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
+        m = Memo{count0[v], bl, bu, index.find_or_add(cl), index.find_or_add(cu), true};
+        if (mult.size() < index.values.size()) mult.resize(index.values.size(), 0.0);
+      }
+      il[v] = m.a;
+      iu[v] = m.b;
+      mult[m.a] += 1.0;
+      mult[m.b] += 1.0;
+    }
+    if (groups) {  // group = distinct (il, iu) pair
+      std::map<std::pair<uint32_t, uint32_t>, uint32_t> ids;
+      groups->of.resize(n);
+      for (uint32_t v = 0; v < n; ++v) {
+        auto it = ids.emplace(std::make_pair(il[v], iu[v]), (uint32_t)ids.size()).first;
+        groups->of[v] = it->second;
+      }
+      groups->L_l.assign(ids.size(), 0.0);
+      groups->L_u.assign(ids.size(), 0.0);
+    }
   }
   // distinct constants with multiplicities, ascending
   const size_t nd = index.values.size();
@@ -313,9 +393,32 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
   const double floor_add = eps_bal * delta / (2.0 * (double)n);
   std::vector<double> Lq(nd);
   for (size_t q = 0; q < nd; ++q) Lq[q] = -log(term(C, index.values[q]) + floor_add);
-  for (uint32_t v = 0; v < n; ++v) {
-    L_l[v] = Lq[il[v]];
-    L_u[v] = Lq[iu[v]];
+  if (!ca.empty()) {
+    if (groups) {
+      groups->of.resize(n);
+      for (uint64_t c = 0; c <= cmax; ++c) {
+        groups->L_l[cgrp[c]] = Lq[ca[c]];
+        groups->L_u[cgrp[c]] = Lq[cb[c]];
+      }
+    }
+    parallel_ranges(n, [&](uint32_t b0, uint32_t e0, unsigned) {
+      for (uint32_t v = b0; v < e0; ++v) {
+        const uint64_t c = count0[v];
+        L_l[v] = Lq[ca[c]];
+        L_u[v] = Lq[cb[c]];
+        if (groups) groups->of[v] = cgrp[c];
+      }
+    });
+  } else {
+    for (uint32_t v = 0; v < n; ++v) {
+      L_l[v] = Lq[il[v]];
+      L_u[v] = Lq[iu[v]];
+    }
+    if (groups)
+      for (uint32_t v = 0; v < n; ++v) {
+        groups->L_l[groups->of[v]] = L_l[v];
+        groups->L_u[groups->of[v]] = L_u[v];
+      }
   }
   if (C_out) *C_out = C;
 }
@@ -395,6 +498,16 @@ StopChecker::StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint
     }
     group_[v] = m.g;
   }
+  gmax_.resize(gL_l_.size());
+  if (mode_ == 1) in_top_.assign(n, 0);
+}
+
+StopChecker::StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
+                         const double *L_l, const double *L_u, Groups &&groups)
+    : n_(n), mode_(mode), k_(k), eps_(eps), omega_(omega), Ll_(L_l), Lu_(L_u) {
+  group_ = std::move(groups.of);
+  gL_l_ = std::move(groups.L_l);
+  gL_u_ = std::move(groups.L_u);
   gmax_.resize(gL_l_.size());
   if (mode_ == 1) in_top_.assign(n, 0);
 }

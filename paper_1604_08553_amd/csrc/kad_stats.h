@@ -4,9 +4,15 @@
 #include <stddef.h>
 #include <stdint.h>
 
+#include <functional>
 #include <vector>
 
 namespace kad {
+
+// Run f(begin, end) over a static split of [0, n) on up to 16 threads (one thread for
+// small n).  Used for per-node loops whose iterations are independent.
+void parallel_ranges(uint32_t n, const std::function<void(uint32_t, uint32_t, unsigned)> &f);
+unsigned parallel_threads(uint32_t n);
 
 uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c);
 uint64_t alpha_of(uint64_t omega);
@@ -20,9 +26,17 @@ int vertex_diameter(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32
                     const uint32_t *rrow, const uint32_t *rcol, double exact_limit, uint32_t *vd,
                     bool *exact);
 
+// Node groups: nodes of one group have identical (L_l, L_u).
+struct Groups {
+  std::vector<uint32_t> of;    // node -> group
+  std::vector<double> L_l, L_u; // group -> values
+};
+
+// computeDelta; optionally also returns a partition of the nodes into groups of
+// identical (L_l, L_u) (not necessarily the coarsest one).
 void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
                    const double *lam_l, const double *lam_u, double delta, double eps_bal,
-                   double *L_l, double *L_u, double *C);
+                   double *L_l, double *L_u, double *C, Groups *groups = nullptr);
 
 void topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha, double eps,
                   double *lam_l, double *lam_u);
@@ -35,6 +49,9 @@ class StopChecker {
  public:
   StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
               const double *L_l, const double *L_u);
+  // with a known grouping (e.g. from compute_delta)
+  StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
+              const double *L_l, const double *L_u, Groups &&groups);
   bool check(const uint64_t *count, uint64_t tau);
   // All-nodes task only: the same decision from the per-group largest counts.  *worst
   // (optional) receives max over groups of max(f, g) / eps, how far the rule is from

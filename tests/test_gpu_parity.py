@@ -116,7 +116,10 @@ def test_paths_grid_unflagged_match(kad, ctx, orc):
 
 
 def test_hit_counts_match(kad, ctx, orc):
-    for g, cnt in [(gg.workload("er2000"), 50000), (gg.gnp(300, 0.02, 5, True), 20000)]:
+    # er2000: short paths (hits pre-aggregated 64 samples at a time); 30x30 grid: longer
+    # paths (fewer samples per aggregation); 600-node path: paths too long to aggregate
+    for g, cnt in [(gg.workload("er2000"), 50000), (gg.gnp(300, 0.02, 5, True), 20000),
+                   (gg.grid(30, 30), 20000), (gg.path_graph(600), 3000)]:
         _say("hit_counts", g.name, cnt)
         G = kad.Graph(ctx, g)
         a, arcs = kad.hit_counts(ctx, G, 4, 1, 100, cnt)
