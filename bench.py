@@ -26,6 +26,19 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sampler_cl1m_traffic.json")
+
+
+def measured_traffic(workload):
+    """HBM bytes per sampler dispatch from the committed counter passes, if they were
+    taken on this workload with the current kernel source; else None."""
+    if workload != "cl1m" or not os.path.exists(TRAFFIC_FILE):
+        return None
+    from paper_1604_08553_amd.profiling import kernel_source_sha256
+    rec = json.load(open(TRAFFIC_FILE))
+    if rec.get("kernel_source_sha256") != kernel_source_sha256():
+        return None
+    return rec["hbm_bytes_per_dispatch"]
 
 
 def algorithmic_bytes(arcs, nodes, hits):
@@ -119,6 +132,8 @@ def main():
     per_launch_bytes = alg / max(tm["launches"], 1)
     avg_launch_s = tm["seconds"] / max(tm["launches"], 1)
     achieved = per_launch_bytes / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    hbm = measured_traffic(args.workload)
+    traffic = hbm / avg_launch_s / 1e9 if hbm and avg_launch_s > 0 else None
 
     out = {
         "metric": "sampled shortest paths/sec",
@@ -151,9 +166,10 @@ def main():
                     "nodes_per_sample": tm["nodes"] / max(tm["samples"], 1),
                     "gteps_in_kernel": tm["arcs"] / max(tm["seconds"], 1e-12) / 1e9},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sampler_kernel",
-                     "alg_bytes_per_launch": per_launch_bytes},
+                     "alg_bytes_per_launch": per_launch_bytes,
+                     "hbm_bytes_per_launch": hbm},
     }
     G.close()
     ctx.close()

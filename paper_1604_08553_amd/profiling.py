@@ -1,0 +1,110 @@
+"""Summaries of rocprofv3 output for the sampler kernel.
+
+    python -m paper_1604_08553_amd.profiling --trace DIR --fetch DIR --write DIR \
+        --copy-fetch DIR --copy-write DIR --copy-mib 512 --out profiles/ --command-file FILE
+
+reads the CSV files rocprofv3 wrote (kernel trace + stats, FETCH_SIZE and WRITE_SIZE
+counter passes over the bench, and the same two counters over a plain device copy of
+known size), and writes:
+
+* ``profiles/sampler_cl1m_kernel_stats.md`` -- per-kernel call counts and durations;
+* ``profiles/sampler_cl1m_traffic.md`` -- HBM bytes per sampler dispatch, each counter
+  scaled by (known copy bytes / what the counter read for the copy);
+* ``profiles/sampler_cl1m_traffic.json`` -- the same numbers with the SHA-256 of the
+  kernel source they were taken with (bench.py reports them only while it matches).
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import glob
+import hashlib
+import json
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "kad_kernels.hip")
+
+
+def kernel_source_sha256() -> str:
+    return hashlib.sha256(open(KERNEL_SOURCE, "rb").read()).hexdigest()
+
+
+def _one(pattern: str) -> str:
+    files = sorted(glob.glob(pattern, recursive=True))
+    if not files:
+        raise FileNotFoundError(pattern)
+    return files[0]
+
+
+def kernel_stats(trace_dir: str):
+    rows = list(csv.DictReader(open(_one(os.path.join(trace_dir, "**", "*kernel_stats.csv")))))
+    return [(r["Name"], int(r["Calls"]), float(r["TotalDurationNs"]), float(r["AverageNs"]),
+             float(r["Percentage"])) for r in rows]
+
+
+def counter_per_dispatch(pmc_dir: str, kernel_substr: str, counter: str):
+    path = _one(os.path.join(pmc_dir, "**", "*counter_collection.csv"))
+    vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
+            if kernel_substr in r["Kernel_Name"] and r["Counter_Name"] == counter]
+    if not vals:
+        raise ValueError(f"no {counter} rows for {kernel_substr} in {path}")
+    return sum(vals) / len(vals), len(vals)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--trace", required=True)
+    ap.add_argument("--fetch", required=True)
+    ap.add_argument("--write", required=True)
+    ap.add_argument("--copy-fetch", required=True)
+    ap.add_argument("--copy-write", required=True)
+    ap.add_argument("--copy-mib", type=int, required=True)
+    ap.add_argument("--out", required=True)
+    ap.add_argument("--command-file", required=True,
+                    help="text file with the exact commands that produced the inputs")
+    args = ap.parse_args()
+    commands = open(args.command_file).read().strip()
+    os.makedirs(args.out, exist_ok=True)
+
+    stats = kernel_stats(args.trace)
+    lines = ["# Kernel trace: sampled-betweenness bench (cl1m)", "",
+             "Undirected Chung-Lu n=1,000,000, beta 2.3, mean degree 20; all-nodes, epsilon 0.005,",
+             "delta 0.1, seed 1.  Produced by:", "", "```", commands, "```", "",
+             "| kernel | calls | total ms | average us | % |", "|---|---|---|---|---|"]
+    for name, calls, tot, avg, pct in stats:
+        short = name.replace("kad::(anonymous namespace)::", "").split("(")[0]
+        lines.append(f"| {short} | {calls} | {tot / 1e6:.3f} | {avg / 1e3:.1f} | {pct:.2f} |")
+    open(os.path.join(args.out, "sampler_cl1m_kernel_stats.md"), "w").write("\n".join(lines) + "\n")
+
+    copy_bytes = args.copy_mib << 20
+    cf, _ = counter_per_dispatch(args.copy_fetch, "copyBuffer", "FETCH_SIZE")
+    cw, _ = counter_per_dispatch(args.copy_write, "copyBuffer", "WRITE_SIZE")
+    fetch_factor = copy_bytes / (cf * 1024.0)
+    write_factor = copy_bytes / (cw * 1024.0)
+    sf, nf = counter_per_dispatch(args.fetch, "sampler_kernel", "FETCH_SIZE")
+    sw, nw = counter_per_dispatch(args.write, "sampler_kernel", "WRITE_SIZE")
+    fetch_b = sf * 1024.0 * fetch_factor
+    write_b = sw * 1024.0 * write_factor
+    rec = {"kernel": "sampler_kernel", "kernel_source_sha256": kernel_source_sha256(),
+           "fetch_kib_per_dispatch": sf, "write_kib_per_dispatch": sw, "dispatches": nf,
+           "copy_fetch_factor": fetch_factor, "copy_write_factor": write_factor,
+           "hbm_bytes_per_dispatch": fetch_b + write_b,
+           "fetch_bytes_per_dispatch": fetch_b, "write_bytes_per_dispatch": write_b}
+    json.dump(rec, open(os.path.join(args.out, "sampler_cl1m_traffic.json"), "w"), indent=1)
+    t = ["# HBM traffic of the sampler kernel (cl1m bench)", "", "Produced by:", "", "```",
+         commands, "```", "",
+         f"* calibration: a plain {args.copy_mib} MiB device copy read FETCH_SIZE {cf:.0f} KiB "
+         f"and WRITE_SIZE {cw:.0f} KiB, so FETCH_SIZE is scaled by {fetch_factor:.3f} and "
+         f"WRITE_SIZE by {write_factor:.3f}",
+         f"* sampler_kernel, {nf} dispatches: FETCH_SIZE {sf:.0f} KiB, WRITE_SIZE {sw:.0f} KiB "
+         f"per dispatch (mean)",
+         f"* scaled HBM bytes per dispatch: read {fetch_b / 1e9:.3f} GB + write "
+         f"{write_b / 1e9:.3f} GB = {(fetch_b + write_b) / 1e9:.3f} GB",
+         f"* kernel source SHA-256: {rec['kernel_source_sha256']}"]
+    open(os.path.join(args.out, "sampler_cl1m_traffic.md"), "w").write("\n".join(t) + "\n")
+    print(json.dumps(rec))
+
+
+if __name__ == "__main__":
+    main()
