@@ -13,7 +13,7 @@ constexpr uint32_t FLAG_OVERFLOW = 1u;
 constexpr uint32_t FLAG_CAPACITY = 2u;
 constexpr uint32_t FLAG_RNG = 4u;
 
-constexpr int SAMPLER_BLOCK = 256;
+constexpr int SAMPLER_BLOCK = 128;  // two waves per sample
 
 struct GraphDev {
   uint32_t n;

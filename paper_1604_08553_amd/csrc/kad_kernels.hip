@@ -28,13 +28,13 @@ namespace {
 constexpr int BLOCK = SAMPLER_BLOCK;
 constexpr int WAVE = 64;
 constexpr int NWAVES = BLOCK / WAVE;
-constexpr int CHUNK = 512;  // frontier nodes staged in LDS per pass (2 per thread)
-constexpr int FILTER_LOG2 = 16;
+constexpr int CHUNK = 2 * BLOCK;  // frontier nodes staged in LDS per pass (2 per thread)
+constexpr int FILTER_LOG2 = 15;
 constexpr int FILTER_WORDS = (1 << FILTER_LOG2) / 32;
-constexpr int PI_LDS = 1024;  // candidate edges kept in LDS; more spill to the slot buffer
+constexpr int PI_LDS = 256;  // candidate edges kept in LDS; more spill to the slot buffer
 constexpr uint32_t MAX_ATTEMPTS = 64;
 constexpr int MAXLEV = 32;     // levels per side whose node lists are remembered
-constexpr int MATCH_CAP = 192; // predecessor candidates a backtracking wave keeps in LDS
+constexpr int MATCH_CAP = 48;  // predecessor candidates a backtracking wave keeps in LDS
 constexpr uint64_t SMALL_EXPANSION = 512;
 constexpr uint32_t MAX_HIT_TILES = MAX_HIT_TILES_PUBLIC;  // arcs: up to this, one combined scan per level
 
@@ -352,7 +352,7 @@ __device__ __forceinline__ void scan_frontier(Lds &L, const GraphDev &g, uint32_
     // Each lane takes U arcs per iteration (independent searches and row loads in
     // flight); every lane of a wave runs the same number of iterations because the
     // ballots and shuffles below must not see inactive lanes.
-    constexpr int U = MODE == Scan::Touch ? 4 : 2;  // arcs per lane per iteration
+    constexpr int U = MODE == Scan::Touch ? 8 : 2;  // arcs per lane per iteration
     uint32_t jlo = 0;
     const uint32_t lane = lane_id();
     for (uint32_t e0 = (tid / WAVE) * (WAVE * U); e0 < tot; e0 += BLOCK * U) {
@@ -796,14 +796,16 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g, SlotState
           const uint64_t key = keys[win < P ? win : 0];
           const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
           __syncthreads();  // the staging area becomes backtracking scratch below
-          // ---- the two halves: wave 0 walks to s, wave 1 walks to t
+          // ---- the two halves: with two or more waves, wave 0 walks to s while wave 1
+          // walks to t; a single wave walks one after the other
           uint32_t fl = 0;
           MatchScratch *scratch = reinterpret_cast<MatchScratch *>(L.pi);
           if (wid == 0) {
             if (lane == 0) path[ls] = v;
             backtrack(g, 0, v, ls, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[0], seed, i,
                       phase, path, ls, fl);
-          } else if (wid == 1) {
+          }
+          if (wid == (NWAVES >= 2 ? 1u : 0u)) {
             if (lane == 0) path[ls + 1] = w;
             backtrack(g, 1, w, lt, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[1], seed, i,
                       phase, path, ls, fl);
