@@ -37,10 +37,11 @@ typedef enum {
   KAD_EINVAL = -1,    /* bad argument or malformed graph */
   KAD_ENOMEM = -2,    /* host or device allocation failed, or over the HBM budget */
   KAD_EDEVICE = -3,   /* HIP runtime error, or no usable GPU */
-  KAD_EBUSY = -4,     /* reserved */
+  KAD_EBUSY = -4,     /* the context is in use, or a served query is still running */
   KAD_ETOOSMALL = -5, /* an output buffer is too small; the needed size is reported */
   KAD_EOVERFLOW = -6, /* a result does not fit the library's fixed-width arithmetic */
-  KAD_ERNG = -7       /* a bounded random draw was rejected 64 times (probability < 2^-64) */
+  KAD_ERNG = -7,      /* a bounded random draw was rejected 64 times (probability < 2^-64) */
+  KAD_ECANCELED = -8  /* a served query was dropped before it started */
 } kad_status;
 
 enum { KAD_MEM_HOST = 0, KAD_MEM_DEVICE = 1 };
@@ -145,6 +146,52 @@ typedef struct {
  * check_interval samples (host, binary64).  Fills `r`. */
 kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_result *r,
                    void *hip_stream);
+
+/* ---------------------------------------------------------------- many queries at once */
+
+/* Multi-query engine.  Several adaptive runs -- on one graph or on many graphs, with
+ * their own epsilon, delta, mode, k and seed -- share every sampler launch: one
+ * launch carries the next pilot samples and check intervals of all of them (a table
+ * of (graph, seed, phase, sample ids) segments read by a persistent kernel), their
+ * hits go to one counter pool in HBM (one reduction per check point for all queries),
+ * and the host evaluates every query's stopping checks while the next launch runs.
+ * Each query follows the schedule of kad_run exactly (same sample ids, same check
+ * points), so every result is identical to kad_run's for the same graph and
+ * parameters; kernel_batch caps a query's samples per launch.  Limits: graphs of up
+ * to 2^25 nodes; the node counts of the queries running at once add up to at most
+ * 2^25 (the counter pool, each query rounded up to 8192 nodes) -- further queries wait
+ * in arrival order until running ones finish ("admission").  Graphs must belong to
+ * the context. */
+
+/* Run count queries (graphs[i], params[i]) together and fill results[i] as kad_run
+ * would (caller-owned arrays, as for kad_run; seconds = wall time of the whole call's
+ * query from start to its completion).  status[i] (may be NULL) receives each query's
+ * status; the call returns the first failing one (KAD_OK if none).  Synchronous;
+ * claims the context for its duration (KAD_EBUSY if a server or another call holds it). */
+kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *graphs,
+                         const kad_params *params, kad_result *results, kad_status *status);
+
+/* Serving: a background thread owns the context and runs the engine continuously;
+ * queries submitted at any time join the next launch once admitted (continuous
+ * batching).  Results are identical to kad_run's.  While a server exists the context
+ * is claimed: other calls on it return KAD_EBUSY. */
+typedef struct kad_server kad_server;
+kad_status kad_server_create(kad_ctx *ctx, kad_server **out);
+/* Queue a query; *ticket identifies it.  Parameters are validated here (KAD_EINVAL). */
+kad_status kad_server_submit(kad_server *srv, const kad_graph *g, const kad_params *p,
+                             uint64_t *ticket);
+/* KAD_EBUSY while the query runs; once done, fills `r` like kad_run (caller-owned arrays;
+ * r->seconds = latency from submit to completion, r->seconds_setup = time queued before
+ * admission) and forgets the ticket.  Returns the query's own status. */
+kad_status kad_server_poll(kad_server *srv, uint64_t ticket, kad_result *r);
+/* As poll, blocking up to timeout_s seconds (negative: no limit); KAD_EBUSY on timeout. */
+kad_status kad_server_wait(kad_server *srv, uint64_t ticket, kad_result *r, double timeout_s);
+/* Completed queries, sampler launches and samples launched so far (any may be NULL). */
+kad_status kad_server_stats(kad_server *srv, uint64_t *completed, uint64_t *launches,
+                            uint64_t *samples);
+/* Stop the server: queries not yet admitted are dropped (their waiters get
+ * KAD_ECANCELED), admitted ones finish first; unretrieved results are discarded. */
+kad_status kad_server_destroy(kad_server *srv);
 
 /* ---------------------------------------------------------------- sampling primitives */
 

@@ -14,7 +14,8 @@ import re
 
 import numpy as np
 
-__all__ = ["Context", "Graph", "run", "sample_paths", "hit_counts", "KadError", "lib",
+__all__ = ["Context", "Graph", "run", "run_batch", "Server", "sample_paths", "hit_counts",
+           "KadError", "lib",
            "library_path", "declared_symbols", "omega", "alpha", "default_interval",
            "vertex_diameter", "bound_f", "bound_g", "compute_delta", "topk_lambdas",
            "have_to_stop"]
@@ -29,7 +30,9 @@ STOP_OMEGA, STOP_RULE = 0, 1
 SAMPLE_OVERFLOW, SAMPLE_CAPACITY, SAMPLE_RNG = 1, 2, 4
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
-           -4: "busy", -5: "buffer too small", -6: "overflow", -7: "random draw rejected"}
+           -4: "busy", -5: "buffer too small", -6: "overflow", -7: "random draw rejected",
+           -8: "canceled"}
+EBUSY = -4
 
 
 class KadError(RuntimeError):
@@ -92,6 +95,13 @@ def lib():
         "kad_compute_delta": ([u32, vp, u64, u64, vp, vp, dbl, dbl, vp, vp, vp], st),
         "kad_topk_lambdas": ([u32, u32, vp, u64, dbl, vp, vp], st),
         "kad_have_to_stop": ([u32, u32, u32, vp, u64, u64, dbl, vp, vp], st),
+        "kad_run_batch": ([vp, u32, vp, vp, vp, vp], st),
+        "kad_server_create": ([vp, vp], st),
+        "kad_server_submit": ([vp, vp, C.POINTER(_Params), vp], st),
+        "kad_server_poll": ([vp, u64, C.POINTER(_Result)], st),
+        "kad_server_wait": ([vp, u64, C.POINTER(_Result), dbl], st),
+        "kad_server_stats": ([vp, vp, vp, vp], st),
+        "kad_server_destroy": ([vp], st),
         "kad_ctx_set_timing": ([vp, i32], st),
         "kad_ctx_get_timing": ([vp, vp, vp, vp, vp, vp, vp], st),
         "kad_last_error": ([], C.c_char_p),
@@ -228,6 +238,48 @@ def _stream(stream):
 # ----------------------------------------------------------------------------- calls
 
 
+_SCALARS = ("tau", "omega", "alpha", "interval", "arcs_scanned", "pilot_arcs_scanned",
+            "overflow_samples", "vd", "vd_exact", "stop_reason", "seconds", "C",
+            "seconds_setup", "seconds_pilot", "seconds_delta", "seconds_main")
+
+
+def _params(epsilon, delta, mode="all", k=0, seed=1, check_interval=0, kernel_batch=0,
+            vd_override=0, c=0.0, balance_eps=0.0):
+    return _Params(epsilon, delta, TOPK if mode == "topk" else ALL_NODES, k, seed,
+                   check_interval, kernel_batch, vd_override, 0, c, balance_eps)
+
+
+def _result(n, topk, topk_cap=0, out=None):
+    """A kad_result wired to numpy arrays (reusing those in ``out`` when they fit)."""
+    prev = out or {}
+    arrs = {}
+    for name, dt in (("count", np.uint64), ("bc", np.float64), ("lower", np.float64),
+                     ("upper", np.float64)):
+        a = prev.get(name)
+        if a is None or a.shape != (n,) or a.dtype != dt or not a.flags.c_contiguous:
+            a = np.empty(n, dtype=dt)
+        arrs[name] = a
+    cap = topk_cap or (n if topk else 0)
+    for name in ("topk_node", "rank_lo", "rank_hi"):
+        arrs[name] = np.zeros(max(cap, 1), dtype=np.uint32)
+    r = _Result()
+    for name, a in arrs.items():
+        setattr(r, name, a.ctypes.data)
+    r.topk_cap = cap
+    return r, arrs
+
+
+def _collect(r, arrs, topk):
+    out = {k: arrs[k] for k in ("count", "bc", "lower", "upper")}
+    for name in _SCALARS:
+        out[name] = getattr(r, name)
+    if topk:
+        m = r.topk_len
+        for name in ("topk_node", "rank_lo", "rank_hi"):
+            out[name] = arrs[name][:m].copy()
+    return out
+
+
 def run(ctx: Context, graph: Graph, epsilon: float, delta: float, mode: str = "all", k: int = 0,
         seed: int = 1, check_interval: int = 0, kernel_batch: int = 0, vd_override: int = 0,
         c: float = 0.0, balance_eps: float = 0.0, topk_cap: int = 0, stream=None,
@@ -236,36 +288,97 @@ def run(ctx: Context, graph: Graph, epsilon: float, delta: float, mode: str = "a
 
     ``out`` may hold preallocated arrays "count" (uint64[n]), "bc", "lower", "upper"
     (float64[n]) to be filled in place (saves page-faulting fresh arrays per call)."""
-    n = graph.n
-    p = _Params(epsilon, delta, TOPK if mode == "topk" else ALL_NODES, k, seed, check_interval,
-                kernel_batch, vd_override, 0, c, balance_eps)
-    prev = out or {}
-    out = {"count": prev.get("count"), "bc": prev.get("bc"), "lower": prev.get("lower"),
-           "upper": prev.get("upper")}
-    for name, dt in (("count", np.uint64), ("bc", np.float64), ("lower", np.float64),
-                     ("upper", np.float64)):
-        a = out[name]
-        if a is None or a.shape != (n,) or a.dtype != dt or not a.flags.c_contiguous:
-            out[name] = np.empty(n, dtype=dt)
-    cap = topk_cap or (n if mode == "topk" else 0)
-    tk = {"topk_node": np.zeros(max(cap, 1), dtype=np.uint32),
-          "rank_lo": np.zeros(max(cap, 1), dtype=np.uint32),
-          "rank_hi": np.zeros(max(cap, 1), dtype=np.uint32)}
-    r = _Result()
-    for name, a in list(out.items()) + list(tk.items()):
-        setattr(r, name, a.ctypes.data)
-    r.topk_cap = cap
+    p = _params(epsilon, delta, mode, k, seed, check_interval, kernel_batch, vd_override, c,
+                balance_eps)
+    r, arrs = _result(graph.n, mode == "topk", topk_cap, out)
     _check(lib().kad_run(ctx.handle, graph.handle, C.byref(p), C.byref(r), _stream(stream)))
-    for name in ("tau", "omega", "alpha", "interval", "arcs_scanned", "pilot_arcs_scanned",
-                 "overflow_samples", "vd", "vd_exact", "stop_reason", "seconds", "C",
-                 "seconds_setup", "seconds_pilot", "seconds_delta", "seconds_main"):
-        out[name] = getattr(r, name)
-    if mode == "topk":
-        m = r.topk_len
-        out["topk_node"] = tk["topk_node"][:m].copy()
-        out["rank_lo"] = tk["rank_lo"][:m].copy()
-        out["rank_hi"] = tk["rank_hi"][:m].copy()
-    return out
+    return _collect(r, arrs, mode == "topk")
+
+
+def run_batch(ctx: Context, graphs, params) -> list:
+    """Run queries (graphs[i], params[i]) together through the multi-query engine
+    (kad_run_batch).  params[i] is a dict of run()'s keyword arguments (epsilon and
+    delta required).  Returns one result dict per query, as run() does; raises on
+    the first failing query."""
+    m = len(graphs)
+    if len(params) != m:
+        raise ValueError("one parameter set per graph")
+    ps = (_Params * max(m, 1))()
+    rs = (_Result * max(m, 1))()
+    keep, topk = [], []
+    for i, (g, kw) in enumerate(zip(graphs, params)):
+        kw = dict(kw)
+        cap = kw.pop("topk_cap", 0)
+        ps[i] = _params(**kw)
+        r, arrs = _result(g.n, kw.get("mode") == "topk", cap)
+        rs[i] = r
+        keep.append(arrs)
+        topk.append(kw.get("mode") == "topk")
+    handles = (C.c_void_p * max(m, 1))(*[g.handle for g in graphs])
+    status = np.zeros(max(m, 1), dtype=np.int32)
+    _check(lib().kad_run_batch(ctx.handle, m, handles, ps, rs, _p(status)))
+    return [_collect(rs[i], keep[i], topk[i]) for i in range(m)]
+
+
+class Server:
+    """Continuous-batching server over a context (kad_server_*): queries submitted at
+    any time join the running engine; results are identical to run()'s."""
+
+    def __init__(self, ctx: Context):
+        h = C.c_void_p()
+        _check(lib().kad_server_create(ctx.handle, C.byref(h)))
+        self.handle = h
+        self.ctx = ctx
+        self._pending = {}
+
+    def submit(self, graph: Graph, epsilon: float, delta: float, topk_cap: int = 0, **kw) -> int:
+        p = _params(epsilon, delta, **kw)
+        t = C.c_uint64()
+        _check(lib().kad_server_submit(self.handle, graph.handle, C.byref(p), C.byref(t)))
+        self._pending[t.value] = _result(graph.n, kw.get("mode") == "topk", topk_cap) + (
+            kw.get("mode") == "topk",)
+        return t.value
+
+    def poll(self, ticket: int):
+        """The result dict, or None while the query runs."""
+        r, arrs, topk = self._pending[ticket]
+        rc = lib().kad_server_poll(self.handle, ticket, C.byref(r))
+        if rc == EBUSY:
+            return None
+        del self._pending[ticket]
+        _check(rc)
+        return _collect(r, arrs, topk)
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        r, arrs, topk = self._pending[ticket]
+        rc = lib().kad_server_wait(self.handle, ticket, C.byref(r), float(timeout))
+        if rc == EBUSY:
+            return None
+        del self._pending[ticket]
+        _check(rc)
+        return _collect(r, arrs, topk)
+
+    def stats(self) -> dict:
+        v = [C.c_uint64() for _ in range(3)]
+        _check(lib().kad_server_stats(self.handle, *[C.byref(x) for x in v]))
+        return {"completed": v[0].value, "launches": v[1].value, "samples": v[2].value}
+
+    def close(self):
+        if getattr(self, "handle", None):
+            lib().kad_server_destroy(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def sample_paths(ctx: Context, graph: Graph, seed: int, phase: int, first: int, count: int,

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libkadabra.so")
 ARCH = os.environ.get("KAD_OFFLOAD_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-SOURCES = ["kad_kernels.hip", "kad_runtime.cpp", "kad_stats.cpp"]
+SOURCES = ["kad_kernels.hip", "kad_runtime.cpp", "kad_engine.cpp", "kad_stats.cpp"]
 
 COMMON = ["-O3", "-fPIC", "-std=c++17", "-ffp-contract=off", "-Wall", "-Wno-unused-function",
           f"-I{INCLUDE}", f"-I{CSRC}"]

@@ -36,6 +36,20 @@ struct SlotState {
   uint64_t *pi;        // [slots * pi_cap]
 };
 
+// One segment of a multi-query launch: sample ids [first, first + count) of
+// (graph, seed, phase), stored at launch indices [begin, begin + count).  Node ids
+// written to the path buffer are shifted by id_base (the query's place in a shared
+// counter pool), so one hit reduction serves every query of the launch.
+struct SampleSeg {
+  const uint32_t *row, *col, *rrow, *rcol;
+  uint64_t seed;
+  uint64_t first;
+  uint32_t n;
+  uint32_t phase;
+  uint32_t begin;
+  uint32_t id_base;
+};
+
 struct SampleOut {
   uint32_t *s, *t, *len, *flags; // [count]
   uint32_t *nodes;               // [count] nodes reached by the two searches
@@ -50,29 +64,65 @@ hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
                           uint32_t grid, hipStream_t stream);
 
+// Samples [0, count) of the launch, segment by segment (segs[] in device memory,
+// ascending `begin`, segs[0].begin == 0); st.n is the slot capacity (>= every
+// segment's n).
+hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const SlotState &st,
+                                uint32_t count, uint32_t *work, const SampleOut &out,
+                                uint32_t grid, hipStream_t stream);
+
 // Node tiles of the hit reduction: 8,192 ids each, at most this many tiles (graphs of
 // up to 2^25 nodes).
 constexpr uint32_t MAX_HIT_TILES_PUBLIC = 4096;
 constexpr uint32_t HIT_TILE_IDS = 8192;
 
-// Scratch of the hit reduction: one bin of `cap` node ids per tile (cap >= the hits of
-// one call), and the bins' fill counters (all zero between calls).
+// Scratch of the hit reduction, in one of two layouts:
+//   fixed   (tile_start == nullptr): one bin of `cap` entries per tile, cap >= the
+//           hits of one call; one partition pass;
+//   compact (tile_start != nullptr): one array of `cap` entries >= the hits of one
+//           call, tile t at tile_start[t]; a counting pass and a prefix sum first.
+// bin_count and tile_fill hold MAX_HIT_TILES_PUBLIC counters, all zero between calls.
 struct HitScratch {
   uint32_t *bins;
   uint64_t cap;
   uint32_t *bin_count;
+  uint32_t *tile_start = nullptr;
+  uint32_t *tile_fill = nullptr;
 };
 
 // count[v] += (or -=, with subtract) the number of samples in [0, nsamp) whose path has
-// v as an interior node.  With gmax != NULL also raises gmax[group[v]] to the new count
+// v as an interior node (v < n: the extent of the counter array).  With gmax != NULL also raises gmax[group[v]] to the new count
 // of every changed node.
 hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t stride,
                              uint32_t nsamp, uint32_t n, uint64_t *count, bool subtract,
                              const uint32_t *group, uint64_t *gmax, const HitScratch &hs,
                              hipStream_t stream);
 
-// Zero a small device buffer with a kernel (no memset node when captured).
-hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t stream);
+// Zero a device buffer with a kernel (no memset node when captured).
+hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream);
+// p[i] = value for i < count.
+hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
+
+// gmax[group[v]] = max(gmax[group[v]], count[v]) for v < n (group values index gmax).
+hipError_t launch_group_max(const uint64_t *count, const uint32_t *group, uint32_t n,
+                            uint64_t *gmax, hipStream_t stream);
+
+// One range copied by launch_gather: snap[dst, dst + len) = src[off, off + len) where src
+// is the group-maximum pool (GATHER_GMAX) or the counter pool (GATHER_COUNT; with
+// GATHER_COUNT_ZERO the counters are also reset to 0).
+enum : uint32_t { GATHER_GMAX = 0, GATHER_COUNT = 1, GATHER_COUNT_ZERO = 2 };
+struct GatherDesc {
+  uint64_t off;
+  uint64_t dst;
+  uint32_t len;
+  uint32_t mode;
+  uint32_t block0;  // first workgroup of this range (ascending over the list)
+  uint32_t pad;
+};
+constexpr uint32_t GATHER_CHUNK = 4096;  // entries per workgroup
+// blocks = the sum over descriptors of ceil(len / GATHER_CHUNK).
+hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint64_t *count_pool,
+                         const uint64_t *gmax_pool, uint64_t *snap, hipStream_t stream);
 
 // Sampler workgroups that fit on the device at once (occupancy query).
 int sampler_blocks_per_cu();

@@ -1,0 +1,996 @@
+// Multi-query engine: many adaptive runs (Algorithm 1 of Borassi & Natale), on one
+// graph or many, share sampler launches and hit reductions.
+//
+// Every query keeps the schedule of a single run -- alpha pilot samples (phase 0),
+// computeDelta (Algorithm 2), then main-phase samples (phase 1) with the stopping
+// rule evaluated after every check interval of B samples -- and its result is exactly
+// the single run's: sample ids, check points and the counts entering each check are
+// the same, only the launches that carry them differ.
+//
+// One engine "tick" is one sampler launch.  It holds, for every active query, its
+// next pilot samples and/or its next check intervals, laid out interval-major
+// ("layers": layer j holds the j-th interval of every query that has one), so that a
+// hit reduction per layer followed by a snapshot per layer gives each query the
+// counts of exactly the samples up to each of its check points.  The node ids of a
+// query live at a fixed offset in a shared counter pool (tile-aligned), so one
+// reduction serves all queries of a layer.  Snapshots are the per-group maxima of
+// the counts (all-nodes task; group = nodes with equal (L_l, L_u), kept current by
+// the reduction itself) or the counts (top-k task, and the first main batch, which
+// is sampled before computeDelta is known).
+//
+// While tick t runs on the GPU the host evaluates tick t-1's checks.  A query that
+// stops has samples past its stopping point in flight: their hits are subtracted
+// again before its counters are read, as in the single run.
+#include <hip/hip_runtime.h>
+#include <string.h>
+
+#include <chrono>
+#include <cmath>
+#include <condition_variable>
+#include <deque>
+#include <map>
+#include <memory>
+#include <thread>
+#include <vector>
+
+#include "kad_internal.h"
+#include "kad_stats.h"
+
+namespace kad {
+namespace {
+
+using clk = std::chrono::steady_clock;
+double secs(clk::time_point a, clk::time_point b) {
+  return std::chrono::duration<double>(b - a).count();
+}
+
+constexpr uint32_t POOL_TILES = MAX_HIT_TILES_PUBLIC;                 // counter pool tiles
+constexpr uint64_t POOL_IDS = (uint64_t)POOL_TILES * HIT_TILE_IDS;    // 2^25 node ids
+constexpr uint32_t TICK_SAMPLES = 1u << 18;    // samples per engine launch, at most
+constexpr uint64_t TICK_PATH_BYTES = 1ull << 30;  // path buffer of one launch, at most
+constexpr uint32_t MAX_LAYERS = 64;            // check intervals of one query per launch
+
+enum class QState { Queued, Pilot, Main, Final, Done };
+enum class Kind : uint8_t { Pilot, PilotLast, MainFull, Main };
+
+struct Query {
+  uint64_t ticket = 0;
+  kad_graph *g = nullptr;
+  kad_params p{};
+  kad_result *direct = nullptr;  // filled at completion (kad_run_batch)
+  QState st = QState::Queued;
+  kad_status status = KAD_OK;
+  std::string error;
+  bool prepared = false;
+  // schedule
+  uint32_t n = 0, vd = 0, stride = 2;
+  bool vd_exact = false;
+  uint64_t omega = 0, alpha = 0, B = 0, K = 0;
+  double eb = 0.001;
+  // counter pool slice: node v of the query is pool id base() + v
+  uint32_t tile0 = 0, ntiles = 0;
+  uint64_t base() const { return (uint64_t)tile0 * HIT_TILE_IDS; }
+  // progress
+  uint64_t pilot_launched = 0, launched = 0, tau = 0;
+  bool main_started = false, delta_ready = false, rule = false;
+  double worst = 0.0;
+  uint64_t arcs = 0, pilot_arcs = 0;
+  int refs = 0;              // unprocessed ticks holding samples of this query
+  uint64_t last_tick = ~0ull;  // the tick being built last added this query
+  // statistics
+  std::vector<uint64_t> count0;
+  std::vector<double> lam_l, lam_u, L_l, L_u;
+  std::unique_ptr<StopChecker> checker;
+  std::vector<uint32_t> gdev;  // group ids shifted to the pool (uploaded once)
+  double C = 0.0;
+  // results
+  PinBuf<uint64_t> final_counts;
+  hipEvent_t final_ev = nullptr;
+  std::vector<uint64_t> count;
+  std::vector<double> bc, lo, hi;
+  std::vector<uint32_t> topk, rlo, rhi;
+  // times
+  clk::time_point t_submit, t_admit, t_pilot, t_delta, t_final, t_done;
+  ~Query() {
+    if (final_ev) (void)hipEventDestroy(final_ev);
+  }
+};
+
+struct Piece {
+  Query *q;
+  Kind kind;
+  uint32_t begin, count;  // launch indices
+  uint64_t first;         // first sample id
+  uint64_t snap;          // snapshot offset (entries), pilots other than the last: none
+};
+
+struct Tick {
+  OutSet out;
+  DevBuf<SampleSeg> d_segs;
+  PinBuf<SampleSeg> h_segs;
+  DevBuf<GatherDesc> d_gat;
+  PinBuf<GatherDesc> h_gat;
+  DevBuf<uint32_t> work;
+  DevBuf<uint64_t> d_snap;
+  PinBuf<uint64_t> h_snap;
+  hipEvent_t sampled = nullptr;
+  std::vector<hipEvent_t> layer_ev;
+  std::vector<Piece> pieces;
+  std::vector<Query *> queries;        // each query with samples in this tick, once
+  std::vector<uint32_t> layer_piece;  // layer L = pieces [layer_piece[L], layer_piece[L+1])
+  std::vector<uint32_t> layer_gat;    // its gather descriptors
+  std::vector<uint32_t> layer_blocks; // and the gather's workgroups
+  std::vector<uint64_t> layer_snap;   // and its snapshot entries
+  uint32_t total = 0, stride = 2, layers = 0;
+  uint64_t id = 0;
+  bool in_flight = false;
+  ~Tick() {
+    if (sampled) (void)hipEventDestroy(sampled);
+    for (auto e : layer_ev) (void)hipEventDestroy(e);
+  }
+};
+
+}  // namespace
+
+class Engine {
+ public:
+  explicit Engine(kad_ctx *c) : ctx_(c) {}
+  ~Engine() {
+    (void)hipStreamSynchronize(ctx_->stream);
+    (void)hipStreamSynchronize(ctx_->rstream);
+  }
+  kad_status init();
+  void enqueue(Query *q) { queue_.push_back(q); }
+  bool busy() const {
+    return !queue_.empty() || !active_.empty() || ticks_[0].in_flight || ticks_[1].in_flight;
+  }
+  // One round: admit queued queries, launch a tick, evaluate the previous one, and
+  // complete stopped queries whose counters have landed.
+  kad_status step();
+  std::vector<Query *> take_done() {
+    std::vector<Query *> d;
+    d.swap(done_);
+    return d;
+  }
+  uint64_t ticks_launched() const { return ticks_launched_.load(); }
+  uint64_t samples_launched() const { return samples_launched_.load(); }
+
+ private:
+  kad_status prepare(Query *q);
+  kad_status admit();
+  kad_status build(Tick &t);
+  kad_status launch(Tick &t);
+  kad_status process(Tick &t, Tick &other);
+  kad_status stop_query(Query *q, Tick &t, size_t after_piece, Tick &other);
+  kad_status finalize(bool block);
+  kad_status reduce(const Tick &t, uint32_t begin, uint32_t count, bool subtract);
+  void release_tiles(Query *q);
+  void finish_failed(Query *q, kad_status st, const std::string &msg);
+  HitScratch scratch() {
+    HitScratch h;
+    h.bins = bins_.p;
+    h.cap = bins_cap_;
+    h.bin_count = bin_count_.p;
+    h.tile_start = tile_start_.p;
+    h.tile_fill = tile_fill_.p;
+    return h;
+  }
+
+  kad_ctx *ctx_;
+  DevBuf<uint64_t> count_pool_, gmax_pool_;
+  DevBuf<uint32_t> group_pool_;
+  std::vector<uint8_t> tile_used_;
+  uint32_t tiles_hw_ = 0;  // reductions cover pool tiles [0, tiles_hw_)
+  DevBuf<uint32_t> bins_, bin_count_, tile_start_, tile_fill_;
+  uint64_t bins_cap_ = 0;
+  Tick ticks_[2];
+  int cur_ = 0;
+  uint64_t tick_id_ = 0;
+  std::deque<Query *> queue_;
+  std::vector<Query *> active_;
+  std::vector<Query *> done_;
+  size_t rr_ = 0;
+  std::atomic<uint64_t> ticks_launched_{0}, samples_launched_{0};
+};
+
+kad_status Engine::init() {
+  HIP_TRY(hipSetDevice(ctx_->device));
+  HIP_TRY(count_pool_.ensure(POOL_IDS));
+  HIP_TRY(gmax_pool_.ensure(POOL_IDS));
+  HIP_TRY(group_pool_.ensure(POOL_IDS));
+  HIP_TRY(hipMemsetAsync(count_pool_.p, 0, POOL_IDS * 8, ctx_->rstream));
+  HIP_TRY(hipMemsetAsync(group_pool_.p, 0, POOL_IDS * 4, ctx_->rstream));
+  HIP_TRY(bin_count_.ensure(POOL_TILES));
+  HIP_TRY(tile_start_.ensure(POOL_TILES));
+  HIP_TRY(tile_fill_.ensure(POOL_TILES));
+  HIP_TRY(hipMemsetAsync(bin_count_.p, 0, POOL_TILES * 4, ctx_->rstream));
+  HIP_TRY(hipMemsetAsync(tile_fill_.p, 0, POOL_TILES * 4, ctx_->rstream));
+  HIP_TRY(hipStreamSynchronize(ctx_->rstream));
+  tile_used_.assign(POOL_TILES, 0);
+  for (Tick &t : ticks_) {
+    HIP_TRY(t.work.ensure(1));
+    HIP_TRY(hipEventCreateWithFlags(&t.sampled, hipEventDisableTiming));
+  }
+  return KAD_OK;
+}
+
+void Engine::finish_failed(Query *q, kad_status st, const std::string &msg) {
+  if (q->status == KAD_OK) {
+    q->status = st;
+    q->error = msg;
+  }
+}
+
+kad_status Engine::prepare(Query *q) {
+  q->prepared = true;
+  const kad_params &p = q->p;
+  q->n = q->g->n;
+  if (q->n > POOL_IDS) {
+    finish_failed(q, KAD_EINVAL, "the engine serves graphs of up to 2^25 nodes");
+    return KAD_OK;
+  }
+  if (p.vd_override) {
+    q->vd = p.vd_override;
+  } else {
+    kad_status s = graph_vd(q->g, &q->vd, &q->vd_exact);
+    if (s) {
+      finish_failed(q, s, kad_last_error());
+      return KAD_OK;
+    }
+  }
+  const double c = p.c > 0 ? p.c : 0.5;
+  q->eb = p.balance_eps > 0 ? p.balance_eps : 0.001;
+  q->omega = omega_of(p.epsilon, p.delta, q->vd, c);
+  q->alpha = alpha_of(q->omega);
+  q->B = p.check_interval ? p.check_interval : interval_of(q->omega);
+  uint64_t K = p.kernel_batch ? p.kernel_batch : DEFAULT_BATCH;
+  q->K = std::min<uint64_t>(std::max<uint64_t>(q->B, (K + q->B - 1) / q->B * q->B),
+                            (uint64_t)q->B * MAX_LAYERS);
+  q->stride = std::max<uint32_t>(q->vd, 2);
+  if (q->B > TICK_SAMPLES || (uint64_t)q->stride * 4 * q->B > TICK_PATH_BYTES)
+    finish_failed(q, KAD_EINVAL, "check interval too large for the engine's launches");
+  return KAD_OK;
+}
+
+void Engine::release_tiles(Query *q) {
+  for (uint32_t t = q->tile0; t < q->tile0 + q->ntiles; ++t) tile_used_[t] = 0;
+  q->ntiles = 0;
+  tiles_hw_ = 0;
+  for (uint32_t t = 0; t < POOL_TILES; ++t)
+    if (tile_used_[t]) tiles_hw_ = t + 1;
+}
+
+kad_status Engine::admit() {
+  while (!queue_.empty()) {
+    Query *q = queue_.front();
+    if (!q->prepared) {
+      kad_status s = prepare(q);
+      if (s) return s;
+    }
+    if (q->status != KAD_OK) {  // rejected before it touched the GPU
+      queue_.pop_front();
+      q->st = QState::Done;
+      q->t_admit = q->t_pilot = q->t_delta = q->t_final = q->t_done = clk::now();
+      done_.push_back(q);
+      continue;
+    }
+    const uint32_t need = (uint32_t)((q->n + HIT_TILE_IDS - 1) / HIT_TILE_IDS);
+    uint32_t start = POOL_TILES;
+    for (uint32_t t = 0, run = 0; t < POOL_TILES; ++t) {  // first fit
+      run = tile_used_[t] ? 0 : run + 1;
+      if (run == need) {
+        start = t + 1 - need;
+        break;
+      }
+    }
+    if (start == POOL_TILES) break;  // wait until running queries release counters
+    if (q->n > ctx_->slot_n) {
+      if (ticks_[0].in_flight || ticks_[1].in_flight) break;  // grow only when idle
+      HIP_TRY(hipStreamSynchronize(ctx_->rstream));
+      kad_status s = ensure_slots(ctx_, q->n);
+      if (s) {
+        finish_failed(q, s, kad_last_error());
+        continue;
+      }
+    }
+    for (uint32_t t = start; t < start + need; ++t) tile_used_[t] = 1;
+    q->tile0 = start;
+    q->ntiles = need;
+    tiles_hw_ = std::max(tiles_hw_, start + need);
+    // until computeDelta assigns groups, every node maps to the query's first
+    // group-maximum entry (rebuilt from the counters when the groups arrive)
+    HIP_TRY(launch_fill_u32(group_pool_.p + q->base(), q->n, (uint32_t)q->base(), ctx_->rstream));
+    if (!q->final_ev) HIP_TRY(hipEventCreateWithFlags(&q->final_ev, hipEventDisableTiming));
+    q->st = QState::Pilot;
+    q->t_admit = clk::now();
+    active_.push_back(q);
+    queue_.pop_front();
+  }
+  return KAD_OK;
+}
+
+kad_status Engine::build(Tick &t) {
+  t.pieces.clear();
+  t.queries.clear();
+  t.layer_piece.assign(1, 0);
+  t.total = 0;
+  t.stride = 2;
+  t.layers = 0;
+  t.id = ++tick_id_;
+  std::vector<std::vector<Piece>> layer(MAX_LAYERS + 1);
+  uint32_t total = 0, stride = 2;
+  auto room = [&](const Query *q, uint64_t want) -> uint32_t {
+    const uint32_t st = std::max(stride, q->stride);
+    const uint64_t by_path = TICK_PATH_BYTES / (4ull * st);
+    const uint64_t cap = std::min<uint64_t>(TICK_SAMPLES, by_path);
+    return total >= cap ? 0u : (uint32_t)std::min<uint64_t>(want, cap - total);
+  };
+  auto add = [&](Query *q, uint32_t L, Kind kind, uint32_t cnt, uint64_t first) {
+    layer[L].push_back(Piece{q, kind, 0, cnt, first, ~0ull});
+    total += cnt;
+    stride = std::max(stride, q->stride);
+    if (q->last_tick != t.id) {
+      q->last_tick = t.id;
+      q->refs++;
+      t.queries.push_back(q);
+    }
+  };
+  const size_t na = active_.size();
+  for (size_t j = 0; j < na; ++j) {
+    Query *q = active_[(rr_ + j) % na];
+    if (q->status != KAD_OK || q->st == QState::Final) continue;
+    bool pilot_done_here = false;
+    if (q->st == QState::Pilot && q->pilot_launched < q->alpha) {
+      const uint32_t cnt = room(q, std::min<uint64_t>(q->alpha - q->pilot_launched, TICK_SAMPLES / 2));
+      if (cnt == 0) continue;
+      const bool last = q->pilot_launched + cnt == q->alpha;
+      add(q, 0, last ? Kind::PilotLast : Kind::Pilot, cnt, q->pilot_launched);
+      q->pilot_launched += cnt;
+      pilot_done_here = last;
+      if (!last) continue;
+    }
+    // main phase: the first batch goes out with the last pilot samples (it does not
+    // depend on them); later ones are sized from the latest check
+    if (q->launched >= q->omega) continue;
+    uint64_t want;
+    uint32_t L0 = 0;
+    if (!q->main_started) {
+      if (!pilot_done_here && !(q->st == QState::Pilot && q->pilot_launched == q->alpha) &&
+          q->st != QState::Main)
+        continue;
+      want = std::min<uint64_t>(q->omega, std::min<uint64_t>(q->K, std::max<uint64_t>(q->B, (q->omega / 2 + q->B - 1) / q->B * q->B)));
+      L0 = pilot_done_here ? 1 : 0;
+    } else {
+      if (q->st != QState::Main || q->tau == 0) continue;  // first batch not yet checked
+      const uint64_t ahead = q->launched - q->tau;
+      double w;
+      if (q->p.mode == KAD_ALL_NODES && q->worst > 0.0)
+        w = (double)q->tau * q->worst - (double)q->launched;  // the bounds shrink about as 1/tau
+      else
+        w = (double)q->K - (double)ahead;
+      if (w <= 0.0) {
+        if (ahead > 0) continue;  // what is in flight is predicted to suffice
+        w = (double)q->B;
+      }
+      want = (uint64_t)std::min<double>(std::ceil(w / (double)q->B), (double)(q->K / q->B)) * q->B;
+    }
+    const bool full = !q->delta_ready;  // groups unknown at launch: snapshot the counts
+    for (uint32_t L = L0; L < MAX_LAYERS && want > 0 && q->launched < q->omega; ++L) {
+      const uint32_t cnt = (uint32_t)std::min<uint64_t>(q->B, q->omega - q->launched);
+      if (room(q, cnt) < cnt) break;
+      add(q, L, full || q->p.mode == KAD_TOPK ? Kind::MainFull : Kind::Main, cnt, q->launched);
+      q->launched += cnt;
+      q->main_started = true;
+      want = want > cnt ? want - cnt : 0;
+    }
+  }
+  rr_ = na ? (rr_ + 1) % na : 0;
+  uint32_t pos = 0;
+  for (uint32_t L = 0; L <= MAX_LAYERS; ++L) {
+    if (layer[L].empty()) break;
+    for (Piece &pc : layer[L]) {
+      pc.begin = pos;
+      pos += pc.count;
+      t.pieces.push_back(pc);
+    }
+    t.layer_piece.push_back((uint32_t)t.pieces.size());
+    t.layers++;
+  }
+  t.total = total;
+  t.stride = stride;
+  return KAD_OK;
+}
+
+kad_status Engine::reduce(const Tick &t, uint32_t begin, uint32_t count, bool subtract) {
+  HIP_TRY(launch_hit_reduce(t.out.path.p + (size_t)begin * t.stride, t.out.len.p + begin,
+                            t.stride, count, tiles_hw_ * HIT_TILE_IDS, count_pool_.p, subtract,
+                            subtract ? nullptr : group_pool_.p,
+                            subtract ? nullptr : gmax_pool_.p, scratch(), ctx_->rstream));
+  return KAD_OK;
+}
+
+kad_status Engine::launch(Tick &t) {
+  hipStream_t s = ctx_->stream, rs = ctx_->rstream;
+  const uint32_t np = (uint32_t)t.pieces.size();
+  // buffers (the previous use of this tick's buffers is complete on the host side;
+  // device-side readers are fenced by out.reduced)
+  if (t.out.cap < t.total || t.out.stride < t.stride) {
+    if (t.out.reduced) HIP_TRY(hipEventSynchronize(t.out.reduced));
+    kad_status st = t.out.ensure(t.total, t.stride, rs);
+    if (st) return st;
+  } else {
+    kad_status st = t.out.ensure(t.total, t.stride, rs);
+    if (st) return st;
+  }
+  HIP_TRY(t.d_segs.ensure(np));
+  HIP_TRY(t.h_segs.ensure(np));
+  uint64_t max_layer = 0;
+  for (uint32_t L = 0; L < t.layers; ++L) {
+    const Piece &a = t.pieces[t.layer_piece[L]];
+    const Piece &b = t.pieces[t.layer_piece[L + 1] - 1];
+    max_layer = std::max<uint64_t>(max_layer, b.begin + b.count - a.begin);
+  }
+  const uint64_t need_bins = max_layer * std::max<uint32_t>(t.stride - 2, 1);
+  if (need_bins > bins_cap_) {
+    HIP_TRY(hipStreamSynchronize(rs));
+    bins_.release();
+    HIP_TRY(bins_.ensure(need_bins));
+    bins_cap_ = need_bins;
+  }
+  // segments
+  for (uint32_t j = 0; j < np; ++j) {
+    const Piece &pc = t.pieces[j];
+    const kad_graph *g = pc.q->g;
+    SampleSeg &sg = t.h_segs.p[j];
+    sg.row = g->d_row;
+    sg.col = g->d_col;
+    sg.rrow = g->directed ? g->d_rrow : g->d_row;
+    sg.rcol = g->directed ? g->d_rcol : g->d_col;
+    sg.seed = pc.q->p.seed;
+    sg.first = pc.first;
+    sg.n = g->n;
+    sg.phase = pc.kind == Kind::Pilot || pc.kind == Kind::PilotLast ? 0u : 1u;
+    sg.begin = pc.begin;
+    sg.id_base = (uint32_t)pc.q->base();
+  }
+  // snapshots, layer by layer
+  std::vector<GatherDesc> gat;
+  t.layer_gat.assign(1, 0);
+  t.layer_blocks.clear();
+  t.layer_snap.assign(1, 0);
+  uint64_t snap = 0;
+  for (uint32_t L = 0; L < t.layers; ++L) {
+    uint32_t blocks = 0;
+    for (uint32_t j = t.layer_piece[L]; j < t.layer_piece[L + 1]; ++j) {
+      Piece &pc = t.pieces[j];
+      GatherDesc d{};
+      if (pc.kind == Kind::Pilot) continue;
+      const Query *q = pc.q;
+      d.off = q->base();
+      d.dst = snap;
+      if (pc.kind == Kind::PilotLast) {
+        d.len = q->n;
+        d.mode = GATHER_COUNT_ZERO;  // count0, and the counters restart for phase 1
+      } else if (pc.kind == Kind::MainFull) {
+        d.len = q->n;
+        d.mode = GATHER_COUNT;
+      } else {
+        d.len = (uint32_t)q->checker->groups();
+        d.mode = GATHER_GMAX;
+      }
+      d.block0 = blocks;
+      blocks += (d.len + GATHER_CHUNK - 1) / GATHER_CHUNK;
+      pc.snap = snap;
+      snap += d.len;
+      if (d.len) gat.push_back(d);
+      else pc.snap = snap;  // empty snapshot
+    }
+    t.layer_gat.push_back((uint32_t)gat.size());
+    t.layer_blocks.push_back(blocks);
+    t.layer_snap.push_back(snap);
+  }
+  HIP_TRY(t.d_gat.ensure(std::max<size_t>(gat.size(), 1)));
+  HIP_TRY(t.h_gat.ensure(std::max<size_t>(gat.size(), 1)));
+  if (!gat.empty()) memcpy(t.h_gat.p, gat.data(), gat.size() * sizeof(GatherDesc));
+  HIP_TRY(t.d_snap.ensure(std::max<uint64_t>(snap, 1)));
+  HIP_TRY(t.h_snap.ensure(std::max<uint64_t>(snap, 1)));
+  while (t.layer_ev.size() < t.layers) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    t.layer_ev.push_back(e);
+  }
+  // ---- sampler
+  HIP_TRY(hipStreamWaitEvent(s, t.out.reduced, 0));
+  HIP_TRY(hipMemcpyAsync(t.d_segs.p, t.h_segs.p, (size_t)np * sizeof(SampleSeg),
+                         hipMemcpyHostToDevice, s));
+  HIP_TRY(launch_zero_u32(t.work.p, 1, s));
+  const uint32_t grid = std::min<uint32_t>(ctx_->slots, t.total);
+  if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k0, s));
+  HIP_TRY(launch_sampler_multi(t.d_segs.p, np, slot_view(ctx_), t.total, t.work.p,
+                               t.out.view(t.stride), grid, s));
+  if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
+  HIP_TRY(hipEventRecord(t.sampled, s));
+  HIP_TRY(hipMemcpyAsync(t.out.h_flags.p, t.out.flags.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));
+  HIP_TRY(hipMemcpyAsync(t.out.h_arcs.p, t.out.arcs.p, (size_t)t.total * 8, hipMemcpyDeviceToHost, s));
+  if (ctx_->timing) {
+    HIP_TRY(hipMemcpyAsync(t.out.h_nodes.p, t.out.nodes.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipMemcpyAsync(t.out.h_len.p, t.out.len.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));
+  }
+  HIP_TRY(hipEventRecord(t.out.copied, s));
+  // ---- per layer: hits into the pool, then the snapshot of each query's check
+  HIP_TRY(hipStreamWaitEvent(rs, t.sampled, 0));
+  if (!gat.empty())
+    HIP_TRY(hipMemcpyAsync(t.d_gat.p, t.h_gat.p, gat.size() * sizeof(GatherDesc),
+                           hipMemcpyHostToDevice, rs));
+  for (uint32_t L = 0; L < t.layers; ++L) {
+    const Piece &a = t.pieces[t.layer_piece[L]];
+    const Piece &b = t.pieces[t.layer_piece[L + 1] - 1];
+    kad_status st = reduce(t, a.begin, b.begin + b.count - a.begin, false);
+    if (st) return st;
+    const uint32_t g0 = t.layer_gat[L], g1 = t.layer_gat[L + 1];
+    if (g1 > g0) {
+      HIP_TRY(launch_gather(t.d_gat.p + g0, g1 - g0, t.layer_blocks[L], count_pool_.p,
+                            gmax_pool_.p, t.d_snap.p, rs));
+      const uint64_t s0 = t.layer_snap[L], s1 = t.layer_snap[L + 1];
+      HIP_TRY(hipMemcpyAsync(t.h_snap.p + s0, t.d_snap.p + s0, (s1 - s0) * 8,
+                             hipMemcpyDeviceToHost, rs));
+    }
+    HIP_TRY(hipEventRecord(t.layer_ev[L], rs));
+  }
+  t.in_flight = true;
+  ticks_launched_++;
+  samples_launched_ += t.total;
+  return KAD_OK;
+}
+
+// A query stops after piece `at` of tick t: its hits from later pieces of t and from
+// the tick in flight are subtracted, then its counters are read and reset.
+kad_status Engine::stop_query(Query *q, Tick &t, size_t at, Tick &other) {
+  hipStream_t rs = ctx_->rstream;
+  if (q->status == KAD_OK) {
+    for (size_t j = at + 1; j < t.pieces.size(); ++j)
+      if (t.pieces[j].q == q) {
+        kad_status st = reduce(t, t.pieces[j].begin, t.pieces[j].count, true);
+        if (st) return st;
+      }
+    if (other.in_flight)
+      for (const Piece &pc : other.pieces)
+        if (pc.q == q) {
+          kad_status st = reduce(other, pc.begin, pc.count, true);
+          if (st) return st;
+        }
+    HIP_TRY(q->final_counts.ensure(q->n));
+    HIP_TRY(hipMemcpyAsync(q->final_counts.p, count_pool_.p + q->base(), (size_t)q->n * 8,
+                           hipMemcpyDeviceToHost, rs));
+  }
+  HIP_TRY(launch_zero_u32((uint32_t *)(count_pool_.p + q->base()), 2ull * q->n, rs));
+  HIP_TRY(hipEventRecord(q->final_ev, rs));
+  q->st = QState::Final;
+  q->t_final = clk::now();
+  return KAD_OK;
+}
+
+kad_status Engine::process(Tick &t, Tick &other) {
+  hipStream_t rs = ctx_->rstream;
+  HIP_TRY(hipEventSynchronize(t.out.copied));
+  if (ctx_->timing) {
+    float ms = 0.f;
+    HIP_TRY(hipEventElapsedTime(&ms, t.out.k0, t.out.k1));
+    ctx_->t_launches += 1;
+    ctx_->t_samples += t.total;
+    ctx_->t_seconds += ms * 1e-3;
+    for (uint32_t k = 0; k < t.total; ++k) {
+      ctx_->t_arcs += t.out.h_arcs.p[k];
+      ctx_->t_nodes += t.out.h_nodes.p[k];
+      ctx_->t_hits += t.out.h_len.p[k] >= 2 ? t.out.h_len.p[k] - 2 : 0;
+    }
+  }
+  for (uint32_t L = 0; L < t.layers; ++L) {
+    HIP_TRY(hipEventSynchronize(t.layer_ev[L]));
+    for (uint32_t j = t.layer_piece[L]; j < t.layer_piece[L + 1]; ++j) {
+      const Piece &pc = t.pieces[j];
+      Query *q = pc.q;
+      if (q->st == QState::Final || q->st == QState::Done) continue;  // past its stop
+      uint64_t arcs = 0;
+      uint32_t bad = 0;
+      for (uint32_t k = pc.begin; k < pc.begin + pc.count; ++k) {
+        arcs += t.out.h_arcs.p[k];
+        bad |= t.out.h_flags.p[k];
+      }
+      if (bad) {
+        if (bad & FLAG_OVERFLOW)
+          finish_failed(q, KAD_EOVERFLOW, "a path count exceeded 128 bits");
+        else if (bad & FLAG_RNG)
+          finish_failed(q, KAD_ERNG, "bounded draw rejected 64 times");
+        else
+          finish_failed(q, KAD_EOVERFLOW, "candidate-edge list or path outgrew its buffer");
+        kad_status st = stop_query(q, t, j, other);
+        if (st) return st;
+        continue;
+      }
+      if (pc.kind == Kind::Pilot || pc.kind == Kind::PilotLast) {
+        q->pilot_arcs += arcs;
+        if (pc.kind == Kind::Pilot) continue;
+        // ---- computeDelta (Algorithm 2) on the pilot counts
+        const uint32_t n = q->n;
+        q->count0.assign(t.h_snap.p + pc.snap, t.h_snap.p + pc.snap + n);
+        q->lam_l.assign(n, q->p.epsilon);
+        q->lam_u.assign(n, q->p.epsilon);
+        q->L_l.resize(n);
+        q->L_u.resize(n);
+        q->t_pilot = clk::now();
+        if (q->p.mode == KAD_TOPK)
+          topk_lambdas(n, q->p.k, q->count0.data(), q->alpha, q->p.epsilon, q->lam_l.data(),
+                       q->lam_u.data());
+        Groups groups;
+        compute_delta(n, q->count0.data(), q->alpha, q->omega, q->lam_l.data(), q->lam_u.data(),
+                      q->p.delta, q->eb, q->L_l.data(), q->L_u.data(), &q->C, &groups);
+        q->checker.reset(new StopChecker(n, q->p.mode, q->p.k, q->p.epsilon, q->omega,
+                                         q->L_l.data(), q->L_u.data(), std::move(groups)));
+        // group ids into the pool, and the group maxima rebuilt from the counters
+        // (the first main batch may already be reduced)
+        const auto &go = q->checker->group_of();
+        q->gdev.resize(n);
+        const uint32_t base = (uint32_t)q->base();
+        for (uint32_t v = 0; v < n; ++v) q->gdev[v] = go[v] + base;
+        HIP_TRY(hipMemcpyAsync(group_pool_.p + base, q->gdev.data(), (size_t)n * 4,
+                               hipMemcpyHostToDevice, rs));
+        HIP_TRY(launch_zero_u32((uint32_t *)(gmax_pool_.p + base), 2ull * q->checker->groups(), rs));
+        HIP_TRY(launch_group_max(count_pool_.p + base, group_pool_.p + base, n, gmax_pool_.p, rs));
+        q->delta_ready = true;
+        q->st = QState::Main;
+        q->t_delta = clk::now();
+        continue;
+      }
+      // ---- a main-phase check point (every B samples, or omega)
+      q->arcs += arcs;
+      q->tau += pc.count;
+      bool stop = false;
+      if (q->tau >= q->omega) {
+        stop = true;
+      } else if (pc.count == q->B) {
+        const uint64_t *sp = t.h_snap.p + pc.snap;
+        if (pc.kind == Kind::MainFull) {
+          if (q->p.mode == KAD_ALL_NODES) {
+            // group maxima from the counts, then the same decision as below
+            std::vector<uint64_t> gm(q->checker->groups(), 0);
+            const auto &go = q->checker->group_of();
+            for (uint32_t v = 0; v < q->n; ++v) gm[go[v]] = std::max(gm[go[v]], sp[v]);
+            stop = q->checker->check_group_max(gm.data(), q->tau, &q->worst);
+          } else {
+            stop = q->checker->check(sp, q->tau);
+          }
+        } else {
+          stop = q->checker->check_group_max(sp, q->tau, &q->worst);
+        }
+        q->rule = stop;
+      }
+      if (stop) {
+        kad_status st = stop_query(q, t, j, other);
+        if (st) return st;
+      }
+    }
+  }
+  for (Query *q : t.queries) q->refs--;
+  HIP_TRY(hipEventRecord(t.out.reduced, rs));
+  t.in_flight = false;
+  return KAD_OK;
+}
+
+kad_status Engine::finalize(bool block) {
+  for (size_t j = 0; j < active_.size();) {
+    Query *q = active_[j];
+    if (q->st != QState::Final || q->refs > 0) {
+      ++j;
+      continue;
+    }
+    if (block) {
+      HIP_TRY(hipEventSynchronize(q->final_ev));
+    } else {
+      const hipError_t e = hipEventQuery(q->final_ev);
+      if (e == hipErrorNotReady) {
+        ++j;
+        continue;
+      }
+      HIP_TRY(e);
+    }
+    if (q->status == KAD_OK) {
+      const uint32_t n = q->n;
+      q->count.assign(q->final_counts.p, q->final_counts.p + n);
+      q->final_counts.release();
+      q->bc.resize(n);
+      q->lo.resize(n);
+      q->hi.resize(n);
+      node_outputs(n, q->count.data(), q->tau, q->omega, q->rule, q->p.epsilon, q->L_l.data(),
+                   q->L_u.data(), q->checker->group_of(), q->bc.data(), q->lo.data(),
+                   q->hi.data());
+      if (q->p.mode == KAD_TOPK)
+        topk_select(n, q->p.k, q->count.data(), q->lo.data(), q->hi.data(), q->topk, q->rlo,
+                    q->rhi);
+    }
+    release_tiles(q);
+    q->checker.reset();
+    q->count0.clear();
+    q->count0.shrink_to_fit();
+    q->gdev.clear();
+    q->gdev.shrink_to_fit();
+    q->st = QState::Done;
+    q->t_done = clk::now();
+    done_.push_back(q);
+    active_.erase(active_.begin() + j);
+  }
+  return KAD_OK;
+}
+
+kad_status Engine::step() {
+  kad_status st = admit();
+  if (st) return st;
+  // ticks_[cur_] is free (processed); ticks_[1 - cur_] may be running
+  Tick &nt = ticks_[cur_];
+  Tick &pt = ticks_[1 - cur_];
+  if ((st = build(nt))) return st;
+  if (nt.total > 0 && (st = launch(nt))) return st;
+  if (pt.in_flight && (st = process(pt, nt))) return st;
+  cur_ = 1 - cur_;
+  // block on a stopped query's counters only when nothing else can move
+  const bool idle = !ticks_[0].in_flight && !ticks_[1].in_flight;
+  return finalize(idle);
+}
+
+}  // namespace kad
+
+// ---------------------------------------------------------------- C ABI
+
+namespace {
+
+void fill_result(const kad::Query *q, kad_result *r, kad_status *ret) {
+  r->tau = q->tau;
+  r->omega = q->omega;
+  r->alpha = q->alpha;
+  r->interval = q->B;
+  r->arcs_scanned = q->arcs;
+  r->pilot_arcs_scanned = q->pilot_arcs;
+  r->overflow_samples = 0;
+  r->vd = q->vd;
+  r->vd_exact = q->vd_exact ? 1u : 0u;
+  r->stop_reason = q->rule ? KAD_STOP_RULE : KAD_STOP_OMEGA;
+  r->n = q->n;
+  r->C = q->C;
+  r->seconds = kad::secs(q->t_submit, q->t_done);
+  r->seconds_setup = kad::secs(q->t_submit, q->t_admit);
+  r->seconds_pilot = q->delta_ready ? kad::secs(q->t_admit, q->t_pilot) : 0.0;
+  r->seconds_delta = q->delta_ready ? kad::secs(q->t_pilot, q->t_delta) : 0.0;
+  r->seconds_main = q->delta_ready ? kad::secs(q->t_delta, q->t_final) : 0.0;
+  r->topk_len = 0;
+  *ret = q->status;
+  if (q->status != KAD_OK) return;
+  const size_t n = q->n;
+  if (r->count) memcpy(r->count, q->count.data(), n * 8);
+  if (r->bc) memcpy(r->bc, q->bc.data(), n * 8);
+  if (r->lower) memcpy(r->lower, q->lo.data(), n * 8);
+  if (r->upper) memcpy(r->upper, q->hi.data(), n * 8);
+  if (q->p.mode == KAD_TOPK) {
+    r->topk_len = (uint32_t)q->topk.size();
+    if (q->topk.size() > r->topk_cap) {
+      *ret = kad::fail(KAD_ETOOSMALL, "top-k output needs %zu entries", q->topk.size());
+      return;
+    }
+    for (size_t j = 0; j < q->topk.size(); ++j) {
+      if (r->topk_node) r->topk_node[j] = q->topk[j];
+      if (r->rank_lo) r->rank_lo[j] = q->rlo[j];
+      if (r->rank_hi) r->rank_hi[j] = q->rhi[j];
+    }
+  }
+}
+
+}  // namespace
+
+struct kad_server {
+  kad_ctx *ctx = nullptr;
+  std::unique_ptr<kad::Engine> eng;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv_work, cv_done;
+  std::deque<kad::Query *> incoming;
+  std::map<uint64_t, std::unique_ptr<kad::Query>> queries;  // submitted, not yet retrieved
+  std::map<uint64_t, bool> finished;
+  uint64_t next_ticket = 1;
+  bool quit = false;
+  kad_status fatal = KAD_OK;
+  std::string fatal_msg;
+  uint64_t completed = 0;
+};
+
+namespace {
+
+void server_loop(kad_server *sv) {
+  (void)hipSetDevice(sv->ctx->device);
+  for (;;) {
+    {
+      std::unique_lock<std::mutex> lk(sv->mu);
+      sv->cv_work.wait(lk, [&] { return sv->quit || !sv->incoming.empty() || sv->eng->busy(); });
+      if (sv->quit && !sv->eng->busy()) break;
+      while (!sv->incoming.empty()) {
+        sv->eng->enqueue(sv->incoming.front());
+        sv->incoming.pop_front();
+      }
+    }
+    kad_status st = sv->eng->step();
+    std::vector<kad::Query *> done = sv->eng->take_done();
+    if (st || !done.empty()) {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      for (kad::Query *q : done) {
+        sv->finished[q->ticket] = true;
+        sv->completed++;
+      }
+      if (st) {
+        sv->fatal = st;
+        sv->fatal_msg = kad_last_error();
+      }
+      sv->cv_done.notify_all();
+    }
+    if (st) break;  // device error: every unfinished query reports it
+  }
+}
+
+kad_status server_take(kad_server *sv, uint64_t ticket, kad_result *r, std::unique_lock<std::mutex> &lk) {
+  auto it = sv->queries.find(ticket);
+  kad::Query *q = it->second.get();
+  kad_status ret = KAD_OK;
+  fill_result(q, r, &ret);
+  if (ret != KAD_OK && q->status != KAD_OK) kad::fail(q->status, "%s", q->error.c_str());
+  sv->finished.erase(ticket);
+  std::unique_ptr<kad::Query> hold = std::move(it->second);
+  sv->queries.erase(it);
+  lk.unlock();
+  hold.reset();
+  return ret;
+}
+
+}  // namespace
+
+extern "C" {
+
+kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *graphs,
+                         const kad_params *params, kad_result *results, kad_status *status) {
+  using kad::fail;
+  if (!ctx || (count && (!graphs || !params || !results)))
+    return fail(KAD_EINVAL, "NULL argument");
+  for (uint32_t i = 0; i < count; ++i) {
+    if (!graphs[i]) return fail(KAD_EINVAL, "graph %u is NULL", i);
+    if (graphs[i]->ctx != ctx) return fail(KAD_EINVAL, "graph %u belongs to another context", i);
+    kad_status st = kad::validate_params(graphs[i], &params[i]);
+    if (st) return st;
+  }
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
+  kad::Engine eng(ctx);
+  kad_status st = eng.init();
+  if (st) return st;
+  std::vector<std::unique_ptr<kad::Query>> qs(count);
+  const auto now = kad::clk::now();
+  for (uint32_t i = 0; i < count; ++i) {
+    qs[i].reset(new kad::Query());
+    qs[i]->ticket = i;
+    qs[i]->g = const_cast<kad_graph *>(graphs[i]);
+    qs[i]->p = params[i];
+    qs[i]->t_submit = now;
+    eng.enqueue(qs[i].get());
+  }
+  while (eng.busy())
+    if ((st = eng.step())) return st;
+  kad_status first = KAD_OK;
+  std::string first_msg;
+  for (uint32_t i = 0; i < count; ++i) {
+    kad_status ri = KAD_OK;
+    fill_result(qs[i].get(), &results[i], &ri);
+    if (ri != KAD_OK && qs[i]->status != KAD_OK) kad::fail(ri, "%s", qs[i]->error.c_str());
+    if (status) status[i] = ri;
+    if (ri != KAD_OK && first == KAD_OK) {
+      first = ri;
+      first_msg = kad_last_error();
+    }
+  }
+  if (first != KAD_OK) return fail(first, "%s", first_msg.c_str());
+  return KAD_OK;
+}
+
+kad_status kad_server_create(kad_ctx *ctx, kad_server **out) {
+  using kad::fail;
+  if (!ctx || !out) return fail(KAD_EINVAL, "NULL argument");
+  *out = nullptr;
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
+  std::unique_ptr<kad_server> sv(new kad_server());
+  sv->ctx = ctx;
+  sv->eng.reset(new kad::Engine(ctx));
+  kad_status st = sv->eng->init();
+  if (st) return st;
+  sv->th = std::thread(server_loop, sv.get());
+  claim.release_to_owner();  // released by kad_server_destroy
+  *out = sv.release();
+  return KAD_OK;
+}
+
+kad_status kad_server_submit(kad_server *sv, const kad_graph *g, const kad_params *p,
+                             uint64_t *ticket) {
+  using kad::fail;
+  if (!sv || !g || !p || !ticket) return fail(KAD_EINVAL, "NULL argument");
+  if (g->ctx != sv->ctx) return fail(KAD_EINVAL, "the graph belongs to another context");
+  kad_status st = kad::validate_params(g, p);
+  if (st) return st;
+  std::unique_ptr<kad::Query> q(new kad::Query());
+  q->g = const_cast<kad_graph *>(g);
+  q->p = *p;
+  q->t_submit = kad::clk::now();
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (sv->fatal) return fail(sv->fatal, "server stopped: %s", sv->fatal_msg.c_str());
+  q->ticket = sv->next_ticket++;
+  *ticket = q->ticket;
+  sv->incoming.push_back(q.get());
+  sv->queries[q->ticket] = std::move(q);
+  sv->cv_work.notify_one();
+  return KAD_OK;
+}
+
+kad_status kad_server_poll(kad_server *sv, uint64_t ticket, kad_result *r) {
+  using kad::fail;
+  if (!sv || !r) return fail(KAD_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (!sv->queries.count(ticket)) return fail(KAD_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  if (!sv->finished.count(ticket)) {
+    if (sv->fatal) return fail(sv->fatal, "server stopped: %s", sv->fatal_msg.c_str());
+    return fail(KAD_EBUSY, "query %llu is running", (unsigned long long)ticket);
+  }
+  return server_take(sv, ticket, r, lk);
+}
+
+kad_status kad_server_wait(kad_server *sv, uint64_t ticket, kad_result *r, double timeout_s) {
+  using kad::fail;
+  if (!sv || !r) return fail(KAD_EINVAL, "NULL argument");
+  std::unique_lock<std::mutex> lk(sv->mu);
+  if (!sv->queries.count(ticket)) return fail(KAD_EINVAL, "unknown ticket %llu", (unsigned long long)ticket);
+  auto ready = [&] {
+    return sv->finished.count(ticket) > 0 || sv->fatal != KAD_OK || !sv->queries.count(ticket);
+  };
+  if (timeout_s < 0) {
+    sv->cv_done.wait(lk, ready);
+  } else if (!sv->cv_done.wait_for(lk, std::chrono::duration<double>(timeout_s), ready)) {
+    return fail(KAD_EBUSY, "query %llu is still running", (unsigned long long)ticket);
+  }
+  if (!sv->queries.count(ticket))
+    return fail(KAD_ECANCELED, "query %llu was dropped by kad_server_destroy", (unsigned long long)ticket);
+  if (!sv->finished.count(ticket)) return fail(sv->fatal, "server stopped: %s", sv->fatal_msg.c_str());
+  return server_take(sv, ticket, r, lk);
+}
+
+kad_status kad_server_stats(kad_server *sv, uint64_t *completed, uint64_t *launches,
+                            uint64_t *samples) {
+  if (!sv) return kad::fail(KAD_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  if (completed) *completed = sv->completed;
+  if (launches) *launches = sv->eng->ticks_launched();
+  if (samples) *samples = sv->eng->samples_launched();
+  return KAD_OK;
+}
+
+kad_status kad_server_destroy(kad_server *sv) {
+  if (!sv) return KAD_OK;
+  {
+    std::lock_guard<std::mutex> lk(sv->mu);
+    // queries not yet admitted are dropped; admitted ones run to completion
+    for (kad::Query *q : sv->incoming) sv->queries.erase(q->ticket);
+    sv->incoming.clear();
+    sv->quit = true;
+    sv->cv_work.notify_one();
+    sv->cv_done.notify_all();
+  }
+  if (sv->th.joinable()) sv->th.join();
+  kad_ctx *ctx = sv->ctx;
+  sv->eng.reset();
+  delete sv;
+  ctx->busy.store(false);
+  return KAD_OK;
+}
+
+}  // extern "C"

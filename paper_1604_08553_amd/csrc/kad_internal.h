@@ -1,0 +1,191 @@
+// Library-internal host structures shared by the single-run path (kad_runtime.cpp)
+// and the multi-query engine (kad_engine.cpp).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+#include <atomic>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/kadabra.h"
+#include "kad_device.h"
+
+namespace kad {
+
+kad_status fail(kad_status st, const char *fmt, ...);
+
+#define HIP_TRY(expr)                                                                   \
+  do {                                                                                  \
+    hipError_t e_ = (expr);                                                             \
+    if (e_ != hipSuccess)                                                               \
+      return ::kad::fail(KAD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));   \
+  } while (0)
+
+template <typename T>
+struct DevBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf &) = delete;
+  DevBuf &operator=(const DevBuf &) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t count) {
+    if (count <= n) return hipSuccess;
+    release();
+    hipError_t e = hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T));
+    if (e == hipSuccess) n = count;
+    return e;
+  }
+};
+
+template <typename T>
+struct PinBuf {
+  T *p = nullptr;
+  size_t n = 0;
+  PinBuf() = default;
+  PinBuf(const PinBuf &) = delete;
+  PinBuf &operator=(const PinBuf &) = delete;
+  ~PinBuf() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    n = 0;
+  }
+  hipError_t ensure(size_t count) {
+    if (count <= n) return hipSuccess;
+    release();
+    hipError_t e = hipHostMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T),
+                                 hipHostMallocDefault);
+    if (e == hipSuccess) n = count;
+    return e;
+  }
+};
+
+constexpr uint32_t PI_CAP = 65536;  // candidate edges per slot (power of two)
+constexpr uint32_t DEFAULT_BATCH = 65536;
+
+// Device outputs of one sampler launch, with pinned host mirrors of the small ones.
+struct OutSet {
+  DevBuf<uint32_t> s, t, len, flags, nodes, path;
+  DevBuf<uint64_t> arcs;
+  PinBuf<uint32_t> h_flags, h_len, h_nodes;
+  PinBuf<uint64_t> h_arcs;
+  uint32_t cap = 0, stride = 0;
+  hipEvent_t k0 = nullptr, k1 = nullptr;  // launch start/end (timing)
+  hipEvent_t copied = nullptr;            // sampler done and mirrors landed
+  hipEvent_t reduced = nullptr;           // every reduction reading this set is done
+  OutSet() = default;
+  OutSet(const OutSet &) = delete;
+  OutSet &operator=(const OutSet &) = delete;
+  ~OutSet() {
+    for (hipEvent_t e : {k0, k1, copied, reduced})
+      if (e) (void)hipEventDestroy(e);
+  }
+  // capacity for `cap` samples of path stride `stride`; events created on first use
+  // (`reduced` starts out recorded on `rs`)
+  kad_status ensure(uint32_t cap, uint32_t stride, hipStream_t rs);
+  SampleOut view(uint32_t path_stride) const;
+};
+
+}  // namespace kad
+
+struct kad_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;   // sampling (unless the caller gives one)
+  hipStream_t rstream = nullptr;  // hit reductions and check snapshots
+  uint64_t budget = 0;
+  uint64_t used_graphs = 0;
+  uint32_t cus = 0;
+  int blocks_per_cu = 1;
+  std::atomic<bool> busy{false};  // one user at a time (a call, or a server's engine)
+  // per-slot working state
+  uint32_t slot_n = 0, slots = 0;
+  kad::DevBuf<uint32_t> tag, visit;
+  kad::DevBuf<uint64_t> sig, pi;
+  // per-launch outputs, double-buffered so the next batch can be sampled while the
+  // host checks the current one
+  kad::OutSet outs[2];
+  kad::DevBuf<uint32_t> work, group;
+  kad::DevBuf<uint64_t> count, gmax;
+  kad::DevBuf<uint32_t> bins, bin_count;  // hit-reduction scratch (bin_count all zero between calls)
+  uint64_t bins_cap = 0;
+  kad::PinBuf<uint32_t> h_s, h_t, h_path;
+  kad::PinBuf<uint64_t> h_count;
+  std::vector<hipEvent_t> chunk_ev;
+  // host scratch of kad_run, kept across calls (large fresh allocations fault in pages)
+  std::vector<uint64_t> h_count0;
+  std::vector<double> h_lam_l, h_lam_u, h_L_l, h_L_u, h_bc, h_lo, h_hi;
+  // timing of the sampler launches (HIP events on the launch stream)
+  bool timing = false;
+  uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0;
+  double t_seconds = 0.0;
+  ~kad_ctx() {
+    for (auto e : chunk_ev) (void)hipEventDestroy(e);
+  }
+};
+
+struct kad_graph {
+  kad_ctx *ctx = nullptr;
+  uint32_t n = 0;
+  uint64_t arcs = 0;
+  bool directed = false;
+  std::vector<uint32_t> row, col, rrow, rcol;  // host copies
+  uint32_t *d_row = nullptr, *d_col = nullptr, *d_rrow = nullptr, *d_rcol = nullptr;
+  bool owns_fwd = false, owns_rev = false;
+  uint64_t bytes = 0;
+  std::mutex vd_mu;
+  uint32_t vd = 0;
+  bool vd_exact = false, vd_known = false;
+};
+
+namespace kad {
+
+// Claims the context for the lifetime of the guard; ok() is false when it is in use.
+class CtxClaim {
+ public:
+  explicit CtxClaim(kad_ctx *c) : c_(c) {
+    bool expect = false;
+    ok_ = c_->busy.compare_exchange_strong(expect, true);
+  }
+  ~CtxClaim() {
+    if (ok_) c_->busy.store(false);
+  }
+  bool ok() const { return ok_; }
+  void release_to_owner() { ok_ = false; }  // keep the claim past this guard
+
+ private:
+  kad_ctx *c_;
+  bool ok_ = false;
+};
+
+// Parameter checks shared by every entry point that runs Algorithm 1.
+kad_status validate_params(const kad_graph *g, const kad_params *p);
+
+GraphDev dev_view(const kad_graph *g);
+// The graph's vertex diameter by the library rule, computed once (thread-safe).
+kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact);
+// Slot state for graphs of up to n nodes (reallocates, and synchronises, when it grows).
+kad_status ensure_slots(kad_ctx *ctx, uint32_t n);
+SlotState slot_view(const kad_ctx *ctx);
+
+// Per-node outputs of a finished run (Theorem 1 intervals and the top-k ranking).
+// bc, lo, hi: length n.  With rule_stop the interval is [bc - f, bc + g], else
+// [bc - eps, bc + eps].  group_of (may be empty) maps nodes to classes of identical
+// (L_l, L_u), used to memoise f and g.
+void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule_stop,
+                  double eps, const double *L_l, const double *L_u,
+                  const std::vector<uint32_t> &group_of, double *bc, double *lo, double *hi);
+// Top-k selection: nodes with rank_lo <= k ordered by (count desc, id asc).
+void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
+                 std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,
+                 std::vector<uint32_t> &rhi_sel);
+
+}  // namespace kad

@@ -20,6 +20,8 @@
 // hit_reduce_kernel: the interior nodes of the sampled paths are counted per
 //   node-id tile in an LDS histogram and added to the global counters by the
 //   tile's owner, so the counters see no atomics.
+#include <algorithm>
+
 #include "kad_device.h"
 
 namespace kad {
@@ -35,8 +37,8 @@ constexpr int PI_LDS = 256;  // candidate edges kept in LDS; more spill to the s
 constexpr uint32_t MAX_ATTEMPTS = 64;
 constexpr int MAXLEV = 32;     // levels per side whose node lists are remembered
 constexpr int MATCH_CAP = 48;  // predecessor candidates a backtracking wave keeps in LDS
-constexpr uint64_t SMALL_EXPANSION = 512;
-constexpr uint32_t MAX_HIT_TILES = MAX_HIT_TILES_PUBLIC;  // arcs: up to this, one combined scan per level
+constexpr uint64_t SMALL_EXPANSION = 512;  // arcs: up to this, one combined scan per level
+constexpr uint32_t MAX_HIT_TILES = MAX_HIT_TILES_PUBLIC;
 
 static_assert(CHUNK == 2 * BLOCK, "two staged frontier nodes per thread");
 
@@ -241,7 +243,7 @@ struct Lds {
   uint64_t arcs;
   uint64_t new_deg;
   uint64_t r_lo, r_hi;
-  uint32_t k, s, t;
+  uint32_t k, s, t, seg;
   uint32_t fb[2], fe[2], lvl[2];
   uint32_t nvis, pi_count, flags, win;
   uint32_t ovf_any;
@@ -499,7 +501,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
                           const uint32_t *tag, const uint64_t *sig, const uint32_t *visit,
                           const uint32_t (*seg_lo)[MAXLEV], const uint32_t (*seg_hi)[MAXLEV],
                           MatchScratch &M, uint64_t seed, uint64_t i, uint32_t phase,
-                          uint32_t *path, uint32_t ls, uint32_t &flags) {
+                          uint32_t *path, uint32_t ls, uint32_t base, uint32_t &flags) {
   const uint32_t lane = lane_id();
   const uint32_t *rp = side == 0 ? g.rrow : g.row;
   const uint32_t *cl = side == 0 ? g.rcol : g.col;
@@ -591,17 +593,22 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
       return;
     }
     x = pick;
-    if (lane == 0) path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x;
+    if (lane == 0) path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x + base;
   }
 }
 
-__global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g, SlotState st, uint64_t seed,
-                                                        uint32_t phase, uint64_t first,
-                                                        uint32_t count, uint32_t *work,
-                                                        SampleOut out) {
+// MULTI = false: one graph and seed, sample id first0 + k for launch index k.
+// MULTI = true: launch index k belongs to the segment segs[j] with the largest
+// begin <= k; graph, seed, phase and id come from there.
+template <bool MULTI>
+__global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g0, SlotState st, uint64_t seed0,
+                                                        uint32_t phase0, uint64_t first0,
+                                                        const SampleSeg *__restrict__ segs,
+                                                        uint32_t nseg, uint32_t count,
+                                                        uint32_t *work, SampleOut out) {
   __shared__ Lds L;
   const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
-  const size_t n = g.n;
+  const size_t n = st.n;  // slot capacity
   const size_t slot = blockIdx.x;
   uint32_t *tag = st.tag + slot * n;
   uint64_t *sig = st.sig + slot * n * 2;
@@ -611,11 +618,36 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g, SlotState
   for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
 
   for (;;) {
-    if (tid == 0) L.k = atomicAdd(work, 1u);
+    if (tid == 0) {
+      const uint32_t k = atomicAdd(work, 1u);
+      L.k = k;
+      if (MULTI && k < count) {
+        uint32_t lo = 0, hi = nseg;  // largest j with segs[j].begin <= k
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (segs[mid].begin <= k) lo = mid; else hi = mid;
+        }
+        L.seg = lo;
+      }
+    }
     __syncthreads();
     const uint32_t k = L.k;
     if (k >= count) break;
-    const uint64_t i = first + k;
+    GraphDev g = g0;
+    uint64_t seed = seed0, i = first0 + k;
+    uint32_t phase = phase0, base = 0;
+    if (MULTI) {
+      const SampleSeg &S = segs[__builtin_amdgcn_readfirstlane(L.seg)];
+      g.n = S.n;
+      g.row = S.row;
+      g.col = S.col;
+      g.rrow = S.rrow;
+      g.rcol = S.rcol;
+      seed = S.seed;
+      phase = S.phase;
+      i = S.first + (k - S.begin);
+      base = S.id_base;
+    }
 
     // ---- the pair and the two initial levels
     if (tid == 0) {
@@ -801,14 +833,14 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g, SlotState
           uint32_t fl = 0;
           MatchScratch *scratch = reinterpret_cast<MatchScratch *>(L.pi);
           if (wid == 0) {
-            if (lane == 0) path[ls] = v;
+            if (lane == 0) path[ls] = v + base;
             backtrack(g, 0, v, ls, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[0], seed, i,
-                      phase, path, ls, fl);
+                      phase, path, ls, base, fl);
           }
           if (wid == (NWAVES >= 2 ? 1u : 0u)) {
-            if (lane == 0) path[ls + 1] = w;
+            if (lane == 0) path[ls + 1] = w + base;
             backtrack(g, 1, w, lt, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[1], seed, i,
-                      phase, path, ls, fl);
+                      phase, path, ls, base, fl);
           }
           if (win >= P) fl |= FLAG_CAPACITY;
           if (fl && lane == 0) atomicOr(&L.flags, fl);
@@ -860,13 +892,15 @@ static_assert((uint64_t)MAX_HIT_TILES * HIT_TILE <= (1ull << ENTRY_ID_BITS), "id
 // spp samples per workgroup.  With aggregate, spp * (stride - 2) <= AGG_SLOTS / 2, so
 // the LDS hash is at most half full and every probe sequence ends; without it (paths
 // too long for the hash) every hit is its own entry of multiplicity 1.
-__global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(const uint32_t *path,
-                                                                  const uint32_t *len,
-                                                                  uint32_t stride,
-                                                                  uint32_t nsamp, uint32_t tiles,
-                                                                  uint32_t spp, int aggregate,
-                                                                  uint32_t *bins, uint64_t cap,
-                                                                  uint32_t *bin_count) {
+// pass: PASS_FIXED reserves room in fixed-size bins and writes the entries;
+// PASS_COUNT only adds the workgroup's entries per tile to bin_count; PASS_WRITE
+// writes them at tile_start[t] + (a place reserved through tile_fill[t]).
+enum : int { PASS_FIXED = 0, PASS_COUNT = 1, PASS_WRITE = 2 };
+
+__global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(
+    const uint32_t *path, const uint32_t *len, uint32_t stride, uint32_t nsamp, uint32_t tiles,
+    uint32_t spp, int aggregate, int pass, uint32_t *bins, uint64_t cap, uint32_t *bin_count,
+    const uint32_t *tile_start, uint32_t *tile_fill) {
   __shared__ uint32_t tcount[MAX_HIT_TILES];
   __shared__ uint32_t tbase[MAX_HIT_TILES];
   __shared__ uint32_t akey[AGG_SLOTS];
@@ -875,6 +909,21 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(const uint32_t
   const uint32_t s1 = min(nsamp, s0 + spp);
   const uint32_t entries = (s1 - s0) * stride;
   for (uint32_t t = threadIdx.x; t < tiles; t += HIT_BLOCK) tcount[t] = 0;
+  // reserve room for this workgroup's tcount[t] entries of every tile
+  auto reserve = [&]() {
+    for (uint32_t t = threadIdx.x; t < tiles; t += HIT_BLOCK) {
+      const uint32_t c = tcount[t];
+      if (c) {
+        if (pass == PASS_FIXED) tbase[t] = atomicAdd(&bin_count[t], c);
+        else if (pass == PASS_COUNT) atomicAdd(&bin_count[t], c);
+        else tbase[t] = tile_start[t] + atomicAdd(&tile_fill[t], c);
+      }
+      tcount[t] = 0;
+    }
+  };
+  auto slot_of = [&](uint32_t t, uint32_t pos) -> size_t {
+    return pass == PASS_FIXED ? (size_t)t * cap + pos : (size_t)pos;
+  };
   if (!aggregate) {
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < entries; e += HIT_BLOCK) {
@@ -882,11 +931,8 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(const uint32_t
       if (j >= 1 && j + 1 < len[k]) atomicAdd(&tcount[path[(size_t)k * stride + j] / HIT_TILE], 1u);
     }
     __syncthreads();
-    for (uint32_t t = threadIdx.x; t < tiles; t += HIT_BLOCK) {
-      const uint32_t c = tcount[t];
-      if (c) tbase[t] = atomicAdd(&bin_count[t], c);
-      tcount[t] = 0;
-    }
+    reserve();
+    if (pass == PASS_COUNT) return;
     __syncthreads();
     for (uint32_t e = threadIdx.x; e < entries; e += HIT_BLOCK) {
       const uint32_t k = s0 + e / stride, j = e % stride;
@@ -894,7 +940,7 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(const uint32_t
         const uint32_t v = path[(size_t)k * stride + j];
         const uint32_t t = v / HIT_TILE;
         const uint32_t pos = tbase[t] + atomicAdd(&tcount[t], 1u);
-        bins[(size_t)t * cap + pos] = v | (1u << ENTRY_ID_BITS);
+        bins[slot_of(t, pos)] = v | (1u << ENTRY_ID_BITS);
       }
     }
     return;
@@ -922,11 +968,8 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(const uint32_t
   for (uint32_t q = threadIdx.x; q < AGG_SLOTS; q += HIT_BLOCK)
     if (acnt[q]) atomicAdd(&tcount[akey[q] / HIT_TILE], 1u);
   __syncthreads();
-  for (uint32_t t = threadIdx.x; t < tiles; t += HIT_BLOCK) {
-    const uint32_t c = tcount[t];
-    if (c) tbase[t] = atomicAdd(&bin_count[t], c);
-    tcount[t] = 0;
-  }
+  reserve();
+  if (pass == PASS_COUNT) return;
   __syncthreads();
   for (uint32_t q = threadIdx.x; q < AGG_SLOTS; q += HIT_BLOCK) {
     const uint32_t c = acnt[q];
@@ -934,13 +977,44 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_partition_kernel(const uint32_t
       const uint32_t v = akey[q];
       const uint32_t t = v / HIT_TILE;
       const uint32_t pos = tbase[t] + atomicAdd(&tcount[t], 1u);
-      bins[(size_t)t * cap + pos] = v | (c << ENTRY_ID_BITS);  // pos < cap (see launcher)
+      bins[slot_of(t, pos)] = v | (c << ENTRY_ID_BITS);  // in range (see the launcher)
     }
   }
 }
 
+// Exclusive prefix sum of bin_count[0, tiles) into tile_start (one workgroup).
+static_assert(MAX_HIT_TILES % HIT_BLOCK == 0, "tiles split evenly over the scan's threads");
+__global__ __launch_bounds__(HIT_BLOCK) void hit_scan_kernel(const uint32_t *bin_count,
+                                                             uint32_t tiles,
+                                                             uint32_t *tile_start) {
+  __shared__ uint32_t part[HIT_BLOCK];
+  constexpr uint32_t PER = MAX_HIT_TILES / HIT_BLOCK;
+  const uint32_t b = threadIdx.x * PER;
+  uint32_t sum = 0;
+  for (uint32_t q = 0; q < PER; ++q)
+    if (b + q < tiles) sum += bin_count[b + q];
+  part[threadIdx.x] = sum;
+  __syncthreads();
+  for (uint32_t d = 1; d < HIT_BLOCK; d <<= 1) {  // Hillis-Steele inclusive scan
+    const uint32_t x = threadIdx.x >= d ? part[threadIdx.x - d] : 0u;
+    __syncthreads();
+    part[threadIdx.x] += x;
+    __syncthreads();
+  }
+  uint32_t run = part[threadIdx.x] - sum;
+  for (uint32_t q = 0; q < PER; ++q)
+    if (b + q < tiles) {
+      tile_start[b + q] = run;
+      run += bin_count[b + q];
+    }
+}
+
+// One workgroup per tile: LDS histogram of the tile's entries, then each node's
+// counter is updated by the one thread that claims its histogram cell.
 __global__ __launch_bounds__(HIT_BLOCK) void hit_tile_kernel(const uint32_t *bins, uint64_t cap,
-                                                             uint32_t *bin_count, uint32_t n,
+                                                             uint32_t *bin_count,
+                                                             const uint32_t *tile_start,
+                                                             uint32_t *tile_fill, uint32_t n,
                                                              uint64_t *count, int subtract,
                                                              const uint32_t *group,
                                                              uint64_t *gmax) {
@@ -949,7 +1023,7 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_tile_kernel(const uint32_t *bin
   const uint32_t m = bin_count[t];
   if (m == 0) return;  // uniform for the workgroup
   const uint32_t tile0 = t * HIT_TILE;
-  const uint32_t *bin = bins + (size_t)t * cap;
+  const uint32_t *bin = bins + (tile_start ? (size_t)tile_start[t] : (size_t)t * cap);
   constexpr uint32_t ID_MASK = (1u << ENTRY_ID_BITS) - 1u;
   for (uint32_t b = threadIdx.x; b < HIT_TILE; b += HIT_BLOCK) hist[b] = 0;
   __syncthreads();
@@ -976,12 +1050,49 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_tile_kernel(const uint32_t *bin
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) bin_count[t] = 0;  // ready for the next interval
+  if (threadIdx.x == 0) {  // ready for the next call
+    bin_count[t] = 0;
+    if (tile_fill) tile_fill[t] = 0;
+  }
 }
 
-__global__ void zero_u32_kernel(uint32_t *p, uint32_t count) {
-  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) p[i] = 0;
+__global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    p[i] = value;
+}
+
+__global__ __launch_bounds__(256) void group_max_kernel(const uint64_t *count,
+                                                        const uint32_t *group, uint32_t n,
+                                                        uint64_t *gmax) {
+  const uint32_t stride = gridDim.x * blockDim.x;
+  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
+    const uint64_t c = count[v];
+    unsigned long long *gm = (unsigned long long *)&gmax[group[v]];
+    if (c > __hip_atomic_load(gm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+      atomicMax(gm, (unsigned long long)c);
+  }
+}
+
+__global__ __launch_bounds__(256) void gather_kernel(const GatherDesc *__restrict__ d, uint32_t nd,
+                                                     uint64_t *count_pool,
+                                                     const uint64_t *gmax_pool, uint64_t *snap) {
+  uint32_t lo = 0, hi = nd;  // descriptor with the largest block0 <= blockIdx.x
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (d[mid].block0 <= blockIdx.x) lo = mid; else hi = mid;
+  }
+  const GatherDesc g = d[lo];
+  const uint64_t b = (uint64_t)(blockIdx.x - g.block0) * GATHER_CHUNK;
+  const uint64_t e = min((uint64_t)g.len, b + GATHER_CHUNK);
+  for (uint64_t j = b + threadIdx.x; j < e; j += 256) {
+    if (g.mode == GATHER_GMAX) {
+      snap[g.dst + j] = gmax_pool[g.off + j];
+    } else {
+      snap[g.dst + j] = count_pool[g.off + j];
+      if (g.mode == GATHER_COUNT_ZERO) count_pool[g.off + j] = 0;
+    }
+  }
 }
 
 }  // namespace
@@ -990,8 +1101,20 @@ hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
                           uint32_t grid, hipStream_t stream) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(sampler_kernel, dim3(grid), dim3(BLOCK), 0, stream, g, st, seed, phase,
-                     first, count, work, out);
+  if (st.n < g.n) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(sampler_kernel<false>, dim3(grid), dim3(BLOCK), 0, stream, g, st, seed,
+                     phase, first, (const SampleSeg *)nullptr, 0u, count, work, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const SlotState &st,
+                                uint32_t count, uint32_t *work, const SampleOut &out,
+                                uint32_t grid, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  if (nseg == 0) return hipErrorInvalidValue;
+  GraphDev none{};
+  hipLaunchKernelGGL(sampler_kernel<true>, dim3(grid), dim3(BLOCK), 0, stream, none, st, 0ull,
+                     0u, 0ull, segs, nseg, count, work, out);
   return hipGetLastError();
 }
 
@@ -1003,25 +1126,61 @@ hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t
   const uint32_t tiles = (n + HIT_TILE - 1) / HIT_TILE;
   const uint32_t inner = stride > 2 ? stride - 2 : 1;  // most interior nodes of a path
   if (tiles > MAX_HIT_TILES || (uint64_t)nsamp * inner > hs.cap) return hipErrorInvalidValue;
+  const bool compact = hs.tile_start != nullptr;
+  if (compact && (!hs.tile_fill || hs.cap > 0xFFFFFFFFull)) return hipErrorInvalidValue;
   const bool aggregate = inner <= AGG_SLOTS / 2;
   const uint32_t spp = aggregate ? max(1u, min(SAMPLES_PER_PART, (AGG_SLOTS / 2) / inner)) : 1u;
-  hipLaunchKernelGGL(hit_partition_kernel, dim3((nsamp + spp - 1) / spp), dim3(HIT_BLOCK), 0,
-                     stream, path, len, stride, nsamp, tiles, spp, aggregate ? 1 : 0, hs.bins,
-                     hs.cap, hs.bin_count);
+  const dim3 pgrid((nsamp + spp - 1) / spp);
+  if (!compact) {
+    hipLaunchKernelGGL(hit_partition_kernel, pgrid, dim3(HIT_BLOCK), 0, stream, path, len, stride,
+                       nsamp, tiles, spp, aggregate ? 1 : 0, (int)PASS_FIXED, hs.bins, hs.cap,
+                       hs.bin_count, (const uint32_t *)nullptr, (uint32_t *)nullptr);
+  } else {
+    hipLaunchKernelGGL(hit_partition_kernel, pgrid, dim3(HIT_BLOCK), 0, stream, path, len, stride,
+                       nsamp, tiles, spp, aggregate ? 1 : 0, (int)PASS_COUNT, hs.bins, hs.cap,
+                       hs.bin_count, (const uint32_t *)hs.tile_start, hs.tile_fill);
+    hipLaunchKernelGGL(hit_scan_kernel, dim3(1), dim3(HIT_BLOCK), 0, stream,
+                       (const uint32_t *)hs.bin_count, tiles, hs.tile_start);
+    hipLaunchKernelGGL(hit_partition_kernel, pgrid, dim3(HIT_BLOCK), 0, stream, path, len, stride,
+                       nsamp, tiles, spp, aggregate ? 1 : 0, (int)PASS_WRITE, hs.bins, hs.cap,
+                       hs.bin_count, (const uint32_t *)hs.tile_start, hs.tile_fill);
+  }
   hipLaunchKernelGGL(hit_tile_kernel, dim3(tiles), dim3(HIT_BLOCK), 0, stream, hs.bins, hs.cap,
-                     hs.bin_count, n, count, subtract ? 1 : 0, group, gmax);
+                     hs.bin_count, (const uint32_t *)hs.tile_start, hs.tile_fill, n, count,
+                     subtract ? 1 : 0, group, gmax);
   return hipGetLastError();
 }
 
-hipError_t launch_zero_u32(uint32_t *p, uint32_t count, hipStream_t stream) {
+hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream) {
   if (count == 0) return hipSuccess;
-  hipLaunchKernelGGL(zero_u32_kernel, dim3((count + 255) / 256), dim3(256), 0, stream, p, count);
+  const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 65536);
+  hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream) {
+  return launch_fill_u32(p, count, 0u, stream);
+}
+
+hipError_t launch_group_max(const uint64_t *count, const uint32_t *group, uint32_t n,
+                            uint64_t *gmax, hipStream_t stream) {
+  if (n == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 8192);
+  hipLaunchKernelGGL(group_max_kernel, dim3(blocks), dim3(256), 0, stream, count, group, n, gmax);
+  return hipGetLastError();
+}
+
+hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint64_t *count_pool,
+                         const uint64_t *gmax_pool, uint64_t *snap, hipStream_t stream) {
+  if (nd == 0 || blocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(gather_kernel, dim3(blocks), dim3(256), 0, stream, d, nd, count_pool,
+                     gmax_pool, snap);
   return hipGetLastError();
 }
 
 int sampler_blocks_per_cu() {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel, BLOCK, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<false>, BLOCK, 0) !=
       hipSuccess)
     return 1;
   return blocks > 0 ? blocks : 1;

@@ -15,11 +15,10 @@
 #include <string>
 #include <vector>
 
-#include "../../include/kadabra.h"
-#include "kad_device.h"
+#include "kad_internal.h"
 #include "kad_stats.h"
 
-namespace {
+namespace kad {
 
 thread_local std::string g_error;
 
@@ -33,124 +32,51 @@ kad_status fail(kad_status st, const char *fmt, ...) {
   return st;
 }
 
-#define HIP_TRY(expr)                                                                   \
-  do {                                                                                  \
-    hipError_t e_ = (expr);                                                             \
-    if (e_ != hipSuccess)                                                               \
-      return fail(KAD_EDEVICE, "%s failed: %s", #expr, hipGetErrorString(e_));          \
-  } while (0)
-
-template <typename T>
-struct DevBuf {
-  T *p = nullptr;
-  size_t n = 0;
-  ~DevBuf() { release(); }
-  void release() {
-    if (p) (void)hipFree(p);
-    p = nullptr;
-    n = 0;
+kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t rs) {
+  if (cap < want_cap || stride < want_stride) {
+    const uint32_t c = std::max(want_cap, cap);
+    const uint32_t st = std::max(want_stride, stride);
+    for (auto *b : {&s, &t, &len, &flags, &nodes, &path}) b->release();
+    arcs.release();
+    HIP_TRY(s.ensure(c));
+    HIP_TRY(t.ensure(c));
+    HIP_TRY(len.ensure(c));
+    HIP_TRY(flags.ensure(c));
+    HIP_TRY(nodes.ensure(c));
+    HIP_TRY(arcs.ensure(c));
+    HIP_TRY(path.ensure((size_t)c * st));
+    HIP_TRY(h_flags.ensure(c));
+    HIP_TRY(h_len.ensure(c));
+    HIP_TRY(h_nodes.ensure(c));
+    HIP_TRY(h_arcs.ensure(c));
+    cap = c;
+    stride = st;
   }
-  hipError_t ensure(size_t count) {
-    if (count <= n) return hipSuccess;
-    release();
-    hipError_t e = hipMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T));
-    if (e == hipSuccess) n = count;
-    return e;
+  if (!k0) HIP_TRY(hipEventCreate(&k0));
+  if (!k1) HIP_TRY(hipEventCreate(&k1));
+  if (!copied) HIP_TRY(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
+  if (!reduced) {
+    HIP_TRY(hipEventCreateWithFlags(&reduced, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(reduced, rs));  // nothing pending yet
   }
-};
+  return KAD_OK;
+}
 
-template <typename T>
-struct PinBuf {
-  T *p = nullptr;
-  size_t n = 0;
-  ~PinBuf() { release(); }
-  void release() {
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    n = 0;
-  }
-  hipError_t ensure(size_t count) {
-    if (count <= n) return hipSuccess;
-    release();
-    hipError_t e = hipHostMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T),
-                                 hipHostMallocDefault);
-    if (e == hipSuccess) n = count;
-    return e;
-  }
-};
+SampleOut OutSet::view(uint32_t path_stride) const {
+  SampleOut so;
+  so.s = s.p;
+  so.t = t.p;
+  so.len = len.p;
+  so.flags = flags.p;
+  so.nodes = nodes.p;
+  so.arcs = arcs.p;
+  so.path = path.p;
+  so.stride = path_stride;
+  return so;
+}
 
-constexpr uint32_t PI_CAP = 65536;       // candidate edges per slot (power of two)
-constexpr uint32_t DEFAULT_BATCH = 65536;
-
-}  // namespace
-
-// Device outputs of one sampler launch, with pinned host mirrors of the small ones.
-struct OutSet {
-  DevBuf<uint32_t> s, t, len, flags, nodes, path;
-  DevBuf<uint64_t> arcs;
-  PinBuf<uint32_t> h_flags, h_len, h_nodes;
-  PinBuf<uint64_t> h_arcs;
-  hipEvent_t k0 = nullptr, k1 = nullptr;  // launch start/end (timing)
-  hipEvent_t copied = nullptr;            // sampler done and mirrors landed
-  hipEvent_t reduced = nullptr;           // every reduction reading this set is done
-  ~OutSet() {
-    for (hipEvent_t e : {k0, k1, copied, reduced})
-      if (e) (void)hipEventDestroy(e);
-  }
-};
-
-struct kad_ctx {
-  int device = 0;
-  hipStream_t stream = nullptr;   // sampling (unless the caller gives one)
-  hipStream_t rstream = nullptr;  // hit reductions and check snapshots
-  uint64_t budget = 0;
-  uint64_t used_graphs = 0;
-  uint32_t cus = 0;
-  int blocks_per_cu = 1;
-  // per-slot working state
-  uint32_t slot_n = 0, slots = 0;
-  DevBuf<uint32_t> tag, visit;
-  DevBuf<uint64_t> sig, pi;
-  // per-launch outputs, double-buffered so the next batch can be sampled while the
-  // host checks the current one
-  uint32_t out_cap = 0, out_stride = 0;
-  OutSet outs[2];
-  DevBuf<uint32_t> work, group;
-  DevBuf<uint64_t> count, gmax;
-  DevBuf<uint32_t> bins, bin_count;  // hit-reduction scratch (bin_count all zero between calls)
-  uint64_t bins_cap = 0;
-  PinBuf<uint32_t> h_s, h_t, h_path;
-  PinBuf<uint64_t> h_count;
-  std::vector<hipEvent_t> chunk_ev;
-  // host scratch of kad_run, kept across calls (large fresh allocations fault in pages)
-  std::vector<uint64_t> h_count0;
-  std::vector<double> h_lam_l, h_lam_u, h_L_l, h_L_u, h_bc, h_lo, h_hi;
-  // timing of the sampler launches (HIP events on the launch stream)
-  bool timing = false;
-  uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0;
-  double t_seconds = 0.0;
-  ~kad_ctx() {
-    for (auto e : chunk_ev) (void)hipEventDestroy(e);
-  }
-};
-
-struct kad_graph {
-  kad_ctx *ctx = nullptr;
-  uint32_t n = 0;
-  uint64_t arcs = 0;
-  bool directed = false;
-  std::vector<uint32_t> row, col, rrow, rcol;  // host copies
-  uint32_t *d_row = nullptr, *d_col = nullptr, *d_rrow = nullptr, *d_rcol = nullptr;
-  bool owns_fwd = false, owns_rev = false;
-  uint64_t bytes = 0;
-  uint32_t vd = 0;
-  bool vd_exact = false, vd_known = false;
-};
-
-namespace {
-
-kad::GraphDev dev_view(const kad_graph *g) {
-  kad::GraphDev d;
+GraphDev dev_view(const kad_graph *g) {
+  GraphDev d;
   d.n = g->n;
   d.arcs = g->arcs;
   d.row = g->d_row;
@@ -159,6 +85,148 @@ kad::GraphDev dev_view(const kad_graph *g) {
   d.rcol = g->directed ? g->d_rcol : g->d_col;
   return d;
 }
+
+kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact) {
+  std::lock_guard<std::mutex> lk(g->vd_mu);
+  if (!g->vd_known) {
+    bool ex = false;
+    const uint32_t *rr = g->directed ? g->rrow.data() : g->row.data();
+    const uint32_t *rc = g->directed ? g->rcol.data() : g->col.data();
+    if (vertex_diameter(g->n, g->arcs, g->row.data(), g->col.data(), rr, rc, 1e9, &g->vd, &ex))
+      return fail(KAD_EINVAL, "vertex diameter: bad graph");
+    g->vd_exact = ex;
+    g->vd_known = true;
+  }
+  *vd = g->vd;
+  *exact = g->vd_exact;
+  return KAD_OK;
+}
+
+kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
+  HIP_TRY(hipSetDevice(ctx->device));
+  if (ctx->slot_n >= n && ctx->slots > 0) return KAD_OK;
+  HIP_TRY(hipDeviceSynchronize());  // no launch may still use the old state
+  ctx->tag.release();
+  ctx->visit.release();
+  ctx->sig.release();
+  ctx->pi.release();
+  ctx->slots = 0;
+  ctx->slot_n = 0;
+  const uint32_t want_slots = ctx->cus * (uint32_t)ctx->blocks_per_cu;
+  const uint64_t per_slot = (uint64_t)n * (4 + 4 + 16) + (uint64_t)PI_CAP * 8;
+  // slots take at most 60% of what the budget leaves after the graphs and 1 GiB
+  const uint64_t avail = ctx->budget > ctx->used_graphs + (1024ull << 20)
+                             ? (uint64_t)(0.6 * (double)(ctx->budget - ctx->used_graphs - (1024ull << 20)))
+                             : 0;
+  const uint64_t slots = std::min<uint64_t>(want_slots, avail / per_slot);
+  if (slots == 0)
+    return fail(KAD_ENOMEM, "HBM budget too small for one sampler slot of a %u-node graph", n);
+  HIP_TRY(ctx->tag.ensure((size_t)slots * n));
+  HIP_TRY(ctx->visit.ensure((size_t)slots * n));
+  HIP_TRY(ctx->sig.ensure((size_t)slots * n * 2));
+  HIP_TRY(ctx->pi.ensure((size_t)slots * PI_CAP));
+  HIP_TRY(hipMemsetAsync(ctx->tag.p, 0, (size_t)slots * n * 4, ctx->stream));
+  HIP_TRY(hipMemsetAsync(ctx->sig.p, 0, (size_t)slots * n * 16, ctx->stream));
+  HIP_TRY(hipStreamSynchronize(ctx->stream));
+  ctx->slots = (uint32_t)slots;
+  ctx->slot_n = n;
+  return KAD_OK;
+}
+
+SlotState slot_view(const kad_ctx *ctx) {
+  SlotState st;
+  st.slots = ctx->slots;
+  st.n = ctx->slot_n;
+  st.pi_cap = PI_CAP;
+  st.tag = ctx->tag.p;
+  st.sig = ctx->sig.p;
+  st.visit = ctx->visit.p;
+  st.pi = ctx->pi.p;
+  return st;
+}
+
+void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule,
+                  double eps, const double *L_l, const double *L_u,
+                  const std::vector<uint32_t> &grp_of, double *bc, double *lo, double *hi) {
+  const double T = (double)tau, W = (double)omega;
+  // f and g depend on (count, L_l, L_u) only: memoise per (group, count)
+  struct Memo {
+    uint64_t c;
+    uint32_t grp;
+    bool used;
+    double f, g;
+  };
+  const bool grouped = grp_of.size() == n;
+  parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+    std::vector<Memo> memo(rule && grouped ? 16384 : 0, Memo{0, 0, false, 0.0, 0.0});
+    for (uint32_t v = vb; v < ve; ++v) {
+      bc[v] = (double)cnt[v] / T;
+      if (rule) {
+        double f, g;
+        if (grouped) {
+          const uint32_t gv = grp_of[v];
+          Memo &m = memo[(uint32_t)((cnt[v] * 0x9E3779B97F4A7C15ULL ^ (uint64_t)gv * 0xC2B2AE3D27D4EB4FULL) >> 50)];
+          if (!(m.used && m.c == cnt[v] && m.grp == gv))
+            m = Memo{cnt[v], gv, true, bound_f(bc[v], L_l[v], W, T), bound_g(bc[v], L_u[v], W, T)};
+          f = m.f;
+          g = m.g;
+        } else {
+          f = bound_f(bc[v], L_l[v], W, T);
+          g = bound_g(bc[v], L_u[v], W, T);
+        }
+        lo[v] = bc[v] - f;
+        hi[v] = bc[v] + g;
+      } else {
+        lo[v] = bc[v] - eps;
+        hi[v] = bc[v] + eps;
+      }
+    }
+  });
+}
+
+void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
+                 std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,
+                 std::vector<uint32_t> &rhi_sel) {
+  std::vector<uint32_t> rlo(n), rhi(n);
+  rank_intervals(n, lo, hi, rlo.data(), rhi.data());
+  sel.clear();
+  for (uint32_t v = 0; v < n; ++v)
+    if (rlo[v] <= k) sel.push_back(v);
+  std::sort(sel.begin(), sel.end(), [cnt](uint32_t a, uint32_t b) {
+    return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b;
+  });
+  rlo_sel.resize(sel.size());
+  rhi_sel.resize(sel.size());
+  for (size_t q = 0; q < sel.size(); ++q) {
+    rlo_sel[q] = rlo[sel[q]];
+    rhi_sel[q] = rhi[sel[q]];
+  }
+}
+
+kad_status validate_params(const kad_graph *g, const kad_params *p) {
+  if (!(p->epsilon > 0 && p->epsilon < 1)) return fail(KAD_EINVAL, "epsilon must be in (0,1)");
+  if (!(p->delta > 0 && p->delta < 1)) return fail(KAD_EINVAL, "delta must be in (0,1)");
+  if (p->mode != KAD_ALL_NODES && p->mode != KAD_TOPK) return fail(KAD_EINVAL, "bad mode");
+  if (p->mode == KAD_TOPK && (p->k < 1 || p->k > g->n)) return fail(KAD_EINVAL, "k must be in [1, n]");
+  if (p->reserved != 0) return fail(KAD_EINVAL, "reserved must be 0");
+  if (p->c < 0) return fail(KAD_EINVAL, "c must be positive (or 0 for the default)");
+  if (!(p->balance_eps >= 0 && p->balance_eps < 0.5))
+    return fail(KAD_EINVAL, "balance_eps must be in (0, 0.5) (or 0 for the default)");
+  return KAD_OK;
+}
+
+}  // namespace kad
+
+namespace {
+
+using kad::DevBuf;
+using kad::PinBuf;
+using kad::OutSet;
+using kad::fail;
+using kad::PI_CAP;
+using kad::DEFAULT_BATCH;
+using kad::dev_view;
+using kad::graph_vd;
 
 // Rows sorted strictly ascending, heads in range, no self-loops.
 kad_status check_rows(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32_t *col,
@@ -193,60 +261,10 @@ hipStream_t pick_stream(kad_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx
 // Size the slot state and both output sets for graph size n and `batch` samples of
 // path stride `stride`.
 kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t stride) {
-  HIP_TRY(hipSetDevice(ctx->device));
-  const uint32_t want_slots = ctx->cus * (uint32_t)ctx->blocks_per_cu;
-  if (ctx->slot_n < n || ctx->slots == 0) {
-    ctx->tag.release();
-    ctx->visit.release();
-    ctx->sig.release();
-    ctx->pi.release();
-    const uint64_t per_slot = (uint64_t)n * (4 + 4 + 16) + (uint64_t)PI_CAP * 8;
-    const uint64_t avail = ctx->budget > ctx->used_graphs + (1024ull << 20)
-                               ? ctx->budget - ctx->used_graphs - (1024ull << 20)
-                               : 0;
-    uint64_t slots = std::min<uint64_t>(want_slots, avail / per_slot);
-    if (slots == 0)
-      return fail(KAD_ENOMEM, "HBM budget too small for one sampler slot of a %u-node graph", n);
-    ctx->slots = (uint32_t)slots;
-    ctx->slot_n = n;
-    HIP_TRY(ctx->tag.ensure((size_t)slots * n));
-    HIP_TRY(ctx->visit.ensure((size_t)slots * n));
-    HIP_TRY(ctx->sig.ensure((size_t)slots * n * 2));
-    HIP_TRY(ctx->pi.ensure((size_t)slots * PI_CAP));
-    HIP_TRY(hipMemsetAsync(ctx->tag.p, 0, (size_t)slots * n * 4, ctx->stream));
-    HIP_TRY(hipMemsetAsync(ctx->sig.p, 0, (size_t)slots * n * 16, ctx->stream));
-    HIP_TRY(hipStreamSynchronize(ctx->stream));
-  }
-  if (ctx->out_cap < batch || ctx->out_stride < stride) {
-    const uint32_t cap = std::max(batch, ctx->out_cap);
-    const uint32_t st = std::max(stride, ctx->out_stride);
-    for (OutSet &o : ctx->outs) {
-      for (auto *b : {&o.s, &o.t, &o.len, &o.flags, &o.nodes, &o.path}) b->release();
-      o.arcs.release();
-      HIP_TRY(o.s.ensure(cap));
-      HIP_TRY(o.t.ensure(cap));
-      HIP_TRY(o.len.ensure(cap));
-      HIP_TRY(o.flags.ensure(cap));
-      HIP_TRY(o.nodes.ensure(cap));
-      HIP_TRY(o.arcs.ensure(cap));
-      HIP_TRY(o.path.ensure((size_t)cap * st));
-      HIP_TRY(o.h_flags.ensure(cap));
-      HIP_TRY(o.h_len.ensure(cap));
-      HIP_TRY(o.h_nodes.ensure(cap));
-      HIP_TRY(o.h_arcs.ensure(cap));
-    }
-    ctx->out_cap = cap;
-    ctx->out_stride = st;
-  }
-  for (OutSet &o : ctx->outs) {
-    if (!o.k0) HIP_TRY(hipEventCreate(&o.k0));
-    if (!o.k1) HIP_TRY(hipEventCreate(&o.k1));
-    if (!o.copied) HIP_TRY(hipEventCreateWithFlags(&o.copied, hipEventDisableTiming));
-    if (!o.reduced) {
-      HIP_TRY(hipEventCreateWithFlags(&o.reduced, hipEventDisableTiming));
-      HIP_TRY(hipEventRecord(o.reduced, ctx->rstream));  // nothing pending yet
-    }
-  }
+  kad_status st = kad::ensure_slots(ctx, n);
+  if (st) return st;
+  for (OutSet &o : ctx->outs)
+    if ((st = o.ensure(batch, stride, ctx->rstream))) return st;
   HIP_TRY(ctx->work.ensure(1));
   HIP_TRY(ctx->count.ensure(n));
   HIP_TRY(ctx->h_count.ensure(n));
@@ -255,7 +273,7 @@ kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t st
   if (tiles > kad::MAX_HIT_TILES_PUBLIC)
     return fail(KAD_EINVAL, "graphs above %u nodes are not supported by the hit reduction",
                 kad::MAX_HIT_TILES_PUBLIC * kad::HIT_TILE_IDS);
-  const uint64_t cap = (uint64_t)ctx->out_cap * std::max<uint32_t>(ctx->out_stride - 2, 1);
+  const uint64_t cap = (uint64_t)ctx->outs[0].cap * std::max<uint32_t>(ctx->outs[0].stride - 2, 1);
   if (cap > ctx->bins_cap || tiles * cap > ctx->bins.n) {
     ctx->bins.release();
     HIP_TRY(ctx->bins.ensure(tiles * cap));
@@ -283,28 +301,11 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
                         uint64_t first, uint32_t count, uint32_t stride, int set,
                         hipStream_t stream) {
   OutSet &o = ctx->outs[set];
-  kad::SlotState st;
-  st.slots = ctx->slots;
-  st.n = g->n;
-  st.pi_cap = PI_CAP;
-  st.tag = ctx->tag.p;
-  st.sig = ctx->sig.p;
-  st.visit = ctx->visit.p;
-  st.pi = ctx->pi.p;
-  kad::SampleOut so;
-  so.s = o.s.p;
-  so.t = o.t.p;
-  so.len = o.len.p;
-  so.flags = o.flags.p;
-  so.nodes = o.nodes.p;
-  so.arcs = o.arcs.p;
-  so.path = o.path.p;
-  so.stride = stride;
   HIP_TRY(kad::launch_zero_u32(ctx->work.p, 1, stream));
   const uint32_t grid = std::min<uint32_t>(ctx->slots, count);
   if (ctx->timing) HIP_TRY(hipEventRecord(o.k0, stream));
-  HIP_TRY(kad::launch_sampler(dev_view(g), st, seed, phase, first, count, ctx->work.p, so, grid,
-                              stream));
+  HIP_TRY(kad::launch_sampler(dev_view(g), kad::slot_view(ctx), seed, phase, first, count,
+                              ctx->work.p, o.view(stride), grid, stream));
   if (ctx->timing) HIP_TRY(hipEventRecord(o.k1, stream));
   HIP_TRY(hipMemcpyAsync(o.h_flags.p, o.flags.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(o.h_arcs.p, o.arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
@@ -344,26 +345,11 @@ kad_status finish_batch(kad_ctx *ctx, int set, uint32_t count, uint32_t used) {
   return KAD_OK;
 }
 
-kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact) {
-  if (!g->vd_known) {
-    bool ex = false;
-    const uint32_t *rr = g->directed ? g->rrow.data() : g->row.data();
-    const uint32_t *rc = g->directed ? g->rcol.data() : g->col.data();
-    if (kad::vertex_diameter(g->n, g->arcs, g->row.data(), g->col.data(), rr, rc, 1e9, &g->vd, &ex))
-      return fail(KAD_EINVAL, "vertex diameter: bad graph");
-    g->vd_exact = ex;
-    g->vd_known = true;
-  }
-  *vd = g->vd;
-  *exact = g->vd_exact;
-  return KAD_OK;
-}
-
 }  // namespace
 
 extern "C" {
 
-const char *kad_last_error(void) { return g_error.c_str(); }
+const char *kad_last_error(void) { return kad::g_error.c_str(); }
 
 kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **out) {
   if (!out) return fail(KAD_EINVAL, "out is NULL");
@@ -554,6 +540,8 @@ kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uin
   if (!ctx || !g) return fail(KAD_EINVAL, "NULL context or graph");
   if (path_nodes && !path_off) return fail(KAD_EINVAL, "path_nodes needs path_off");
   if (phase > 255) return fail(KAD_EINVAL, "phase must fit 8 bits");
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
   kad_graph *gm = const_cast<kad_graph *>(g);
   uint32_t vd;
   bool ex;
@@ -605,6 +593,8 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
                           uint64_t first, uint64_t count, uint64_t *count_out,
                           uint64_t *arcs_scanned, void *hip_stream) {
   if (!ctx || !g || !count_out) return fail(KAD_EINVAL, "NULL argument");
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
   kad_graph *gm = const_cast<kad_graph *>(g);
   uint32_t vd;
   bool ex;
@@ -639,17 +629,14 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   using clock = std::chrono::steady_clock;
   const auto t0 = clock::now();
   if (!ctx || !g || !p || !r) return fail(KAD_EINVAL, "NULL argument");
-  if (!(p->epsilon > 0 && p->epsilon < 1)) return fail(KAD_EINVAL, "epsilon must be in (0,1)");
-  if (!(p->delta > 0 && p->delta < 1)) return fail(KAD_EINVAL, "delta must be in (0,1)");
-  if (p->mode != KAD_ALL_NODES && p->mode != KAD_TOPK) return fail(KAD_EINVAL, "bad mode");
-  if (p->mode == KAD_TOPK && (p->k < 1 || p->k > g->n)) return fail(KAD_EINVAL, "k must be in [1, n]");
-  if (p->reserved != 0) return fail(KAD_EINVAL, "reserved must be 0");
+  kad_status st = kad::validate_params(g, p);
+  if (st) return st;
   const double c = p->c > 0 ? p->c : 0.5;
   const double eb = p->balance_eps > 0 ? p->balance_eps : 0.001;
-  if (!(eb < 0.5)) return fail(KAD_EINVAL, "balance_eps must be below 0.5");
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
   kad_graph *gm = const_cast<kad_graph *>(g);
   const uint32_t n = g->n;
-  kad_status st;
 
   uint32_t vd;
   bool vd_exact = false;
@@ -681,7 +668,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       if ((st = finish_batch(ctx, 0, pilot_last, pilot_last))) return st;
       for (uint32_t k = 0; k < pilot_last; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
     }
-    const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->out_cap, alpha - done);
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, alpha - done);
     if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream))) return st;
     HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
                                    ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
@@ -856,55 +843,26 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   double *bc = r->bc ? r->bc : (bcs.resize(n), bcs.data());
   double *lo = r->lower && !topk ? r->lower : (los.resize(n), los.data());
   double *hi = r->upper && !topk ? r->upper : (his.resize(n), his.data());
-  const double T = (double)tau, W = (double)omega;
-  // f and g depend on (count, L_l, L_u) only: memoise per (group, count)
-  struct Memo {
-    uint64_t c;
-    uint32_t grp;
-    bool used;
-    double f, g;
-  };
-  const auto &grp_of = checker.group_of();
-  kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
-    std::vector<Memo> memo(rule ? 16384 : 0, Memo{0, 0, false, 0.0, 0.0});
-    if (r->count) memcpy(r->count + vb, cnt + vb, (size_t)(ve - vb) * 8);
-    for (uint32_t v = vb; v < ve; ++v) {
-      bc[v] = (double)cnt[v] / T;
-      if (rule) {
-        const uint32_t gv = grp_of[v];
-        Memo &m = memo[(uint32_t)((cnt[v] * 0x9E3779B97F4A7C15ULL ^ (uint64_t)gv * 0xC2B2AE3D27D4EB4FULL) >> 50)];
-        if (!(m.used && m.c == cnt[v] && m.grp == gv))
-          m = Memo{cnt[v], gv, true, kad::bound_f(bc[v], L_l[v], W, T), kad::bound_g(bc[v], L_u[v], W, T)};
-        lo[v] = bc[v] - m.f;
-        hi[v] = bc[v] + m.g;
-      } else {
-        lo[v] = bc[v] - p->epsilon;
-        hi[v] = bc[v] + p->epsilon;
-      }
-    }
-  });
+  if (r->count) memcpy(r->count, cnt, (size_t)n * 8);
+  kad::node_outputs(n, cnt, tau, omega, rule, p->epsilon, L_l.data(), L_u.data(),
+                    checker.group_of(), bc, lo, hi);
   if (topk) {
     if (r->lower) memcpy(r->lower, lo, (size_t)n * 8);
     if (r->upper) memcpy(r->upper, hi, (size_t)n * 8);
   }
   r->topk_len = 0;
   kad_status ret = KAD_OK;
-  if (p->mode == KAD_TOPK) {
-    std::vector<uint32_t> rlo(n), rhi(n), sel;
-    kad::rank_intervals(n, lo, hi, rlo.data(), rhi.data());
-    for (uint32_t v = 0; v < n; ++v)
-      if (rlo[v] <= p->k) sel.push_back(v);
-    std::sort(sel.begin(), sel.end(), [cnt](uint32_t a, uint32_t b) {
-      return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b;
-    });
+  if (topk) {
+    std::vector<uint32_t> sel, rlo, rhi;
+    kad::topk_select(n, p->k, cnt, lo, hi, sel, rlo, rhi);
     r->topk_len = (uint32_t)sel.size();
     if (sel.size() > r->topk_cap) {
       ret = fail(KAD_ETOOSMALL, "top-k output needs %zu entries", sel.size());
     } else {
       for (size_t q = 0; q < sel.size(); ++q) {
         if (r->topk_node) r->topk_node[q] = sel[q];
-        if (r->rank_lo) r->rank_lo[q] = rlo[sel[q]];
-        if (r->rank_hi) r->rank_hi[q] = rhi[sel[q]];
+        if (r->rank_lo) r->rank_lo[q] = rlo[q];
+        if (r->rank_hi) r->rank_hi[q] = rhi[q];
       }
     }
   }
