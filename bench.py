@@ -10,6 +10,14 @@ Workload (default): undirected Chung-Lu graph, n = 1,000,000, power-law exponent
 mean degree 20 (2.0e7 arcs), uint32 CSR; all-nodes task, epsilon = 0.005, delta = 0.1,
 seed 1, 65,536 samples per sampler launch.
 
+Other workloads (--workload):
+  er2000    the same run on G(2000, 8/1999)'s largest component, epsilon 0.01;
+  batch256  256 Chung-Lu graphs (seed 1000+i; n log-uniform in [1e3, 1e5], half directed,
+            exponents in [2.1, 2.8], mean degree 4..30), epsilon 0.01, delta 0.1, seed 1:
+            one step = all 256 adaptive runs through the multi-query engine
+            (kad_run_batch); the same 256 runs one after another through kad_run are
+            timed beside it, and the results are checked identical.
+
 Prints one JSON line.  value = sampled shortest paths per second over the timed steps
 (pilot + main-phase samples that enter the result; samples computed past the stopping
 point of the last batch are not counted).  roofline = the sampler kernel's algorithmic
@@ -26,6 +34,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+WORKLOAD_TEXT = {"cl1m": "undirected Chung-Lu, beta 2.3, mean degree 20",
+                 "er2000": "G(2000, 8/1999) seed 1, largest component",
+                 "dcl4m": "directed Chung-Lu, out beta 2.5, in beta 2.1, mean degree 15",
+                 "grid2000": "2000x2000 grid, 5% of edges deleted"}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sampler_cl1m_traffic.json")
 
 
@@ -57,6 +69,89 @@ def cpu_baseline(csr, samples, seed):
             "kind": "oracle", "gteps": float(S.arcs.sum()) / dt / 1e9,
             "sample": f"oracle sample_paths: main-phase ids 0..{samples - 1}, seed {seed}, "
                       f"same graph ({dt:.1f} s)"}
+
+
+def _same_result(a, b):
+    import numpy as np
+    return (a["tau"] == b["tau"] and a["stop_reason"] == b["stop_reason"]
+            and np.array_equal(a["count"], b["count"]) and np.array_equal(a["lower"], b["lower"])
+            and np.array_equal(a["upper"], b["upper"]))
+
+
+def bench_batch(args, torch, gg, kad):
+    """256-graph family: engine (one step = one kad_run_batch of all queries) against
+    the same queries run one after another with kad_run."""
+    ngraphs = 256
+    t0 = time.perf_counter()
+    csrs = [gg.batch_graph(i) for i in range(ngraphs)]
+    print(f"[bench] {ngraphs} graphs: {sum(g.n for g in csrs)} nodes, "
+          f"{sum(g.arcs for g in csrs)} arcs ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    ctx = kad.Context(0)
+    Gs = [kad.Graph(ctx, g) for g in csrs]
+    eps = 0.01
+    kw = dict(epsilon=eps, delta=args.delta, seed=args.seed)
+    params = [dict(kw) for _ in Gs]
+    for w in range(args.warmup):
+        kad.run_batch(ctx, Gs, params)
+        for G in Gs:
+            kad.run(ctx, G, **kw)
+        print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
+    # sequential single runs
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        single = [kad.run(ctx, G, **kw) for G in Gs]
+    torch.cuda.synchronize()
+    seq_s = (time.perf_counter() - t0) / args.steps
+    print(f"[bench] sequential kad_run: {seq_s:.3f} s per pass", file=sys.stderr, flush=True)
+    # the engine
+    ctx.set_timing(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        batch = kad.run_batch(ctx, Gs, params)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    step_s = elapsed / args.steps
+    print(f"[bench] kad_run_batch: {step_s:.3f} s per step", file=sys.stderr, flush=True)
+    identical = all(_same_result(a, b) for a, b in zip(batch, single))
+    paths = sum(r["alpha"] + r["tau"] for r in batch)
+    arcs = sum(r["arcs_scanned"] + r["pilot_arcs_scanned"] for r in batch)
+    alg = algorithmic_bytes(tm["arcs"], tm["nodes"], tm["hits"])
+    avg_launch_s = tm["seconds"] / max(tm["launches"], 1)
+    achieved = alg / max(tm["launches"], 1) / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    out = {
+        "metric": "sampled shortest paths/sec",
+        "value": paths / step_s,
+        "unit": "paths/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u128", "data": "synthetic",
+        "config": {"workload": f"{ngraphs} Chung-Lu graphs (seed 1000+i, n log-uniform in "
+                               f"[1e3,1e5], half directed), all-nodes, epsilon={eps}, "
+                               f"delta={args.delta}, seed {args.seed}, one multi-query engine "
+                               "run"},
+        "gteps": arcs / step_s / 1e9,
+        "time_to_epsilon_s": step_s,
+        "sequential_time_to_epsilon_s": seq_s,
+        "speedup_vs_sequential": seq_s / step_s,
+        "results_identical_to_single_runs": identical,
+        "sampler": {"launches": tm["launches"], "samples": tm["samples"],
+                    "avg_launch_ms": avg_launch_s * 1e3,
+                    "gteps_in_kernel": tm["arcs"] / max(tm["seconds"], 1e-12) / 1e9,
+                    "busy_fraction": tm["seconds"] / elapsed},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sampler_kernel (multi-segment)"},
+    }
+    for G in Gs:
+        G.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
 
 
 def main():
@@ -96,6 +191,8 @@ def main():
         print(json.dumps({"calibration": "device copy", "bytes_read": nbytes,
                           "bytes_written": nbytes}), flush=True)
         return
+    if args.workload == "batch256":
+        return bench_batch(args, torch, gg, kad)
     t0 = time.perf_counter()
     csr = gg.workload(args.workload)
     gen_s = time.perf_counter() - t0
@@ -149,8 +246,9 @@ def main():
         "dtype": "u128",
         "data": "synthetic",
         "config": {
-            "workload": f"undirected Chung-Lu n={csr.n} beta=2.3 mean degree 20 ({csr.arcs} arcs), "
-                        f"all-nodes, epsilon={args.epsilon}, delta={args.delta}, seed {args.seed}, "
+            "workload": f"{WORKLOAD_TEXT.get(args.workload, args.workload)}: n={csr.n}, "
+                        f"{csr.arcs} arcs; all-nodes, epsilon={args.epsilon}, "
+                        f"delta={args.delta}, seed {args.seed}, "
                         f"{args.kernel_batch} samples per sampler launch",
             "graph_sha256": csr.sha256(),
         },

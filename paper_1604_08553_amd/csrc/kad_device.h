@@ -103,10 +103,6 @@ hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream);
 // p[i] = value for i < count.
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 
-// gmax[group[v]] = max(gmax[group[v]], count[v]) for v < n (group values index gmax).
-hipError_t launch_group_max(const uint64_t *count, const uint32_t *group, uint32_t n,
-                            uint64_t *gmax, hipStream_t stream);
-
 // One range copied by launch_gather: snap[dst, dst + len) = src[off, off + len) where src
 // is the group-maximum pool (GATHER_GMAX) or the counter pool (GATHER_COUNT; with
 // GATHER_COUNT_ZERO the counters are also reset to 0).

@@ -15,8 +15,9 @@
 // query live at a fixed offset in a shared counter pool (tile-aligned), so one
 // reduction serves all queries of a layer.  Snapshots are the per-group maxima of
 // the counts (all-nodes task; group = nodes with equal (L_l, L_u), kept current by
-// the reduction itself) or the counts (top-k task, and the first main batch, which
-// is sampled before computeDelta is known).
+// the reduction itself) or the counts (top-k task).  A query's main phase starts once
+// its computeDelta has run (its groups are then known); until then other queries
+// keep the device busy.
 //
 // While tick t runs on the GPU the host evaluates tick t-1's checks.  A query that
 // stops has samples past its stopping point in flight: their hits are subtracted
@@ -51,13 +52,16 @@ constexpr uint64_t TICK_PATH_BYTES = 1ull << 30;  // path buffer of one launch, 
 constexpr uint32_t MAX_LAYERS = 64;            // check intervals of one query per launch
 
 enum class QState { Queued, Pilot, Main, Final, Done };
+// Pilot: pilot samples; PilotLast: the last ones (snapshot = count0, then the
+// counters restart); Main: a check interval, snapshot = group maxima (all-nodes) or
+// counts (MainFull, top-k).
 enum class Kind : uint8_t { Pilot, PilotLast, MainFull, Main };
 
 struct Query {
   uint64_t ticket = 0;
   kad_graph *g = nullptr;
   kad_params p{};
-  kad_result *direct = nullptr;  // filled at completion (kad_run_batch)
+  kad_result *direct = nullptr;  // kad_run_batch: per-node outputs go straight here
   QState st = QState::Queued;
   kad_status status = KAD_OK;
   std::string error;
@@ -83,11 +87,12 @@ struct Query {
   std::unique_ptr<StopChecker> checker;
   std::vector<uint32_t> gdev;  // group ids shifted to the pool (uploaded once)
   double C = 0.0;
-  // results
-  PinBuf<uint64_t> final_counts;
+  // results: o_* point into the caller's arrays (direct) or into the vectors
   hipEvent_t final_ev = nullptr;
   std::vector<uint64_t> count;
   std::vector<double> bc, lo, hi;
+  uint64_t *o_count = nullptr;
+  double *o_bc = nullptr, *o_lo = nullptr, *o_hi = nullptr;
   std::vector<uint32_t> topk, rlo, rhi;
   // times
   clk::time_point t_submit, t_admit, t_pilot, t_delta, t_final, t_done;
@@ -178,6 +183,7 @@ class Engine {
 
   kad_ctx *ctx_;
   DevBuf<uint64_t> count_pool_, gmax_pool_;
+  PinBuf<uint64_t> final_pool_;  // host landing area of stopped queries' counters
   DevBuf<uint32_t> group_pool_;
   std::vector<uint8_t> tile_used_;
   uint32_t tiles_hw_ = 0;  // reductions cover pool tiles [0, tiles_hw_)
@@ -198,6 +204,7 @@ kad_status Engine::init() {
   HIP_TRY(count_pool_.ensure(POOL_IDS));
   HIP_TRY(gmax_pool_.ensure(POOL_IDS));
   HIP_TRY(group_pool_.ensure(POOL_IDS));
+  HIP_TRY(final_pool_.ensure(POOL_IDS));
   HIP_TRY(hipMemsetAsync(count_pool_.p, 0, POOL_IDS * 8, ctx_->rstream));
   HIP_TRY(hipMemsetAsync(group_pool_.p, 0, POOL_IDS * 4, ctx_->rstream));
   HIP_TRY(bin_count_.ensure(POOL_TILES));
@@ -339,29 +346,23 @@ kad_status Engine::build(Tick &t) {
   for (size_t j = 0; j < na; ++j) {
     Query *q = active_[(rr_ + j) % na];
     if (q->status != KAD_OK || q->st == QState::Final) continue;
-    bool pilot_done_here = false;
-    if (q->st == QState::Pilot && q->pilot_launched < q->alpha) {
+    if (q->st == QState::Pilot) {
+      if (q->pilot_launched >= q->alpha) continue;  // waiting for computeDelta
       const uint32_t cnt = room(q, std::min<uint64_t>(q->alpha - q->pilot_launched, TICK_SAMPLES / 2));
       if (cnt == 0) continue;
       const bool last = q->pilot_launched + cnt == q->alpha;
       add(q, 0, last ? Kind::PilotLast : Kind::Pilot, cnt, q->pilot_launched);
       q->pilot_launched += cnt;
-      pilot_done_here = last;
-      if (!last) continue;
+      continue;
     }
-    // main phase: the first batch goes out with the last pilot samples (it does not
-    // depend on them); later ones are sized from the latest check
-    if (q->launched >= q->omega) continue;
+    // main phase: the first batch is half the cap (in check intervals, at most K);
+    // later ones are sized from the latest check
+    if (q->st != QState::Main || q->launched >= q->omega) continue;
     uint64_t want;
-    uint32_t L0 = 0;
     if (!q->main_started) {
-      if (!pilot_done_here && !(q->st == QState::Pilot && q->pilot_launched == q->alpha) &&
-          q->st != QState::Main)
-        continue;
       want = std::min<uint64_t>(q->omega, std::min<uint64_t>(q->K, std::max<uint64_t>(q->B, (q->omega / 2 + q->B - 1) / q->B * q->B)));
-      L0 = pilot_done_here ? 1 : 0;
     } else {
-      if (q->st != QState::Main || q->tau == 0) continue;  // first batch not yet checked
+      if (q->tau == 0) continue;  // first batch not yet checked
       const uint64_t ahead = q->launched - q->tau;
       double w;
       if (q->p.mode == KAD_ALL_NODES && q->worst > 0.0)
@@ -374,11 +375,11 @@ kad_status Engine::build(Tick &t) {
       }
       want = (uint64_t)std::min<double>(std::ceil(w / (double)q->B), (double)(q->K / q->B)) * q->B;
     }
-    const bool full = !q->delta_ready;  // groups unknown at launch: snapshot the counts
-    for (uint32_t L = L0; L < MAX_LAYERS && want > 0 && q->launched < q->omega; ++L) {
+    const Kind kind = q->p.mode == KAD_TOPK ? Kind::MainFull : Kind::Main;
+    for (uint32_t L = 0; L < MAX_LAYERS && want > 0 && q->launched < q->omega; ++L) {
       const uint32_t cnt = (uint32_t)std::min<uint64_t>(q->B, q->omega - q->launched);
       if (room(q, cnt) < cnt) break;
-      add(q, L, full || q->p.mode == KAD_TOPK ? Kind::MainFull : Kind::Main, cnt, q->launched);
+      add(q, L, kind, cnt, q->launched);
       q->launched += cnt;
       q->main_started = true;
       want = want > cnt ? want - cnt : 0;
@@ -559,9 +560,8 @@ kad_status Engine::stop_query(Query *q, Tick &t, size_t at, Tick &other) {
           kad_status st = reduce(other, pc.begin, pc.count, true);
           if (st) return st;
         }
-    HIP_TRY(q->final_counts.ensure(q->n));
-    HIP_TRY(hipMemcpyAsync(q->final_counts.p, count_pool_.p + q->base(), (size_t)q->n * 8,
-                           hipMemcpyDeviceToHost, rs));
+    HIP_TRY(hipMemcpyAsync(final_pool_.p + q->base(), count_pool_.p + q->base(),
+                           (size_t)q->n * 8, hipMemcpyDeviceToHost, rs));
   }
   HIP_TRY(launch_zero_u32((uint32_t *)(count_pool_.p + q->base()), 2ull * q->n, rs));
   HIP_TRY(hipEventRecord(q->final_ev, rs));
@@ -627,8 +627,7 @@ kad_status Engine::process(Tick &t, Tick &other) {
                       q->p.delta, q->eb, q->L_l.data(), q->L_u.data(), &q->C, &groups);
         q->checker.reset(new StopChecker(n, q->p.mode, q->p.k, q->p.epsilon, q->omega,
                                          q->L_l.data(), q->L_u.data(), std::move(groups)));
-        // group ids into the pool, and the group maxima rebuilt from the counters
-        // (the first main batch may already be reduced)
+        // group ids into the pool; the group maxima start at 0 with the counters
         const auto &go = q->checker->group_of();
         q->gdev.resize(n);
         const uint32_t base = (uint32_t)q->base();
@@ -636,7 +635,6 @@ kad_status Engine::process(Tick &t, Tick &other) {
         HIP_TRY(hipMemcpyAsync(group_pool_.p + base, q->gdev.data(), (size_t)n * 4,
                                hipMemcpyHostToDevice, rs));
         HIP_TRY(launch_zero_u32((uint32_t *)(gmax_pool_.p + base), 2ull * q->checker->groups(), rs));
-        HIP_TRY(launch_group_max(count_pool_.p + base, group_pool_.p + base, n, gmax_pool_.p, rs));
         q->delta_ready = true;
         q->st = QState::Main;
         q->t_delta = clk::now();
@@ -651,15 +649,7 @@ kad_status Engine::process(Tick &t, Tick &other) {
       } else if (pc.count == q->B) {
         const uint64_t *sp = t.h_snap.p + pc.snap;
         if (pc.kind == Kind::MainFull) {
-          if (q->p.mode == KAD_ALL_NODES) {
-            // group maxima from the counts, then the same decision as below
-            std::vector<uint64_t> gm(q->checker->groups(), 0);
-            const auto &go = q->checker->group_of();
-            for (uint32_t v = 0; v < q->n; ++v) gm[go[v]] = std::max(gm[go[v]], sp[v]);
-            stop = q->checker->check_group_max(gm.data(), q->tau, &q->worst);
-          } else {
-            stop = q->checker->check(sp, q->tau);
-          }
+          stop = q->checker->check(sp, q->tau);
         } else {
           stop = q->checker->check_group_max(sp, q->tau, &q->worst);
         }
@@ -696,17 +686,22 @@ kad_status Engine::finalize(bool block) {
     }
     if (q->status == KAD_OK) {
       const uint32_t n = q->n;
-      q->count.assign(q->final_counts.p, q->final_counts.p + n);
-      q->final_counts.release();
-      q->bc.resize(n);
-      q->lo.resize(n);
-      q->hi.resize(n);
-      node_outputs(n, q->count.data(), q->tau, q->omega, q->rule, q->p.epsilon, q->L_l.data(),
-                   q->L_u.data(), q->checker->group_of(), q->bc.data(), q->lo.data(),
-                   q->hi.data());
+      kad_result *d = q->direct;
+      auto pick64 = [n](uint64_t *caller, std::vector<uint64_t> &own) {
+        return caller ? caller : (own.resize(n), own.data());
+      };
+      auto pickd = [n](double *caller, std::vector<double> &own) {
+        return caller ? caller : (own.resize(n), own.data());
+      };
+      q->o_count = pick64(d ? d->count : nullptr, q->count);
+      q->o_bc = pickd(d ? d->bc : nullptr, q->bc);
+      q->o_lo = pickd(d ? d->lower : nullptr, q->lo);
+      q->o_hi = pickd(d ? d->upper : nullptr, q->hi);
+      memcpy(q->o_count, final_pool_.p + q->base(), (size_t)n * 8);
+      node_outputs(n, q->o_count, q->tau, q->omega, q->rule, q->p.epsilon, q->L_l.data(),
+                   q->L_u.data(), q->checker->group_of(), q->o_bc, q->o_lo, q->o_hi);
       if (q->p.mode == KAD_TOPK)
-        topk_select(n, q->p.k, q->count.data(), q->lo.data(), q->hi.data(), q->topk, q->rlo,
-                    q->rhi);
+        topk_select(n, q->p.k, q->o_count, q->o_lo, q->o_hi, q->topk, q->rlo, q->rhi);
     }
     release_tiles(q);
     q->checker.reset();
@@ -737,6 +732,19 @@ kad_status Engine::step() {
   return finalize(idle);
 }
 
+kad_status context_engine(kad_ctx *ctx, Engine **out) {
+  if (!ctx->engine) {
+    std::unique_ptr<Engine> e(new Engine(ctx));
+    kad_status st = e->init();
+    if (st) return st;
+    ctx->engine = e.release();
+  }
+  *out = ctx->engine;
+  return KAD_OK;
+}
+
+void destroy_engine(Engine *e) { delete e; }
+
 }  // namespace kad
 
 // ---------------------------------------------------------------- C ABI
@@ -765,10 +773,10 @@ void fill_result(const kad::Query *q, kad_result *r, kad_status *ret) {
   *ret = q->status;
   if (q->status != KAD_OK) return;
   const size_t n = q->n;
-  if (r->count) memcpy(r->count, q->count.data(), n * 8);
-  if (r->bc) memcpy(r->bc, q->bc.data(), n * 8);
-  if (r->lower) memcpy(r->lower, q->lo.data(), n * 8);
-  if (r->upper) memcpy(r->upper, q->hi.data(), n * 8);
+  if (r->count && r->count != q->o_count) memcpy(r->count, q->o_count, n * 8);
+  if (r->bc && r->bc != q->o_bc) memcpy(r->bc, q->o_bc, n * 8);
+  if (r->lower && r->lower != q->o_lo) memcpy(r->lower, q->o_lo, n * 8);
+  if (r->upper && r->upper != q->o_hi) memcpy(r->upper, q->o_hi, n * 8);
   if (q->p.mode == KAD_TOPK) {
     r->topk_len = (uint32_t)q->topk.size();
     if (q->topk.size() > r->topk_cap) {
@@ -787,7 +795,7 @@ void fill_result(const kad::Query *q, kad_result *r, kad_status *ret) {
 
 struct kad_server {
   kad_ctx *ctx = nullptr;
-  std::unique_ptr<kad::Engine> eng;
+  kad::Engine *eng = nullptr;  // the context's engine
   std::thread th;
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -799,6 +807,7 @@ struct kad_server {
   kad_status fatal = KAD_OK;
   std::string fatal_msg;
   uint64_t completed = 0;
+  uint64_t launches0 = 0, samples0 = 0;  // engine totals when the server started
 };
 
 namespace {
@@ -864,9 +873,10 @@ kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *g
   }
   kad::CtxClaim claim(ctx);
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
-  kad::Engine eng(ctx);
-  kad_status st = eng.init();
+  kad::Engine *ep = nullptr;
+  kad_status st = kad::context_engine(ctx, &ep);
   if (st) return st;
+  kad::Engine &eng = *ep;
   std::vector<std::unique_ptr<kad::Query>> qs(count);
   const auto now = kad::clk::now();
   for (uint32_t i = 0; i < count; ++i) {
@@ -874,11 +884,20 @@ kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *g
     qs[i]->ticket = i;
     qs[i]->g = const_cast<kad_graph *>(graphs[i]);
     qs[i]->p = params[i];
+    qs[i]->direct = &results[i];
     qs[i]->t_submit = now;
     eng.enqueue(qs[i].get());
   }
-  while (eng.busy())
-    if ((st = eng.step())) return st;
+  while (eng.busy()) {
+    if ((st = eng.step())) {
+      // the engine may still point at this call's queries: start over next time
+      std::string msg = kad_last_error();
+      kad::destroy_engine(ctx->engine);
+      ctx->engine = nullptr;
+      return fail(st, "%s", msg.c_str());
+    }
+  }
+  (void)eng.take_done();  // every query of this call is done
   kad_status first = KAD_OK;
   std::string first_msg;
   for (uint32_t i = 0; i < count; ++i) {
@@ -903,9 +922,11 @@ kad_status kad_server_create(kad_ctx *ctx, kad_server **out) {
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
   std::unique_ptr<kad_server> sv(new kad_server());
   sv->ctx = ctx;
-  sv->eng.reset(new kad::Engine(ctx));
-  kad_status st = sv->eng->init();
+  kad_status st = kad::context_engine(ctx, &sv->eng);
   if (st) return st;
+  (void)sv->eng->take_done();
+  sv->launches0 = sv->eng->ticks_launched();
+  sv->samples0 = sv->eng->samples_launched();
   sv->th = std::thread(server_loop, sv.get());
   claim.release_to_owner();  // released by kad_server_destroy
   *out = sv.release();
@@ -969,8 +990,8 @@ kad_status kad_server_stats(kad_server *sv, uint64_t *completed, uint64_t *launc
   if (!sv) return kad::fail(KAD_EINVAL, "NULL server");
   std::lock_guard<std::mutex> lk(sv->mu);
   if (completed) *completed = sv->completed;
-  if (launches) *launches = sv->eng->ticks_launched();
-  if (samples) *samples = sv->eng->samples_launched();
+  if (launches) *launches = sv->eng->ticks_launched() - sv->launches0;
+  if (samples) *samples = sv->eng->samples_launched() - sv->samples0;
   return KAD_OK;
 }
 
@@ -987,7 +1008,10 @@ kad_status kad_server_destroy(kad_server *sv) {
   }
   if (sv->th.joinable()) sv->th.join();
   kad_ctx *ctx = sv->ctx;
-  sv->eng.reset();
+  if (sv->fatal) {  // the engine may still point at this server's queries
+    kad::destroy_engine(ctx->engine);
+    ctx->engine = nullptr;
+  }
   delete sv;
   ctx->busy.store(false);
   return KAD_OK;

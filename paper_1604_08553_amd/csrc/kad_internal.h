@@ -95,6 +95,9 @@ struct OutSet {
   SampleOut view(uint32_t path_stride) const;
 };
 
+class Engine;
+void destroy_engine(Engine *e);
+
 }  // namespace kad
 
 struct kad_ctx {
@@ -127,7 +130,10 @@ struct kad_ctx {
   bool timing = false;
   uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0;
   double t_seconds = 0.0;
+  // the multi-query engine (kad_run_batch, kad_server_*), created on first use
+  kad::Engine *engine = nullptr;
   ~kad_ctx() {
+    kad::destroy_engine(engine);
     for (auto e : chunk_ev) (void)hipEventDestroy(e);
   }
 };
@@ -165,6 +171,9 @@ class CtxClaim {
   kad_ctx *c_;
   bool ok_ = false;
 };
+
+// The context's multi-query engine (created, with its counter pools, on first use).
+kad_status context_engine(kad_ctx *ctx, Engine **out);
 
 // Parameter checks shared by every entry point that runs Algorithm 1.
 kad_status validate_params(const kad_graph *g, const kad_params *p);

@@ -1062,18 +1062,6 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value) {
     p[i] = value;
 }
 
-__global__ __launch_bounds__(256) void group_max_kernel(const uint64_t *count,
-                                                        const uint32_t *group, uint32_t n,
-                                                        uint64_t *gmax) {
-  const uint32_t stride = gridDim.x * blockDim.x;
-  for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += stride) {
-    const uint64_t c = count[v];
-    unsigned long long *gm = (unsigned long long *)&gmax[group[v]];
-    if (c > __hip_atomic_load(gm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
-      atomicMax(gm, (unsigned long long)c);
-  }
-}
-
 __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc *__restrict__ d, uint32_t nd,
                                                      uint64_t *count_pool,
                                                      const uint64_t *gmax_pool, uint64_t *snap) {
@@ -1160,14 +1148,6 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStrea
 
 hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream) {
   return launch_fill_u32(p, count, 0u, stream);
-}
-
-hipError_t launch_group_max(const uint64_t *count, const uint32_t *group, uint32_t n,
-                            uint64_t *gmax, hipStream_t stream) {
-  if (n == 0) return hipSuccess;
-  const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 8192);
-  hipLaunchKernelGGL(group_max_kernel, dim3(blocks), dim3(256), 0, stream, count, group, n, gmax);
-  return hipGetLastError();
 }
 
 hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint64_t *count_pool,

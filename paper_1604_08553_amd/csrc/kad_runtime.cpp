@@ -377,6 +377,8 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
 kad_status kad_ctx_destroy(kad_ctx *ctx) {
   if (!ctx) return KAD_OK;
   (void)hipSetDevice(ctx->device);
+  kad::destroy_engine(ctx->engine);  // waits for its work on the context's streams
+  ctx->engine = nullptr;
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   if (ctx->rstream) (void)hipStreamDestroy(ctx->rstream);
   delete ctx;
