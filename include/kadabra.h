@@ -118,7 +118,9 @@ typedef struct {
   uint64_t interval;       /* check interval used */
   uint64_t arcs_scanned;   /* arcs scanned by the main phase's level expansions */
   uint64_t pilot_arcs_scanned;
-  uint64_t overflow_samples; /* samples recomputed with wide path counts */
+  uint64_t overflow_samples; /* samples whose 128-bit path counts overflowed and were sampled
+                                again with multi-limb counts (kad_run: over every launch,
+                                including samples past the stopping point; engine: 0) */
   uint32_t vd, vd_exact;   /* vertex diameter used, and whether it is exact */
   uint32_t stop_reason;    /* KAD_STOP_RULE or KAD_STOP_OMEGA */
   uint32_t n;
@@ -256,6 +258,24 @@ kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint
  * Return 1 (stop), 0 (continue) or a negative kad_status. */
 int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *count, uint64_t tau,
                      uint64_t omega, double epsilon, const double *L_l, const double *L_u);
+
+/* ---------------------------------------------------------------- launch shape */
+
+/* Sampler launch shape used for graph g (by kad_run, kad_sample_paths, kad_hit_counts and
+ * engine launches where g has the most samples): `block` threads per workgroup (64, 128
+ * or 256; one sample per workgroup) and `small_expansion`, the largest level expansion
+ * (in arcs) handled by one combined scan instead of a touch scan plus a discovery scan.
+ * (0, 0) restores the library default (128, 128).  Performance only: results never
+ * depend on the shape. */
+kad_status kad_graph_set_launch(kad_graph *g, uint32_t block, uint32_t small_expansion);
+kad_status kad_graph_get_launch(const kad_graph *g, uint32_t *block, uint32_t *small_expansion);
+
+/* Autotuner: time one sampler launch of `samples` main-phase sample ids (0 = 65,536) of
+ * g with every candidate shape (block 64/128/256 x small_expansion 0/32/128/512; the
+ * faster of two launches each) and keep the fastest as g's shape.  Reports it and its
+ * launch time in seconds (any pointer may be NULL). */
+kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *block,
+                        uint32_t *small_expansion, double *seconds);
 
 /* ---------------------------------------------------------------- measurement hooks */
 

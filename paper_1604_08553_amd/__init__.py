@@ -102,6 +102,9 @@ def lib():
         "kad_server_wait": ([vp, u64, C.POINTER(_Result), dbl], st),
         "kad_server_stats": ([vp, vp, vp, vp], st),
         "kad_server_destroy": ([vp], st),
+        "kad_graph_set_launch": ([vp, u32, u32], st),
+        "kad_graph_get_launch": ([vp, vp, vp], st),
+        "kad_autotune": ([vp, vp, u32, vp, vp, vp], st),
         "kad_ctx_set_timing": ([vp, i32], st),
         "kad_ctx_get_timing": ([vp, vp, vp, vp, vp, vp, vp], st),
         "kad_last_error": ([], C.c_char_p),
@@ -214,6 +217,22 @@ class Graph:
         _check(rc)
         self.handle = h
         self.arcs = arcs
+
+    def set_launch(self, block: int = 0, small_expansion: int = 0):
+        """Sampler launch shape for this graph ((0, 0) = library default)."""
+        _check(lib().kad_graph_set_launch(self.handle, block, small_expansion))
+
+    def launch(self):
+        b, e = C.c_uint32(), C.c_uint32()
+        _check(lib().kad_graph_get_launch(self.handle, C.byref(b), C.byref(e)))
+        return b.value, e.value
+
+    def autotune(self, samples: int = 0) -> dict:
+        """Time every candidate launch shape and keep the fastest (kad_autotune)."""
+        b, e, sec = C.c_uint32(), C.c_uint32(), C.c_double()
+        _check(lib().kad_autotune(self.ctx.handle, self.handle, samples, C.byref(b), C.byref(e),
+                                  C.byref(sec)))
+        return {"block": b.value, "small_expansion": e.value, "seconds": sec.value}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -13,7 +13,14 @@ constexpr uint32_t FLAG_OVERFLOW = 1u;
 constexpr uint32_t FLAG_CAPACITY = 2u;
 constexpr uint32_t FLAG_RNG = 4u;
 
-constexpr int SAMPLER_BLOCK = 128;  // two waves per sample
+// Launch shape of the sampler: workgroup size (64, 128 or 256 threads, one sample
+// per workgroup) and the largest level expansion (in arcs) that takes the combined
+// single scan.  Neither changes any result.
+struct LaunchShape {
+  int block = 128;
+  uint32_t small_exp = 128;
+};
+constexpr int SAMPLER_BLOCKS[3] = {64, 128, 256};
 
 struct GraphDev {
   uint32_t n;
@@ -50,6 +57,19 @@ struct SampleSeg {
   uint32_t id_base;
 };
 
+// Working memory of the wide-count resampling (wide_kernel): the sampler slots' tag,
+// node-list and count arrays are reused (the count array of a slot holds node
+// positions meanwhile); per wide slot a limb arena and level tables of max_lev
+// levels per side.
+struct WideState {
+  uint32_t slots;       // <= the sampler slots
+  uint32_t max_lev;
+  uint64_t arena_limbs; // per slot
+  uint64_t *arena;      // [slots * arena_limbs]
+  uint32_t *lv;         // [slots * 2 * max_lev * 4]
+  uint64_t *lbase;      // [slots * 2 * max_lev]
+};
+
 struct SampleOut {
   uint32_t *s, *t, *len, *flags; // [count]
   uint32_t *nodes;               // [count] nodes reached by the two searches
@@ -62,14 +82,25 @@ struct SampleOut {
 // slot workgroups through *work (must be 0 at launch).
 hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed, uint32_t phase,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
-                          uint32_t grid, hipStream_t stream);
+                          uint32_t grid, const LaunchShape &shape, hipStream_t stream);
 
 // Samples [0, count) of the launch, segment by segment (segs[] in device memory,
 // ascending `begin`, segs[0].begin == 0); st.n is the slot capacity (>= every
 // segment's n).
 hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const SlotState &st,
                                 uint32_t count, uint32_t *work, const SampleOut &out,
-                                uint32_t grid, hipStream_t stream);
+                                uint32_t grid, const LaunchShape &shape, hipStream_t stream);
+
+// Resample, with multi-limb path counts, every sample of the launch whose flags carry
+// FLAG_OVERFLOW (same results as exact arithmetic; FLAG_CAPACITY if the arena or the
+// level tables are too small).  list: room for `count` launch indices; list_count and
+// work: one counter each (set here).  segs == nullptr: the single-graph launch (g,
+// seed, phase, first).
+hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
+                           const SampleSeg *segs, uint32_t nseg, const SlotState &st,
+                           const WideState &ws, uint32_t count, uint32_t *list,
+                           uint32_t *list_count, uint32_t *work, const SampleOut &out,
+                           hipStream_t stream);
 
 // Node tiles of the hit reduction: 8,192 ids each, at most this many tiles (graphs of
 // up to 2^25 nodes).
@@ -120,7 +151,7 @@ constexpr uint32_t GATHER_CHUNK = 4096;  // entries per workgroup
 hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint64_t *count_pool,
                          const uint64_t *gmax_pool, uint64_t *snap, hipStream_t stream);
 
-// Sampler workgroups that fit on the device at once (occupancy query).
-int sampler_blocks_per_cu();
+// Sampler workgroups of `block` threads resident per CU (occupancy query).
+int sampler_blocks_per_cu(int block);
 
 }  // namespace kad

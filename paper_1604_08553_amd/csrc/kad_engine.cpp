@@ -505,11 +505,30 @@ kad_status Engine::launch(Tick &t) {
   HIP_TRY(hipMemcpyAsync(t.d_segs.p, t.h_segs.p, (size_t)np * sizeof(SampleSeg),
                          hipMemcpyHostToDevice, s));
   HIP_TRY(launch_zero_u32(t.work.p, 1, s));
-  const uint32_t grid = std::min<uint32_t>(ctx_->slots, t.total);
+  // launch shape of the graph with the most samples in this launch
+  const kad_graph *major = nullptr;
+  {
+    std::map<const kad_graph *, uint64_t> by_graph;
+    uint64_t most = 0;
+    for (const Piece &pc : t.pieces) {
+      const uint64_t c = by_graph[pc.q->g] += pc.count;
+      if (c > most) {
+        most = c;
+        major = pc.q->g;
+      }
+    }
+  }
+  const LaunchShape shape = graph_shape(major);
+  const uint32_t grid = launch_grid(ctx_, shape, t.total);
   if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k0, s));
   HIP_TRY(launch_sampler_multi(t.d_segs.p, np, slot_view(ctx_), t.total, t.work.p,
-                               t.out.view(t.stride), grid, s));
+                               t.out.view(t.stride), grid, shape, s));
   if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
+  {
+    kad_status st = launch_wide(ctx_, GraphDev{}, 0, 0, 0, t.d_segs.p, np, t.total,
+                                t.out.view(t.stride), t.out.h_nwide.p, s);
+    if (st) return st;
+  }
   HIP_TRY(hipEventRecord(t.sampled, s));
   HIP_TRY(hipMemcpyAsync(t.out.h_flags.p, t.out.flags.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));
   HIP_TRY(hipMemcpyAsync(t.out.h_arcs.p, t.out.arcs.p, (size_t)t.total * 8, hipMemcpyDeviceToHost, s));
@@ -579,6 +598,7 @@ kad_status Engine::process(Tick &t, Tick &other) {
     ctx_->t_launches += 1;
     ctx_->t_samples += t.total;
     ctx_->t_seconds += ms * 1e-3;
+    ctx_->t_wide += t.out.h_nwide.p[0];
     for (uint32_t k = 0; k < t.total; ++k) {
       ctx_->t_arcs += t.out.h_arcs.p[k];
       ctx_->t_nodes += t.out.h_nodes.p[k];
@@ -758,7 +778,7 @@ void fill_result(const kad::Query *q, kad_result *r, kad_status *ret) {
   r->interval = q->B;
   r->arcs_scanned = q->arcs;
   r->pilot_arcs_scanned = q->pilot_arcs;
-  r->overflow_samples = 0;
+  r->overflow_samples = 0;  // not tracked per query by the engine
   r->vd = q->vd;
   r->vd_exact = q->vd_exact ? 1u : 0u;
   r->stop_reason = q->rule ? KAD_STOP_RULE : KAD_STOP_OMEGA;

@@ -76,7 +76,7 @@ constexpr uint32_t DEFAULT_BATCH = 65536;
 struct OutSet {
   DevBuf<uint32_t> s, t, len, flags, nodes, path;
   DevBuf<uint64_t> arcs;
-  PinBuf<uint32_t> h_flags, h_len, h_nodes;
+  PinBuf<uint32_t> h_flags, h_len, h_nodes, h_nwide;  // h_nwide: samples resampled wide
   PinBuf<uint64_t> h_arcs;
   uint32_t cap = 0, stride = 0;
   hipEvent_t k0 = nullptr, k1 = nullptr;  // launch start/end (timing)
@@ -107,12 +107,18 @@ struct kad_ctx {
   uint64_t budget = 0;
   uint64_t used_graphs = 0;
   uint32_t cus = 0;
-  int blocks_per_cu = 1;
+  int blocks_per_cu[3] = {1, 1, 1};  // resident sampler workgroups per CU, per SAMPLER_BLOCKS
   std::atomic<bool> busy{false};  // one user at a time (a call, or a server's engine)
   // per-slot working state
   uint32_t slot_n = 0, slots = 0;
   kad::DevBuf<uint32_t> tag, visit;
   kad::DevBuf<uint64_t> sig, pi;
+  // wide-count resampling of overflowed samples (kad::WideState)
+  uint32_t w_slots = 0, w_max_lev = 0;
+  uint64_t run_wide = 0;  // samples resampled wide during the current kad_run
+  uint64_t w_arena_limbs = 0;
+  kad::DevBuf<uint64_t> w_arena, w_lbase;
+  kad::DevBuf<uint32_t> w_lv, w_list, w_cnt;  // w_cnt: list length, work counter
   // per-launch outputs, double-buffered so the next batch can be sampled while the
   // host checks the current one
   kad::OutSet outs[2];
@@ -128,7 +134,7 @@ struct kad_ctx {
   std::vector<double> h_lam_l, h_lam_u, h_L_l, h_L_u, h_bc, h_lo, h_hi;
   // timing of the sampler launches (HIP events on the launch stream)
   bool timing = false;
-  uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0;
+  uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0, t_wide = 0;
   double t_seconds = 0.0;
   // the multi-query engine (kad_run_batch, kad_server_*), created on first use
   kad::Engine *engine = nullptr;
@@ -150,6 +156,8 @@ struct kad_graph {
   std::mutex vd_mu;
   uint32_t vd = 0;
   bool vd_exact = false, vd_known = false;
+  kad::LaunchShape shape;  // sampler launch shape (kad_graph_set_launch / kad_autotune)
+  bool shape_set = false;
 };
 
 namespace kad {
@@ -184,6 +192,17 @@ kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact);
 // Slot state for graphs of up to n nodes (reallocates, and synchronises, when it grows).
 kad_status ensure_slots(kad_ctx *ctx, uint32_t n);
 SlotState slot_view(const kad_ctx *ctx);
+WideState wide_view(const kad_ctx *ctx);
+// Launch the wide-count resampling after a sampler launch of `count` samples whose
+// outputs are `out` (segs == nullptr: single graph g), and queue the copy of the
+// number of resampled samples into *h_nwide.  No-op without wide slots.
+kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
+                       uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
+                       const SampleOut &out, uint32_t *h_nwide, hipStream_t stream);
+// The graph's launch shape (set or tuned, else a default by size), and the grid of a
+// launch of `count` samples with it.
+LaunchShape graph_shape(const kad_graph *g);
+uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t count);
 
 // Per-node outputs of a finished run (Theorem 1 intervals and the top-k ranking).
 // bc, lo, hi: length n.  With rule_stop the interval is [bc - f, bc + g], else

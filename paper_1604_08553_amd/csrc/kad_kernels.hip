@@ -27,20 +27,17 @@
 namespace kad {
 namespace {
 
-constexpr int BLOCK = SAMPLER_BLOCK;
+// The sampler is compiled for workgroups of 64, 128 and 256 threads (one sample per
+// workgroup); the launcher picks one per launch.
 constexpr int WAVE = 64;
-constexpr int NWAVES = BLOCK / WAVE;
-constexpr int CHUNK = 2 * BLOCK;  // frontier nodes staged in LDS per pass (2 per thread)
 constexpr int FILTER_LOG2 = 15;
 constexpr int FILTER_WORDS = (1 << FILTER_LOG2) / 32;
 constexpr int PI_LDS = 256;  // candidate edges kept in LDS; more spill to the slot buffer
 constexpr uint32_t MAX_ATTEMPTS = 64;
 constexpr int MAXLEV = 32;     // levels per side whose node lists are remembered
 constexpr int MATCH_CAP = 48;  // predecessor candidates a backtracking wave keeps in LDS
-constexpr uint64_t SMALL_EXPANSION = 512;  // arcs: up to this, one combined scan per level
 constexpr uint32_t MAX_HIT_TILES = MAX_HIT_TILES_PUBLIC;
 
-static_assert(CHUNK == 2 * BLOCK, "two staged frontier nodes per thread");
 
 // ------------------------------------------------------------------ Philox4x64-10
 // Salmon et al., SC'11: ten rounds of two 64x64->128 multiplications; the key is
@@ -50,8 +47,8 @@ constexpr uint64_t PH_M1 = 0xCA5A826395121157ULL;
 constexpr uint64_t PH_W0 = 0x9E3779B97F4A7C15ULL;
 constexpr uint64_t PH_W1 = 0xBB67AE8584CAA73BULL;
 
-__device__ __forceinline__ void philox2(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
-                                        uint64_t k0, uint64_t k1, uint64_t &o0, uint64_t &o1) {
+__device__ __forceinline__ void philox4(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                        uint64_t k0, uint64_t k1, uint64_t out[4]) {
 #pragma unroll
   for (int r = 0; r < 10; ++r) {
     if (r > 0) {
@@ -67,8 +64,19 @@ __device__ __forceinline__ void philox2(uint64_t c0, uint64_t c1, uint64_t c2, u
     c2 = y2;
     c3 = lo0;
   }
-  o0 = c0;
-  o1 = c1;
+  out[0] = c0;
+  out[1] = c1;
+  out[2] = c2;
+  out[3] = c3;
+}
+
+// The first two output words (all that draws of up to 128 bits use).
+__device__ __forceinline__ void philox2(uint64_t c0, uint64_t c1, uint64_t c2, uint64_t c3,
+                                        uint64_t k0, uint64_t k1, uint64_t &o0, uint64_t &o1) {
+  uint64_t w[4];
+  philox4(c0, c1, c2, c3, k0, k1, w);
+  o0 = w[0];
+  o1 = w[1];
 }
 
 __device__ __forceinline__ uint64_t stream_word(uint32_t phase, uint32_t purpose, uint64_t step) {
@@ -228,7 +236,10 @@ __device__ __forceinline__ u128 wave_incl_u128(u128 v, bool &ovf) {
   return v;
 }
 
+template <int BLOCK>
 struct Lds {
+  static constexpr int NWAVES = BLOCK / WAVE;
+  static constexpr int CHUNK = 2 * BLOCK;  // frontier nodes staged per pass (2 per thread)
   uint32_t filter[FILTER_WORDS];
   uint64_t pi[PI_LDS];
   uint64_t c_sig_lo[CHUNK];
@@ -261,7 +272,9 @@ struct MatchScratch {
 static_assert(2 * sizeof(MatchScratch) <= PI_LDS * sizeof(uint64_t), "scratch fits the staging area");
 
 // Exclusive block scan of one value per thread; *total gets the block sum.
-__device__ __forceinline__ uint32_t block_excl_u32(Lds &L, uint32_t v, uint32_t &total) {
+template <int BLOCK>
+__device__ __forceinline__ uint32_t block_excl_u32(Lds<BLOCK> &L, uint32_t v, uint32_t &total) {
+  constexpr int NWAVES = BLOCK / WAVE;
   const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
   const uint32_t inc = wave_incl_u32(v);
   if (lane == WAVE - 1) L.red32[wid] = inc;
@@ -279,7 +292,9 @@ __device__ __forceinline__ uint32_t block_excl_u32(Lds &L, uint32_t v, uint32_t 
 }
 
 // Inclusive block scan of 128-bit values; *total gets the block sum.
-__device__ __forceinline__ u128 block_incl_u128(Lds &L, u128 v, u128 &total, bool &ovf) {
+template <int BLOCK>
+__device__ __forceinline__ u128 block_incl_u128(Lds<BLOCK> &L, u128 v, u128 &total, bool &ovf) {
+  constexpr int NWAVES = BLOCK / WAVE;
   const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
   u128 inc = wave_incl_u128(v, ovf);
   if (lane == WAVE - 1) {
@@ -317,12 +332,13 @@ __device__ __forceinline__ uint32_t wave_reserve(bool pred, uint32_t *counter, u
 enum class Scan { Touch, Discover, Both };
 
 // One pass over the rows of frontier [fb, fe) (chunked through LDS).
-template <Scan MODE>
-__device__ __forceinline__ void scan_frontier(Lds &L, const GraphDev &g, uint32_t me,
+template <int BLOCK, Scan MODE>
+__device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, uint32_t me,
                                               uint32_t fb, uint32_t fe, uint32_t *tag,
                                               uint64_t *sig, uint32_t *visit, uint64_t *gpi,
                                               uint32_t pi_cap, uint32_t other_tag,
                                               uint32_t next_tag, bool &ovf) {
+  constexpr int CHUNK = 2 * BLOCK;
   const uint32_t tid = threadIdx.x;
   const uint32_t *rp = me == 0 ? g.row : g.rrow;
   const uint32_t *cl = me == 0 ? g.col : g.rcol;
@@ -467,6 +483,7 @@ __device__ __forceinline__ uint64_t wave_sort64(uint64_t x) {
 }
 
 // In-place ascending bitonic sort of keys[0, M), M a power of two, by the workgroup.
+template <int BLOCK>
 __device__ void bitonic_sort(uint64_t *keys, uint32_t M) {
   for (uint32_t k = 2; k <= M; k <<= 1) {
     for (uint32_t j = k >> 1; j > 0; j >>= 1) {
@@ -600,13 +617,19 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
 // MULTI = false: one graph and seed, sample id first0 + k for launch index k.
 // MULTI = true: launch index k belongs to the segment segs[j] with the largest
 // begin <= k; graph, seed, phase and id come from there.
-template <bool MULTI>
-__global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g0, SlotState st, uint64_t seed0,
+// A level expansion of at most small_exp arcs takes one combined scan; larger ones
+// take a touch scan and, if the searches did not meet, a discovery scan.
+// Occupancy targets: 5 waves per SIMD (VGPR-bound) for 128 and 256 threads; 64-thread
+// workgroups are LDS-bound at 4.
+template <int BLOCK, bool MULTI>
+__global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(GraphDev g0, SlotState st, uint64_t seed0,
                                                         uint32_t phase0, uint64_t first0,
                                                         const SampleSeg *__restrict__ segs,
                                                         uint32_t nseg, uint32_t count,
-                                                        uint32_t *work, SampleOut out) {
-  __shared__ Lds L;
+                                                        uint32_t *work, SampleOut out,
+                                                        uint32_t small_exp) {
+  constexpr int NWAVES = BLOCK / WAVE;
+  __shared__ Lds<BLOCK> L;
   const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
   const size_t n = st.n;  // slot capacity
   const size_t slot = blockIdx.x;
@@ -699,12 +722,12 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g0, SlotStat
       }
       const uint32_t nb = L.nvis;  // the next level starts here
       needed = nb;
-      if (dme <= SMALL_EXPANSION) {
+      if (dme <= (uint64_t)small_exp) {
         // small level: meeting test by tag and discovery in one pass (the nodes it
         // claims are never read if the two searches touched; they are reset anyway)
         __syncthreads();
         bool ovf_next = false;  // counts of the next level matter only if there is one
-        scan_frontier<Scan::Both>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
+        scan_frontier<BLOCK, Scan::Both>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
                                   next_tag, ovf_next);
         if (L.pi_count > 0) {
           met = true;
@@ -717,7 +740,7 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g0, SlotStat
           atomicOr(&L.filter[h >> 5], 1u << (h & 31));
         }
         __syncthreads();
-        scan_frontier<Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
+        scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
                                    next_tag, ovf);
         for (uint32_t j = ob + tid; j < oe; j += BLOCK) L.filter[filter_bit(visit[j]) >> 5] = 0;
         const uint32_t P = L.pi_count;
@@ -726,7 +749,7 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g0, SlotStat
           met = true;
           break;
         }
-        scan_frontier<Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
+        scan_frontier<BLOCK, Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
                                       other_tag, next_tag, ovf);
       }
       __syncthreads();
@@ -773,12 +796,12 @@ __global__ __launch_bounds__(BLOCK, 5) void sampler_kernel(GraphDev g0, SlotStat
         } else if (P <= (uint32_t)PI_LDS) {
           for (uint32_t j = P + tid; j < M; j += BLOCK) L.pi[j] = ~0ULL;
           __syncthreads();
-          bitonic_sort(L.pi, M);
+          bitonic_sort<BLOCK>(L.pi, M);
         } else {
           for (uint32_t j = tid; j < (uint32_t)PI_LDS; j += BLOCK) gpi[j] = L.pi[j];
           for (uint32_t j = P + tid; j < M; j += BLOCK) gpi[j] = ~0ULL;
           __syncthreads();
-          bitonic_sort(gpi, M);
+          bitonic_sort<BLOCK>(gpi, M);
           keys = gpi;
         }
         // ---- sigma_st = sum of sigma_s(v) sigma_t(w); draw r < sigma_st
@@ -1083,26 +1106,481 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc *__restric
   }
 }
 
+// ------------------------------------------------------------------ wide path counts
+// wide_kernel: a sample whose 128-bit path counts overflowed is sampled again with
+// multi-limb counts.  The procedure is the one of sampler_kernel (same pair, same
+// level order, same draws; uniform_below consumes the same words whatever the width),
+// so the result is the one exact arithmetic gives.  One workgroup per sample, working
+// in a sampler slot's tag and node-list arrays (all zero between samples); the counts
+// of level l of a side are stored contiguously, `stride` limbs per node in the order
+// of the node list, with stride = (width of level l-1) + 1, which always holds the
+// sum of the predecessors' counts; the level's width is then the widest count.
+// A new level's counts are pulled from each node's predecessors on the level before,
+// so no two threads write the same count.
+constexpr int WB = 256;
+constexpr int WNW = WB / WAVE;
+
+// Limb arrays: 64-bit limbs, least significant first.
+__device__ uint32_t wide_len(const uint64_t *a, uint32_t w) {
+  while (w > 0 && a[w - 1] == 0) --w;
+  return w;
+}
+
+__device__ int wide_cmp(const uint64_t *a, uint32_t aw, const uint64_t *b, uint32_t bw) {
+  aw = wide_len(a, aw);
+  bw = wide_len(b, bw);
+  if (aw != bw) return aw < bw ? -1 : 1;
+  for (uint32_t j = aw; j-- > 0;)
+    if (a[j] != b[j]) return a[j] < b[j] ? -1 : 1;
+  return 0;
+}
+
+// acc[0, aw) += x[0, xw), xw <= aw; returns the carry out of acc[aw - 1].
+__device__ uint64_t wide_add(uint64_t *acc, uint32_t aw, const uint64_t *x, uint32_t xw) {
+  uint64_t c = 0;
+  for (uint32_t j = 0; j < aw; ++j) {
+    if (j >= xw && c == 0) break;
+    const uint64_t xv = j < xw ? x[j] : 0;
+    const uint64_t s1 = acc[j] + xv;
+    const uint64_t c1 = s1 < xv ? 1u : 0u;
+    const uint64_t s2 = s1 + c;
+    const uint64_t c2 = s2 < c ? 1u : 0u;
+    acc[j] = s2;
+    c = c1 | c2;
+  }
+  return c;
+}
+
+// out[0, aw + bw) = a * b (schoolbook).
+__device__ void wide_mul(const uint64_t *a, uint32_t aw, const uint64_t *b, uint32_t bw,
+                         uint64_t *out) {
+  for (uint32_t j = 0; j < aw + bw; ++j) out[j] = 0;
+  for (uint32_t x = 0; x < aw; ++x) {
+    const uint64_t ax = a[x];
+    if (ax == 0) continue;
+    uint64_t carry = 0;
+    for (uint32_t y = 0; y < bw; ++y) {
+      const uint64_t lo = ax * b[y], hi = __umul64hi(ax, b[y]);
+      uint64_t s = out[x + y] + lo;
+      uint64_t c = s < lo ? 1u : 0u;
+      s += carry;
+      c += s < carry ? 1u : 0u;
+      out[x + y] = s;
+      carry = hi + c;  // the 128-bit sum fits, so this does not wrap
+    }
+    out[x + bw] = carry;
+  }
+}
+
+// r[0, bw) uniform in [0, bound), bound = bound[0, bw) >= 1, by the rule of
+// uniform_below (W = bitlength(bound - 1), ceil(W/64) words per attempt taken from
+// blocks 0, 1, ... of the attempt's counter, least-significant first).  tmp: bw limbs.
+__device__ void uniform_below_wide(const uint64_t *bound, uint32_t bw, uint64_t seed, uint64_t i,
+                                   uint64_t sword, uint64_t *r, uint64_t *tmp,
+                                   uint32_t &flags) {
+  const uint32_t blen = wide_len(bound, bw);
+  for (uint32_t j = 0; j < bw; ++j) r[j] = 0;
+  if (blen == 0) {  // unreachable for consistent counts
+    flags |= FLAG_CAPACITY;
+    return;
+  }
+  if (blen == 1 && bound[0] == 1) return;
+  for (uint32_t j = 0; j < blen; ++j) tmp[j] = bound[j];
+  for (uint32_t j = 0; j < blen; ++j) {  // tmp = bound - 1
+    if (tmp[j] != 0) {
+      tmp[j] -= 1;
+      break;
+    }
+    tmp[j] = ~0ULL;
+  }
+  const uint32_t tw = wide_len(tmp, blen);
+  const uint32_t W = 64 * (tw - 1) + (64 - (uint32_t)__clzll(tmp[tw - 1]));
+  const uint32_t q = (W + 63) / 64;
+  const uint32_t top = W - 64 * (q - 1);
+  const uint64_t mask = top == 64 ? ~0ULL : ((1ULL << top) - 1);
+  for (uint32_t a = 0; a < MAX_ATTEMPTS; ++a) {
+    uint64_t w[4];
+    for (uint32_t j = 0; j < q; ++j) {
+      if ((j & 3) == 0) philox4(i, sword, a, j / 4, seed, 0, w);
+      r[j] = w[j & 3];
+    }
+    r[q - 1] &= mask;
+    if (wide_cmp(r, bw, bound, bw) < 0) return;
+  }
+  flags |= FLAG_RNG;
+  for (uint32_t j = 0; j < bw; ++j) r[j] = 0;
+}
+
+struct WideLds {
+  uint32_t k, seg, s, t, flags;
+  uint32_t lvl[2];
+  uint32_t nvis, pi_count, maxw, maxw_all, sel;
+  uint64_t deg[2], new_deg, arcs, top;
+};
+
+// Level tables of a wide slot: fields of level l of side x at lv[(x * max_lev + l) * 4 + f].
+enum : uint32_t { LV_LO = 0, LV_HI = 1, LV_STRIDE = 2, LV_WIDTH = 3 };
+
+template <bool MULTI>
+__global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *__restrict__ segs,
+                                                  uint32_t nseg, uint64_t seed0, uint32_t phase0,
+                                                  uint64_t first0, SlotState st, WideState ws,
+                                                  const uint32_t *list,
+                                                  const uint32_t *list_count, uint32_t *work,
+                                                  SampleOut out) {
+  __shared__ WideLds L;
+  const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
+  const size_t n = st.n;
+  const size_t slot = blockIdx.x;
+  uint32_t *tag = st.tag + slot * n;
+  uint32_t *visit = st.visit + slot * n;
+  uint32_t *pos = reinterpret_cast<uint32_t *>(st.sig + slot * n * 2);  // zero between samples
+  uint64_t *gpi = st.pi + slot * st.pi_cap;
+  uint64_t *arena = ws.arena + slot * ws.arena_limbs;
+  uint32_t *lv = ws.lv + slot * 2 * (size_t)ws.max_lev * 4;
+  uint64_t *lb = ws.lbase + slot * 2 * (size_t)ws.max_lev;
+  const uint32_t nlist = *list_count;
+  auto LV = [&](uint32_t side, uint32_t l, uint32_t f) -> uint32_t & {
+    return lv[((size_t)side * ws.max_lev + l) * 4 + f];
+  };
+  auto LB = [&](uint32_t side, uint32_t l) -> uint64_t & {
+    return lb[(size_t)side * ws.max_lev + l];
+  };
+  for (;;) {
+    if (tid == 0) {
+      const uint32_t j = atomicAdd(work, 1u);
+      L.k = j < nlist ? list[j] : 0xFFFFFFFFu;
+      if (MULTI && L.k != 0xFFFFFFFFu) {
+        uint32_t lo = 0, hi = nseg;
+        while (hi - lo > 1) {
+          const uint32_t mid = (lo + hi) >> 1;
+          if (segs[mid].begin <= L.k) lo = mid; else hi = mid;
+        }
+        L.seg = lo;
+      }
+    }
+    __syncthreads();
+    const uint32_t k = L.k;
+    if (k == 0xFFFFFFFFu) break;
+    GraphDev g = g0;
+    uint64_t seed = seed0, i = first0 + k;
+    uint32_t phase = phase0, base = 0;
+    if (MULTI) {
+      const SampleSeg &S = segs[__builtin_amdgcn_readfirstlane(L.seg)];
+      g.n = S.n;
+      g.row = S.row;
+      g.col = S.col;
+      g.rrow = S.rrow;
+      g.rcol = S.rcol;
+      seed = S.seed;
+      phase = S.phase;
+      i = S.first + (k - S.begin);
+      base = S.id_base;
+    }
+    if (tid == 0) {
+      uint32_t fl = 0;
+      const uint32_t s = (uint32_t)uniform_below(u128{g.n, 0}, seed, i, stream_word(phase, P_S, 0), fl).lo;
+      const uint32_t tp = (uint32_t)uniform_below(u128{g.n - 1u, 0}, seed, i, stream_word(phase, P_T, 0), fl).lo;
+      const uint32_t t = tp + (tp >= s ? 1u : 0u);
+      L.s = s;
+      L.t = t;
+      tag[s] = 1u;
+      tag[t] = TAG_T | 1u;
+      visit[0] = s;
+      visit[1] = t;
+      pos[s] = 0;
+      pos[t] = 1;
+      arena[0] = 1;
+      arena[1] = 1;
+      for (uint32_t x = 0; x < 2; ++x) {
+        LV(x, 0, LV_LO) = x;
+        LV(x, 0, LV_HI) = x + 1;
+        LV(x, 0, LV_STRIDE) = 1;
+        LV(x, 0, LV_WIDTH) = 1;
+        LB(x, 0) = x;
+      }
+      L.top = 2;
+      L.lvl[0] = 0;
+      L.lvl[1] = 0;
+      L.deg[0] = (uint64_t)(g.row[s + 1] - g.row[s]);
+      L.deg[1] = (uint64_t)(g.rrow[t + 1] - g.rrow[t]);
+      L.arcs = 0;
+      L.nvis = 2;
+      L.flags = fl;
+      L.maxw = 0;
+      L.maxw_all = 1;
+    }
+    __syncthreads();
+    bool met = false;
+    uint32_t needed = 0;
+    for (;;) {
+      const uint32_t me = L.deg[0] <= L.deg[1] ? 0u : 1u;  // ties expand the s side
+      const uint32_t ot = 1u - me;
+      const uint32_t l = L.lvl[me], lo_ = L.lvl[ot];
+      const uint32_t fb = LV(me, l, LV_LO), fe = LV(me, l, LV_HI);
+      const uint32_t other_tag = (ot == 0 ? 0u : TAG_T) | (lo_ + 1);
+      const uint32_t cur_tag = (me == 0 ? 0u : TAG_T) | (l + 1);
+      const uint32_t next_tag = (me == 0 ? 0u : TAG_T) | (l + 2);
+      const uint32_t *rp = me == 0 ? g.row : g.rrow;
+      const uint32_t *cl = me == 0 ? g.col : g.rcol;
+      const uint64_t dme = L.deg[me];
+      const uint32_t nb = L.nvis;
+      needed = nb;
+      __syncthreads();
+      if (tid == 0) {
+        L.arcs += dme;
+        L.pi_count = 0;
+        L.new_deg = 0;
+      }
+      __syncthreads();
+      // ---- pass 1: meeting test and discovery (a wave per frontier node)
+      for (uint32_t f = fb + wid; f < fe; f += WNW) {
+        const uint32_t u = visit[f];
+        const uint32_t rb = rp[u], re = rp[u + 1];
+        for (uint32_t e = rb + lane; e < re; e += WAVE) {
+          const uint32_t w = cl[e];
+          const uint32_t tg = ld_tag(tag + w);
+          if (tg == other_tag) {
+            const uint32_t idx = atomicAdd(&L.pi_count, 1u);
+            const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+            if (idx < st.pi_cap) gpi[idx] = key;
+          } else if (tg == 0 && cas_tag(tag + w, 0u, next_tag) == 0u) {
+            const uint32_t p = atomicAdd(&L.nvis, 1u);
+            visit[p] = w;
+            pos[w] = p;
+            atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)(rp[w + 1] - rp[w]));
+          }
+        }
+      }
+      __syncthreads();
+      if (L.pi_count > 0) {
+        met = true;
+        break;
+      }
+      const uint32_t ne = L.nvis;
+      if (ne == nb) break;  // the expanded side closed: s and t are disconnected
+      const uint32_t wl = LV(me, l, LV_WIDTH), sl = LV(me, l, LV_STRIDE);
+      const uint64_t bl = LB(me, l);
+      const uint32_t stride = wl + 1;
+      const uint64_t nbase = L.top;
+      if (l + 1 >= ws.max_lev || nbase + (uint64_t)(ne - nb) * stride > ws.arena_limbs) {
+        if (tid == 0) L.flags |= FLAG_CAPACITY;
+        break;
+      }
+      // ---- pass 2: counts of the new level, pulled from the level before
+      const uint32_t *pr = me == 0 ? g.rrow : g.row;
+      const uint32_t *pc = me == 0 ? g.rcol : g.col;
+      uint32_t used_max = 0;
+      for (uint32_t q = nb + tid; q < ne; q += WB) {
+        const uint32_t w = visit[q];
+        uint64_t *acc = arena + nbase + (size_t)(q - nb) * stride;
+        for (uint32_t j = 0; j < stride; ++j) acc[j] = 0;
+        for (uint32_t e = pr[w]; e < pr[w + 1]; ++e) {
+          const uint32_t u = pc[e];
+          if (ld_tag(tag + u) == cur_tag)
+            (void)wide_add(acc, stride, arena + bl + (size_t)(pos[u] - fb) * sl, wl);
+        }
+        used_max = max(used_max, wide_len(acc, stride));
+      }
+      atomicMax(&L.maxw, used_max);
+      __syncthreads();
+      if (tid == 0) {
+        const uint32_t wn = max(L.maxw, 1u);
+        LV(me, l + 1, LV_LO) = nb;
+        LV(me, l + 1, LV_HI) = ne;
+        LV(me, l + 1, LV_STRIDE) = stride;
+        LV(me, l + 1, LV_WIDTH) = wn;
+        LB(me, l + 1) = nbase;
+        L.top = nbase + (uint64_t)(ne - nb) * stride;
+        L.deg[me] = L.new_deg;
+        L.lvl[me] = l + 1;
+        L.maxw = 0;
+        L.maxw_all = max(L.maxw_all, wn);
+      }
+      __syncthreads();
+    }
+    __syncthreads();
+    const uint32_t ls = L.lvl[0], lt = L.lvl[1];
+    uint32_t len = 0;
+    uint32_t *path = out.path + (size_t)k * out.stride;
+    if (met && L.flags == 0) {
+      const uint32_t P = L.pi_count;
+      const uint32_t ws_ = LV(0, ls, LV_WIDTH), wt_ = LV(1, lt, LV_WIDTH);
+      const uint32_t pw = ws_ + wt_;
+      const uint32_t tw = max(pw, L.maxw_all) + 2;  // totals, draws, running sums
+      const uint64_t prod = L.top;
+      const uint64_t need = prod + (uint64_t)P * pw + 4ull * tw;
+      if (P > st.pi_cap || ls + lt + 2 > out.stride || need > ws.arena_limbs) {
+        if (tid == 0) L.flags |= FLAG_CAPACITY;
+      } else {
+        // ---- candidate edges in canonical order, and their weights
+        uint32_t M = 1;
+        while (M < P) M <<= 1;
+        for (uint32_t j = P + tid; j < M; j += WB) gpi[j] = ~0ULL;
+        __syncthreads();
+        bitonic_sort<WB>(gpi, M);
+        const uint32_t so = LV(0, ls, LV_LO), ss = LV(0, ls, LV_STRIDE);
+        const uint32_t to = LV(1, lt, LV_LO), ts = LV(1, lt, LV_STRIDE);
+        const uint64_t sb = LB(0, ls), tb = LB(1, lt);
+        for (uint32_t j = tid; j < P; j += WB) {
+          const uint64_t key = gpi[j];
+          const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
+          wide_mul(arena + sb + (size_t)(pos[v] - so) * ss, ws_,
+                   arena + tb + (size_t)(pos[w] - to) * ts, wt_, arena + prod + (size_t)j * pw);
+        }
+        __syncthreads();
+        if (tid == 0) {
+          uint64_t *total = arena + prod + (size_t)P * pw;
+          uint64_t *r = total + tw, *tmp = r + tw, *acc = tmp + tw;
+          uint32_t fl = 0;
+          for (uint32_t j = 0; j < tw; ++j) total[j] = 0;
+          for (uint32_t j = 0; j < P; ++j) (void)wide_add(total, tw, arena + prod + (size_t)j * pw, pw);
+          uniform_below_wide(total, tw, seed, i, stream_word(phase, P_EDGE, 0), r, tmp, fl);
+          uint32_t sel = P;
+          for (uint32_t j = 0; j < tw; ++j) acc[j] = 0;
+          for (uint32_t j = 0; j < P && fl == 0; ++j) {
+            (void)wide_add(acc, tw, arena + prod + (size_t)j * pw, pw);
+            if (wide_cmp(acc, tw, r, tw) > 0) {
+              sel = j;
+              break;
+            }
+          }
+          if (sel >= P) fl |= FLAG_CAPACITY;
+          // ---- backtracking, one side after the other (section 4)
+          for (uint32_t side = 0; side < 2 && fl == 0; ++side) {
+            const uint64_t key = gpi[sel];
+            uint32_t x = side == 0 ? (uint32_t)(key >> 32) : (uint32_t)key;
+            const uint32_t lev = side == 0 ? ls : lt;
+            path[side == 0 ? ls : ls + 1] = x + base;
+            const uint32_t *brp = side == 0 ? g.rrow : g.row;
+            const uint32_t *bcl = side == 0 ? g.rcol : g.col;
+            for (uint32_t j = lev; j >= 1 && fl == 0; --j) {
+              const uint32_t xw = LV(side, j, LV_WIDTH);
+              const uint64_t *sx = arena + LB(side, j) +
+                                   (size_t)(pos[x] - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
+              uniform_below_wide(sx, xw, seed, i,
+                                 stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j), r, tmp, fl);
+              const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1
+              const uint32_t pwid = LV(side, j - 1, LV_WIDTH), plo = LV(side, j - 1, LV_LO);
+              const uint32_t pst = LV(side, j - 1, LV_STRIDE);
+              const uint64_t pb = LB(side, j - 1);
+              for (uint32_t q = 0; q < tw; ++q) acc[q] = 0;
+              uint32_t pick = 0xFFFFFFFFu;
+              for (uint32_t e = brp[x]; e < brp[x + 1] && fl == 0; ++e) {
+                const uint32_t u = bcl[e];
+                if (ld_tag(tag + u) != want) continue;
+                (void)wide_add(acc, tw, arena + pb + (size_t)(pos[u] - plo) * pst, pwid);
+                if (wide_cmp(acc, tw, r, xw) > 0) {
+                  pick = u;
+                  break;
+                }
+              }
+              if (pick == 0xFFFFFFFFu) {
+                fl |= FLAG_CAPACITY;  // unreachable for consistent counts
+                break;
+              }
+              x = pick;
+              path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x + base;
+            }
+          }
+          L.flags |= fl;
+        }
+        __syncthreads();
+        if (L.flags == 0) len = ls + lt + 2;
+      }
+    }
+    __syncthreads();
+    if (tid == 0) {
+      out.s[k] = L.s;
+      out.t[k] = L.t;
+      out.len[k] = L.flags ? 0u : len;
+      out.arcs[k] = L.arcs;
+      out.flags[k] = L.flags;
+      out.nodes[k] = needed;
+    }
+    // ---- restore the slot's all-zero state
+    const uint32_t nv = L.nvis;
+    for (uint32_t j = tid; j < nv; j += WB) {
+      const uint32_t v = visit[j];
+      tag[v] = 0;
+      pos[v] = 0;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void overflow_list_kernel(const uint32_t *flags, uint32_t count, uint32_t *list,
+                                     uint32_t *list_count) {
+  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < count && (flags[k] & FLAG_OVERFLOW)) list[atomicAdd(list_count, 1u)] = k;
+}
+
 }  // namespace
+
+template <bool MULTI>
+hipError_t launch_sampler_variant(int block, uint32_t grid, hipStream_t stream, const GraphDev &g,
+                                  const SlotState &st, uint64_t seed, uint32_t phase,
+                                  uint64_t first, const SampleSeg *segs, uint32_t nseg,
+                                  uint32_t count, uint32_t *work, const SampleOut &out,
+                                  uint32_t small_exp) {
+  switch (block) {
+    case 64:
+      hipLaunchKernelGGL((sampler_kernel<64, MULTI>), dim3(grid), dim3(64), 0, stream, g, st,
+                         seed, phase, first, segs, nseg, count, work, out, small_exp);
+      break;
+    case 128:
+      hipLaunchKernelGGL((sampler_kernel<128, MULTI>), dim3(grid), dim3(128), 0, stream, g, st,
+                         seed, phase, first, segs, nseg, count, work, out, small_exp);
+      break;
+    case 256:
+      hipLaunchKernelGGL((sampler_kernel<256, MULTI>), dim3(grid), dim3(256), 0, stream, g, st,
+                         seed, phase, first, segs, nseg, count, work, out, small_exp);
+      break;
+    default:
+      return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed, uint32_t phase,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
-                          uint32_t grid, hipStream_t stream) {
+                          uint32_t grid, const LaunchShape &shape, hipStream_t stream) {
   if (count == 0) return hipSuccess;
-  if (st.n < g.n) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(sampler_kernel<false>, dim3(grid), dim3(BLOCK), 0, stream, g, st, seed,
-                     phase, first, (const SampleSeg *)nullptr, 0u, count, work, out);
-  return hipGetLastError();
+  if (st.n < g.n || grid > st.slots) return hipErrorInvalidValue;
+  return launch_sampler_variant<false>(shape.block, grid, stream, g, st, seed, phase, first,
+                                       nullptr, 0u, count, work, out, shape.small_exp);
 }
 
 hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const SlotState &st,
                                 uint32_t count, uint32_t *work, const SampleOut &out,
-                                uint32_t grid, hipStream_t stream) {
+                                uint32_t grid, const LaunchShape &shape, hipStream_t stream) {
   if (count == 0) return hipSuccess;
-  if (nseg == 0) return hipErrorInvalidValue;
+  if (nseg == 0 || grid > st.slots) return hipErrorInvalidValue;
   GraphDev none{};
-  hipLaunchKernelGGL(sampler_kernel<true>, dim3(grid), dim3(BLOCK), 0, stream, none, st, 0ull,
-                     0u, 0ull, segs, nseg, count, work, out);
+  return launch_sampler_variant<true>(shape.block, grid, stream, none, st, 0ull, 0u, 0ull, segs,
+                                      nseg, count, work, out, shape.small_exp);
+}
+
+hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
+                           const SampleSeg *segs, uint32_t nseg, const SlotState &st,
+                           const WideState &ws, uint32_t count, uint32_t *list,
+                           uint32_t *list_count, uint32_t *work, const SampleOut &out,
+                           hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  if (ws.slots == 0 || ws.slots > st.slots || !ws.arena) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, stream, list_count, (uint64_t)2, 0u);
+  hipLaunchKernelGGL(overflow_list_kernel, dim3((count + 255) / 256), dim3(256), 0, stream,
+                     (const uint32_t *)out.flags, count, list, list_count);
+  // work == list_count + 1 (zeroed above)
+  if (work != list_count + 1) return hipErrorInvalidValue;
+  if (segs)
+    hipLaunchKernelGGL(wide_kernel<true>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
+                       seed, phase, first, st, ws, (const uint32_t *)list,
+                       (const uint32_t *)list_count, work, out);
+  else
+    hipLaunchKernelGGL(wide_kernel<false>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
+                       seed, phase, first, st, ws, (const uint32_t *)list,
+                       (const uint32_t *)list_count, work, out);
   return hipGetLastError();
 }
 
@@ -1158,11 +1636,16 @@ hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint
   return hipGetLastError();
 }
 
-int sampler_blocks_per_cu() {
+int sampler_blocks_per_cu(int block) {
   int blocks = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<false>, BLOCK, 0) !=
-      hipSuccess)
-    return 1;
+  hipError_t e = hipErrorInvalidValue;
+  if (block == 64)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<64, false>, 64, 0);
+  else if (block == 128)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<128, false>, 128, 0);
+  else if (block == 256)
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<256, false>, 256, 0);
+  if (e != hipSuccess) return 1;
   return blocks > 0 ? blocks : 1;
 }
 

@@ -46,6 +46,7 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
     HIP_TRY(arcs.ensure(c));
     HIP_TRY(path.ensure((size_t)c * st));
     HIP_TRY(h_flags.ensure(c));
+    HIP_TRY(h_nwide.ensure(1));
     HIP_TRY(h_len.ensure(c));
     HIP_TRY(h_nodes.ensure(c));
     HIP_TRY(h_arcs.ensure(c));
@@ -112,7 +113,8 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   ctx->pi.release();
   ctx->slots = 0;
   ctx->slot_n = 0;
-  const uint32_t want_slots = ctx->cus * (uint32_t)ctx->blocks_per_cu;
+  const uint32_t want_slots =
+      ctx->cus * (uint32_t)*std::max_element(ctx->blocks_per_cu, ctx->blocks_per_cu + 3);
   const uint64_t per_slot = (uint64_t)n * (4 + 4 + 16) + (uint64_t)PI_CAP * 8;
   // slots take at most 60% of what the budget leaves after the graphs and 1 GiB
   const uint64_t avail = ctx->budget > ctx->used_graphs + (1024ull << 20)
@@ -130,7 +132,79 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   ctx->slots = (uint32_t)slots;
   ctx->slot_n = n;
+  // wide-count resampling: up to 16 workgroups, each with a limb arena of up to 1 GiB,
+  // in at most half of what the budget leaves after the sampler slots
+  ctx->w_arena.release();
+  ctx->w_lv.release();
+  ctx->w_lbase.release();
+  ctx->w_slots = 0;
+  const uint64_t slot_bytes = slots * per_slot;
+  const uint64_t left = ctx->budget > ctx->used_graphs + slot_bytes + (1024ull << 20)
+                            ? ctx->budget - ctx->used_graphs - slot_bytes - (1024ull << 20)
+                            : 0;
+  const uint32_t w_slots = (uint32_t)std::min<uint64_t>(16, slots);
+  const uint32_t max_lev = 16384;
+  const uint64_t tables = (uint64_t)w_slots * 2 * max_lev * (16 + 8);
+  uint64_t limbs = left / 2 > tables ? (left / 2 - tables) / (8ull * w_slots) : 0;
+  limbs = std::min<uint64_t>(limbs, 1ull << 27);
+  if (limbs >= (1ull << 20)) {
+    if (ctx->w_arena.ensure((size_t)w_slots * limbs) == hipSuccess &&
+        ctx->w_lv.ensure((size_t)w_slots * 2 * max_lev * 4) == hipSuccess &&
+        ctx->w_lbase.ensure((size_t)w_slots * 2 * max_lev) == hipSuccess &&
+        ctx->w_cnt.ensure(2) == hipSuccess) {
+      ctx->w_slots = w_slots;
+      ctx->w_max_lev = max_lev;
+      ctx->w_arena_limbs = limbs;
+    } else {
+      (void)hipGetLastError();
+      ctx->w_arena.release();
+      ctx->w_lv.release();
+      ctx->w_lbase.release();
+    }
+  }
   return KAD_OK;
+}
+
+WideState wide_view(const kad_ctx *ctx) {
+  WideState w;
+  w.slots = ctx->w_slots;
+  w.max_lev = ctx->w_max_lev;
+  w.arena_limbs = ctx->w_arena_limbs;
+  w.arena = ctx->w_arena.p;
+  w.lv = ctx->w_lv.p;
+  w.lbase = ctx->w_lbase.p;
+  return w;
+}
+
+kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
+                       uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
+                       const SampleOut &out, uint32_t *h_nwide, hipStream_t stream) {
+  if (ctx->w_slots == 0 || count == 0) {
+    *h_nwide = 0;
+    return KAD_OK;
+  }
+  if (ctx->w_list.n < count) {
+    HIP_TRY(hipDeviceSynchronize());  // the old list may still be read
+    ctx->w_list.release();
+    HIP_TRY(ctx->w_list.ensure(std::max<size_t>(count, 1u << 18)));
+  }
+  HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, slot_view(ctx), wide_view(ctx),
+                          count, ctx->w_list.p, ctx->w_cnt.p, ctx->w_cnt.p + 1, out, stream));
+  HIP_TRY(hipMemcpyAsync(h_nwide, ctx->w_cnt.p, 4, hipMemcpyDeviceToHost, stream));
+  return KAD_OK;
+}
+
+LaunchShape graph_shape(const kad_graph *g) {
+  if (g->shape_set) return g->shape;
+  return LaunchShape{};
+}
+
+uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t count) {
+  int per_cu = 1;
+  for (int j = 0; j < 3; ++j)
+    if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx->blocks_per_cu[j];
+  const uint64_t resident = (uint64_t)ctx->cus * (uint64_t)per_cu;
+  return (uint32_t)std::min<uint64_t>(std::min<uint64_t>(ctx->slots, resident), count);
 }
 
 SlotState slot_view(const kad_ctx *ctx) {
@@ -302,11 +376,15 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
                         hipStream_t stream) {
   OutSet &o = ctx->outs[set];
   HIP_TRY(kad::launch_zero_u32(ctx->work.p, 1, stream));
-  const uint32_t grid = std::min<uint32_t>(ctx->slots, count);
-  if (ctx->timing) HIP_TRY(hipEventRecord(o.k0, stream));
+  const kad::LaunchShape shape = kad::graph_shape(g);
+  const uint32_t grid = kad::launch_grid(ctx, shape, count);
+  HIP_TRY(hipEventRecord(o.k0, stream));
   HIP_TRY(kad::launch_sampler(dev_view(g), kad::slot_view(ctx), seed, phase, first, count,
-                              ctx->work.p, o.view(stride), grid, stream));
-  if (ctx->timing) HIP_TRY(hipEventRecord(o.k1, stream));
+                              ctx->work.p, o.view(stride), grid, shape, stream));
+  HIP_TRY(hipEventRecord(o.k1, stream));
+  kad_status st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count,
+                                   o.view(stride), o.h_nwide.p, stream);
+  if (st) return st;
   HIP_TRY(hipMemcpyAsync(o.h_flags.p, o.flags.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(o.h_arcs.p, o.arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
   if (ctx->timing) {
@@ -322,12 +400,14 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
 kad_status finish_batch(kad_ctx *ctx, int set, uint32_t count, uint32_t used) {
   OutSet &o = ctx->outs[set];
   HIP_TRY(hipEventSynchronize(o.copied));
+  ctx->run_wide += o.h_nwide.p[0];
   if (ctx->timing) {
     float ms = 0.f;
     HIP_TRY(hipEventElapsedTime(&ms, o.k0, o.k1));
     ctx->t_launches += 1;
     ctx->t_samples += count;
     ctx->t_seconds += ms * 1e-3;
+    ctx->t_wide += o.h_nwide.p[0];
     for (uint32_t k = 0; k < count; ++k) {
       ctx->t_arcs += o.h_arcs.p[k];
       ctx->t_nodes += o.h_nodes.p[k];
@@ -366,7 +446,7 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   c->cus = (uint32_t)prop.multiProcessorCount;
-  c->blocks_per_cu = kad::sampler_blocks_per_cu();
+  for (int j = 0; j < 3; ++j) c->blocks_per_cu[j] = kad::sampler_blocks_per_cu(kad::SAMPLER_BLOCKS[j]);
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
@@ -639,6 +719,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
   kad_graph *gm = const_cast<kad_graph *>(g);
   const uint32_t n = g->n;
+  ctx->run_wide = 0;
 
   uint32_t vd;
   bool vd_exact = false;
@@ -832,7 +913,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   r->interval = B;
   r->arcs_scanned = arcs;
   r->pilot_arcs_scanned = pilot_arcs;
-  r->overflow_samples = 0;
+  r->overflow_samples = ctx->run_wide;
   r->vd = vd;
   r->vd_exact = vd_exact ? 1u : 0u;
   r->stop_reason = rule ? KAD_STOP_RULE : KAD_STOP_OMEGA;
@@ -878,6 +959,83 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   r->seconds_delta = secs(t_pilot, t_delta);
   r->seconds_main = secs(t_delta, t_main);
   return ret;
+}
+
+// ---------------------------------------------------------------- launch shape
+
+kad_status kad_graph_set_launch(kad_graph *g, uint32_t block, uint32_t small_expansion) {
+  if (!g) return fail(KAD_EINVAL, "NULL graph");
+  if (block == 0 && small_expansion == 0) {
+    g->shape_set = false;
+    g->shape = kad::LaunchShape{};
+    return KAD_OK;
+  }
+  if (block != 64 && block != 128 && block != 256)
+    return fail(KAD_EINVAL, "block must be 64, 128 or 256");
+  g->shape.block = (int)block;
+  g->shape.small_exp = small_expansion;
+  g->shape_set = true;
+  return KAD_OK;
+}
+
+kad_status kad_graph_get_launch(const kad_graph *g, uint32_t *block, uint32_t *small_expansion) {
+  if (!g) return fail(KAD_EINVAL, "NULL graph");
+  const kad::LaunchShape sh = kad::graph_shape(g);
+  if (block) *block = (uint32_t)sh.block;
+  if (small_expansion) *small_expansion = sh.small_exp;
+  return KAD_OK;
+}
+
+kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *block,
+                        uint32_t *small_expansion, double *seconds) {
+  if (!ctx || !g) return fail(KAD_EINVAL, "NULL argument");
+  if (samples == 0) samples = DEFAULT_BATCH;
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
+  uint32_t vd;
+  bool ex;
+  kad_status st = graph_vd(g, &vd, &ex);
+  if (st) return st;
+  const uint32_t stride = std::max<uint32_t>(vd, 2);
+  if ((st = ensure_capacity(ctx, g->n, samples, stride))) return st;
+  const kad::LaunchShape saved = g->shape;
+  const bool saved_set = g->shape_set;
+  const uint32_t exps[4] = {0, 32, 128, 512};
+  kad::LaunchShape best;
+  double best_s = 1e300;
+  auto time_shape = [&](double *t_min) -> kad_status {
+    *t_min = 1e300;
+    for (int rep = 0; rep < 2; ++rep) {  // the faster of two launches
+      kad_status s2 = launch_batch(ctx, g, 1, 1, 0, samples, stride, 0, ctx->stream);
+      if (s2) return s2;
+      HIP_TRY(hipStreamSynchronize(ctx->stream));
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, ctx->outs[0].k0, ctx->outs[0].k1));
+      *t_min = std::min(*t_min, ms * 1e-3);
+    }
+    return KAD_OK;
+  };
+  g->shape_set = true;
+  for (int b : kad::SAMPLER_BLOCKS)
+    for (uint32_t e : exps) {
+      g->shape.block = b;
+      g->shape.small_exp = e;
+      double t = 0;
+      if ((st = time_shape(&t))) {
+        g->shape = saved;
+        g->shape_set = saved_set;
+        return st;
+      }
+      if (t < best_s) {
+        best_s = t;
+        best = g->shape;
+      }
+    }
+  g->shape = best;
+  if (block) *block = (uint32_t)best.block;
+  if (small_expansion) *small_expansion = best.small_exp;
+  if (seconds) *seconds = best_s;
+  return KAD_OK;
 }
 
 // ---------------------------------------------------------------- timing (bench support)

@@ -58,6 +58,7 @@ def _mix():
         (gg.workload("er2000"), dict(epsilon=0.02, delta=0.05, seed=7, check_interval=2048)),
         (gg.gnp(400, 0.02, 5, True), dict(epsilon=0.015, delta=0.1, seed=11)),
         (gg.grid(30, 30), dict(epsilon=0.02, delta=0.1, seed=4)),
+        (gg.damaged_grid(120, 120, 0.05, 5), dict(epsilon=0.03, delta=0.1, seed=4)),
     ]
 
 
@@ -77,7 +78,7 @@ def test_batch_equals_single_runs(kad, ctx):
 def test_batch_matches_oracle(kad, ctx):
     import oracle
     oracle.build(force=False)
-    mix = _mix()[:4]
+    mix = _mix()[:4] + _mix()[-1:]
     Gs = [kad.Graph(ctx, g) for g, _ in mix]
     got = kad.run_batch(ctx, Gs, [kw for _, kw in mix])
     for (g, kw), a in zip(mix, got):

@@ -100,19 +100,77 @@ def test_paths_chung_lu_1m_sampled_ids(kad, ctx, orc):
     _compare_paths(kad, ctx, orc, g, 1, 0, 0, 1000)
 
 
-def test_paths_grid_unflagged_match(kad, ctx, orc):
-    """On a 500x500 grid the frontier path counts of distant pairs pass 2^128 (a node
-    l levels out on a diagonal has C(l, l/2) shortest paths): those samples are
-    flagged, all others must match the oracle exactly."""
+_SHAPE_GRAPHS = {}
+
+
+def _shape_graph(name):
+    if name not in _SHAPE_GRAPHS:
+        _SHAPE_GRAPHS[name] = {
+            "er2000": lambda: (gg.workload("er2000"), 4099),
+            "kbip1500": lambda: (gg.complete_bipartite(1500, 1500), 200),
+            "dcl": lambda: (gg.chung_lu_directed(200_000, 2.5, 2.1, 10.0, 9), 1500),
+            "union": lambda: (gg.disjoint_union(gg.path_graph(90), gg.star_graph(300),
+                                                gg.grid(20, 30)), 3000),
+        }[name]()
+    return _SHAPE_GRAPHS[name]
+
+
+@pytest.mark.parametrize("block", [64, 128, 256])
+@pytest.mark.parametrize("small", [128, 2048])
+@pytest.mark.parametrize("name", ["er2000", "kbip1500", "dcl", "union"])
+def test_paths_every_launch_shape(kad, ctx, orc, block, small, name):
+    """Workgroup size and scan threshold are performance choices only: every shape
+    gives the oracle's paths."""
+    g, cnt = _shape_graph(name)
+    G = kad.Graph(ctx, g)
+    G.set_launch(block, small)
+    assert G.launch() == (block, small)
+    _say("shape", block, small, name)
+    A = kad.sample_paths(ctx, G, 3, 1, 17, cnt)
+    B = orc.sample_paths(g, 3, 1, 17, cnt, threads=16)
+    assert (A["flags"] == 0).all()
+    assert np.array_equal(A["s"], B.s) and np.array_equal(A["t"], B.t)
+    assert np.array_equal(A["arcs"], B.arcs)
+    assert np.array_equal(A["path_off"], B.path_off.astype(np.uint64))
+    assert np.array_equal(A["nodes"], B.nodes)
+    G.close()
+
+
+def test_autotune_keeps_results(kad, ctx, orc):
+    g = gg.workload("er2000")
+    G = kad.Graph(ctx, g)
+    before = kad.run(ctx, G, epsilon=0.01, delta=0.1, seed=1)
+    t = G.autotune(16384)
+    _say("autotune er2000", t)
+    assert t["block"] in (64, 128, 256) and t["seconds"] > 0
+    assert G.launch() == (t["block"], t["small_expansion"])
+    after = kad.run(ctx, G, epsilon=0.01, delta=0.1, seed=1)
+    assert after["tau"] == before["tau"] and np.array_equal(after["count"], before["count"])
+    G.close()
+
+
+def test_paths_grid_wide_counts(kad, ctx, orc):
+    """On a 500x500 grid the path counts of distant pairs pass 2^128 (a node l levels
+    out on a diagonal has C(l, l/2) shortest paths): those samples are sampled again
+    with multi-limb counts and must match the oracle's arbitrary precision exactly."""
     g = gg.grid(500, 500)
-    A, B = _compare_paths(kad, ctx, orc, g, 2, 1, 0, 160, allow_flags=True)
-    flagged = A["flags"] != 0
-    assert flagged.any() and (~flagged).sum() >= 5
-    assert np.all(A["flags"][flagged] == kad.SAMPLE_OVERFLOW)
-    # a flagged sample really has a count beyond 128 bits somewhere on its frontier:
-    # at least its distance is long enough for one
+    A, B = _compare_paths(kad, ctx, orc, g, 2, 1, 0, 160)
     d = np.diff(B.path_off.astype(np.int64)) - 1
-    assert np.all(d[flagged] >= 120)
+    assert (d >= 300).sum() >= 20  # far beyond 128-bit counts
+
+
+def test_hit_counts_wide(kad, ctx, orc):
+    g = gg.damaged_grid(150, 150, 0.05, 3)
+    G = kad.Graph(ctx, g)
+    a, arcs = kad.hit_counts(ctx, G, 4, 1, 0, 3000)
+    S = orc.sample_paths(g, 4, 1, 0, 3000, threads=16)
+    b = np.zeros(g.n, dtype=np.uint64)
+    for k in range(3000):
+        p = S.path(k)
+        b[p[1:-1]] += 1
+    assert np.array_equal(a, b)
+    assert arcs == int(S.arcs.sum())
+    G.close()
 
 
 def test_hit_counts_match(kad, ctx, orc):
@@ -179,6 +237,13 @@ def test_run_topk(kad, ctx, orc):
     assert a["topk_node"].tolist() == sel
     assert a["rank_lo"].tolist() == [int(rlo[v]) for v in sel]
     assert a["rank_hi"].tolist() == [int(rhi[v]) for v in sel]
+
+
+def test_run_damaged_grid_wide(kad, ctx, orc):
+    """A high-diameter graph where most samples need counts beyond 128 bits."""
+    g = gg.damaged_grid(120, 120, 0.05, 5)
+    a, b = _compare_run(kad, ctx, orc, g, epsilon=0.03, delta=0.1, seed=4)
+    assert a["overflow_samples"] > 0
 
 
 def test_run_complete_graph_g_only(kad, ctx, orc):
