@@ -25,7 +25,8 @@ __all__ = [
     "CSR", "csr_from_edges", "er_lcc", "chung_lu", "chung_lu_directed",
     "grid", "damaged_grid", "path_graph", "star_graph", "cycle_graph",
     "complete_graph", "complete_bipartite", "disjoint_union", "gnp",
-    "batch_family_spec", "batch_graph", "workload",
+    "batch_family_spec", "batch_graph", "serve_family_spec", "serve_graph", "serve_queries",
+    "workload",
 ]
 
 
@@ -390,6 +391,54 @@ def batch_graph(i: int) -> CSR:
         return chung_lu_directed(sp["n"], sp["beta_out"], sp["beta_in"], sp["mean_deg"],
                                  sp["seed"])
     return chung_lu(sp["n"], sp["beta_out"], sp["mean_deg"], sp["seed"])
+
+
+def serve_family_spec(i: int) -> dict:
+    """Graph i (0..29) of the serving set's Chung-Lu graphs: n log-uniform in
+    [1e4, 1e6], half directed, exponents in [2.1, 2.8], mean degree 4..30 (seed 2000+i)."""
+    rng = np.random.default_rng(2000 + i)
+    n = int(round(10.0 ** rng.uniform(4.0, 6.0)))
+    directed = bool(i % 2 == 1)
+    b_out = float(rng.uniform(2.1, 2.8))
+    b_in = float(rng.uniform(2.1, 2.8))
+    mean_deg = float(rng.uniform(4.0, 30.0))
+    return {"n": n, "directed": directed, "beta_out": b_out, "beta_in": b_in,
+            "mean_deg": mean_deg, "seed": 2000 + i}
+
+
+SERVE_GRAPHS = 33
+
+
+def serve_graph(i: int) -> CSR:
+    """The resident graphs of the serving workload: 0 = er2000, 1 = cl1m,
+    2..31 = serve_family_spec(0..29), 32 = grid2000."""
+    if i == 0:
+        return workload("er2000")
+    if i == 1:
+        return workload("cl1m")
+    if i == 32:
+        return workload("grid2000")
+    sp = serve_family_spec(i - 2)
+    if sp["directed"]:
+        return chung_lu_directed(sp["n"], sp["beta_out"], sp["beta_in"], sp["mean_deg"],
+                                 sp["seed"])
+    return chung_lu(sp["n"], sp["beta_out"], sp["mean_deg"], sp["seed"])
+
+
+def serve_queries(count: int, rate: float = 20.0, seed: int = 7, graphs: int = 33):
+    """Poisson query stream: arrival times (s), graph index, mode, k, epsilon, seed.
+    Graph index graphs-1 is the damaged grid; all-nodes or top-k (k in {10, 100}) with
+    probability 1/2 each; epsilon uniform in [0.002, 0.02]; delta 0.1; Philox seed =
+    query id + 1."""
+    rng = np.random.default_rng(seed)
+    t = np.cumsum(rng.exponential(1.0 / rate, count))
+    gi = rng.integers(0, graphs, count)
+    topk = rng.random(count) < 0.5
+    k = np.where(rng.random(count) < 0.5, 10, 100)
+    eps = rng.uniform(0.002, 0.02, count)
+    return [{"t": float(t[q]), "graph": int(gi[q]), "mode": "topk" if topk[q] else "all",
+             "k": int(k[q]) if topk[q] else 0, "epsilon": float(eps[q]), "delta": 0.1,
+             "seed": q + 1} for q in range(count)]
 
 
 def workload(name: str) -> CSR:

@@ -55,6 +55,8 @@ struct SampleSeg {
   uint32_t phase;
   uint32_t begin;
   uint32_t id_base;
+  uint32_t wide_only;  // nonzero: sampled by the wide-count kernel only (high diameter)
+  uint32_t pad;
 };
 
 // Working memory of the wide-count resampling (wide_kernel): the sampler slots' tag,
@@ -92,13 +94,14 @@ hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const Slot
                                 uint32_t grid, const LaunchShape &shape, hipStream_t stream);
 
 // Resample, with multi-limb path counts, every sample of the launch whose flags carry
-// FLAG_OVERFLOW (same results as exact arithmetic; FLAG_CAPACITY if the arena or the
-// level tables are too small).  list: room for `count` launch indices; list_count and
-// work: one counter each (set here).  segs == nullptr: the single-graph launch (g,
-// seed, phase, first).
+// FLAG_OVERFLOW -- or, with `all`, every sample (no sampler launch before it) -- with
+// the results of exact arithmetic (FLAG_CAPACITY if the arena or the level tables are
+// too small).  list: room for `count` launch indices; list_count and work = list_count
+// + 1: two counters (set here).  segs == nullptr: the single-graph launch (g, seed,
+// phase, first).
 hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
                            const SampleSeg *segs, uint32_t nseg, const SlotState &st,
-                           const WideState &ws, uint32_t count, uint32_t *list,
+                           const WideState &ws, uint32_t count, bool all, uint32_t *list,
                            uint32_t *list_count, uint32_t *work, const SampleOut &out,
                            hipStream_t stream);
 

@@ -69,6 +69,7 @@ struct Query {
   // schedule
   uint32_t n = 0, vd = 0, stride = 2;
   bool vd_exact = false;
+  int ovc = 1;  // overflow_class of the graph
   uint64_t omega = 0, alpha = 0, B = 0, K = 0;
   double eb = 0.001;
   // counter pool slice: node v of the query is pool id base() + v
@@ -254,6 +255,7 @@ kad_status Engine::prepare(Query *q) {
   q->K = std::min<uint64_t>(std::max<uint64_t>(q->B, (K + q->B - 1) / q->B * q->B),
                             (uint64_t)q->B * MAX_LAYERS);
   q->stride = std::max<uint32_t>(q->vd, 2);
+  q->ovc = overflow_class(q->g, q->vd, p.vd_override == 0);
   if (q->B > TICK_SAMPLES || (uint64_t)q->stride * 4 * q->B > TICK_PATH_BYTES)
     finish_failed(q, KAD_EINVAL, "check interval too large for the engine's launches");
   return KAD_OK;
@@ -439,6 +441,7 @@ kad_status Engine::launch(Tick &t) {
     bins_cap_ = need_bins;
   }
   // segments
+  bool wide = false;
   for (uint32_t j = 0; j < np; ++j) {
     const Piece &pc = t.pieces[j];
     const kad_graph *g = pc.q->g;
@@ -453,6 +456,9 @@ kad_status Engine::launch(Tick &t) {
     sg.phase = pc.kind == Kind::Pilot || pc.kind == Kind::PilotLast ? 0u : 1u;
     sg.begin = pc.begin;
     sg.id_base = (uint32_t)pc.q->base();
+    sg.wide_only = pc.q->ovc == 2 ? 1u : 0u;
+    sg.pad = 0;
+    wide |= pc.q->ovc != 0;
   }
   // snapshots, layer by layer
   std::vector<GatherDesc> gat;
@@ -524,10 +530,12 @@ kad_status Engine::launch(Tick &t) {
   HIP_TRY(launch_sampler_multi(t.d_segs.p, np, slot_view(ctx_), t.total, t.work.p,
                                t.out.view(t.stride), grid, shape, s));
   if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
-  {
-    kad_status st = launch_wide(ctx_, GraphDev{}, 0, 0, 0, t.d_segs.p, np, t.total,
+  if (wide) {
+    kad_status st = launch_wide(ctx_, GraphDev{}, 0, 0, 0, t.d_segs.p, np, t.total, false,
                                 t.out.view(t.stride), t.out.h_nwide.p, s);
     if (st) return st;
+  } else {
+    t.out.h_nwide.p[0] = 0;
   }
   HIP_TRY(hipEventRecord(t.sampled, s));
   HIP_TRY(hipMemcpyAsync(t.out.h_flags.p, t.out.flags.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));

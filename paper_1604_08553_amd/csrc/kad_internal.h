@@ -111,6 +111,7 @@ struct kad_ctx {
   std::atomic<bool> busy{false};  // one user at a time (a call, or a server's engine)
   // per-slot working state
   uint32_t slot_n = 0, slots = 0;
+  uint64_t slot_bytes = 0;
   kad::DevBuf<uint32_t> tag, visit;
   kad::DevBuf<uint64_t> sig, pi;
   // wide-count resampling of overflowed samples (kad::WideState)
@@ -125,7 +126,9 @@ struct kad_ctx {
   kad::DevBuf<uint32_t> work, group;
   kad::DevBuf<uint64_t> count, gmax;
   kad::DevBuf<uint32_t> bins, bin_count;  // hit-reduction scratch (bin_count all zero between calls)
+  kad::DevBuf<uint32_t> tile_start, tile_fill;  // compact layout (tile_fill all zero between calls)
   uint64_t bins_cap = 0;
+  bool bins_compact = false;
   kad::PinBuf<uint32_t> h_s, h_t, h_path;
   kad::PinBuf<uint64_t> h_count;
   std::vector<hipEvent_t> chunk_ev;
@@ -156,6 +159,7 @@ struct kad_graph {
   std::mutex vd_mu;
   uint32_t vd = 0;
   bool vd_exact = false, vd_known = false;
+  uint32_t maxdeg = 0;  // largest out- or in-degree
   kad::LaunchShape shape;  // sampler launch shape (kad_graph_set_launch / kad_autotune)
   bool shape_set = false;
 };
@@ -193,12 +197,19 @@ kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact);
 kad_status ensure_slots(kad_ctx *ctx, uint32_t n);
 SlotState slot_view(const kad_ctx *ctx);
 WideState wide_view(const kad_ctx *ctx);
-// Launch the wide-count resampling after a sampler launch of `count` samples whose
-// outputs are `out` (segs == nullptr: single graph g), and queue the copy of the
-// number of resampled samples into *h_nwide.  No-op without wide slots.
+// Wide path counts: 0 = a graph whose path counts always fit 128 bits (VD and the
+// largest degree bound them), 1 = overflowed samples are resampled wide, 2 = a
+// high-diameter graph whose samples all go to the wide kernel.  vd_from_library:
+// false for a caller's VD override, whose bound is not trusted (then 1).
+int overflow_class(const kad_graph *g, uint32_t vd, bool vd_from_library);
+// Wide working memory, allocated on first use.
+kad_status ensure_wide(kad_ctx *ctx);
+// Launch the wide-count resampling of a launch of `count` samples whose outputs are
+// `out` (segs == nullptr: single graph g; all: every sample, no sampler launch
+// before), and queue the copy of the number of resampled samples into *h_nwide.
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
-                       const SampleOut &out, uint32_t *h_nwide, hipStream_t stream);
+                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream);
 // The graph's launch shape (set or tuned, else a default by size), and the grid of a
 // launch of `count` samples with it.
 LaunchShape graph_shape(const kad_graph *g);

@@ -670,6 +670,14 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       phase = S.phase;
       i = S.first + (k - S.begin);
       base = S.id_base;
+      if (S.wide_only) {  // left to the wide-count kernel (uniform for the workgroup)
+        if (tid == 0) {
+          out.flags[k] = FLAG_OVERFLOW;
+          out.len[k] = 0;
+        }
+        __syncthreads();  // every thread has read L.k and L.seg before they change
+        continue;
+      }
     }
 
     // ---- the pair and the two initial levels
@@ -1115,8 +1123,9 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc *__restric
 // of level l of a side are stored contiguously, `stride` limbs per node in the order
 // of the node list, with stride = (width of level l-1) + 1, which always holds the
 // sum of the predecessors' counts; the level's width is then the widest count.
-// A new level's counts are pulled from each node's predecessors on the level before,
-// so no two threads write the same count.
+// A level is expanded in one arc-parallel pass: the thread that claims a new node
+// pulls its count from the node's predecessors on the (complete) level before, so no
+// two threads write the same count.
 constexpr int WB = 256;
 constexpr int WNW = WB / WAVE;
 
@@ -1211,23 +1220,62 @@ __device__ void uniform_below_wide(const uint64_t *bound, uint32_t bw, uint64_t 
   for (uint32_t j = 0; j < bw; ++j) r[j] = 0;
 }
 
+constexpr int WCHUNK = 2 * WB;  // frontier nodes staged per pass
+
+// acc[0, stride) (+)= the sum of the counts src[idx[q] * sl, + wl), q < np (np <= 4),
+// four limbs at a time in registers so that the loads of a chunk overlap; with first
+// the old contents of acc are ignored.  wl < stride, so the sum fits.
+__device__ void pull_add(uint64_t *__restrict__ acc, uint32_t stride,
+                         const uint64_t *__restrict__ src, uint32_t sl, uint32_t wl,
+                         const uint32_t *idx, uint32_t np, bool first) {
+  uint64_t carry = 0;  // carry into the next limb (at most np)
+  for (uint32_t c0 = 0; c0 < stride; c0 += 4) {
+    uint64_t v[4], x[4][4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) v[j] = (!first && c0 + j < stride) ? acc[c0 + j] : 0;
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int j = 0; j < 4; ++j)
+        x[q][j] = ((uint32_t)q < np && c0 + j < wl) ? src[(size_t)idx[q] * sl + c0 + j] : 0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      uint64_t sum = v[j] + carry;
+      uint64_t c = sum < carry ? 1u : 0u;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        sum += x[q][j];
+        c += sum < x[q][j] ? 1u : 0u;
+      }
+      v[j] = sum;
+      carry = c;
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      if (c0 + j < stride) acc[c0 + j] = v[j];
+  }
+}
+
 struct WideLds {
   uint32_t k, seg, s, t, flags;
   uint32_t lvl[2];
   uint32_t nvis, pi_count, maxw, maxw_all, sel;
   uint64_t deg[2], new_deg, arcs, top;
+  uint32_t c_node[WCHUNK], c_start[WCHUNK], c_pref[WCHUNK + 1];
+  uint32_t red[WNW];
 };
 
 // Level tables of a wide slot: fields of level l of side x at lv[(x * max_lev + l) * 4 + f].
 enum : uint32_t { LV_LO = 0, LV_HI = 1, LV_STRIDE = 2, LV_WIDTH = 3 };
 
+// list == nullptr: every launch index below all_count.
 template <bool MULTI>
 __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *__restrict__ segs,
                                                   uint32_t nseg, uint64_t seed0, uint32_t phase0,
                                                   uint64_t first0, SlotState st, WideState ws,
                                                   const uint32_t *list,
-                                                  const uint32_t *list_count, uint32_t *work,
-                                                  SampleOut out) {
+                                                  const uint32_t *list_count, uint32_t all_count,
+                                                  uint32_t *work, SampleOut out) {
   __shared__ WideLds L;
   const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
   const size_t n = st.n;
@@ -1239,7 +1287,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
   uint64_t *arena = ws.arena + slot * ws.arena_limbs;
   uint32_t *lv = ws.lv + slot * 2 * (size_t)ws.max_lev * 4;
   uint64_t *lb = ws.lbase + slot * 2 * (size_t)ws.max_lev;
-  const uint32_t nlist = *list_count;
+  const uint32_t nlist = list ? *list_count : all_count;
   auto LV = [&](uint32_t side, uint32_t l, uint32_t f) -> uint32_t & {
     return lv[((size_t)side * ws.max_lev + l) * 4 + f];
   };
@@ -1249,7 +1297,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
   for (;;) {
     if (tid == 0) {
       const uint32_t j = atomicAdd(work, 1u);
-      L.k = j < nlist ? list[j] : 0xFFFFFFFFu;
+      L.k = j < nlist ? (list ? list[j] : j) : 0xFFFFFFFFu;
       if (MULTI && L.k != 0xFFFFFFFFu) {
         uint32_t lo = 0, hi = nseg;
         while (hi - lo > 1) {
@@ -1323,22 +1371,67 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       const uint32_t next_tag = (me == 0 ? 0u : TAG_T) | (l + 2);
       const uint32_t *rp = me == 0 ? g.row : g.rrow;
       const uint32_t *cl = me == 0 ? g.col : g.rcol;
+      const uint32_t *pr = me == 0 ? g.rrow : g.row;  // predecessors of the new level
+      const uint32_t *pc = me == 0 ? g.rcol : g.col;
       const uint64_t dme = L.deg[me];
       const uint32_t nb = L.nvis;
+      const uint32_t wl = LV(me, l, LV_WIDTH), sl = LV(me, l, LV_STRIDE);
+      const uint64_t bl = LB(me, l);
+      const uint32_t stride = wl + 1;
+      const uint64_t nbase = L.top;
       needed = nb;
+      if (l + 1 >= ws.max_lev) {  // no room for the next level's table entry
+        __syncthreads();
+        if (tid == 0) L.flags |= FLAG_CAPACITY;
+        break;
+      }
       __syncthreads();
       if (tid == 0) {
         L.arcs += dme;
         L.pi_count = 0;
         L.new_deg = 0;
+        L.maxw = 0;
       }
       __syncthreads();
-      // ---- pass 1: meeting test and discovery (a wave per frontier node)
-      for (uint32_t f = fb + wid; f < fe; f += WNW) {
-        const uint32_t u = visit[f];
-        const uint32_t rb = rp[u], re = rp[u + 1];
-        for (uint32_t e = rb + lane; e < re; e += WAVE) {
-          const uint32_t w = cl[e];
+      // ---- one pass over the frontier's arcs: meeting test, discovery, and the new
+      // node's count pulled from its predecessors on level l
+      uint32_t used_max = 0;
+      bool cap = false;
+      for (uint32_t cb = fb; cb < fe; cb += WCHUNK) {
+        const uint32_t m = min((uint32_t)WCHUNK, fe - cb);
+        uint32_t d[2] = {0, 0};
+        for (int q = 0; q < 2; ++q) {
+          const uint32_t j = 2 * tid + q;
+          if (j < m) {
+            const uint32_t u = visit[cb + j];
+            const uint32_t st0 = rp[u];
+            d[q] = rp[u + 1] - st0;
+            L.c_node[j] = u;
+            L.c_start[j] = st0;
+          }
+        }
+        // exclusive scan of the staged degrees
+        const uint32_t inc = wave_incl_u32(d[0] + d[1]);
+        if (lane == WAVE - 1) L.red[wid] = inc;
+        __syncthreads();
+        uint32_t before = 0, tot = 0;
+        for (int q = 0; q < WNW; ++q) {
+          if ((uint32_t)q < wid) before += L.red[q];
+          tot += L.red[q];
+        }
+        const uint32_t ex = before + inc - (d[0] + d[1]);
+        if (2 * tid < m) L.c_pref[2 * tid] = ex;
+        if (2 * tid + 1 < m) L.c_pref[2 * tid + 1] = ex + d[0];
+        if (tid == 0) L.c_pref[m] = tot;
+        __syncthreads();
+        for (uint32_t e = tid; e < tot; e += WB) {
+          uint32_t lo = 0, hi = m;  // largest j with c_pref[j] <= e
+          while (hi - lo > 1) {
+            const uint32_t mid = (lo + hi) >> 1;
+            if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
+          }
+          const uint32_t u = L.c_node[lo];
+          const uint32_t w = cl[L.c_start[lo] + (e - L.c_pref[lo])];
           const uint32_t tg = ld_tag(tag + w);
           if (tg == other_tag) {
             const uint32_t idx = atomicAdd(&L.pi_count, 1u);
@@ -1349,9 +1442,31 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
             visit[p] = w;
             pos[w] = p;
             atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)(rp[w + 1] - rp[w]));
+            if (nbase + (uint64_t)(p - nb + 1) * stride > ws.arena_limbs) {
+              cap = true;
+            } else {
+              uint64_t *acc = arena + nbase + (size_t)(p - nb) * stride;
+              uint32_t idx[4], np = 0;
+              bool first = true;
+              const uint32_t pe = pr[w + 1];
+              for (uint32_t e2 = pr[w]; e2 < pe; ++e2) {
+                const uint32_t u2 = pc[e2];
+                if (ld_tag(tag + u2) == cur_tag) idx[np++] = pos[u2] - fb;
+                if (np == 4 || (e2 + 1 == pe && (np > 0 || first))) {
+                  pull_add(acc, stride, arena + bl, sl, wl, idx, np, first);
+                  first = false;
+                  np = 0;
+                }
+              }
+              if (first) pull_add(acc, stride, arena + bl, sl, wl, idx, 0, true);  // no predecessor
+              used_max = max(used_max, wide_len(acc, stride));
+            }
           }
         }
+        __syncthreads();
       }
+      atomicMax(&L.maxw, used_max);
+      if (cap) atomicOr(&L.flags, FLAG_CAPACITY);
       __syncthreads();
       if (L.pi_count > 0) {
         met = true;
@@ -1359,30 +1474,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       }
       const uint32_t ne = L.nvis;
       if (ne == nb) break;  // the expanded side closed: s and t are disconnected
-      const uint32_t wl = LV(me, l, LV_WIDTH), sl = LV(me, l, LV_STRIDE);
-      const uint64_t bl = LB(me, l);
-      const uint32_t stride = wl + 1;
-      const uint64_t nbase = L.top;
-      if (l + 1 >= ws.max_lev || nbase + (uint64_t)(ne - nb) * stride > ws.arena_limbs) {
-        if (tid == 0) L.flags |= FLAG_CAPACITY;
-        break;
-      }
-      // ---- pass 2: counts of the new level, pulled from the level before
-      const uint32_t *pr = me == 0 ? g.rrow : g.row;
-      const uint32_t *pc = me == 0 ? g.rcol : g.col;
-      uint32_t used_max = 0;
-      for (uint32_t q = nb + tid; q < ne; q += WB) {
-        const uint32_t w = visit[q];
-        uint64_t *acc = arena + nbase + (size_t)(q - nb) * stride;
-        for (uint32_t j = 0; j < stride; ++j) acc[j] = 0;
-        for (uint32_t e = pr[w]; e < pr[w + 1]; ++e) {
-          const uint32_t u = pc[e];
-          if (ld_tag(tag + u) == cur_tag)
-            (void)wide_add(acc, stride, arena + bl + (size_t)(pos[u] - fb) * sl, wl);
-        }
-        used_max = max(used_max, wide_len(acc, stride));
-      }
-      atomicMax(&L.maxw, used_max);
+      if (L.flags & FLAG_CAPACITY) break;
       __syncthreads();
       if (tid == 0) {
         const uint32_t wn = max(L.maxw, 1u);
@@ -1394,7 +1486,6 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
         L.top = nbase + (uint64_t)(ne - nb) * stride;
         L.deg[me] = L.new_deg;
         L.lvl[me] = l + 1;
-        L.maxw = 0;
         L.maxw_all = max(L.maxw_all, wn);
       }
       __syncthreads();
@@ -1408,8 +1499,10 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       const uint32_t ws_ = LV(0, ls, LV_WIDTH), wt_ = LV(1, lt, LV_WIDTH);
       const uint32_t pw = ws_ + wt_;
       const uint32_t tw = max(pw, L.maxw_all) + 2;  // totals, draws, running sums
+      constexpr uint32_t GROUPS = 16;  // block sums are combined in 16 groups of 16
+      static_assert(WB == GROUPS * 16, "one block of candidate edges per thread");
       const uint64_t prod = L.top;
-      const uint64_t need = prod + (uint64_t)P * pw + 4ull * tw;
+      const uint64_t need = prod + (uint64_t)P * pw + (uint64_t)(WB + GROUPS + 11) * tw;
       if (P > st.pi_cap || ls + lt + 2 > out.stride || need > ws.arena_limbs) {
         if (tid == 0) L.flags |= FLAG_CAPACITY;
       } else {
@@ -1429,61 +1522,107 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
                    arena + tb + (size_t)(pos[w] - to) * ts, wt_, arena + prod + (size_t)j * pw);
         }
         __syncthreads();
+        // sums of contiguous blocks of weights (one block per thread), then of groups
+        // of 16 blocks, so that the total and the prefix that passes r need few serial adds
+        uint64_t *bsum = arena + prod + (size_t)P * pw;
+        uint64_t *gsum = bsum + (size_t)WB * tw;
+        uint64_t *scr = gsum + (size_t)GROUPS * tw;  // 11 scratch numbers
+        const uint32_t b0 = (uint32_t)((uint64_t)P * tid / WB), b1 = (uint32_t)((uint64_t)P * (tid + 1) / WB);
+        {
+          uint64_t *bs = bsum + (size_t)tid * tw;
+          for (uint32_t j = 0; j < tw; ++j) bs[j] = 0;
+          for (uint32_t j = b0; j < b1; ++j) (void)wide_add(bs, tw, arena + prod + (size_t)j * pw, pw);
+        }
+        __syncthreads();
+        if (tid < GROUPS) {
+          uint64_t *gs = gsum + (size_t)tid * tw;
+          for (uint32_t j = 0; j < tw; ++j) gs[j] = 0;
+          for (uint32_t b = tid * 16; b < tid * 16 + 16; ++b) (void)wide_add(gs, tw, bsum + (size_t)b * tw, tw);
+        }
+        __syncthreads();
         if (tid == 0) {
-          uint64_t *total = arena + prod + (size_t)P * pw;
-          uint64_t *r = total + tw, *tmp = r + tw, *acc = tmp + tw;
+          uint64_t *total = scr, *r = scr + tw, *tmp = scr + 2 * tw, *acc = scr + 3 * tw,
+                   *sv = scr + 4 * tw;
           uint32_t fl = 0;
           for (uint32_t j = 0; j < tw; ++j) total[j] = 0;
-          for (uint32_t j = 0; j < P; ++j) (void)wide_add(total, tw, arena + prod + (size_t)j * pw, pw);
+          for (uint32_t gi = 0; gi < GROUPS; ++gi) (void)wide_add(total, tw, gsum + (size_t)gi * tw, tw);
           uniform_below_wide(total, tw, seed, i, stream_word(phase, P_EDGE, 0), r, tmp, fl);
-          uint32_t sel = P;
+          // the first edge whose prefix sum passes r: group, then block, then edge
           for (uint32_t j = 0; j < tw; ++j) acc[j] = 0;
-          for (uint32_t j = 0; j < P && fl == 0; ++j) {
-            (void)wide_add(acc, tw, arena + prod + (size_t)j * pw, pw);
+          auto step = [&](const uint64_t *x, uint32_t xw) -> bool {  // acc += x unless that passes r
+            for (uint32_t j = 0; j < tw; ++j) sv[j] = acc[j];
+            (void)wide_add(acc, tw, x, xw);
             if (wide_cmp(acc, tw, r, tw) > 0) {
-              sel = j;
+              for (uint32_t j = 0; j < tw; ++j) acc[j] = sv[j];
+              return true;
+            }
+            return false;
+          };
+          uint32_t gsel = GROUPS, bsel = WB, sel = P;
+          for (uint32_t gi = 0; gi < GROUPS && fl == 0; ++gi)
+            if (step(gsum + (size_t)gi * tw, tw)) {
+              gsel = gi;
               break;
             }
-          }
-          if (sel >= P) fl |= FLAG_CAPACITY;
-          // ---- backtracking, one side after the other (section 4)
-          for (uint32_t side = 0; side < 2 && fl == 0; ++side) {
-            const uint64_t key = gpi[sel];
-            uint32_t x = side == 0 ? (uint32_t)(key >> 32) : (uint32_t)key;
-            const uint32_t lev = side == 0 ? ls : lt;
-            path[side == 0 ? ls : ls + 1] = x + base;
-            const uint32_t *brp = side == 0 ? g.rrow : g.row;
-            const uint32_t *bcl = side == 0 ? g.rcol : g.col;
-            for (uint32_t j = lev; j >= 1 && fl == 0; --j) {
-              const uint32_t xw = LV(side, j, LV_WIDTH);
-              const uint64_t *sx = arena + LB(side, j) +
-                                   (size_t)(pos[x] - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
-              uniform_below_wide(sx, xw, seed, i,
-                                 stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j), r, tmp, fl);
-              const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1
-              const uint32_t pwid = LV(side, j - 1, LV_WIDTH), plo = LV(side, j - 1, LV_LO);
-              const uint32_t pst = LV(side, j - 1, LV_STRIDE);
-              const uint64_t pb = LB(side, j - 1);
-              for (uint32_t q = 0; q < tw; ++q) acc[q] = 0;
-              uint32_t pick = 0xFFFFFFFFu;
-              for (uint32_t e = brp[x]; e < brp[x + 1] && fl == 0; ++e) {
-                const uint32_t u = bcl[e];
-                if (ld_tag(tag + u) != want) continue;
-                (void)wide_add(acc, tw, arena + pb + (size_t)(pos[u] - plo) * pst, pwid);
-                if (wide_cmp(acc, tw, r, xw) > 0) {
-                  pick = u;
-                  break;
-                }
-              }
-              if (pick == 0xFFFFFFFFu) {
-                fl |= FLAG_CAPACITY;  // unreachable for consistent counts
+          for (uint32_t b = gsel * 16; gsel < GROUPS && b < gsel * 16 + 16; ++b)
+            if (step(bsum + (size_t)b * tw, tw)) {
+              bsel = b;
+              break;
+            }
+          if (bsel < WB) {
+            const uint32_t e0 = (uint32_t)((uint64_t)P * bsel / WB), e1 = (uint32_t)((uint64_t)P * (bsel + 1) / WB);
+            for (uint32_t j = e0; j < e1; ++j)
+              if (step(arena + prod + (size_t)j * pw, pw)) {
+                sel = j;
                 break;
               }
-              x = pick;
-              path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x + base;
-            }
           }
+          if (sel >= P) fl |= FLAG_CAPACITY;  // unreachable for consistent counts
+          L.sel = sel;
           L.flags |= fl;
+        }
+        __syncthreads();
+        // ---- backtracking (section 4): the two sides at once, by lane 0 of waves 0 and 1
+        if (L.flags == 0 && (tid == 0 || tid == WAVE)) {
+          const uint32_t side = tid == 0 ? 0u : 1u;
+          uint64_t *r = scr + (size_t)(5 + 3 * side) * tw;  // scratch numbers 5..10
+          uint64_t *acc = r + tw, *tmp2 = r + 2 * tw;
+          uint32_t fl = 0;
+          const uint64_t key = gpi[L.sel];
+          uint32_t x = side == 0 ? (uint32_t)(key >> 32) : (uint32_t)key;
+          const uint32_t lev = side == 0 ? ls : lt;
+          path[side == 0 ? ls : ls + 1] = x + base;
+          const uint32_t *brp = side == 0 ? g.rrow : g.row;
+          const uint32_t *bcl = side == 0 ? g.rcol : g.col;
+          for (uint32_t j = lev; j >= 1 && fl == 0; --j) {
+            const uint32_t xw = LV(side, j, LV_WIDTH);
+            const uint64_t *sx = arena + LB(side, j) +
+                                 (size_t)(pos[x] - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
+            uniform_below_wide(sx, xw, seed, i,
+                               stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j), r, tmp2, fl);
+            const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1
+            const uint32_t pwid = LV(side, j - 1, LV_WIDTH), plo = LV(side, j - 1, LV_LO);
+            const uint32_t pst = LV(side, j - 1, LV_STRIDE);
+            const uint64_t pb = LB(side, j - 1);
+            for (uint32_t q = 0; q < tw; ++q) acc[q] = 0;
+            uint32_t pick = 0xFFFFFFFFu;
+            for (uint32_t e = brp[x]; e < brp[x + 1] && fl == 0; ++e) {
+              const uint32_t u = bcl[e];
+              if (ld_tag(tag + u) != want) continue;
+              (void)wide_add(acc, tw, arena + pb + (size_t)(pos[u] - plo) * pst, pwid);
+              if (wide_cmp(acc, tw, r, xw) > 0) {
+                pick = u;
+                break;
+              }
+            }
+            if (pick == 0xFFFFFFFFu) {
+              fl |= FLAG_CAPACITY;  // unreachable for consistent counts
+              break;
+            }
+            x = pick;
+            path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x + base;
+          }
+          if (fl) atomicOr(&L.flags, fl);
         }
         __syncthreads();
         if (L.flags == 0) len = ls + lt + 2;
@@ -1563,24 +1702,28 @@ hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const Slot
 
 hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
                            const SampleSeg *segs, uint32_t nseg, const SlotState &st,
-                           const WideState &ws, uint32_t count, uint32_t *list,
+                           const WideState &ws, uint32_t count, bool all, uint32_t *list,
                            uint32_t *list_count, uint32_t *work, const SampleOut &out,
                            hipStream_t stream) {
   if (count == 0) return hipSuccess;
   if (ws.slots == 0 || ws.slots > st.slots || !ws.arena) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, stream, list_count, (uint64_t)2, 0u);
-  hipLaunchKernelGGL(overflow_list_kernel, dim3((count + 255) / 256), dim3(256), 0, stream,
-                     (const uint32_t *)out.flags, count, list, list_count);
-  // work == list_count + 1 (zeroed above)
   if (work != list_count + 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, stream, list_count, (uint64_t)2,
+                     0u);  // list length and work counter
+  const uint32_t *lst = nullptr;
+  if (!all) {
+    hipLaunchKernelGGL(overflow_list_kernel, dim3((count + 255) / 256), dim3(256), 0, stream,
+                       (const uint32_t *)out.flags, count, list, list_count);
+    lst = list;
+  }
   if (segs)
     hipLaunchKernelGGL(wide_kernel<true>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
-                       seed, phase, first, st, ws, (const uint32_t *)list,
-                       (const uint32_t *)list_count, work, out);
+                       seed, phase, first, st, ws, lst, (const uint32_t *)list_count, count, work,
+                       out);
   else
     hipLaunchKernelGGL(wide_kernel<false>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
-                       seed, phase, first, st, ws, (const uint32_t *)list,
-                       (const uint32_t *)list_count, work, out);
+                       seed, phase, first, st, ws, lst, (const uint32_t *)list_count, count, work,
+                       out);
   return hipGetLastError();
 }
 

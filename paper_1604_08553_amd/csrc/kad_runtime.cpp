@@ -132,42 +132,48 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   ctx->slots = (uint32_t)slots;
   ctx->slot_n = n;
-  // wide-count resampling: up to 16 workgroups, each with a limb arena of up to 1 GiB,
-  // in at most half of what the budget leaves after the sampler slots
-  ctx->w_arena.release();
-  ctx->w_lv.release();
-  ctx->w_lbase.release();
-  ctx->w_slots = 0;
-  const uint64_t slot_bytes = slots * per_slot;
-  const uint64_t left = ctx->budget > ctx->used_graphs + slot_bytes + (1024ull << 20)
-                            ? ctx->budget - ctx->used_graphs - slot_bytes - (1024ull << 20)
+  ctx->slot_bytes = slots * per_slot;
+  ctx->w_slots = std::min<uint32_t>(ctx->w_slots, ctx->slots);
+  return KAD_OK;
+}
+
+kad_status ensure_wide(kad_ctx *ctx) {
+  if (ctx->w_slots > 0) return KAD_OK;
+  // up to 64 workgroups, each with a limb arena of up to 1 GiB, in at most half of
+  // what the budget leaves after the graphs and the sampler slots
+  const uint64_t left = ctx->budget > ctx->used_graphs + ctx->slot_bytes + (1024ull << 20)
+                            ? ctx->budget - ctx->used_graphs - ctx->slot_bytes - (1024ull << 20)
                             : 0;
-  const uint32_t w_slots = (uint32_t)std::min<uint64_t>(16, slots);
+  const uint32_t w_slots = std::min<uint32_t>(64, ctx->slots);
   const uint32_t max_lev = 16384;
   const uint64_t tables = (uint64_t)w_slots * 2 * max_lev * (16 + 8);
-  uint64_t limbs = left / 2 > tables ? (left / 2 - tables) / (8ull * w_slots) : 0;
+  uint64_t limbs = left / 2 > tables ? (left / 2 - tables) / (8ull * std::max(w_slots, 1u)) : 0;
   limbs = std::min<uint64_t>(limbs, 1ull << 27);
-  if (limbs >= (1ull << 20)) {
-    if (ctx->w_arena.ensure((size_t)w_slots * limbs) == hipSuccess &&
-        ctx->w_lv.ensure((size_t)w_slots * 2 * max_lev * 4) == hipSuccess &&
-        ctx->w_lbase.ensure((size_t)w_slots * 2 * max_lev) == hipSuccess &&
-        ctx->w_cnt.ensure(2) == hipSuccess) {
-      ctx->w_slots = w_slots;
-      ctx->w_max_lev = max_lev;
-      ctx->w_arena_limbs = limbs;
-    } else {
-      (void)hipGetLastError();
-      ctx->w_arena.release();
-      ctx->w_lv.release();
-      ctx->w_lbase.release();
-    }
-  }
+  if (w_slots == 0 || limbs < (1ull << 20))
+    return fail(KAD_ENOMEM, "no HBM left for wide path counts (needed by this graph)");
+  HIP_TRY(ctx->w_arena.ensure((size_t)w_slots * limbs));
+  HIP_TRY(ctx->w_lv.ensure((size_t)w_slots * 2 * max_lev * 4));
+  HIP_TRY(ctx->w_lbase.ensure((size_t)w_slots * 2 * max_lev));
+  HIP_TRY(ctx->w_cnt.ensure(2));
+  ctx->w_slots = w_slots;
+  ctx->w_max_lev = max_lev;
+  ctx->w_arena_limbs = limbs;
   return KAD_OK;
+}
+
+int overflow_class(const kad_graph *g, uint32_t vd, bool vd_from_library) {
+  if (!vd_from_library) return 1;
+  if (vd <= 2 || g->maxdeg <= 1) return 0;
+  // a path count is at most maxdeg^(levels), and levels < VD
+  const double bits = (double)(vd - 1) * std::log2((double)g->maxdeg);
+  if (bits < 127.0) return 0;
+  if (vd >= 256 && g->arcs >= 3ull * g->n) return 2;
+  return 1;
 }
 
 WideState wide_view(const kad_ctx *ctx) {
   WideState w;
-  w.slots = ctx->w_slots;
+  w.slots = std::min(ctx->w_slots, ctx->slots);
   w.max_lev = ctx->w_max_lev;
   w.arena_limbs = ctx->w_arena_limbs;
   w.arena = ctx->w_arena.p;
@@ -178,18 +184,20 @@ WideState wide_view(const kad_ctx *ctx) {
 
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
-                       const SampleOut &out, uint32_t *h_nwide, hipStream_t stream) {
-  if (ctx->w_slots == 0 || count == 0) {
+                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream) {
+  if (count == 0) {
     *h_nwide = 0;
     return KAD_OK;
   }
+  kad_status st = ensure_wide(ctx);
+  if (st) return st;
   if (ctx->w_list.n < count) {
     HIP_TRY(hipDeviceSynchronize());  // the old list may still be read
     ctx->w_list.release();
     HIP_TRY(ctx->w_list.ensure(std::max<size_t>(count, 1u << 18)));
   }
   HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, slot_view(ctx), wide_view(ctx),
-                          count, ctx->w_list.p, ctx->w_cnt.p, ctx->w_cnt.p + 1, out, stream));
+                          count, all, ctx->w_list.p, ctx->w_cnt.p, ctx->w_cnt.p + 1, out, stream));
   HIP_TRY(hipMemcpyAsync(h_nwide, ctx->w_cnt.p, 4, hipMemcpyDeviceToHost, stream));
   return KAD_OK;
 }
@@ -343,19 +351,27 @@ kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t st
   HIP_TRY(ctx->count.ensure(n));
   HIP_TRY(ctx->h_count.ensure(n));
   // hit-reduction bins: room in every tile for all the hits of one reduction call
+  // (fixed layout), or, when that would pass 1 GiB (long paths), one array sized by the
+  // hits with a counting pass first (compact layout)
   const uint64_t tiles = (n + kad::HIT_TILE_IDS - 1) / kad::HIT_TILE_IDS;
   if (tiles > kad::MAX_HIT_TILES_PUBLIC)
     return fail(KAD_EINVAL, "graphs above %u nodes are not supported by the hit reduction",
                 kad::MAX_HIT_TILES_PUBLIC * kad::HIT_TILE_IDS);
   const uint64_t cap = (uint64_t)ctx->outs[0].cap * std::max<uint32_t>(ctx->outs[0].stride - 2, 1);
-  if (cap > ctx->bins_cap || tiles * cap > ctx->bins.n) {
+  const bool compact = tiles * cap * 4 > (1ull << 30);
+  const uint64_t want = compact ? cap : tiles * cap;
+  if (cap > ctx->bins_cap || want > ctx->bins.n || compact != ctx->bins_compact) {
     ctx->bins.release();
-    HIP_TRY(ctx->bins.ensure(tiles * cap));
+    HIP_TRY(ctx->bins.ensure(want));
     ctx->bins_cap = cap;
+    ctx->bins_compact = compact;
   }
   if (ctx->bin_count.n == 0) {
     HIP_TRY(ctx->bin_count.ensure(kad::MAX_HIT_TILES_PUBLIC));
+    HIP_TRY(ctx->tile_start.ensure(kad::MAX_HIT_TILES_PUBLIC));
+    HIP_TRY(ctx->tile_fill.ensure(kad::MAX_HIT_TILES_PUBLIC));
     HIP_TRY(hipMemset(ctx->bin_count.p, 0, kad::MAX_HIT_TILES_PUBLIC * 4));
+    HIP_TRY(hipMemset(ctx->tile_fill.p, 0, kad::MAX_HIT_TILES_PUBLIC * 4));
   }
   return KAD_OK;
 }
@@ -365,26 +381,44 @@ kad::HitScratch hit_scratch(kad_ctx *ctx) {
   h.bins = ctx->bins.p;
   h.cap = ctx->bins_cap;
   h.bin_count = ctx->bin_count.p;
+  if (ctx->bins_compact) {
+    h.tile_start = ctx->tile_start.p;
+    h.tile_fill = ctx->tile_fill.p;
+  }
   return h;
 }
 
 // Enqueue the sampler on ids [first, first+count) into output set `set`, then the
 // copies of its flags and arcs (and, when timing, nodes and lengths) to the host
 // mirrors; nothing waits.
+// ovc: the graph's overflow class (kad::overflow_class): 0 = 128-bit counts always
+// suffice, 1 = resample overflowed samples wide, 2 = sample everything wide.
 kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                         uint64_t first, uint32_t count, uint32_t stride, int set,
-                        hipStream_t stream) {
+                        hipStream_t stream, int ovc) {
   OutSet &o = ctx->outs[set];
-  HIP_TRY(kad::launch_zero_u32(ctx->work.p, 1, stream));
-  const kad::LaunchShape shape = kad::graph_shape(g);
-  const uint32_t grid = kad::launch_grid(ctx, shape, count);
+  kad_status st = KAD_OK;
   HIP_TRY(hipEventRecord(o.k0, stream));
-  HIP_TRY(kad::launch_sampler(dev_view(g), kad::slot_view(ctx), seed, phase, first, count,
-                              ctx->work.p, o.view(stride), grid, shape, stream));
-  HIP_TRY(hipEventRecord(o.k1, stream));
-  kad_status st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count,
-                                   o.view(stride), o.h_nwide.p, stream);
-  if (st) return st;
+  if (ovc == 2) {
+    st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, true,
+                          o.view(stride), o.h_nwide.p, stream);
+    if (st) return st;
+    HIP_TRY(hipEventRecord(o.k1, stream));
+  } else {
+    HIP_TRY(kad::launch_zero_u32(ctx->work.p, 1, stream));
+    const kad::LaunchShape shape = kad::graph_shape(g);
+    const uint32_t grid = kad::launch_grid(ctx, shape, count);
+    HIP_TRY(kad::launch_sampler(dev_view(g), kad::slot_view(ctx), seed, phase, first, count,
+                                ctx->work.p, o.view(stride), grid, shape, stream));
+    HIP_TRY(hipEventRecord(o.k1, stream));
+    if (ovc == 1) {
+      st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, false,
+                            o.view(stride), o.h_nwide.p, stream);
+      if (st) return st;
+    } else {
+      o.h_nwide.p[0] = 0;
+    }
+  }
   HIP_TRY(hipMemcpyAsync(o.h_flags.p, o.flags.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(o.h_arcs.p, o.arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
   if (ctx->timing) {
@@ -508,6 +542,10 @@ kad_status kad_graph_create(kad_ctx *ctx, uint32_t n, uint64_t arcs, int directe
     g->rrow.swap(trow);
     g->rcol.swap(tcol);
   }
+  for (uint32_t v = 0; v < n; ++v) {
+    g->maxdeg = std::max(g->maxdeg, g->row[v + 1] - g->row[v]);
+    if (g->directed) g->maxdeg = std::max(g->maxdeg, g->rrow[v + 1] - g->rrow[v]);
+  }
   const bool borrow = mem == KAD_MEM_DEVICE;
   const size_t rbytes = ((size_t)n + 1) * 4, cbytes = (size_t)arcs * 4;
   if (borrow) {
@@ -630,6 +668,7 @@ kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uin
   kad_status st = graph_vd(gm, &vd, &ex);
   if (st) return st;
   const uint32_t stride = std::max<uint32_t>(vd, 2);
+  const int ovc = kad::overflow_class(g, vd, true);
   const uint32_t batch = std::min<uint32_t>(std::max<uint32_t>(count, 1), DEFAULT_BATCH);
   if ((st = ensure_capacity(ctx, g->n, batch, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
@@ -641,7 +680,7 @@ kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uin
   bool short_buf = false;
   for (uint64_t done = 0; done < count;) {
     const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
-    if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream))) return st;
+    if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream, ovc))) return st;
     HIP_TRY(hipMemcpyAsync(ctx->h_s.p, o.s.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipMemcpyAsync(ctx->h_t.p, o.t.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipMemcpyAsync(o.h_len.p, o.len.p, (size_t)nb * 4, hipMemcpyDeviceToHost, stream));
@@ -683,6 +722,7 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
   kad_status st = graph_vd(gm, &vd, &ex);
   if (st) return st;
   const uint32_t stride = std::max<uint32_t>(vd, 2);
+  const int ovc = kad::overflow_class(g, vd, true);
   const uint32_t batch = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(count, 1), DEFAULT_BATCH);
   if ((st = ensure_capacity(ctx, g->n, batch, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
@@ -690,7 +730,7 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
   uint64_t arcs = 0;
   for (uint64_t done = 0; done < count;) {
     const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
-    if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream))) return st;
+    if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream, ovc))) return st;
     HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, g->n,
                                    ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
     if ((st = finish_batch(ctx, 0, nb, nb))) return st;
@@ -736,6 +776,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   if (K > (1u << 30)) return fail(KAD_EINVAL, "kernel_batch too large");
   const uint32_t chunks_per_batch = (uint32_t)(K / B);
   const uint32_t stride = std::max<uint32_t>(vd, 2);
+  const int ovc = kad::overflow_class(g, vd, p->vd_override == 0);
   if ((st = ensure_capacity(ctx, n, (uint32_t)K, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
   const auto t_setup = clock::now();
@@ -752,7 +793,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       for (uint32_t k = 0; k < pilot_last; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
     }
     const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, alpha - done);
-    if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream))) return st;
+    if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream, ovc))) return st;
     HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
                                    ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
     pilot_last = nb;
@@ -769,7 +810,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   const uint32_t first_nb = (uint32_t)std::min<uint64_t>(
       omega, std::min<uint64_t>(K, std::max<uint64_t>(B, (omega / 2 + B - 1) / B * B)));
   HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[first_set].reduced, 0));
-  if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream))) {
+  if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream, ovc))) {
     (void)hipEventDestroy(pilot_done);
     return st;
   }
@@ -857,7 +898,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       next_nb = (uint32_t)std::min<uint64_t>(round_up(want), omega - launched);
       const int nxt = 1 - cur;
       HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[nxt].reduced, 0));
-      kad_status s2 = launch_batch(ctx, g, p->seed, 1, launched, next_nb, stride, nxt, stream);
+      kad_status s2 = launch_batch(ctx, g, p->seed, 1, launched, next_nb, stride, nxt, stream, ovc);
       if (s2) return s2;
       launched += next_nb;
       return KAD_OK;
@@ -997,6 +1038,7 @@ kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *
   kad_status st = graph_vd(g, &vd, &ex);
   if (st) return st;
   const uint32_t stride = std::max<uint32_t>(vd, 2);
+  const int ovc = kad::overflow_class(g, vd, true);
   if ((st = ensure_capacity(ctx, g->n, samples, stride))) return st;
   const kad::LaunchShape saved = g->shape;
   const bool saved_set = g->shape_set;
@@ -1006,7 +1048,7 @@ kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *
   auto time_shape = [&](double *t_min) -> kad_status {
     *t_min = 1e300;
     for (int rep = 0; rep < 2; ++rep) {  // the faster of two launches
-      kad_status s2 = launch_batch(ctx, g, 1, 1, 0, samples, stride, 0, ctx->stream);
+      kad_status s2 = launch_batch(ctx, g, 1, 1, 0, samples, stride, 0, ctx->stream, ovc);
       if (s2) return s2;
       HIP_TRY(hipStreamSynchronize(ctx->stream));
       float ms = 0.f;

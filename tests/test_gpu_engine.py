@@ -59,6 +59,7 @@ def _mix():
         (gg.gnp(400, 0.02, 5, True), dict(epsilon=0.015, delta=0.1, seed=11)),
         (gg.grid(30, 30), dict(epsilon=0.02, delta=0.1, seed=4)),
         (gg.damaged_grid(120, 120, 0.05, 5), dict(epsilon=0.03, delta=0.1, seed=4)),
+        (gg.damaged_grid(150, 150, 0.05, 6), dict(epsilon=0.05, delta=0.1, seed=8)),
     ]
 
 

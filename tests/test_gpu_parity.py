@@ -159,6 +159,14 @@ def test_paths_grid_wide_counts(kad, ctx, orc):
     assert (d >= 300).sum() >= 20  # far beyond 128-bit counts
 
 
+def test_paths_high_diameter_all_wide(kad, ctx, orc):
+    """A damaged grid with vertex diameter above 256: every sample goes straight to the
+    wide-count kernel (no 128-bit attempt first); parity is unchanged."""
+    g = gg.damaged_grid(200, 200, 0.05, 7)
+    _compare_paths(kad, ctx, orc, g, 6, 1, 0, 300)
+    _compare_paths(kad, ctx, orc, g, 6, 0, 1000, 100)
+
+
 def test_hit_counts_wide(kad, ctx, orc):
     g = gg.damaged_grid(150, 150, 0.05, 3)
     G = kad.Graph(ctx, g)
