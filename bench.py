@@ -17,6 +17,13 @@ Other workloads (--workload):
             one step = all 256 adaptive runs through the multi-query engine
             (kad_run_batch); the same 256 runs one after another through kad_run are
             timed beside it, and the results are checked identical.
+  serve     the serving workload: 33 resident graphs (er2000, cl1m, 30 Chung-Lu graphs of
+            1e4..1e6 nodes, the 2000x2000 grid with 5% of edges deleted), a Poisson stream
+            of --queries queries at --rate per second (seed 7), each on a uniformly drawn
+            graph, all-nodes or top-k (k in {10, 100}) with epsilon uniform in
+            [0.002, 0.02], delta 0.1, through kad_server_*.  Latency = submit to result,
+            measured by the server.  Queries still running --drain seconds after the
+            last arrival are canceled and counted with their age as a lower bound.
 
 Prints one JSON line.  value = sampled shortest paths per second over the timed steps
 (pilot + main-phase samples that enter the result; samples computed past the stopping
@@ -154,6 +161,132 @@ def bench_batch(args, torch, gg, kad):
     print(json.dumps(out), flush=True)
 
 
+def _pct(xs, q):
+    import numpy as np
+    return float(np.percentile(np.asarray(xs, dtype=np.float64), q)) if len(xs) else None
+
+
+def bench_serve(args, torch, gg, kad):
+    """Serving: Poisson query stream through kad_server_* over resident graphs."""
+    grid_id = gg.SERVE_GRAPHS - 1
+    ids = [i for i in range(gg.SERVE_GRAPHS) if not (args.exclude_grid and i == grid_id)]
+    t0 = time.perf_counter()
+    csrs = {i: gg.serve_graph(i) for i in ids}
+    print(f"[bench] {len(csrs)} graphs, {sum(g.n for g in csrs.values())} nodes, "
+          f"{sum(g.arcs for g in csrs.values())} arcs ({time.perf_counter() - t0:.1f} s)",
+          file=sys.stderr, flush=True)
+    ctx = kad.Context(0)
+    Gs = {i: kad.Graph(ctx, g) for i, g in csrs.items()}
+    stream = [q for q in gg.serve_queries(args.queries, rate=args.rate, seed=7,
+                                          graphs=gg.SERVE_GRAPHS) if q["graph"] in Gs]
+    # warm-up: one light query per graph (vertex diameters, slot state, counter pools)
+    t0 = time.perf_counter()
+    with kad.Server(ctx) as srv:
+        ts = [srv.submit(G, epsilon=0.1, delta=0.1, seed=99) for G in Gs.values()]
+        for t in ts:
+            srv.wait(t)
+    print(f"[bench] warm-up {time.perf_counter() - t0:.1f} s", file=sys.stderr, flush=True)
+
+    srv = kad.Server(ctx)
+    pending = {}   # ticket -> (query, host submit time)
+    done = []      # (query, result)
+    canceled = []  # (query, age at cancel)
+
+    def collect():
+        for t in list(pending):
+            try:
+                r = srv.poll(t)
+            except kad.KadError as e:
+                q, ts_ = pending.pop(t)
+                canceled.append((q, time.perf_counter() - ts_, e.status))
+                continue
+            if r is not None:
+                done.append((pending.pop(t)[0], r))
+
+    start = time.perf_counter()
+    next_report = start + 10.0
+    for q in stream:
+        while True:
+            now = time.perf_counter()
+            if now >= start + q["t"]:
+                break
+            collect()
+            time.sleep(min(0.002, start + q["t"] - now))
+        kw = dict(epsilon=q["epsilon"], delta=q["delta"], seed=q["seed"])
+        if q["mode"] == "topk":
+            kw.update(mode="topk", k=q["k"])
+        t = srv.submit(Gs[q["graph"]], **kw)
+        pending[t] = (q, time.perf_counter())
+        if time.perf_counter() > next_report:
+            print(f"[bench] t={time.perf_counter() - start:.0f} s submitted {len(done) + len(pending) + len(canceled)}"
+                  f" done {len(done)}", file=sys.stderr, flush=True)
+            next_report += 10.0
+    last_arrival = time.perf_counter()
+    while pending and time.perf_counter() < last_arrival + args.drain:
+        collect()
+        time.sleep(0.005)
+        if time.perf_counter() > next_report:
+            print(f"[bench] draining: {len(pending)} running", file=sys.stderr, flush=True)
+            next_report += 10.0
+    cut = time.perf_counter()
+    unfinished = [(q, cut - ts_) for t, (q, ts_) in pending.items()]
+    srv.cancel()
+    for t in list(pending):
+        try:
+            srv.wait(t, timeout=60.0)
+        except kad.KadError:
+            pass
+    st = srv.stats()
+    srv.close()
+    elapsed = cut - start
+    lat = [r["seconds"] for _, r in done]
+    lower = lat + [age for _, age in unfinished]
+    paths = sum(r["alpha"] + r["tau"] for _, r in done)
+
+    def cls(pred):
+        xs = [r["seconds"] for q, r in done if pred(q)]
+        ys = [age for q, age in unfinished if pred(q)]
+        return {"completed": len(xs), "unfinished": len(ys), "p50_s": _pct(xs + ys, 50),
+                "p99_s": _pct(xs + ys, 99)}
+
+    p99 = _pct(lower, 99)
+    out = {
+        "metric": "p99 query latency",
+        "value": p99,
+        "unit": "s",
+        "n_gpus": 1, "steps": 1, "warmup": 1,
+        "ms_per_step": elapsed * 1e3,
+        "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+        "dtype": "u128", "data": "synthetic",
+        "config": {"workload": f"serving: {len(Gs)} resident graphs, {len(stream)} queries at "
+                               f"{args.rate}/s (Poisson, seed 7), all-nodes or top-k k in "
+                               "{10,100}, epsilon U[0.002,0.02], delta 0.1"
+                               + (", grid excluded" if args.exclude_grid else "")},
+        "p50_s": _pct(lower, 50), "p99_s": p99, "mean_s": float(sum(lower) / max(len(lower), 1)),
+        "p99_is_lower_bound": bool(unfinished) and p99 is not None and p99 >= min(a for _, a in unfinished),
+        "completed": len(done), "unfinished_at_cutoff": len(unfinished),
+        "cutoff_s": elapsed, "queries_per_s": len(done) / elapsed,
+        "sampled_paths_per_s": paths / elapsed,
+        "server": st,
+        "by_class": {"all_nodes": cls(lambda q: q["mode"] == "all"),
+                     "topk": cls(lambda q: q["mode"] == "topk"),
+                     "grid": cls(lambda q: q["graph"] == grid_id),
+                     "not_grid": cls(lambda q: q["graph"] != grid_id)},
+    }
+    for q, age in sorted(unfinished, key=lambda x: -x[1])[:12]:
+        print(f"[bench] unfinished: graph {q['graph']} (n={csrs[q['graph']].n}) {q['mode']} "
+              f"k={q['k']} eps={q['epsilon']:.4f} age {age:.1f} s", file=sys.stderr, flush=True)
+    slow = sorted(done, key=lambda x: -x[1]["seconds"])[:8]
+    for q, r in slow:
+        print(f"[bench] slowest: graph {q['graph']} (n={csrs[q['graph']].n}) {q['mode']} "
+              f"k={q['k']} eps={q['epsilon']:.4f} {r['seconds']:.2f} s tau={r['tau']} "
+              f"omega={r['omega']} queued {r['seconds_setup']:.2f} s", file=sys.stderr, flush=True)
+    for G in Gs.values():
+        G.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -167,6 +300,12 @@ def main():
     ap.add_argument("--check-interval", type=int, default=0)
     ap.add_argument("--cpu-samples", type=int, default=20000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--queries", type=int, default=1000, help="serve: queries in the stream")
+    ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
+    ap.add_argument("--drain", type=float, default=30.0,
+                    help="serve: seconds after the last arrival before running queries are canceled")
+    ap.add_argument("--exclude-grid", action="store_true",
+                    help="serve: leave the 2000x2000 grid (and its queries) out")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM counters)")
     args = ap.parse_args()
@@ -193,6 +332,8 @@ def main():
         return
     if args.workload == "batch256":
         return bench_batch(args, torch, gg, kad)
+    if args.workload == "serve":
+        return bench_serve(args, torch, gg, kad)
     t0 = time.perf_counter()
     csr = gg.workload(args.workload)
     gen_s = time.perf_counter() - t0

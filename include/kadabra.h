@@ -191,8 +191,13 @@ kad_status kad_server_wait(kad_server *srv, uint64_t ticket, kad_result *r, doub
 /* Completed queries, sampler launches and samples launched so far (any may be NULL). */
 kad_status kad_server_stats(kad_server *srv, uint64_t *completed, uint64_t *launches,
                             uint64_t *samples);
+/* Cancel every query submitted so far that has not completed: poll/wait then report
+ * KAD_ECANCELED for it (samples already on the GPU drain first).  The server keeps
+ * serving later submissions. */
+kad_status kad_server_cancel(kad_server *srv);
 /* Stop the server: queries not yet admitted are dropped (their waiters get
- * KAD_ECANCELED), admitted ones finish first; unretrieved results are discarded. */
+ * KAD_ECANCELED), admitted ones finish first (cancel them before to stop sooner);
+ * unretrieved results are discarded. */
 kad_status kad_server_destroy(kad_server *srv);
 
 /* ---------------------------------------------------------------- sampling primitives */

@@ -101,6 +101,7 @@ def lib():
         "kad_server_poll": ([vp, u64, C.POINTER(_Result)], st),
         "kad_server_wait": ([vp, u64, C.POINTER(_Result), dbl], st),
         "kad_server_stats": ([vp, vp, vp, vp], st),
+        "kad_server_cancel": ([vp], st),
         "kad_server_destroy": ([vp], st),
         "kad_graph_set_launch": ([vp, u32, u32], st),
         "kad_graph_get_launch": ([vp, vp, vp], st),
@@ -376,6 +377,10 @@ class Server:
         del self._pending[ticket]
         _check(rc)
         return _collect(r, arrs, topk)
+
+    def cancel(self):
+        """Cancel every query not yet completed (their results report KAD_ECANCELED)."""
+        _check(lib().kad_server_cancel(self.handle))
 
     def stats(self) -> dict:
         v = [C.c_uint64() for _ in range(3)]

@@ -31,9 +31,9 @@ DEVICE = [f"--offload-arch={ARCH}", "-Xclang", "-target-feature", "-Xclang", "-p
 def _compile(src: str) -> str:
     obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
     path = os.path.join(CSRC, src)
-    cmd = [HIPCC] + COMMON
+    cmd = [HIPCC] + COMMON + DEVICE  # host-only sources hold no kernels
     if src.endswith(".hip"):
-        cmd += DEVICE + ["-x", "hip"]
+        cmd += ["-x", "hip"]
     else:
         cmd += ["-D__HIP_PLATFORM_AMD__"]
     cmd += ["-c", path, "-o", obj]

@@ -134,6 +134,13 @@ hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t
 
 // Zero a device buffer with a kernel (no memset node when captured).
 hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream);
+// dst[i] = src[i], i < count, by a kernel on `stream`; either side may be pinned,
+// coherent host memory.  Used instead of runtime copies where a copy must not wait
+// behind kernels of other streams.
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t count,
+                              hipStream_t stream);
+hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t count,
+                              hipStream_t stream);
 // p[i] = value for i < count.
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 

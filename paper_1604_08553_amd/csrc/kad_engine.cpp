@@ -22,6 +22,11 @@
 // While tick t runs on the GPU the host evaluates tick t-1's checks.  A query that
 // stops has samples past its stopping point in flight: their hits are subtracted
 // again before its counters are read, as in the single run.
+//
+// Two lanes of ticks run side by side, each with its own streams, sampler slots and
+// reduction scratch: lane 0 for most graphs, lane 1 for high-diameter graphs whose
+// samples all take the (slow) wide-count kernel, so that those never hold up the
+// queries of lane 0.  Lane 1's running tick is polled, never waited on.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -50,6 +55,10 @@ constexpr uint64_t POOL_IDS = (uint64_t)POOL_TILES * HIT_TILE_IDS;    // 2^25 no
 constexpr uint32_t TICK_SAMPLES = 1u << 18;    // samples per engine launch, at most
 constexpr uint64_t TICK_PATH_BYTES = 1ull << 30;  // path buffer of one launch, at most
 constexpr uint32_t MAX_LAYERS = 64;            // check intervals of one query per launch
+constexpr uint32_t MAX_PIECES = 1u << 16;      // segments of one launch
+// Buffers of a running engine are sized once (or grow by doubling, their old storage
+// released only while nothing runs): freeing device memory waits for the whole
+// device, which would stall one lane behind the other.
 
 enum class QState { Queued, Pilot, Main, Final, Done };
 // Pilot: pilot samples; PilotLast: the last ones (snapshot = count0, then the
@@ -70,6 +79,7 @@ struct Query {
   uint32_t n = 0, vd = 0, stride = 2;
   bool vd_exact = false;
   int ovc = 1;  // overflow_class of the graph
+  int lane = 0;
   uint64_t omega = 0, alpha = 0, B = 0, K = 0;
   double eb = 0.001;
   // counter pool slice: node v of the query is pool id base() + v
@@ -86,7 +96,6 @@ struct Query {
   std::vector<uint64_t> count0;
   std::vector<double> lam_l, lam_u, L_l, L_u;
   std::unique_ptr<StopChecker> checker;
-  std::vector<uint32_t> gdev;  // group ids shifted to the pool (uploaded once)
   double C = 0.0;
   // results: o_* point into the caller's arrays (direct) or into the vectors
   hipEvent_t final_ev = nullptr;
@@ -112,6 +121,7 @@ struct Piece {
 
 struct Tick {
   OutSet out;
+  DevBuf<uint32_t> wlist, wcnt;  // wide-count resampling: list, length and work counter
   DevBuf<SampleSeg> d_segs;
   PinBuf<SampleSeg> h_segs;
   DevBuf<GatherDesc> d_gat;
@@ -136,19 +146,47 @@ struct Tick {
   }
 };
 
+struct Lane {
+  Tick ticks[2];
+  int cur = 0;                      // ticks[cur] is the next to fill
+  hipStream_t s = nullptr, rs = nullptr;
+  bool own_streams = false;
+  DevBuf<uint32_t> bins, bin_count, tile_start, tile_fill;  // compact hit reduction
+  uint64_t bins_cap = 0;
+  uint32_t slot0 = 0, nslots = 0;   // sampler slots
+  uint32_t wslot0 = 0, nwslots = 0; // wide-count slots (arena and slot arrays of that index)
+  bool busy() const { return ticks[0].in_flight || ticks[1].in_flight; }
+  HitScratch scratch() const {
+    HitScratch h;
+    h.bins = bins.p;
+    h.cap = bins_cap;
+    h.bin_count = bin_count.p;
+    h.tile_start = tile_start.p;
+    h.tile_fill = tile_fill.p;
+    return h;
+  }
+};
+
 }  // namespace
 
 class Engine {
  public:
   explicit Engine(kad_ctx *c) : ctx_(c) {}
   ~Engine() {
-    (void)hipStreamSynchronize(ctx_->stream);
-    (void)hipStreamSynchronize(ctx_->rstream);
+    release_graveyard();
+    for (Lane &L : lanes_) {
+      if (L.s) (void)hipStreamSynchronize(L.s);
+      if (L.rs) (void)hipStreamSynchronize(L.rs);
+      if (L.own_streams) {
+        (void)hipStreamDestroy(L.s);
+        (void)hipStreamDestroy(L.rs);
+      }
+    }
   }
   kad_status init();
   void enqueue(Query *q) { queue_.push_back(q); }
   bool busy() const {
-    return !queue_.empty() || !active_.empty() || ticks_[0].in_flight || ticks_[1].in_flight;
+    return !queue_.empty() || !active_.empty() || lanes_[0].busy() || lanes_[1].busy();
   }
   // One round: admit queued queries, launch a tick, evaluate the previous one, and
   // complete stopped queries whose counters have landed.
@@ -158,40 +196,64 @@ class Engine {
     d.swap(done_);
     return d;
   }
+  // Stop every admitted query (status KAD_ECANCELED; its in-flight samples drain
+  // normally) and drop the queued ones.
+  kad_status cancel_all();
   uint64_t ticks_launched() const { return ticks_launched_.load(); }
   uint64_t samples_launched() const { return samples_launched_.load(); }
 
  private:
   kad_status prepare(Query *q);
   kad_status admit();
-  kad_status build(Tick &t);
-  kad_status launch(Tick &t);
-  kad_status process(Tick &t, Tick &other);
-  kad_status stop_query(Query *q, Tick &t, size_t after_piece, Tick &other);
+  kad_status build(int li, Tick &t);
+  kad_status launch(Lane &L, Tick &t);
+  kad_status process(Lane &L, Tick &t, Tick &other);
+  kad_status stop_query(Query *q, Lane &L, Tick &t, size_t after_piece, Tick &other);
   kad_status finalize(bool block);
-  kad_status reduce(const Tick &t, uint32_t begin, uint32_t count, bool subtract);
+  kad_status reduce(const Lane &L, const Tick &t, uint32_t begin, uint32_t count, bool subtract);
   void release_tiles(Query *q);
   void finish_failed(Query *q, kad_status st, const std::string &msg);
-  HitScratch scratch() {
-    HitScratch h;
-    h.bins = bins_.p;
-    h.cap = bins_cap_;
-    h.bin_count = bin_count_.p;
-    h.tile_start = tile_start_.p;
-    h.tile_fill = tile_fill_.p;
-    return h;
+  void layout();
+  SlotState lane_slots(const Lane &L, bool wide) const;
+  WideState lane_wide(const Lane &L) const;
+  static bool tick_complete(const Tick &t);
+  // Double a buffer's capacity (at least to n) without freeing: the old storage is
+  // released by release_graveyard() once no lane runs.
+  template <typename T>
+  void grow(DevBuf<T> &b, size_t n) {
+    if (b.p) grave_dev_.push_back(b.p);
+    b.p = nullptr;
+    const size_t want = std::max(n, 2 * b.n);
+    b.n = 0;
+    if (hipMalloc((void **)&b.p, want * sizeof(T)) == hipSuccess) b.n = want;
+    else b.p = nullptr;
   }
+  template <typename T>
+  void grow(PinBuf<T> &b, size_t n) {
+    if (b.p) grave_host_.push_back(b.p);
+    b.p = nullptr;
+    const size_t want = std::max(n, 2 * b.n);
+    b.n = 0;
+    if (hipHostMalloc((void **)&b.p, want * sizeof(T), hipHostMallocCoherent) == hipSuccess) b.n = want;
+    else b.p = nullptr;
+  }
+  void release_graveyard() {
+    for (void *p : grave_dev_) (void)hipFree(p);
+    for (void *p : grave_host_) (void)hipHostFree(p);
+    grave_dev_.clear();
+    grave_host_.clear();
+  }
+  std::vector<void *> grave_dev_, grave_host_;
 
   kad_ctx *ctx_;
   DevBuf<uint64_t> count_pool_, gmax_pool_;
   PinBuf<uint64_t> final_pool_;  // host landing area of stopped queries' counters
+  PinBuf<uint32_t> group_stage_; // pinned staging of group ids (a pageable copy would wait)
   DevBuf<uint32_t> group_pool_;
   std::vector<uint8_t> tile_used_;
   uint32_t tiles_hw_ = 0;  // reductions cover pool tiles [0, tiles_hw_)
-  DevBuf<uint32_t> bins_, bin_count_, tile_start_, tile_fill_;
-  uint64_t bins_cap_ = 0;
-  Tick ticks_[2];
-  int cur_ = 0;
+  Lane lanes_[2];
+  bool split_ = false;  // lane 1 in use
   uint64_t tick_id_ = 0;
   std::deque<Query *> queue_;
   std::vector<Query *> active_;
@@ -206,20 +268,80 @@ kad_status Engine::init() {
   HIP_TRY(gmax_pool_.ensure(POOL_IDS));
   HIP_TRY(group_pool_.ensure(POOL_IDS));
   HIP_TRY(final_pool_.ensure(POOL_IDS));
+  HIP_TRY(group_stage_.ensure(POOL_IDS));
   HIP_TRY(hipMemsetAsync(count_pool_.p, 0, POOL_IDS * 8, ctx_->rstream));
   HIP_TRY(hipMemsetAsync(group_pool_.p, 0, POOL_IDS * 4, ctx_->rstream));
-  HIP_TRY(bin_count_.ensure(POOL_TILES));
-  HIP_TRY(tile_start_.ensure(POOL_TILES));
-  HIP_TRY(tile_fill_.ensure(POOL_TILES));
-  HIP_TRY(hipMemsetAsync(bin_count_.p, 0, POOL_TILES * 4, ctx_->rstream));
-  HIP_TRY(hipMemsetAsync(tile_fill_.p, 0, POOL_TILES * 4, ctx_->rstream));
+  lanes_[0].s = ctx_->stream;
+  lanes_[0].rs = ctx_->rstream;
+  HIP_TRY(hipStreamCreateWithFlags(&lanes_[1].s, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&lanes_[1].rs, hipStreamNonBlocking));
+  lanes_[1].own_streams = true;
+  for (Lane &L : lanes_) {
+    HIP_TRY(L.bin_count.ensure(POOL_TILES));
+    HIP_TRY(L.tile_start.ensure(POOL_TILES));
+    HIP_TRY(L.tile_fill.ensure(POOL_TILES));
+    HIP_TRY(hipMemsetAsync(L.bin_count.p, 0, POOL_TILES * 4, ctx_->rstream));
+    HIP_TRY(hipMemsetAsync(L.tile_fill.p, 0, POOL_TILES * 4, ctx_->rstream));
+    for (Tick &t : L.ticks) {
+      HIP_TRY(t.work.ensure(1));
+      HIP_TRY(t.wcnt.ensure(2));
+      HIP_TRY(hipEventCreateWithFlags(&t.sampled, hipEventDisableTiming));
+    }
+  }
   HIP_TRY(hipStreamSynchronize(ctx_->rstream));
   tile_used_.assign(POOL_TILES, 0);
-  for (Tick &t : ticks_) {
-    HIP_TRY(t.work.ensure(1));
-    HIP_TRY(hipEventCreateWithFlags(&t.sampled, hipEventDisableTiming));
-  }
+  layout();
   return KAD_OK;
+}
+
+// Lane 1 takes 3/4 of the wide-count slots; lane 0 keeps the rest of them for its
+// overflowed samples and the sampler slots past all of them.  Without enough slots,
+// lane 0 alone serves everything.
+void Engine::layout() {
+  const uint32_t W = ctx_->w_slots ? std::min(ctx_->w_slots, ctx_->slots) : 0, S = ctx_->slots;
+  Lane &a = lanes_[0], &b = lanes_[1];
+  split_ = W >= 4 && S >= W + 64;
+  if (split_) {
+    b.wslot0 = 0;
+    b.nwslots = W * 3 / 4;
+    b.slot0 = 0;
+    b.nslots = 0;
+    a.wslot0 = b.nwslots;
+    a.nwslots = W - b.nwslots;
+    a.slot0 = W;
+    a.nslots = S - W;
+  } else {
+    a.wslot0 = 0;
+    a.nwslots = W;
+    a.slot0 = 0;
+    a.nslots = S;
+    b.nslots = b.nwslots = 0;
+  }
+}
+
+SlotState Engine::lane_slots(const Lane &L, bool wide) const {
+  SlotState st = slot_view(ctx_);
+  const size_t off = wide ? L.wslot0 : L.slot0, n = st.n;
+  st.tag += off * n;
+  st.visit += off * n;
+  st.sig += off * n * 2;
+  st.pi += off * (size_t)st.pi_cap;
+  st.slots = wide ? L.nwslots : L.nslots;
+  return st;
+}
+
+WideState Engine::lane_wide(const Lane &L) const {
+  WideState w = wide_view(ctx_);
+  w.arena += (size_t)L.wslot0 * w.arena_limbs;
+  w.lv += (size_t)L.wslot0 * 2 * w.max_lev * 4;
+  w.lbase += (size_t)L.wslot0 * 2 * w.max_lev;
+  w.slots = L.nwslots;
+  return w;
+}
+
+bool Engine::tick_complete(const Tick &t) {
+  if (hipEventQuery(t.out.copied) != hipSuccess) return false;
+  return t.layers == 0 || hipEventQuery(t.layer_ev[t.layers - 1]) == hipSuccess;
 }
 
 void Engine::finish_failed(Query *q, kad_status st, const std::string &msg) {
@@ -293,22 +415,27 @@ kad_status Engine::admit() {
       }
     }
     if (start == POOL_TILES) break;  // wait until running queries release counters
-    if (q->n > ctx_->slot_n) {
-      if (ticks_[0].in_flight || ticks_[1].in_flight) break;  // grow only when idle
-      HIP_TRY(hipStreamSynchronize(ctx_->rstream));
-      kad_status s = ensure_slots(ctx_, q->n);
+    const bool need_wide = q->ovc != 0 && ctx_->w_slots == 0;
+    if (q->n > ctx_->slot_n || need_wide) {
+      if (lanes_[0].busy() || lanes_[1].busy()) break;  // grow only when idle
+      for (Lane &L : lanes_) HIP_TRY(hipStreamSynchronize(L.rs));
+      kad_status s = q->n > ctx_->slot_n ? ensure_slots(ctx_, q->n) : KAD_OK;
+      if (!s && q->ovc != 0) s = ensure_wide(ctx_);
+      layout();
       if (s) {
         finish_failed(q, s, kad_last_error());
         continue;
       }
     }
+    q->lane = split_ && q->ovc == 2 ? 1 : 0;
     for (uint32_t t = start; t < start + need; ++t) tile_used_[t] = 1;
     q->tile0 = start;
     q->ntiles = need;
     tiles_hw_ = std::max(tiles_hw_, start + need);
     // until computeDelta assigns groups, every node maps to the query's first
     // group-maximum entry (rebuilt from the counters when the groups arrive)
-    HIP_TRY(launch_fill_u32(group_pool_.p + q->base(), q->n, (uint32_t)q->base(), ctx_->rstream));
+    HIP_TRY(launch_fill_u32(group_pool_.p + q->base(), q->n, (uint32_t)q->base(),
+                            lanes_[q->lane].rs));
     if (!q->final_ev) HIP_TRY(hipEventCreateWithFlags(&q->final_ev, hipEventDisableTiming));
     q->st = QState::Pilot;
     q->t_admit = clk::now();
@@ -318,7 +445,7 @@ kad_status Engine::admit() {
   return KAD_OK;
 }
 
-kad_status Engine::build(Tick &t) {
+kad_status Engine::build(int li, Tick &t) {
   t.pieces.clear();
   t.queries.clear();
   t.layer_piece.assign(1, 0);
@@ -328,13 +455,16 @@ kad_status Engine::build(Tick &t) {
   t.id = ++tick_id_;
   std::vector<std::vector<Piece>> layer(MAX_LAYERS + 1);
   uint32_t total = 0, stride = 2;
+  uint32_t npieces = 0;
   auto room = [&](const Query *q, uint64_t want) -> uint32_t {
     const uint32_t st = std::max(stride, q->stride);
     const uint64_t by_path = TICK_PATH_BYTES / (4ull * st);
     const uint64_t cap = std::min<uint64_t>(TICK_SAMPLES, by_path);
+    if (npieces >= MAX_PIECES) return 0u;
     return total >= cap ? 0u : (uint32_t)std::min<uint64_t>(want, cap - total);
   };
   auto add = [&](Query *q, uint32_t L, Kind kind, uint32_t cnt, uint64_t first) {
+    ++npieces;
     layer[L].push_back(Piece{q, kind, 0, cnt, first, ~0ull});
     total += cnt;
     stride = std::max(stride, q->stride);
@@ -347,7 +477,7 @@ kad_status Engine::build(Tick &t) {
   const size_t na = active_.size();
   for (size_t j = 0; j < na; ++j) {
     Query *q = active_[(rr_ + j) % na];
-    if (q->status != KAD_OK || q->st == QState::Final) continue;
+    if (q->lane != li || q->status != KAD_OK || q->st == QState::Final) continue;
     if (q->st == QState::Pilot) {
       if (q->pilot_launched >= q->alpha) continue;  // waiting for computeDelta
       const uint32_t cnt = room(q, std::min<uint64_t>(q->alpha - q->pilot_launched, TICK_SAMPLES / 2));
@@ -404,42 +534,40 @@ kad_status Engine::build(Tick &t) {
   return KAD_OK;
 }
 
-kad_status Engine::reduce(const Tick &t, uint32_t begin, uint32_t count, bool subtract) {
+kad_status Engine::reduce(const Lane &L, const Tick &t, uint32_t begin, uint32_t count,
+                          bool subtract) {
   HIP_TRY(launch_hit_reduce(t.out.path.p + (size_t)begin * t.stride, t.out.len.p + begin,
                             t.stride, count, tiles_hw_ * HIT_TILE_IDS, count_pool_.p, subtract,
                             subtract ? nullptr : group_pool_.p,
-                            subtract ? nullptr : gmax_pool_.p, scratch(), ctx_->rstream));
+                            subtract ? nullptr : gmax_pool_.p, L.scratch(), L.rs));
   return KAD_OK;
 }
 
-kad_status Engine::launch(Tick &t) {
-  hipStream_t s = ctx_->stream, rs = ctx_->rstream;
+kad_status Engine::launch(Lane &L, Tick &t) {
+  hipStream_t s = L.s, rs = L.rs;
   const uint32_t np = (uint32_t)t.pieces.size();
-  // buffers (the previous use of this tick's buffers is complete on the host side;
-  // device-side readers are fenced by out.reduced)
-  if (t.out.cap < t.total || t.out.stride < t.stride) {
-    if (t.out.reduced) HIP_TRY(hipEventSynchronize(t.out.reduced));
-    kad_status st = t.out.ensure(t.total, t.stride, rs);
-    if (st) return st;
-  } else {
-    kad_status st = t.out.ensure(t.total, t.stride, rs);
+  // fixed-size buffers, allocated on first use
+  {
+    kad_status st = t.out.ensure_entries(TICK_SAMPLES, TICK_PATH_BYTES / 4, rs);
     if (st) return st;
   }
-  HIP_TRY(t.d_segs.ensure(np));
-  HIP_TRY(t.h_segs.ensure(np));
+  HIP_TRY(t.d_segs.ensure(MAX_PIECES));
+  HIP_TRY(t.h_segs.ensure(MAX_PIECES));
+  HIP_TRY(t.d_gat.ensure(MAX_PIECES));
+  HIP_TRY(t.h_gat.ensure(MAX_PIECES));
+  HIP_TRY(t.wlist.ensure(TICK_SAMPLES));
+  if (L.bins.n == 0) {
+    HIP_TRY(L.bins.ensure(TICK_PATH_BYTES / 4));
+    L.bins_cap = TICK_PATH_BYTES / 4;
+  }
   uint64_t max_layer = 0;
-  for (uint32_t L = 0; L < t.layers; ++L) {
-    const Piece &a = t.pieces[t.layer_piece[L]];
-    const Piece &b = t.pieces[t.layer_piece[L + 1] - 1];
+  for (uint32_t ly = 0; ly < t.layers; ++ly) {
+    const Piece &a = t.pieces[t.layer_piece[ly]];
+    const Piece &b = t.pieces[t.layer_piece[ly + 1] - 1];
     max_layer = std::max<uint64_t>(max_layer, b.begin + b.count - a.begin);
   }
   const uint64_t need_bins = max_layer * std::max<uint32_t>(t.stride - 2, 1);
-  if (need_bins > bins_cap_) {
-    HIP_TRY(hipStreamSynchronize(rs));
-    bins_.release();
-    HIP_TRY(bins_.ensure(need_bins));
-    bins_cap_ = need_bins;
-  }
+  if (need_bins > L.bins_cap) return fail(KAD_EINVAL, "internal: hit bins too small");
   // segments
   bool wide = false;
   for (uint32_t j = 0; j < np; ++j) {
@@ -466,9 +594,9 @@ kad_status Engine::launch(Tick &t) {
   t.layer_blocks.clear();
   t.layer_snap.assign(1, 0);
   uint64_t snap = 0;
-  for (uint32_t L = 0; L < t.layers; ++L) {
+  for (uint32_t ly = 0; ly < t.layers; ++ly) {
     uint32_t blocks = 0;
-    for (uint32_t j = t.layer_piece[L]; j < t.layer_piece[L + 1]; ++j) {
+    for (uint32_t j = t.layer_piece[ly]; j < t.layer_piece[ly + 1]; ++j) {
       Piece &pc = t.pieces[j];
       GatherDesc d{};
       if (pc.kind == Kind::Pilot) continue;
@@ -496,11 +624,10 @@ kad_status Engine::launch(Tick &t) {
     t.layer_blocks.push_back(blocks);
     t.layer_snap.push_back(snap);
   }
-  HIP_TRY(t.d_gat.ensure(std::max<size_t>(gat.size(), 1)));
-  HIP_TRY(t.h_gat.ensure(std::max<size_t>(gat.size(), 1)));
   if (!gat.empty()) memcpy(t.h_gat.p, gat.data(), gat.size() * sizeof(GatherDesc));
-  HIP_TRY(t.d_snap.ensure(std::max<uint64_t>(snap, 1)));
-  HIP_TRY(t.h_snap.ensure(std::max<uint64_t>(snap, 1)));
+  if (t.d_snap.n < snap) grow(t.d_snap, snap);
+  if (t.h_snap.n < snap) grow(t.h_snap, snap);
+  if (!t.d_snap.p || !t.h_snap.p) return fail(KAD_ENOMEM, "snapshot buffers");
   while (t.layer_ev.size() < t.layers) {
     hipEvent_t e;
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -508,8 +635,9 @@ kad_status Engine::launch(Tick &t) {
   }
   // ---- sampler
   HIP_TRY(hipStreamWaitEvent(s, t.out.reduced, 0));
-  HIP_TRY(hipMemcpyAsync(t.d_segs.p, t.h_segs.p, (size_t)np * sizeof(SampleSeg),
-                         hipMemcpyHostToDevice, s));
+  static_assert(sizeof(SampleSeg) % 8 == 0 && sizeof(GatherDesc) % 8 == 0, "copied as words");
+  HIP_TRY(launch_copy_u64((uint64_t *)t.d_segs.p, (const uint64_t *)t.h_segs.p,
+                          (uint64_t)np * sizeof(SampleSeg) / 8, s));
   HIP_TRY(launch_zero_u32(t.work.p, 1, s));
   // launch shape of the graph with the most samples in this launch
   const kad_graph *major = nullptr;
@@ -525,45 +653,57 @@ kad_status Engine::launch(Tick &t) {
     }
   }
   const LaunchShape shape = graph_shape(major);
-  const uint32_t grid = launch_grid(ctx_, shape, t.total);
+  const bool wide_lane = &L == &lanes_[1];
   if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k0, s));
-  HIP_TRY(launch_sampler_multi(t.d_segs.p, np, slot_view(ctx_), t.total, t.work.p,
-                               t.out.view(t.stride), grid, shape, s));
-  if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
-  if (wide) {
-    kad_status st = launch_wide(ctx_, GraphDev{}, 0, 0, 0, t.d_segs.p, np, t.total, false,
-                                t.out.view(t.stride), t.out.h_nwide.p, s);
-    if (st) return st;
+  if (!wide_lane) {
+    int per_cu = 1;
+    for (int j = 0; j < 3; ++j)
+      if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx_->blocks_per_cu[j];
+    const uint32_t grid = (uint32_t)std::min<uint64_t>(
+        std::min<uint64_t>(L.nslots, (uint64_t)ctx_->cus * per_cu), t.total);
+    HIP_TRY(launch_sampler_multi(t.d_segs.p, np, lane_slots(L, false), t.total, t.work.p,
+                                 t.out.view(t.stride), grid, shape, s));
+  }
+  if (wide_lane || wide) {  // every sample of lane 1; the overflowed ones of lane 0
+    if (L.nwslots == 0) return fail(KAD_ENOMEM, "no wide-count slots for this launch");
+    HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, np, lane_slots(L, true),
+                            lane_wide(L), t.total, wide_lane, t.wlist.p, t.wcnt.p, t.wcnt.p + 1,
+                            t.out.view(t.stride), s));
+    if (wide_lane)
+      t.out.h_nwide.p[0] = t.total;
+    else
+      HIP_TRY(launch_copy_u32(t.out.h_nwide.p, t.wcnt.p, 1, s));
   } else {
     t.out.h_nwide.p[0] = 0;
   }
+  if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
   HIP_TRY(hipEventRecord(t.sampled, s));
-  HIP_TRY(hipMemcpyAsync(t.out.h_flags.p, t.out.flags.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));
-  HIP_TRY(hipMemcpyAsync(t.out.h_arcs.p, t.out.arcs.p, (size_t)t.total * 8, hipMemcpyDeviceToHost, s));
+  // host copies by kernels: runtime copies were seen waiting for the other lane's kernels
+  HIP_TRY(launch_copy_u32(t.out.h_flags.p, t.out.flags.p, t.total, s));
+  HIP_TRY(launch_copy_u64(t.out.h_arcs.p, t.out.arcs.p, t.total, s));
   if (ctx_->timing) {
-    HIP_TRY(hipMemcpyAsync(t.out.h_nodes.p, t.out.nodes.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));
-    HIP_TRY(hipMemcpyAsync(t.out.h_len.p, t.out.len.p, (size_t)t.total * 4, hipMemcpyDeviceToHost, s));
+    HIP_TRY(launch_copy_u32(t.out.h_nodes.p, t.out.nodes.p, t.total, s));
+    HIP_TRY(launch_copy_u32(t.out.h_len.p, t.out.len.p, t.total, s));
   }
   HIP_TRY(hipEventRecord(t.out.copied, s));
   // ---- per layer: hits into the pool, then the snapshot of each query's check
   HIP_TRY(hipStreamWaitEvent(rs, t.sampled, 0));
   if (!gat.empty())
-    HIP_TRY(hipMemcpyAsync(t.d_gat.p, t.h_gat.p, gat.size() * sizeof(GatherDesc),
-                           hipMemcpyHostToDevice, rs));
-  for (uint32_t L = 0; L < t.layers; ++L) {
-    const Piece &a = t.pieces[t.layer_piece[L]];
-    const Piece &b = t.pieces[t.layer_piece[L + 1] - 1];
-    kad_status st = reduce(t, a.begin, b.begin + b.count - a.begin, false);
+    HIP_TRY(launch_copy_u64((uint64_t *)t.d_gat.p, (const uint64_t *)t.h_gat.p,
+                            gat.size() * sizeof(GatherDesc) / 8, rs));
+  for (uint32_t ly = 0; ly < t.layers; ++ly) {
+    const Piece &a = t.pieces[t.layer_piece[ly]];
+    const Piece &b = t.pieces[t.layer_piece[ly + 1] - 1];
+    kad_status st = reduce(L, t, a.begin, b.begin + b.count - a.begin, false);
     if (st) return st;
-    const uint32_t g0 = t.layer_gat[L], g1 = t.layer_gat[L + 1];
+    const uint32_t g0 = t.layer_gat[ly], g1 = t.layer_gat[ly + 1];
     if (g1 > g0) {
-      HIP_TRY(launch_gather(t.d_gat.p + g0, g1 - g0, t.layer_blocks[L], count_pool_.p,
+      HIP_TRY(launch_gather(t.d_gat.p + g0, g1 - g0, t.layer_blocks[ly], count_pool_.p,
                             gmax_pool_.p, t.d_snap.p, rs));
-      const uint64_t s0 = t.layer_snap[L], s1 = t.layer_snap[L + 1];
-      HIP_TRY(hipMemcpyAsync(t.h_snap.p + s0, t.d_snap.p + s0, (s1 - s0) * 8,
-                             hipMemcpyDeviceToHost, rs));
+      const uint64_t s0 = t.layer_snap[ly], s1 = t.layer_snap[ly + 1];
+      HIP_TRY(launch_copy_u64(t.h_snap.p + s0, t.d_snap.p + s0, s1 - s0, rs));
     }
-    HIP_TRY(hipEventRecord(t.layer_ev[L], rs));
+    HIP_TRY(hipEventRecord(t.layer_ev[ly], rs));
   }
   t.in_flight = true;
   ticks_launched_++;
@@ -573,22 +713,21 @@ kad_status Engine::launch(Tick &t) {
 
 // A query stops after piece `at` of tick t: its hits from later pieces of t and from
 // the tick in flight are subtracted, then its counters are read and reset.
-kad_status Engine::stop_query(Query *q, Tick &t, size_t at, Tick &other) {
-  hipStream_t rs = ctx_->rstream;
+kad_status Engine::stop_query(Query *q, Lane &L, Tick &t, size_t at, Tick &other) {
+  hipStream_t rs = L.rs;
   if (q->status == KAD_OK) {
     for (size_t j = at + 1; j < t.pieces.size(); ++j)
       if (t.pieces[j].q == q) {
-        kad_status st = reduce(t, t.pieces[j].begin, t.pieces[j].count, true);
+        kad_status st = reduce(L, t, t.pieces[j].begin, t.pieces[j].count, true);
         if (st) return st;
       }
     if (other.in_flight)
       for (const Piece &pc : other.pieces)
         if (pc.q == q) {
-          kad_status st = reduce(other, pc.begin, pc.count, true);
+          kad_status st = reduce(L, other, pc.begin, pc.count, true);
           if (st) return st;
         }
-    HIP_TRY(hipMemcpyAsync(final_pool_.p + q->base(), count_pool_.p + q->base(),
-                           (size_t)q->n * 8, hipMemcpyDeviceToHost, rs));
+    HIP_TRY(launch_copy_u64(final_pool_.p + q->base(), count_pool_.p + q->base(), q->n, rs));
   }
   HIP_TRY(launch_zero_u32((uint32_t *)(count_pool_.p + q->base()), 2ull * q->n, rs));
   HIP_TRY(hipEventRecord(q->final_ev, rs));
@@ -597,8 +736,8 @@ kad_status Engine::stop_query(Query *q, Tick &t, size_t at, Tick &other) {
   return KAD_OK;
 }
 
-kad_status Engine::process(Tick &t, Tick &other) {
-  hipStream_t rs = ctx_->rstream;
+kad_status Engine::process(Lane &L, Tick &t, Tick &other) {
+  hipStream_t rs = L.rs;
   HIP_TRY(hipEventSynchronize(t.out.copied));
   if (ctx_->timing) {
     float ms = 0.f;
@@ -613,9 +752,9 @@ kad_status Engine::process(Tick &t, Tick &other) {
       ctx_->t_hits += t.out.h_len.p[k] >= 2 ? t.out.h_len.p[k] - 2 : 0;
     }
   }
-  for (uint32_t L = 0; L < t.layers; ++L) {
-    HIP_TRY(hipEventSynchronize(t.layer_ev[L]));
-    for (uint32_t j = t.layer_piece[L]; j < t.layer_piece[L + 1]; ++j) {
+  for (uint32_t ly = 0; ly < t.layers; ++ly) {
+    HIP_TRY(hipEventSynchronize(t.layer_ev[ly]));
+    for (uint32_t j = t.layer_piece[ly]; j < t.layer_piece[ly + 1]; ++j) {
       const Piece &pc = t.pieces[j];
       Query *q = pc.q;
       if (q->st == QState::Final || q->st == QState::Done) continue;  // past its stop
@@ -632,7 +771,7 @@ kad_status Engine::process(Tick &t, Tick &other) {
           finish_failed(q, KAD_ERNG, "bounded draw rejected 64 times");
         else
           finish_failed(q, KAD_EOVERFLOW, "candidate-edge list or path outgrew its buffer");
-        kad_status st = stop_query(q, t, j, other);
+        kad_status st = stop_query(q, L, t, j, other);
         if (st) return st;
         continue;
       }
@@ -657,11 +796,10 @@ kad_status Engine::process(Tick &t, Tick &other) {
                                          q->L_l.data(), q->L_u.data(), std::move(groups)));
         // group ids into the pool; the group maxima start at 0 with the counters
         const auto &go = q->checker->group_of();
-        q->gdev.resize(n);
         const uint32_t base = (uint32_t)q->base();
-        for (uint32_t v = 0; v < n; ++v) q->gdev[v] = go[v] + base;
-        HIP_TRY(hipMemcpyAsync(group_pool_.p + base, q->gdev.data(), (size_t)n * 4,
-                               hipMemcpyHostToDevice, rs));
+        uint32_t *stage = group_stage_.p + base;  // the query's own pinned range
+        for (uint32_t v = 0; v < n; ++v) stage[v] = go[v] + base;
+        HIP_TRY(launch_copy_u32(group_pool_.p + base, stage, n, rs));
         HIP_TRY(launch_zero_u32((uint32_t *)(gmax_pool_.p + base), 2ull * q->checker->groups(), rs));
         q->delta_ready = true;
         q->st = QState::Main;
@@ -684,7 +822,7 @@ kad_status Engine::process(Tick &t, Tick &other) {
         q->rule = stop;
       }
       if (stop) {
-        kad_status st = stop_query(q, t, j, other);
+        kad_status st = stop_query(q, L, t, j, other);
         if (st) return st;
       }
     }
@@ -692,6 +830,27 @@ kad_status Engine::process(Tick &t, Tick &other) {
   for (Query *q : t.queries) q->refs--;
   HIP_TRY(hipEventRecord(t.out.reduced, rs));
   t.in_flight = false;
+  return KAD_OK;
+}
+
+kad_status Engine::cancel_all() {
+  for (Query *q : active_) {
+    if (q->st == QState::Final || q->st == QState::Done) continue;
+    hipStream_t rs = lanes_[q->lane].rs;
+    finish_failed(q, KAD_ECANCELED, "canceled");
+    HIP_TRY(launch_zero_u32((uint32_t *)(count_pool_.p + q->base()), 2ull * q->n, rs));
+    HIP_TRY(hipEventRecord(q->final_ev, rs));
+    q->st = QState::Final;
+    q->t_final = clk::now();
+  }
+  while (!queue_.empty()) {
+    Query *q = queue_.front();
+    queue_.pop_front();
+    finish_failed(q, KAD_ECANCELED, "canceled before admission");
+    q->st = QState::Done;
+    q->t_admit = q->t_pilot = q->t_delta = q->t_final = q->t_done = clk::now();
+    done_.push_back(q);
+  }
   return KAD_OK;
 }
 
@@ -735,8 +894,6 @@ kad_status Engine::finalize(bool block) {
     q->checker.reset();
     q->count0.clear();
     q->count0.shrink_to_fit();
-    q->gdev.clear();
-    q->gdev.shrink_to_fit();
     q->st = QState::Done;
     q->t_done = clk::now();
     done_.push_back(q);
@@ -748,16 +905,34 @@ kad_status Engine::finalize(bool block) {
 kad_status Engine::step() {
   kad_status st = admit();
   if (st) return st;
-  // ticks_[cur_] is free (processed); ticks_[1 - cur_] may be running
-  Tick &nt = ticks_[cur_];
-  Tick &pt = ticks_[1 - cur_];
-  if ((st = build(nt))) return st;
-  if (nt.total > 0 && (st = launch(nt))) return st;
-  if (pt.in_flight && (st = process(pt, nt))) return st;
-  cur_ = 1 - cur_;
+  bool acted = false;
+  for (int li = 0; li < 2; ++li) {
+    Lane &L = lanes_[li];
+    Tick &newer = L.ticks[L.cur], &older = L.ticks[1 - L.cur];
+    if (!newer.in_flight) {
+      if ((st = build(li, newer))) return st;
+      if (newer.total > 0) {
+        if ((st = launch(L, newer))) return st;
+        acted = true;
+      }
+    }
+    // lane 0's running tick is waited for; lane 1's only evaluated once complete
+    if (older.in_flight) {
+      if (li == 0 || tick_complete(older)) {
+        if ((st = process(L, older, newer))) return st;
+        L.cur = 1 - L.cur;
+        acted = true;
+      }
+    } else if (newer.in_flight) {
+      L.cur = 1 - L.cur;
+    }
+  }
   // block on a stopped query's counters only when nothing else can move
-  const bool idle = !ticks_[0].in_flight && !ticks_[1].in_flight;
-  return finalize(idle);
+  const bool idle = !lanes_[0].busy() && !lanes_[1].busy();
+  if (idle && (!grave_dev_.empty() || !grave_host_.empty())) release_graveyard();
+  st = finalize(idle);
+  if (!acted && !idle) std::this_thread::sleep_for(std::chrono::microseconds(200));
+  return st;
 }
 
 kad_status context_engine(kad_ctx *ctx, Engine **out) {
@@ -832,6 +1007,7 @@ struct kad_server {
   std::map<uint64_t, bool> finished;
   uint64_t next_ticket = 1;
   bool quit = false;
+  uint64_t cancel_req = 0, cancel_done = 0;  // kad_server_cancel calls, and those handled
   kad_status fatal = KAD_OK;
   std::string fatal_msg;
   uint64_t completed = 0;
@@ -845,14 +1021,25 @@ void server_loop(kad_server *sv) {
   for (;;) {
     {
       std::unique_lock<std::mutex> lk(sv->mu);
-      sv->cv_work.wait(lk, [&] { return sv->quit || !sv->incoming.empty() || sv->eng->busy(); });
+      sv->cv_work.wait(lk, [&] {
+        return sv->quit || !sv->incoming.empty() || sv->eng->busy() ||
+               sv->cancel_req != sv->cancel_done;
+      });
       if (sv->quit && !sv->eng->busy()) break;
       while (!sv->incoming.empty()) {
         sv->eng->enqueue(sv->incoming.front());
         sv->incoming.pop_front();
       }
     }
-    kad_status st = sv->eng->step();
+    kad_status st = KAD_OK;
+    bool cancel = false;
+    {
+      std::lock_guard<std::mutex> lk(sv->mu);
+      cancel = sv->cancel_req != sv->cancel_done;
+      sv->cancel_done = sv->cancel_req;
+    }
+    if (cancel) st = sv->eng->cancel_all();
+    if (!st && sv->eng->busy()) st = sv->eng->step();
     std::vector<kad::Query *> done = sv->eng->take_done();
     if (st || !done.empty()) {
       std::lock_guard<std::mutex> lk(sv->mu);
@@ -1020,6 +1207,22 @@ kad_status kad_server_stats(kad_server *sv, uint64_t *completed, uint64_t *launc
   if (completed) *completed = sv->completed;
   if (launches) *launches = sv->eng->ticks_launched() - sv->launches0;
   if (samples) *samples = sv->eng->samples_launched() - sv->samples0;
+  return KAD_OK;
+}
+
+kad_status kad_server_cancel(kad_server *sv) {
+  if (!sv) return kad::fail(KAD_EINVAL, "NULL server");
+  std::lock_guard<std::mutex> lk(sv->mu);
+  for (kad::Query *q : sv->incoming) {  // not yet seen by the engine
+    q->status = KAD_ECANCELED;
+    q->error = "canceled before admission";
+    q->t_admit = q->t_pilot = q->t_delta = q->t_final = q->t_done = kad::clk::now();
+    sv->finished[q->ticket] = true;
+  }
+  sv->incoming.clear();
+  sv->cancel_req++;
+  sv->cv_work.notify_one();
+  sv->cv_done.notify_all();
   return KAD_OK;
 }
 

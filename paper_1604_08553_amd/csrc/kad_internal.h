@@ -62,8 +62,9 @@ struct PinBuf {
   hipError_t ensure(size_t count) {
     if (count <= n) return hipSuccess;
     release();
+    // coherent: kernels may write it directly (see launch_to_host_*)
     hipError_t e = hipHostMalloc((void **)&p, std::max<size_t>(count, 1) * sizeof(T),
-                                 hipHostMallocDefault);
+                                 hipHostMallocCoherent);
     if (e == hipSuccess) n = count;
     return e;
   }
@@ -92,6 +93,9 @@ struct OutSet {
   // capacity for `cap` samples of path stride `stride`; events created on first use
   // (`reduced` starts out recorded on `rs`)
   kad_status ensure(uint32_t cap, uint32_t stride, hipStream_t rs);
+  // capacity for `cap` samples and `path_entries` path entries in all (any stride with
+  // samples * stride <= path_entries)
+  kad_status ensure_entries(uint32_t cap, uint64_t path_entries, hipStream_t rs);
   SampleOut view(uint32_t path_stride) const;
 };
 

@@ -1093,6 +1093,15 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value) {
     p[i] = value;
 }
 
+// A copy by a kernel between device memory and pinned, coherent host memory (the GPU
+// reads or writes the host side over the bus); the stream's next event covers it.
+template <typename T>
+__global__ __launch_bounds__(256) void copy_kernel(T *dst, const T *src, uint64_t count) {
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
+    dst[i] = src[i];
+}
+
 __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc *__restrict__ d, uint32_t nd,
                                                      uint64_t *count_pool,
                                                      const uint64_t *gmax_pool, uint64_t *snap) {
@@ -1769,6 +1778,22 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStrea
 
 hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream) {
   return launch_fill_u32(p, count, 0u, stream);
+}
+
+hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t count,
+                              hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(copy_kernel<uint32_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count);
+  return hipGetLastError();
+}
+
+hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t count,
+                              hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 1024);
+  hipLaunchKernelGGL(copy_kernel<uint64_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count);
+  return hipGetLastError();
 }
 
 hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint64_t *count_pool,

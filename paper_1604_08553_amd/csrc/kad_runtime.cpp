@@ -63,6 +63,28 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
   return KAD_OK;
 }
 
+kad_status OutSet::ensure_entries(uint32_t want_cap, uint64_t path_entries, hipStream_t rs) {
+  if (cap < want_cap || path.n < path_entries) {
+    for (auto *b : {&s, &t, &len, &flags, &nodes, &path}) b->release();
+    arcs.release();
+    HIP_TRY(s.ensure(want_cap));
+    HIP_TRY(t.ensure(want_cap));
+    HIP_TRY(len.ensure(want_cap));
+    HIP_TRY(flags.ensure(want_cap));
+    HIP_TRY(nodes.ensure(want_cap));
+    HIP_TRY(arcs.ensure(want_cap));
+    HIP_TRY(path.ensure(path_entries));
+    HIP_TRY(h_flags.ensure(want_cap));
+    HIP_TRY(h_nwide.ensure(1));
+    HIP_TRY(h_len.ensure(want_cap));
+    HIP_TRY(h_nodes.ensure(want_cap));
+    HIP_TRY(h_arcs.ensure(want_cap));
+    cap = want_cap;
+    stride = (uint32_t)std::min<uint64_t>(path_entries / std::max(want_cap, 1u), 0xFFFFFFFFu);
+  }
+  return ensure(cap, 0, rs);  // events
+}
+
 SampleOut OutSet::view(uint32_t path_stride) const {
   SampleOut so;
   so.s = s.p;

@@ -532,7 +532,8 @@ bool StopChecker::check_group_max(const uint64_t *gmax, uint64_t tau, double *wo
 bool StopChecker::check(const uint64_t *count, uint64_t tau) {
   const double T = (double)tau, W = (double)omega_;
   std::fill(gmax_.begin(), gmax_.end(), 0);
-  std::vector<uint8_t> seen(gmax_.size(), 0);
+  std::vector<uint8_t> &seen = seen_;
+  seen.assign(gmax_.size(), 0);
   if (mode_ == 0) {
     for (uint32_t v = 0; v < n_; ++v) {
       const uint32_t g = group_[v];
@@ -550,13 +551,21 @@ bool StopChecker::check(const uint64_t *count, uint64_t tau) {
   // top-k (Algorithm 3): the k+1 largest by (count desc, id asc) are handled one by one;
   // for the rest only the per-group maximum can decide the second loop's condition.
   const uint32_t head = std::min(n_, k_ + 1);
-  order_.resize(n_);
-  for (uint32_t v = 0; v < n_; ++v) order_[v] = v;
+  // Counts never decrease between checks, so the k+1 largest now all have a count of
+  // at least the (k+1)-th largest of the previous check: select among those only.
+  order_.clear();
+  for (uint32_t v = 0; v < n_; ++v)
+    if (count[v] >= head_floor_) order_.push_back(v);
+  if (order_.size() < head) {  // cannot happen for non-decreasing counts; select among all
+    order_.resize(n_);
+    for (uint32_t v = 0; v < n_; ++v) order_[v] = v;
+  }
   auto cmp = [count](uint32_t a, uint32_t b) {
     return count[a] != count[b] ? count[a] > count[b] : a < b;
   };
   std::nth_element(order_.begin(), order_.begin() + (head - 1), order_.end(), cmp);
   std::sort(order_.begin(), order_.begin() + head, cmp);
+  head_floor_ = count[order_[head - 1]];
   auto bt = [&](uint32_t v) { return (double)count[v] / T; };
   auto fv = [&](uint32_t v) { return bound_f(bt(v), Ll_[v], W, T); };
   auto gv = [&](uint32_t v) { return bound_g(bt(v), Lu_[v], W, T); };

@@ -52,6 +52,7 @@ class StopChecker {
   // with a known grouping (e.g. from compute_delta)
   StopChecker(uint32_t n, uint32_t mode, uint32_t k, double eps, uint64_t omega,
               const double *L_l, const double *L_u, Groups &&groups);
+  // Counts passed to successive calls must not decrease (as within a run).
   bool check(const uint64_t *count, uint64_t tau);
   // All-nodes task only: the same decision from the per-group largest counts.  *worst
   // (optional) receives max over groups of max(f, g) / eps, how far the rule is from
@@ -69,7 +70,8 @@ class StopChecker {
   std::vector<double> gL_l_, gL_u_;  // group -> L values
   std::vector<uint64_t> gmax_;       // scratch: largest count per group
   std::vector<uint32_t> order_;      // scratch for the top-k order
-  std::vector<uint8_t> in_top_;
+  std::vector<uint8_t> in_top_, seen_;
+  uint64_t head_floor_ = 0;          // (k+1)-th largest count at the last top-k check
 };
 
 // Rank intervals of the top-k output: rank_lo = 1 + #{w != v: lower(w) >= upper(v)},

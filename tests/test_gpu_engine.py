@@ -167,3 +167,22 @@ def test_server_poll_and_reuse(kad, ctx):
         for t2 in ts:
             _same(srv.wait(t2, timeout=120.0), b)
     G.close()
+
+
+def test_server_cancel(kad, ctx):
+    """A long query is canceled; a query submitted afterwards still runs normally."""
+    heavy = kad.Graph(ctx, gg.damaged_grid(200, 200, 0.05, 7))
+    light_g = gg.workload("er2000")
+    light = kad.Graph(ctx, light_g)
+    b = kad.run(ctx, light, epsilon=0.01, delta=0.1, seed=3)
+    with kad.Server(ctx) as srv:
+        t1 = srv.submit(heavy, epsilon=0.004, delta=0.1, seed=1)
+        time.sleep(0.5)
+        srv.cancel()
+        with pytest.raises(kad.KadError) as e:
+            srv.wait(t1, timeout=120.0)
+        assert e.value.status == -8
+        t2 = srv.submit(light, epsilon=0.01, delta=0.1, seed=3)
+        _same(srv.wait(t2, timeout=120.0), b)
+    heavy.close()
+    light.close()
