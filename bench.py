@@ -12,6 +12,9 @@ seed 1, 65,536 samples per sampler launch.
 
 Other workloads (--workload):
   er2000    the same run on G(2000, 8/1999)'s largest component, epsilon 0.01;
+  dcl4m     directed Chung-Lu, n = 4,000,000, out/in exponents 2.5/2.1, mean degree 15,
+            top-k with k = 50, epsilon 0.0002 (the paper's top-k setting), launch shape
+            autotuned before the timed steps;
   batch256  256 Chung-Lu graphs (seed 1000+i; n log-uniform in [1e3, 1e5], half directed,
             exponents in [2.1, 2.8], mean degree 4..30), epsilon 0.01, delta 0.1, seed 1:
             one step = all 256 adaptive runs through the multi-query engine
@@ -293,7 +296,13 @@ def main():
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl1m")
-    ap.add_argument("--epsilon", type=float, default=0.005)
+    ap.add_argument("--epsilon", type=float, default=None,
+                    help="default 0.005 (0.01 for er2000, 0.0002 for dcl4m)")
+    ap.add_argument("--mode", default=None, choices=["all", "topk"],
+                    help="default all (topk for dcl4m)")
+    ap.add_argument("--k", type=int, default=50, help="top-k: k")
+    ap.add_argument("--autotune", action="store_true",
+                    help="autotune the sampler launch shape before timing (always for dcl4m)")
     ap.add_argument("--delta", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-batch", type=int, default=65536)
@@ -309,6 +318,12 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM counters)")
     args = ap.parse_args()
+    if args.epsilon is None:
+        args.epsilon = {"er2000": 0.01, "dcl4m": 0.0002}.get(args.workload, 0.005)
+    if args.mode is None:
+        args.mode = "topk" if args.workload == "dcl4m" else "all"
+    if args.workload == "dcl4m":
+        args.autotune = True
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(samples would shard across GPUs with one all-reduce of the counters per "
@@ -341,8 +356,14 @@ def main():
           flush=True)
     ctx = kad.Context(0)
     G = kad.Graph(ctx, csr)
+    tuned = None
+    if args.autotune:
+        tuned = G.autotune(args.kernel_batch)
+        print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
     kw = dict(epsilon=args.epsilon, delta=args.delta, seed=args.seed,
               kernel_batch=args.kernel_batch, check_interval=args.check_interval)
+    if args.mode == "topk":
+        kw.update(mode="topk", k=args.k)
     for w in range(args.warmup):
         r = kad.run(ctx, G, **kw)
         print(f"[bench] warmup {w}: tau={r['tau']} {r['seconds']:.3f} s", file=sys.stderr, flush=True)
@@ -388,9 +409,11 @@ def main():
         "data": "synthetic",
         "config": {
             "workload": f"{WORKLOAD_TEXT.get(args.workload, args.workload)}: n={csr.n}, "
-                        f"{csr.arcs} arcs; all-nodes, epsilon={args.epsilon}, "
-                        f"delta={args.delta}, seed {args.seed}, "
+                        f"{csr.arcs} arcs; "
+                        + (f"top-k k={args.k}" if args.mode == "topk" else "all-nodes")
+                        + f", epsilon={args.epsilon}, delta={args.delta}, seed {args.seed}, "
                         f"{args.kernel_batch} samples per sampler launch",
+            "launch_shape": tuned,
             "graph_sha256": csr.sha256(),
         },
         "gteps": arcs / elapsed / 1e9,

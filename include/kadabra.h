@@ -46,7 +46,15 @@ typedef enum {
 
 enum { KAD_MEM_HOST = 0, KAD_MEM_DEVICE = 1 };
 enum { KAD_ALL_NODES = 0, KAD_TOPK = 1 };
-enum { KAD_STOP_OMEGA = 0, KAD_STOP_RULE = 1 };
+enum { KAD_STOP_OMEGA = 0, KAD_STOP_RULE = 1, KAD_STOP_FIXED = 2 };
+/* sample schedules (kad_params.schedule) */
+enum {
+  KAD_SCHEDULE_ADAPTIVE = 0,  /* Algorithm 1: pilot, computeDelta, stopping rule (KADABRA) */
+  KAD_SCHEDULE_RK = 1,        /* fixed c/eps^2 (floor(log2(VD-2)) + 1 + ln(1/delta)) samples
+                                 (the Riondato-Kornaropoulos bound of section 6) */
+  KAD_SCHEDULE_HOEFFDING = 2  /* fixed ln(2n/delta) / (2 eps^2) samples (Hoeffding's inequality
+                                 with a union bound over the nodes, section 2) */
+};
 
 /* per-sample flag bits reported by kad_sample_paths */
 enum {
@@ -105,7 +113,8 @@ typedef struct {
                               check interval); 0 = library choice.  Performance only. */
   uint32_t vd_override;    /* 0 = library vertex-diameter rule (exact when n*arcs <= 1e9,
                               else a strongly-connected-component bound) */
-  uint32_t reserved;       /* must be 0 */
+  uint32_t schedule;       /* KAD_SCHEDULE_*; the fixed schedules take no pilot and no
+                              stopping check, and report [bc - eps, bc + eps] (kad_run only) */
   double c;                /* constant of the sample cap omega; 0 = 0.5 */
   double balance_eps;      /* epsilon of computeDelta (Algorithm 2); 0 = 0.001 */
 } kad_params;
@@ -113,8 +122,9 @@ typedef struct {
 typedef struct {
   /* scalar outputs */
   uint64_t tau;            /* samples taken in the main phase */
-  uint64_t omega;          /* cap: ceil(c/eps^2 (floor(log2(max(VD-2,1))) + 1 + ln(2/delta))) */
-  uint64_t alpha;          /* pilot samples: max(1, floor(omega/100)) */
+  uint64_t omega;          /* cap: ceil(c/eps^2 (floor(log2(max(VD-2,1))) + 1 + ln(2/delta)));
+                              fixed schedules: their sample count */
+  uint64_t alpha;          /* pilot samples: max(1, floor(omega/100)); fixed schedules: 0 */
   uint64_t interval;       /* check interval used */
   uint64_t arcs_scanned;   /* arcs scanned by the main phase's level expansions */
   uint64_t pilot_arcs_scanned;
@@ -122,7 +132,7 @@ typedef struct {
                                 again with multi-limb counts (kad_run: over every launch,
                                 including samples past the stopping point; engine: 0) */
   uint32_t vd, vd_exact;   /* vertex diameter used, and whether it is exact */
-  uint32_t stop_reason;    /* KAD_STOP_RULE or KAD_STOP_OMEGA */
+  uint32_t stop_reason;    /* KAD_STOP_RULE, KAD_STOP_OMEGA, or KAD_STOP_FIXED (fixed schedule) */
   uint32_t n;
   double seconds;          /* wall time of the call */
   double C;                /* the constant found by computeDelta's bisection */
@@ -231,6 +241,11 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
 uint64_t kad_omega(double epsilon, double delta, uint32_t vd, double c);
 /* Pilot size of Algorithm 2: max(1, floor(omega/100)). */
 uint64_t kad_alpha(uint64_t omega);
+/* Sample count of a fixed schedule: KAD_SCHEDULE_RK gives
+ * ceil(c/eps^2 (floor(log2(max(vd-2,1))) + 1 + ln(1/delta))), KAD_SCHEDULE_HOEFFDING gives
+ * ceil(ln(2n/delta) / (2 eps^2)); 0 for any other schedule.  c <= 0 means 0.5. */
+uint64_t kad_fixed_samples(uint32_t schedule, double epsilon, double delta, uint32_t vd,
+                           uint32_t n, double c);
 /* Default check interval: 2^floor(log2(omega/16)) clamped to [1024, 65536]. */
 uint64_t kad_default_interval(uint64_t omega);
 

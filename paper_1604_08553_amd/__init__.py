@@ -26,7 +26,8 @@ _HEADER = os.path.join(os.path.dirname(_HERE), "include", "kadabra.h")
 
 ALL_NODES, TOPK = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
-STOP_OMEGA, STOP_RULE = 0, 1
+STOP_OMEGA, STOP_RULE, STOP_FIXED = 0, 1, 2
+SCHEDULES = {"adaptive": 0, "rk": 1, "hoeffding": 2}
 SAMPLE_OVERFLOW, SAMPLE_CAPACITY, SAMPLE_RNG = 1, 2, 4
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
@@ -45,7 +46,7 @@ class _Params(C.Structure):
     _fields_ = [("epsilon", C.c_double), ("delta", C.c_double), ("mode", C.c_uint32),
                 ("k", C.c_uint32), ("seed", C.c_uint64), ("check_interval", C.c_uint32),
                 ("kernel_batch", C.c_uint32), ("vd_override", C.c_uint32),
-                ("reserved", C.c_uint32), ("c", C.c_double), ("balance_eps", C.c_double)]
+                ("schedule", C.c_uint32), ("c", C.c_double), ("balance_eps", C.c_double)]
 
 
 class _Result(C.Structure):
@@ -88,6 +89,7 @@ def lib():
         "kad_hit_counts": ([vp, vp, u64, u32, u64, u64, vp, vp, vp], st),
         "kad_omega": ([dbl, dbl, u32, dbl], u64),
         "kad_alpha": ([u64], u64),
+        "kad_fixed_samples": ([u32, dbl, dbl, u32, u32, dbl], u64),
         "kad_default_interval": ([u64], u64),
         "kad_vertex_diameter": ([u32, u64, i32, vp, vp, vp, vp, dbl, vp, vp], st),
         "kad_bound_f": ([dbl, dbl, dbl, dbl], dbl),
@@ -264,9 +266,10 @@ _SCALARS = ("tau", "omega", "alpha", "interval", "arcs_scanned", "pilot_arcs_sca
 
 
 def _params(epsilon, delta, mode="all", k=0, seed=1, check_interval=0, kernel_batch=0,
-            vd_override=0, c=0.0, balance_eps=0.0):
+            vd_override=0, c=0.0, balance_eps=0.0, schedule="adaptive"):
     return _Params(epsilon, delta, TOPK if mode == "topk" else ALL_NODES, k, seed,
-                   check_interval, kernel_batch, vd_override, 0, c, balance_eps)
+                   check_interval, kernel_batch, vd_override, SCHEDULES[schedule], c,
+                   balance_eps)
 
 
 def _result(n, topk, topk_cap=0, out=None):
@@ -303,13 +306,14 @@ def _collect(r, arrs, topk):
 def run(ctx: Context, graph: Graph, epsilon: float, delta: float, mode: str = "all", k: int = 0,
         seed: int = 1, check_interval: int = 0, kernel_batch: int = 0, vd_override: int = 0,
         c: float = 0.0, balance_eps: float = 0.0, topk_cap: int = 0, stream=None,
-        out: dict = None) -> dict:
-    """The adaptive run (Algorithm 1).  Returns scalars plus the per-node arrays.
+        out: dict = None, schedule: str = "adaptive") -> dict:
+    """The adaptive run (Algorithm 1), or a fixed schedule ("rk", "hoeffding").  Returns
+    scalars plus the per-node arrays.
 
     ``out`` may hold preallocated arrays "count" (uint64[n]), "bc", "lower", "upper"
     (float64[n]) to be filled in place (saves page-faulting fresh arrays per call)."""
     p = _params(epsilon, delta, mode, k, seed, check_interval, kernel_batch, vd_override, c,
-                balance_eps)
+                balance_eps, schedule)
     r, arrs = _result(graph.n, mode == "topk", topk_cap, out)
     _check(lib().kad_run(ctx.handle, graph.handle, C.byref(p), C.byref(r), _stream(stream)))
     return _collect(r, arrs, mode == "topk")
@@ -442,6 +446,11 @@ def hit_counts(ctx: Context, graph: Graph, seed: int, phase: int, first: int, co
 
 def omega(epsilon, delta, vd, c=0.5) -> int:
     return int(lib().kad_omega(epsilon, delta, vd, c))
+
+
+def fixed_samples(schedule, epsilon, delta, vd, n, c=0.0) -> int:
+    """Sample count of a fixed schedule ("rk" or "hoeffding")."""
+    return int(lib().kad_fixed_samples(SCHEDULES[schedule], epsilon, delta, vd, n, c))
 
 
 def alpha(om) -> int:

@@ -1085,6 +1085,8 @@ kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *g
     if (graphs[i]->ctx != ctx) return fail(KAD_EINVAL, "graph %u belongs to another context", i);
     kad_status st = kad::validate_params(graphs[i], &params[i]);
     if (st) return st;
+    if (params[i].schedule != KAD_SCHEDULE_ADAPTIVE)
+      return fail(KAD_EINVAL, "query %u: fixed schedules run through kad_run", i);
   }
   kad::CtxClaim claim(ctx);
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
@@ -1155,6 +1157,8 @@ kad_status kad_server_submit(kad_server *sv, const kad_graph *g, const kad_param
   if (g->ctx != sv->ctx) return fail(KAD_EINVAL, "the graph belongs to another context");
   kad_status st = kad::validate_params(g, p);
   if (st) return st;
+  if (p->schedule != KAD_SCHEDULE_ADAPTIVE)
+    return fail(KAD_EINVAL, "fixed schedules run through kad_run");
   std::unique_ptr<kad::Query> q(new kad::Query());
   q->g = const_cast<kad_graph *>(g);
   q->p = *p;

@@ -312,7 +312,7 @@ kad_status validate_params(const kad_graph *g, const kad_params *p) {
   if (!(p->delta > 0 && p->delta < 1)) return fail(KAD_EINVAL, "delta must be in (0,1)");
   if (p->mode != KAD_ALL_NODES && p->mode != KAD_TOPK) return fail(KAD_EINVAL, "bad mode");
   if (p->mode == KAD_TOPK && (p->k < 1 || p->k > g->n)) return fail(KAD_EINVAL, "k must be in [1, n]");
-  if (p->reserved != 0) return fail(KAD_EINVAL, "reserved must be 0");
+  if (p->schedule > KAD_SCHEDULE_HOEFFDING) return fail(KAD_EINVAL, "unknown schedule");
   if (p->c < 0) return fail(KAD_EINVAL, "c must be positive (or 0 for the default)");
   if (!(p->balance_eps >= 0 && p->balance_eps < 0.5))
     return fail(KAD_EINVAL, "balance_eps must be in (0, 0.5) (or 0 for the default)");
@@ -621,6 +621,15 @@ uint64_t kad_omega(double epsilon, double delta, uint32_t vd, double c) {
   return kad::omega_of(epsilon, delta, vd, c > 0 ? c : 0.5);
 }
 uint64_t kad_alpha(uint64_t omega) { return kad::alpha_of(omega); }
+
+uint64_t kad_fixed_samples(uint32_t schedule, double epsilon, double delta, uint32_t vd,
+                           uint32_t n, double c) {
+  if (schedule == KAD_SCHEDULE_RK)  // ln(2/(2 delta)) = ln(1/delta): omega's form with 2 delta
+    return kad::omega_of(epsilon, 2.0 * delta, vd, c > 0 ? c : 0.5);
+  if (schedule == KAD_SCHEDULE_HOEFFDING)
+    return (uint64_t)std::ceil(std::log(2.0 * (double)n / delta) / (2.0 * epsilon * epsilon));
+  return 0;
+}
 uint64_t kad_default_interval(uint64_t omega) { return kad::interval_of(omega); }
 
 kad_status kad_vertex_diameter(uint32_t n, uint64_t arcs, int directed, const uint32_t *row_ptr,
@@ -802,6 +811,71 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   if ((st = ensure_capacity(ctx, n, (uint32_t)K, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
   const auto t_setup = clock::now();
+
+  if (p->schedule != KAD_SCHEDULE_ADAPTIVE) {
+    // ---- a fixed number of main-phase samples, no pilot and no stopping check
+    const uint64_t tau_fixed = kad_fixed_samples(p->schedule, p->epsilon, p->delta, vd, n, c);
+    HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, stream));
+    uint64_t arcs_f = 0;
+    for (uint64_t done = 0; done < tau_fixed;) {
+      const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, tau_fixed - done);
+      if ((st = launch_batch(ctx, g, p->seed, 1, done, nb, stride, 0, stream, ovc))) return st;
+      HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
+                                     ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
+      if ((st = finish_batch(ctx, 0, nb, nb))) return st;
+      for (uint32_t k = 0; k < nb; ++k) arcs_f += ctx->outs[0].h_arcs.p[k];
+      done += nb;
+    }
+    HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    const auto t_main_f = clock::now();
+    r->tau = tau_fixed;
+    r->omega = tau_fixed;
+    r->alpha = 0;
+    r->interval = 0;
+    r->arcs_scanned = arcs_f;
+    r->pilot_arcs_scanned = 0;
+    r->overflow_samples = ctx->run_wide;
+    r->vd = vd;
+    r->vd_exact = vd_exact ? 1u : 0u;
+    r->stop_reason = KAD_STOP_FIXED;
+    r->n = n;
+    r->C = 0.0;
+    const uint64_t *cnt = ctx->h_count.p;
+    std::vector<double> &bcs = ctx->h_bc, &los = ctx->h_lo, &his = ctx->h_hi;
+    double *bc = r->bc ? r->bc : (bcs.resize(n), bcs.data());
+    double *lo = r->lower ? r->lower : (los.resize(n), los.data());
+    double *hi = r->upper ? r->upper : (his.resize(n), his.data());
+    if (r->count) memcpy(r->count, cnt, (size_t)n * 8);
+    kad::node_outputs(n, cnt, tau_fixed, tau_fixed, false, p->epsilon, nullptr, nullptr, {}, bc,
+                      lo, hi);
+    r->topk_len = 0;
+    kad_status ret = KAD_OK;
+    if (p->mode == KAD_TOPK) {
+      std::vector<uint32_t> sel, rlo, rhi;
+      kad::topk_select(n, p->k, cnt, lo, hi, sel, rlo, rhi);
+      r->topk_len = (uint32_t)sel.size();
+      if (sel.size() > r->topk_cap) {
+        ret = fail(KAD_ETOOSMALL, "top-k output needs %zu entries", sel.size());
+      } else {
+        for (size_t q = 0; q < sel.size(); ++q) {
+          if (r->topk_node) r->topk_node[q] = sel[q];
+          if (r->rank_lo) r->rank_lo[q] = rlo[q];
+          if (r->rank_hi) r->rank_hi[q] = rhi[q];
+        }
+      }
+    }
+    const auto t_end_f = clock::now();
+    auto secs_f = [](clock::time_point a, clock::time_point b) {
+      return std::chrono::duration<double>(b - a).count();
+    };
+    r->seconds = secs_f(t0, t_end_f);
+    r->seconds_setup = secs_f(t0, t_setup);
+    r->seconds_pilot = 0.0;
+    r->seconds_delta = 0.0;
+    r->seconds_main = secs_f(t_setup, t_main_f);
+    return ret;
+  }
 
   // ---- pilot (phase 0): alpha samples -> count0
   std::vector<uint64_t> &count0 = ctx->h_count0;

@@ -270,3 +270,24 @@ def test_device_memory_graph_and_torch_stream(kad, ctx, orc):
     B = orc.sample_paths(g, 1, 1, 0, 2000, threads=16)
     assert np.array_equal(A["nodes"], B.nodes)
     G.close()
+
+
+@pytest.mark.parametrize("schedule", ["rk", "hoeffding"])
+def test_run_fixed_schedule(kad, ctx, orc, schedule):
+    """Fixed schedules: exactly tau main-phase samples (ids 0..tau-1), counts equal the
+    oracle's hits over the same samples, intervals bc +- eps."""
+    g = gg.workload("er2000")
+    G = kad.Graph(ctx, g)
+    r = kad.run(ctx, G, epsilon=0.02, delta=0.1, seed=5, schedule=schedule)
+    tau = kad.fixed_samples(schedule, 0.02, 0.1, 8, g.n)
+    assert r["tau"] == tau and r["stop_reason"] == kad.STOP_FIXED and r["alpha"] == 0
+    S = orc.sample_paths(g, 5, 1, 0, tau, threads=16)
+    b = np.zeros(g.n, dtype=np.uint64)
+    for k in range(tau):
+        p = S.path(k)
+        b[p[1:-1]] += 1
+    assert np.array_equal(r["count"], b)
+    assert r["arcs_scanned"] == int(S.arcs.sum())
+    assert np.array_equal(r["bc"], b / float(tau))
+    assert np.array_equal(r["lower"], r["bc"] - 0.02) and np.array_equal(r["upper"], r["bc"] + 0.02)
+    G.close()

@@ -136,3 +136,21 @@ def test_grouped_stop_check_equals_plain_oracle(klib, oracle_lib):
                 assert a == b, (trial, mode, k, tau)
                 decisions += a
     assert decisions > 0
+
+
+def test_fixed_schedule_sample_counts(klib):
+    """RK: the printed RK iteration counts of the appendix tables (delta = 0.1) are
+    c/eps^2 (floor(log2(VD-2)) + 1 + ln(1/delta)) for some vertex diameter; Hoeffding:
+    the smallest k with 2n exp(-2 k eps^2) <= delta."""
+    import math
+    golden = os.path.join(os.path.dirname(__file__), "golden", "appF_iterations.txt")
+    rows = [l.split() for l in open(golden) if l.strip() and not l.startswith("#")]
+    assert len(rows) == 180
+    for kind, lam, _kad, rk in rows:
+        lam, rk = float(lam), int(rk)
+        assert any(kad.fixed_samples("rk", lam, 0.1, 2 ** j + 2, 1000) == rk for j in range(0, 40)), rk
+    for n, eps, delta in [(1000, 0.01, 0.1), (2 ** 20, 0.005, 0.05), (7, 0.3, 0.5)]:
+        k = kad.fixed_samples("hoeffding", eps, delta, 10, n)
+        assert 2 * n * math.exp(-2 * k * eps * eps) <= delta
+        assert 2 * n * math.exp(-2 * (k - 1) * eps * eps) > delta
+    assert kad.fixed_samples("adaptive", 0.01, 0.1, 8, 100) == 0
