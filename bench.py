@@ -234,12 +234,21 @@ def bench_serve(args, torch, gg, kad):
     cut = time.perf_counter()
     unfinished = [(q, cut - ts_) for t, (q, ts_) in pending.items()]
     srv.cancel()
-    for t in list(pending):
-        try:
-            srv.wait(t, timeout=60.0)
-        except kad.KadError:
-            pass
+    settle = time.perf_counter() + 120.0  # canceled queries finish once their launches drain
+    while pending and time.perf_counter() < settle:
+        for t in list(pending):
+            try:
+                if srv.poll(t) is not None:
+                    pending.pop(t)
+            except kad.KadError:
+                pending.pop(t)
+        if pending:
+            time.sleep(0.05)
+            if time.perf_counter() > next_report:
+                print(f"[bench] canceling: {len(pending)} left", file=sys.stderr, flush=True)
+                next_report += 10.0
     st = srv.stats()
+    print("[bench] closing the server (waits for launches in flight)", file=sys.stderr, flush=True)
     srv.close()
     elapsed = cut - start
     lat = [r["seconds"] for _, r in done]

@@ -391,30 +391,49 @@ void Engine::release_tiles(Query *q) {
     if (tile_used_[t]) tiles_hw_ = t + 1;
 }
 
+// Admission: queries are taken in arrival order within each lane; a lane whose next
+// query does not fit (counter pool, or slot memory that can only grow while nothing
+// runs) waits without holding up the other lane.  Lane 1 (slow, high-diameter
+// queries) may hold at most half of the counter pool.
 kad_status Engine::admit() {
-  while (!queue_.empty()) {
-    Query *q = queue_.front();
+  bool blocked[2] = {false, false};
+  uint32_t lane1_tiles = 0;
+  for (const Query *q : active_)
+    if (q->lane == 1) lane1_tiles += q->ntiles;
+  for (size_t j = 0; j < queue_.size();) {
+    Query *q = queue_[j];
     if (!q->prepared) {
       kad_status s = prepare(q);
       if (s) return s;
     }
     if (q->status != KAD_OK) {  // rejected before it touched the GPU
-      queue_.pop_front();
+      queue_.erase(queue_.begin() + j);
       q->st = QState::Done;
       q->t_admit = q->t_pilot = q->t_delta = q->t_final = q->t_done = clk::now();
       done_.push_back(q);
       continue;
     }
+    const int lane = split_ && q->ovc == 2 ? 1 : 0;
+    if (blocked[lane]) {
+      ++j;
+      continue;
+    }
     const uint32_t need = (uint32_t)((q->n + HIT_TILE_IDS - 1) / HIT_TILE_IDS);
     uint32_t start = POOL_TILES;
-    for (uint32_t t = 0, run = 0; t < POOL_TILES; ++t) {  // first fit
-      run = tile_used_[t] ? 0 : run + 1;
-      if (run == need) {
-        start = t + 1 - need;
-        break;
+    if (lane == 0 || lane1_tiles + need <= POOL_TILES / 2) {
+      for (uint32_t t = 0, run = 0; t < POOL_TILES; ++t) {  // first fit
+        run = tile_used_[t] ? 0 : run + 1;
+        if (run == need) {
+          start = t + 1 - need;
+          break;
+        }
       }
     }
-    if (start == POOL_TILES) break;  // wait until running queries release counters
+    if (start == POOL_TILES) {  // wait until running queries release counters
+      blocked[lane] = true;
+      ++j;
+      continue;
+    }
     const bool need_wide = q->ovc != 0 && ctx_->w_slots == 0;
     if (q->n > ctx_->slot_n || need_wide) {
       if (lanes_[0].busy() || lanes_[1].busy()) break;  // grow only when idle
@@ -422,25 +441,24 @@ kad_status Engine::admit() {
       kad_status s = q->n > ctx_->slot_n ? ensure_slots(ctx_, q->n) : KAD_OK;
       if (!s && q->ovc != 0) s = ensure_wide(ctx_);
       layout();
-      if (s) {
-        finish_failed(q, s, kad_last_error());
-        continue;
-      }
+      if (s) finish_failed(q, s, kad_last_error());
+      continue;  // looked at again with the new layout (or as failed)
     }
-    q->lane = split_ && q->ovc == 2 ? 1 : 0;
+    q->lane = lane;
+    if (lane == 1) lane1_tiles += need;
     for (uint32_t t = start; t < start + need; ++t) tile_used_[t] = 1;
     q->tile0 = start;
     q->ntiles = need;
     tiles_hw_ = std::max(tiles_hw_, start + need);
     // until computeDelta assigns groups, every node maps to the query's first
-    // group-maximum entry (rebuilt from the counters when the groups arrive)
+    // group-maximum entry
     HIP_TRY(launch_fill_u32(group_pool_.p + q->base(), q->n, (uint32_t)q->base(),
                             lanes_[q->lane].rs));
     if (!q->final_ev) HIP_TRY(hipEventCreateWithFlags(&q->final_ev, hipEventDisableTiming));
     q->st = QState::Pilot;
     q->t_admit = clk::now();
     active_.push_back(q);
-    queue_.pop_front();
+    queue_.erase(queue_.begin() + j);
   }
   return KAD_OK;
 }
