@@ -11,7 +11,9 @@ known size), and writes:
 * ``profiles/sampler_cl1m_traffic.md`` -- HBM bytes per sampler dispatch, each counter
   scaled by (known copy bytes / what the counter read for the copy);
 * ``profiles/sampler_cl1m_traffic.json`` -- the same numbers with the SHA-256 of the
-  kernel source they were taken with (bench.py reports them only while it matches).
+  kernel source they were taken with (bench.py reports them only while it matches);
+* ``profiles/sampler_cl1m_counters.md`` (with --sq-a/--sq-b/--tcc) -- wave-state and
+  instruction counters and the L2 hit rate of the sampler kernel.
 """
 from __future__ import annotations
 
@@ -61,6 +63,9 @@ def main():
     ap.add_argument("--copy-write", required=True)
     ap.add_argument("--copy-mib", type=int, required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--sq-a", default=None, help="pass: SQ wave-cycle counters")
+    ap.add_argument("--sq-b", default=None, help="pass: SQ instruction counters")
+    ap.add_argument("--tcc", default=None, help="pass: TCC/TCP hit counters")
     ap.add_argument("--command-file", required=True,
                     help="text file with the exact commands that produced the inputs")
     args = ap.parse_args()
@@ -103,6 +108,28 @@ def main():
          f"{write_b / 1e9:.3f} GB = {(fetch_b + write_b) / 1e9:.3f} GB",
          f"* kernel source SHA-256: {rec['kernel_source_sha256']}"]
     open(os.path.join(args.out, "sampler_cl1m_traffic.md"), "w").write("\n".join(t) + "\n")
+    if args.sq_a and args.sq_b and args.tcc:
+        c = {}
+        for d in (args.sq_a, args.sq_b, args.tcc):
+            path = _one(os.path.join(d, "**", "*counter_collection.csv"))
+            acc = {}
+            for r in csv.DictReader(open(path)):
+                if "sampler_kernel" in r["Kernel_Name"]:
+                    acc.setdefault(r["Counter_Name"], []).append(float(r["Counter_Value"]))
+            c.update({k: sum(v) / len(v) for k, v in acc.items()})
+        wave = c.get("SQ_WAVE_CYCLES", 0.0) or 1.0
+        hit, miss = c.get("TCC_HIT_sum", 0.0), c.get("TCC_MISS_sum", 0.0)
+        lines = ["# Counters of the sampler kernel (cl1m bench), mean per dispatch", "",
+                 "Produced by:", "", "```", commands, "```", "",
+                 "| counter | value |", "|---|---|"]
+        lines += [f"| {k} | {v:.4g} |" for k, v in sorted(c.items())]
+        lines += ["", f"* waves waiting (SQ_WAIT_ANY / SQ_WAVE_CYCLES): {c.get('SQ_WAIT_ANY', 0) / wave:.3f}",
+                  f"* waves issuing (SQ_ACTIVE_INST_ANY / SQ_WAVE_CYCLES): {c.get('SQ_ACTIVE_INST_ANY', 0) / wave:.3f}",
+                  f"* L2 hit rate (TCC_HIT / (TCC_HIT + TCC_MISS)): {hit / max(hit + miss, 1.0):.3f}",
+                  f"* LDS bank conflicts per LDS instruction: "
+                  f"{c.get('SQ_LDS_BANK_CONFLICT', 0) / max(c.get('SQ_INSTS_LDS', 1), 1):.3f}",
+                  f"* kernel source SHA-256: {rec['kernel_source_sha256']}"]
+        open(os.path.join(args.out, "sampler_cl1m_counters.md"), "w").write("\n".join(lines) + "\n")
     print(json.dumps(rec))
 
 
