@@ -187,23 +187,32 @@ __device__ __forceinline__ uint64_t add_u64(uint64_t *p, uint64_t x) {
   return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
-// sigma(w) += x with exact carry into the high word; true when the sum reached 2^128.
-__device__ __forceinline__ bool atomic_add_sig(uint64_t *sig, uint32_t w, uint64_t xlo,
-                                               uint64_t xhi) {
-  uint64_t *p = sig + 2 * (size_t)w;
-  const uint64_t old = add_u64(p, xlo);
-  const uint64_t c = (old + xlo < old) ? 1u : 0u;
-  const uint64_t add = xhi + c;
-  bool ovf = add < xhi;
-  if (add != 0) {
-    const uint64_t oh = add_u64(p + 1, add);
-    ovf |= oh + add < oh;
-  }
-  return ovf;
-}
-
 __device__ __forceinline__ uint32_t filter_bit(uint32_t w) {
   return (w * 2654435761u) >> (32 - FILTER_LOG2);
+}
+
+// Exact set of node ids in SLOTS words of LDS (open addressing, linear probing), kept
+// at most half full so that every probe sequence reaches an empty word.
+constexpr uint32_t FSET_EMPTY = 0xFFFFFFFFu;  // never a node id
+constexpr int ilog2(int x) { return x <= 1 ? 0 : 1 + ilog2(x / 2); }
+template <int SLOTS>
+__device__ __forceinline__ uint32_t fset_slot(uint32_t w) {
+  return (w * 0x85EBCA6Bu) >> (32 - ilog2(SLOTS));
+}
+template <int SLOTS>
+__device__ __forceinline__ void fset_insert(uint32_t *fs, uint32_t w) {
+  uint32_t h = fset_slot<SLOTS>(w);
+  while (atomicCAS(&fs[h], FSET_EMPTY, w) != FSET_EMPTY) h = (h + 1) & (SLOTS - 1);
+}
+template <int SLOTS>
+__device__ __forceinline__ bool fset_has(const uint32_t *fs, uint32_t w) {
+  uint32_t h = fset_slot<SLOTS>(w);
+  for (;;) {
+    const uint32_t x = fs[h];
+    if (x == w) return true;
+    if (x == FSET_EMPTY) return false;
+    h = (h + 1) & (SLOTS - 1);
+  }
 }
 
 // ------------------------------------------------------------------ wave / block scans
@@ -240,20 +249,36 @@ template <int BLOCK>
 struct Lds {
   static constexpr int NWAVES = BLOCK / WAVE;
   static constexpr int CHUNK = 2 * BLOCK;  // frontier nodes staged per pass (2 per thread)
-  uint32_t filter[FILTER_WORDS];
+  // The frontier bit filter; once the searches have met, its words (and those of the
+  // count staging area below) hold the candidate edges while they are sorted.
+  union {
+    uint32_t filter[FILTER_WORDS];
+    uint64_t sort_lo[FILTER_WORDS / 2];
+  };
   uint64_t pi[PI_LDS];
-  uint64_t c_sig_lo[CHUNK];
-  uint64_t c_sig_hi[CHUNK];
+  // The path counts of a chunk's rows (discovery scans); during a touch scan the same
+  // bytes hold the other side's frontier as an exact hash set.
+  union {
+    struct {
+      uint64_t c_sig_lo[CHUNK];
+      uint64_t c_sig_hi[CHUNK];
+    };
+    uint32_t fset[4 * CHUNK];
+    uint64_t sort_hi[2 * CHUNK];
+  };
   uint32_t c_node[CHUNK];
-  uint32_t c_start[CHUNK];
-  uint32_t c_pref[CHUNK + 1];
+  uint32_t c_off[CHUNK];  // row start minus the row's first position in the chunk's arc space
+  uint32_t wmask[3][WAVE];  // row starts of an arc window, one bit per arc (triple-buffered)
+  uint32_t wfirst[3];       // the row that holds a window's first arc
   uint32_t red32[NWAVES + 1];
+  uint32_t red32b[NWAVES + 1];
   uint64_t red_lo[NWAVES];
   uint64_t red_hi[NWAVES];
   uint64_t deg[2];
   uint64_t arcs;
   uint64_t new_deg;
-  uint64_t r_lo, r_hi;
+  uint64_t r_lo, r_hi, wkey;
+  uint32_t rfl;
   uint32_t k, s, t, seg;
   uint32_t fb[2], fe[2], lvl[2];
   uint32_t nvis, pi_count, flags, win;
@@ -289,6 +314,37 @@ __device__ __forceinline__ uint32_t block_excl_u32(Lds<BLOCK> &L, uint32_t v, ui
   __syncthreads();
   total = all;
   return before + inc - v;
+}
+
+// Exclusive block scan of two values per thread at once.
+template <int BLOCK>
+__device__ __forceinline__ void block_excl2_u32(Lds<BLOCK> &L, uint32_t a, uint32_t b,
+                                                uint32_t &ea, uint32_t &eb, uint32_t &ta,
+                                                uint32_t &tb) {
+  constexpr int NWAVES = BLOCK / WAVE;
+  const uint32_t lane = lane_id(), wid = threadIdx.x / WAVE;
+  const uint32_t ia = wave_incl_u32(a), ib = wave_incl_u32(b);
+  if (lane == WAVE - 1) {
+    L.red32[wid] = ia;
+    L.red32b[wid] = ib;
+  }
+  __syncthreads();
+  uint32_t ba = 0, bb = 0, aa = 0, ab = 0;
+#pragma unroll
+  for (int q = 0; q < NWAVES; ++q) {
+    const uint32_t xa = L.red32[q], xb = L.red32b[q];
+    if ((uint32_t)q < wid) {
+      ba += xa;
+      bb += xb;
+    }
+    aa += xa;
+    ab += xb;
+  }
+  __syncthreads();
+  ta = aa;
+  tb = ab;
+  ea = ba + ia - a;
+  eb = bb + ib - b;
 }
 
 // Inclusive block scan of 128-bit values; *total gets the block sum.
@@ -331,132 +387,231 @@ __device__ __forceinline__ uint32_t wave_reserve(bool pred, uint32_t *counter, u
 // Both: the meeting test by tag and the discovery in one pass (small expansions).
 enum class Scan { Touch, Discover, Both };
 
-// One pass over the rows of frontier [fb, fe) (chunked through LDS).
+// One pass over the rows of frontier [fb, fe), chunked through LDS.
+//
+// A chunk's rows of nonzero degree are laid end to end in one arc space [0, tot)
+// (rows of degree zero own no arcs and are dropped).  The arcs are walked in windows
+// of BLOCK * U; lane l of wave w takes arcs e0 + w*WAVE*U + q*WAVE + l, q < U.  The
+// row that owns an arc is found without a search: every row that starts inside the
+// window sets the bit of its first position in an LDS mask, and the owner of
+// position p is the window's first row plus the number of starts in (0, p] -- a
+// popcount over the mask.  The masks are triple-buffered so that a window takes one
+// barrier: window k sets its bits in mask k mod 3 and clears mask (k+1) mod 3, which
+// every wave finished reading before the barrier of window k-1.  wk is the window
+// counter (mod 3), carried from call to call.
 template <int BLOCK, Scan MODE>
 __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, uint32_t me,
                                               uint32_t fb, uint32_t fe, uint32_t *tag,
                                               uint64_t *sig, uint32_t *visit, uint64_t *gpi,
                                               uint32_t pi_cap, uint32_t other_tag,
-                                              uint32_t next_tag, bool &ovf) {
+                                              uint32_t next_tag, bool &ovf, uint32_t &wk,
+                                              bool exact) {
   constexpr int CHUNK = 2 * BLOCK;
-  const uint32_t tid = threadIdx.x;
+  // arcs per lane per window: a window costs a few dependent round trips whatever its
+  // size; wider touch windows than 8 run out of registers
+  constexpr int U = MODE == Scan::Touch ? 8 : (MODE == Scan::Discover ? 4 : 2);
+  constexpr uint32_t WIN = BLOCK * U;
+  constexpr uint32_t NWORDS = WIN / 32;
+  static_assert(NWORDS <= (uint32_t)WAVE && WIN % 64 == 0, "a window's mask fits one wave");
+  const uint32_t tid = threadIdx.x, lane = lane_id();
+  const uint32_t wid = __builtin_amdgcn_readfirstlane(tid / WAVE);
   const uint32_t *rp = me == 0 ? g.row : g.rrow;
   const uint32_t *cl = me == 0 ? g.col : g.rcol;
+  // bits of the mask word at or below this lane's position (positions of a wave's
+  // group are 64-aligned, so a lane always sits at bit lane mod 32)
+  const uint32_t below = ((1u << (lane & 31)) << 1) - 1u;
   for (uint32_t cb = fb; cb < fe; cb += CHUNK) {
     const uint32_t m = min((uint32_t)CHUNK, fe - cb);
-    uint32_t d[2] = {0, 0};
+    uint32_t u[2] = {0, 0}, st[2] = {0, 0}, d[2] = {0, 0};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       const uint32_t j = 2 * tid + q;
       if (j < m) {
-        const uint32_t u = visit[cb + j];
-        const uint32_t st = rp[u];
-        d[q] = rp[u + 1] - st;
-        L.c_node[j] = u;
-        L.c_start[j] = st;
+        u[q] = visit[cb + j];
+        st[q] = rp[u[q]];
+        d[q] = rp[u[q] + 1] - st[q];
+      }
+    }
+    u128 su[2] = {{0, 0}, {0, 0}};
+    if (MODE != Scan::Touch) {
+#pragma unroll
+      for (int q = 0; q < 2; ++q)
+        if (d[q] != 0) su[q] = ld_sig(sig, u[q]);
+    }
+    uint32_t ex, cx, tot, nrows;
+    block_excl2_u32(L, d[0] + d[1], (d[0] != 0 ? 1u : 0u) + (d[1] != 0 ? 1u : 0u), ex, cx, tot,
+                    nrows);
+    // this thread's rows: chunk slot, first position in the arc space, end
+    uint32_t slot[2], pos[2];
+    slot[0] = cx;
+    slot[1] = cx + (d[0] != 0 ? 1u : 0u);
+    pos[0] = ex;
+    pos[1] = ex + d[0];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (d[q] != 0) {
+        L.c_node[slot[q]] = u[q];
+        L.c_off[slot[q]] = st[q] - pos[q];
         if (MODE != Scan::Touch) {
-          const u128 su = ld_sig(sig, u);
-          L.c_sig_lo[j] = su.lo;
-          L.c_sig_hi[j] = su.hi;
+          L.c_sig_lo[slot[q]] = su[q].lo;
+          L.c_sig_hi[slot[q]] = su[q].hi;
         }
       }
     }
-    uint32_t tot;
-    const uint32_t ex = block_excl_u32(L, d[0] + d[1], tot);
-    if (2 * tid < m) L.c_pref[2 * tid] = ex;
-    if (2 * tid + 1 < m) L.c_pref[2 * tid + 1] = ex + d[0];
-    if (tid == 0) L.c_pref[m] = tot;
-    __syncthreads();
-    // Each lane takes U arcs per iteration (independent searches and row loads in
-    // flight); every lane of a wave runs the same number of iterations because the
-    // ballots and shuffles below must not see inactive lanes.
-    constexpr int U = MODE == Scan::Touch ? 8 : 2;  // arcs per lane per iteration
-    uint32_t jlo = 0;
-    const uint32_t lane = lane_id();
-    for (uint32_t e0 = (tid / WAVE) * (WAVE * U); e0 < tot; e0 += BLOCK * U) {
-      uint32_t uu[U], ww[U], jj[U];
-      bool vv[U];
+    (void)nrows;
+    // Every lane of a wave runs the same number of windows because the ballots and
+    // shuffles below must not see inactive lanes.
+    for (uint32_t e0 = 0; e0 < tot; e0 += WIN) {
+      const uint32_t kn = wk == 2 ? 0u : wk + 1;
+      // clear all WAVE words: scans of other modes use more words of the same masks
+      if (tid < (uint32_t)WAVE) L.wmask[kn][tid] = 0;
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const uint32_t e = e0 + q * WAVE + lane;
-        vv[q] = e < tot;
-        uint32_t lo = jlo;
-        // largest j with c_pref[j] <= e (then c_pref[j+1] > e: node j owns arc e); arcs
-        // of a long row stay in the row of the lane's previous arc, so test that first
-        if (vv[q] && L.c_pref[lo + 1] <= e) {
-          uint32_t hi = m;
-          ++lo;
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
-          }
-        }
-        jj[q] = lo;
-      }
-#pragma unroll
-      for (int q = 0; q < U; ++q) {
-        const uint32_t e = e0 + q * WAVE + lane;
-        uu[q] = 0;
-        ww[q] = 0;
-        if (vv[q]) {
-          uu[q] = L.c_node[jj[q]];
-          ww[q] = cl[L.c_start[jj[q]] + (e - L.c_pref[jj[q]])];
-          jlo = jj[q];
+      for (int q = 0; q < 2; ++q) {
+        if (d[q] != 0) {
+          const uint32_t s0 = pos[q];
+          if (s0 > e0 && s0 - e0 < WIN)
+            atomicOr(&L.wmask[wk][(s0 - e0) >> 5], 1u << ((s0 - e0) & 31));
+          if (s0 <= e0 && e0 - s0 < d[q]) L.wfirst[wk] = slot[q];
         }
       }
+      __syncthreads();
+      const uint32_t word = lane < NWORDS ? L.wmask[wk][lane] : 0u;
+      const uint32_t jf = L.wfirst[wk];
+      wk = kn;
+      // starts in the words before this wave's first word: their popcounts (at most
+      // 32, six bits) summed one bit plane at a time with ballots
+      const uint32_t fw = wid * (2 * U);  // this wave's first word (below 64)
+      const uint32_t pc = (uint32_t)__popc(word);
+      const uint64_t before_fw = (1ull << fw) - 1ull;
+      uint32_t base = 0;
+#pragma unroll
+      for (int b = 0; b < 6; ++b)
+        base += (uint32_t)__popcll(__ballot((pc >> b) & 1u) & before_fw) << b;
+      const bool hi_half = lane >= 32;
+      uint32_t ww[U], jj[(U + 1) / 2];  // owners, two 16-bit slots per word
+      uint32_t vm = 0;  // bit q: group q's arc of this lane exists
 #pragma unroll
       for (int q = 0; q < U; ++q) {
-        const uint32_t u = uu[q], w = ww[q];
-        const bool valid = vv[q];
-        if (MODE == Scan::Touch) {
-          bool hit = false;
-          if (valid) {
-            const uint32_t h = filter_bit(w);
-            if ((L.filter[h >> 5] >> (h & 31)) & 1u) hit = ld_tag(tag + w) == other_tag;
-          }
-          uint32_t rank = 0;
-          const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
-          if (hit) {
-            const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
-            const uint32_t idx = base + rank;
-            if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
-            else if (idx < pi_cap) gpi[idx] = key;
-          }
+        const uint32_t wi = fw + 2 * q;  // group q covers words wi and wi + 1
+        const uint32_t w0 = __builtin_amdgcn_readlane(word, wi);
+        const uint32_t w1 = __builtin_amdgcn_readlane(word, wi + 1);
+        const uint32_t p0 = base, p1 = base + (uint32_t)__popc(w0);
+        base = p1 + (uint32_t)__popc(w1);
+        const uint32_t j = jf + (hi_half ? p1 : p0) + (uint32_t)__popc((hi_half ? w1 : w0) & below);
+        if (q % 2 == 0) jj[q / 2] = j;
+        else jj[q / 2] |= j << 16;
+        vm |= (e0 + fw * 32 + q * WAVE + lane < tot ? 1u : 0u) << q;
+      }
+      auto owner = [&](int q) -> uint32_t { return (jj[q / 2] >> (16 * (q % 2))) & 0xFFFFu; };
+      // Lanes past the end of the arc space re-read its last arc (their owner is the
+      // last row), so every lane loads and the LDS reads and the row loads of all U
+      // groups go out back to back.
+#pragma unroll
+      for (int q = 0; q < U; ++q) ww[q] = L.c_off[owner(q)];
+#pragma unroll
+      for (int q = 0; q < U; ++q) ww[q] = cl[ww[q] + min(e0 + fw * 32 + q * WAVE + lane, tot - 1)];
+      // Every stage below first issues the loads or atomics of all U arcs and only
+      // then uses their results, so a lane keeps U memory requests in flight instead
+      // of waiting on one arc at a time.
+      if (MODE == Scan::Touch) {
+        // filter probes; an arc that passes is confirmed in the exact set when the other
+        // frontier has one, else by its tag (the tag loads of all arcs go out together)
+        uint32_t fword[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) fword[q] = L.filter[filter_bit(ww[q]) >> 5];
+        uint32_t pass = 0, hitm = 0;
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          pass |= (fword[q] >> (filter_bit(ww[q]) & 31)) & (vm >> q) & 1u ? 1u << q : 0u;
+        if (exact) {
+#pragma unroll
+          for (int q = 0; q < U; ++q)
+            if ((pass >> q) & 1u) hitm |= fset_has<4 * CHUNK>(L.fset, ww[q]) ? 1u << q : 0u;
         } else {
-          bool disc = false, hit = false;
-          if (valid) {
-            uint32_t tg = ld_tag(tag + w);
-            if (MODE == Scan::Both) hit = tg == other_tag;
-            if (tg == 0) {
-              const uint32_t old = cas_tag(tag + w, 0u, next_tag);
-              disc = old == 0;
-              tg = disc ? next_tag : old;
-            }
-            if (tg == next_tag) {
-              const uint32_t j = jj[q];
-              ovf |= atomic_add_sig(sig, w, L.c_sig_lo[j], L.c_sig_hi[j]);
+          uint32_t tg[U];
+#pragma unroll
+          for (int q = 0; q < U; ++q) tg[q] = (pass >> q) & 1u ? ld_tag(tag + ww[q]) : 0u;
+#pragma unroll
+          for (int q = 0; q < U; ++q) hitm |= tg[q] == other_tag ? 1u << q : 0u;  // never 0
+        }
+        if (__ballot(hitm != 0)) {  // uniform: some lane of this wave found candidates
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const bool hit = (hitm >> q) & 1u;
+            uint32_t rank = 0;
+            const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
+            if (hit) {
+              const uint32_t u = L.c_node[owner(q)], w = ww[q];
+              const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+              const uint32_t idx = base + rank;
+              if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
+              else if (idx < pi_cap) gpi[idx] = key;
             }
           }
-          if (MODE == Scan::Both) {
+        }
+      } else {
+        // Claims: one compare-and-swap per arc returns the head's tag as it was (0 if
+        // unseen, then this arc claimed it; next_tag if another arc of this level did;
+        // other_tag if the head is in the other side's frontier).
+        uint32_t tg[U], dm = 0;  // dm bit q: this lane's arc of group q claimed its head
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          tg[q] = 0;
+          if ((vm >> q) & 1u) {
+            const uint32_t old = cas_tag(tag + ww[q], 0u, next_tag);
+            dm |= old == 0 ? 1u << q : 0u;
+            tg[q] = old == 0 ? next_tag : old;
+          }
+        }
+        // sigma(w) += sigma(u) on the low words, the appends of the claimed heads and
+        // the loads of their degrees all go out before any result is used; the carries
+        // into the high words follow
+        uint64_t old_lo[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          old_lo[q] = 0;
+          if (tg[q] == next_tag) old_lo[q] = add_u64(sig + 2 * (size_t)ww[q], L.c_sig_lo[owner(q)]);
+        }
+        if (MODE == Scan::Both) {
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const bool hit = tg[q] == other_tag;  // never 0
             uint32_t prank = 0;
             const uint32_t pbase = wave_reserve(hit, &L.pi_count, prank);
             if (hit) {
+              const uint32_t u = L.c_node[owner(q)], w = ww[q];
               const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
               const uint32_t idx = pbase + prank;
               if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
               else if (idx < pi_cap) gpi[idx] = key;
             }
           }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const bool disc = (dm >> q) & 1u;
           uint32_t rank = 0;
           const uint32_t base = wave_reserve(disc, &L.nvis, rank);
-          if (base != 0xFFFFFFFFu) {  // uniform: some lane of this wave discovered a node
-            uint64_t dg = 0;
-            if (disc) {
-              visit[base + rank] = w;
-              dg = (uint64_t)(rp[w + 1] - rp[w]);
+          if (disc) visit[base + rank] = ww[q];
+        }
+        if (__ballot(dm != 0)) {  // uniform: some lane of this wave discovered a node
+          uint64_t dg = 0;
+#pragma unroll
+          for (int q = 0; q < U; ++q)
+            if ((dm >> q) & 1u) dg += (uint64_t)(rp[ww[q] + 1] - rp[ww[q]]);
+          const uint64_t sum = wave_sum_u64(dg);
+          if (lane == 0) atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)sum);
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          if (tg[q] == next_tag) {
+            const uint64_t xlo = L.c_sig_lo[owner(q)], xhi = L.c_sig_hi[owner(q)];
+            const uint64_t add = xhi + ((old_lo[q] + xlo < old_lo[q]) ? 1u : 0u);
+            ovf |= add < xhi;
+            if (add != 0) {
+              const uint64_t oh = add_u64(sig + 2 * (size_t)ww[q] + 1, add);
+              ovf |= oh + add < oh;
             }
-            const uint64_t sum = wave_sum_u64(dg);
-            if (lane == 0) atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)sum);
           }
         }
       }
@@ -503,6 +658,31 @@ __device__ void bitonic_sort(uint64_t *keys, uint32_t M) {
   }
 }
 
+// The same network over an array split in two LDS parts: element i is lo[i] below nlo,
+// hi[i - nlo] above.
+template <int BLOCK>
+__device__ void bitonic_sort2(uint64_t *lo, uint32_t nlo, uint64_t *hi, uint32_t M) {
+  auto at = [&](uint32_t i) -> uint64_t & { return i < nlo ? lo[i] : hi[i - nlo]; };
+  for (uint32_t k = 2; k <= M; k <<= 1) {
+    for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+      for (uint32_t i = threadIdx.x; i < M; i += BLOCK) {
+        const uint32_t ixj = i ^ j;
+        if (ixj > i) {
+          const uint64_t a = at(i), b = at(ixj);
+          const bool up = (i & k) == 0;
+          if ((a > b) == up) {
+            at(i) = b;
+            at(ixj) = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+constexpr uint32_t pow2floor(uint32_t x) { return x <= 1 ? 1u : 2u * pow2floor(x / 2); }
+
 // One backtracking walk of a wave (section 4, "by backtracking"): from `start` on
 // level `lev` of side `side` down to level 0.  Each step draws r < sigma(x) and takes,
 // among x's neighbours on the level below in row order (the s side looks at
@@ -518,18 +698,27 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
                           const uint32_t *tag, const uint64_t *sig, const uint32_t *visit,
                           const uint32_t (*seg_lo)[MAXLEV], const uint32_t (*seg_hi)[MAXLEV],
                           MatchScratch &M, uint64_t seed, uint64_t i, uint32_t phase,
-                          uint32_t *path, uint32_t ls, uint32_t base, uint32_t &flags) {
+                          uint32_t *path, uint32_t ls, uint32_t base, uint32_t endpoint,
+                          uint32_t &flags) {
   const uint32_t lane = lane_id();
   const uint32_t *rp = side == 0 ? g.rrow : g.row;
   const uint32_t *cl = side == 0 ? g.rcol : g.col;
   const uint64_t lanes_below = (1ULL << lane) - 1ULL;
   uint32_t x = start;
   for (uint32_t j = lev; j >= 1; --j) {
+    // A level of one node holds x's only predecessor, whatever the draw (the draw is
+    // skipped: every draw is a pure function of its counter, so no other draw moves).
+    // Level 0 is the endpoint itself.
+    if (j == 1 || (j - 1 < (uint32_t)MAXLEV && seg_hi[side][j - 1] - seg_lo[side][j - 1] == 1)) {
+      x = j == 1 ? endpoint : visit[seg_lo[side][j - 1]];
+      if (lane == 0) path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x + base;
+      continue;
+    }
+    const uint32_t beg = rp[x], end = rp[x + 1];  // in flight during the draw
     const u128 bound = ld_sig(sig, x);
     const u128 r = uniform_below(bound, seed, i, stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j),
                                  flags);
     const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1, stored as (j-1)+1
-    const uint32_t beg = rp[x], end = rp[x + 1];
     uint32_t pick = 0xFFFFFFFFu;
     bool row_scan = true;
     if (j - 1 < (uint32_t)MAXLEV) {
@@ -639,10 +828,25 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
   uint64_t *gpi = st.pi + slot * st.pi_cap;
 
   for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
+  for (uint32_t j = tid; j < 3u * WAVE; j += BLOCK) (&L.wmask[0][0])[j] = 0;
+  uint32_t wk = 0;  // arc-window counter of scan_frontier (mod 3)
 
+  // Sample ids: the first three quarters of the rounds are dealt out statically
+  // (workgroup b takes b, b + grid, ...); the rest come from the shared counter, which
+  // evens out the tail.  A device-wide atomic is a slow round trip, so tid 0 fetches
+  // the next id while the current sample starts.
+  const uint32_t grid = gridDim.x;
+  const uint32_t rounds = count / grid - (count / grid) / 4;
+  const uint32_t static_end = rounds * grid;
+  uint32_t taken = 0;  // static ids taken by this workgroup (tid 0)
+  auto next_id = [&]() -> uint32_t {
+    if (taken < rounds) return blockIdx.x + grid * taken++;
+    return static_end + atomicAdd(work, 1u);
+  };
+  uint32_t k_next = tid == 0 ? next_id() : 0u;
   for (;;) {
     if (tid == 0) {
-      const uint32_t k = atomicAdd(work, 1u);
+      const uint32_t k = k_next;
       L.k = k;
       if (MULTI && k < count) {
         uint32_t lo = 0, hi = nseg;  // largest j with segs[j].begin <= k
@@ -672,6 +876,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       base = S.id_base;
       if (S.wide_only) {  // left to the wide-count kernel (uniform for the workgroup)
         if (tid == 0) {
+          k_next = next_id();
           out.flags[k] = FLAG_OVERFLOW;
           out.len[k] = 0;
         }
@@ -682,6 +887,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
 
     // ---- the pair and the two initial levels
     if (tid == 0) {
+      k_next = next_id();
       uint32_t fl = 0;
       const uint32_t s = (uint32_t)uniform_below(u128{g.n, 0}, seed, i, stream_word(phase, P_S, 0), fl).lo;
       const uint32_t tp = (uint32_t)uniform_below(u128{g.n - 1u, 0}, seed, i, stream_word(phase, P_T, 0), fl).lo;
@@ -736,21 +942,30 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         __syncthreads();
         bool ovf_next = false;  // counts of the next level matter only if there is one
         scan_frontier<BLOCK, Scan::Both>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
-                                  next_tag, ovf_next);
+                                  next_tag, ovf_next, wk, false);
         if (L.pi_count > 0) {
           met = true;
           break;
         }
         ovf |= ovf_next;
       } else {
+        // the other side's frontier: a bit filter, and an exact set when it is small
+        constexpr uint32_t FSET_SLOTS = 4 * Lds<BLOCK>::CHUNK;
+        const bool exact = oe - ob <= FSET_SLOTS / 2;
+        if (exact) {
+          for (uint32_t j = tid; j < FSET_SLOTS; j += BLOCK) L.fset[j] = FSET_EMPTY;
+          __syncthreads();
+        }
         for (uint32_t j = ob + tid; j < oe; j += BLOCK) {
-          const uint32_t h = filter_bit(visit[j]);
+          const uint32_t v = visit[j];
+          const uint32_t h = filter_bit(v);
           atomicOr(&L.filter[h >> 5], 1u << (h & 31));
+          if (exact) fset_insert<FSET_SLOTS>(L.fset, v);
         }
         __syncthreads();
         scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
-                                   next_tag, ovf);
-        for (uint32_t j = ob + tid; j < oe; j += BLOCK) L.filter[filter_bit(visit[j]) >> 5] = 0;
+                                   next_tag, ovf, wk, exact);
+        for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
         const uint32_t P = L.pi_count;
         __syncthreads();
         if (P > 0) {
@@ -758,7 +973,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           break;
         }
         scan_frontier<BLOCK, Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
-                                      other_tag, next_tag, ovf);
+                                      other_tag, next_tag, ovf, wk, false);
       }
       __syncthreads();
       const uint32_t ne = L.nvis;
@@ -791,72 +1006,130 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       if (P > st.pi_cap || ls + lt + 2 > out.stride) {
         if (tid == 0) L.flags |= FLAG_CAPACITY;
       } else {
-        // ---- candidate edges in canonical order (v ascending, then w ascending)
-        uint32_t M = 1;
-        while (M < P) M <<= 1;
-        uint64_t *keys = L.pi;
-        if (P <= (uint32_t)WAVE) {
-          if (wid == 0) {
-            const uint64_t x = wave_sort64(lane < P ? L.pi[lane] : ~0ULL);
-            if (lane < P) L.pi[lane] = x;
+        // ---- candidate edges in canonical order (v ascending, then w ascending), weight
+        // sigma_s(v) sigma_t(w) each; draw r < sigma_st = the sum of the weights and
+        // take the edge whose interval of prefixes holds r
+        bool arena = false;  // the sort used the filter's words (cleared again below)
+        if (P <= (uint32_t)BLOCK) {
+          // one candidate per thread, no sort: a candidate's prefix in canonical order is
+          // the sum of the weights of the smaller keys (keys are distinct)
+          bool wov = false;
+          uint64_t key = 0;
+          u128 wt{0, 0};
+          if (tid < P) {
+            key = L.pi[tid];
+            wt = mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), wov);
+            L.c_sig_lo[tid] = wt.lo;
+            L.c_sig_hi[tid] = wt.hi;
           }
-          __syncthreads();
-        } else if (P <= (uint32_t)PI_LDS) {
-          for (uint32_t j = P + tid; j < M; j += BLOCK) L.pi[j] = ~0ULL;
-          __syncthreads();
-          bitonic_sort<BLOCK>(L.pi, M);
-        } else {
-          for (uint32_t j = tid; j < (uint32_t)PI_LDS; j += BLOCK) gpi[j] = L.pi[j];
-          for (uint32_t j = P + tid; j < M; j += BLOCK) gpi[j] = ~0ULL;
-          __syncthreads();
-          bitonic_sort<BLOCK>(gpi, M);
-          keys = gpi;
-        }
-        // ---- sigma_st = sum of sigma_s(v) sigma_t(w); draw r < sigma_st
-        bool wov = false;
-        u128 acc{0, 0};
-        for (uint32_t j = tid; j < P; j += BLOCK) {
-          const uint64_t key = keys[j];
-          acc = add128(acc, mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), wov), wov);
-        }
-        u128 total;
-        (void)block_incl_u128(L, acc, total, wov);
-        if (wov) atomicOr(&L.ovf_any, 2u);
-        __syncthreads();
-        if (tid == 0) {
-          if (L.ovf_any & 2u) {
-            L.flags |= FLAG_OVERFLOW;
-          } else {
-            uint32_t fl = 0;
+          u128 total;
+          (void)block_incl_u128(L, wt, total, wov);  // its barriers publish the weights
+          if (wov) atomicOr(&L.ovf_any, 2u);
+          if (tid == BLOCK - 1) {  // the draw (pure; void if a count overflowed) overlaps
+            uint32_t fl = 0;       // the prefix sums of the other threads
             const u128 r = uniform_below(total, seed, i, stream_word(phase, P_EDGE, 0), fl);
-            L.flags |= fl;
             L.r_lo = r.lo;
             L.r_hi = r.hi;
+            L.rfl = fl;
+            L.win = 0xFFFFFFFFu;
+            L.wkey = L.pi[0];
           }
-          L.win = 0xFFFFFFFFu;
-        }
-        __syncthreads();
-        if (L.flags == 0) {
-          const u128 r{L.r_lo, L.r_hi};
-          u128 carry{0, 0};
-          for (uint32_t base = 0; base < P; base += BLOCK) {
-            const uint32_t j = base + tid;
-            u128 wt{0, 0};
-            bool dm = false;
-            if (j < P) {
-              const uint64_t key = keys[j];
-              wt = mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), dm);
-            }
-            u128 chunk_total;
-            u128 inc = block_incl_u128(L, wt, chunk_total, dm);
-            inc = add128(inc, carry, dm);
-            const u128 exc = sub128(inc, wt);
-            if (j < P && !lt128(r, exc) && lt128(r, inc)) L.win = j;
-            carry = add128(carry, chunk_total, dm);
+          u128 pre{0, 0};
+          if (tid < P) {
+            bool dm = false;  // partial sums of a total that fits do not overflow
+            for (uint32_t j = 0; j < P; ++j)
+              if (L.pi[j] < key) pre = add128(pre, u128{L.c_sig_lo[j], L.c_sig_hi[j]}, dm);
           }
           __syncthreads();
+          const uint32_t fl = (L.ovf_any & 2u) ? (uint32_t)FLAG_OVERFLOW : L.rfl;
+          if (fl == 0 && tid < P) {
+            const u128 r{L.r_lo, L.r_hi};
+            bool dm = false;
+            if (!lt128(r, pre) && lt128(r, add128(pre, wt, dm))) {
+              L.win = tid;
+              L.wkey = key;
+            }
+          }
+          if (tid == 0) L.flags |= fl;
+        } else {
+          // sort, then prefix sums chunk by chunk.  Up to SORT_CAP keys are sorted in the
+          // LDS words the searches no longer need, more in the slot's candidate buffer.
+          constexpr uint32_t NLO = FILTER_WORDS / 2, NHI = 2 * Lds<BLOCK>::CHUNK;
+          constexpr uint32_t SORT_CAP = pow2floor(NLO + NHI);
+          uint32_t M = 1;
+          while (M < P) M <<= 1;
+          arena = M <= SORT_CAP;
+          if (arena) {
+            for (uint32_t j = tid; j < M; j += BLOCK) {
+              const uint64_t x = j < P ? (j < (uint32_t)PI_LDS ? L.pi[j] : gpi[j]) : ~0ULL;
+              if (j < NLO) L.sort_lo[j] = x;
+              else L.sort_hi[j - NLO] = x;
+            }
+            __syncthreads();
+            bitonic_sort2<BLOCK>(L.sort_lo, NLO, L.sort_hi, M);
+          } else {
+            for (uint32_t j = tid; j < (uint32_t)PI_LDS; j += BLOCK) gpi[j] = L.pi[j];
+            for (uint32_t j = P + tid; j < M; j += BLOCK) gpi[j] = ~0ULL;
+            __syncthreads();
+            bitonic_sort<BLOCK>(gpi, M);
+          }
+          auto key_at = [&](uint32_t j) -> uint64_t {
+            return arena ? (j < NLO ? L.sort_lo[j] : L.sort_hi[j - NLO]) : gpi[j];
+          };
+          bool wov = false;
+          u128 acc{0, 0};
+          for (uint32_t j = tid; j < P; j += BLOCK) {
+            const uint64_t key = key_at(j);
+            acc = add128(acc, mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), wov), wov);
+          }
+          u128 total;
+          (void)block_incl_u128(L, acc, total, wov);
+          if (wov) atomicOr(&L.ovf_any, 2u);
+          __syncthreads();
+          if (tid == 0) {
+            if (L.ovf_any & 2u) {
+              L.flags |= FLAG_OVERFLOW;
+            } else {
+              uint32_t fl = 0;
+              const u128 r = uniform_below(total, seed, i, stream_word(phase, P_EDGE, 0), fl);
+              L.flags |= fl;
+              L.r_lo = r.lo;
+              L.r_hi = r.hi;
+            }
+            L.win = 0xFFFFFFFFu;
+            L.wkey = key_at(0);
+          }
+          __syncthreads();
+          if (L.flags == 0) {
+            const u128 r{L.r_lo, L.r_hi};
+            u128 carry{0, 0};
+            for (uint32_t c0 = 0; c0 < P; c0 += BLOCK) {
+              const uint32_t j = c0 + tid;
+              u128 wt{0, 0};
+              bool dm = false;
+              uint64_t key = 0;
+              if (j < P) {
+                key = key_at(j);
+                wt = mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), dm);
+              }
+              u128 chunk_total;
+              u128 inc = block_incl_u128(L, wt, chunk_total, dm);
+              inc = add128(inc, carry, dm);
+              const u128 exc = sub128(inc, wt);
+              if (j < P && !lt128(r, exc) && lt128(r, inc)) {
+                L.win = j;
+                L.wkey = key;
+              }
+              carry = add128(carry, chunk_total, dm);
+            }
+          }
+        }
+        __syncthreads();
+        if (arena)  // the filter is all zero between searches
+          for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
+        if (L.flags == 0) {
           const uint32_t win = L.win;
-          const uint64_t key = keys[win < P ? win : 0];
+          const uint64_t key = L.wkey;  // a candidate of this sample even if none was won
           const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
           __syncthreads();  // the staging area becomes backtracking scratch below
           // ---- the two halves: with two or more waves, wave 0 walks to s while wave 1
@@ -866,12 +1139,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           if (wid == 0) {
             if (lane == 0) path[ls] = v + base;
             backtrack(g, 0, v, ls, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[0], seed, i,
-                      phase, path, ls, base, fl);
+                      phase, path, ls, base, L.s, fl);
           }
           if (wid == (NWAVES >= 2 ? 1u : 0u)) {
             if (lane == 0) path[ls + 1] = w + base;
             backtrack(g, 1, w, lt, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[1], seed, i,
-                      phase, path, ls, base, fl);
+                      phase, path, ls, base, L.t, fl);
           }
           if (win >= P) fl |= FLAG_CAPACITY;
           if (fl && lane == 0) atomicOr(&L.flags, fl);
