@@ -268,13 +268,15 @@ struct Lds {
   };
   uint32_t c_node[CHUNK];
   uint32_t c_off[CHUNK];  // row start minus the row's first position in the chunk's arc space
-  uint32_t wmask[3][WAVE];  // row starts of an arc window, one bit per arc (triple-buffered)
+  static constexpr int MASK_WORDS = BLOCK / 4;  // the widest window: 8 arcs per thread
+  uint32_t wmask[3][MASK_WORDS];  // row starts of an arc window, one bit per arc (triple-buffered)
   uint32_t wfirst[3];       // the row that holds a window's first arc
   uint32_t red32[NWAVES + 1];
   uint32_t red32b[NWAVES + 1];
   uint64_t red_lo[NWAVES];
   uint64_t red_hi[NWAVES];
   uint64_t deg[2];
+  uint32_t st0[2];  // row starts of s (out-row) and t (in-row)
   uint64_t arcs;
   uint64_t new_deg;
   uint64_t r_lo, r_hi, wkey;
@@ -405,14 +407,16 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
                                               uint64_t *sig, uint32_t *visit, uint64_t *gpi,
                                               uint32_t pi_cap, uint32_t other_tag,
                                               uint32_t next_tag, bool &ovf, uint32_t &wk,
-                                              bool exact) {
+                                              bool exact, bool first) {
   constexpr int CHUNK = 2 * BLOCK;
   // arcs per lane per window: a window costs a few dependent round trips whatever its
   // size; wider touch windows than 8 run out of registers
   constexpr int U = MODE == Scan::Touch ? 8 : (MODE == Scan::Discover ? 4 : 2);
   constexpr uint32_t WIN = BLOCK * U;
   constexpr uint32_t NWORDS = WIN / 32;
-  static_assert(NWORDS <= (uint32_t)WAVE && WIN % 64 == 0, "a window's mask fits one wave");
+  static_assert(NWORDS <= (uint32_t)Lds<BLOCK>::MASK_WORDS && NWORDS <= (uint32_t)WAVE &&
+                    WIN % 64 == 0,
+                "a window's mask fits its buffer and one wave");
   const uint32_t tid = threadIdx.x, lane = lane_id();
   const uint32_t wid = __builtin_amdgcn_readfirstlane(tid / WAVE);
   const uint32_t *rp = me == 0 ? g.row : g.rrow;
@@ -423,20 +427,26 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
   for (uint32_t cb = fb; cb < fe; cb += CHUNK) {
     const uint32_t m = min((uint32_t)CHUNK, fe - cb);
     uint32_t u[2] = {0, 0}, st[2] = {0, 0}, d[2] = {0, 0};
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-      const uint32_t j = 2 * tid + q;
-      if (j < m) {
-        u[q] = visit[cb + j];
-        st[q] = rp[u[q]];
-        d[q] = rp[u[q] + 1] - st[q];
-      }
-    }
     u128 su[2] = {{0, 0}, {0, 0}};
-    if (MODE != Scan::Touch) {
+    if (first) {
+      // the endpoint alone (level 0): its row and count are known, nothing to load
+      if (tid == 0) {
+        u[0] = me == 0 ? L.s : L.t;
+        st[0] = L.st0[me];
+        d[0] = (uint32_t)L.deg[me];
+        su[0] = u128{1, 0};
+      }
+    } else {
 #pragma unroll
-      for (int q = 0; q < 2; ++q)
-        if (d[q] != 0) su[q] = ld_sig(sig, u[q]);
+      for (int q = 0; q < 2; ++q) {
+        const uint32_t j = 2 * tid + q;
+        if (j < m) {
+          u[q] = visit[cb + j];
+          st[q] = rp[u[q]];
+          d[q] = rp[u[q] + 1] - st[q];
+          if (MODE != Scan::Touch) su[q] = ld_sig(sig, u[q]);
+        }
+      }
     }
     uint32_t ex, cx, tot, nrows;
     block_excl2_u32(L, d[0] + d[1], (d[0] != 0 ? 1u : 0u) + (d[1] != 0 ? 1u : 0u), ex, cx, tot,
@@ -463,8 +473,8 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
     // shuffles below must not see inactive lanes.
     for (uint32_t e0 = 0; e0 < tot; e0 += WIN) {
       const uint32_t kn = wk == 2 ? 0u : wk + 1;
-      // clear all WAVE words: scans of other modes use more words of the same masks
-      if (tid < (uint32_t)WAVE) L.wmask[kn][tid] = 0;
+      // clear every word: scans of other modes use more words of the same masks
+      if (tid < (uint32_t)Lds<BLOCK>::MASK_WORDS) L.wmask[kn][tid] = 0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
         if (d[q] != 0) {
@@ -828,7 +838,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
   uint64_t *gpi = st.pi + slot * st.pi_cap;
 
   for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
-  for (uint32_t j = tid; j < 3u * WAVE; j += BLOCK) (&L.wmask[0][0])[j] = 0;
+  for (uint32_t j = tid; j < 3u * Lds<BLOCK>::MASK_WORDS; j += BLOCK) (&L.wmask[0][0])[j] = 0;
   uint32_t wk = 0;  // arc-window counter of scan_frontier (mod 3)
 
   // Sample ids: the first three quarters of the rounds are dealt out statically
@@ -885,12 +895,17 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       }
     }
 
-    // ---- the pair and the two initial levels
-    if (tid == 0) {
+    // ---- the pair and the two initial levels (lanes 0 and 1 draw s and t' side by side)
+    if (wid == 0) {
+      uint32_t fl = 0, x = 0;
+      if (lane < 2)
+        x = (uint32_t)uniform_below(u128{lane == 0 ? g.n : g.n - 1u, 0}, seed, i,
+                                    stream_word(phase, lane == 0 ? P_S : P_T, 0), fl).lo;
+      const uint32_t s = __builtin_amdgcn_readlane(x, 0);
+      const uint32_t tp = __builtin_amdgcn_readlane(x, 1);
+      fl = __builtin_amdgcn_readlane(fl, 0) | __builtin_amdgcn_readlane(fl, 1);
+      if (lane == 0) {
       k_next = next_id();
-      uint32_t fl = 0;
-      const uint32_t s = (uint32_t)uniform_below(u128{g.n, 0}, seed, i, stream_word(phase, P_S, 0), fl).lo;
-      const uint32_t tp = (uint32_t)uniform_below(u128{g.n - 1u, 0}, seed, i, stream_word(phase, P_T, 0), fl).lo;
       const uint32_t t = tp + (tp >= s ? 1u : 0u);
       L.s = s;
       L.t = t;
@@ -907,12 +922,16 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       L.seg_lo[0][0] = 0; L.seg_hi[0][0] = 1;
       L.seg_lo[1][0] = 1; L.seg_hi[1][0] = 2;
       L.lvl[0] = 0; L.lvl[1] = 0;
-      L.deg[0] = (uint64_t)(g.row[s + 1] - g.row[s]);
-      L.deg[1] = (uint64_t)(g.rrow[t + 1] - g.rrow[t]);
+      const uint32_t s0 = g.row[s], t0 = g.rrow[t];
+      L.st0[0] = s0;
+      L.st0[1] = t0;
+      L.deg[0] = (uint64_t)(g.row[s + 1] - s0);
+      L.deg[1] = (uint64_t)(g.rrow[t + 1] - t0);
       L.arcs = 0;
       L.nvis = 2;
       L.flags = fl;
       L.ovf_any = 0;
+      }
     }
     __syncthreads();
 
@@ -942,7 +961,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         __syncthreads();
         bool ovf_next = false;  // counts of the next level matter only if there is one
         scan_frontier<BLOCK, Scan::Both>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
-                                  next_tag, ovf_next, wk, false);
+                                  next_tag, ovf_next, wk, false, lme == 0);
         if (L.pi_count > 0) {
           met = true;
           break;
@@ -964,7 +983,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         }
         __syncthreads();
         scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
-                                   next_tag, ovf, wk, exact);
+                                   next_tag, ovf, wk, exact, lme == 0);
         for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
         const uint32_t P = L.pi_count;
         __syncthreads();
@@ -973,7 +992,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           break;
         }
         scan_frontier<BLOCK, Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
-                                      other_tag, next_tag, ovf, wk, false);
+                                      other_tag, next_tag, ovf, wk, false, lme == 0);
       }
       __syncthreads();
       const uint32_t ne = L.nvis;
