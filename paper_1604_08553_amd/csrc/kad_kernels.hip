@@ -267,7 +267,9 @@ struct Lds {
     uint64_t sort_hi[2 * CHUNK];
   };
   uint32_t c_node[CHUNK];
-  uint32_t c_off[CHUNK];  // row start minus the row's first position in the chunk's arc space
+  uint32_t c_off[CHUNK];  // short rows: row start minus the row's first position in the
+                          // chunk's arc space; long rows: the row start
+  uint32_t c_deg[CHUNK];
   static constexpr int MASK_WORDS = BLOCK / 4;  // the widest window: 8 arcs per thread
   uint32_t wmask[3][MASK_WORDS];  // row starts of an arc window, one bit per arc (triple-buffered)
   uint32_t wfirst[3];       // the row that holds a window's first arc
@@ -391,16 +393,19 @@ enum class Scan { Touch, Discover, Both };
 
 // One pass over the rows of frontier [fb, fe), chunked through LDS.
 //
-// A chunk's rows of nonzero degree are laid end to end in one arc space [0, tot)
-// (rows of degree zero own no arcs and are dropped).  The arcs are walked in windows
-// of BLOCK * U; lane l of wave w takes arcs e0 + w*WAVE*U + q*WAVE + l, q < U.  The
-// row that owns an arc is found without a search: every row that starts inside the
-// window sets the bit of its first position in an LDS mask, and the owner of
-// position p is the window's first row plus the number of starts in (0, p] -- a
-// popcount over the mask.  The masks are triple-buffered so that a window takes one
-// barrier: window k sets its bits in mask k mod 3 and clears mask (k+1) mod 3, which
-// every wave finished reading before the barrier of window k-1.  wk is the window
-// counter (mod 3), carried from call to call.
+// Rows of at least one window of arcs ("long" rows) are walked by the waves piece by
+// piece: a piece is WAVE * U consecutive arcs of one row, so every arc's row is known
+// and a long row costs no bookkeeping.  The other rows of nonzero degree ("short"
+// rows; rows of degree zero own no arcs and are dropped) are laid end to end in one
+// arc space [0, tot) and walked in windows of BLOCK * U: lane l of wave w takes arcs
+// e0 + w*WAVE*U + q*WAVE + l, q < U.  The short row that owns an arc is found without
+// a search: every short row that starts inside the window sets the bit of its first
+// position in an LDS mask, and the owner of position p is the window's first row plus
+// the number of starts in (0, p] -- a popcount over the mask.  The masks are
+// triple-buffered so that a window takes one barrier: window k sets its bits in mask
+// k mod 3 and clears mask (k+1) mod 3, which every wave finished reading before the
+// barrier of window k-1.  wk is the window counter (mod 3), carried from call to call.
+// Short rows take the chunk slots from the front, long rows from the back.
 template <int BLOCK, Scan MODE>
 __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, uint32_t me,
                                               uint32_t fb, uint32_t fe, uint32_t *tag,
@@ -409,10 +414,12 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
                                               uint32_t next_tag, bool &ovf, uint32_t &wk,
                                               bool exact, bool first) {
   constexpr int CHUNK = 2 * BLOCK;
-  // arcs per lane per window: a window costs a few dependent round trips whatever its
-  // size; wider touch windows than 8 run out of registers
+  // arcs per lane per window or piece: a window costs a few dependent round trips
+  // whatever its size; wider touch windows than 8 run out of registers
   constexpr int U = MODE == Scan::Touch ? 8 : (MODE == Scan::Discover ? 4 : 2);
   constexpr uint32_t WIN = BLOCK * U;
+  constexpr uint32_t PIECE = WAVE * U;
+  constexpr uint32_t NWAVES = BLOCK / WAVE;
   constexpr uint32_t NWORDS = WIN / 32;
   static_assert(NWORDS <= (uint32_t)Lds<BLOCK>::MASK_WORDS && NWORDS <= (uint32_t)WAVE &&
                     WIN % 64 == 0,
@@ -424,6 +431,117 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
   // bits of the mask word at or below this lane's position (positions of a wave's
   // group are 64-aligned, so a lane always sits at bit lane mod 32)
   const uint32_t below = ((1u << (lane & 31)) << 1) - 1u;
+
+  // The arcs ww[q] of this lane (bit q of vm: the arc exists), owned by the chunk rows
+  // owner(q): the touch test or the discovery step.  Every stage first issues the loads
+  // or atomics of all U arcs and only then uses their results, so a lane keeps U memory
+  // requests in flight instead of waiting on one arc at a time.
+  auto process = [&](const uint32_t (&ww)[U], uint32_t vm, auto owner) {
+    if (MODE == Scan::Touch) {
+      // filter probes; an arc that passes is confirmed in the exact set when the other
+      // frontier has one, else by its tag (the tag loads of all arcs go out together)
+      uint32_t fword[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) fword[q] = L.filter[filter_bit(ww[q]) >> 5];
+      uint32_t pass = 0, hitm = 0;
+#pragma unroll
+      for (int q = 0; q < U; ++q)
+        pass |= (fword[q] >> (filter_bit(ww[q]) & 31)) & (vm >> q) & 1u ? 1u << q : 0u;
+      if (exact) {
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          if ((pass >> q) & 1u) hitm |= fset_has<4 * CHUNK>(L.fset, ww[q]) ? 1u << q : 0u;
+      } else {
+        uint32_t tg[U];
+#pragma unroll
+        for (int q = 0; q < U; ++q) tg[q] = (pass >> q) & 1u ? ld_tag(tag + ww[q]) : 0u;
+#pragma unroll
+        for (int q = 0; q < U; ++q) hitm |= tg[q] == other_tag ? 1u << q : 0u;  // never 0
+      }
+      if (__ballot(hitm != 0)) {  // uniform: some lane of this wave found candidates
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const bool hit = (hitm >> q) & 1u;
+          uint32_t rank = 0;
+          const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
+          if (hit) {
+            const uint32_t u = L.c_node[owner(q)], w = ww[q];
+            const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+            const uint32_t idx = base + rank;
+            if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
+            else if (idx < pi_cap) gpi[idx] = key;
+          }
+        }
+      }
+    } else {
+      // Claims: one compare-and-swap per arc returns the head's tag as it was (0 if
+      // unseen, then this arc claimed it; next_tag if another arc of this level did;
+      // other_tag if the head is in the other side's frontier).
+      uint32_t tg[U], dm = 0;  // dm bit q: this lane's arc of group q claimed its head
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        tg[q] = 0;
+        if ((vm >> q) & 1u) {
+          const uint32_t old = cas_tag(tag + ww[q], 0u, next_tag);
+          dm |= old == 0 ? 1u << q : 0u;
+          tg[q] = old == 0 ? next_tag : old;
+        }
+      }
+      // sigma(w) += sigma(u) on the low words, the appends of the claimed heads and
+      // the loads of their degrees all go out before any result is used; the carries
+      // into the high words follow
+      uint64_t old_lo[U];
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        old_lo[q] = 0;
+        if (tg[q] == next_tag) old_lo[q] = add_u64(sig + 2 * (size_t)ww[q], L.c_sig_lo[owner(q)]);
+      }
+      if (MODE == Scan::Both) {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          const bool hit = tg[q] == other_tag;  // never 0
+          uint32_t prank = 0;
+          const uint32_t pbase = wave_reserve(hit, &L.pi_count, prank);
+          if (hit) {
+            const uint32_t u = L.c_node[owner(q)], w = ww[q];
+            const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+            const uint32_t idx = pbase + prank;
+            if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
+            else if (idx < pi_cap) gpi[idx] = key;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        const bool disc = (dm >> q) & 1u;
+        uint32_t rank = 0;
+        const uint32_t base = wave_reserve(disc, &L.nvis, rank);
+        if (disc) visit[base + rank] = ww[q];
+      }
+      if (__ballot(dm != 0)) {  // uniform: some lane of this wave discovered a node
+        uint64_t dg = 0;
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          if ((dm >> q) & 1u) dg += (uint64_t)(rp[ww[q] + 1] - rp[ww[q]]);
+        const uint64_t sum = wave_sum_u64(dg);
+        if (lane == 0) atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)sum);
+      }
+#pragma unroll
+      for (int q = 0; q < U; ++q) {
+        if (tg[q] == next_tag) {
+          const uint32_t j = owner(q);
+          const uint64_t xlo = L.c_sig_lo[j], xhi = L.c_sig_hi[j];
+          const uint64_t add = xhi + ((old_lo[q] + xlo < old_lo[q]) ? 1u : 0u);
+          ovf |= add < xhi;
+          if (add != 0) {
+            const uint64_t oh = add_u64(sig + 2 * (size_t)ww[q] + 1, add);
+            ovf |= oh + add < oh;
+          }
+        }
+      }
+    }
+  };
+
   for (uint32_t cb = fb; cb < fe; cb += CHUNK) {
     const uint32_t m = min((uint32_t)CHUNK, fe - cb);
     uint32_t u[2] = {0, 0}, st[2] = {0, 0}, d[2] = {0, 0};
@@ -448,36 +566,64 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
         }
       }
     }
-    uint32_t ex, cx, tot, nrows;
-    block_excl2_u32(L, d[0] + d[1], (d[0] != 0 ? 1u : 0u) + (d[1] != 0 ? 1u : 0u), ex, cx, tot,
-                    nrows);
-    // this thread's rows: chunk slot, first position in the arc space, end
+    // classes: 0 none, 1 short, 2 long
+    uint32_t cls[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) cls[q] = d[q] == 0 ? 0u : (d[q] < WIN ? 1u : 2u);
+    const uint32_t sarcs = (cls[0] == 1 ? d[0] : 0u) + (cls[1] == 1 ? d[1] : 0u);
+    const uint32_t cnts = (cls[0] == 1 ? 1u : 0u) + (cls[1] == 1 ? 1u : 0u) +
+                          ((cls[0] == 2 ? 1u : 0u) + (cls[1] == 2 ? 1u : 0u)) * 65536u;
+    uint32_t ex, cx, tot, ncx;
+    block_excl2_u32(L, sarcs, cnts, ex, cx, tot, ncx);
+    const uint32_t nlong = ncx >> 16;
+    // this thread's rows: chunk slot and (short rows) first position in the arc space
     uint32_t slot[2], pos[2];
-    slot[0] = cx;
-    slot[1] = cx + (d[0] != 0 ? 1u : 0u);
+    slot[0] = cls[0] == 2 ? CHUNK - 1 - (cx >> 16) : (cx & 0xFFFFu);
+    slot[1] = cls[1] == 2 ? CHUNK - 1 - (cx >> 16) - (cls[0] == 2 ? 1u : 0u)
+                          : (cx & 0xFFFFu) + (cls[0] == 1 ? 1u : 0u);
     pos[0] = ex;
-    pos[1] = ex + d[0];
+    pos[1] = ex + (cls[0] == 1 ? d[0] : 0u);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-      if (d[q] != 0) {
+      if (cls[q] != 0) {
         L.c_node[slot[q]] = u[q];
-        L.c_off[slot[q]] = st[q] - pos[q];
+        L.c_off[slot[q]] = cls[q] == 2 ? st[q] : st[q] - pos[q];
+        L.c_deg[slot[q]] = d[q];
         if (MODE != Scan::Touch) {
           L.c_sig_lo[slot[q]] = su[q].lo;
           L.c_sig_hi[slot[q]] = su[q].hi;
         }
       }
     }
-    (void)nrows;
-    // Every lane of a wave runs the same number of windows because the ballots and
-    // shuffles below must not see inactive lanes.
+
+    // ---- long rows, piece by piece (no barrier between pieces)
+    if (nlong > 0) {
+      __syncthreads();
+      for (uint32_t r = 0; r < nlong; ++r) {
+        const uint32_t sl = CHUNK - 1 - r;
+        const uint32_t rst = L.c_off[sl], rd = L.c_deg[sl];
+        for (uint32_t off = wid * PIECE; off < rd; off += NWAVES * PIECE) {
+          uint32_t ww[U], vm = 0;
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const uint32_t e = off + q * WAVE + lane;
+            vm |= (e < rd ? 1u : 0u) << q;
+            ww[q] = cl[rst + min(e, rd - 1)];
+          }
+          process(ww, vm, [&](int) -> uint32_t { return sl; });
+        }
+      }
+    }
+
+    // ---- short rows, window by window.  Every lane of a wave runs the same number of
+    // windows because the ballots and shuffles must not see inactive lanes.
     for (uint32_t e0 = 0; e0 < tot; e0 += WIN) {
       const uint32_t kn = wk == 2 ? 0u : wk + 1;
       // clear every word: scans of other modes use more words of the same masks
       if (tid < (uint32_t)Lds<BLOCK>::MASK_WORDS) L.wmask[kn][tid] = 0;
 #pragma unroll
       for (int q = 0; q < 2; ++q) {
-        if (d[q] != 0) {
+        if (cls[q] == 1) {
           const uint32_t s0 = pos[q];
           if (s0 > e0 && s0 - e0 < WIN)
             atomicOr(&L.wmask[wk][(s0 - e0) >> 5], 1u << ((s0 - e0) & 31));
@@ -514,117 +660,13 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
       }
       auto owner = [&](int q) -> uint32_t { return (jj[q / 2] >> (16 * (q % 2))) & 0xFFFFu; };
       // Lanes past the end of the arc space re-read its last arc (their owner is the
-      // last row), so every lane loads and the LDS reads and the row loads of all U
-      // groups go out back to back.
+      // last short row), so every lane loads and the LDS reads and the row loads of
+      // all U groups go out back to back.
 #pragma unroll
       for (int q = 0; q < U; ++q) ww[q] = L.c_off[owner(q)];
 #pragma unroll
       for (int q = 0; q < U; ++q) ww[q] = cl[ww[q] + min(e0 + fw * 32 + q * WAVE + lane, tot - 1)];
-      // Every stage below first issues the loads or atomics of all U arcs and only
-      // then uses their results, so a lane keeps U memory requests in flight instead
-      // of waiting on one arc at a time.
-      if (MODE == Scan::Touch) {
-        // filter probes; an arc that passes is confirmed in the exact set when the other
-        // frontier has one, else by its tag (the tag loads of all arcs go out together)
-        uint32_t fword[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) fword[q] = L.filter[filter_bit(ww[q]) >> 5];
-        uint32_t pass = 0, hitm = 0;
-#pragma unroll
-        for (int q = 0; q < U; ++q)
-          pass |= (fword[q] >> (filter_bit(ww[q]) & 31)) & (vm >> q) & 1u ? 1u << q : 0u;
-        if (exact) {
-#pragma unroll
-          for (int q = 0; q < U; ++q)
-            if ((pass >> q) & 1u) hitm |= fset_has<4 * CHUNK>(L.fset, ww[q]) ? 1u << q : 0u;
-        } else {
-          uint32_t tg[U];
-#pragma unroll
-          for (int q = 0; q < U; ++q) tg[q] = (pass >> q) & 1u ? ld_tag(tag + ww[q]) : 0u;
-#pragma unroll
-          for (int q = 0; q < U; ++q) hitm |= tg[q] == other_tag ? 1u << q : 0u;  // never 0
-        }
-        if (__ballot(hitm != 0)) {  // uniform: some lane of this wave found candidates
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-            const bool hit = (hitm >> q) & 1u;
-            uint32_t rank = 0;
-            const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
-            if (hit) {
-              const uint32_t u = L.c_node[owner(q)], w = ww[q];
-              const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
-              const uint32_t idx = base + rank;
-              if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
-              else if (idx < pi_cap) gpi[idx] = key;
-            }
-          }
-        }
-      } else {
-        // Claims: one compare-and-swap per arc returns the head's tag as it was (0 if
-        // unseen, then this arc claimed it; next_tag if another arc of this level did;
-        // other_tag if the head is in the other side's frontier).
-        uint32_t tg[U], dm = 0;  // dm bit q: this lane's arc of group q claimed its head
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          tg[q] = 0;
-          if ((vm >> q) & 1u) {
-            const uint32_t old = cas_tag(tag + ww[q], 0u, next_tag);
-            dm |= old == 0 ? 1u << q : 0u;
-            tg[q] = old == 0 ? next_tag : old;
-          }
-        }
-        // sigma(w) += sigma(u) on the low words, the appends of the claimed heads and
-        // the loads of their degrees all go out before any result is used; the carries
-        // into the high words follow
-        uint64_t old_lo[U];
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          old_lo[q] = 0;
-          if (tg[q] == next_tag) old_lo[q] = add_u64(sig + 2 * (size_t)ww[q], L.c_sig_lo[owner(q)]);
-        }
-        if (MODE == Scan::Both) {
-#pragma unroll
-          for (int q = 0; q < U; ++q) {
-            const bool hit = tg[q] == other_tag;  // never 0
-            uint32_t prank = 0;
-            const uint32_t pbase = wave_reserve(hit, &L.pi_count, prank);
-            if (hit) {
-              const uint32_t u = L.c_node[owner(q)], w = ww[q];
-              const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
-              const uint32_t idx = pbase + prank;
-              if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
-              else if (idx < pi_cap) gpi[idx] = key;
-            }
-          }
-        }
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          const bool disc = (dm >> q) & 1u;
-          uint32_t rank = 0;
-          const uint32_t base = wave_reserve(disc, &L.nvis, rank);
-          if (disc) visit[base + rank] = ww[q];
-        }
-        if (__ballot(dm != 0)) {  // uniform: some lane of this wave discovered a node
-          uint64_t dg = 0;
-#pragma unroll
-          for (int q = 0; q < U; ++q)
-            if ((dm >> q) & 1u) dg += (uint64_t)(rp[ww[q] + 1] - rp[ww[q]]);
-          const uint64_t sum = wave_sum_u64(dg);
-          if (lane == 0) atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)sum);
-        }
-#pragma unroll
-        for (int q = 0; q < U; ++q) {
-          if (tg[q] == next_tag) {
-            const uint64_t xlo = L.c_sig_lo[owner(q)], xhi = L.c_sig_hi[owner(q)];
-            const uint64_t add = xhi + ((old_lo[q] + xlo < old_lo[q]) ? 1u : 0u);
-            ovf |= add < xhi;
-            if (add != 0) {
-              const uint64_t oh = add_u64(sig + 2 * (size_t)ww[q] + 1, add);
-              ovf |= oh + add < oh;
-            }
-          }
-        }
-      }
+      process(ww, vm, owner);
     }
     __syncthreads();
   }
