@@ -573,8 +573,14 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
     const uint32_t sarcs = (cls[0] == 1 ? d[0] : 0u) + (cls[1] == 1 ? d[1] : 0u);
     const uint32_t cnts = (cls[0] == 1 ? 1u : 0u) + (cls[1] == 1 ? 1u : 0u) +
                           ((cls[0] == 2 ? 1u : 0u) + (cls[1] == 2 ? 1u : 0u)) * 65536u;
-    uint32_t ex, cx, tot, ncx;
-    block_excl2_u32(L, sarcs, cnts, ex, cx, tot, ncx);
+    uint32_t ex = 0, cx = 0, tot, ncx;
+    if (first) {  // one row, held by thread 0: the scan's results are known
+      const uint32_t dd = (uint32_t)L.deg[me];
+      tot = dd < WIN ? dd : 0u;
+      ncx = dd == 0 ? 0u : (dd < WIN ? 1u : 65536u);
+    } else {
+      block_excl2_u32(L, sarcs, cnts, ex, cx, tot, ncx);
+    }
     const uint32_t nlong = ncx >> 16;
     // this thread's rows: chunk slot and (short rows) first position in the arc space
     uint32_t slot[2], pos[2];
@@ -596,19 +602,30 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
       }
     }
 
-    // ---- long rows, piece by piece (no barrier between pieces)
+    // ---- long rows, piece by piece (no barrier between pieces); the row loads of a
+    // wave's next piece go out before its current piece is tested
     if (nlong > 0) {
       __syncthreads();
       for (uint32_t r = 0; r < nlong; ++r) {
         const uint32_t sl = CHUNK - 1 - r;
         const uint32_t rst = L.c_off[sl], rd = L.c_deg[sl];
-        for (uint32_t off = wid * PIECE; off < rd; off += NWAVES * PIECE) {
+        uint32_t nx[U];
+        uint32_t off = wid * PIECE;
+        if (off < rd) {
+#pragma unroll
+          for (int q = 0; q < U; ++q) nx[q] = cl[rst + min(off + q * WAVE + lane, rd - 1)];
+        }
+        for (; off < rd; off += NWAVES * PIECE) {
           uint32_t ww[U], vm = 0;
 #pragma unroll
           for (int q = 0; q < U; ++q) {
-            const uint32_t e = off + q * WAVE + lane;
-            vm |= (e < rd ? 1u : 0u) << q;
-            ww[q] = cl[rst + min(e, rd - 1)];
+            ww[q] = nx[q];
+            vm |= (off + q * WAVE + lane < rd ? 1u : 0u) << q;
+          }
+          const uint32_t nxt = off + NWAVES * PIECE;
+          if (nxt < rd) {
+#pragma unroll
+            for (int q = 0; q < U; ++q) nx[q] = cl[rst + min(nxt + q * WAVE + lane, rd - 1)];
           }
           process(ww, vm, [&](int) -> uint32_t { return sl; });
         }
