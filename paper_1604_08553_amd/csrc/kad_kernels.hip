@@ -801,12 +801,22 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
           bool match = false;
           if (q < Le) {
             cand = visit[q];
-            uint32_t lo = beg, hi = end;
+            // the arc between cand and x (cand -> x on the s side, x -> cand on the t
+            // side) is searched in the shorter of x's row and cand's row of the other
+            // direction: x is usually a hub, cand usually not
+            const uint32_t *orp = side == 0 ? g.row : g.rrow;
+            const uint32_t *ocl = side == 0 ? g.col : g.rcol;
+            const uint32_t cb = orp[cand], ce = orp[cand + 1];
+            const bool in_cand = ce - cb < end - beg;
+            const uint32_t *arr = in_cand ? ocl : cl;
+            const uint32_t target = in_cand ? x : cand;
+            uint32_t lo = in_cand ? cb : beg, hi = in_cand ? ce : end;
+            const uint32_t stop = hi;
             while (lo < hi) {
               const uint32_t mid = (lo + hi) >> 1;
-              if (cl[mid] < cand) lo = mid + 1; else hi = mid;
+              if (arr[mid] < target) lo = mid + 1; else hi = mid;
             }
-            match = lo < end && cl[lo] == cand;
+            match = lo < stop && arr[lo] == target;
           }
           const uint64_t mk = __ballot(match);
           if (match) {
@@ -1115,6 +1125,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           u128 pre{0, 0};
           if (tid < P) {
             bool dm = false;  // partial sums of a total that fits do not overflow
+#pragma unroll 4
             for (uint32_t j = 0; j < P; ++j)
               if (L.pi[j] < key) pre = add128(pre, u128{L.c_sig_lo[j], L.c_sig_hi[j]}, dm);
           }
