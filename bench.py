@@ -302,7 +302,8 @@ def bench_serve(args, torch, gg, kad):
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=None,
+                    help="timed runs (default 10; 3 for dcl4m)")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--workload", default="cl1m")
     ap.add_argument("--epsilon", type=float, default=None,
@@ -327,6 +328,8 @@ def main():
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM counters)")
     args = ap.parse_args()
+    if args.steps is None:
+        args.steps = 3 if args.workload == "dcl4m" else 10
     if args.epsilon is None:
         args.epsilon = {"er2000": 0.01, "dcl4m": 0.0002}.get(args.workload, 0.005)
     if args.mode is None:
@@ -373,15 +376,16 @@ def main():
               kernel_batch=args.kernel_batch, check_interval=args.check_interval)
     if args.mode == "topk":
         kw.update(mode="topk", k=args.k)
+    arrays = None  # result arrays, allocated by the warmup and reused by every step
     for w in range(args.warmup):
-        r = kad.run(ctx, G, **kw)
+        r = kad.run(ctx, G, out=arrays, **kw)
+        arrays = {k: r[k] for k in ("count", "bc", "lower", "upper")}
         print(f"[bench] warmup {w}: tau={r['tau']} {r['seconds']:.3f} s", file=sys.stderr, flush=True)
 
     ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
-    arrays = None  # result arrays reused across steps
     for s in range(args.steps):
         r = kad.run(ctx, G, out=arrays, **kw)
         arrays = {k: r[k] for k in ("count", "bc", "lower", "upper")}

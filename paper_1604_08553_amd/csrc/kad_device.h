@@ -134,6 +134,12 @@ hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t
 
 // Zero a device buffer with a kernel (no memset node when captured).
 hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream);
+// hist[c] += #{v < n : count[v] == c} for c < bins (hist zeroed by the caller)
+hipError_t launch_count_hist(const uint64_t *count, uint32_t n, uint32_t *hist, uint32_t bins,
+                             hipStream_t stream);
+// group[v] = cgrp[count[v]] for v < n (count[v] < bins)
+hipError_t launch_group_map(const uint64_t *count, uint32_t n, const uint32_t *cgrp, uint32_t bins,
+                            uint32_t *group, hipStream_t stream);
 // dst[i] = src[i], i < count, by a kernel on `stream`; either side may be pinned,
 // coherent host memory.  Used instead of runtime copies where a copy must not wait
 // behind kernels of other streams.

@@ -129,6 +129,10 @@ struct kad_ctx {
   kad::OutSet outs[2];
   kad::DevBuf<uint32_t> work, group;
   kad::DevBuf<uint64_t> count, gmax;
+  kad::DevBuf<uint64_t> count0d;         // pilot counts (all-nodes runs)
+  kad::DevBuf<uint32_t> hist, cgrp;      // their histogram; count -> stopping group
+  kad::PinBuf<uint32_t> h_hist, h_cgrp;
+  kad::PinBuf<uint64_t> h_count0p;
   kad::DevBuf<uint32_t> bins, bin_count;  // hit-reduction scratch (bin_count all zero between calls)
   kad::DevBuf<uint32_t> tile_start, tile_fill;  // compact layout (tile_fill all zero between calls)
   uint64_t bins_cap = 0;
@@ -226,6 +230,11 @@ uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t coun
 void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule_stop,
                   double eps, const double *L_l, const double *L_u,
                   const std::vector<uint32_t> &group_of, double *bc, double *lo, double *hi);
+// The same outputs when node v's group is cgrp[count0[v]] (group L values gL_l, gL_u).
+void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule,
+                        double eps, const uint64_t *count0, const std::vector<uint32_t> &cgrp,
+                        const std::vector<double> &gL_l, const std::vector<double> &gL_u,
+                        double *bc, double *lo, double *hi);
 // Top-k selection: nodes with rank_lo <= k ordered by (count desc, id asc).
 void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
                  std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,

@@ -1016,7 +1016,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       const uint32_t other_tag = (ot == 0 ? 0u : TAG_T) | (lot + 1);
       const uint32_t next_tag = (me == 0 ? 0u : TAG_T) | (lme + 2);
       const uint64_t dme = L.deg[me];
-      __syncthreads();
+      // (tid 0 resets fields read only before the previous level's last barrier; the
+      // barrier before each scan publishes the resets)
       if (tid == 0) {
         L.arcs += dme;
         L.pi_count = 0;
@@ -1054,8 +1055,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
                                    next_tag, ovf, wk, exact, lme == 0);
         for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
-        const uint32_t P = L.pi_count;
-        __syncthreads();
+        const uint32_t P = L.pi_count;  // final: the scan ends with a barrier
         if (P > 0) {
           met = true;
           break;
@@ -1063,10 +1063,9 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         scan_frontier<BLOCK, Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
                                       other_tag, next_tag, ovf, wk, false, lme == 0);
       }
-      __syncthreads();
+      // final: every scan ends with a barrier; tid 0 writes other fields below
       const uint32_t ne = L.nvis;
       const uint64_t nd = L.new_deg;
-      __syncthreads();
       if (ne == nb) break;  // the expanded side closed: s and t are disconnected
       if (tid == 0) {
         L.fb[me] = nb;
@@ -1446,6 +1445,40 @@ __global__ __launch_bounds__(HIT_BLOCK) void hit_tile_kernel(const uint32_t *bin
   if (threadIdx.x == 0) {  // ready for the next call
     bin_count[t] = 0;
     if (tile_fill) tile_fill[t] = 0;
+  }
+}
+
+// Histogram of pilot counts over [0, bins): the first LDS_BINS bins (where nearly every
+// node falls) are aggregated per workgroup in LDS, higher counts go to global atomics.
+// Counts never exceed bins - 1 (a pilot count is at most the pilot's sample count); the
+// clamp only keeps every access in bounds.
+constexpr uint32_t HIST_LDS_BINS = 4096;
+__global__ __launch_bounds__(256) void count_hist_kernel(const uint64_t *__restrict__ count,
+                                                         uint32_t n, uint32_t *hist,
+                                                         uint32_t bins) {
+  __shared__ uint32_t h[HIST_LDS_BINS];
+  const uint32_t lb = min(bins, HIST_LDS_BINS);
+  for (uint32_t j = threadIdx.x; j < lb; j += 256) h[j] = 0;
+  __syncthreads();
+  for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+    const uint64_t c = count[v];
+    const uint32_t b = c < bins ? (uint32_t)c : bins - 1;
+    if (b < lb) atomicAdd(&h[b], 1u);
+    else atomicAdd(&hist[b], 1u);
+  }
+  __syncthreads();
+  for (uint32_t j = threadIdx.x; j < lb; j += 256)
+    if (h[j]) atomicAdd(&hist[j], h[j]);
+}
+
+// group[v] = cgrp[pilot count of v]
+__global__ __launch_bounds__(256) void group_map_kernel(const uint64_t *__restrict__ count,
+                                                        uint32_t n,
+                                                        const uint32_t *__restrict__ cgrp,
+                                                        uint32_t bins, uint32_t *group) {
+  for (uint32_t v = blockIdx.x * 256 + threadIdx.x; v < n; v += gridDim.x * 256) {
+    const uint64_t c = count[v];
+    group[v] = cgrp[c < bins ? c : bins - 1];
   }
 }
 
@@ -2135,6 +2168,23 @@ hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStrea
   if (count == 0) return hipSuccess;
   const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 65536);
   hipLaunchKernelGGL(fill_u32_kernel, dim3((uint32_t)blocks), dim3(256), 0, stream, p, count, value);
+  return hipGetLastError();
+}
+
+hipError_t launch_count_hist(const uint64_t *count, uint32_t n, uint32_t *hist, uint32_t bins,
+                             hipStream_t stream) {
+  if (n == 0 || bins == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(count_hist_kernel, dim3(blocks), dim3(256), 0, stream, count, n, hist, bins);
+  return hipGetLastError();
+}
+
+hipError_t launch_group_map(const uint64_t *count, uint32_t n, const uint32_t *cgrp, uint32_t bins,
+                            uint32_t *group, hipStream_t stream) {
+  if (n == 0 || bins == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>((n + 255) / 256, 4096);
+  hipLaunchKernelGGL(group_map_kernel, dim3(blocks), dim3(256), 0, stream, count, n, cgrp, bins,
+                     group);
   return hipGetLastError();
 }
 

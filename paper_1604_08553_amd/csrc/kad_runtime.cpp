@@ -288,6 +288,36 @@ void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega,
   });
 }
 
+void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule,
+                        double eps, const uint64_t *count0, const std::vector<uint32_t> &cgrp,
+                        const std::vector<double> &gL_l, const std::vector<double> &gL_u,
+                        double *bc, double *lo, double *hi) {
+  const double T = (double)tau, W = (double)omega;
+  struct Memo {
+    uint64_t c;
+    uint32_t grp;
+    bool used;
+    double f, g;
+  };
+  parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+    std::vector<Memo> memo(rule ? 16384 : 0, Memo{0, 0, false, 0.0, 0.0});
+    for (uint32_t v = vb; v < ve; ++v) {
+      bc[v] = (double)cnt[v] / T;
+      if (rule) {
+        const uint32_t gv = cgrp[count0[v]];
+        Memo &m = memo[(uint32_t)((cnt[v] * 0x9E3779B97F4A7C15ULL ^ (uint64_t)gv * 0xC2B2AE3D27D4EB4FULL) >> 50)];
+        if (!(m.used && m.c == cnt[v] && m.grp == gv))
+          m = Memo{cnt[v], gv, true, bound_f(bc[v], gL_l[gv], W, T), bound_g(bc[v], gL_u[gv], W, T)};
+        lo[v] = bc[v] - m.f;
+        hi[v] = bc[v] + m.g;
+      } else {
+        lo[v] = bc[v] - eps;
+        hi[v] = bc[v] + eps;
+      }
+    }
+  });
+}
+
 void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
                  std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,
                  std::vector<uint32_t> &rhi_sel) {
@@ -879,8 +909,23 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
 
   // ---- pilot (phase 0): alpha samples -> count0
   std::vector<uint64_t> &count0 = ctx->h_count0;
-  count0.resize(n);
-  HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, stream));
+  // All-nodes runs have the same half-width at every node, so computeDelta needs only
+  // the histogram of the pilot counts (at most alpha + 1 bins): the counts stay on the
+  // device, and the node -> group map is built there too.
+  const bool pilot_hist = p->mode == KAD_ALL_NODES && alpha < (1u << 24);
+  const uint32_t bins = pilot_hist ? (uint32_t)alpha + 1 : 0u;
+  if (pilot_hist) {
+    HIP_TRY(ctx->count0d.ensure(n));
+    HIP_TRY(ctx->hist.ensure(bins));
+    HIP_TRY(ctx->cgrp.ensure(bins));
+    HIP_TRY(ctx->h_hist.ensure(bins));
+    HIP_TRY(ctx->h_cgrp.ensure(bins));
+    HIP_TRY(ctx->h_count0p.ensure(n));
+  } else {
+    count0.resize(n);
+  }
+  uint64_t *pcount = pilot_hist ? ctx->count0d.p : ctx->count.p;
+  HIP_TRY(hipMemsetAsync(pcount, 0, (size_t)n * 8, stream));
   uint64_t pilot_arcs = 0;
   uint32_t pilot_last = 0;
   for (uint64_t done = 0; done < alpha;) {
@@ -891,11 +936,19 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, alpha - done);
     if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream, ovc))) return st;
     HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
-                                   ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
+                                   pcount, false, nullptr, nullptr, hit_scratch(ctx), stream));
     pilot_last = nb;
     done += nb;
   }
-  HIP_TRY(hipMemcpyAsync(count0.data(), ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
+  if (pilot_hist) {
+    HIP_TRY(kad::launch_zero_u32(ctx->hist.p, bins, stream));
+    HIP_TRY(kad::launch_count_hist(ctx->count0d.p, n, ctx->hist.p, bins, stream));
+    HIP_TRY(hipMemcpyAsync(ctx->h_hist.p, ctx->hist.p, (size_t)bins * 4, hipMemcpyDeviceToHost,
+                           stream));
+  } else {
+    HIP_TRY(hipMemcpyAsync(count0.data(), ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost,
+                           stream));
+  }
   hipEvent_t pilot_done = nullptr;
   HIP_TRY(hipEventCreateWithFlags(&pilot_done, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(pilot_done, stream));
@@ -919,16 +972,29 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   // ---- computeDelta (host, binary64)
   std::vector<double> &lam_l = ctx->h_lam_l, &lam_u = ctx->h_lam_u, &L_l = ctx->h_L_l,
                       &L_u = ctx->h_L_u;
-  lam_l.assign(n, p->epsilon);
-  lam_u.assign(n, p->epsilon);
-  L_l.resize(n);
-  L_u.resize(n);
-  if (p->mode == KAD_TOPK) kad::topk_lambdas(n, p->k, count0.data(), alpha, p->epsilon, lam_l.data(), lam_u.data());
   double Cb = 0;
   kad::Groups groups;
-  kad::compute_delta(n, count0.data(), alpha, omega, lam_l.data(), lam_u.data(), p->delta, eb,
-                     L_l.data(), L_u.data(), &Cb, &groups);
-  kad::StopChecker checker(n, p->mode, p->k, p->epsilon, omega, L_l.data(), L_u.data(),
+  std::vector<uint32_t> cgrp_h;   // pilot_hist: pilot count -> group
+  std::vector<double> gLl, gLu;   // pilot_hist: group -> L values
+  if (pilot_hist) {
+    std::vector<uint64_t> h64(bins);
+    for (uint32_t c = 0; c < bins; ++c) h64[c] = ctx->h_hist.p[c];
+    kad::compute_delta_hist(n, h64.data(), bins - 1, alpha, omega, p->epsilon, p->epsilon,
+                            p->delta, eb, cgrp_h, groups, &Cb);
+    gLl = groups.L_l;
+    gLu = groups.L_u;
+  } else {
+    lam_l.assign(n, p->epsilon);
+    lam_u.assign(n, p->epsilon);
+    L_l.resize(n);
+    L_u.resize(n);
+    if (p->mode == KAD_TOPK) kad::topk_lambdas(n, p->k, count0.data(), alpha, p->epsilon, lam_l.data(), lam_u.data());
+    kad::compute_delta(n, count0.data(), alpha, omega, lam_l.data(), lam_u.data(), p->delta, eb,
+                       L_l.data(), L_u.data(), &Cb, &groups);
+  }
+  // (per-node L arrays are read only by the top-k check, never on the histogram path)
+  kad::StopChecker checker(n, p->mode, p->k, p->epsilon, omega,
+                           pilot_hist ? nullptr : L_l.data(), pilot_hist ? nullptr : L_u.data(),
                            std::move(groups));
 
   const auto t_delta = clock::now();
@@ -949,8 +1015,18 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   if (by_group) {
     HIP_TRY(ctx->group.ensure(n));
     HIP_TRY(ctx->gmax.ensure(ngroups));
-    HIP_TRY(hipMemcpyAsync(ctx->group.p, checker.group_of().data(), (size_t)n * 4,
-                           hipMemcpyHostToDevice, rs));
+    if (pilot_hist) {
+      memcpy(ctx->h_cgrp.p, cgrp_h.data(), (size_t)bins * 4);
+      HIP_TRY(hipMemcpyAsync(ctx->cgrp.p, ctx->h_cgrp.p, (size_t)bins * 4, hipMemcpyHostToDevice,
+                             rs));
+      HIP_TRY(kad::launch_group_map(ctx->count0d.p, n, ctx->cgrp.p, bins, ctx->group.p, rs));
+      // the pilot counts, for the intervals at the end (off the critical path)
+      HIP_TRY(hipMemcpyAsync(ctx->h_count0p.p, ctx->count0d.p, (size_t)n * 8,
+                             hipMemcpyDeviceToHost, rs));
+    } else {
+      HIP_TRY(hipMemcpyAsync(ctx->group.p, checker.group_of().data(), (size_t)n * 4,
+                             hipMemcpyHostToDevice, rs));
+    }
     HIP_TRY(hipMemsetAsync(ctx->gmax.p, 0, ngroups * 8, rs));
   }
   PinBuf<uint64_t> snaps;  // one snapshot per check of the current batch
@@ -988,9 +1064,12 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     uint32_t next_nb = 0;
     auto launch_next = [&]() -> kad_status {
       if (launched >= omega) return KAD_OK;
-      // remaining samples predicted from the last check: the bounds shrink about as 1/tau
+      // remaining samples predicted from the last check (the bounds shrink about as
+      // 1/tau), but at most half of what has been launched: a prediction made at an early
+      // check is coarse, and a later batch is sized from a later check
       double want = (double)K;
       if (by_group && worst > 0.0 && tau > 0) want = (double)tau * worst - (double)launched;
+      want = std::min(want, 0.5 * (double)launched);
       next_nb = (uint32_t)std::min<uint64_t>(round_up(want), omega - launched);
       const int nxt = 1 - cur;
       HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[nxt].reduced, 0));
@@ -1064,8 +1143,12 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   double *lo = r->lower && !topk ? r->lower : (los.resize(n), los.data());
   double *hi = r->upper && !topk ? r->upper : (his.resize(n), his.data());
   if (r->count) memcpy(r->count, cnt, (size_t)n * 8);
-  kad::node_outputs(n, cnt, tau, omega, rule, p->epsilon, L_l.data(), L_u.data(),
-                    checker.group_of(), bc, lo, hi);
+  if (pilot_hist)
+    kad::node_outputs_pilot(n, cnt, tau, omega, rule, p->epsilon, ctx->h_count0p.p, cgrp_h, gLl,
+                            gLu, bc, lo, hi);
+  else
+    kad::node_outputs(n, cnt, tau, omega, rule, p->epsilon, L_l.data(), L_u.data(),
+                      checker.group_of(), bc, lo, hi);
   if (topk) {
     if (r->lower) memcpy(r->lower, lo, (size_t)n * 8);
     if (r->upper) memcpy(r->upper, hi, (size_t)n * 8);

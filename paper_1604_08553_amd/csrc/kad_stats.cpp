@@ -271,19 +271,76 @@ class ValueIndex {
 };
 }  // namespace
 
+namespace {
+// The constants c = 2 b0 omega / lambda^2 of the nodes, as distinct values with
+// multiplicities, and the bisection for C over them: the smallest C with
+// sum_v exp(-C/c_L(v)) + exp(-C/c_U(v)) <= delta/2 - eps_bal*delta (the sum decreases in
+// C).  Lq[q] = L of distinct value q.
+struct DeltaSolver {
+  ValueIndex index{4096};
+  std::vector<double> mult;
+  uint32_t add_value(double x, double times) {
+    const uint32_t q = index.find_or_add(x);
+    if (mult.size() < index.values.size()) mult.resize(index.values.size(), 0.0);
+    mult[q] += times;
+    return q;
+  }
+  void solve(uint32_t n, double delta, double eps_bal, std::vector<double> &Lq, double *C_out) {
+    const size_t nd = index.values.size();
+    if (mult.size() < nd) mult.resize(nd, 0.0);
+    std::vector<uint32_t> ord(nd);
+    for (uint32_t q = 0; q < nd; ++q) ord[q] = q;
+    std::sort(ord.begin(), ord.end(),
+              [&](uint32_t a, uint32_t b) { return index.values[a] < index.values[b]; });
+    auto term = [](double C, double c) { return c == 0.0 ? 0.0 : exp(-C / c); };
+    auto total = [&](double C) {
+      double s = 0.0;
+      for (uint32_t q : ord) s += mult[q] * term(C, index.values[q]);
+      return s;
+    };
+    const double target = delta / 2.0 - eps_bal * delta;
+    double lo = 0.0, hi = 1.0;
+    while (total(hi) > target) hi *= 2.0;
+    for (int it = 0; it < 100; ++it) {
+      const double mid = (lo + hi) / 2.0;
+      if (total(mid) > target)
+        lo = mid;
+      else
+        hi = mid;
+    }
+    const double C = hi;
+    const double floor_add = eps_bal * delta / (2.0 * (double)n);
+    Lq.resize(nd);
+    for (size_t q = 0; q < nd; ++q) Lq[q] = -log(term(C, index.values[q]) + floor_add);
+    if (C_out) *C_out = C;
+  }
+};
+
+// Uniform half-widths: the constants of the nodes with pilot count c, for every count
+// present (h[c] > 0) in ascending order; group = rank of the count among those present.
+void uniform_values(DeltaSolver &S, const uint64_t *h, uint64_t cmax, uint64_t alpha,
+                    uint64_t omega, double lam_l, double lam_u, std::vector<uint32_t> &ca,
+                    std::vector<uint32_t> &cb, std::vector<uint32_t> &cgrp, uint32_t &ngrp) {
+  ca.assign(cmax + 1, 0);
+  cb.assign(cmax + 1, 0);
+  cgrp.assign(cmax + 1, 0);
+  ngrp = 0;
+  for (uint64_t c = 0; c <= cmax; ++c) {
+    if (!h[c]) continue;
+    const double b0 = (double)c / (double)alpha;
+    ca[c] = S.add_value(2.0 * b0 * (double)omega / (lam_l * lam_l), (double)h[c]);
+    cb[c] = S.add_value(2.0 * b0 * (double)omega / (lam_u * lam_u), (double)h[c]);
+    cgrp[c] = ngrp++;
+  }
+}
+}  // namespace
+
 void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
                    const double *lam_l, const double *lam_u, double delta, double eps_bal,
                    double *L_l, double *L_u, double *C_out, Groups *groups) {
   // The 2n constants c_L(v) = 2 b0(v) omega / lambda_L(v)^2 (and c_U) are handled as
   // indices into their distinct values with multiplicities.
-  ValueIndex index(4096);
-  std::vector<double> mult;
-  auto add_value = [&](double x, double times) {
-    const uint32_t q = index.find_or_add(x);
-    if (mult.size() < index.values.size()) mult.resize(index.values.size(), 0.0);
-    mult[q] += times;
-    return q;
-  };
+  DeltaSolver S;
   // Uniform half-widths (the all-nodes task): a node's constants depend on its pilot
   // count only, so they are computed once per distinct count.
   const unsigned nt = parallel_threads(n);
@@ -308,19 +365,11 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
     parallel_ranges(n, [&](uint32_t b0, uint32_t e0, unsigned w) {
       for (uint32_t v = b0; v < e0; ++v) th[w][count0[v]]++;
     });
-    ca.assign(cmax + 1, 0);
-    cb.assign(cmax + 1, 0);
-    cgrp.assign(cmax + 1, 0);
+    std::vector<uint64_t> h(cmax + 1, 0);
+    for (uint64_t c = 0; c <= cmax; ++c)
+      for (unsigned w = 0; w < nt; ++w) h[c] += th[w][c];
     uint32_t ngrp = 0;
-    for (uint64_t c = 0; c <= cmax; ++c) {
-      uint64_t h = 0;
-      for (unsigned w = 0; w < nt; ++w) h += th[w][c];
-      if (!h) continue;
-      const double b0 = (double)c / (double)alpha;
-      ca[c] = add_value(2.0 * b0 * (double)omega / (lam_l[0] * lam_l[0]), (double)h);
-      cb[c] = add_value(2.0 * b0 * (double)omega / (lam_u[0] * lam_u[0]), (double)h);
-      cgrp[c] = ngrp++;
-    }
+    uniform_values(S, h.data(), cmax, alpha, omega, lam_l[0], lam_u[0], ca, cb, cgrp, ngrp);
     if (groups) {
       groups->L_l.assign(ngrp, 0.0);
       groups->L_u.assign(ngrp, 0.0);
@@ -347,13 +396,13 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
         const double b0 = (double)count0[v] / (double)alpha;
         const double cl = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
         const double cu = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
-        m = Memo{count0[v], bl, bu, index.find_or_add(cl), index.find_or_add(cu), true};
-        if (mult.size() < index.values.size()) mult.resize(index.values.size(), 0.0);
+        m = Memo{count0[v], bl, bu, S.index.find_or_add(cl), S.index.find_or_add(cu), true};
+        if (S.mult.size() < S.index.values.size()) S.mult.resize(S.index.values.size(), 0.0);
       }
       il[v] = m.a;
       iu[v] = m.b;
-      mult[m.a] += 1.0;
-      mult[m.b] += 1.0;
+      S.mult[m.a] += 1.0;
+      S.mult[m.b] += 1.0;
     }
     if (groups) {  // group = distinct (il, iu) pair
       std::map<std::pair<uint32_t, uint32_t>, uint32_t> ids;
@@ -366,33 +415,8 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
       groups->L_u.assign(ids.size(), 0.0);
     }
   }
-  // distinct constants with multiplicities, ascending
-  const size_t nd = index.values.size();
-  std::vector<uint32_t> ord(nd);
-  for (uint32_t q = 0; q < nd; ++q) ord[q] = q;
-  std::sort(ord.begin(), ord.end(),
-            [&](uint32_t a, uint32_t b) { return index.values[a] < index.values[b]; });
-  auto term = [](double C, double c) { return c == 0.0 ? 0.0 : exp(-C / c); };
-  auto total = [&](double C) {
-    double s = 0.0;
-    for (uint32_t q : ord) s += mult[q] * term(C, index.values[q]);
-    return s;
-  };
-  // smallest C with total(C) <= delta/2 - eps*delta (the sum decreases in C)
-  const double target = delta / 2.0 - eps_bal * delta;
-  double lo = 0.0, hi = 1.0;
-  while (total(hi) > target) hi *= 2.0;
-  for (int it = 0; it < 100; ++it) {
-    const double mid = (lo + hi) / 2.0;
-    if (total(mid) > target)
-      lo = mid;
-    else
-      hi = mid;
-  }
-  const double C = hi;
-  const double floor_add = eps_bal * delta / (2.0 * (double)n);
-  std::vector<double> Lq(nd);
-  for (size_t q = 0; q < nd; ++q) Lq[q] = -log(term(C, index.values[q]) + floor_add);
+  std::vector<double> Lq;
+  S.solve(n, delta, eps_bal, Lq, C_out);
   if (!ca.empty()) {
     if (groups) {
       groups->of.resize(n);
@@ -420,7 +444,25 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
         groups->L_u[groups->of[v]] = L_u[v];
       }
   }
-  if (C_out) *C_out = C;
+}
+
+void compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cmax, uint64_t alpha,
+                        uint64_t omega, double lam_l, double lam_u, double delta, double eps_bal,
+                        std::vector<uint32_t> &cgrp, Groups &groups, double *C_out) {
+  DeltaSolver S;
+  std::vector<uint32_t> ca, cb;
+  uint32_t ngrp = 0;
+  uniform_values(S, hist, cmax, alpha, omega, lam_l, lam_u, ca, cb, cgrp, ngrp);
+  std::vector<double> Lq;
+  S.solve(n, delta, eps_bal, Lq, C_out);
+  groups.of.clear();
+  groups.L_l.assign(ngrp, 0.0);
+  groups.L_u.assign(ngrp, 0.0);
+  for (uint64_t c = 0; c <= cmax; ++c) {
+    if (!hist[c]) continue;
+    groups.L_l[cgrp[c]] = Lq[ca[c]];
+    groups.L_u[cgrp[c]] = Lq[cb[c]];
+  }
 }
 
 // ------------------------------------------------------------------ top-k half-widths

@@ -38,6 +38,14 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
                    const double *lam_l, const double *lam_u, double delta, double eps_bal,
                    double *L_l, double *L_u, double *C, Groups *groups = nullptr);
 
+// computeDelta for half-widths equal at every node, from the histogram of the pilot
+// counts (hist[c] nodes have count c, c <= cmax): the arithmetic of compute_delta's
+// uniform case, in its order.  Group g is the g-th count present in ascending order:
+// cgrp[c] for every c with hist[c] > 0; groups.L_l/L_u per group; groups.of left empty.
+void compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cmax, uint64_t alpha,
+                        uint64_t omega, double lam_l, double lam_u, double delta, double eps_bal,
+                        std::vector<uint32_t> &cgrp, Groups &groups, double *C);
+
 void topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha, double eps,
                   double *lam_l, double *lam_u);
 
