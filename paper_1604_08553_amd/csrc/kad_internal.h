@@ -129,6 +129,7 @@ struct kad_ctx {
   kad::OutSet outs[2];
   kad::DevBuf<uint32_t> work, group;
   kad::DevBuf<uint64_t> count, gmax;
+  hipEvent_t ev_s = nullptr, ev_rs = nullptr;  // wait_stream's markers
   kad::DevBuf<uint64_t> count0d;         // pilot counts (all-nodes runs)
   kad::DevBuf<uint32_t> hist, cgrp;      // their histogram; count -> stopping group
   kad::PinBuf<uint32_t> h_hist, h_cgrp;

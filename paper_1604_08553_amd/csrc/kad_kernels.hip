@@ -566,18 +566,18 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
         }
       }
     }
-    // classes: 0 none, 1 short, 2 long
+    // classes: 0 none, 1 short, 2 long (an endpoint's row, alone, always takes the
+    // piece walk: it needs no window bookkeeping)
     uint32_t cls[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) cls[q] = d[q] == 0 ? 0u : (d[q] < WIN ? 1u : 2u);
+    for (int q = 0; q < 2; ++q) cls[q] = d[q] == 0 ? 0u : (d[q] < WIN && !first ? 1u : 2u);
     const uint32_t sarcs = (cls[0] == 1 ? d[0] : 0u) + (cls[1] == 1 ? d[1] : 0u);
     const uint32_t cnts = (cls[0] == 1 ? 1u : 0u) + (cls[1] == 1 ? 1u : 0u) +
                           ((cls[0] == 2 ? 1u : 0u) + (cls[1] == 2 ? 1u : 0u)) * 65536u;
     uint32_t ex = 0, cx = 0, tot, ncx;
-    if (first) {  // one row, held by thread 0: the scan's results are known
-      const uint32_t dd = (uint32_t)L.deg[me];
-      tot = dd < WIN ? dd : 0u;
-      ncx = dd == 0 ? 0u : (dd < WIN ? 1u : 65536u);
+    if (first) {  // one long row, held by thread 0: the scan's results are known
+      tot = 0;
+      ncx = L.deg[me] == 0 ? 0u : 65536u;
     } else {
       block_excl2_u32(L, sarcs, cnts, ex, cx, tot, ncx);
     }

@@ -481,11 +481,36 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
   return KAD_OK;
 }
 
+// Wait for an event by polling: a run waits on many short GPU steps, and a blocking
+// wait was seen to wake several hundred microseconds late.  After 2 ms of polling the
+// wait blocks.
+hipError_t wait_event(hipEvent_t ev) {
+  const auto t0 = std::chrono::steady_clock::now();
+  for (;;) {
+    const hipError_t e = hipEventQuery(ev);
+    if (e != hipErrorNotReady) return e;
+    if (std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2))
+      return hipEventSynchronize(ev);
+  }
+}
+
+// A stream's work so far, waited for with wait_event.
+hipError_t wait_stream(kad_ctx *ctx, hipStream_t s) {
+  hipEvent_t &ev = s == ctx->rstream ? ctx->ev_rs : ctx->ev_s;
+  if (!ev) {
+    const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e != hipSuccess) return e;
+  }
+  const hipError_t e = hipEventRecord(ev, s);
+  if (e != hipSuccess) return e;
+  return wait_event(ev);
+}
+
 // Wait for a batch's mirrors, account its launch time, and reject flagged samples
 // among the first `used` samples (samples past a stopping point do not matter).
 kad_status finish_batch(kad_ctx *ctx, int set, uint32_t count, uint32_t used) {
   OutSet &o = ctx->outs[set];
-  HIP_TRY(hipEventSynchronize(o.copied));
+  HIP_TRY(wait_event(o.copied));
   ctx->run_wide += o.h_nwide.p[0];
   if (ctx->timing) {
     float ms = 0.f;
@@ -545,6 +570,8 @@ kad_status kad_ctx_destroy(kad_ctx *ctx) {
   (void)hipSetDevice(ctx->device);
   kad::destroy_engine(ctx->engine);  // waits for its work on the context's streams
   ctx->engine = nullptr;
+  if (ctx->ev_s) (void)hipEventDestroy(ctx->ev_s);
+  if (ctx->ev_rs) (void)hipEventDestroy(ctx->ev_rs);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   if (ctx->rstream) (void)hipStreamDestroy(ctx->rstream);
   delete ctx;
@@ -963,7 +990,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     (void)hipEventDestroy(pilot_done);
     return st;
   }
-  HIP_TRY(hipEventSynchronize(pilot_done));
+  HIP_TRY(wait_event(pilot_done));
   (void)hipEventDestroy(pilot_done);
   if ((st = finish_batch(ctx, 0, pilot_last, pilot_last))) return st;
   for (uint32_t k = 0; k < pilot_last; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
@@ -1050,17 +1077,26 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     if (cur_nb == 0) return fail(KAD_EINVAL, "internal: empty batch before the stopping point");
     const OutSet &o = ctx->outs[cur];
     HIP_TRY(hipStreamWaitEvent(rs, o.copied, 0));
-    uint32_t nchunks = 0;
-    for (uint32_t c0 = 0; c0 < cur_nb; c0 += (uint32_t)B, ++nchunks) {
-      const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - c0);
-      HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)c0 * stride, o.len.p + c0, stride, cb, n,
-                                     ctx->count.p, false, by_group ? ctx->group.p : nullptr,
-                                     by_group ? ctx->gmax.p : nullptr, hit_scratch(ctx), rs));
-      HIP_TRY(hipMemcpyAsync(snaps.p + (size_t)nchunks * snap, by_group ? ctx->gmax.p : ctx->count.p,
-                             snap * 8, hipMemcpyDeviceToHost, rs));
-      HIP_TRY(hipEventRecord(ctx->chunk_ev[nchunks], rs));
-    }
-    HIP_TRY(hipEventRecord(ctx->outs[cur].reduced, rs));
+    const uint32_t nch = (uint32_t)((cur_nb + B - 1) / B);
+    uint32_t queued = 0;  // check intervals whose reduction and snapshot are enqueued
+    auto enqueue_upto = [&](uint32_t upto) -> kad_status {
+      for (; queued < upto; ++queued) {
+        const uint32_t q0 = queued * (uint32_t)B;
+        const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - q0);
+        HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)q0 * stride, o.len.p + q0, stride, cb, n,
+                                       ctx->count.p, false, by_group ? ctx->group.p : nullptr,
+                                       by_group ? ctx->gmax.p : nullptr, hit_scratch(ctx), rs));
+        HIP_TRY(hipMemcpyAsync(snaps.p + (size_t)queued * snap,
+                               by_group ? ctx->gmax.p : ctx->count.p, snap * 8,
+                               hipMemcpyDeviceToHost, rs));
+        HIP_TRY(hipEventRecord(ctx->chunk_ev[queued], rs));
+        if (queued + 1 == nch) HIP_TRY(hipEventRecord(ctx->outs[cur].reduced, rs));
+      }
+      return KAD_OK;
+    };
+    // The first check sizes the next batch, which is launched before the batch's other
+    // reductions are enqueued: enqueueing them keeps the host busy for a while.
+    if ((st = enqueue_upto(1))) return st;
     uint32_t next_nb = 0;
     auto launch_next = [&]() -> kad_status {
       if (launched >= omega) return KAD_OK;
@@ -1082,7 +1118,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     uint32_t c = 0, c0 = 0;
     for (; c0 < cur_nb; ++c, c0 += (uint32_t)B) {
       const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - c0);
-      HIP_TRY(hipEventSynchronize(ctx->chunk_ev[c]));
+      HIP_TRY(wait_event(ctx->chunk_ev[c]));
       tau += cb;
       const uint64_t *sp = snaps.p + (size_t)c * snap;
       if (tau >= omega) {
@@ -1097,15 +1133,18 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
         if ((st = launch_next())) return st;
         next_done = true;
       }
+      if ((st = enqueue_upto(nch))) return st;
     }
     const uint32_t used = stop ? c0 + (uint32_t)std::min<uint64_t>(B, cur_nb - c0) : cur_nb;
     if ((st = finish_batch(ctx, cur, cur_nb, used))) return st;
     for (uint32_t k = 0; k < used; ++k) arcs += ctx->outs[cur].h_arcs.p[k];
     if (stop) {
-      // undo the reductions of the check intervals past the stopping point
-      if (used < cur_nb)
+      // undo the reductions enqueued past the stopping point
+      const uint32_t reduced_end = (uint32_t)std::min<uint64_t>((uint64_t)queued * B, cur_nb);
+      if (used < reduced_end)
         HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)used * stride, o.len.p + used, stride,
-                                       cur_nb - used, n, ctx->count.p, true, nullptr, nullptr, hit_scratch(ctx), rs));
+                                       reduced_end - used, n, ctx->count.p, true, nullptr, nullptr,
+                                       hit_scratch(ctx), rs));
       if (next_done && next_nb) {
         if ((st = finish_batch(ctx, 1 - cur, next_nb, 0))) return st;  // drain (timing only)
       }
@@ -1118,8 +1157,8 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     cur_nb = next_nb;
   }
   HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, rs));
-  HIP_TRY(hipStreamSynchronize(rs));
-  HIP_TRY(hipStreamSynchronize(stream));
+  HIP_TRY(wait_stream(ctx, rs));
+  HIP_TRY(wait_stream(ctx, stream));
   const auto t_main = clock::now();
 
   // ---- outputs (Theorem 1 intervals)
@@ -1142,7 +1181,10 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   double *bc = r->bc ? r->bc : (bcs.resize(n), bcs.data());
   double *lo = r->lower && !topk ? r->lower : (los.resize(n), los.data());
   double *hi = r->upper && !topk ? r->upper : (his.resize(n), his.data());
-  if (r->count) memcpy(r->count, cnt, (size_t)n * 8);
+  if (r->count)
+    kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+      memcpy(r->count + vb, cnt + vb, (size_t)(ve - vb) * 8);
+    });
   if (pilot_hist)
     kad::node_outputs_pilot(n, cnt, tau, omega, rule, p->epsilon, ctx->h_count0p.p, cgrp_h, gLl,
                             gLu, bc, lo, hi);
