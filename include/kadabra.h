@@ -304,8 +304,10 @@ kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *
  * per launch. */
 kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable);
 /* Totals over the timed sampler launches since timing was enabled: launches, samples,
- * seconds (sum of the event-measured launch durations), arcs scanned, nodes reached by
- * the two searches, and hits (interior path nodes).  Any pointer may be NULL. */
+ * seconds (the time the launches kept the GPU busy: the sum of the event-measured launch
+ * durations, except that within one kad_run, whose first main batch may run beside the
+ * pilot, the union of the launches' intervals), arcs scanned, nodes reached by the two
+ * searches, and hits (interior path nodes).  Any pointer may be NULL. */
 kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *samples,
                               double *seconds, uint64_t *arcs, uint64_t *nodes, uint64_t *hits);
 

@@ -107,6 +107,7 @@ void destroy_engine(Engine *e);
 struct kad_ctx {
   int device = 0;
   hipStream_t stream = nullptr;   // sampling (unless the caller gives one)
+  hipStream_t pstream = nullptr;  // a run's first main batch, beside its pilot
   hipStream_t rstream = nullptr;  // hit reductions and check snapshots
   uint64_t budget = 0;
   uint64_t used_graphs = 0;
@@ -127,9 +128,9 @@ struct kad_ctx {
   // per-launch outputs, double-buffered so the next batch can be sampled while the
   // host checks the current one
   kad::OutSet outs[2];
-  kad::DevBuf<uint32_t> work, group;
+  kad::DevBuf<uint32_t> work, work2, group;  // work2: the work counter of pstream launches
   kad::DevBuf<uint64_t> count, gmax;
-  hipEvent_t ev_s = nullptr, ev_rs = nullptr;  // wait_stream's markers
+  hipEvent_t ev_s = nullptr, ev_rs = nullptr, ev_ps = nullptr;  // wait_stream's markers
   kad::DevBuf<uint64_t> count0d;         // pilot counts (all-nodes runs)
   kad::DevBuf<uint32_t> hist, cgrp;      // their histogram; count -> stopping group
   kad::PinBuf<uint32_t> h_hist, h_cgrp;
@@ -148,6 +149,9 @@ struct kad_ctx {
   bool timing = false;
   uint64_t t_launches = 0, t_samples = 0, t_arcs = 0, t_nodes = 0, t_hits = 0, t_wide = 0;
   double t_seconds = 0.0;
+  hipEvent_t t_ref = nullptr;                      // a run's timing reference
+  bool t_run_ref = false;                          // t_ref holds the running kad_run's
+  std::vector<std::pair<float, float>> t_iv;       // its launches' intervals (ms from t_ref)
   // the multi-query engine (kad_run_batch, kad_server_*), created on first use
   kad::Engine *engine = nullptr;
   ~kad_ctx() {
@@ -204,7 +208,7 @@ GraphDev dev_view(const kad_graph *g);
 kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact);
 // Slot state for graphs of up to n nodes (reallocates, and synchronises, when it grows).
 kad_status ensure_slots(kad_ctx *ctx, uint32_t n);
-SlotState slot_view(const kad_ctx *ctx);
+SlotState slot_view(const kad_ctx *ctx, uint32_t slot0 = 0);
 WideState wide_view(const kad_ctx *ctx);
 // Wide path counts: 0 = a graph whose path counts always fit 128 bits (VD and the
 // largest degree bound them), 1 = overflowed samples are resampled wide, 2 = a
@@ -218,11 +222,13 @@ kad_status ensure_wide(kad_ctx *ctx);
 // before), and queue the copy of the number of resampled samples into *h_nwide.
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
-                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream);
+                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream,
+                       uint32_t slot0 = 0);
 // The graph's launch shape (set or tuned, else a default by size), and the grid of a
 // launch of `count` samples with it.
 LaunchShape graph_shape(const kad_graph *g);
-uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t count);
+uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t count,
+                     uint32_t slot0 = 0);
 
 // Per-node outputs of a finished run (Theorem 1 intervals and the top-k ranking).
 // bc, lo, hi: length n.  With rule_stop the interval is [bc - f, bc + g], else

@@ -206,7 +206,8 @@ WideState wide_view(const kad_ctx *ctx) {
 
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
-                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream) {
+                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream,
+                       uint32_t slot0) {
   if (count == 0) {
     *h_nwide = 0;
     return KAD_OK;
@@ -218,8 +219,11 @@ kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t 
     ctx->w_list.release();
     HIP_TRY(ctx->w_list.ensure(std::max<size_t>(count, 1u << 18)));
   }
-  HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, slot_view(ctx), wide_view(ctx),
-                          count, all, ctx->w_list.p, ctx->w_cnt.p, ctx->w_cnt.p + 1, out, stream));
+  const SlotState sv = slot_view(ctx, slot0);
+  WideState wv = wide_view(ctx);
+  wv.slots = std::min(wv.slots, sv.slots);  // the wide slots reuse these sampler slots
+  HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, sv, wv, count, all, ctx->w_list.p,
+                          ctx->w_cnt.p, ctx->w_cnt.p + 1, out, stream));
   HIP_TRY(hipMemcpyAsync(h_nwide, ctx->w_cnt.p, 4, hipMemcpyDeviceToHost, stream));
   return KAD_OK;
 }
@@ -229,23 +233,25 @@ LaunchShape graph_shape(const kad_graph *g) {
   return LaunchShape{};
 }
 
-uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t count) {
+uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t count, uint32_t slot0) {
   int per_cu = 1;
   for (int j = 0; j < 3; ++j)
     if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx->blocks_per_cu[j];
   const uint64_t resident = (uint64_t)ctx->cus * (uint64_t)per_cu;
-  return (uint32_t)std::min<uint64_t>(std::min<uint64_t>(ctx->slots, resident), count);
+  const uint64_t slots = ctx->slots > slot0 ? ctx->slots - slot0 : 0;
+  return (uint32_t)std::min<uint64_t>(std::min<uint64_t>(slots, resident), count);
 }
 
-SlotState slot_view(const kad_ctx *ctx) {
+SlotState slot_view(const kad_ctx *ctx, uint32_t slot0) {
   SlotState st;
-  st.slots = ctx->slots;
+  const size_t n = ctx->slot_n;
+  st.slots = ctx->slots > slot0 ? ctx->slots - slot0 : 0;
   st.n = ctx->slot_n;
   st.pi_cap = PI_CAP;
-  st.tag = ctx->tag.p;
-  st.sig = ctx->sig.p;
-  st.visit = ctx->visit.p;
-  st.pi = ctx->pi.p;
+  st.tag = ctx->tag.p + (size_t)slot0 * n;
+  st.sig = ctx->sig.p + (size_t)slot0 * n * 2;
+  st.visit = ctx->visit.p + (size_t)slot0 * n;
+  st.pi = ctx->pi.p + (size_t)slot0 * PI_CAP;
   return st;
 }
 
@@ -400,6 +406,7 @@ kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t st
   for (OutSet &o : ctx->outs)
     if ((st = o.ensure(batch, stride, ctx->rstream))) return st;
   HIP_TRY(ctx->work.ensure(1));
+  HIP_TRY(ctx->work2.ensure(1));
   HIP_TRY(ctx->count.ensure(n));
   HIP_TRY(ctx->h_count.ensure(n));
   // hit-reduction bins: room in every tile for all the hits of one reduction call
@@ -445,27 +452,34 @@ kad::HitScratch hit_scratch(kad_ctx *ctx) {
 // mirrors; nothing waits.
 // ovc: the graph's overflow class (kad::overflow_class): 0 = 128-bit counts always
 // suffice, 1 = resample overflowed samples wide, 2 = sample everything wide.
+// slot0, work: the launch's sampler slots start at slot0 and its work counter is *work
+// (ctx->work when null), so that two launches on different streams may overlap.
+// wide_after: the wide-count fix (which shares one arena across launches) waits for it.
 kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                         uint64_t first, uint32_t count, uint32_t stride, int set,
-                        hipStream_t stream, int ovc) {
+                        hipStream_t stream, int ovc, uint32_t slot0 = 0, uint32_t *work = nullptr,
+                        hipEvent_t wide_after = nullptr) {
   OutSet &o = ctx->outs[set];
   kad_status st = KAD_OK;
+  uint32_t *wk = work ? work : ctx->work.p;
   HIP_TRY(hipEventRecord(o.k0, stream));
   if (ovc == 2) {
+    if (wide_after) HIP_TRY(hipStreamWaitEvent(stream, wide_after, 0));
     st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, true,
-                          o.view(stride), o.h_nwide.p, stream);
+                          o.view(stride), o.h_nwide.p, stream, slot0);
     if (st) return st;
     HIP_TRY(hipEventRecord(o.k1, stream));
   } else {
-    HIP_TRY(kad::launch_zero_u32(ctx->work.p, 1, stream));
+    HIP_TRY(kad::launch_zero_u32(wk, 1, stream));
     const kad::LaunchShape shape = kad::graph_shape(g);
-    const uint32_t grid = kad::launch_grid(ctx, shape, count);
-    HIP_TRY(kad::launch_sampler(dev_view(g), kad::slot_view(ctx), seed, phase, first, count,
-                                ctx->work.p, o.view(stride), grid, shape, stream));
+    const uint32_t grid = kad::launch_grid(ctx, shape, count, slot0);
+    HIP_TRY(kad::launch_sampler(dev_view(g), kad::slot_view(ctx, slot0), seed, phase, first,
+                                count, wk, o.view(stride), grid, shape, stream));
     HIP_TRY(hipEventRecord(o.k1, stream));
     if (ovc == 1) {
+      if (wide_after) HIP_TRY(hipStreamWaitEvent(stream, wide_after, 0));
       st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, false,
-                            o.view(stride), o.h_nwide.p, stream);
+                            o.view(stride), o.h_nwide.p, stream, slot0);
       if (st) return st;
     } else {
       o.h_nwide.p[0] = 0;
@@ -496,7 +510,7 @@ hipError_t wait_event(hipEvent_t ev) {
 
 // A stream's work so far, waited for with wait_event.
 hipError_t wait_stream(kad_ctx *ctx, hipStream_t s) {
-  hipEvent_t &ev = s == ctx->rstream ? ctx->ev_rs : ctx->ev_s;
+  hipEvent_t &ev = s == ctx->rstream ? ctx->ev_rs : (s == ctx->pstream ? ctx->ev_ps : ctx->ev_s);
   if (!ev) {
     const hipError_t e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
     if (e != hipSuccess) return e;
@@ -506,6 +520,38 @@ hipError_t wait_stream(kad_ctx *ctx, hipStream_t s) {
   return wait_event(ev);
 }
 
+// Timing within kad_run: the first main batch may run beside the pilot, so the run's
+// sampler time is the union of its launches' event intervals (measured from a reference
+// event recorded when the run starts), not their sum.
+kad_status run_timing_begin(kad_ctx *ctx, hipStream_t s) {
+  ctx->t_run_ref = false;
+  if (!ctx->timing) return KAD_OK;
+  if (!ctx->t_ref) HIP_TRY(hipEventCreate(&ctx->t_ref));
+  HIP_TRY(hipEventRecord(ctx->t_ref, s));
+  ctx->t_iv.clear();
+  ctx->t_run_ref = true;
+  return KAD_OK;
+}
+void run_timing_end(kad_ctx *ctx) {
+  if (!ctx->t_run_ref) return;
+  auto &iv = ctx->t_iv;
+  std::sort(iv.begin(), iv.end());
+  double busy = 0.0, lo = 0.0, hi = -1.0;
+  for (const auto &x : iv) {
+    if (x.first > hi) {
+      if (hi > lo) busy += hi - lo;
+      lo = x.first;
+      hi = x.second;
+    } else {
+      hi = std::max(hi, (double)x.second);
+    }
+  }
+  if (hi > lo) busy += hi - lo;
+  ctx->t_seconds += busy * 1e-3;
+  iv.clear();
+  ctx->t_run_ref = false;
+}
+
 // Wait for a batch's mirrors, account its launch time, and reject flagged samples
 // among the first `used` samples (samples past a stopping point do not matter).
 kad_status finish_batch(kad_ctx *ctx, int set, uint32_t count, uint32_t used) {
@@ -513,11 +559,18 @@ kad_status finish_batch(kad_ctx *ctx, int set, uint32_t count, uint32_t used) {
   HIP_TRY(wait_event(o.copied));
   ctx->run_wide += o.h_nwide.p[0];
   if (ctx->timing) {
-    float ms = 0.f;
-    HIP_TRY(hipEventElapsedTime(&ms, o.k0, o.k1));
+    if (ctx->t_run_ref) {  // a kad_run in progress: its launches may overlap; see run_busy
+      float a = 0.f, b = 0.f;
+      HIP_TRY(hipEventElapsedTime(&a, ctx->t_ref, o.k0));
+      HIP_TRY(hipEventElapsedTime(&b, ctx->t_ref, o.k1));
+      ctx->t_iv.emplace_back(a, b);
+    } else {
+      float ms = 0.f;
+      HIP_TRY(hipEventElapsedTime(&ms, o.k0, o.k1));
+      ctx->t_seconds += ms * 1e-3;
+    }
     ctx->t_launches += 1;
     ctx->t_samples += count;
-    ctx->t_seconds += ms * 1e-3;
     ctx->t_wide += o.h_nwide.p[0];
     for (uint32_t k = 0; k < count; ++k) {
       ctx->t_arcs += o.h_arcs.p[k];
@@ -554,6 +607,7 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
   HIP_TRY(hipSetDevice(hip_device));
   HIP_TRY(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
   HIP_TRY(hipStreamCreateWithFlags(&c->rstream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamCreateWithFlags(&c->pstream, hipStreamNonBlocking));
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   c->cus = (uint32_t)prop.multiProcessorCount;
@@ -572,8 +626,11 @@ kad_status kad_ctx_destroy(kad_ctx *ctx) {
   ctx->engine = nullptr;
   if (ctx->ev_s) (void)hipEventDestroy(ctx->ev_s);
   if (ctx->ev_rs) (void)hipEventDestroy(ctx->ev_rs);
+  if (ctx->ev_ps) (void)hipEventDestroy(ctx->ev_ps);
+  if (ctx->t_ref) (void)hipEventDestroy(ctx->t_ref);
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   if (ctx->rstream) (void)hipStreamDestroy(ctx->rstream);
+  if (ctx->pstream) (void)hipStreamDestroy(ctx->pstream);
   delete ctx;
   return KAD_OK;
 }
@@ -867,6 +924,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   const int ovc = kad::overflow_class(g, vd, p->vd_override == 0);
   if ((st = ensure_capacity(ctx, n, (uint32_t)K, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
+  if ((st = run_timing_begin(ctx, stream))) return st;
+  struct RunTimingEnd {  // also on early returns
+    kad_ctx *c;
+    ~RunTimingEnd() { run_timing_end(c); }
+  } run_timing_guard{ctx};
   const auto t_setup = clock::now();
 
   if (p->schedule != KAD_SCHEDULE_ADAPTIVE) {
@@ -885,6 +947,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     }
     HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, stream));
     HIP_TRY(hipStreamSynchronize(stream));
+    run_timing_end(ctx);
     const auto t_main_f = clock::now();
     r->tau = tau_fixed;
     r->omega = tau_fixed;
@@ -953,6 +1016,19 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   }
   uint64_t *pcount = pilot_hist ? ctx->count0d.p : ctx->count.p;
   HIP_TRY(hipMemsetAsync(pcount, 0, (size_t)n * 8, stream));
+  // The first main-phase batch (phase 1 does not depend on the pilot): half the cap, in
+  // whole check intervals.  When the slots allow it, it runs beside the pilot on its own
+  // stream, slots and work counter (a pilot of alpha samples is one short launch whose
+  // last samples would otherwise hold the GPU); its wide-count fix, which shares one
+  // arena, waits for the pilot's.
+  const int first_set = 1;
+  const uint32_t first_nb = (uint32_t)std::min<uint64_t>(
+      omega, std::min<uint64_t>(K, std::max<uint64_t>(B, (omega / 2 + B - 1) / B * B)));
+  const uint32_t b1_slot0 = (uint32_t)std::max<uint64_t>(alpha, 64);
+  const bool overlap = hip_stream == nullptr && ovc != 2 && alpha <= ctx->outs[0].cap &&
+                       (uint64_t)ctx->slots >= (uint64_t)b1_slot0 + kad::launch_grid(
+                                                   ctx, kad::graph_shape(g), first_nb);
+  hipStream_t b1_stream = overlap ? ctx->pstream : stream;
   uint64_t pilot_arcs = 0;
   uint32_t pilot_last = 0;
   for (uint64_t done = 0; done < alpha;) {
@@ -962,6 +1038,12 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     }
     const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, alpha - done);
     if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream, ovc))) return st;
+    if (overlap) {
+      HIP_TRY(hipStreamWaitEvent(b1_stream, ctx->outs[first_set].reduced, 0));
+      if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, b1_stream, ovc,
+                             b1_slot0, ctx->work2.p, ctx->outs[0].copied)))
+        return st;
+    }
     HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
                                    pcount, false, nullptr, nullptr, hit_scratch(ctx), stream));
     pilot_last = nb;
@@ -980,15 +1062,14 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   HIP_TRY(hipEventCreateWithFlags(&pilot_done, hipEventDisableTiming));
   HIP_TRY(hipEventRecord(pilot_done, stream));
 
-  // ---- the first main-phase batch (phase 1 does not depend on the pilot) is sampled
-  // while the host runs computeDelta; half the cap, in whole check intervals
-  const int first_set = 1;
-  const uint32_t first_nb = (uint32_t)std::min<uint64_t>(
-      omega, std::min<uint64_t>(K, std::max<uint64_t>(B, (omega / 2 + B - 1) / B * B)));
-  HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[first_set].reduced, 0));
-  if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream, ovc))) {
-    (void)hipEventDestroy(pilot_done);
-    return st;
+  // ---- otherwise the first main-phase batch follows the pilot on the stream and is
+  // sampled while the host runs computeDelta
+  if (!overlap) {
+    HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[first_set].reduced, 0));
+    if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream, ovc))) {
+      (void)hipEventDestroy(pilot_done);
+      return st;
+    }
   }
   HIP_TRY(wait_event(pilot_done));
   (void)hipEventDestroy(pilot_done);
@@ -1159,6 +1240,8 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, rs));
   HIP_TRY(wait_stream(ctx, rs));
   HIP_TRY(wait_stream(ctx, stream));
+  if (overlap) HIP_TRY(wait_stream(ctx, b1_stream));
+  run_timing_end(ctx);
   const auto t_main = clock::now();
 
   // ---- outputs (Theorem 1 intervals)

@@ -10,7 +10,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <condition_variable>
 #include <map>
+#include <mutex>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -22,18 +24,83 @@ unsigned parallel_threads(uint32_t n) {
   return std::max(1u, std::min({16u, hw, n / 65536u + 1u}));
 }
 
+namespace {
+// Persistent workers for parallel_ranges (starting threads per call cost about as much as
+// the loops they ran).  One job at a time; the calling thread takes share 0.
+class WorkerPool {
+ public:
+  explicit WorkerPool(unsigned n) {
+    for (unsigned i = 1; i < n; ++i) th_.emplace_back([this, i] { loop(i); });
+  }
+  ~WorkerPool() {
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      quit_ = true;
+      ++gen_;
+    }
+    cv_.notify_all();
+    for (auto &t : th_) t.join();
+  }
+  unsigned size() const { return (unsigned)th_.size() + 1; }
+  void run(unsigned nt, const std::function<void(unsigned)> &job) {
+    std::lock_guard<std::mutex> one(run_m_);
+    {
+      std::lock_guard<std::mutex> lk(m_);
+      job_ = &job;
+      nt_ = nt;
+      left_ = nt - 1;
+      ++gen_;
+    }
+    cv_.notify_all();
+    job(0);
+    std::unique_lock<std::mutex> lk(m_);
+    done_.wait(lk, [&] { return left_ == 0; });
+    job_ = nullptr;
+  }
+
+ private:
+  void loop(unsigned i) {
+    uint64_t seen = 0;
+    for (;;) {
+      const std::function<void(unsigned)> *job = nullptr;
+      {
+        std::unique_lock<std::mutex> lk(m_);
+        cv_.wait(lk, [&] { return gen_ != seen; });
+        seen = gen_;
+        if (quit_) return;
+        if (i >= nt_) continue;
+        job = job_;
+      }
+      (*job)(i);
+      std::lock_guard<std::mutex> lk(m_);
+      if (--left_ == 0) done_.notify_one();
+    }
+  }
+  std::vector<std::thread> th_;
+  std::mutex m_, run_m_;
+  std::condition_variable cv_, done_;
+  const std::function<void(unsigned)> *job_ = nullptr;
+  unsigned nt_ = 0, left_ = 0;
+  uint64_t gen_ = 0;
+  bool quit_ = false;
+};
+
+WorkerPool &workers() {
+  static WorkerPool pool(std::max(1u, std::min(16u, std::thread::hardware_concurrency())));
+  return pool;
+}
+}  // namespace
+
 void parallel_ranges(uint32_t n, const std::function<void(uint32_t, uint32_t, unsigned)> &f) {
-  const unsigned nt = parallel_threads(n);
+  const unsigned nt = std::min(parallel_threads(n), workers().size());
   if (nt == 1) {
     f(0, n, 0);
     return;
   }
-  std::vector<std::thread> pool;
-  for (unsigned w = 0; w < nt; ++w) {
+  workers().run(nt, [&](unsigned w) {
     const uint32_t b = (uint32_t)((uint64_t)n * w / nt), e = (uint32_t)((uint64_t)n * (w + 1) / nt);
-    pool.emplace_back(f, b, e, w);
-  }
-  for (auto &t : pool) t.join();
+    f(b, e, w);
+  });
 }
 
 // ------------------------------------------------------------------ schedule

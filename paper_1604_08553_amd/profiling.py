@@ -45,6 +45,26 @@ def kernel_stats(trace_dir: str):
              float(r["Percentage"])) for r in rows]
 
 
+def busy_time(trace_dir: str, kernel_substr: str):
+    """(dispatches, sum of durations, union of the dispatch intervals) in ns: a run's
+    first main batch may run beside its pilot, so the kernel's busy time is the union."""
+    path = _one(os.path.join(trace_dir, "**", "*kernel_trace.csv"))
+    iv = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]))
+                for r in csv.DictReader(open(path)) if kernel_substr in r["Kernel_Name"])
+    total = sum(e - b for b, e in iv)
+    busy, lo, hi = 0, None, None
+    for b, e in iv:
+        if hi is None or b > hi:
+            if hi is not None:
+                busy += hi - lo
+            lo, hi = b, e
+        else:
+            hi = max(hi, e)
+    if hi is not None:
+        busy += hi - lo
+    return len(iv), total, busy
+
+
 def counter_per_dispatch(pmc_dir: str, kernel_substr: str, counter: str):
     path = _one(os.path.join(pmc_dir, "**", "*counter_collection.csv"))
     vals = [float(r["Counter_Value"]) for r in csv.DictReader(open(path))
@@ -80,6 +100,12 @@ def main():
     for name, calls, tot, avg, pct in stats:
         short = name.replace("kad::(anonymous namespace)::", "").split("(")[0]
         lines.append(f"| {short} | {calls} | {tot / 1e6:.3f} | {avg / 1e3:.1f} | {pct:.2f} |")
+    nd, tot_ns, busy_ns = busy_time(args.trace, "sampler_kernel")
+    if nd:
+        lines += ["", f"* sampler_kernel: {nd} dispatches, mean duration {tot_ns / nd / 1e3:.1f} us; "
+                  f"busy time (union of the dispatch intervals: a run's first main batch runs "
+                  f"beside its pilot) {busy_ns / 1e6:.3f} ms = {busy_ns / nd / 1e3:.1f} us per "
+                  f"dispatch, the figure the bench's HIP events give"]
     open(os.path.join(args.out, "sampler_cl1m_kernel_stats.md"), "w").write("\n".join(lines) + "\n")
 
     copy_bytes = args.copy_mib << 20
