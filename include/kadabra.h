@@ -270,6 +270,19 @@ kad_status kad_compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha,
                              const double *lambda_l, const double *lambda_u, double delta,
                              double balance_eps, double *L_l, double *L_u, double *C);
 
+/* computeDelta (Algorithm 2) when every node has the same half-widths lambda_l and
+ * lambda_u (the all-nodes task), from the histogram of the pilot counts: hist[c] nodes
+ * have pilot count c, for c = 0..cmax (host array of cmax + 1 entries; n = the sum).  The
+ * nodes with one count share their L values: group_of_count[c] receives the group of
+ * count c (entries of counts absent from the histogram are 0), L_l[g] and L_u[g] the
+ * group's -ln(delta_L), -ln(delta_U) (room for cmax + 1 groups), *ngroups the number of
+ * groups, *C the bisection's constant (may be NULL).  The same values, bit for bit, as
+ * kad_compute_delta gives each node. */
+kad_status kad_compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cmax, uint64_t alpha,
+                                  uint64_t omega, double lambda_l, double lambda_u, double delta,
+                                  double balance_eps, uint32_t *group_of_count, double *L_l,
+                                  double *L_u, uint32_t *ngroups, double *C);
+
 /* Wanted half-widths for the top-k task (section 5) from the pilot counts. */
 kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha,
                             double epsilon, double *lambda_l, double *lambda_u);

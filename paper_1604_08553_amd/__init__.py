@@ -95,6 +95,8 @@ def lib():
         "kad_bound_f": ([dbl, dbl, dbl, dbl], dbl),
         "kad_bound_g": ([dbl, dbl, dbl, dbl], dbl),
         "kad_compute_delta": ([u32, vp, u64, u64, vp, vp, dbl, dbl, vp, vp, vp], st),
+        "kad_compute_delta_hist": ([u32, vp, u64, u64, u64, dbl, dbl, dbl, dbl, vp, vp, vp, vp,
+                                    vp], st),
         "kad_topk_lambdas": ([u32, u32, vp, u64, dbl, vp, vp], st),
         "kad_have_to_stop": ([u32, u32, u32, vp, u64, u64, dbl, vp, vp], st),
         "kad_run_batch": ([vp, u32, vp, vp, vp, vp], st),
@@ -489,6 +491,20 @@ def compute_delta(count0, alpha_, omega_, lam_l, lam_u, delta, balance_eps=0.001
     _check(lib().kad_compute_delta(n, _p(count0), alpha_, omega_, _p(ll), _p(lu), delta,
                                    balance_eps, _p(Ll), _p(Lu), C.byref(Cv)))
     return Ll, Lu, Cv.value
+
+
+def compute_delta_hist(hist, alpha_, omega_, lam_l, lam_u, delta, balance_eps=0.001):
+    """computeDelta for uniform half-widths from the pilot-count histogram: returns
+    (group_of_count, L_l per group, L_u per group, C)."""
+    hist = np.ascontiguousarray(hist, dtype=np.uint64)
+    m = hist.size
+    gof = np.zeros(m, dtype=np.uint32)
+    Ll, Lu = np.zeros(m), np.zeros(m)
+    ng, Cv = C.c_uint32(), C.c_double()
+    _check(lib().kad_compute_delta_hist(int(hist.sum()), _p(hist), m - 1, alpha_, omega_, lam_l,
+                                        lam_u, delta, balance_eps, _p(gof), _p(Ll), _p(Lu),
+                                        C.byref(ng), C.byref(Cv)))
+    return gof, Ll[:ng.value], Lu[:ng.value], Cv.value
 
 
 def topk_lambdas(count0, k, alpha_, epsilon):

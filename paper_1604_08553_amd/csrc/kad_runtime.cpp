@@ -778,6 +778,31 @@ kad_status kad_compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha,
   return KAD_OK;
 }
 
+kad_status kad_compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cmax, uint64_t alpha,
+                                  uint64_t omega, double lambda_l, double lambda_u, double delta,
+                                  double balance_eps, uint32_t *group_of_count, double *L_l,
+                                  double *L_u, uint32_t *ngroups, double *C) {
+  if (!n || !hist || !alpha || !group_of_count || !L_l || !L_u || !ngroups)
+    return fail(KAD_EINVAL, "bad argument");
+  if (!(delta > 0 && delta < 1) || !(balance_eps > 0 && balance_eps < 0.5))
+    return fail(KAD_EINVAL, "delta must be in (0,1) and balance_eps in (0,0.5)");
+  if (cmax >= (1ull << 32)) return fail(KAD_EINVAL, "cmax too large");
+  uint64_t total = 0;
+  for (uint64_t c = 0; c <= cmax; ++c) total += hist[c];
+  if (total != n) return fail(KAD_EINVAL, "the histogram does not count n nodes");
+  std::vector<uint32_t> cgrp;
+  kad::Groups groups;
+  kad::compute_delta_hist(n, hist, cmax, alpha, omega, lambda_l, lambda_u, delta, balance_eps,
+                          cgrp, groups, C);
+  for (uint64_t c = 0; c <= cmax; ++c) group_of_count[c] = hist[c] ? cgrp[c] : 0u;
+  for (size_t g = 0; g < groups.L_l.size(); ++g) {
+    L_l[g] = groups.L_l[g];
+    L_u[g] = groups.L_u[g];
+  }
+  *ngroups = (uint32_t)groups.L_l.size();
+  return KAD_OK;
+}
+
 kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha,
                             double epsilon, double *lambda_l, double *lambda_u) {
   if (!n || k < 1 || k > n || !count0 || !lambda_l || !lambda_u || !alpha)

@@ -99,6 +99,24 @@ def test_compute_delta_matches_oracle(klib, oracle_lib):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_compute_delta_hist_matches_oracle(klib, oracle_lib):
+    """The all-nodes run solves computeDelta from the histogram of the pilot counts; the
+    L value of each node (through its count's group) and C equal the oracle's per-node
+    computeDelta bit for bit."""
+    for seed, n in enumerate((10, 1000, 20000, 50000)):
+        alpha, om = 299 + 40 * seed, 29979 + 1000 * seed
+        c0 = _pilot(n, alpha, 50 + seed)
+        lam = 0.004 + 0.003 * seed
+        hist = np.bincount(c0.astype(np.int64), minlength=alpha + 1).astype(np.uint64)
+        gof, gll, glu, cv = kad.compute_delta_hist(hist, alpha, om, lam, lam, 0.1, 0.001)
+        b = oracle_lib.compute_delta(c0, alpha, om, np.full(n, lam), np.full(n, lam), 0.1, 0.001)
+        g = gof[c0.astype(np.int64)]
+        assert np.array_equal(gll[g], b[0]) and np.array_equal(glu[g], b[1]) and cv == b[2]
+        # one group per count present, in ascending order of the count
+        present = np.nonzero(hist)[0]
+        assert np.array_equal(gof[present], np.arange(present.size))
+
+
 def test_topk_lambdas_match_oracle(klib, oracle_lib):
     for seed in range(6):
         n = 500
