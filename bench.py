@@ -317,7 +317,7 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-batch", type=int, default=65536)
     ap.add_argument("--check-interval", type=int, default=0)
-    ap.add_argument("--cpu-samples", type=int, default=20000)
+    ap.add_argument("--cpu-samples", type=int, default=150000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queries", type=int, default=1000, help="serve: queries in the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")

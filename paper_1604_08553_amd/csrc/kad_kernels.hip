@@ -387,6 +387,20 @@ __device__ __forceinline__ uint32_t wave_reserve(bool pred, uint32_t *counter, u
   return base;
 }
 
+// Whether a touch scan tests a long row of d arcs against the other side's frontier
+// (om nodes) by binary searches instead of reading it.  The row is sorted, so each
+// search finds one frontier node or proves it absent; om searches read about
+// om * (log2(d) - 4) lines below the levels they share (4-byte ids, 128-byte lines),
+// reading the row takes d / 32 lines, and all searches of a chunk form one chain of
+// about log2(d) dependent loads where the row takes d / (BLOCK * U) rounds.  The edges
+// found are the same; their order in the candidate list is not, and the choice among
+// them depends only on their keys.
+__device__ __forceinline__ bool touch_by_search(uint32_t d, uint32_t om) {
+  if (d < 1024u || om == 0) return false;
+  const uint32_t depth = 27u - (uint32_t)__clz(d);  // floor(log2 d) - 4, at least 6
+  return (uint64_t)om * depth * 64u < (uint64_t)d;
+}
+
 // Touch: meeting test only (filter + tag).  Discover: next-level claims and counts only.
 // Both: the meeting test by tag and the discovery in one pass (small expansions).
 enum class Scan { Touch, Discover, Both };
@@ -405,14 +419,17 @@ enum class Scan { Touch, Discover, Both };
 // triple-buffered so that a window takes one barrier: window k sets its bits in mask
 // k mod 3 and clears mask (k+1) mod 3, which every wave finished reading before the
 // barrier of window k-1.  wk is the window counter (mod 3), carried from call to call.
-// Short rows take the chunk slots from the front, long rows from the back.
+// Short rows take the chunk slots from the front, long rows from the back, and below
+// them (touch scans only) the long rows that are searched for the other frontier's om
+// nodes visit[ob, ob + om) rather than read (touch_by_search).
 template <int BLOCK, Scan MODE>
 __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, uint32_t me,
                                               uint32_t fb, uint32_t fe, uint32_t *tag,
                                               uint64_t *sig, uint32_t *visit, uint64_t *gpi,
                                               uint32_t pi_cap, uint32_t other_tag,
                                               uint32_t next_tag, bool &ovf, uint32_t &wk,
-                                              bool exact, bool first) {
+                                              bool exact, bool first, uint32_t ob = 0,
+                                              uint32_t om = 0) {
   constexpr int CHUNK = 2 * BLOCK;
   // arcs per lane per window or piece: a window costs a few dependent round trips
   // whatever its size; wider touch windows than 8 run out of registers
@@ -566,34 +583,48 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
         }
       }
     }
-    // classes: 0 none, 1 short, 2 long (an endpoint's row, alone, always takes the
-    // piece walk: it needs no window bookkeeping)
+    // classes: 0 none, 1 short, 2 long, 3 searched (an endpoint's row, alone, is never
+    // short: it needs no window bookkeeping)
     uint32_t cls[2];
 #pragma unroll
-    for (int q = 0; q < 2; ++q) cls[q] = d[q] == 0 ? 0u : (d[q] < WIN && !first ? 1u : 2u);
+    for (int q = 0; q < 2; ++q) {
+      cls[q] = d[q] == 0 ? 0u : (d[q] < WIN && !first ? 1u : 2u);
+      if (MODE == Scan::Touch && cls[q] == 2 && touch_by_search(d[q], om)) cls[q] = 3;
+    }
+    // per-class row counts in three 10-bit fields (a chunk has at most 512 rows)
+    static_assert(CHUNK < 1024, "row counts fit their fields");
+    constexpr uint32_t F_LONG = 1u << 10, F_SEARCH = 1u << 20;
     const uint32_t sarcs = (cls[0] == 1 ? d[0] : 0u) + (cls[1] == 1 ? d[1] : 0u);
-    const uint32_t cnts = (cls[0] == 1 ? 1u : 0u) + (cls[1] == 1 ? 1u : 0u) +
-                          ((cls[0] == 2 ? 1u : 0u) + (cls[1] == 2 ? 1u : 0u)) * 65536u;
+    uint32_t cnts = 0;
+#pragma unroll
+    for (int q = 0; q < 2; ++q)
+      cnts += cls[q] == 1 ? 1u : (cls[q] == 2 ? F_LONG : (cls[q] == 3 ? F_SEARCH : 0u));
     uint32_t ex = 0, cx = 0, tot, ncx;
-    if (first) {  // one long row, held by thread 0: the scan's results are known
+    if (first) {  // one row, held by thread 0: the scan's results are known
+      const uint32_t d0 = (uint32_t)L.deg[me];
       tot = 0;
-      ncx = L.deg[me] == 0 ? 0u : 65536u;
+      ncx = d0 == 0 ? 0u
+                    : (MODE == Scan::Touch && touch_by_search(d0, om) ? F_SEARCH : F_LONG);
     } else {
       block_excl2_u32(L, sarcs, cnts, ex, cx, tot, ncx);
     }
-    const uint32_t nlong = ncx >> 16;
+    const uint32_t nlong = (ncx >> 10) & 1023u, nsearch = ncx >> 20;
     // this thread's rows: chunk slot and (short rows) first position in the arc space
     uint32_t slot[2], pos[2];
-    slot[0] = cls[0] == 2 ? CHUNK - 1 - (cx >> 16) : (cx & 0xFFFFu);
-    slot[1] = cls[1] == 2 ? CHUNK - 1 - (cx >> 16) - (cls[0] == 2 ? 1u : 0u)
-                          : (cx & 0xFFFFu) + (cls[0] == 1 ? 1u : 0u);
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const uint32_t same = q == 1 && cls[0] == cls[1] ? 1u : 0u;  // row 0 goes first
+      slot[q] = cls[q] == 1   ? (cx & 1023u) + same
+                : cls[q] == 2 ? CHUNK - 1 - ((cx >> 10) & 1023u) - same
+                              : CHUNK - 1 - nlong - (cx >> 20) - same;
+    }
     pos[0] = ex;
     pos[1] = ex + (cls[0] == 1 ? d[0] : 0u);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
       if (cls[q] != 0) {
         L.c_node[slot[q]] = u[q];
-        L.c_off[slot[q]] = cls[q] == 2 ? st[q] : st[q] - pos[q];
+        L.c_off[slot[q]] = cls[q] == 1 ? st[q] - pos[q] : st[q];
         L.c_deg[slot[q]] = d[q];
         if (MODE != Scan::Touch) {
           L.c_sig_lo[slot[q]] = su[q].lo;
@@ -602,10 +633,46 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
       }
     }
 
+    if (nlong + nsearch > 0) __syncthreads();
+    // ---- searched rows: one lane per (row, other-frontier node) pair
+    if (MODE == Scan::Touch && nsearch > 0) {
+      const uint32_t pairs = nsearch * om;
+      for (uint32_t p0 = 0; p0 < pairs; p0 += BLOCK) {
+        const uint32_t p = p0 + tid;
+        bool hit = false;
+        uint32_t u = 0, w = 0;
+        if (p < pairs) {
+          const uint32_t r = p / om;
+          const uint32_t sl = CHUNK - 1 - nlong - r;
+          const uint32_t rst = L.c_off[sl], rd = L.c_deg[sl];
+          w = visit[ob + (p - r * om)];
+          u = L.c_node[sl];
+          uint32_t lo = 0, len = rd;  // first position whose id is not below w
+          while (len > 0) {
+            const uint32_t half = len >> 1;
+            if (cl[rst + lo + half] < w) {
+              lo += half + 1;
+              len -= half + 1;
+            } else {
+              len = half;
+            }
+          }
+          hit = lo < rd && cl[rst + lo] == w;
+        }
+        uint32_t rank = 0;
+        const uint32_t base = wave_reserve(hit, &L.pi_count, rank);
+        if (hit) {
+          const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+          const uint32_t idx = base + rank;
+          if (idx < (uint32_t)PI_LDS) L.pi[idx] = key;
+          else if (idx < pi_cap) gpi[idx] = key;
+        }
+      }
+    }
+
     // ---- long rows, piece by piece (no barrier between pieces); the row loads of a
     // wave's next piece go out before its current piece is tested
     if (nlong > 0) {
-      __syncthreads();
       for (uint32_t r = 0; r < nlong; ++r) {
         const uint32_t sl = CHUNK - 1 - r;
         const uint32_t rst = L.c_off[sl], rd = L.c_deg[sl];
@@ -1053,7 +1120,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         }
         __syncthreads();
         scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
-                                   next_tag, ovf, wk, exact, lme == 0);
+                                   next_tag, ovf, wk, exact, lme == 0, ob, oe - ob);
         for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
         const uint32_t P = L.pi_count;  // final: the scan ends with a barrier
         if (P > 0) {
