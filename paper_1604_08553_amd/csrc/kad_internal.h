@@ -241,7 +241,7 @@ void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega,
 void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule,
                         double eps, const uint64_t *count0, const std::vector<uint32_t> &cgrp,
                         const std::vector<double> &gL_l, const std::vector<double> &gL_u,
-                        double *bc, double *lo, double *hi);
+                        double *bc, double *lo, double *hi, uint64_t *count_out);
 // Top-k selection: nodes with rank_lo <= k ordered by (count desc, id asc).
 void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
                  std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,

@@ -297,7 +297,7 @@ void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega,
 void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule,
                         double eps, const uint64_t *count0, const std::vector<uint32_t> &cgrp,
                         const std::vector<double> &gL_l, const std::vector<double> &gL_u,
-                        double *bc, double *lo, double *hi) {
+                        double *bc, double *lo, double *hi, uint64_t *count_out) {
   const double T = (double)tau, W = (double)omega;
   struct Memo {
     uint64_t c;
@@ -305,20 +305,25 @@ void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t 
     bool used;
     double f, g;
   };
+  // one pass over the nodes: the caller's counts, b~ and the two bounds
   parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
-    std::vector<Memo> memo(rule ? 16384 : 0, Memo{0, 0, false, 0.0, 0.0});
+    thread_local std::vector<Memo> memo;  // kept by each worker: no fresh pages per call
+    if (rule) memo.assign(16384, Memo{0, 0, false, 0.0, 0.0});
     for (uint32_t v = vb; v < ve; ++v) {
-      bc[v] = (double)cnt[v] / T;
+      const uint64_t c = cnt[v];
+      if (count_out) count_out[v] = c;
+      const double b = (double)c / T;
+      bc[v] = b;
       if (rule) {
         const uint32_t gv = cgrp[count0[v]];
-        Memo &m = memo[(uint32_t)((cnt[v] * 0x9E3779B97F4A7C15ULL ^ (uint64_t)gv * 0xC2B2AE3D27D4EB4FULL) >> 50)];
-        if (!(m.used && m.c == cnt[v] && m.grp == gv))
-          m = Memo{cnt[v], gv, true, bound_f(bc[v], gL_l[gv], W, T), bound_g(bc[v], gL_u[gv], W, T)};
-        lo[v] = bc[v] - m.f;
-        hi[v] = bc[v] + m.g;
+        Memo &m = memo[(uint32_t)((c * 0x9E3779B97F4A7C15ULL ^ (uint64_t)gv * 0xC2B2AE3D27D4EB4FULL) >> 50)];
+        if (!(m.used && m.c == c && m.grp == gv))
+          m = Memo{c, gv, true, bound_f(b, gL_l[gv], W, T), bound_g(b, gL_u[gv], W, T)};
+        lo[v] = b - m.f;
+        hi[v] = b + m.g;
       } else {
-        lo[v] = bc[v] - eps;
-        hi[v] = bc[v] + eps;
+        lo[v] = b - eps;
+        hi[v] = b + eps;
       }
     }
   });
@@ -1289,13 +1294,13 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   double *bc = r->bc ? r->bc : (bcs.resize(n), bcs.data());
   double *lo = r->lower && !topk ? r->lower : (los.resize(n), los.data());
   double *hi = r->upper && !topk ? r->upper : (his.resize(n), his.data());
-  if (r->count)
+  if (r->count && !pilot_hist)
     kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
       memcpy(r->count + vb, cnt + vb, (size_t)(ve - vb) * 8);
     });
   if (pilot_hist)
     kad::node_outputs_pilot(n, cnt, tau, omega, rule, p->epsilon, ctx->h_count0p.p, cgrp_h, gLl,
-                            gLu, bc, lo, hi);
+                            gLu, bc, lo, hi, r->count);
   else
     kad::node_outputs(n, cnt, tau, omega, rule, p->epsilon, L_l.data(), L_u.data(),
                       checker.group_of(), bc, lo, hi);
