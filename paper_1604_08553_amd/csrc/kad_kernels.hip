@@ -388,17 +388,17 @@ __device__ __forceinline__ uint32_t wave_reserve(bool pred, uint32_t *counter, u
 }
 
 // Whether a touch scan tests a long row of d arcs against the other side's frontier
-// (om nodes) by binary searches instead of reading it.  The row is sorted, so each
-// search finds one frontier node or proves it absent; om searches read about
-// om * (log2(d) - 4) lines below the levels they share (4-byte ids, 128-byte lines),
-// reading the row takes d / 32 lines, and all searches of a chunk form one chain of
-// about log2(d) dependent loads where the row takes d / (BLOCK * U) rounds.  The edges
-// found are the same; their order in the candidate list is not, and the choice among
-// them depends only on their keys.
+// (om nodes) by binary searches instead of reading it: when the searches read fewer
+// lines.  The row is sorted, so each search finds one frontier node or proves it
+// absent; om searches read about om * (log2(d) - 4) lines below the levels they share
+// (4-byte ids, 128-byte lines), reading the row takes d / 32 lines.  (All searches of
+// a chunk form one chain of about log2(d) dependent loads; the row takes
+// d / (BLOCK * U) rounds.)  The edges found are the same; their order in the candidate
+// list is not, and the choice among them depends only on their keys.
 __device__ __forceinline__ bool touch_by_search(uint32_t d, uint32_t om) {
   if (d < 1024u || om == 0) return false;
   const uint32_t depth = 27u - (uint32_t)__clz(d);  // floor(log2 d) - 4, at least 6
-  return (uint64_t)om * depth * 64u < (uint64_t)d;
+  return (uint64_t)om * depth * 32u < (uint64_t)d;
 }
 
 // Touch: meeting test only (filter + tag).  Discover: next-level claims and counts only.
