@@ -30,15 +30,16 @@ struct GraphDev {
 };
 
 // Per-slot working state: one slot per resident sampler workgroup.  Each slot owns
-// n tags, n 128-bit path counts (zero between samples), an n-entry list of the
-// nodes reached (the frontiers are contiguous segments of it) and a candidate-edge
-// buffer of pi_cap entries.
+// n node records of REC_WORDS words -- tag, wide-count position, 128-bit path count
+// (low, high) -- all zero between samples, an n-entry list of the nodes reached (the
+// frontiers are contiguous segments of it) and a candidate-edge buffer of pi_cap
+// entries.
+constexpr uint32_t REC_WORDS = 8;
 struct SlotState {
   uint32_t slots;
   uint32_t n;
   uint32_t pi_cap;     // power of two
-  uint32_t *tag;       // [slots * n]
-  uint64_t *sig;       // [slots * n * 2]  (lo, hi)
+  uint32_t *rec;       // [slots * n * REC_WORDS]
   uint32_t *visit;     // [slots * n]
   uint64_t *pi;        // [slots * pi_cap]
 };
@@ -59,10 +60,10 @@ struct SampleSeg {
   uint32_t pad;
 };
 
-// Working memory of the wide-count resampling (wide_kernel): the sampler slots' tag,
-// node-list and count arrays are reused (the count array of a slot holds node
-// positions meanwhile); per wide slot a limb arena and level tables of max_lev
-// levels per side.
+// Working memory of the wide-count resampling (wide_kernel): the sampler slots' node
+// records and node lists are reused (a record's position word holds the node's
+// position meanwhile); per wide slot a limb arena and level tables of max_lev levels
+// per side.
 struct WideState {
   uint32_t slots;       // <= the sampler slots
   uint32_t max_lev;

@@ -322,9 +322,8 @@ void Engine::layout() {
 SlotState Engine::lane_slots(const Lane &L, bool wide) const {
   SlotState st = slot_view(ctx_);
   const size_t off = wide ? L.wslot0 : L.slot0, n = st.n;
-  st.tag += off * n;
+  st.rec += off * n * REC_WORDS;
   st.visit += off * n;
-  st.sig += off * n * 2;
   st.pi += off * (size_t)st.pi_cap;
   st.slots = wide ? L.nwslots : L.nslots;
   return st;

@@ -117,8 +117,8 @@ struct kad_ctx {
   // per-slot working state
   uint32_t slot_n = 0, slots = 0;
   uint64_t slot_bytes = 0;
-  kad::DevBuf<uint32_t> tag, visit;
-  kad::DevBuf<uint64_t> sig, pi;
+  kad::DevBuf<uint32_t> rec, visit;  // node records (REC_WORDS words each), reached lists
+  kad::DevBuf<uint64_t> pi;
   // wide-count resampling of overflowed samples (kad::WideState)
   uint32_t w_slots = 0, w_max_lev = 0;
   uint64_t run_wide = 0;  // samples resampled wide during the current kad_run

@@ -169,13 +169,33 @@ __device__ u128 uniform_below(u128 bound, uint64_t seed, uint64_t i, uint64_t sw
 // so every atomic and every load that must observe one is workgroup-scoped: it stays
 // in the CU's XCD (no cross-XCD coherence traffic), and __syncthreads orders it.
 // Between launches the slot state is all-zero, whichever XCD ran it last.
+//
+// A node's state in a slot is one record of REC_WORDS words (32 bytes, so four nodes
+// share a 128-byte line and a node's tag and count share one): word 0 the tag, word 1
+// the wide-count kernel's node position, words 2-5 the 128-bit path count (low, high).
+__device__ __forceinline__ uint32_t *tag_of(uint32_t *rec, uint32_t v) {
+  return rec + (size_t)REC_WORDS * v;
+}
+__device__ __forceinline__ const uint32_t *tag_of(const uint32_t *rec, uint32_t v) {
+  return rec + (size_t)REC_WORDS * v;
+}
+__device__ __forceinline__ uint32_t *pos_of(uint32_t *rec, uint32_t v) {
+  return rec + (size_t)REC_WORDS * v + 1;
+}
+__device__ __forceinline__ uint64_t *sig_of(uint32_t *rec, uint32_t v) {
+  return reinterpret_cast<uint64_t *>(rec + (size_t)REC_WORDS * v + 2);
+}
+__device__ __forceinline__ const uint64_t *sig_of(const uint32_t *rec, uint32_t v) {
+  return reinterpret_cast<const uint64_t *>(rec + (size_t)REC_WORDS * v + 2);
+}
 __device__ __forceinline__ uint32_t ld_tag(const uint32_t *p) {
   return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
-__device__ __forceinline__ u128 ld_sig(const uint64_t *sig, uint32_t v) {
+__device__ __forceinline__ u128 ld_sig(const uint32_t *rec, uint32_t v) {
+  const uint64_t *p = sig_of(rec, v);
   u128 r;
-  r.lo = __hip_atomic_load(sig + 2 * (size_t)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  r.hi = __hip_atomic_load(sig + 2 * (size_t)v + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  r.lo = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  r.hi = __hip_atomic_load(p + 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
   return r;
 }
 __device__ __forceinline__ uint32_t cas_tag(uint32_t *p, uint32_t expect, uint32_t want) {
@@ -424,8 +444,8 @@ enum class Scan { Touch, Discover, Both };
 // nodes visit[ob, ob + om) rather than read (touch_by_search).
 template <int BLOCK, Scan MODE>
 __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, uint32_t me,
-                                              uint32_t fb, uint32_t fe, uint32_t *tag,
-                                              uint64_t *sig, uint32_t *visit, uint64_t *gpi,
+                                              uint32_t fb, uint32_t fe, uint32_t *rec,
+                                              uint32_t *visit, uint64_t *gpi,
                                               uint32_t pi_cap, uint32_t other_tag,
                                               uint32_t next_tag, bool &ovf, uint32_t &wk,
                                               bool exact, bool first, uint32_t ob = 0,
@@ -471,7 +491,7 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
       } else {
         uint32_t tg[U];
 #pragma unroll
-        for (int q = 0; q < U; ++q) tg[q] = (pass >> q) & 1u ? ld_tag(tag + ww[q]) : 0u;
+        for (int q = 0; q < U; ++q) tg[q] = (pass >> q) & 1u ? ld_tag(tag_of(rec, ww[q])) : 0u;
 #pragma unroll
         for (int q = 0; q < U; ++q) hitm |= tg[q] == other_tag ? 1u << q : 0u;  // never 0
       }
@@ -499,7 +519,7 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
       for (int q = 0; q < U; ++q) {
         tg[q] = 0;
         if ((vm >> q) & 1u) {
-          const uint32_t old = cas_tag(tag + ww[q], 0u, next_tag);
+          const uint32_t old = cas_tag(tag_of(rec, ww[q]), 0u, next_tag);
           dm |= old == 0 ? 1u << q : 0u;
           tg[q] = old == 0 ? next_tag : old;
         }
@@ -511,7 +531,7 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         old_lo[q] = 0;
-        if (tg[q] == next_tag) old_lo[q] = add_u64(sig + 2 * (size_t)ww[q], L.c_sig_lo[owner(q)]);
+        if (tg[q] == next_tag) old_lo[q] = add_u64(sig_of(rec, ww[q]), L.c_sig_lo[owner(q)]);
       }
       if (MODE == Scan::Both) {
 #pragma unroll
@@ -551,7 +571,7 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
           const uint64_t add = xhi + ((old_lo[q] + xlo < old_lo[q]) ? 1u : 0u);
           ovf |= add < xhi;
           if (add != 0) {
-            const uint64_t oh = add_u64(sig + 2 * (size_t)ww[q] + 1, add);
+            const uint64_t oh = add_u64(sig_of(rec, ww[q]) + 1, add);
             ovf |= oh + add < oh;
           }
         }
@@ -579,7 +599,7 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
           u[q] = visit[cb + j];
           st[q] = rp[u[q]];
           d[q] = rp[u[q] + 1] - st[q];
-          if (MODE != Scan::Touch) su[q] = ld_sig(sig, u[q]);
+          if (MODE != Scan::Touch) su[q] = ld_sig(rec, u[q]);
         }
       }
     }
@@ -831,7 +851,7 @@ constexpr uint32_t pow2floor(uint32_t x) { return x <= 1 ? 1u : 2u * pow2floor(x
 //                taken in ascending id.  Used when the list is much shorter than the
 //                row (x a hub).
 __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint32_t lev,
-                          const uint32_t *tag, const uint64_t *sig, const uint32_t *visit,
+                          const uint32_t *rec, const uint32_t *visit,
                           const uint32_t (*seg_lo)[MAXLEV], const uint32_t (*seg_hi)[MAXLEV],
                           MatchScratch &M, uint64_t seed, uint64_t i, uint32_t phase,
                           uint32_t *path, uint32_t ls, uint32_t base, uint32_t endpoint,
@@ -851,7 +871,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
       continue;
     }
     const uint32_t beg = rp[x], end = rp[x + 1];  // in flight during the draw
-    const u128 bound = ld_sig(sig, x);
+    const u128 bound = ld_sig(rec, x);
     const u128 r = uniform_below(bound, seed, i, stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j),
                                  flags);
     const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1, stored as (j-1)+1
@@ -889,7 +909,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
           if (match) {
             const uint32_t pos = nm + (uint32_t)__popcll(mk & lanes_below);
             if (pos < (uint32_t)MATCH_CAP) {
-              const u128 sv = ld_sig(sig, cand);
+              const u128 sv = ld_sig(rec, cand);
               M.id[pos] = cand;
               M.lo[pos] = sv.lo;
               M.hi[pos] = sv.hi;
@@ -926,7 +946,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
         u128 val{0, 0};
         if (idx < end) {
           u = cl[idx];
-          if (ld_tag(tag + u) == want) val = ld_sig(sig, u);
+          if (ld_tag(tag_of(rec, u)) == want) val = ld_sig(rec, u);
         }
         bool dummy = false;
         u128 inc = wave_incl_u128(val, dummy);
@@ -968,8 +988,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
   const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
   const size_t n = st.n;  // slot capacity
   const size_t slot = blockIdx.x;
-  uint32_t *tag = st.tag + slot * n;
-  uint64_t *sig = st.sig + slot * n * 2;
+  uint32_t *rec = st.rec + slot * n * REC_WORDS;
   uint32_t *visit = st.visit + slot * n;
   uint64_t *gpi = st.pi + slot * st.pi_cap;
 
@@ -1045,12 +1064,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       const uint32_t t = tp + (tp >= s ? 1u : 0u);
       L.s = s;
       L.t = t;
-      tag[s] = 1u;
-      tag[t] = TAG_T | 1u;
-      sig[2 * (size_t)s] = 1;
-      sig[2 * (size_t)s + 1] = 0;
-      sig[2 * (size_t)t] = 1;
-      sig[2 * (size_t)t + 1] = 0;
+      *tag_of(rec, s) = 1u;
+      *tag_of(rec, t) = TAG_T | 1u;
+      sig_of(rec, s)[0] = 1;
+      sig_of(rec, s)[1] = 0;
+      sig_of(rec, t)[0] = 1;
+      sig_of(rec, t)[1] = 0;
       visit[0] = s;
       visit[1] = t;
       L.fb[0] = 0; L.fe[0] = 1;
@@ -1097,7 +1116,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         // claims are never read if the two searches touched; they are reset anyway)
         __syncthreads();
         bool ovf_next = false;  // counts of the next level matter only if there is one
-        scan_frontier<BLOCK, Scan::Both>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
+        scan_frontier<BLOCK, Scan::Both>(L, g, me, fb, fe, rec, visit, gpi, st.pi_cap, other_tag,
                                   next_tag, ovf_next, wk, false, lme == 0);
         if (L.pi_count > 0) {
           met = true;
@@ -1119,7 +1138,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           if (exact) fset_insert<FSET_SLOTS>(L.fset, v);
         }
         __syncthreads();
-        scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap, other_tag,
+        scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, rec, visit, gpi, st.pi_cap, other_tag,
                                    next_tag, ovf, wk, exact, lme == 0, ob, oe - ob);
         for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
         const uint32_t P = L.pi_count;  // final: the scan ends with a barrier
@@ -1127,7 +1146,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           met = true;
           break;
         }
-        scan_frontier<BLOCK, Scan::Discover>(L, g, me, fb, fe, tag, sig, visit, gpi, st.pi_cap,
+        scan_frontier<BLOCK, Scan::Discover>(L, g, me, fb, fe, rec, visit, gpi, st.pi_cap,
                                       other_tag, next_tag, ovf, wk, false, lme == 0);
       }
       // final: every scan ends with a barrier; tid 0 writes other fields below
@@ -1172,7 +1191,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           u128 wt{0, 0};
           if (tid < P) {
             key = L.pi[tid];
-            wt = mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), wov);
+            wt = mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), wov);
             L.c_sig_lo[tid] = wt.lo;
             L.c_sig_hi[tid] = wt.hi;
           }
@@ -1235,7 +1254,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           u128 acc{0, 0};
           for (uint32_t j = tid; j < P; j += BLOCK) {
             const uint64_t key = key_at(j);
-            acc = add128(acc, mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), wov), wov);
+            acc = add128(acc, mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), wov), wov);
           }
           u128 total;
           (void)block_incl_u128(L, acc, total, wov);
@@ -1265,7 +1284,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
               uint64_t key = 0;
               if (j < P) {
                 key = key_at(j);
-                wt = mul128(ld_sig(sig, (uint32_t)(key >> 32)), ld_sig(sig, (uint32_t)key), dm);
+                wt = mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), dm);
               }
               u128 chunk_total;
               u128 inc = block_incl_u128(L, wt, chunk_total, dm);
@@ -1293,12 +1312,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           MatchScratch *scratch = reinterpret_cast<MatchScratch *>(L.pi);
           if (wid == 0) {
             if (lane == 0) path[ls] = v + base;
-            backtrack(g, 0, v, ls, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[0], seed, i,
+            backtrack(g, 0, v, ls, rec, visit, L.seg_lo, L.seg_hi, scratch[0], seed, i,
                       phase, path, ls, base, L.s, fl);
           }
           if (wid == (NWAVES >= 2 ? 1u : 0u)) {
             if (lane == 0) path[ls + 1] = w + base;
-            backtrack(g, 1, w, lt, tag, sig, visit, L.seg_lo, L.seg_hi, scratch[1], seed, i,
+            backtrack(g, 1, w, lt, rec, visit, L.seg_lo, L.seg_hi, scratch[1], seed, i,
                       phase, path, ls, base, L.t, fl);
           }
           if (win >= P) fl |= FLAG_CAPACITY;
@@ -1320,10 +1339,9 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
     // ---- restore the slot's all-zero state for the next sample
     const uint32_t nv = L.nvis;
     for (uint32_t j = tid; j < nv; j += BLOCK) {
-      const uint32_t v = visit[j];
-      tag[v] = 0;
-      sig[2 * (size_t)v] = 0;
-      sig[2 * (size_t)v + 1] = 0;
+      uint4 *r4 = reinterpret_cast<uint4 *>(tag_of(rec, visit[j]));
+      r4[0] = make_uint4(0, 0, 0, 0);  // tag, position, count low
+      r4[1] = make_uint4(0, 0, 0, 0);  // count high (and the unused words)
     }
     __syncthreads();
   }
@@ -1751,9 +1769,8 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
   const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
   const size_t n = st.n;
   const size_t slot = blockIdx.x;
-  uint32_t *tag = st.tag + slot * n;
+  uint32_t *rec = st.rec + slot * n * REC_WORDS;  // tags and node positions
   uint32_t *visit = st.visit + slot * n;
-  uint32_t *pos = reinterpret_cast<uint32_t *>(st.sig + slot * n * 2);  // zero between samples
   uint64_t *gpi = st.pi + slot * st.pi_cap;
   uint64_t *arena = ws.arena + slot * ws.arena_limbs;
   uint32_t *lv = ws.lv + slot * 2 * (size_t)ws.max_lev * 4;
@@ -1803,12 +1820,12 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       const uint32_t t = tp + (tp >= s ? 1u : 0u);
       L.s = s;
       L.t = t;
-      tag[s] = 1u;
-      tag[t] = TAG_T | 1u;
+      *tag_of(rec, s) = 1u;
+      *tag_of(rec, t) = TAG_T | 1u;
       visit[0] = s;
       visit[1] = t;
-      pos[s] = 0;
-      pos[t] = 1;
+      *pos_of(rec, s) = 0;
+      *pos_of(rec, t) = 1;
       arena[0] = 1;
       arena[1] = 1;
       for (uint32_t x = 0; x < 2; ++x) {
@@ -1903,15 +1920,15 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
           }
           const uint32_t u = L.c_node[lo];
           const uint32_t w = cl[L.c_start[lo] + (e - L.c_pref[lo])];
-          const uint32_t tg = ld_tag(tag + w);
+          const uint32_t tg = ld_tag(tag_of(rec, w));
           if (tg == other_tag) {
             const uint32_t idx = atomicAdd(&L.pi_count, 1u);
             const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
             if (idx < st.pi_cap) gpi[idx] = key;
-          } else if (tg == 0 && cas_tag(tag + w, 0u, next_tag) == 0u) {
+          } else if (tg == 0 && cas_tag(tag_of(rec, w), 0u, next_tag) == 0u) {
             const uint32_t p = atomicAdd(&L.nvis, 1u);
             visit[p] = w;
-            pos[w] = p;
+            *pos_of(rec, w) = p;
             atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)(rp[w + 1] - rp[w]));
             if (nbase + (uint64_t)(p - nb + 1) * stride > ws.arena_limbs) {
               cap = true;
@@ -1922,7 +1939,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
               const uint32_t pe = pr[w + 1];
               for (uint32_t e2 = pr[w]; e2 < pe; ++e2) {
                 const uint32_t u2 = pc[e2];
-                if (ld_tag(tag + u2) == cur_tag) idx[np++] = pos[u2] - fb;
+                if (ld_tag(tag_of(rec, u2)) == cur_tag) idx[np++] = *pos_of(rec, u2) - fb;
                 if (np == 4 || (e2 + 1 == pe && (np > 0 || first))) {
                   pull_add(acc, stride, arena + bl, sl, wl, idx, np, first);
                   first = false;
@@ -1989,8 +2006,8 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
         for (uint32_t j = tid; j < P; j += WB) {
           const uint64_t key = gpi[j];
           const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
-          wide_mul(arena + sb + (size_t)(pos[v] - so) * ss, ws_,
-                   arena + tb + (size_t)(pos[w] - to) * ts, wt_, arena + prod + (size_t)j * pw);
+          wide_mul(arena + sb + (size_t)(*pos_of(rec, v) - so) * ss, ws_,
+                   arena + tb + (size_t)(*pos_of(rec, w) - to) * ts, wt_, arena + prod + (size_t)j * pw);
         }
         __syncthreads();
         // sums of contiguous blocks of weights (one block per thread), then of groups
@@ -2068,7 +2085,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
           for (uint32_t j = lev; j >= 1 && fl == 0; --j) {
             const uint32_t xw = LV(side, j, LV_WIDTH);
             const uint64_t *sx = arena + LB(side, j) +
-                                 (size_t)(pos[x] - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
+                                 (size_t)(*pos_of(rec, x) - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
             uniform_below_wide(sx, xw, seed, i,
                                stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j), r, tmp2, fl);
             const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1
@@ -2079,8 +2096,8 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
             uint32_t pick = 0xFFFFFFFFu;
             for (uint32_t e = brp[x]; e < brp[x + 1] && fl == 0; ++e) {
               const uint32_t u = bcl[e];
-              if (ld_tag(tag + u) != want) continue;
-              (void)wide_add(acc, tw, arena + pb + (size_t)(pos[u] - plo) * pst, pwid);
+              if (ld_tag(tag_of(rec, u)) != want) continue;
+              (void)wide_add(acc, tw, arena + pb + (size_t)(*pos_of(rec, u) - plo) * pst, pwid);
               if (wide_cmp(acc, tw, r, xw) > 0) {
                 pick = u;
                 break;
@@ -2112,8 +2129,8 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
     const uint32_t nv = L.nvis;
     for (uint32_t j = tid; j < nv; j += WB) {
       const uint32_t v = visit[j];
-      tag[v] = 0;
-      pos[v] = 0;
+      *tag_of(rec, v) = 0;
+      *pos_of(rec, v) = 0;
     }
     __syncthreads();
   }

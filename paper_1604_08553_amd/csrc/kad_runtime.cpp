@@ -129,28 +129,26 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   HIP_TRY(hipSetDevice(ctx->device));
   if (ctx->slot_n >= n && ctx->slots > 0) return KAD_OK;
   HIP_TRY(hipDeviceSynchronize());  // no launch may still use the old state
-  ctx->tag.release();
+  ctx->rec.release();
   ctx->visit.release();
-  ctx->sig.release();
   ctx->pi.release();
   ctx->slots = 0;
   ctx->slot_n = 0;
   const uint32_t want_slots =
       ctx->cus * (uint32_t)*std::max_element(ctx->blocks_per_cu, ctx->blocks_per_cu + 3);
-  const uint64_t per_slot = (uint64_t)n * (4 + 4 + 16) + (uint64_t)PI_CAP * 8;
-  // slots take at most 60% of what the budget leaves after the graphs and 1 GiB
+  const uint64_t per_slot = (uint64_t)n * (4ull * REC_WORDS + 4) + (uint64_t)PI_CAP * 8;
+  // slots take at most 85% of what the budget leaves after the graphs and 1 GiB (the
+  // wide-count arenas and the run buffers use the rest)
   const uint64_t avail = ctx->budget > ctx->used_graphs + (1024ull << 20)
-                             ? (uint64_t)(0.6 * (double)(ctx->budget - ctx->used_graphs - (1024ull << 20)))
+                             ? (uint64_t)(0.85 * (double)(ctx->budget - ctx->used_graphs - (1024ull << 20)))
                              : 0;
   const uint64_t slots = std::min<uint64_t>(want_slots, avail / per_slot);
   if (slots == 0)
     return fail(KAD_ENOMEM, "HBM budget too small for one sampler slot of a %u-node graph", n);
-  HIP_TRY(ctx->tag.ensure((size_t)slots * n));
+  HIP_TRY(ctx->rec.ensure((size_t)slots * n * REC_WORDS));
   HIP_TRY(ctx->visit.ensure((size_t)slots * n));
-  HIP_TRY(ctx->sig.ensure((size_t)slots * n * 2));
   HIP_TRY(ctx->pi.ensure((size_t)slots * PI_CAP));
-  HIP_TRY(hipMemsetAsync(ctx->tag.p, 0, (size_t)slots * n * 4, ctx->stream));
-  HIP_TRY(hipMemsetAsync(ctx->sig.p, 0, (size_t)slots * n * 16, ctx->stream));
+  HIP_TRY(hipMemsetAsync(ctx->rec.p, 0, (size_t)slots * n * 4 * REC_WORDS, ctx->stream));
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   ctx->slots = (uint32_t)slots;
   ctx->slot_n = n;
@@ -248,8 +246,7 @@ SlotState slot_view(const kad_ctx *ctx, uint32_t slot0) {
   st.slots = ctx->slots > slot0 ? ctx->slots - slot0 : 0;
   st.n = ctx->slot_n;
   st.pi_cap = PI_CAP;
-  st.tag = ctx->tag.p + (size_t)slot0 * n;
-  st.sig = ctx->sig.p + (size_t)slot0 * n * 2;
+  st.rec = ctx->rec.p + (size_t)slot0 * n * REC_WORDS;
   st.visit = ctx->visit.p + (size_t)slot0 * n;
   st.pi = ctx->pi.p + (size_t)slot0 * PI_CAP;
   return st;
