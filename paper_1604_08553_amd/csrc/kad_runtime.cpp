@@ -137,10 +137,10 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   const uint32_t want_slots =
       ctx->cus * (uint32_t)*std::max_element(ctx->blocks_per_cu, ctx->blocks_per_cu + 3);
   const uint64_t per_slot = (uint64_t)n * (4ull * REC_WORDS + 4) + (uint64_t)PI_CAP * 8;
-  // slots take at most 85% of what the budget leaves after the graphs and 1 GiB (the
-  // wide-count arenas and the run buffers use the rest)
+  // slots take at most 70% of what the budget leaves after the graphs and 1 GiB (the
+  // wide-count arenas, the engine's pools and the run buffers use the rest)
   const uint64_t avail = ctx->budget > ctx->used_graphs + (1024ull << 20)
-                             ? (uint64_t)(0.85 * (double)(ctx->budget - ctx->used_graphs - (1024ull << 20)))
+                             ? (uint64_t)(0.7 * (double)(ctx->budget - ctx->used_graphs - (1024ull << 20)))
                              : 0;
   const uint64_t slots = std::min<uint64_t>(want_slots, avail / per_slot);
   if (slots == 0)
