@@ -1,6 +1,7 @@
 // Library-internal host structures shared by the single-run path (kad_runtime.cpp)
 // and the multi-query engine (kad_engine.cpp).
 #pragma once
+#include <functional>
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -241,7 +242,8 @@ void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega,
 void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule,
                         double eps, const uint64_t *count0, const std::vector<uint32_t> &cgrp,
                         const std::vector<double> &gL_l, const std::vector<double> &gL_u,
-                        double *bc, double *lo, double *hi, uint64_t *count_out);
+                        double *bc, double *lo, double *hi, uint64_t *count_out,
+                        const std::function<void(uint32_t)> &wait_to = nullptr);
 // Top-k selection: nodes with rank_lo <= k ordered by (count desc, id asc).
 void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
                  std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,

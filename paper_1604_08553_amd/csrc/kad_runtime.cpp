@@ -2,6 +2,8 @@
 // (Algorithm 1 of Borassi & Natale with a batched stopping check) and the sampling
 // primitives.  The sampling itself runs in the HIP kernels of kad_kernels.hip; this
 // file moves data, schedules launches and evaluates the binary64 statistics.
+#include <functional>
+#include <atomic>
 #include <hip/hip_runtime.h>
 #include <math.h>
 #include <stdarg.h>
@@ -294,7 +296,8 @@ void node_outputs(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega,
 void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t omega, bool rule,
                         double eps, const uint64_t *count0, const std::vector<uint32_t> &cgrp,
                         const std::vector<double> &gL_l, const std::vector<double> &gL_u,
-                        double *bc, double *lo, double *hi, uint64_t *count_out) {
+                        double *bc, double *lo, double *hi, uint64_t *count_out,
+                        const std::function<void(uint32_t)> &wait_to) {
   const double T = (double)tau, W = (double)omega;
   struct Memo {
     uint64_t c;
@@ -306,6 +309,7 @@ void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t 
   parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
     thread_local std::vector<Memo> memo;  // kept by each worker: no fresh pages per call
     if (rule) memo.assign(16384, Memo{0, 0, false, 0.0, 0.0});
+    if (wait_to) wait_to(ve);  // the counts of [0, ve) have landed
     for (uint32_t v = vb; v < ve; ++v) {
       const uint64_t c = cnt[v];
       if (count_out) count_out[v] = c;
@@ -1264,8 +1268,23 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     cur = 1 - cur;
     cur_nb = next_nb;
   }
-  HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)n * 8, hipMemcpyDeviceToHost, rs));
-  HIP_TRY(wait_stream(ctx, rs));
+  // The final counts come back in parts, each with its event, so that the host's pass
+  // over the nodes (below) starts on the first part while the others are in flight.
+  constexpr uint32_t OUT_PARTS = 4;
+  while (ctx->chunk_ev.size() < OUT_PARTS) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->chunk_ev.push_back(e);
+  }
+  uint32_t part_lo[OUT_PARTS + 1];
+  for (uint32_t q = 0; q <= OUT_PARTS; ++q) part_lo[q] = (uint32_t)((uint64_t)n * q / OUT_PARTS);
+  HIP_TRY(wait_stream(ctx, rs));  // the last reduction (the sampler time ends here)
+  for (uint32_t q = 0; q < OUT_PARTS; ++q) {
+    if (part_lo[q + 1] > part_lo[q])
+      HIP_TRY(hipMemcpyAsync(ctx->h_count.p + part_lo[q], ctx->count.p + part_lo[q],
+                             (size_t)(part_lo[q + 1] - part_lo[q]) * 8, hipMemcpyDeviceToHost, rs));
+    HIP_TRY(hipEventRecord(ctx->chunk_ev[q], rs));
+  }
   HIP_TRY(wait_stream(ctx, stream));
   if (overlap) HIP_TRY(wait_stream(ctx, b1_stream));
   run_timing_end(ctx);
@@ -1291,16 +1310,25 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   double *bc = r->bc ? r->bc : (bcs.resize(n), bcs.data());
   double *lo = r->lower && !topk ? r->lower : (los.resize(n), los.data());
   double *hi = r->upper && !topk ? r->upper : (his.resize(n), his.data());
-  if (r->count && !pilot_hist)
-    kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
-      memcpy(r->count + vb, cnt + vb, (size_t)(ve - vb) * 8);
-    });
-  if (pilot_hist)
+  if (pilot_hist) {
+    // one pass; each worker first waits for the parts that hold its range
+    std::atomic<int> werr{0};
     kad::node_outputs_pilot(n, cnt, tau, omega, rule, p->epsilon, ctx->h_count0p.p, cgrp_h, gLl,
-                            gLu, bc, lo, hi, r->count);
-  else
+                            gLu, bc, lo, hi, r->count, [&](uint32_t ve) {
+                              for (uint32_t q = 0; q < OUT_PARTS && part_lo[q] < ve; ++q)
+                                if (wait_event(ctx->chunk_ev[q]) != hipSuccess) werr = 1;
+                            });
+    HIP_TRY(wait_event(ctx->chunk_ev[OUT_PARTS - 1]));
+    if (werr) return fail(KAD_EDEVICE, "copying the counts back failed");
+  } else {
+    HIP_TRY(wait_event(ctx->chunk_ev[OUT_PARTS - 1]));
+    if (r->count)
+      kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+        memcpy(r->count + vb, cnt + vb, (size_t)(ve - vb) * 8);
+      });
     kad::node_outputs(n, cnt, tau, omega, rule, p->epsilon, L_l.data(), L_u.data(),
                       checker.group_of(), bc, lo, hi);
+  }
   if (topk) {
     if (r->lower) memcpy(r->lower, lo, (size_t)n * 8);
     if (r->upper) memcpy(r->upper, hi, (size_t)n * 8);
