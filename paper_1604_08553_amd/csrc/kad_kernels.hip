@@ -165,7 +165,7 @@ __device__ u128 uniform_below(u128 bound, uint64_t seed, uint64_t i, uint64_t sw
 }
 
 // ------------------------------------------------------------------ memory helpers
-// A slot's tags and path counts are touched only by the workgroup that owns the slot,
+// A slot's node records are touched only by the workgroup that owns the slot,
 // so every atomic and every load that must observe one is workgroup-scoped: it stays
 // in the CU's XCD (no cross-XCD coherence traffic), and __syncthreads orders it.
 // Between launches the slot state is all-zero, whichever XCD ran it last.
@@ -1608,7 +1608,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc *__restric
 // multi-limb counts.  The procedure is the one of sampler_kernel (same pair, same
 // level order, same draws; uniform_below consumes the same words whatever the width),
 // so the result is the one exact arithmetic gives.  One workgroup per sample, working
-// in a sampler slot's tag and node-list arrays (all zero between samples); the counts
+// in a sampler slot's node records and node list (all zero between samples); the counts
 // of level l of a side are stored contiguously, `stride` limbs per node in the order
 // of the node list, with stride = (width of level l-1) + 1, which always holds the
 // sum of the predecessors' counts; the level's width is then the widest count.
