@@ -70,6 +70,9 @@ typedef struct kad_graph kad_graph;
 
 /* Open HIP device `hip_device`.  hbm_budget_bytes caps the library's device memory
  * (graphs + per-sample working state); 0 means 90% of the free memory at creation.
+ * The working state is one slot per resident sampler workgroup, 36 bytes per node of the
+ * largest graph run so far plus 512 KiB each, in at most 70% of the budget left after
+ * the graphs (fewer slots than workgroups only lower throughput).
  * Fails with KAD_EDEVICE when the device does not exist. */
 kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **out);
 kad_status kad_ctx_destroy(kad_ctx *ctx);
