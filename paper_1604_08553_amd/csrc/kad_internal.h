@@ -82,13 +82,14 @@ struct OutSet {
   PinBuf<uint64_t> h_arcs;
   uint32_t cap = 0, stride = 0;
   hipEvent_t k0 = nullptr, k1 = nullptr;  // launch start/end (timing)
+  hipEvent_t sampled = nullptr;           // sampler (and wide fix) done: paths final
   hipEvent_t copied = nullptr;            // sampler done and mirrors landed
   hipEvent_t reduced = nullptr;           // every reduction reading this set is done
   OutSet() = default;
   OutSet(const OutSet &) = delete;
   OutSet &operator=(const OutSet &) = delete;
   ~OutSet() {
-    for (hipEvent_t e : {k0, k1, copied, reduced})
+    for (hipEvent_t e : {k0, k1, sampled, copied, reduced})
       if (e) (void)hipEventDestroy(e);
   }
   // capacity for `cap` samples of path stride `stride`; events created on first use

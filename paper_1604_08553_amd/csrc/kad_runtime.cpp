@@ -57,6 +57,7 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
   }
   if (!k0) HIP_TRY(hipEventCreate(&k0));
   if (!k1) HIP_TRY(hipEventCreate(&k1));
+  if (!sampled) HIP_TRY(hipEventCreateWithFlags(&sampled, hipEventDisableTiming));
   if (!copied) HIP_TRY(hipEventCreateWithFlags(&copied, hipEventDisableTiming));
   if (!reduced) {
     HIP_TRY(hipEventCreateWithFlags(&reduced, hipEventDisableTiming));
@@ -491,6 +492,9 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
       o.h_nwide.p[0] = 0;
     }
   }
+  // the reductions need only the paths: they wait for this event, not for the mirrors
+  // (a set is launched into again only after the host has waited for its mirrors)
+  HIP_TRY(hipEventRecord(o.sampled, stream));
   HIP_TRY(hipMemcpyAsync(o.h_flags.p, o.flags.p, (size_t)count * 4, hipMemcpyDeviceToHost, stream));
   HIP_TRY(hipMemcpyAsync(o.h_arcs.p, o.arcs.p, (size_t)count * 8, hipMemcpyDeviceToHost, stream));
   if (ctx->timing) {
@@ -1188,7 +1192,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   while (!stop) {
     if (cur_nb == 0) return fail(KAD_EINVAL, "internal: empty batch before the stopping point");
     const OutSet &o = ctx->outs[cur];
-    HIP_TRY(hipStreamWaitEvent(rs, o.copied, 0));
+    HIP_TRY(hipStreamWaitEvent(rs, o.sampled, 0));
     const uint32_t nch = (uint32_t)((cur_nb + B - 1) / B);
     uint32_t queued = 0;  // check intervals whose reduction and snapshot are enqueued
     auto enqueue_upto = [&](uint32_t upto) -> kad_status {
