@@ -2215,11 +2215,50 @@ hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uin
   return hipGetLastError();
 }
 
+// The same reduction for the hits of one check interval: count[v] += 1 per interior hit
+// by a device atomic, and the group maximum is raised to the count the atomic returned
+// plus one -- the largest of those for a node is its final count, so counts and maxima
+// equal the tiled reduction's.  One kernel and no LDS: a run reduces a batch's check
+// intervals one after another, and this chain is on its critical path.
+__global__ __launch_bounds__(HIT_BLOCK) void hit_atomic_kernel(const uint32_t *path,
+                                                               const uint32_t *len,
+                                                               uint32_t stride, uint32_t nsamp,
+                                                               uint32_t n, uint64_t *count,
+                                                               const uint32_t *group,
+                                                               uint64_t *gmax) {
+  const uint64_t entries = (uint64_t)nsamp * stride;
+  for (uint64_t e = (uint64_t)blockIdx.x * HIT_BLOCK + threadIdx.x; e < entries;
+       e += (uint64_t)gridDim.x * HIT_BLOCK) {
+    const uint32_t k = (uint32_t)(e / stride), j = (uint32_t)(e % stride);
+    if (j < 1 || j + 1 >= len[k]) continue;
+    const uint32_t v = path[e];
+    if (v >= n) continue;
+    const uint64_t c = (uint64_t)atomicAdd((unsigned long long *)&count[v], 1ull) + 1u;
+    if (gmax) {
+      unsigned long long *gm = (unsigned long long *)&gmax[group[v]];
+      if (c > __hip_atomic_load(gm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(gm, (unsigned long long)c);
+    }
+  }
+}
+
+// Additions of at most this many interior hits take the atomic kernel; subtractions and
+// larger calls (where hot nodes would serialise many atomics) the tiled kernels.
+constexpr uint64_t ATOMIC_MAX_HITS = 1u << 17;
+
 hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t stride,
                              uint32_t nsamp, uint32_t n, uint64_t *count, bool subtract,
                              const uint32_t *group, uint64_t *gmax, const HitScratch &hs,
                              hipStream_t stream) {
   if (nsamp == 0) return hipSuccess;
+  if (!subtract && (uint64_t)nsamp * (stride > 2 ? stride - 2 : 1) <= ATOMIC_MAX_HITS) {
+    const uint64_t entries = (uint64_t)nsamp * stride;
+    const uint32_t blocks =
+        (uint32_t)std::min<uint64_t>((entries + HIT_BLOCK - 1) / HIT_BLOCK, 1024);
+    hipLaunchKernelGGL(hit_atomic_kernel, dim3(blocks), dim3(HIT_BLOCK), 0, stream, path, len,
+                       stride, nsamp, n, count, group, gmax);
+    return hipGetLastError();
+  }
   const uint32_t tiles = (n + HIT_TILE - 1) / HIT_TILE;
   const uint32_t inner = stride > 2 ? stride - 2 : 1;  // most interior nodes of a path
   if (tiles > MAX_HIT_TILES || (uint64_t)nsamp * inner > hs.cap) return hipErrorInvalidValue;

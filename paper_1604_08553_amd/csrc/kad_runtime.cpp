@@ -1212,7 +1212,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     };
     // The first check sizes the next batch, which is launched before the batch's other
     // reductions are enqueued: enqueueing them keeps the host busy for a while.
-    if ((st = enqueue_upto(1))) return st;
+    if ((st = enqueue_upto(nch))) return st;  // every interval, before the next batch
     uint32_t next_nb = 0;
     auto launch_next = [&]() -> kad_status {
       if (launched >= omega) return KAD_OK;
@@ -1230,7 +1230,6 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       launched += next_nb;
       return KAD_OK;
     };
-    bool next_done = false;
     uint32_t c = 0, c0 = 0;
     for (; c0 < cur_nb; ++c, c0 += (uint32_t)B) {
       const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - c0);
@@ -1245,11 +1244,6 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
         rule = true;
       }
       if (stop) break;
-      if (!next_done) {
-        if ((st = launch_next())) return st;
-        next_done = true;
-      }
-      if ((st = enqueue_upto(nch))) return st;
     }
     const uint32_t used = stop ? c0 + (uint32_t)std::min<uint64_t>(B, cur_nb - c0) : cur_nb;
     if ((st = finish_batch(ctx, cur, cur_nb, used))) return st;
@@ -1261,14 +1255,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
         HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)used * stride, o.len.p + used, stride,
                                        reduced_end - used, n, ctx->count.p, true, nullptr, nullptr,
                                        hit_scratch(ctx), rs));
-      if (next_done && next_nb) {
-        if ((st = finish_batch(ctx, 1 - cur, next_nb, 0))) return st;  // drain (timing only)
-      }
       break;
     }
-    if (!next_done) {
-      if ((st = launch_next())) return st;
-    }
+    // the next batch, sized from this batch's last check: its reductions ran on an idle
+    // GPU (beside a sampler grid they wait for its last workgroups)
+    if ((st = launch_next())) return st;
     cur = 1 - cur;
     cur_nb = next_nb;
   }
