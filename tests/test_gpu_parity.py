@@ -239,9 +239,13 @@ def test_hit_counts_wide(kad, ctx, orc):
 
 def test_hit_counts_match(kad, ctx, orc):
     # er2000: short paths (hits pre-aggregated 64 samples at a time); 30x30 grid: longer
-    # paths (fewer samples per aggregation); 600-node path: paths too long to aggregate
+    # paths (fewer samples per aggregation); 600-node path: paths too long to aggregate.
+    # Calls of at most 2^17 interior hits take the one-atomic-per-hit kernel instead:
+    # er2000 with 4,096 samples, and a star whose centre lies on nearly every path (one
+    # counter under ~4,000 concurrent atomics)
     for g, cnt in [(gg.workload("er2000"), 50000), (gg.gnp(300, 0.02, 5, True), 20000),
-                   (gg.grid(30, 30), 20000), (gg.path_graph(600), 3000)]:
+                   (gg.grid(30, 30), 20000), (gg.path_graph(600), 3000),
+                   (gg.workload("er2000"), 4096), (gg.star_graph(3000), 4000)]:
         _say("hit_counts", g.name, cnt)
         G = kad.Graph(ctx, g)
         a, arcs = kad.hit_counts(ctx, G, 4, 1, 100, cnt)
