@@ -1144,10 +1144,10 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
 
   // ---- main phase (phase 1): batches of samples, a check every B samples.
   // The sampler runs on `stream`; the hit reductions and the check snapshots on the
-  // context's reduction stream, so batch b+1 is sampled while batch b is reduced and
-  // checked.  Batch b+1 is launched right after batch b's first check, sized from how
-  // far that check is from stopping; batch sizes never change the result, because the
-  // check is made at every multiple of B whatever the batches are.
+  // context's reduction stream.  Batch b+1 is launched once every check of batch b is
+  // made, sized from how far its last check is from stopping (launched earlier, its grid
+  // holds every CU while batch b's reductions wait); batch sizes never change the result,
+  // because the check is made at every multiple of B whatever the batches are.
   // All-nodes: the reduction also keeps each stopping group's largest count on the
   // device, so a check copies only those maxima.  Top-k: a check copies the counts.
   hipStream_t rs = ctx->rstream;
@@ -1210,8 +1210,6 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       }
       return KAD_OK;
     };
-    // The first check sizes the next batch, which is launched before the batch's other
-    // reductions are enqueued: enqueueing them keeps the host busy for a while.
     if ((st = enqueue_upto(nch))) return st;  // every interval, before the next batch
     uint32_t next_nb = 0;
     auto launch_next = [&]() -> kad_status {
