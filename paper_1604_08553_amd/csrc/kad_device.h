@@ -133,6 +133,17 @@ hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t
                              const uint32_t *group, uint64_t *gmax, const HitScratch &hs,
                              hipStream_t stream);
 
+// Every check interval of a batch in three launches: samples [0, nsamp) in intervals of
+// per_iv; count[v] += the interior hits, gmax[group[v]] raised, and snap[i * ngroups + g]
+// = group g's largest count after interval i (snap may be coherent pinned host memory).
+// tmp: n * (number of intervals) counters and ivmax: (number of intervals) * ngroups,
+// both all zero between calls (the kernels leave them so).
+hipError_t launch_hit_batch(const uint32_t *path, const uint32_t *len, uint32_t stride,
+                            uint32_t nsamp, uint32_t per_iv, uint32_t n, uint64_t *count,
+                            const uint32_t *group, uint64_t *gmax, uint32_t ngroups,
+                            uint32_t *tmp, uint64_t *ivmax, uint64_t *snap,
+                            hipStream_t stream);
+
 // Zero a device buffer with a kernel (no memset node when captured).
 hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream);
 // hist[c] += #{v < n : count[v] == c} for c < bins (hist zeroed by the caller)

@@ -143,6 +143,8 @@ struct kad_ctx {
   bool bins_compact = false;
   kad::PinBuf<uint32_t> h_s, h_t, h_path;
   kad::PinBuf<uint64_t> h_count;
+  kad::DevBuf<uint32_t> ivtmp;   // launch_hit_batch: hits per node and check interval
+  kad::DevBuf<uint64_t> ivmax;   // launch_hit_batch: group maxima per check interval
   std::vector<hipEvent_t> chunk_ev;
   // host scratch of kad_run, kept across calls (large fresh allocations fault in pages)
   std::vector<uint64_t> h_count0;

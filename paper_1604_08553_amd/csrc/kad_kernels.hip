@@ -2287,6 +2287,89 @@ hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t
   return hipGetLastError();
 }
 
+// Every check interval of a batch at once (launch_hit_batch).  iv_count_kernel counts
+// each node's interior hits per interval in tmp[interval * n + node]; iv_prefix_kernel
+// walks each node's intervals in order, adds its hits to its count and raises the
+// interval's group maximum to the count the node reached there (clearing tmp);
+// iv_snap_kernel takes, per group, the running maximum over the intervals starting from
+// the maximum before the batch -- a group's largest count after interval c is that of a
+// node hit by then (its count at its last hit) or the earlier maximum -- and writes one
+// snapshot per interval (clearing the per-interval maxima).
+__global__ __launch_bounds__(HIT_BLOCK) void iv_count_kernel(const uint32_t *path,
+                                                             const uint32_t *len,
+                                                             uint32_t stride, uint32_t nsamp,
+                                                             uint32_t per_iv, uint32_t n,
+                                                             uint32_t *tmp) {
+  const uint64_t entries = (uint64_t)nsamp * stride;
+  for (uint64_t e = (uint64_t)blockIdx.x * HIT_BLOCK + threadIdx.x; e < entries;
+       e += (uint64_t)gridDim.x * HIT_BLOCK) {
+    const uint32_t k = (uint32_t)(e / stride), j = (uint32_t)(e % stride);
+    if (j < 1 || j + 1 >= len[k]) continue;
+    const uint32_t v = path[e];
+    if (v < n) atomicAdd(&tmp[(size_t)(k / per_iv) * n + v], 1u);
+  }
+}
+
+__global__ __launch_bounds__(HIT_BLOCK) void iv_prefix_kernel(uint32_t n, uint32_t niv,
+                                                              uint32_t *tmp, uint64_t *count,
+                                                              const uint32_t *group,
+                                                              uint32_t ngroups,
+                                                              uint64_t *ivmax) {
+  for (uint32_t v = blockIdx.x * HIT_BLOCK + threadIdx.x; v < n; v += gridDim.x * HIT_BLOCK) {
+    uint64_t c = 0;
+    bool hit = false;
+    for (uint32_t q = 0; q < niv; ++q) {
+      const uint32_t h = tmp[(size_t)q * n + v];
+      if (h == 0) continue;
+      if (!hit) c = count[v];
+      hit = true;
+      tmp[(size_t)q * n + v] = 0;
+      c += h;
+      unsigned long long *m = (unsigned long long *)&ivmax[(size_t)q * ngroups + group[v]];
+      if (c > __hip_atomic_load(m, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT))
+        atomicMax(m, (unsigned long long)c);
+    }
+    if (hit) count[v] = c;
+  }
+}
+
+__global__ __launch_bounds__(HIT_BLOCK) void iv_snap_kernel(uint32_t niv, uint32_t ngroups,
+                                                            uint64_t *ivmax, uint64_t *gmax,
+                                                            uint64_t *snap) {
+  for (uint32_t g = blockIdx.x * HIT_BLOCK + threadIdx.x; g < ngroups;
+       g += gridDim.x * HIT_BLOCK) {
+    uint64_t m = gmax[g];
+    for (uint32_t q = 0; q < niv; ++q) {
+      const size_t i = (size_t)q * ngroups + g;
+      m = max(m, ivmax[i]);
+      ivmax[i] = 0;
+      snap[i] = m;
+    }
+    gmax[g] = m;
+  }
+}
+
+hipError_t launch_hit_batch(const uint32_t *path, const uint32_t *len, uint32_t stride,
+                            uint32_t nsamp, uint32_t per_iv, uint32_t n, uint64_t *count,
+                            const uint32_t *group, uint64_t *gmax, uint32_t ngroups,
+                            uint32_t *tmp, uint64_t *ivmax, uint64_t *snap,
+                            hipStream_t stream) {
+  if (nsamp == 0) return hipSuccess;
+  if (per_iv == 0 || !group || !gmax || !tmp || !ivmax || !snap) return hipErrorInvalidValue;
+  const uint32_t niv = (nsamp + per_iv - 1) / per_iv;
+  const uint64_t entries = (uint64_t)nsamp * stride;
+  const uint32_t b1 = (uint32_t)std::min<uint64_t>((entries + HIT_BLOCK - 1) / HIT_BLOCK, 4096);
+  hipLaunchKernelGGL(iv_count_kernel, dim3(b1), dim3(HIT_BLOCK), 0, stream, path, len, stride,
+                     nsamp, per_iv, n, tmp);
+  const uint32_t b2 = std::min<uint32_t>((n + HIT_BLOCK - 1) / HIT_BLOCK, 4096);
+  hipLaunchKernelGGL(iv_prefix_kernel, dim3(b2), dim3(HIT_BLOCK), 0, stream, n, niv, tmp, count,
+                     group, ngroups, ivmax);
+  const uint32_t b3 = std::max<uint32_t>(1, std::min<uint32_t>((ngroups + HIT_BLOCK - 1) / HIT_BLOCK, 1024));
+  hipLaunchKernelGGL(iv_snap_kernel, dim3(b3), dim3(HIT_BLOCK), 0, stream, niv, ngroups, ivmax,
+                     gmax, snap);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream) {
   if (count == 0) return hipSuccess;
   const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 65536);

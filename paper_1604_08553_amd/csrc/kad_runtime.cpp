@@ -1174,6 +1174,17 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   }
   PinBuf<uint64_t> snaps;  // one snapshot per check of the current batch
   HIP_TRY(snaps.ensure(snap * chunks_per_batch));
+  // All-nodes runs reduce a batch's check intervals together (launch_hit_batch) when the
+  // per-interval hit counters fit 256 MiB; its scratch is cleared here, beside the pilot.
+  const bool batch_reduce = by_group && chunks_per_batch >= 2 &&
+                            (uint64_t)n * chunks_per_batch * 4 <= (256ull << 20);
+  if (batch_reduce) {
+    HIP_TRY(ctx->ivtmp.ensure((size_t)n * chunks_per_batch));
+    HIP_TRY(ctx->ivmax.ensure((size_t)chunks_per_batch * ngroups));
+    HIP_TRY(kad::launch_zero_u32(ctx->ivtmp.p, (uint64_t)n * chunks_per_batch, rs));
+    HIP_TRY(kad::launch_zero_u32(reinterpret_cast<uint32_t *>(ctx->ivmax.p),
+                                 (uint64_t)chunks_per_batch * ngroups * 2, rs));
+  }
   while (ctx->chunk_ev.size() < chunks_per_batch) {
     hipEvent_t e;
     HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
@@ -1210,7 +1221,16 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       }
       return KAD_OK;
     };
-    if ((st = enqueue_upto(nch))) return st;  // every interval, before the next batch
+    if (batch_reduce) {  // every interval in three launches; all snapshots land together
+      HIP_TRY(kad::launch_hit_batch(o.path.p, o.len.p, stride, cur_nb, (uint32_t)B, n,
+                                    ctx->count.p, ctx->group.p, ctx->gmax.p, (uint32_t)ngroups,
+                                    ctx->ivtmp.p, ctx->ivmax.p, snaps.p, rs));
+      for (uint32_t q = 0; q < nch; ++q) HIP_TRY(hipEventRecord(ctx->chunk_ev[q], rs));
+      HIP_TRY(hipEventRecord(ctx->outs[cur].reduced, rs));
+      queued = nch;
+    } else if ((st = enqueue_upto(nch))) {  // every interval, before the next batch
+      return st;
+    }
     uint32_t next_nb = 0;
     auto launch_next = [&]() -> kad_status {
       if (launched >= omega) return KAD_OK;
