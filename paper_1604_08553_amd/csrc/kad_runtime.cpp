@@ -1195,6 +1195,28 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     return (uint64_t)std::min<double>(q, (double)(K / B)) * B;
   };
 
+  // The final counts come back in parts, each with its event, so that the host's pass
+  // over the nodes (after the loop) starts on the first part while the others are in
+  // flight; they are enqueued as soon as the stopping point is known.
+  constexpr uint32_t OUT_PARTS = 4;
+  while (ctx->chunk_ev.size() < OUT_PARTS) {
+    hipEvent_t e;
+    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    ctx->chunk_ev.push_back(e);
+  }
+  uint32_t part_lo[OUT_PARTS + 1];
+  for (uint32_t q = 0; q <= OUT_PARTS; ++q) part_lo[q] = (uint32_t)((uint64_t)n * q / OUT_PARTS);
+  auto enqueue_count_copy = [&]() -> kad_status {
+    for (uint32_t q = 0; q < OUT_PARTS; ++q) {
+      if (part_lo[q + 1] > part_lo[q])
+        HIP_TRY(hipMemcpyAsync(ctx->h_count.p + part_lo[q], ctx->count.p + part_lo[q],
+                               (size_t)(part_lo[q + 1] - part_lo[q]) * 8, hipMemcpyDeviceToHost,
+                               rs));
+      HIP_TRY(hipEventRecord(ctx->chunk_ev[q], rs));
+    }
+    return KAD_OK;
+  };
+
   uint64_t tau = 0, arcs = 0, launched = first_nb;
   bool rule = false, stop = false;
   int cur = first_set;
@@ -1264,39 +1286,25 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       if (stop) break;
     }
     const uint32_t used = stop ? c0 + (uint32_t)std::min<uint64_t>(B, cur_nb - c0) : cur_nb;
-    if ((st = finish_batch(ctx, cur, cur_nb, used))) return st;
-    for (uint32_t k = 0; k < used; ++k) arcs += ctx->outs[cur].h_arcs.p[k];
+    // the GPU's next work first, then this batch's host accounting (its flags and arcs)
     if (stop) {
-      // undo the reductions enqueued past the stopping point
+      // undo the reductions enqueued past the stopping point; the counts go home
       const uint32_t reduced_end = (uint32_t)std::min<uint64_t>((uint64_t)queued * B, cur_nb);
       if (used < reduced_end)
         HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)used * stride, o.len.p + used, stride,
                                        reduced_end - used, n, ctx->count.p, true, nullptr, nullptr,
                                        hit_scratch(ctx), rs));
-      break;
+      if ((st = enqueue_count_copy())) return st;
+    } else {
+      // the next batch, sized from this batch's last check: its reductions ran on an
+      // idle GPU (beside a sampler grid they wait for its last workgroups)
+      if ((st = launch_next())) return st;
     }
-    // the next batch, sized from this batch's last check: its reductions ran on an idle
-    // GPU (beside a sampler grid they wait for its last workgroups)
-    if ((st = launch_next())) return st;
+    if ((st = finish_batch(ctx, cur, cur_nb, used))) return st;
+    for (uint32_t k = 0; k < used; ++k) arcs += ctx->outs[cur].h_arcs.p[k];
+    if (stop) break;
     cur = 1 - cur;
     cur_nb = next_nb;
-  }
-  // The final counts come back in parts, each with its event, so that the host's pass
-  // over the nodes (below) starts on the first part while the others are in flight.
-  constexpr uint32_t OUT_PARTS = 4;
-  while (ctx->chunk_ev.size() < OUT_PARTS) {
-    hipEvent_t e;
-    HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
-    ctx->chunk_ev.push_back(e);
-  }
-  uint32_t part_lo[OUT_PARTS + 1];
-  for (uint32_t q = 0; q <= OUT_PARTS; ++q) part_lo[q] = (uint32_t)((uint64_t)n * q / OUT_PARTS);
-  HIP_TRY(wait_stream(ctx, rs));  // the last reduction (the sampler time ends here)
-  for (uint32_t q = 0; q < OUT_PARTS; ++q) {
-    if (part_lo[q + 1] > part_lo[q])
-      HIP_TRY(hipMemcpyAsync(ctx->h_count.p + part_lo[q], ctx->count.p + part_lo[q],
-                             (size_t)(part_lo[q + 1] - part_lo[q]) * 8, hipMemcpyDeviceToHost, rs));
-    HIP_TRY(hipEventRecord(ctx->chunk_ev[q], rs));
   }
   HIP_TRY(wait_stream(ctx, stream));
   if (overlap) HIP_TRY(wait_stream(ctx, b1_stream));
