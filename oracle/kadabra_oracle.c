@@ -15,9 +15,12 @@
  * Parity status: every function below is pinned by a test against something
  * other than itself (numpy's Philox, Python integers, networkx shortest-path
  * counts and betweenness, closed forms, the paper's printed tables, exact
- * transition probabilities, the derivation's quadratic identities); the one
- * exception is the stopping time tau of a full run, which the paper pins only
- * through Theorem 1 (tested statistically) -- "parity unpinned" for tau itself.
+ * transition probabilities, the derivation's quadratic identities, arcs
+ * scanned derived by hand from section 4's side rule on small gadgets, hand-
+ * worked cases of Algorithm 3 and of section 5's half-widths).  The stopping
+ * time tau of a whole run is pinned where it has a closed form (complete
+ * graphs: every count is zero, so tau is the first check at which g(0) falls
+ * to lambda) and elsewhere through Theorem 1's guarantee, tested over 200 seeds.
  */
 #include <math.h>
 #include <stdint.h>

@@ -416,13 +416,16 @@ def test_epsilon_guarantee_er2000(oracle_lib):
     g = oracle_lib.Graph(gg.workload("er2000"))
     bc = oracle_lib.brandes(g)
     bad_eps = bad_cov = 0
-    runs = 24
+    runs = 200
     for seed in range(1, runs + 1):
         r = oracle_lib.run(g, 0.01, 0.1, seed=seed, threads=8)
         if np.max(np.abs(r["bc"] - bc)) > 0.01:
             bad_eps += 1
         if not np.all((r["lower"] <= bc) & (bc <= r["upper"])):
             bad_cov += 1
+    # the theorem allows a fraction delta of failing runs; the bounds are loose, so in
+    # practice none fails
+    assert bad_eps <= 0.1 * runs and bad_cov <= 0.1 * runs
     assert bad_eps <= 2 and bad_cov <= 2
 
 
@@ -439,3 +442,311 @@ def test_topk_run_finds_true_top(oracle_lib):
     true_rank[np.argsort(-bc, kind="stable")] = np.arange(1, g.n + 1)
     for v in reported:
         assert rlo[v] <= true_rank[v] <= rhi[v]
+
+
+# ----------------------------------------------------------------------------- arcs scanned and the side rule
+#
+# Section 4: the side whose frontier has the smaller degree sum is expanded (out-degrees
+# on the s side, in-degrees on the t side of a directed graph; ties expand s), a level is
+# always processed whole, and every arc of an expanded level counts as one visited edge.
+# On the small gadgets below the arcs of a pair follow from that rule by hand; each
+# derivation is written next to its expected value.
+
+
+def _pair_samples(oracle_lib, g, want, seed=3, count=40000):
+    """Sample ids whose (s, t) is one of the pairs in ``want``; every pair must occur."""
+    S = oracle_lib.sample_paths(g, seed, 1, 0, count, threads=4)
+    seen = {}
+    for k in range(count):
+        key = (int(S.s[k]), int(S.t[k]))
+        if key in want:
+            seen.setdefault(key, []).append(k)
+    assert set(seen) == set(want), sorted(set(want) - set(seen))
+    return S, seen
+
+
+def _gadget_directed_tie(k=6, r=3):
+    """s=0 -> m=2 and s -> p_1..p_k (no out-arcs); m -> t=1; q_1..q_k -> t; every r_j -> every
+    q_i.  out(s) = k+1 = in(t): a tie."""
+    m, p0, q0, r0 = 2, 3, 3 + k, 3 + 2 * k
+    n = r0 + r
+    src = [0, m] + [0] * k + list(range(q0, q0 + k))
+    dst = [m, 1] + list(range(p0, p0 + k)) + [1] * k
+    for j in range(r):
+        for i in range(k):
+            src.append(r0 + j)
+            dst.append(q0 + i)
+    return gg.csr_from_edges(n, src, dst, True, name="tie_gadget"), dict(k=k, r=r, m=m, p0=p0,
+                                                                            q0=q0, r0=r0)
+
+
+def test_arcs_side_rule_directed_gadget(oracle_lib):
+    g, P = _gadget_directed_tie()
+    k, r, m, q0, r0, p0 = P["k"], P["r"], P["m"], P["q0"], P["r0"], P["p0"]
+    want = {
+        # D_S = out(s) = k+1 <= D_T = in(t) = k+1: expand s (k+1 arcs); its next level {m, p_*}
+        # has out-degree sum 1 < k+1: expand it (1 arc, m -> t touches).  k+2 arcs.  Expanding
+        # t first ("<") would cost in(t) = k+1, then the s level k+1 again: 2k+2.
+        (0, 1): (k + 2, [0, m, 1]),
+        # out(1) = 0 <= in(0) = 0: the s side is expanded and gains no node: disconnected.
+        (1, 0): (0, []),
+        # (m, t): out(m) = 1 <= 7: one arc, m -> t touches.
+        (m, 1): (1, [m, 1]),
+        # (p, t): out(p) = 0: the s side closes at once.
+        (p0, 1): (0, []),
+        # (s, q): in(q) = r < out(s) = k+1: expand q's in-row (r arcs) -> {r_*}, whose in-degree
+        # sum is 0 < k+1: expanded again with no arcs and no node: disconnected after r arcs.
+        (0, q0): (r, []),
+    }
+    # (r_j, t): out(r_j) = k <= in(t) = k+1: k arcs to the q's, whose out-degree sum k <= k+1:
+    # expanded, k arcs, each q_i -> t touches.  2k arcs; the path is r_j, one q_i, t.
+    for j in range(r):
+        want[(r0 + j, 1)] = (2 * k, None)
+    S, seen = _pair_samples(oracle_lib, g, want)
+    for pair, ids in seen.items():
+        arcs, path = want[pair]
+        for i in ids:
+            assert int(S.arcs[i]) == arcs, (pair, int(S.arcs[i]), arcs)
+            got = [int(x) for x in S.path(i)]
+            if path is not None:
+                assert got == path, (pair, got)
+            else:
+                assert len(got) == 3 and q0 <= got[1] < q0 + k, (pair, got)
+
+
+def test_arcs_whole_level_undirected_gadget(oracle_lib):
+    """0-1, 0-2, 1-3, 2-{4..8}, 3-{9..12}: degrees 0:2, 1:2, 2:6, 3:5, leaves 1."""
+    src = [0, 0, 1] + [2] * 5 + [3] * 4
+    dst = [1, 2, 3] + list(range(4, 9)) + list(range(9, 13))
+    g = gg.csr_from_edges(13, src, dst, False, name="level_gadget")
+    want = {
+        # (0, 3): 2 <= 5: expand 0 (2 arcs) -> {1, 2}, sum 8 > 5: expand 3 -- its whole row of 5
+        # arcs, although the first (3 -> 1) already touches.  7 arcs (3 if the level were cut
+        # at the first touching arc).
+        (0, 3): (7, [0, 1, 3]),
+        # (3, 0): 5 > 2: expand 0's row (2 arcs) -> {1, 2}, sum 8 > 5: expand 3 (5 arcs).  7.
+        (3, 0): (7, [3, 1, 0]),
+        # (4, 9): 1 <= 1: expand 4 (1 arc) -> {2}, sum 6 > 1: expand 9 (1) -> {3}, 5 < 6: expand
+        # 3 (5 arcs) -> {1, 10, 11, 12}, sum 5 < 6: expand (5 arcs) -> {0}, 2 < 6: expand 0
+        # (2 arcs; 0 -> 2 touches).  1+1+5+5+2 = 14 arcs, path 4, 2, 0, 1, 3, 9.
+        (4, 9): (14, [4, 2, 0, 1, 3, 9]),
+        # (1, 2): 2 <= 6: expand 1 (2 arcs) -> {0, 3}, sum 7 > 6: expand 2 (6 arcs; 2 -> 0
+        # touches).  8 arcs.
+        (1, 2): (8, [1, 0, 2]),
+    }
+    S, seen = _pair_samples(oracle_lib, g, want)
+    for pair, ids in seen.items():
+        arcs, path = want[pair]
+        for i in ids:
+            assert int(S.arcs[i]) == arcs, (pair, int(S.arcs[i]), arcs)
+            assert [int(x) for x in S.path(i)] == path, (pair, S.path(i))
+
+
+def test_arcs_star_and_path_closed_forms(oracle_lib):
+    # star, centre 0: leaf-leaf 1 <= 1 expands the s leaf (1 arc) -> {0}, n-1 > 1: the t
+    # leaf's arc touches (1): 2 arcs; a pair with the centre: the leaf's one arc: 1 arc
+    n = 9
+    g = gg.star_graph(n)
+    S = oracle_lib.sample_paths(g, 2, 1, 0, 3000)
+    for i in range(3000):
+        s, t = int(S.s[i]), int(S.t[i])
+        assert int(S.arcs[i]) == (1 if 0 in (s, t) else 2), (s, t)
+    # path P_n, a pair at distance L >= 2 of nodes L away from both ends: the frontiers
+    # have degree sums 2 at level 0 and 4 later, always tied, so the sides alternate s, t,
+    # s, t, ...: 2 + 2 + 4 (L - 2) arcs; L = 1: one expansion of 2 arcs
+    n = 40
+    g = gg.path_graph(n)
+    S = oracle_lib.sample_paths(g, 8, 1, 0, 20000, threads=4)
+    checked = 0
+    for i in range(20000):
+        s, t = int(S.s[i]), int(S.t[i])
+        L = abs(s - t)
+        if min(s, t) >= L and max(s, t) <= n - 1 - L:
+            assert int(S.arcs[i]) == (2 if L == 1 else 4 * L - 4), (s, t)
+            checked += 1
+    assert checked > 2000
+
+
+# ----------------------------------------------------------------------------- tau on K_n
+#
+# On a complete graph every pair is adjacent, so no path has an interior node: the pilot
+# and main counts are all zero.  computeDelta then gives c_L = c_U = 0, exp(-C/0) = 0 and
+# delta_L = delta_U = eps * delta / (2n) for every node, i.e. L = ln(2n / (eps * delta)).
+# f(0) = 0 exactly, and g(0) = (2L/tau)(1/3 + omega/tau): the run stops at the first
+# multiple of the check interval B where that is <= lambda (VD = 2, so
+# omega = ceil(c/lambda^2 (1 + ln(2/delta)))), or at omega.
+
+
+def _kn_tau(n, lam, delta=0.1, eps=0.001, c=0.5):
+    om = math.ceil(c / lam ** 2 * (1 + math.log(2 / delta)))
+    b = 1
+    while b * 2 <= om // 16:
+        b *= 2
+    B = min(max(b, 1024), 65536)
+    L = math.log(2.0 * n / (eps * delta))
+    tau = B
+    while tau < om:
+        if 2 * L / tau * (1 / 3 + om / tau) <= lam:
+            return tau, om, 1
+        tau += B
+    return om, om, 0
+
+
+@pytest.mark.parametrize("n,lam", [(20, 0.01), (30, 0.02), (12, 0.005), (50, 0.015), (8, 0.03),
+                                   (10, 0.05)])
+def test_run_complete_graph_tau_closed_form(oracle_lib, n, lam):
+    tau, om, rule = _kn_tau(n, lam)
+    r = oracle_lib.run(gg.complete_graph(n), lam, 0.1, seed=3)
+    assert r["vd"] == 2 and r["omega"] == om
+    assert int(r["count"].sum()) == 0 and int(r["count0"].sum()) == 0
+    assert r["tau"] == tau and r["stop_rule"] == rule
+    L = math.log(2.0 * n / (0.001 * 0.1))
+    assert np.allclose(r["L_l"], L, rtol=1e-12) and np.allclose(r["L_u"], L, rtol=1e-12)
+    if rule:
+        assert np.all(r["lower"] == 0.0)   # f(0) = 0
+        g0 = 2 * L / tau * (1 / 3 + om / tau)
+        assert np.allclose(r["upper"], g0, rtol=1e-12)
+    else:                                  # omega reached: [b - lambda, b + lambda]
+        assert np.all(r["lower"] == -lam) and np.all(r["upper"] == lam)
+    assert (10, 0.05) != (n, lam) or (rule == 0 and tau == om)   # omega < B: stops at omega
+
+
+# ----------------------------------------------------------------------------- Algorithm 3
+#
+# Hand cases of the top-k stopping condition (appendix, Algorithm 3) with n = 6.  Positions
+# v_1..v_6 are given in decreasing order of the estimate; node ids are scrambled.  A node
+# is "narrow" (L = 1e-3: f, g about 2e-4 <= lambda = 0.01) or "wide" (L = 20 or 12:
+# f, g about 0.02 > lambda).  Each case first checks that its intervals are laid out as
+# described, then the decision written from the algorithm.
+
+_A3_OM, _A3_TAU, _A3_LAM = 1_000_000, 100_000, 0.01
+_A3_IDS = [4, 0, 5, 2, 1, 3]   # node id of position v_1..v_6
+_N, _W = 1e-3, 20.0
+
+
+def _alg3(oracle_lib, spec, k):
+    """spec: (count, L) of v_1..v_6.  Returns (decision, lower[pos], upper[pos], wide[pos])."""
+    n = len(spec)
+    cnt = np.zeros(n, dtype=np.uint64)
+    L = np.zeros(n)
+    for pos, (c, l) in enumerate(spec):
+        cnt[_A3_IDS[pos]] = c
+        L[_A3_IDS[pos]] = l
+    lo, hi, wide = [], [], []
+    for c, l in spec:
+        b = c / _A3_TAU
+        f = oracle_lib.f(b, l, _A3_OM, _A3_TAU)
+        g = oracle_lib.g(b, l, _A3_OM, _A3_TAU)
+        lo.append(b - f)
+        hi.append(b + g)
+        wide.append(f > _A3_LAM or g > _A3_LAM)
+    return oracle_lib.stop_topk(cnt, k, _A3_TAU, _A3_OM, _A3_LAM, L, L), lo, hi, wide
+
+
+def test_alg3_all_narrow_stops_even_when_overlapping(oracle_lib):
+    tail = [(10000, _N), (5000, _N), (1000, _N)]
+    d, lo, hi, wide = _alg3(oracle_lib, [(20000, _N), (15000, _N), (12000, _N)] + tail, 2)
+    assert not any(wide) and d
+    # f, g <= lambda at every node: no separation test is made, so overlaps do not matter
+    d, lo, hi, wide = _alg3(oracle_lib, [(20000, _N), (19990, _N), (19980, _N)] + tail, 2)
+    assert lo[0] < hi[1] and lo[1] < hi[2] and not any(wide)
+    assert d
+
+
+def test_alg3_previous_neighbour(oracle_lib):
+    # v_2 wide, its interval reaches above b(v_1) - f(v_1) (the i-1 test fails) but stays
+    # above v_3's (the i+1 test passes): no stop
+    spec = [(17600, _N), (15000, _W), (12000, _N), (10000, _N), (5000, _N), (1000, _N)]
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 2)
+    assert wide == [False, True, False, False, False, False]
+    assert lo[0] < hi[1] and lo[1] >= hi[2]
+    assert not d
+    # the same with v_1 far above: stop
+    spec[0] = (20000, _N)
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 2)
+    assert lo[0] >= hi[1] and lo[1] >= hi[2] and d
+
+
+def test_alg3_next_neighbour(oracle_lib):
+    # v_1 wide (there is no v_0, whose test never fails) overlapping v_2 below: no stop
+    spec = [(20000, _W), (17500, _N), (12000, _N), (10000, _N), (5000, _N), (1000, _N)]
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 2)
+    assert wide[0] and not any(wide[1:]) and lo[0] < hi[1]
+    assert not d
+    spec[1] = (15000, _N)
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 2)
+    assert lo[0] >= hi[1] and d
+
+
+def test_alg3_nodes_below_k_against_v_k(oracle_lib):
+    # top two narrow and separated; v_4 (i > k) wide and reaching above b(v_k) - f(v_k): no stop
+    spec = [(20000, _N), (15000, _N), (14000, _N), (13500, _W), (5000, _N), (1000, _N)]
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 2)
+    assert wide == [False, False, False, True, False, False]
+    assert lo[0] >= hi[1] and hi[3] > lo[1]
+    assert not d
+    # v_4's upper end between b(v_3) - f(v_3) and b(v_2) - f(v_2): the test is against v_k
+    # (= v_2), so it passes (against v_{k+1} it would not): stop
+    spec = [(20000, _N), (15000, _N), (14800, _N), (13000, 12.0), (5000, _N), (1000, _N)]
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 2)
+    assert wide == [False, False, False, True, False, False]
+    assert lo[2] < hi[3] <= lo[1]
+    assert d
+
+
+def test_alg3_last_position_has_no_successor(oracle_lib):
+    # k = n: v_6 wide (L = 40); separated from v_5 it does not block the stop (there is no v_7)
+    spec = [(20000, _N), (15000, _N), (12000, _N), (10000, _N), (5000, _N), (1000, 40.0)]
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 6)
+    assert wide[5] and lo[4] >= hi[5] and d
+    spec[5] = (4000, _W)
+    d, lo, hi, wide = _alg3(oracle_lib, spec, 6)
+    assert wide[5] and lo[4] < hi[5] and not d
+
+
+# ----------------------------------------------------------------------------- top-k half-widths
+#
+# Section 5: pilot estimates b0 sorted decreasingly give v_1..v_n; for i <= k,
+# lambda_U(v_i) = (b0(v_{i-1}) - b0(v_i))/2 (1 for v_1) and lambda_L(v_i) =
+# (b0(v_i) - b0(v_{i+1}))/2 (1 when there is no v_{i+1}); a gap b0(v_i) - b0(v_{i+1}) < 2
+# lambda for i <= k sets all four values of v_i and v_{i+1} to lambda; for i > k,
+# lambda_L = 1 and lambda_U = b0(v_k) - lambda_L(v_k) - b0(v_i); every value is clamped to
+# [lambda, 1].  Expected arrays below are worked by hand (per position v_1..v_6).
+
+
+def _topk_case(oracle_lib, counts_by_pos, k, alpha, lam, ids):
+    n = len(counts_by_pos)
+    c0 = np.zeros(n, dtype=np.uint64)
+    for pos, c in enumerate(counts_by_pos):
+        c0[ids[pos]] = c
+    ll, lu = oracle_lib.topk_lambdas(c0, k, alpha, lam)
+    return [float(ll[ids[p]]) for p in range(n)], [float(lu[ids[p]]) for p in range(n)]
+
+
+def test_topk_lambdas_hand_worked(oracle_lib):
+    ids = [3, 0, 5, 1, 4, 2]
+    # b0 = 0.80, 0.60, 0.59, 0.58, 0.30, 0.00; lambda = 0.05, k = 2.  Gap v_1-v_2 = 0.20
+    # (no tie); gap v_2-v_3 = 0.01 < 0.10: v_2 and v_3 get (0.05, 0.05).  v_1: lambda_L =
+    # 0.10, lambda_U = 1.  b0(v_k) - lambda_L(v_k) = 0.60 - 0.05 = 0.55, so v_4: 0.55 - 0.58 =
+    # -0.03, clamped to 0.05; v_5: 0.25; v_6: 0.55; all of them lambda_L = 1.
+    ll, lu = _topk_case(oracle_lib, [80, 60, 59, 58, 30, 0], 2, 100, 0.05, ids)
+    assert np.allclose(ll, [0.10, 0.05, 0.05, 1.0, 1.0, 1.0], atol=1e-12, rtol=0)
+    assert np.allclose(lu, [1.0, 0.05, 0.05, 0.05, 0.25, 0.55], atol=1e-12, rtol=0)
+    # b0 = 0.80, 0.72, 0.50, 0.20, 0.10, 0.05; lambda = 0.05, k = 2.  Gap v_1-v_2 = 0.08 lies
+    # between lambda and 2 lambda: a tie, v_1 and v_2 get (0.05, 0.05); gap v_2-v_3 = 0.22.
+    # 0.72 - 0.05 = 0.67: v_3..v_6 get lambda_U = 0.17, 0.47, 0.57, 0.62.
+    ll, lu = _topk_case(oracle_lib, [80, 72, 50, 20, 10, 5], 2, 100, 0.05, ids)
+    assert np.allclose(ll, [0.05, 0.05, 1.0, 1.0, 1.0, 1.0], atol=1e-12, rtol=0)
+    assert np.allclose(lu, [0.05, 0.05, 0.17, 0.47, 0.57, 0.62], atol=1e-12, rtol=0)
+    # k = n = 3, b0 = 0.5, 0.3, 0.1 (alpha 10), lambda 0.05: no tie; v_3 has no successor
+    ll, lu = _topk_case(oracle_lib, [5, 3, 1], 3, 10, 0.05, [2, 0, 1])
+    assert np.allclose(ll, [0.1, 0.1, 1.0], atol=1e-12, rtol=0)
+    assert np.allclose(lu, [1.0, 0.1, 0.1], atol=1e-12, rtol=0)
+    # equal pilot counts are ordered by id: nodes 1 and 4 both at 0.6 (gap 0 < 2 lambda:
+    # tied), node 1 is v_2 (k = 2) and node 4 is v_3
+    c0 = np.array([90, 60, 10, 0, 60], dtype=np.uint64)
+    ll, lu = oracle_lib.topk_lambdas(c0, 2, 100, 0.05)
+    assert np.allclose([ll[0], lu[0]], [0.15, 1.0], atol=1e-12, rtol=0)
+    assert np.allclose([ll[1], lu[1], ll[4], lu[4]], [0.05] * 4, atol=1e-12, rtol=0)
+    # b0(v_k) - lambda_L(v_k) = 0.55: node 2 (0.10) gets 0.45, node 3 (0.00) 0.55
+    assert np.allclose([ll[2], lu[2], ll[3], lu[3]], [1.0, 0.45, 1.0, 0.55], atol=1e-12, rtol=0)
