@@ -32,7 +32,11 @@ Prints one JSON line.  value = sampled shortest paths per second over the timed 
 (pilot + main-phase samples that enter the result; samples computed past the stopping
 point of the last batch are not counted).  roofline = the sampler kernel's algorithmic
 bytes per launch over its event-timed average launch duration, against 8 TB/s.
-cpu_baseline = the CPU oracle on a bounded sample of the same workload.
+cpu_baseline = the CPU oracle beside it: for cl1m and er2000 its whole adaptive run on the
+same graph and parameters (time to epsilon, paths/s, and whether its result equals the
+GPU's), plus its one-thread sampling rate; for the other workloads its sampling rate on
+a bounded prefix of sample ids.  time_to_epsilon_cold_s = a graph registered anew and its
+first run (vertex diameter included) on the warm context.
 """
 import argparse
 import json
@@ -69,14 +73,61 @@ def algorithmic_bytes(arcs, nodes, hits):
     return 4.125 * arcs + 26.0 * nodes + 4.0 * hits
 
 
-def cpu_baseline(csr, samples, seed):
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def host_threads():
+    return int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+
+
+def cpu_baseline_run(csr, kw, gpu, one_thread_samples):
+    """The oracle's whole adaptive run on the same graph and parameters (all host threads):
+    its time to epsilon and sampling rate, and whether its result equals the GPU's; plus the
+    oracle's sampling rate on one thread over a prefix of main-phase ids."""
+    import numpy as np
     import oracle
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or os.cpu_count() or 1
+    threads = host_threads()
+    okw = {k: v for k, v in kw.items() if k != "kernel_batch"}
+    t0 = time.perf_counter()
+    r = oracle.run(csr, threads=threads, **okw)
+    dt = time.perf_counter() - t0
+    parity = bool(r["tau"] == gpu["tau"] and r["stop_rule"] == gpu["stop_reason"]
+                  and r["arcs"] == gpu["arcs_scanned"]
+                  and np.array_equal(r["count"], gpu["count"])
+                  and np.array_equal(r["lower"], gpu["lower"])
+                  and np.array_equal(r["upper"], gpu["upper"]))
+    paths = r["alpha"] + r["tau"]
+    t1 = time.perf_counter()
+    S = oracle.sample_paths(csr, kw["seed"], 1, 0, one_thread_samples, threads=1)
+    dt1 = time.perf_counter() - t1
+    return {"value": paths / dt, "unit": "sampled shortest paths/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(),
+            "time_to_epsilon_s": dt, "gteps": (r["arcs"] + r["pilot_arcs"]) / dt / 1e9,
+            "parity": parity, "tau": int(r["tau"]),
+            "one_thread": {"value": one_thread_samples / dt1, "unit": "sampled shortest paths/s",
+                           "gteps": float(S.arcs.sum()) / dt1 / 1e9,
+                           "sample": f"main-phase ids 0..{one_thread_samples - 1}"},
+            "sample": f"the oracle's whole adaptive run on the same graph and parameters "
+                      f"(vertex diameter, pilot, computeDelta, {paths} samples; {dt:.1f} s), "
+                      "all host threads; result compared with the GPU's"}
+
+
+def cpu_baseline(csr, samples, seed):
+    """The oracle's sampling rate over main-phase ids [0, samples) (all host threads)."""
+    import oracle
+    threads = host_threads()
     t0 = time.perf_counter()
     S = oracle.sample_paths(csr, seed, 1, 0, samples, threads=threads)
     dt = time.perf_counter() - t0
     return {"value": samples / dt, "unit": "sampled shortest paths/s", "cores": threads,
-            "kind": "oracle", "gteps": float(S.arcs.sum()) / dt / 1e9,
+            "kind": "oracle", "cpu_model": cpu_model(), "gteps": float(S.arcs.sum()) / dt / 1e9,
             "sample": f"oracle sample_paths: main-phase ids 0..{samples - 1}, seed {seed}, "
                       f"same graph ({dt:.1f} s)"}
 
@@ -317,7 +368,13 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-batch", type=int, default=65536)
     ap.add_argument("--check-interval", type=int, default=0)
-    ap.add_argument("--cpu-samples", type=int, default=150000)
+    ap.add_argument("--cpu-samples", type=int, default=150000,
+                    help="oracle sampling-rate baseline: main-phase ids (--no-cpu-full-run)")
+    ap.add_argument("--cpu-full-run", dest="cpu_full_run", action="store_true", default=None,
+                    help="baseline = the oracle's whole adaptive run (default for cl1m, er2000)")
+    ap.add_argument("--no-cpu-full-run", dest="cpu_full_run", action="store_false")
+    ap.add_argument("--cpu-one-thread", type=int, default=4000,
+                    help="main-phase ids the one-thread oracle rate is measured on")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--queries", type=int, default=1000, help="serve: queries in the stream")
     ap.add_argument("--rate", type=float, default=20.0, help="serve: arrivals per second")
@@ -336,6 +393,8 @@ def main():
         args.mode = "topk" if args.workload == "dcl4m" else "all"
     if args.workload == "dcl4m":
         args.autotune = True
+    if args.cpu_full_run is None:
+        args.cpu_full_run = args.workload in ("cl1m", "er2000")
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path "
               "(samples would shard across GPUs with one all-reduce of the counters per "
@@ -366,7 +425,9 @@ def main():
     gen_s = time.perf_counter() - t0
     print(f"[bench] graph {csr.name}: n={csr.n} arcs={csr.arcs} ({gen_s:.1f} s)", file=sys.stderr,
           flush=True)
+    t0 = time.perf_counter()
     ctx = kad.Context(0)
+    ctx_create_s = time.perf_counter() - t0
     G = kad.Graph(ctx, csr)
     tuned = None
     if args.autotune:
@@ -377,9 +438,12 @@ def main():
     if args.mode == "topk":
         kw.update(mode="topk", k=args.k)
     arrays = None  # result arrays, allocated by the warmup and reused by every step
+    first_call_s = None
     for w in range(args.warmup):
         r = kad.run(ctx, G, out=arrays, **kw)
         arrays = {k: r[k] for k in ("count", "bc", "lower", "upper")}
+        if first_call_s is None:
+            first_call_s = r["seconds"]
         print(f"[bench] warmup {w}: tau={r['tau']} {r['seconds']:.3f} s", file=sys.stderr, flush=True)
 
     ctx.set_timing(True)
@@ -389,6 +453,8 @@ def main():
     for s in range(args.steps):
         r = kad.run(ctx, G, out=arrays, **kw)
         arrays = {k: r[k] for k in ("count", "bc", "lower", "upper")}
+        if first_call_s is None:
+            first_call_s = r["seconds"]
         runs.append(r)
         print(f"[bench] step {s}: tau={r['tau']} omega={r['omega']} stop={r['stop_reason']} "
               f"{r['seconds']:.3f} s", file=sys.stderr, flush=True)
@@ -446,10 +512,32 @@ def main():
                      "alg_bytes_per_launch": per_launch_bytes,
                      "hbm_bytes_per_launch": hbm},
     }
+    # cold time to epsilon: a graph registered anew (upload, validation, transpose) and its
+    # first run (vertex diameter, buffers) on the warm context
     G.close()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    G2 = kad.Graph(ctx, csr)
+    t_graph = time.perf_counter() - t0
+    if tuned:
+        G2.set_launch(tuned["block"], tuned["small_expansion"])
+    rc = kad.run(ctx, G2, out=arrays, **kw)
+    t_cold = time.perf_counter() - t0
+    out["time_to_epsilon_cold_s"] = t_cold
+    out["cold"] = {"graph_create_s": t_graph, "first_run_s": rc["seconds"],
+                   "first_run_setup_s": rc["seconds_setup"],
+                   "context_create_s": ctx_create_s, "first_call_on_new_context_s": first_call_s,
+                   "note": "time_to_epsilon_cold_s = graph_create_s + first_run_s (vertex "
+                           "diameter computed); first_call_on_new_context_s also allocates "
+                           "and clears the sampler slots"}
+    assert rc["tau"] == r0["tau"] and rc["stop_reason"] == r0["stop_reason"]
+    G2.close()
     ctx.close()
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(csr, args.cpu_samples, args.seed)
+        if args.cpu_full_run:
+            out["cpu_baseline"] = cpu_baseline_run(csr, kw, rc, args.cpu_one_thread)
+        else:
+            out["cpu_baseline"] = cpu_baseline(csr, args.cpu_samples, args.seed)
     print(json.dumps(out), flush=True)
 
 
