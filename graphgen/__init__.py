@@ -25,7 +25,7 @@ __all__ = [
     "CSR", "csr_from_edges", "er_lcc", "chung_lu", "chung_lu_directed",
     "grid", "damaged_grid", "path_graph", "star_graph", "cycle_graph",
     "complete_graph", "complete_bipartite", "disjoint_union", "gnp",
-    "batch_family_spec", "batch_graph", "serve_family_spec", "serve_graph", "serve_queries",
+    "hub_layers", "batch_family_spec", "batch_graph", "serve_family_spec", "serve_graph", "serve_queries",
     "workload",
 ]
 
@@ -367,6 +367,37 @@ def chung_lu_directed(n: int, beta_out: float, beta_in: float, mean_deg: float,
                           name=f"dcl{n}_bo{beta_out}_bi{beta_in}_d{mean_deg}_s{seed}",
                           meta={"model": "chung-lu-directed", "beta_out": beta_out,
                                 "beta_in": beta_in, "mean_deg": mean_deg, "seed": seed})
+
+
+# ----------------------------------------------------------------------------
+# a layered gadget with hub rows
+# ----------------------------------------------------------------------------
+
+def hub_layers(seed: int = 21) -> CSR:
+    """Directed graph whose touch scans test hub rows by binary search: a regular node
+    points to 16 of 64 A hubs and is pointed to by 16 of 64 B hubs; an A hub points to
+    20,000 of 50,000 feeder nodes and 3 B hubs; a feeder points to 32 B hubs.  For two
+    regular endpoints the s side's second level is 16 A hubs (320K arcs), the t side's
+    16 B hubs (400K arcs in), so the A rows are searched for 16 nodes each: 256 (row,
+    node) pairs, more than one pass of a workgroup."""
+    rng = np.random.default_rng(seed)
+    nr, nc, na, nb = 40_000, 50_000, 64, 64
+    R0, C0, A0, B0 = 0, nr, nr + nc, nr + nc + na
+    n = B0 + nb
+    src, dst = [], []
+    pick = np.argsort(rng.random((nr, na)), axis=1)[:, :16]
+    src.append(np.repeat(np.arange(nr) + R0, 16)); dst.append(pick.ravel() + A0)
+    pick = np.argsort(rng.random((nr, nb)), axis=1)[:, :16]
+    src.append(pick.ravel() + B0); dst.append(np.repeat(np.arange(nr) + R0, 16))
+    for a in range(na):
+        tg = rng.choice(nc, 20_000, replace=False) + C0
+        src.append(np.full(tg.size, A0 + a)); dst.append(tg)
+        bb = rng.choice(nb, 3, replace=False) + B0
+        src.append(np.full(3, A0 + a)); dst.append(bb)
+    pick = np.argsort(rng.random((nc, nb)), axis=1)[:, :32]
+    src.append(np.repeat(np.arange(nc) + C0, 32)); dst.append(pick.ravel() + B0)
+    return csr_from_edges(n, np.concatenate(src), np.concatenate(dst), True,
+                          name="hub_layers")
 
 
 # ----------------------------------------------------------------------------

@@ -59,7 +59,9 @@ enum {
 /* per-sample flag bits reported by kad_sample_paths */
 enum {
   KAD_SAMPLE_OVERFLOW = 1u, /* a path count or the candidate-edge total reached 2^128 */
-  KAD_SAMPLE_CAPACITY = 2u, /* the candidate-edge list or the path outgrew its buffer */
+  KAD_SAMPLE_CAPACITY = 2u, /* the wide-count arena or level tables, or the path, outgrew
+                               their buffers (samples that outgrow the 128-bit sampler's
+                               candidate-edge buffer are sampled again and are not flagged) */
   KAD_SAMPLE_RNG = 4u       /* a bounded draw exhausted its attempts */
 };
 
@@ -131,8 +133,9 @@ typedef struct {
   uint64_t interval;       /* check interval used */
   uint64_t arcs_scanned;   /* arcs scanned by the main phase's level expansions */
   uint64_t pilot_arcs_scanned;
-  uint64_t overflow_samples; /* samples whose 128-bit path counts overflowed and were sampled
-                                again with multi-limb counts (kad_run: over every launch,
+  uint64_t overflow_samples; /* samples sampled again by the wide-count kernel: their 128-bit
+                                path counts overflowed, or they met through more candidate
+                                edges than a sampler slot holds (kad_run: over every launch,
                                 including samples past the stopping point; engine: 0) */
   uint32_t vd, vd_exact;   /* vertex diameter used, and whether it is exact */
   uint32_t stop_reason;    /* KAD_STOP_RULE, KAD_STOP_OMEGA, or KAD_STOP_FIXED (fixed schedule) */

@@ -79,6 +79,12 @@ struct SampleOut {
   uint64_t *arcs;                // [count] arcs scanned by level expansions
   uint32_t *path;                // [count * stride], path nodes s..t
   uint32_t stride;
+  // The sampler appends the launch index of every sample it flags FLAG_OVERFLOW or
+  // FLAG_CAPACITY (and of every sample of a wide_only segment) to fix_list[0, *fix_count)
+  // (room for the launch's samples; *fix_count zero at launch); launch_wide_fix samples
+  // them again.  May be null (no list kept).
+  uint32_t *fix_list = nullptr;
+  uint32_t *fix_count = nullptr;
 };
 
 // Sample ids [first, first + count) of `phase`, dynamically distributed over the
@@ -94,17 +100,18 @@ hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const Slot
                                 uint32_t count, uint32_t *work, const SampleOut &out,
                                 uint32_t grid, const LaunchShape &shape, hipStream_t stream);
 
-// Resample, with multi-limb path counts, every sample of the launch whose flags carry
-// FLAG_OVERFLOW -- or, with `all`, every sample (no sampler launch before it) -- with
-// the results of exact arithmetic (FLAG_CAPACITY if the arena or the level tables are
-// too small).  list: room for `count` launch indices; list_count and work = list_count
-// + 1: two counters (set here).  segs == nullptr: the single-graph launch (g, seed,
-// phase, first).
+// Sample again, with multi-limb path counts and no limit on the candidate edges but the
+// arena, the samples of the launch listed in list[0, *list_count) -- the sampler's fix
+// list -- or, with `all` (list == nullptr), every sample of the launch (no sampler launch
+// before it).  The results are those of exact arithmetic; FLAG_CAPACITY remains only if
+// the arena or the level tables are too small, or the path outgrows the stride.  work:
+// a counter, zero at launch.  segs == nullptr: the single-graph launch (g, seed, phase,
+// first).  With an empty list the kernel's workgroups exit at once.
 hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
                            const SampleSeg *segs, uint32_t nseg, const SlotState &st,
-                           const WideState &ws, uint32_t count, bool all, uint32_t *list,
-                           uint32_t *list_count, uint32_t *work, const SampleOut &out,
-                           hipStream_t stream);
+                           const WideState &ws, uint32_t count, bool all,
+                           const uint32_t *list, const uint32_t *list_count, uint32_t *work,
+                           const SampleOut &out, hipStream_t stream);
 
 // Node tiles of the hit reduction: 8,192 ids each, at most this many tiles (graphs of
 // up to 2^25 nodes).

@@ -121,7 +121,7 @@ struct Piece {
 
 struct Tick {
   OutSet out;
-  DevBuf<uint32_t> wlist, wcnt;  // wide-count resampling: list, length and work counter
+  DevBuf<uint32_t> wlist;  // samples left by the sampler to the wide-count kernel
   DevBuf<SampleSeg> d_segs;
   PinBuf<SampleSeg> h_segs;
   DevBuf<GatherDesc> d_gat;
@@ -283,8 +283,7 @@ kad_status Engine::init() {
     HIP_TRY(hipMemsetAsync(L.bin_count.p, 0, POOL_TILES * 4, ctx_->rstream));
     HIP_TRY(hipMemsetAsync(L.tile_fill.p, 0, POOL_TILES * 4, ctx_->rstream));
     for (Tick &t : L.ticks) {
-      HIP_TRY(t.work.ensure(1));
-      HIP_TRY(t.wcnt.ensure(2));
+      HIP_TRY(t.work.ensure(3));  // sampler counter, fix-list length, fix counter
       HIP_TRY(hipEventCreateWithFlags(&t.sampled, hipEventDisableTiming));
     }
   }
@@ -433,12 +432,12 @@ kad_status Engine::admit() {
       ++j;
       continue;
     }
-    const bool need_wide = q->ovc != 0 && ctx_->w_slots == 0;
+    const bool need_wide = !wide_fits(ctx_, q->g, q->ovc);
     if (q->n > ctx_->slot_n || need_wide) {
       if (lanes_[0].busy() || lanes_[1].busy()) break;  // grow only when idle
       for (Lane &L : lanes_) HIP_TRY(hipStreamSynchronize(L.rs));
       kad_status s = q->n > ctx_->slot_n ? ensure_slots(ctx_, q->n) : KAD_OK;
-      if (!s && q->ovc != 0) s = ensure_wide(ctx_);
+      if (!s) s = ensure_wide(ctx_, q->g, q->ovc);
       layout();
       if (s) finish_failed(q, s, kad_last_error());
       continue;  // looked at again with the new layout (or as failed)
@@ -586,7 +585,6 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   const uint64_t need_bins = max_layer * std::max<uint32_t>(t.stride - 2, 1);
   if (need_bins > L.bins_cap) return fail(KAD_EINVAL, "internal: hit bins too small");
   // segments
-  bool wide = false;
   for (uint32_t j = 0; j < np; ++j) {
     const Piece &pc = t.pieces[j];
     const kad_graph *g = pc.q->g;
@@ -603,7 +601,6 @@ kad_status Engine::launch(Lane &L, Tick &t) {
     sg.id_base = (uint32_t)pc.q->base();
     sg.wide_only = pc.q->ovc == 2 ? 1u : 0u;
     sg.pad = 0;
-    wide |= pc.q->ovc != 0;
   }
   // snapshots, layer by layer
   std::vector<GatherDesc> gat;
@@ -655,7 +652,7 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   static_assert(sizeof(SampleSeg) % 8 == 0 && sizeof(GatherDesc) % 8 == 0, "copied as words");
   HIP_TRY(launch_copy_u64((uint64_t *)t.d_segs.p, (const uint64_t *)t.h_segs.p,
                           (uint64_t)np * sizeof(SampleSeg) / 8, s));
-  HIP_TRY(launch_zero_u32(t.work.p, 1, s));
+  HIP_TRY(launch_zero_u32(t.work.p, 3, s));
   // launch shape of the graph with the most samples in this launch
   const kad_graph *major = nullptr;
   {
@@ -678,21 +675,22 @@ kad_status Engine::launch(Lane &L, Tick &t) {
       if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx_->blocks_per_cu[j];
     const uint32_t grid = (uint32_t)std::min<uint64_t>(
         std::min<uint64_t>(L.nslots, (uint64_t)ctx_->cus * per_cu), t.total);
-    HIP_TRY(launch_sampler_multi(t.d_segs.p, np, lane_slots(L, false), t.total, t.work.p,
-                                 t.out.view(t.stride), grid, shape, s));
+    SampleOut so = t.out.view(t.stride);
+    so.fix_list = t.wlist.p;
+    so.fix_count = t.work.p + 1;
+    HIP_TRY(launch_sampler_multi(t.d_segs.p, np, lane_slots(L, false), t.total, t.work.p, so,
+                                 grid, shape, s));
   }
-  if (wide_lane || wide) {  // every sample of lane 1; the overflowed ones of lane 0
-    if (L.nwslots == 0) return fail(KAD_ENOMEM, "no wide-count slots for this launch");
-    HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, np, lane_slots(L, true),
-                            lane_wide(L), t.total, wide_lane, t.wlist.p, t.wcnt.p, t.wcnt.p + 1,
-                            t.out.view(t.stride), s));
-    if (wide_lane)
-      t.out.h_nwide.p[0] = t.total;
-    else
-      HIP_TRY(launch_copy_u32(t.out.h_nwide.p, t.wcnt.p, 1, s));
-  } else {
-    t.out.h_nwide.p[0] = 0;
-  }
+  // every sample of lane 1; in lane 0 the samples its sampler left (counts past 128 bits,
+  // wide_only segments, more candidate edges than a slot holds)
+  if (L.nwslots == 0) return fail(KAD_ENOMEM, "no wide-count slots for this launch");
+  HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, np, lane_slots(L, true),
+                          lane_wide(L), t.total, wide_lane, t.wlist.p, t.work.p + 1,
+                          t.work.p + 2, t.out.view(t.stride), s));
+  if (wide_lane)
+    t.out.h_nwide.p[0] = t.total;
+  else
+    HIP_TRY(launch_copy_u32(t.out.h_nwide.p, t.work.p + 1, 1, s));
   if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
   HIP_TRY(hipEventRecord(t.sampled, s));
   // host copies by kernels: runtime copies were seen waiting for the other lane's kernels

@@ -77,6 +77,7 @@ constexpr uint32_t DEFAULT_BATCH = 65536;
 // Device outputs of one sampler launch, with pinned host mirrors of the small ones.
 struct OutSet {
   DevBuf<uint32_t> s, t, len, flags, nodes, path;
+  DevBuf<uint32_t> fix_list;  // samples the sampler leaves to the wide-count kernel
   DevBuf<uint64_t> arcs;
   PinBuf<uint32_t> h_flags, h_len, h_nodes, h_nwide;  // h_nwide: samples resampled wide
   PinBuf<uint64_t> h_arcs;
@@ -98,7 +99,8 @@ struct OutSet {
   // capacity for `cap` samples and `path_entries` path entries in all (any stride with
   // samples * stride <= path_entries)
   kad_status ensure_entries(uint32_t cap, uint64_t path_entries, hipStream_t rs);
-  SampleOut view(uint32_t path_stride) const;
+  // fix_count: the launch's counter of fix_list entries (null: no list kept)
+  SampleOut view(uint32_t path_stride, uint32_t *fix_count = nullptr) const;
 };
 
 class Engine;
@@ -121,16 +123,21 @@ struct kad_ctx {
   uint64_t slot_bytes = 0;
   kad::DevBuf<uint32_t> rec, visit;  // node records (REC_WORDS words each), reached lists
   kad::DevBuf<uint64_t> pi;
-  // wide-count resampling of overflowed samples (kad::WideState)
+  // wide-count resampling (kad::WideState): samples whose counts pass 128 bits or whose
+  // candidate edges outgrow a slot.  w_big: the arena sized for wide counts (graphs whose
+  // counts can pass 128 bits), else for the candidate edges of 128-bit graphs only.
   uint32_t w_slots = 0, w_max_lev = 0;
+  bool w_big = false;
   uint64_t run_wide = 0;  // samples resampled wide during the current kad_run
   uint64_t w_arena_limbs = 0;
   kad::DevBuf<uint64_t> w_arena, w_lbase;
-  kad::DevBuf<uint32_t> w_lv, w_list, w_cnt;  // w_cnt: list length, work counter
+  kad::DevBuf<uint32_t> w_lv;
   // per-launch outputs, double-buffered so the next batch can be sampled while the
   // host checks the current one
   kad::OutSet outs[2];
-  kad::DevBuf<uint32_t> work, work2, group;  // work2: the work counter of pstream launches
+  // work counters of a launch: [0] the sampler's, [1] its fix-list length, [2] the wide
+  // fix's; work2: the same for pstream launches
+  kad::DevBuf<uint32_t> work, work2, group;
   kad::DevBuf<uint64_t> count, gmax;
   hipEvent_t ev_s = nullptr, ev_rs = nullptr, ev_ps = nullptr;  // wait_stream's markers
   kad::DevBuf<uint64_t> count0d;         // pilot counts (all-nodes runs)
@@ -219,14 +226,19 @@ WideState wide_view(const kad_ctx *ctx);
 // high-diameter graph whose samples all go to the wide kernel.  vd_from_library:
 // false for a caller's VD override, whose bound is not trusted (then 1).
 int overflow_class(const kad_graph *g, uint32_t vd, bool vd_from_library);
-// Wide working memory, allocated on first use.
-kad_status ensure_wide(kad_ctx *ctx);
+// Wide working memory able to sample graph g (of overflow class ovc) again: every graph
+// needs it, for samples with more candidate edges than a slot holds; a graph whose counts
+// can pass 128 bits needs the large arena.  Allocated on first use, grown (after a device
+// synchronisation) when a graph needs more.
+kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc);
+bool wide_fits(const kad_ctx *ctx, const kad_graph *g, int ovc);
 // Launch the wide-count resampling of a launch of `count` samples whose outputs are
-// `out` (segs == nullptr: single graph g; all: every sample, no sampler launch
-// before), and queue the copy of the number of resampled samples into *h_nwide.
+// `out`: the samples of its fix list (list, *list_count), or with `all` every sample (no
+// sampler launch before); work: zero at launch.  segs == nullptr: single graph g.
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
-                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream,
+                       bool all, const uint32_t *list, const uint32_t *list_count,
+                       uint32_t *work, const SampleOut &out, hipStream_t stream,
                        uint32_t slot0 = 0);
 // The graph's launch shape (set or tuned, else a default by size), and the grid of a
 // launch of `count` samples with it.

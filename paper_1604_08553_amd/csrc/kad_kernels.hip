@@ -17,9 +17,15 @@
 //   The expansion that meets -- normally the largest one -- therefore costs
 //   coalesced row reads and LDS probes only.
 //
-// hit_reduce_kernel: the interior nodes of the sampled paths are counted per
-//   node-id tile in an LDS histogram and added to the global counters by the
-//   tile's owner, so the counters see no atomics.
+// Hit reductions (interior nodes of the sampled paths -> per-node counters), three kinds:
+//   hit_partition/hit_tile -- per node-id tile, an LDS histogram whose cells are added to
+//     the counters by the one thread that claims each cell: no atomics on the counters
+//     (large calls and subtractions);
+//   hit_atomic_kernel -- one device atomic add per hit (calls of at most 2^17 hits);
+//   iv_count/iv_prefix/iv_snap -- every check interval of a batch at once: per-interval
+//     hit counts by device atomics on scratch, then one owner per node adds them to its
+//     counter interval by interval.
+//   The atomic forms were measured faster on the run's critical path.
 #include <algorithm>
 
 #include "kad_device.h"
@@ -1044,6 +1050,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           k_next = next_id();
           out.flags[k] = FLAG_OVERFLOW;
           out.len[k] = 0;
+          if (out.fix_list) out.fix_list[atomicAdd(out.fix_count, 1u)] = k;
         }
         __syncthreads();  // every thread has read L.k and L.seg before they change
         continue;
@@ -1335,6 +1342,10 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       out.arcs[k] = L.arcs;
       out.flags[k] = L.flags;
       out.nodes[k] = L.needed;
+      // counts beyond 128 bits, or more candidate edges than the slot holds: sampled again
+      // by the wide-count kernel, which has neither limit
+      if ((L.flags & (FLAG_OVERFLOW | FLAG_CAPACITY)) && out.fix_list)
+        out.fix_list[atomicAdd(out.fix_count, 1u)] = k;
     }
     // ---- restore the slot's all-zero state for the next sample
     const uint32_t nv = L.nvis;
@@ -1748,8 +1759,10 @@ __device__ void pull_add(uint64_t *__restrict__ acc, uint32_t stride,
 struct WideLds {
   uint32_t k, seg, s, t, flags;
   uint32_t lvl[2];
-  uint32_t nvis, pi_count, maxw, maxw_all, sel;
+  uint32_t nvis, pi_count, maxw, maxw_all, sel, capf;
+  uint32_t kcount, kfound;
   uint64_t deg[2], new_deg, arcs, top;
+  uint64_t skey, kmask, kwant;  // the chosen candidate edge; the radix select's digits so far
   uint32_t c_node[WCHUNK], c_start[WCHUNK], c_pref[WCHUNK + 1];
   uint32_t red[WNW];
 };
@@ -1849,6 +1862,8 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
     __syncthreads();
     bool met = false;
     uint32_t needed = 0;
+    // the expansion that met: its side, frontier and the other side's tag (uniform)
+    uint32_t m_side = 0, m_fb = 0, m_fe = 0, m_otag = 0;
     for (;;) {
       const uint32_t me = L.deg[0] <= L.deg[1] ? 0u : 1u;  // ties expand the s side
       const uint32_t ot = 1u - me;
@@ -1879,6 +1894,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
         L.pi_count = 0;
         L.new_deg = 0;
         L.maxw = 0;
+        L.capf = 0;
       }
       __syncthreads();
       // ---- one pass over the frontier's arcs: meeting test, discovery, and the new
@@ -1954,15 +1970,22 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
         __syncthreads();
       }
       atomicMax(&L.maxw, used_max);
-      if (cap) atomicOr(&L.flags, FLAG_CAPACITY);
+      if (cap) atomicOr(&L.capf, 1u);
       __syncthreads();
-      if (L.pi_count > 0) {
+      if (L.pi_count > 0) {  // the level just discovered is never used: no arena limit
         met = true;
+        m_side = me;
+        m_fb = fb;
+        m_fe = fe;
+        m_otag = other_tag;
         break;
       }
       const uint32_t ne = L.nvis;
       if (ne == nb) break;  // the expanded side closed: s and t are disconnected
-      if (L.flags & FLAG_CAPACITY) break;
+      if (L.capf) {
+        if (tid == 0) L.flags |= FLAG_CAPACITY;
+        break;
+      }
       __syncthreads();
       if (tid == 0) {
         const uint32_t wn = max(L.maxw, 1u);
@@ -1989,132 +2012,286 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       const uint32_t tw = max(pw, L.maxw_all) + 2;  // totals, draws, running sums
       constexpr uint32_t GROUPS = 16;  // block sums are combined in 16 groups of 16
       static_assert(WB == GROUPS * 16, "one block of candidate edges per thread");
-      const uint64_t prod = L.top;
-      const uint64_t need = prod + (uint64_t)P * pw + (uint64_t)(WB + GROUPS + 11) * tw;
-      if (P > st.pi_cap || ls + lt + 2 > out.stride || need > ws.arena_limbs) {
+      const uint32_t so = LV(0, ls, LV_LO), ss = LV(0, ls, LV_STRIDE);
+      const uint32_t to = LV(1, lt, LV_LO), ts = LV(1, lt, LV_STRIDE);
+      const uint64_t sb = LB(0, ls), tb = LB(1, lt);
+      // weight of candidate edge (v, w): sigma_s(v) sigma_t(w), pw limbs at dst
+      auto weight = [&](uint64_t key, uint64_t *dst) {
+        const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
+        wide_mul(arena + sb + (size_t)(*pos_of(rec, v) - so) * ss, ws_,
+                 arena + tb + (size_t)(*pos_of(rec, w) - to) * ts, wt_, dst);
+      };
+      const uint64_t prod = L.top;  // the (unused) new level's place: free from here on
+      uint64_t *bscr = nullptr;     // six numbers of tw limbs for the two backtracking walks
+      if (ls + lt + 2 > out.stride) {
         if (tid == 0) L.flags |= FLAG_CAPACITY;
+      } else if (P <= st.pi_cap) {
+        const uint64_t need = prod + (uint64_t)P * pw + (uint64_t)(WB + GROUPS + 11) * tw;
+        if (need > ws.arena_limbs) {
+          if (tid == 0) L.flags |= FLAG_CAPACITY;
+        } else {
+          // ---- candidate edges in canonical order, and their weights
+          uint32_t M = 1;
+          while (M < P) M <<= 1;
+          for (uint32_t j = P + tid; j < M; j += WB) gpi[j] = ~0ULL;
+          __syncthreads();
+          bitonic_sort<WB>(gpi, M);
+          for (uint32_t j = tid; j < P; j += WB) weight(gpi[j], arena + prod + (size_t)j * pw);
+          __syncthreads();
+          // sums of contiguous blocks of weights (one block per thread), then of groups
+          // of 16 blocks, so that the total and the prefix that passes r need few serial adds
+          uint64_t *bsum = arena + prod + (size_t)P * pw;
+          uint64_t *gsum = bsum + (size_t)WB * tw;
+          uint64_t *scr = gsum + (size_t)GROUPS * tw;  // 11 scratch numbers
+          bscr = scr + 5 * (size_t)tw;
+          const uint32_t b0 = (uint32_t)((uint64_t)P * tid / WB), b1 = (uint32_t)((uint64_t)P * (tid + 1) / WB);
+          {
+            uint64_t *bs = bsum + (size_t)tid * tw;
+            for (uint32_t j = 0; j < tw; ++j) bs[j] = 0;
+            for (uint32_t j = b0; j < b1; ++j) (void)wide_add(bs, tw, arena + prod + (size_t)j * pw, pw);
+          }
+          __syncthreads();
+          if (tid < GROUPS) {
+            uint64_t *gs = gsum + (size_t)tid * tw;
+            for (uint32_t j = 0; j < tw; ++j) gs[j] = 0;
+            for (uint32_t b = tid * 16; b < tid * 16 + 16; ++b) (void)wide_add(gs, tw, bsum + (size_t)b * tw, tw);
+          }
+          __syncthreads();
+          if (tid == 0) {
+            uint64_t *total = scr, *r = scr + tw, *tmp = scr + 2 * tw, *acc = scr + 3 * tw,
+                     *sv = scr + 4 * tw;
+            uint32_t fl = 0;
+            for (uint32_t j = 0; j < tw; ++j) total[j] = 0;
+            for (uint32_t gi = 0; gi < GROUPS; ++gi) (void)wide_add(total, tw, gsum + (size_t)gi * tw, tw);
+            uniform_below_wide(total, tw, seed, i, stream_word(phase, P_EDGE, 0), r, tmp, fl);
+            // the first edge whose prefix sum passes r: group, then block, then edge
+            for (uint32_t j = 0; j < tw; ++j) acc[j] = 0;
+            auto step = [&](const uint64_t *x, uint32_t xw) -> bool {  // acc += x unless that passes r
+              for (uint32_t j = 0; j < tw; ++j) sv[j] = acc[j];
+              (void)wide_add(acc, tw, x, xw);
+              if (wide_cmp(acc, tw, r, tw) > 0) {
+                for (uint32_t j = 0; j < tw; ++j) acc[j] = sv[j];
+                return true;
+              }
+              return false;
+            };
+            uint32_t gsel = GROUPS, bsel = WB, sel = P;
+            for (uint32_t gi = 0; gi < GROUPS && fl == 0; ++gi)
+              if (step(gsum + (size_t)gi * tw, tw)) {
+                gsel = gi;
+                break;
+              }
+            for (uint32_t b = gsel * 16; gsel < GROUPS && b < gsel * 16 + 16; ++b)
+              if (step(bsum + (size_t)b * tw, tw)) {
+                bsel = b;
+                break;
+              }
+            if (bsel < WB) {
+              const uint32_t e0 = (uint32_t)((uint64_t)P * bsel / WB), e1 = (uint32_t)((uint64_t)P * (bsel + 1) / WB);
+              for (uint32_t j = e0; j < e1; ++j)
+                if (step(arena + prod + (size_t)j * pw, pw)) {
+                  sel = j;
+                  break;
+                }
+            }
+            if (sel >= P) fl |= FLAG_CAPACITY;  // unreachable for consistent counts
+            else L.skey = gpi[sel];
+            L.flags |= fl;
+          }
+        }
       } else {
-        // ---- candidate edges in canonical order, and their weights
-        uint32_t M = 1;
-        while (M < P) M <<= 1;
-        for (uint32_t j = P + tid; j < M; j += WB) gpi[j] = ~0ULL;
-        __syncthreads();
-        bitonic_sort<WB>(gpi, M);
-        const uint32_t so = LV(0, ls, LV_LO), ss = LV(0, ls, LV_STRIDE);
-        const uint32_t to = LV(1, lt, LV_LO), ts = LV(1, lt, LV_STRIDE);
-        const uint64_t sb = LB(0, ls), tb = LB(1, lt);
-        for (uint32_t j = tid; j < P; j += WB) {
-          const uint64_t key = gpi[j];
-          const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
-          wide_mul(arena + sb + (size_t)(*pos_of(rec, v) - so) * ss, ws_,
-                   arena + tb + (size_t)(*pos_of(rec, w) - to) * ts, wt_, arena + prod + (size_t)j * pw);
-        }
-        __syncthreads();
-        // sums of contiguous blocks of weights (one block per thread), then of groups
-        // of 16 blocks, so that the total and the prefix that passes r need few serial adds
-        uint64_t *bsum = arena + prod + (size_t)P * pw;
-        uint64_t *gsum = bsum + (size_t)WB * tw;
-        uint64_t *scr = gsum + (size_t)GROUPS * tw;  // 11 scratch numbers
-        const uint32_t b0 = (uint32_t)((uint64_t)P * tid / WB), b1 = (uint32_t)((uint64_t)P * (tid + 1) / WB);
-        {
-          uint64_t *bs = bsum + (size_t)tid * tw;
-          for (uint32_t j = 0; j < tw; ++j) bs[j] = 0;
-          for (uint32_t j = b0; j < b1; ++j) (void)wide_add(bs, tw, arena + prod + (size_t)j * pw, pw);
-        }
-        __syncthreads();
-        if (tid < GROUPS) {
-          uint64_t *gs = gsum + (size_t)tid * tw;
-          for (uint32_t j = 0; j < tw; ++j) gs[j] = 0;
-          for (uint32_t b = tid * 16; b < tid * 16 + 16; ++b) (void)wide_add(gs, tw, bsum + (size_t)b * tw, tw);
-        }
-        __syncthreads();
-        if (tid == 0) {
-          uint64_t *total = scr, *r = scr + tw, *tmp = scr + 2 * tw, *acc = scr + 3 * tw,
-                   *sv = scr + 4 * tw;
-          uint32_t fl = 0;
-          for (uint32_t j = 0; j < tw; ++j) total[j] = 0;
-          for (uint32_t gi = 0; gi < GROUPS; ++gi) (void)wide_add(total, tw, gsum + (size_t)gi * tw, tw);
-          uniform_below_wide(total, tw, seed, i, stream_word(phase, P_EDGE, 0), r, tmp, fl);
-          // the first edge whose prefix sum passes r: group, then block, then edge
-          for (uint32_t j = 0; j < tw; ++j) acc[j] = 0;
-          auto step = [&](const uint64_t *x, uint32_t xw) -> bool {  // acc += x unless that passes r
-            for (uint32_t j = 0; j < tw; ++j) sv[j] = acc[j];
-            (void)wide_add(acc, tw, x, xw);
-            if (wide_cmp(acc, tw, r, tw) > 0) {
-              for (uint32_t j = 0; j < tw; ++j) acc[j] = sv[j];
-              return true;
-            }
-            return false;
-          };
-          uint32_t gsel = GROUPS, bsel = WB, sel = P;
-          for (uint32_t gi = 0; gi < GROUPS && fl == 0; ++gi)
-            if (step(gsum + (size_t)gi * tw, tw)) {
-              gsel = gi;
-              break;
-            }
-          for (uint32_t b = gsel * 16; gsel < GROUPS && b < gsel * 16 + 16; ++b)
-            if (step(bsum + (size_t)b * tw, tw)) {
-              bsel = b;
-              break;
-            }
-          if (bsel < WB) {
-            const uint32_t e0 = (uint32_t)((uint64_t)P * bsel / WB), e1 = (uint32_t)((uint64_t)P * (bsel + 1) / WB);
-            for (uint32_t j = e0; j < e1; ++j)
-              if (step(arena + prod + (size_t)j * pw, pw)) {
-                sel = j;
-                break;
-              }
+        // ---- more candidate edges than the slot's buffer holds.  Every one is written
+        // to the arena by a second pass over the meeting level (its tags are unchanged,
+        // so it finds the same edges), and the edge is chosen without sorting: a weighted
+        // radix select over the 64-bit keys (v << 32 | w), four bits at a time from the
+        // top.  Pass d sums the weights of the keys that agree with the digits chosen so
+        // far into 16 buckets by their next digit; the digit taken is the first whose
+        // bucket makes the running sum pass r.  The key found is the first key, in
+        // ascending order, whose prefix sum of weights passes r -- the canonical choice.
+        constexpr uint32_t NB = 16;
+        uint64_t *keys = arena + prod;
+        uint64_t *part = keys + P;                     // WB x NB numbers: per-thread buckets
+        uint64_t *l2 = part + (size_t)WB * NB * tw;    // WB numbers: partial bucket sums
+        uint64_t *bsum = l2 + (size_t)WB * tw;         // NB numbers: bucket sums
+        uint64_t *scr = bsum + (size_t)NB * tw;        // total, r, tmp, below, saved; 6 more
+        uint64_t *prodt = scr + 11 * (size_t)tw;       // WB products of pw limbs
+        bscr = scr + 5 * (size_t)tw;
+        const uint64_t need = (uint64_t)(prodt - arena) + (uint64_t)WB * pw;
+        if (need > ws.arena_limbs) {
+          if (tid == 0) L.flags |= FLAG_CAPACITY;
+        } else {
+          const uint32_t *rp = m_side == 0 ? g.row : g.rrow;
+          const uint32_t *cl = m_side == 0 ? g.col : g.rcol;
+          if (tid == 0) {
+            L.kcount = 0;
+            L.kmask = 0;
+            L.kwant = 0;
           }
-          if (sel >= P) fl |= FLAG_CAPACITY;  // unreachable for consistent counts
-          L.sel = sel;
-          L.flags |= fl;
-        }
-        __syncthreads();
-        // ---- backtracking (section 4): the two sides at once, by lane 0 of waves 0 and 1
-        if (L.flags == 0 && (tid == 0 || tid == WAVE)) {
-          const uint32_t side = tid == 0 ? 0u : 1u;
-          uint64_t *r = scr + (size_t)(5 + 3 * side) * tw;  // scratch numbers 5..10
-          uint64_t *acc = r + tw, *tmp2 = r + 2 * tw;
-          uint32_t fl = 0;
-          const uint64_t key = gpi[L.sel];
-          uint32_t x = side == 0 ? (uint32_t)(key >> 32) : (uint32_t)key;
-          const uint32_t lev = side == 0 ? ls : lt;
-          path[side == 0 ? ls : ls + 1] = x + base;
-          const uint32_t *brp = side == 0 ? g.rrow : g.row;
-          const uint32_t *bcl = side == 0 ? g.rcol : g.col;
-          for (uint32_t j = lev; j >= 1 && fl == 0; --j) {
-            const uint32_t xw = LV(side, j, LV_WIDTH);
-            const uint64_t *sx = arena + LB(side, j) +
-                                 (size_t)(*pos_of(rec, x) - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
-            uniform_below_wide(sx, xw, seed, i,
-                               stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j), r, tmp2, fl);
-            const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1
-            const uint32_t pwid = LV(side, j - 1, LV_WIDTH), plo = LV(side, j - 1, LV_LO);
-            const uint32_t pst = LV(side, j - 1, LV_STRIDE);
-            const uint64_t pb = LB(side, j - 1);
-            for (uint32_t q = 0; q < tw; ++q) acc[q] = 0;
-            uint32_t pick = 0xFFFFFFFFu;
-            for (uint32_t e = brp[x]; e < brp[x + 1] && fl == 0; ++e) {
-              const uint32_t u = bcl[e];
-              if (ld_tag(tag_of(rec, u)) != want) continue;
-              (void)wide_add(acc, tw, arena + pb + (size_t)(*pos_of(rec, u) - plo) * pst, pwid);
-              if (wide_cmp(acc, tw, r, xw) > 0) {
-                pick = u;
-                break;
+          __syncthreads();
+          for (uint32_t cb = m_fb; cb < m_fe; cb += WCHUNK) {
+            const uint32_t m = min((uint32_t)WCHUNK, m_fe - cb);
+            uint32_t d[2] = {0, 0};
+            for (int q = 0; q < 2; ++q) {
+              const uint32_t j = 2 * tid + q;
+              if (j < m) {
+                const uint32_t u = visit[cb + j];
+                const uint32_t st0 = rp[u];
+                d[q] = rp[u + 1] - st0;
+                L.c_node[j] = u;
+                L.c_start[j] = st0;
               }
             }
-            if (pick == 0xFFFFFFFFu) {
-              fl |= FLAG_CAPACITY;  // unreachable for consistent counts
-              break;
+            const uint32_t inc = wave_incl_u32(d[0] + d[1]);
+            if (lane == WAVE - 1) L.red[wid] = inc;
+            __syncthreads();
+            uint32_t before = 0, tot = 0;
+            for (int q = 0; q < WNW; ++q) {
+              if ((uint32_t)q < wid) before += L.red[q];
+              tot += L.red[q];
             }
-            x = pick;
-            path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x + base;
+            const uint32_t ex = before + inc - (d[0] + d[1]);
+            if (2 * tid < m) L.c_pref[2 * tid] = ex;
+            if (2 * tid + 1 < m) L.c_pref[2 * tid + 1] = ex + d[0];
+            if (tid == 0) L.c_pref[m] = tot;
+            __syncthreads();
+            for (uint32_t e = tid; e < tot; e += WB) {
+              uint32_t lo = 0, hi = m;  // largest j with c_pref[j] <= e
+              while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
+              }
+              const uint32_t u = L.c_node[lo];
+              const uint32_t w = cl[L.c_start[lo] + (e - L.c_pref[lo])];
+              if (ld_tag(tag_of(rec, w)) == m_otag) {
+                const uint32_t idx = atomicAdd(&L.kcount, 1u);
+                const uint64_t key = m_side == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+                if (idx < P) keys[idx] = key;
+              }
+            }
+            __syncthreads();
           }
-          if (fl) atomicOr(&L.flags, fl);
+          if (L.kcount != P) {  // unreachable: the same level, the same tags
+            if (tid == 0) L.flags |= FLAG_CAPACITY;
+          } else {
+            uint32_t nbits = 1;  // both halves of a key are below n: bits [0, 4D) each
+            while (nbits < 32 && ((g.n - 1u) >> nbits) != 0) ++nbits;
+            const uint32_t D = (nbits + 3) / 4;
+            uint64_t *mypart = part + (size_t)tid * NB * tw;
+            uint64_t *myprod = prodt + (size_t)tid * pw;
+            for (uint32_t pass = 0; pass < 2 * D; ++pass) {
+              const uint32_t sh = (pass < D ? 32u : 0u) + 4u * (D - 1u - pass % D);
+              const uint64_t kmask = L.kmask, kwant = L.kwant;
+              for (uint32_t j = 0; j < NB * tw; ++j) mypart[j] = 0;
+              for (uint32_t j = tid; j < P; j += WB) {
+                const uint64_t key = keys[j];
+                if ((key & kmask) != kwant) continue;
+                weight(key, myprod);
+                (void)wide_add(mypart + (size_t)((key >> sh) & (NB - 1)) * tw, tw, myprod, pw);
+              }
+              __syncthreads();
+              {  // bucket tid % NB over threads [16 (tid / NB), +16)
+                const uint32_t b = tid % NB, t0 = (tid / NB) * 16;
+                uint64_t *acc = l2 + (size_t)tid * tw;
+                for (uint32_t j = 0; j < tw; ++j) acc[j] = 0;
+                for (uint32_t t = t0; t < t0 + 16; ++t)
+                  (void)wide_add(acc, tw, part + ((size_t)t * NB + b) * tw, tw);
+              }
+              __syncthreads();
+              if (tid < NB) {  // bucket tid: the WB / NB partial sums of the threads above
+                uint64_t *acc = bsum + (size_t)tid * tw;
+                for (uint32_t j = 0; j < tw; ++j) acc[j] = 0;
+                for (uint32_t q = tid; q < (uint32_t)WB; q += NB)
+                  (void)wide_add(acc, tw, l2 + (size_t)q * tw, tw);
+              }
+              __syncthreads();
+              if (tid == 0) {
+                uint64_t *total = scr, *r = scr + tw, *tmp = scr + 2 * tw, *below = scr + 3 * tw,
+                         *sv = scr + 4 * tw;
+                uint32_t fl = 0;
+                if (pass == 0) {
+                  for (uint32_t j = 0; j < tw; ++j) total[j] = 0;
+                  for (uint32_t b = 0; b < NB; ++b) (void)wide_add(total, tw, bsum + (size_t)b * tw, tw);
+                  uniform_below_wide(total, tw, seed, i, stream_word(phase, P_EDGE, 0), r, tmp, fl);
+                  for (uint32_t j = 0; j < tw; ++j) below[j] = 0;
+                }
+                uint32_t pick = NB;
+                for (uint32_t b = 0; b < NB && fl == 0; ++b) {
+                  for (uint32_t j = 0; j < tw; ++j) sv[j] = below[j];
+                  (void)wide_add(below, tw, bsum + (size_t)b * tw, tw);
+                  if (wide_cmp(below, tw, r, tw) > 0) {
+                    for (uint32_t j = 0; j < tw; ++j) below[j] = sv[j];
+                    pick = b;
+                    break;
+                  }
+                }
+                if (pick == NB) fl |= FLAG_CAPACITY;  // unreachable: r < total
+                L.kmask = kmask | ((uint64_t)(NB - 1) << sh);
+                L.kwant = kwant | ((uint64_t)(pick & (NB - 1)) << sh);
+                L.flags |= fl;
+              }
+              __syncthreads();
+              if (L.flags) break;
+            }
+            if (L.flags == 0) {  // the digits name one key of the list (keys are distinct)
+              if (tid == 0) L.kfound = 0;
+              __syncthreads();
+              const uint64_t kw = L.kwant;
+              for (uint32_t j = tid; j < P; j += WB)
+                if (keys[j] == kw) atomicAdd(&L.kfound, 1u);
+              __syncthreads();
+              if (tid == 0) {
+                if (L.kfound == 1) L.skey = kw;
+                else L.flags |= FLAG_CAPACITY;  // unreachable
+              }
+            }
+          }
         }
-        __syncthreads();
-        if (L.flags == 0) len = ls + lt + 2;
       }
+      __syncthreads();
+      // ---- backtracking (section 4): the two sides at once, by lane 0 of waves 0 and 1
+      if (L.flags == 0 && (tid == 0 || tid == WAVE)) {
+        const uint32_t side = tid == 0 ? 0u : 1u;
+        uint64_t *r = bscr + (size_t)(3 * side) * tw;
+        uint64_t *acc = r + tw, *tmp2 = r + 2 * tw;
+        uint32_t fl = 0;
+        const uint64_t key = L.skey;
+        uint32_t x = side == 0 ? (uint32_t)(key >> 32) : (uint32_t)key;
+        const uint32_t lev = side == 0 ? ls : lt;
+        path[side == 0 ? ls : ls + 1] = x + base;
+        const uint32_t *brp = side == 0 ? g.rrow : g.row;
+        const uint32_t *bcl = side == 0 ? g.rcol : g.col;
+        for (uint32_t j = lev; j >= 1 && fl == 0; --j) {
+          const uint32_t xw = LV(side, j, LV_WIDTH);
+          const uint64_t *sx = arena + LB(side, j) +
+                               (size_t)(*pos_of(rec, x) - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
+          uniform_below_wide(sx, xw, seed, i,
+                             stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j), r, tmp2, fl);
+          const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1
+          const uint32_t pwid = LV(side, j - 1, LV_WIDTH), plo = LV(side, j - 1, LV_LO);
+          const uint32_t pst = LV(side, j - 1, LV_STRIDE);
+          const uint64_t pb = LB(side, j - 1);
+          for (uint32_t q = 0; q < tw; ++q) acc[q] = 0;
+          uint32_t pick = 0xFFFFFFFFu;
+          for (uint32_t e = brp[x]; e < brp[x + 1] && fl == 0; ++e) {
+            const uint32_t u = bcl[e];
+            if (ld_tag(tag_of(rec, u)) != want) continue;
+            (void)wide_add(acc, tw, arena + pb + (size_t)(*pos_of(rec, u) - plo) * pst, pwid);
+            if (wide_cmp(acc, tw, r, xw) > 0) {
+              pick = u;
+              break;
+            }
+          }
+          if (pick == 0xFFFFFFFFu) {
+            fl |= FLAG_CAPACITY;  // unreachable for consistent counts
+            break;
+          }
+          x = pick;
+          path[side == 0 ? j - 1 : ls + 1 + (lev - j) + 1] = x + base;
+        }
+        if (fl) atomicOr(&L.flags, fl);
+      }
+      __syncthreads();
+      if (L.flags == 0) len = ls + lt + 2;
     }
     __syncthreads();
     if (tid == 0) {
@@ -2134,12 +2311,6 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
     }
     __syncthreads();
   }
-}
-
-__global__ void overflow_list_kernel(const uint32_t *flags, uint32_t count, uint32_t *list,
-                                     uint32_t *list_count) {
-  const uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-  if (k < count && (flags[k] & FLAG_OVERFLOW)) list[atomicAdd(list_count, 1u)] = k;
 }
 
 }  // namespace
@@ -2190,28 +2361,19 @@ hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const Slot
 
 hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
                            const SampleSeg *segs, uint32_t nseg, const SlotState &st,
-                           const WideState &ws, uint32_t count, bool all, uint32_t *list,
-                           uint32_t *list_count, uint32_t *work, const SampleOut &out,
-                           hipStream_t stream) {
+                           const WideState &ws, uint32_t count, bool all,
+                           const uint32_t *list, const uint32_t *list_count, uint32_t *work,
+                           const SampleOut &out, hipStream_t stream) {
   if (count == 0) return hipSuccess;
-  if (ws.slots == 0 || ws.slots > st.slots || !ws.arena) return hipErrorInvalidValue;
-  if (work != list_count + 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, stream, list_count, (uint64_t)2,
-                     0u);  // list length and work counter
-  const uint32_t *lst = nullptr;
-  if (!all) {
-    hipLaunchKernelGGL(overflow_list_kernel, dim3((count + 255) / 256), dim3(256), 0, stream,
-                       (const uint32_t *)out.flags, count, list, list_count);
-    lst = list;
-  }
+  if (ws.slots == 0 || ws.slots > st.slots || !ws.arena || !work) return hipErrorInvalidValue;
+  if (!all && (!list || !list_count)) return hipErrorInvalidValue;
+  const uint32_t *lst = all ? nullptr : list;
   if (segs)
     hipLaunchKernelGGL(wide_kernel<true>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
-                       seed, phase, first, st, ws, lst, (const uint32_t *)list_count, count, work,
-                       out);
+                       seed, phase, first, st, ws, lst, list_count, count, work, out);
   else
     hipLaunchKernelGGL(wide_kernel<false>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
-                       seed, phase, first, st, ws, lst, (const uint32_t *)list_count, count, work,
-                       out);
+                       seed, phase, first, st, ws, lst, list_count, count, work, out);
   return hipGetLastError();
 }
 

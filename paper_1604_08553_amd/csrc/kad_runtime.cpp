@@ -38,13 +38,14 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
   if (cap < want_cap || stride < want_stride) {
     const uint32_t c = std::max(want_cap, cap);
     const uint32_t st = std::max(want_stride, stride);
-    for (auto *b : {&s, &t, &len, &flags, &nodes, &path}) b->release();
+    for (auto *b : {&s, &t, &len, &flags, &nodes, &path, &fix_list}) b->release();
     arcs.release();
     HIP_TRY(s.ensure(c));
     HIP_TRY(t.ensure(c));
     HIP_TRY(len.ensure(c));
     HIP_TRY(flags.ensure(c));
     HIP_TRY(nodes.ensure(c));
+    HIP_TRY(fix_list.ensure(c));
     HIP_TRY(arcs.ensure(c));
     HIP_TRY(path.ensure((size_t)c * st));
     HIP_TRY(h_flags.ensure(c));
@@ -68,13 +69,14 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
 
 kad_status OutSet::ensure_entries(uint32_t want_cap, uint64_t path_entries, hipStream_t rs) {
   if (cap < want_cap || path.n < path_entries) {
-    for (auto *b : {&s, &t, &len, &flags, &nodes, &path}) b->release();
+    for (auto *b : {&s, &t, &len, &flags, &nodes, &path, &fix_list}) b->release();
     arcs.release();
     HIP_TRY(s.ensure(want_cap));
     HIP_TRY(t.ensure(want_cap));
     HIP_TRY(len.ensure(want_cap));
     HIP_TRY(flags.ensure(want_cap));
     HIP_TRY(nodes.ensure(want_cap));
+    HIP_TRY(fix_list.ensure(want_cap));
     HIP_TRY(arcs.ensure(want_cap));
     HIP_TRY(path.ensure(path_entries));
     HIP_TRY(h_flags.ensure(want_cap));
@@ -88,7 +90,7 @@ kad_status OutSet::ensure_entries(uint32_t want_cap, uint64_t path_entries, hipS
   return ensure(cap, 0, rs);  // events
 }
 
-SampleOut OutSet::view(uint32_t path_stride) const {
+SampleOut OutSet::view(uint32_t path_stride, uint32_t *fix_count) const {
   SampleOut so;
   so.s = s.p;
   so.t = t.p;
@@ -98,6 +100,8 @@ SampleOut OutSet::view(uint32_t path_stride) const {
   so.arcs = arcs.p;
   so.path = path.p;
   so.stride = path_stride;
+  so.fix_list = fix_count ? fix_list.p : nullptr;
+  so.fix_count = fix_count;
   return so;
 }
 
@@ -160,27 +164,51 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   return KAD_OK;
 }
 
-kad_status ensure_wide(kad_ctx *ctx) {
-  if (ctx->w_slots > 0) return KAD_OK;
-  // up to 64 workgroups, each with a limb arena of up to 1 GiB, in at most half of
-  // what the budget leaves after the graphs and the sampler slots
+// Limbs of one wide slot's arena for graph g: with counts that may pass 128 bits, as much
+// as the budget allows (up to 1 GiB); otherwise the counts of every node at three limbs,
+// every arc as a candidate-edge key, and the selection's scratch.
+static uint64_t wide_limbs_needed(const kad_graph *g, int ovc) {
+  if (ovc != 0) return 1ull << 20;  // at least; the large arena takes what the budget gives
+  return std::min<uint64_t>(1ull << 27, 3ull * g->n + g->arcs + (1ull << 18));
+}
+
+bool wide_fits(const kad_ctx *ctx, const kad_graph *g, int ovc) {
+  return ctx->w_slots > 0 && (ovc == 0 || ctx->w_big) &&
+         ctx->w_arena_limbs >= wide_limbs_needed(g, ovc);
+}
+
+kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc) {
+  if (wide_fits(ctx, g, ovc)) return KAD_OK;
+  const bool big = ovc != 0 || ctx->w_big;
+  const uint64_t want = std::max(wide_limbs_needed(g, ovc),
+                                 ctx->w_slots ? ctx->w_arena_limbs : (uint64_t)0);
+  HIP_TRY(hipDeviceSynchronize());  // no launch may still use the old arena
+  ctx->w_arena.release();
+  ctx->w_lv.release();
+  ctx->w_lbase.release();
+  ctx->w_slots = 0;
+  ctx->w_arena_limbs = 0;
+  // the large arena: up to 64 workgroups, each with up to 1 GiB, in at most half of what
+  // the budget leaves after the graphs and the sampler slots; the small one: 16 workgroups
   const uint64_t left = ctx->budget > ctx->used_graphs + ctx->slot_bytes + (1024ull << 20)
                             ? ctx->budget - ctx->used_graphs - ctx->slot_bytes - (1024ull << 20)
                             : 0;
-  const uint32_t w_slots = std::min<uint32_t>(64, ctx->slots);
+  const uint32_t w_slots = std::min<uint32_t>(big ? 64 : 16, ctx->slots);
   const uint32_t max_lev = 16384;
   const uint64_t tables = (uint64_t)w_slots * 2 * max_lev * (16 + 8);
   uint64_t limbs = left / 2 > tables ? (left / 2 - tables) / (8ull * std::max(w_slots, 1u)) : 0;
   limbs = std::min<uint64_t>(limbs, 1ull << 27);
-  if (w_slots == 0 || limbs < (1ull << 20))
-    return fail(KAD_ENOMEM, "no HBM left for wide path counts (needed by this graph)");
+  if (!big) limbs = std::min(limbs, want);
+  if (w_slots == 0 || limbs < want)
+    return fail(KAD_ENOMEM, "no HBM left for the wide-count arena (%llu limbs per slot needed)",
+                (unsigned long long)want);
   HIP_TRY(ctx->w_arena.ensure((size_t)w_slots * limbs));
   HIP_TRY(ctx->w_lv.ensure((size_t)w_slots * 2 * max_lev * 4));
   HIP_TRY(ctx->w_lbase.ensure((size_t)w_slots * 2 * max_lev));
-  HIP_TRY(ctx->w_cnt.ensure(2));
   ctx->w_slots = w_slots;
   ctx->w_max_lev = max_lev;
   ctx->w_arena_limbs = limbs;
+  ctx->w_big = big;
   return KAD_OK;
 }
 
@@ -207,25 +235,16 @@ WideState wide_view(const kad_ctx *ctx) {
 
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
-                       bool all, const SampleOut &out, uint32_t *h_nwide, hipStream_t stream,
+                       bool all, const uint32_t *list, const uint32_t *list_count,
+                       uint32_t *work, const SampleOut &out, hipStream_t stream,
                        uint32_t slot0) {
-  if (count == 0) {
-    *h_nwide = 0;
-    return KAD_OK;
-  }
-  kad_status st = ensure_wide(ctx);
-  if (st) return st;
-  if (ctx->w_list.n < count) {
-    HIP_TRY(hipDeviceSynchronize());  // the old list may still be read
-    ctx->w_list.release();
-    HIP_TRY(ctx->w_list.ensure(std::max<size_t>(count, 1u << 18)));
-  }
+  if (count == 0) return KAD_OK;
+  if (ctx->w_slots == 0) return fail(KAD_EINVAL, "internal: wide-count arena not allocated");
   const SlotState sv = slot_view(ctx, slot0);
   WideState wv = wide_view(ctx);
   wv.slots = std::min(wv.slots, sv.slots);  // the wide slots reuse these sampler slots
-  HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, sv, wv, count, all, ctx->w_list.p,
-                          ctx->w_cnt.p, ctx->w_cnt.p + 1, out, stream));
-  HIP_TRY(hipMemcpyAsync(h_nwide, ctx->w_cnt.p, 4, hipMemcpyDeviceToHost, stream));
+  HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, sv, wv, count, all, list,
+                          list_count, work, out, stream));
   return KAD_OK;
 }
 
@@ -405,15 +424,18 @@ void transpose(uint32_t n, const std::vector<uint32_t> &row, const std::vector<u
 
 hipStream_t pick_stream(kad_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }
 
-// Size the slot state and both output sets for graph size n and `batch` samples of
-// path stride `stride`.
-kad_status ensure_capacity(kad_ctx *ctx, uint32_t n, uint32_t batch, uint32_t stride) {
+// Size the slot state, the wide-count arena and both output sets for graph g (overflow
+// class ovc) and `batch` samples of path stride `stride`.
+kad_status ensure_capacity(kad_ctx *ctx, const kad_graph *g, int ovc, uint32_t batch,
+                           uint32_t stride) {
+  const uint32_t n = g->n;
   kad_status st = kad::ensure_slots(ctx, n);
   if (st) return st;
+  if ((st = kad::ensure_wide(ctx, g, ovc))) return st;
   for (OutSet &o : ctx->outs)
     if ((st = o.ensure(batch, stride, ctx->rstream))) return st;
-  HIP_TRY(ctx->work.ensure(1));
-  HIP_TRY(ctx->work2.ensure(1));
+  HIP_TRY(ctx->work.ensure(3));
+  HIP_TRY(ctx->work2.ensure(3));
   HIP_TRY(ctx->count.ensure(n));
   HIP_TRY(ctx->h_count.ensure(n));
   // hit-reduction bins: room in every tile for all the hits of one reduction call
@@ -468,29 +490,29 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
                         hipEvent_t wide_after = nullptr) {
   OutSet &o = ctx->outs[set];
   kad_status st = KAD_OK;
-  uint32_t *wk = work ? work : ctx->work.p;
+  uint32_t *wk = work ? work : ctx->work.p;  // sampler counter, fix-list length, fix counter
   HIP_TRY(hipEventRecord(o.k0, stream));
+  HIP_TRY(kad::launch_zero_u32(wk, 3, stream));
   if (ovc == 2) {
     if (wide_after) HIP_TRY(hipStreamWaitEvent(stream, wide_after, 0));
-    st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, true,
-                          o.view(stride), o.h_nwide.p, stream, slot0);
+    st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, true, nullptr,
+                          nullptr, wk + 2, o.view(stride), stream, slot0);
     if (st) return st;
     HIP_TRY(hipEventRecord(o.k1, stream));
+    o.h_nwide.p[0] = count;
   } else {
-    HIP_TRY(kad::launch_zero_u32(wk, 1, stream));
     const kad::LaunchShape shape = kad::graph_shape(g);
     const uint32_t grid = kad::launch_grid(ctx, shape, count, slot0);
     HIP_TRY(kad::launch_sampler(dev_view(g), kad::slot_view(ctx, slot0), seed, phase, first,
-                                count, wk, o.view(stride), grid, shape, stream));
+                                count, wk, o.view(stride, wk + 1), grid, shape, stream));
     HIP_TRY(hipEventRecord(o.k1, stream));
-    if (ovc == 1) {
-      if (wide_after) HIP_TRY(hipStreamWaitEvent(stream, wide_after, 0));
-      st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, false,
-                            o.view(stride), o.h_nwide.p, stream, slot0);
-      if (st) return st;
-    } else {
-      o.h_nwide.p[0] = 0;
-    }
+    // the samples the sampler left (counts past 128 bits, more candidate edges than a slot
+    // holds) are sampled again by the wide-count kernel; an empty list costs one short launch
+    if (wide_after) HIP_TRY(hipStreamWaitEvent(stream, wide_after, 0));
+    st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, false,
+                          o.fix_list.p, wk + 1, wk + 2, o.view(stride), stream, slot0);
+    if (st) return st;
+    HIP_TRY(hipMemcpyAsync(o.h_nwide.p, wk + 1, 4, hipMemcpyDeviceToHost, stream));
   }
   // the reductions need only the paths: they wait for this event, not for the mirrors
   // (a set is launched into again only after the host has waited for its mirrors)
@@ -850,7 +872,7 @@ kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uin
   const uint32_t stride = std::max<uint32_t>(vd, 2);
   const int ovc = kad::overflow_class(g, vd, true);
   const uint32_t batch = std::min<uint32_t>(std::max<uint32_t>(count, 1), DEFAULT_BATCH);
-  if ((st = ensure_capacity(ctx, g->n, batch, stride))) return st;
+  if ((st = ensure_capacity(ctx, g, ovc, batch, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
   HIP_TRY(ctx->h_s.ensure(batch));
   HIP_TRY(ctx->h_t.ensure(batch));
@@ -904,7 +926,7 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
   const uint32_t stride = std::max<uint32_t>(vd, 2);
   const int ovc = kad::overflow_class(g, vd, true);
   const uint32_t batch = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(count, 1), DEFAULT_BATCH);
-  if ((st = ensure_capacity(ctx, g->n, batch, stride))) return st;
+  if ((st = ensure_capacity(ctx, g, ovc, batch, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
   HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)g->n * 8, stream));
   uint64_t arcs = 0;
@@ -957,7 +979,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   const uint32_t chunks_per_batch = (uint32_t)(K / B);
   const uint32_t stride = std::max<uint32_t>(vd, 2);
   const int ovc = kad::overflow_class(g, vd, p->vd_override == 0);
-  if ((st = ensure_capacity(ctx, n, (uint32_t)K, stride))) return st;
+  if ((st = ensure_capacity(ctx, g, ovc, (uint32_t)K, stride))) return st;
   hipStream_t stream = pick_stream(ctx, hip_stream);
   if ((st = run_timing_begin(ctx, stream))) return st;
   struct RunTimingEnd {  // also on early returns
@@ -1419,7 +1441,7 @@ kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *
   if (st) return st;
   const uint32_t stride = std::max<uint32_t>(vd, 2);
   const int ovc = kad::overflow_class(g, vd, true);
-  if ((st = ensure_capacity(ctx, g->n, samples, stride))) return st;
+  if ((st = ensure_capacity(ctx, g, ovc, samples, stride))) return st;
   const kad::LaunchShape saved = g->shape;
   const bool saved_set = g->shape_set;
   const uint32_t exps[4] = {0, 32, 128, 512};

@@ -101,58 +101,59 @@ def test_paths_chung_lu_1m_sampled_ids(kad, ctx, orc):
 
 
 def _hub_layers(seed=21):
-    """Directed graph whose touch scans test hub rows by binary search: a regular node
-    points to 16 of 64 A hubs and is pointed to by 16 of 64 B hubs; an A hub points to
-    20,000 of 50,000 feeder nodes and 3 B hubs; a feeder points to 32 B hubs.  For two
-    regular endpoints the s side's second level is 16 A hubs (320K arcs), the t side's
-    16 B hubs (400K arcs in), so the A rows are searched for 16 nodes each: 256 (row,
-    node) pairs, more than one pass of a workgroup."""
-    rng = np.random.default_rng(seed)
-    nr, nc, na, nb = 40_000, 50_000, 64, 64
-    R0, C0, A0, B0 = 0, nr, nr + nc, nr + nc + na
-    n = B0 + nb
-    src, dst = [], []
-    pick = np.argsort(rng.random((nr, na)), axis=1)[:, :16]
-    src.append(np.repeat(np.arange(nr) + R0, 16)); dst.append(pick.ravel() + A0)
-    pick = np.argsort(rng.random((nr, nb)), axis=1)[:, :16]
-    src.append(pick.ravel() + B0); dst.append(np.repeat(np.arange(nr) + R0, 16))
-    for a in range(na):
-        tg = rng.choice(nc, 20_000, replace=False) + C0
-        src.append(np.full(tg.size, A0 + a)); dst.append(tg)
-        bb = rng.choice(nb, 3, replace=False) + B0
-        src.append(np.full(3, A0 + a)); dst.append(bb)
-    pick = np.argsort(rng.random((nc, nb)), axis=1)[:, :32]
-    src.append(np.repeat(np.arange(nc) + C0, 32)); dst.append(pick.ravel() + B0)
-    return gg.csr_from_edges(n, np.concatenate(src), np.concatenate(dst), True,
-                             name="hub_layers")
+    return gg.hub_layers(seed)
 
 
 @pytest.mark.parametrize("block", [64, 128, 256])
 def test_paths_hub_rows_searched(kad, ctx, orc, block):
     """Touch scans that search long rows for the other frontier's nodes (several
-    passes of pairs per chunk, endpoints that are hubs) give the oracle's paths."""
+    passes of pairs per chunk, endpoints that are hubs) give the oracle's paths.  Two
+    endpoints off the regular layer (mostly two feeders) meet through up to ~370K
+    candidate edges, more than a slot's 65,536-entry buffer: those samples are sampled
+    again by the wide-count kernel, which keeps every candidate edge in its arena and
+    picks one by a weighted radix select -- the same edge as the oracle's canonical
+    prefix sum."""
     g = _hub_layers()
     G = kad.Graph(ctx, g)
     G.set_launch(block, 0)
     _say("hub_layers", block)
     A = kad.sample_paths(ctx, G, 4, 1, 0, 3000)
     B = orc.sample_paths(g, 4, 1, 0, 3000, threads=16)
+    assert (A["flags"] == 0).all(), np.unique(A["flags"])
     assert np.array_equal(A["s"], B.s) and np.array_equal(A["t"], B.t)
-    # two endpoints off the regular layer (mostly two feeders) meet through up to
-    # ~370K edges, beyond the 65,536-entry candidate buffer: those samples report
-    # KAD_SAMPLE_CAPACITY; every sample with a regular endpoint has fewer than 50
-    ok = A["flags"] == 0
-    regular = (B.s < 40_000) | (B.t < 40_000)
-    assert np.isin(A["flags"], [0, 2]).all() and ok[regular].all()
-    assert ok.sum() >= 1500
-    assert np.array_equal(A["arcs"][ok], B.arcs[ok])
+    assert np.array_equal(A["arcs"], B.arcs)
+    assert np.array_equal(A["path_off"], B.path_off.astype(np.uint64))
+    assert np.array_equal(A["nodes"], B.nodes)
     lens = np.diff(B.path_off.astype(np.int64))
-    for k in np.nonzero(ok)[0]:
-        a = A["nodes"][A["path_off"][k]:A["path_off"][k + 1]]
-        assert np.array_equal(a, B.path(k)), (k, a, B.path(k))
     # the layered case occurred: paths s -> A hub -> B hub -> t between regular nodes
     both = (B.s < 40_000) & (B.t < 40_000)
     assert (lens[both] == 4).sum() > 100
+    # and the large meetings did: pairs of two feeder nodes
+    feeders = (B.s >= 40_000) & (B.s < 90_000) & (B.t >= 40_000) & (B.t < 90_000)
+    assert feeders.sum() > 500
+    G.close()
+
+
+def test_run_hub_layers_large_meetings(kad, ctx, orc):
+    """Whole runs where about half the samples meet through more candidate edges than a
+    slot holds: the single run and the engine equal the oracle."""
+    g = _hub_layers()
+    G = kad.Graph(ctx, g)
+    kw = dict(epsilon=0.02, delta=0.1, seed=6)
+    _say("hub_layers kad_run")
+    a = kad.run(ctx, G, **kw)
+    b = orc.run(g, threads=16, **kw)
+    assert a["tau"] == b["tau"] and a["stop_reason"] == b["stop_rule"]
+    assert a["arcs_scanned"] == b["arcs"] and a["pilot_arcs_scanned"] == b["pilot_arcs"]
+    assert np.array_equal(a["count"], b["count"])
+    assert np.array_equal(a["lower"], b["lower"]) and np.array_equal(a["upper"], b["upper"])
+    assert a["overflow_samples"] > a["tau"] // 10   # sampled again for their candidate edges
+    _say("hub_layers run_batch")
+    c = kad.run_batch(ctx, [G, G], [kw, dict(kw, seed=7)])
+    assert c[0]["tau"] == b["tau"] and np.array_equal(c[0]["count"], b["count"])
+    assert np.array_equal(c[0]["lower"], b["lower"]) and np.array_equal(c[0]["upper"], b["upper"])
+    d = orc.run(g, threads=16, **dict(kw, seed=7))
+    assert c[1]["tau"] == d["tau"] and np.array_equal(c[1]["count"], d["count"])
     G.close()
 
 
