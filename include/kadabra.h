@@ -240,6 +240,27 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
                           uint64_t first, uint64_t count, uint64_t *count_out,
                           uint64_t *arcs_scanned, void *hip_stream);
 
+/* The same hit counts for callers that cannot allocate device memory: code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc.  This call allocates and
+ * frees nothing: its working memory (sampler slots, one launch's per-sample outputs, a
+ * small wide-count arena for samples with many candidate edges) lies in a fixed device
+ * array of KAD_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, held until the
+ * process ends.  It only enqueues work on hip_stream (NULL: the device's null stream, not
+ * the context's) and returns without waiting; it does not claim the context.
+ *   count_dev : device uint64[n]; count_dev[v] += hits of v (as kad_hit_counts adds)
+ *   arcs_dev  : device uint64[1]; += arcs scanned by the level expansions
+ *   flags_dev : device uint32[1]; |= the KAD_SAMPLE_* bits of every sample (0 when every
+ *               sample is valid; a flagged sample adds no hits)
+ * Errors: KAD_EINVAL for a graph whose path counts may pass 128 bits (its samples need the
+ * context's large wide-count arena: use kad_hit_counts); KAD_ENOMEM when the graph's
+ * working memory does not fit the scratch (the message gives the sizes); about 3.5M nodes
+ * at most, with fewer concurrent samples as n grows.  Calls that overlap on one GPU (any
+ * context, any stream) race on the shared scratch and must be ordered by the caller. */
+#define KAD_NOALLOC_SCRATCH_BYTES (128ull << 20)
+kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                                  uint64_t first, uint64_t count, uint64_t *count_dev,
+                                  uint64_t *arcs_dev, uint32_t *flags_dev, void *hip_stream);
+
 /* ---------------------------------------------------------------- host statistics */
 /* These run on the CPU only (no device needed); binary64, no FMA contraction. */
 

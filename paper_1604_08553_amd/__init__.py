@@ -15,6 +15,7 @@ import re
 import numpy as np
 
 __all__ = ["Context", "Graph", "run", "run_batch", "Server", "sample_paths", "hit_counts",
+           "hit_counts_noalloc",
            "KadError", "lib",
            "library_path", "declared_symbols", "omega", "alpha", "default_interval",
            "vertex_diameter", "bound_f", "bound_g", "compute_delta", "topk_lambdas",
@@ -87,6 +88,7 @@ def lib():
         "kad_run": ([vp, vp, C.POINTER(_Params), C.POINTER(_Result), vp], st),
         "kad_sample_paths": ([vp, vp, u64, u32, u64, u32, vp, vp, vp, vp, u64, vp, vp, vp], st),
         "kad_hit_counts": ([vp, vp, u64, u32, u64, u64, vp, vp, vp], st),
+        "kad_hit_counts_noalloc": ([vp, vp, u64, u32, u64, u64, vp, vp, vp, vp], st),
         "kad_omega": ([dbl, dbl, u32, dbl], u64),
         "kad_alpha": ([u64], u64),
         "kad_fixed_samples": ([u32, dbl, dbl, u32, u32, dbl], u64),
@@ -441,6 +443,16 @@ def hit_counts(ctx: Context, graph: Graph, seed: int, phase: int, first: int, co
     _check(lib().kad_hit_counts(ctx.handle, graph.handle, seed, phase, first, count, _p(cnt),
                                 C.byref(arcs), _stream(stream)))
     return cnt, arcs.value
+
+
+def hit_counts_noalloc(ctx: Context, graph: Graph, seed: int, phase: int, first: int,
+                       count: int, count_dev, arcs_dev, flags_dev, stream=None):
+    """kad_hit_counts_noalloc: enqueue the hit counts of ids [first, first+count) into
+    device tensors (count_dev: 8-byte integers [n], arcs_dev: 8-byte [1], flags_dev: 4-byte
+    [1], all accumulated) using only the library's fixed scratch; returns without waiting."""
+    _check(lib().kad_hit_counts_noalloc(ctx.handle, graph.handle, seed, phase, first, count,
+                                        count_dev.data_ptr(), arcs_dev.data_ptr(),
+                                        flags_dev.data_ptr(), _stream(stream)))
 
 
 # ----------------------------------------------------------------------------- host statistics

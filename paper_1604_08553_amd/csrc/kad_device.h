@@ -186,6 +186,23 @@ constexpr uint32_t GATHER_CHUNK = 4096;  // entries per workgroup
 hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint64_t *count_pool,
                          const uint64_t *gmax_pool, uint64_t *snap, hipStream_t stream);
 
+// count[v] += 1 for every interior node v (< n) of the paths of samples [0, nsamp), one
+// device atomic per hit.
+hipError_t launch_hit_add_atomic(const uint32_t *path, const uint32_t *len, uint32_t stride,
+                                 uint32_t nsamp, uint32_t n, uint64_t *count,
+                                 hipStream_t stream);
+// *arcs_total += sum of arcs[0, count); *flags_or |= OR of flags[0, count).
+hipError_t launch_sample_sums(const uint64_t *arcs, const uint32_t *flags, uint32_t count,
+                              uint64_t *arcs_total, uint32_t *flags_or, hipStream_t stream);
+
+// The fixed working memory of the entry point that allocates nothing: a file-scope device
+// array of NOALLOC_SCRATCH_BYTES in the kernels' code object, one copy per device, kept
+// until the process ends.  noalloc_scratch gives its device address on the current device
+// (looked up once per device with hipGetSymbolAddress).
+constexpr size_t NOALLOC_SCRATCH_BYTES = (size_t)128 << 20;
+constexpr int NOALLOC_MAX_DEVICES = 64;
+hipError_t noalloc_scratch(void **ptr);
+
 // Sampler workgroups of `block` threads resident per CU (occupancy query).
 int sampler_blocks_per_cu(int block);
 

@@ -165,6 +165,8 @@ struct kad_ctx {
   std::vector<std::pair<float, float>> t_iv;       // its launches' intervals (ms from t_ref)
   // the multi-query engine (kad_run_batch, kad_server_*), created on first use
   kad::Engine *engine = nullptr;
+  // device address of the fixed scratch array used by kad_hit_counts_noalloc
+  void *noalloc = nullptr;
   ~kad_ctx() {
     kad::destroy_engine(engine);
     for (auto e : chunk_ev) (void)hipEventDestroy(e);

@@ -27,6 +27,7 @@
 //     counter interval by interval.
 //   The atomic forms were measured faster on the run's critical path.
 #include <algorithm>
+#include <mutex>
 
 #include "kad_device.h"
 
@@ -1316,15 +1317,15 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           // ---- the two halves: with two or more waves, wave 0 walks to s while wave 1
           // walks to t; a single wave walks one after the other
           uint32_t fl = 0;
-          MatchScratch *scratch = reinterpret_cast<MatchScratch *>(L.pi);
+          MatchScratch *mscr = reinterpret_cast<MatchScratch *>(L.pi);
           if (wid == 0) {
             if (lane == 0) path[ls] = v + base;
-            backtrack(g, 0, v, ls, rec, visit, L.seg_lo, L.seg_hi, scratch[0], seed, i,
+            backtrack(g, 0, v, ls, rec, visit, L.seg_lo, L.seg_hi, mscr[0], seed, i,
                       phase, path, ls, base, L.s, fl);
           }
           if (wid == (NWAVES >= 2 ? 1u : 0u)) {
             if (lane == 0) path[ls + 1] = w + base;
-            backtrack(g, 1, w, lt, rec, visit, L.seg_lo, L.seg_hi, scratch[1], seed, i,
+            backtrack(g, 1, w, lt, rec, visit, L.seg_lo, L.seg_hi, mscr[1], seed, i,
                       phase, path, ls, base, L.t, fl);
           }
           if (win >= P) fl |= FLAG_CAPACITY;
@@ -2313,6 +2314,40 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
   }
 }
 
+// *arcs_total += the sum of arcs[0, count); *flags_or |= the OR of flags[0, count).
+__global__ __launch_bounds__(256) void sample_sums_kernel(const uint64_t *__restrict__ arcs,
+                                                          const uint32_t *__restrict__ flags,
+                                                          uint32_t count, uint64_t *arcs_total,
+                                                          uint32_t *flags_or) {
+  __shared__ uint64_t sa[256 / WAVE];
+  __shared__ uint32_t sf[256 / WAVE];
+  uint64_t a = 0;
+  uint32_t f = 0;
+  for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < count; k += gridDim.x * 256) {
+    a += arcs[k];
+    f |= flags[k];
+  }
+  a = wave_sum_u64(a);
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) f |= __shfl_xor(f, d, WAVE);
+  if (lane_id() == 0) {
+    sa[threadIdx.x / WAVE] = a;
+    sf[threadIdx.x / WAVE] = f;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    for (int w = 1; w < 256 / WAVE; ++w) {
+      a += sa[w];
+      f |= sf[w];
+    }
+    if (a) atomicAdd((unsigned long long *)arcs_total, (unsigned long long)a);
+    if (f) atomicOr(flags_or, f);
+  }
+}
+
+// The fixed working memory of the calls that allocate nothing (see noalloc_scratch).
+static __device__ __align__(256) uint64_t scratch[NOALLOC_SCRATCH_BYTES / 8];
+
 }  // namespace
 
 template <bool MULTI>
@@ -2530,6 +2565,47 @@ hipError_t launch_hit_batch(const uint32_t *path, const uint32_t *len, uint32_t 
   hipLaunchKernelGGL(iv_snap_kernel, dim3(b3), dim3(HIT_BLOCK), 0, stream, niv, ngroups, ivmax,
                      gmax, snap);
   return hipGetLastError();
+}
+
+hipError_t launch_hit_add_atomic(const uint32_t *path, const uint32_t *len, uint32_t stride,
+                                 uint32_t nsamp, uint32_t n, uint64_t *count,
+                                 hipStream_t stream) {
+  if (nsamp == 0) return hipSuccess;
+  const uint64_t entries = (uint64_t)nsamp * stride;
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>((entries + HIT_BLOCK - 1) / HIT_BLOCK, 1024);
+  hipLaunchKernelGGL(hit_atomic_kernel, dim3(blocks), dim3(HIT_BLOCK), 0, stream, path, len,
+                     stride, nsamp, n, count, (const uint32_t *)nullptr, (uint64_t *)nullptr);
+  return hipGetLastError();
+}
+
+hipError_t launch_sample_sums(const uint64_t *arcs, const uint32_t *flags, uint32_t count,
+                              uint64_t *arcs_total, uint32_t *flags_or, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  const uint32_t blocks = std::min<uint32_t>((count + 255) / 256, 256);
+  hipLaunchKernelGGL(sample_sums_kernel, dim3(blocks), dim3(256), 0, stream, arcs, flags, count,
+                     arcs_total, flags_or);
+  return hipGetLastError();
+}
+
+// The device address of `scratch` on the current device, looked up once per device (each
+// device holds its own copy of the array, at its own address; in host code the array's
+// name is only a stand-in and must never be passed to a kernel).
+hipError_t noalloc_scratch(void **ptr) {
+  static std::mutex mu;
+  static void *addr[NOALLOC_MAX_DEVICES] = {};
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lk(mu);
+  if (!addr[dev]) {
+    void *p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    addr[dev] = p;
+  }
+  *ptr = addr[dev];
+  return hipSuccess;
 }
 
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream) {

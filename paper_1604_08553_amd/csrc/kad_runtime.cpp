@@ -647,6 +647,9 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
+  // the fixed scratch of kad_hit_counts_noalloc: its address on this device, looked up now
+  // (with the device current) so that the call itself needs no runtime set-up
+  HIP_TRY(kad::noalloc_scratch(&c->noalloc));
   *out = c.release();
   return KAD_OK;
 }
@@ -943,6 +946,108 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
   HIP_TRY(hipStreamSynchronize(stream));
   for (uint32_t v = 0; v < g->n; ++v) count_out[v] += ctx->h_count.p[v];
   if (arcs_scanned) *arcs_scanned = arcs;
+  return KAD_OK;
+}
+
+// ---------------------------------------------------------------- hit counts, no allocation
+
+kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                                  uint64_t first, uint64_t count, uint64_t *count_dev,
+                                  uint64_t *arcs_dev, uint32_t *flags_dev, void *hip_stream) {
+  if (!ctx || !g || !count_dev || !arcs_dev || !flags_dev) return fail(KAD_EINVAL, "NULL argument");
+  if (phase > 255) return fail(KAD_EINVAL, "phase must fit 8 bits");
+  if (!ctx->noalloc) return fail(KAD_EDEVICE, "the fixed scratch of this device is not set up");
+  if (count == 0) return KAD_OK;
+  kad_graph *gm = const_cast<kad_graph *>(g);
+  uint32_t vd;
+  bool ex;
+  kad_status st = graph_vd(gm, &vd, &ex);  // host only, cached on the graph
+  if (st) return st;
+  if (kad::overflow_class(g, vd, true) != 0)
+    return fail(KAD_EINVAL, "path counts of this graph may pass 128 bits: its samples need the "
+                "wide-count arena, which the fixed scratch does not hold (use kad_hit_counts)");
+  const uint32_t n = g->n, stride = std::max<uint32_t>(vd, 2);
+  // layout of the scratch, each region 256-byte aligned: launch counters, per-sample outputs
+  // of one launch (C samples), one wide-count slot (arena and level tables), then the
+  // sampler slots (node records, reached lists, candidate buffers of PI_SMALL entries)
+  constexpr uint32_t PI_SMALL = 4096, MAX_LEV = 1024, C_MAX = 8192;
+  const uint64_t total = kad::NOALLOC_SCRATCH_BYTES;
+  auto align = [](uint64_t x) { return (x + 255) & ~(uint64_t)255; };
+  const uint32_t C = (uint32_t)std::min<uint64_t>(count, C_MAX);
+  uint64_t off = 0;
+  const uint64_t o_cnt = off;
+  off = align(off + 64);
+  const uint64_t o_s = off; off = align(off + 4ull * C);
+  const uint64_t o_t = off; off = align(off + 4ull * C);
+  const uint64_t o_len = off; off = align(off + 4ull * C);
+  const uint64_t o_flags = off; off = align(off + 4ull * C);
+  const uint64_t o_nodes = off; off = align(off + 4ull * C);
+  const uint64_t o_fix = off; off = align(off + 4ull * C);
+  const uint64_t o_arcs = off; off = align(off + 8ull * C);
+  const uint64_t o_path = off; off = align(off + 4ull * C * stride);
+  const uint64_t limbs = 3ull * n + g->arcs + (1ull << 18);
+  const uint64_t o_arena = off; off = align(off + 8ull * limbs);
+  const uint64_t o_lv = off; off = align(off + 2ull * MAX_LEV * 4 * 4);
+  const uint64_t o_lb = off; off = align(off + 2ull * MAX_LEV * 8);
+  const uint64_t per_slot = align((uint64_t)n * 4 * kad::REC_WORDS) + align(4ull * n) +
+                            8ull * PI_SMALL;
+  const kad::LaunchShape shape = kad::graph_shape(g);
+  const uint64_t resident = (uint64_t)ctx->cus *
+      (uint64_t)ctx->blocks_per_cu[shape.block == 64 ? 0 : (shape.block == 128 ? 1 : 2)];
+  const uint64_t room = off < total ? total - off : 0;
+  const uint64_t G = std::min<uint64_t>(resident, room / per_slot);
+  if (G == 0)
+    return fail(KAD_ENOMEM, "graph too large for the fixed scratch of %llu bytes: %llu bytes of "
+                "working memory and one sampler slot of %llu bytes are needed",
+                (unsigned long long)total, (unsigned long long)off, (unsigned long long)per_slot);
+  uint8_t *base = static_cast<uint8_t *>(ctx->noalloc);
+  uint32_t *cnt = reinterpret_cast<uint32_t *>(base + o_cnt);
+  kad::SampleOut out;
+  out.s = reinterpret_cast<uint32_t *>(base + o_s);
+  out.t = reinterpret_cast<uint32_t *>(base + o_t);
+  out.len = reinterpret_cast<uint32_t *>(base + o_len);
+  out.flags = reinterpret_cast<uint32_t *>(base + o_flags);
+  out.nodes = reinterpret_cast<uint32_t *>(base + o_nodes);
+  out.arcs = reinterpret_cast<uint64_t *>(base + o_arcs);
+  out.path = reinterpret_cast<uint32_t *>(base + o_path);
+  out.stride = stride;
+  out.fix_list = reinterpret_cast<uint32_t *>(base + o_fix);
+  out.fix_count = cnt + 1;
+  kad::SlotState sv;
+  sv.slots = (uint32_t)G;
+  sv.n = n;
+  sv.pi_cap = PI_SMALL;
+  uint8_t *slots = base + off;
+  sv.rec = reinterpret_cast<uint32_t *>(slots);
+  sv.visit = reinterpret_cast<uint32_t *>(slots + G * align((uint64_t)n * 4 * kad::REC_WORDS));
+  sv.pi = reinterpret_cast<uint64_t *>(slots + G * (align((uint64_t)n * 4 * kad::REC_WORDS) +
+                                                    align(4ull * n)));
+  kad::WideState wv;  // one wide-count slot, on sampler slot 0's node records
+  wv.slots = 1;
+  wv.max_lev = MAX_LEV;
+  wv.arena_limbs = limbs;
+  wv.arena = reinterpret_cast<uint64_t *>(base + o_arena);
+  wv.lv = reinterpret_cast<uint32_t *>(base + o_lv);
+  wv.lbase = reinterpret_cast<uint64_t *>(base + o_lb);
+  // NULL is the device's null stream: the work is only enqueued, so the caller must be able
+  // to order its own work after it
+  hipStream_t stream = (hipStream_t)hip_stream;
+  HIP_TRY(hipSetDevice(ctx->device));
+  // node records start all zero (the kernels leave them so, but the region may have held
+  // other data in an earlier call with another layout); cleared by a kernel, not a memset
+  HIP_TRY(kad::launch_zero_u32(sv.rec, (uint64_t)G * n * kad::REC_WORDS, stream));
+  const kad::GraphDev gd = dev_view(g);
+  for (uint64_t done = 0; done < count;) {
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(C, count - done);
+    HIP_TRY(kad::launch_zero_u32(cnt, 3, stream));
+    HIP_TRY(kad::launch_sampler(gd, sv, seed, phase, first + done, nb, cnt, out,
+                                (uint32_t)std::min<uint64_t>(G, nb), shape, stream));
+    HIP_TRY(kad::launch_wide_fix(gd, seed, phase, first + done, nullptr, 0, sv, wv, nb, false,
+                                 out.fix_list, cnt + 1, cnt + 2, out, stream));
+    HIP_TRY(kad::launch_hit_add_atomic(out.path, out.len, stride, nb, n, count_dev, stream));
+    HIP_TRY(kad::launch_sample_sums(out.arcs, out.flags, nb, arcs_dev, flags_dev, stream));
+    done += nb;
+  }
   return KAD_OK;
 }
 
