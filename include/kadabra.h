@@ -319,6 +319,22 @@ kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint
 int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *count, uint64_t tau,
                      uint64_t omega, double epsilon, const double *L_l, const double *L_u);
 
+/* ---------------------------------------------------------------- search strategy */
+
+/* How graph g's samples find their shortest paths (every sampling call on g follows it):
+ *   KAD_SEARCH_BALANCED (default) -- section 4's balanced bidirectional BFS: the side whose
+ *       frontier has the smaller degree sum is expanded, until the two searches touch;
+ *   KAD_SEARCH_FORWARD -- a plain BFS from s, level by level until the level that reaches
+ *       t is finished: the search of the samplers the paper compares against (section 6,
+ *       where it costs m_avg arcs per sample), kept to measure what the balanced search
+ *       saves (Theorem 2).
+ * Both give a uniformly random shortest s-t path of the same pair; the paths drawn differ,
+ * so results depend on the choice (the oracle takes the same flag).  Returns KAD_EINVAL for
+ * any other value. */
+enum { KAD_SEARCH_BALANCED = 0, KAD_SEARCH_FORWARD = 1 };
+kad_status kad_graph_set_search(kad_graph *g, uint32_t search);
+kad_status kad_graph_get_search(const kad_graph *g, uint32_t *search);
+
 /* ---------------------------------------------------------------- launch shape */
 
 /* Sampler launch shape used for graph g (by kad_run, kad_sample_paths, kad_hit_counts and

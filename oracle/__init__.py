@@ -48,7 +48,7 @@ class _Params(C.Structure):
     _fields_ = [("epsilon", C.c_double), ("delta", C.c_double), ("mode", C.c_uint32),
                 ("k", C.c_uint32), ("seed", C.c_uint64), ("check_interval", C.c_uint64),
                 ("vd_override", C.c_uint32), ("c", C.c_double), ("balance_eps", C.c_double),
-                ("exact_vd_limit", C.c_double), ("threads", C.c_int32)]
+                ("exact_vd_limit", C.c_double), ("threads", C.c_int32), ("forward", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -75,6 +75,9 @@ def lib():
         L.or_sample_paths.argtypes = [C.POINTER(_Graph), u64, u32, u64, u64, C.c_int, vp, vp, vp,
                                       vp, u64, vp, vp]
         L.or_sample_paths.restype = C.c_int
+        L.or_sample_paths_search.argtypes = [C.POINTER(_Graph), u64, u32, u64, u64, C.c_int,
+                                             C.c_int, vp, vp, vp, vp, u64, vp, vp]
+        L.or_sample_paths_search.restype = C.c_int
         L.or_vertex_diameter.argtypes = [C.POINTER(_Graph), dbl, vp, vp]
         L.or_vertex_diameter.restype = C.c_int
         L.or_omega.argtypes = [dbl, dbl, u32, dbl]
@@ -171,8 +174,12 @@ class Samples:
         return self.nodes[self.path_off[k]:self.path_off[k + 1]]
 
 
-def sample_paths(g, seed: int, phase: int, first: int, count: int, threads: int = 0) -> Samples:
+def sample_paths(g, seed: int, phase: int, first: int, count: int, threads: int = 0,
+                 search: str = "balanced") -> Samples:
+    """Sample ids [first, first+count): the balanced bidirectional search of section 4, or
+    with search="forward" the plain BFS from s until t's level is done."""
     g = as_graph(g)
+    forward = {"balanced": 0, "forward": 1}[search]
     s = np.zeros(count, dtype=np.uint32)
     t = np.zeros(count, dtype=np.uint32)
     off = np.zeros(count + 1, dtype=np.uint64)
@@ -181,8 +188,9 @@ def sample_paths(g, seed: int, phase: int, first: int, count: int, threads: int 
     cap = max(16, count * 16)
     while True:
         nodes = np.zeros(cap, dtype=np.uint32)
-        rc = lib().or_sample_paths(C.byref(g.s), seed, phase, first, count, threads, _ptr(s),
-                                   _ptr(t), _ptr(off), _ptr(nodes), cap, _ptr(arcs), _ptr(bits))
+        rc = lib().or_sample_paths_search(C.byref(g.s), seed, phase, first, count, threads,
+                                          forward, _ptr(s), _ptr(t), _ptr(off), _ptr(nodes),
+                                          cap, _ptr(arcs), _ptr(bits))
         if rc == -3:
             cap *= 4
             continue
@@ -271,12 +279,13 @@ def rank_intervals(lower, upper):
 # ---------------------------------------------------------------- whole run
 
 def run(g, epsilon, delta, mode="all", k=0, seed=1, check_interval=0, vd_override=0, c=0.0,
-        balance_eps=0.0, exact_vd_limit=0.0, threads=0) -> dict:
+        balance_eps=0.0, exact_vd_limit=0.0, threads=0, search="balanced") -> dict:
     """Algorithm 1 with the batched stopping check; returns a dict of results."""
     g = as_graph(g)
     n = g.n
     p = _Params(epsilon, delta, 1 if mode == "topk" else 0, k, seed, check_interval,
-                vd_override, c, balance_eps, exact_vd_limit, threads)
+                vd_override, c, balance_eps, exact_vd_limit, threads,
+                {"balanced": 0, "forward": 1}[search])
     out = {name: np.zeros(n, dtype=np.uint64) for name in ("count", "count0")}
     for name in ("bc", "lower", "upper", "L_l", "L_u"):
         out[name] = np.zeros(n)

@@ -366,9 +366,15 @@ typedef struct {
  *    id and w in v's row order.  The two halves are completed by backtracking:
  *    a predecessor (s side, in-row order) or successor (t side, out-row order)
  *    on the level below, chosen with probability proportional to its count.
+ *
+ * With `forward` set the s side is always expanded: the plain BFS from s that
+ * runs until the level reaching t is finished (the search of the samplers the
+ * paper compares against in section 6, whose cost it calls m_avg).  The t side
+ * keeps its level 0 = {t}, so the candidate edges are the arcs (v, t) out of
+ * the s side's last level, and the path is uniform as well.
  */
 static int sample_one(const or_graph *g, ows *w, uint64_t seed, uint32_t phase, uint64_t i,
-                      osample *out) {
+                      int forward, osample *out) {
   int rc;
   const uint32_t n = g->n;
   /* pair */
@@ -407,7 +413,7 @@ static int sample_one(const or_graph *g, ows *w, uint64_t seed, uint32_t phase, 
   int met = 0;
 
   for (;;) {
-    int expand_s = ds <= dt;
+    int expand_s = forward || ds <= dt;
     const uint32_t *rp = expand_s ? g->row : g->rrow;
     const uint32_t *cl = expand_s ? g->col : g->rcol;
     uint32_t *dist_me = expand_s ? w->dist_s : w->dist_t;
@@ -552,10 +558,10 @@ static int sample_one(const or_graph *g, ows *w, uint64_t seed, uint32_t phase, 
  * path_off[k+1]), the arcs scanned and the bit length of sigma_st.  Samples
  * are independent, so the threads only split the id range.
  */
-int or_sample_paths(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t first,
-                    uint64_t count, int threads, uint32_t *s_out, uint32_t *t_out,
-                    uint64_t *path_off, uint32_t *path_nodes, uint64_t path_cap,
-                    uint64_t *arcs_out, uint64_t *sigma_bits_out) {
+int or_sample_paths_search(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t first,
+                           uint64_t count, int threads, int forward, uint32_t *s_out,
+                           uint32_t *t_out, uint64_t *path_off, uint32_t *path_nodes,
+                           uint64_t path_cap, uint64_t *arcs_out, uint64_t *sigma_bits_out) {
   if (!g || g->n < 2) return OR_EINVAL;
   uint32_t *lens = (uint32_t *)calloc(count ? count : 1, sizeof(uint32_t));
   uint32_t **paths = (uint32_t **)calloc(count ? count : 1, sizeof(uint32_t *));
@@ -583,7 +589,7 @@ int or_sample_paths(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t f
       if (err || !w || !buf) continue;
       osample o;
       o.path = buf;
-      int rc = sample_one(g, w, seed, phase, first + (uint64_t)k, &o);
+      int rc = sample_one(g, w, seed, phase, first + (uint64_t)k, forward, &o);
       if (rc) {
 #pragma omp critical
         err = rc;
@@ -626,11 +632,20 @@ int or_sample_paths(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t f
   return err;
 }
 
+/* The balanced bidirectional search (section 4). */
+int or_sample_paths(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t first,
+                    uint64_t count, int threads, uint32_t *s_out, uint32_t *t_out,
+                    uint64_t *path_off, uint32_t *path_nodes, uint64_t path_cap,
+                    uint64_t *arcs_out, uint64_t *sigma_bits_out) {
+  return or_sample_paths_search(g, seed, phase, first, count, threads, 0, s_out, t_out,
+                                path_off, path_nodes, path_cap, arcs_out, sigma_bits_out);
+}
+
 /* Hits of samples [first, first+count): count[v] += 1 for every interior node
  * v of each sampled path (section 2: X_i(v) = 1 iff v is on the path and
  * differs from s and t).  Adds the arcs scanned to *arcs. */
 static int add_hits(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t first,
-                    uint64_t count, int threads, uint64_t *cnt, uint64_t *arcs) {
+                    uint64_t count, int threads, int forward, uint64_t *cnt, uint64_t *arcs) {
   if (count == 0) return OR_OK;
   uint64_t cap = count * (uint64_t)(g->n < 64 ? g->n : 64) + 1;
   uint64_t *off = (uint64_t *)malloc((count + 1) * sizeof(uint64_t));
@@ -643,8 +658,8 @@ static int add_hits(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t f
       rc = OR_ENOMEM;
       break;
     }
-    rc = or_sample_paths(g, seed, phase, first, count, threads, NULL, NULL, off, nodes, cap, ar,
-                         NULL);
+    rc = or_sample_paths_search(g, seed, phase, first, count, threads, forward, NULL, NULL, off,
+                                nodes, cap, ar, NULL);
     if (rc != OR_ECAP) break;
     free(nodes);
     nodes = NULL;
@@ -1117,6 +1132,7 @@ typedef struct {
   double c, balance_eps;   /* 0: 0.5 and 0.001 */
   double exact_vd_limit;   /* 0: 1e9 */
   int32_t threads;
+  int32_t forward;         /* 1: forward BFS from s instead of the balanced search */
 } or_params;
 
 typedef struct {
@@ -1161,7 +1177,8 @@ int or_run(const or_graph *g, const or_params *p, or_result *r) {
 
   /* pilot: phase 0, ids 0..alpha-1 */
   r->pilot_arcs = 0;
-  if ((rc = add_hits(g, p->seed, 0, 0, r->alpha, p->threads, cnt0, &r->pilot_arcs))) return rc;
+  if ((rc = add_hits(g, p->seed, 0, 0, r->alpha, p->threads, p->forward, cnt0, &r->pilot_arcs)))
+    return rc;
   if (p->mode == 1) {
     if ((rc = or_topk_lambdas(n, p->k, cnt0, r->alpha, p->epsilon, lam_l, lam_u))) return rc;
   } else {
@@ -1177,7 +1194,7 @@ int or_run(const or_graph *g, const or_params *p, or_result *r) {
   r->stop_rule = 0;
   for (;;) {
     uint64_t b = r->omega - tau < r->interval ? r->omega - tau : r->interval;
-    if ((rc = add_hits(g, p->seed, 1, tau, b, p->threads, cnt, &r->arcs))) return rc;
+    if ((rc = add_hits(g, p->seed, 1, tau, b, p->threads, p->forward, cnt, &r->arcs))) return rc;
     tau += b;
     if (tau >= r->omega) break;
     int stop = p->mode == 1

@@ -29,6 +29,7 @@ ALL_NODES, TOPK = 0, 1
 MEM_HOST, MEM_DEVICE = 0, 1
 STOP_OMEGA, STOP_RULE, STOP_FIXED = 0, 1, 2
 SCHEDULES = {"adaptive": 0, "rk": 1, "hoeffding": 2}
+SEARCHES = {"balanced": 0, "forward": 1}
 SAMPLE_OVERFLOW, SAMPLE_CAPACITY, SAMPLE_RNG = 1, 2, 4
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
@@ -110,6 +111,8 @@ def lib():
         "kad_server_cancel": ([vp], st),
         "kad_server_destroy": ([vp], st),
         "kad_graph_set_launch": ([vp, u32, u32], st),
+        "kad_graph_set_search": ([vp, u32], st),
+        "kad_graph_get_search": ([vp, vp], st),
         "kad_graph_get_launch": ([vp, vp, vp], st),
         "kad_autotune": ([vp, vp, u32, vp, vp, vp], st),
         "kad_ctx_set_timing": ([vp, i32], st),
@@ -228,6 +231,16 @@ class Graph:
     def set_launch(self, block: int = 0, small_expansion: int = 0):
         """Sampler launch shape for this graph ((0, 0) = library default)."""
         _check(lib().kad_graph_set_launch(self.handle, block, small_expansion))
+
+    def set_search(self, search: str = "balanced"):
+        """How this graph's samples search for paths: "balanced" (section 4's balanced
+        bidirectional BFS, the default) or "forward" (a plain BFS from s until t's level)."""
+        _check(lib().kad_graph_set_search(self.handle, SEARCHES[search]))
+
+    def search(self) -> str:
+        v = C.c_uint32()
+        _check(lib().kad_graph_get_search(self.handle, C.byref(v)))
+        return {b: a for a, b in SEARCHES.items()}[v.value]
 
     def launch(self):
         b, e = C.c_uint32(), C.c_uint32()

@@ -27,6 +27,7 @@ struct GraphDev {
   uint64_t arcs;
   const uint32_t *row, *col;   // out-rows
   const uint32_t *rrow, *rcol; // in-rows (alias the out-rows when undirected)
+  uint32_t forward = 0;        // nonzero: always expand the s side (a plain BFS from s)
 };
 
 // Per-slot working state: one slot per resident sampler workgroup.  Each slot owns
@@ -57,7 +58,7 @@ struct SampleSeg {
   uint32_t begin;
   uint32_t id_base;
   uint32_t wide_only;  // nonzero: sampled by the wide-count kernel only (high diameter)
-  uint32_t pad;
+  uint32_t forward;    // nonzero: the forward search (GraphDev::forward)
 };
 
 // Working memory of the wide-count resampling (wide_kernel): the sampler slots' node

@@ -600,7 +600,7 @@ kad_status Engine::launch(Lane &L, Tick &t) {
     sg.begin = pc.begin;
     sg.id_base = (uint32_t)pc.q->base();
     sg.wide_only = pc.q->ovc == 2 ? 1u : 0u;
-    sg.pad = 0;
+    sg.forward = g->search == KAD_SEARCH_FORWARD ? 1u : 0u;
   }
   // snapshots, layer by layer
   std::vector<GatherDesc> gat;

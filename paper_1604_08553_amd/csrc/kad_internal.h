@@ -188,6 +188,7 @@ struct kad_graph {
   uint32_t maxdeg = 0;  // largest out- or in-degree
   kad::LaunchShape shape;  // sampler launch shape (kad_graph_set_launch / kad_autotune)
   bool shape_set = false;
+  uint32_t search = 0;     // KAD_SEARCH_BALANCED or KAD_SEARCH_FORWARD
 };
 
 namespace kad {

@@ -1042,6 +1042,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       g.col = S.col;
       g.rrow = S.rrow;
       g.rcol = S.rcol;
+      g.forward = S.forward;
       seed = S.seed;
       phase = S.phase;
       i = S.first + (k - S.begin);
@@ -1102,7 +1103,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
     bool met = false;
     uint32_t needed = 0;
     for (;;) {
-      const uint32_t me = L.deg[0] <= L.deg[1] ? 0u : 1u;  // ties expand the s side
+      // ties expand the s side; the forward search expands it always
+      const uint32_t me = (g.forward || L.deg[0] <= L.deg[1]) ? 0u : 1u;
       const uint32_t ot = 1u - me;
       const uint32_t fb = L.fb[me], fe = L.fe[me];
       const uint32_t ob = L.fb[ot], oe = L.fe[ot];
@@ -1822,6 +1824,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       g.col = S.col;
       g.rrow = S.rrow;
       g.rcol = S.rcol;
+      g.forward = S.forward;
       seed = S.seed;
       phase = S.phase;
       i = S.first + (k - S.begin);
@@ -1866,7 +1869,8 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
     // the expansion that met: its side, frontier and the other side's tag (uniform)
     uint32_t m_side = 0, m_fb = 0, m_fe = 0, m_otag = 0;
     for (;;) {
-      const uint32_t me = L.deg[0] <= L.deg[1] ? 0u : 1u;  // ties expand the s side
+      // ties expand the s side; the forward search expands it always
+      const uint32_t me = (g.forward || L.deg[0] <= L.deg[1]) ? 0u : 1u;
       const uint32_t ot = 1u - me;
       const uint32_t l = L.lvl[me], lo_ = L.lvl[ot];
       const uint32_t fb = LV(me, l, LV_LO), fe = LV(me, l, LV_HI);

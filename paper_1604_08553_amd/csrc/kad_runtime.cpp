@@ -113,6 +113,7 @@ GraphDev dev_view(const kad_graph *g) {
   d.col = g->d_col;
   d.rrow = g->directed ? g->d_rrow : g->d_row;
   d.rcol = g->directed ? g->d_rcol : g->d_col;
+  d.forward = g->search == KAD_SEARCH_FORWARD ? 1u : 0u;
   return d;
 }
 
@@ -1523,6 +1524,20 @@ kad_status kad_graph_set_launch(kad_graph *g, uint32_t block, uint32_t small_exp
   g->shape.block = (int)block;
   g->shape.small_exp = small_expansion;
   g->shape_set = true;
+  return KAD_OK;
+}
+
+kad_status kad_graph_set_search(kad_graph *g, uint32_t search) {
+  if (!g) return fail(KAD_EINVAL, "NULL graph");
+  if (search != KAD_SEARCH_BALANCED && search != KAD_SEARCH_FORWARD)
+    return fail(KAD_EINVAL, "search must be KAD_SEARCH_BALANCED or KAD_SEARCH_FORWARD");
+  g->search = search;
+  return KAD_OK;
+}
+
+kad_status kad_graph_get_search(const kad_graph *g, uint32_t *search) {
+  if (!g || !search) return fail(KAD_EINVAL, "NULL argument");
+  *search = g->search;
   return KAD_OK;
 }
 

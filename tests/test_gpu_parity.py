@@ -352,3 +352,53 @@ def test_run_fixed_schedule(kad, ctx, orc, schedule):
     assert np.array_equal(r["bc"], b / float(tau))
     assert np.array_equal(r["lower"], r["bc"] - 0.02) and np.array_equal(r["upper"], r["bc"] + 0.02)
     G.close()
+
+
+@pytest.mark.parametrize("name", ["er2000", "dcl", "grid", "kbip", "union"])
+def test_paths_forward_search(kad, ctx, orc, name):
+    """The forward search (a plain BFS from s until t's level) gives the oracle's paths and
+    arcs; on the 500x500 grid its counts pass 128 bits and go to the wide-count kernel."""
+    g, cnt = {"er2000": (gg.workload("er2000"), 4099),
+              "dcl": (gg.chung_lu_directed(200_000, 2.5, 2.1, 10.0, 9), 1500),
+              "grid": (gg.grid(120, 120), 200),
+              "kbip": (gg.complete_bipartite(300, 400), 500),
+              "union": (gg.disjoint_union(gg.path_graph(90), gg.star_graph(300),
+                                          gg.grid(20, 30)), 3000)}[name]
+    G = kad.Graph(ctx, g)
+    G.set_search("forward")
+    assert G.search() == "forward"
+    _say("forward search", name)
+    A = kad.sample_paths(ctx, G, 3, 1, 11, cnt)
+    B = orc.sample_paths(g, 3, 1, 11, cnt, threads=16, search="forward")
+    assert (A["flags"] == 0).all()
+    assert np.array_equal(A["s"], B.s) and np.array_equal(A["t"], B.t)
+    assert np.array_equal(A["arcs"], B.arcs)
+    assert np.array_equal(A["path_off"], B.path_off.astype(np.uint64))
+    assert np.array_equal(A["nodes"], B.nodes)
+    G.close()
+
+
+def test_run_forward_search_equals_oracle(kad, ctx, orc):
+    """Algorithm 1 with the forward search, and the RK algorithm (fixed RK sample count with
+    the forward search: the comparison system of section 6) on the same graph."""
+    g = gg.chung_lu(20_000, 2.5, 8.0, 12)
+    G = kad.Graph(ctx, g)
+    G.set_search("forward")
+    a = kad.run(ctx, G, epsilon=0.01, delta=0.1, seed=4)
+    b = orc.run(g, 0.01, 0.1, seed=4, threads=16, search="forward")
+    assert a["tau"] == b["tau"] and a["stop_reason"] == b["stop_rule"]
+    assert a["arcs_scanned"] == b["arcs"] and a["pilot_arcs_scanned"] == b["pilot_arcs"]
+    assert np.array_equal(a["count"], b["count"])
+    assert np.array_equal(a["lower"], b["lower"]) and np.array_equal(a["upper"], b["upper"])
+    r = kad.run(ctx, G, epsilon=0.02, delta=0.1, seed=4, schedule="rk")
+    S = orc.sample_paths(g, 4, 1, 0, r["tau"], threads=16, search="forward")
+    cnt = np.zeros(g.n, dtype=np.uint64)
+    for k in range(r["tau"]):
+        p = S.path(k)
+        cnt[p[1:-1]] += 1
+    assert np.array_equal(r["count"], cnt) and r["arcs_scanned"] == int(S.arcs.sum())
+    # the balanced search scans far fewer arcs for the same kind of run
+    G.set_search("balanced")
+    c = kad.run(ctx, G, epsilon=0.02, delta=0.1, seed=4, schedule="rk")
+    assert c["arcs_scanned"] * 3 < r["arcs_scanned"]
+    G.close()

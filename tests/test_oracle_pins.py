@@ -750,3 +750,86 @@ def test_topk_lambdas_hand_worked(oracle_lib):
     assert np.allclose([ll[1], lu[1], ll[4], lu[4]], [0.05] * 4, atol=1e-12, rtol=0)
     # b0(v_k) - lambda_L(v_k) = 0.55: node 2 (0.10) gets 0.45, node 3 (0.00) 0.55
     assert np.allclose([ll[2], lu[2], ll[3], lu[3]], [1.0, 0.45, 1.0, 0.55], atol=1e-12, rtol=0)
+
+
+# ----------------------------------------------------------------------------- forward search
+#
+# The search of the samplers section 6 compares against: a BFS from s only, level by level,
+# until the level that reaches t is finished.  Its arcs follow from the levels of s alone.
+
+
+def test_forward_search_closed_forms(oracle_lib):
+    # star, centre 0: leaf -> leaf expands the leaf (1 arc) and the centre's whole row
+    # (n-1 arcs): n; centre -> leaf: n-1; leaf -> centre: 1
+    n = 9
+    S = oracle_lib.sample_paths(gg.star_graph(n), 2, 1, 0, 3000, search="forward")
+    for i in range(3000):
+        s, t = int(S.s[i]), int(S.t[i])
+        want = 1 if t == 0 else (n - 1 if s == 0 else n)
+        assert int(S.arcs[i]) == want, (s, t)
+    # path P_n: levels 0..d-1 of s are expanded, 2 arcs for s and 4 for each later level
+    # when s is at least d from both ends: 4d - 2
+    n = 40
+    S = oracle_lib.sample_paths(gg.path_graph(n), 8, 1, 0, 20000, threads=4, search="forward")
+    checked = 0
+    for i in range(20000):
+        s, t = int(S.s[i]), int(S.t[i])
+        d = abs(s - t)
+        if min(s, n - 1 - s) >= d:
+            assert int(S.arcs[i]) == 4 * d - 2, (s, t)
+            checked += 1
+    assert checked > 1000
+    # the directed tie gadget: (s, q) -- the balanced search stops after q's r in-arcs; the
+    # forward search expands s (k+1 arcs), {m, p_*} (1 arc, m -> t), {t} (no arcs): k+2,
+    # disconnected
+    g, P = _gadget_directed_tie()
+    k, q0 = P["k"], P["q0"]
+    S, seen = _pair_samples(oracle_lib, g, {(0, q0): None, (0, 1): None})
+    F = oracle_lib.sample_paths(g, 3, 1, 0, 40000, threads=4, search="forward")
+    for i in seen[(0, q0)]:
+        assert int(S.arcs[i]) == P["r"] and int(F.arcs[i]) == k + 2 and len(F.path(i)) == 0
+    for i in seen[(0, 1)]:
+        assert int(F.arcs[i]) == k + 2 and [int(x) for x in F.path(i)] == [0, P["m"], 1]
+
+
+@pytest.mark.parametrize("which", ["grid", "undirected", "directed"])
+def test_forward_search_paths_uniform(oracle_lib, which):
+    """Chi-square of sampled (s, t, path) triples against 1/(n(n-1) sigma_st), forward search."""
+    import networkx as nx
+    from scipy.stats import chi2
+    g = {"grid": gg.grid(3, 4), "undirected": gg.gnp(9, 0.35, 3),
+         "directed": gg.gnp(8, 0.35, 2, directed=True)}[which]
+    G = _nx(g)
+    N = 150000
+    S = oracle_lib.sample_paths(g, 23, 1, 0, N, threads=4, search="forward")
+    index, expect = {}, []
+    n = g.n
+    for s in range(n):
+        for t in range(n):
+            if s == t or not nx.has_path(G, s, t):
+                continue
+            paths = list(nx.all_shortest_paths(G, s, t))
+            for p in paths:
+                index[tuple(p)] = len(expect)
+                expect.append(N / (n * (n - 1)) / len(paths))
+    obs = np.zeros(len(expect))
+    for k in range(N):
+        p = tuple(int(x) for x in S.path(k))
+        if p:
+            obs[index[p]] += 1
+    expect = np.array(expect)
+    assert abs(obs.sum() - expect.sum()) < 6 * math.sqrt(N)
+    stat = ((obs - expect) ** 2 / expect).sum()
+    assert chi2.sf(stat, len(expect)) > 1e-5, (which, stat, len(expect))
+
+
+def test_forward_search_same_pairs_scans_more(oracle_lib):
+    """Same sample ids give the same pairs and paths of the same length (both searches
+    return shortest paths); on a power-law graph the forward search scans several times
+    the arcs of the balanced one (section 6, Theorem 2)."""
+    g = gg.chung_lu(3000, 2.3, 6.0, 7)
+    B = oracle_lib.sample_paths(g, 5, 1, 0, 3000, threads=4)
+    F = oracle_lib.sample_paths(g, 5, 1, 0, 3000, threads=4, search="forward")
+    assert np.array_equal(B.s, F.s) and np.array_equal(B.t, F.t)
+    assert np.array_equal(np.diff(B.path_off.astype(np.int64)), np.diff(F.path_off.astype(np.int64)))
+    assert F.arcs.mean() > 3 * B.arcs.mean()
