@@ -20,6 +20,11 @@ Other workloads (--workload):
             one step = all 256 adaptive runs through the multi-query engine
             (kad_run_batch); the same 256 runs one after another through kad_run are
             timed beside it, and the results are checked identical.
+  exponent  Theorem 2 / Fig. 2: arcs visited per sampled path with the balanced search and
+            with the forward BFS from s, on the appendix's random-graph models (Chung-Lu,
+            configuration model, Norros-Reittu, generalized random graph; --models) with
+            power-law exponents --betas at mean degree --mean-degree, n in --sizes; fits
+            arcs ~ n^alpha per model, exponent and search (value = mean balanced alpha).
   serve     the serving workload: 33 resident graphs (er2000, cl1m, 30 Chung-Lu graphs of
             1e4..1e6 nodes, the 2000x2000 grid with 5% of edges deleted), a Poisson stream
             of --queries queries at --rate per second (seed 7), each on a uniformly drawn
@@ -350,6 +355,75 @@ def bench_serve(args, torch, gg, kad):
     print(json.dumps(out), flush=True)
 
 
+def _gen_model(spec):
+    import graphgen as gg
+    model, n, beta, mean, seed = spec
+    g = gg.random_model(model, n, beta, mean, seed)
+    return spec, g
+
+
+def bench_exponent(args, torch, gg, kad):
+    """Theorem 2 and Fig. 2: arcs visited per sampled path, balanced bidirectional search
+    against the forward BFS from s, on the appendix's random-graph models as n grows."""
+    import numpy as np
+    from concurrent.futures import ProcessPoolExecutor
+    models = args.models.split(",")
+    betas = [float(b) for b in args.betas.split(",")]
+    sizes = [int(float(x)) for x in args.sizes.split(",")]
+    specs = [(m, n, b, args.mean_degree, 77 + i) for m in models for b in betas
+             for i, n in enumerate(sizes)]
+    t0 = time.perf_counter()
+    workers = min(len(specs), max(1, min(16, host_threads())))
+    graphs = {}
+    with ProcessPoolExecutor(max_workers=workers) as ex:
+        for spec, g in ex.map(_gen_model, specs):
+            graphs[spec] = g
+            print(f"[bench] generated {g.name}: n={g.n} arcs={g.arcs}", file=sys.stderr, flush=True)
+    gen_s = time.perf_counter() - t0
+    ctx = kad.Context(0)
+    rows = []
+    for spec in specs:
+        g = graphs.pop(spec)
+        G = kad.Graph(ctx, g)
+        row = {"model": spec[0], "beta": spec[2], "n": g.n, "arcs": g.arcs}
+        for search in ("balanced", "forward"):
+            G.set_search(search)
+            A = kad.sample_paths(ctx, G, 1, 1, 0, args.exp_samples)
+            arcs = A["arcs"].astype(np.float64)
+            conn = np.diff(A["path_off"].astype(np.int64)) > 0
+            row[search] = {"arcs_per_sample": float(arcs.mean()),
+                           "arcs_per_connected_sample": float(arcs[conn].mean()) if conn.any() else None,
+                           "connected": float(conn.mean()),
+                           # the paper's Fig. 2 exponent: log(m_avg) / log(m)
+                           "alpha_fig2": float(np.log(arcs.mean()) / np.log(g.arcs))}
+        print(f"[bench] {g.name}: balanced {row['balanced']['arcs_per_sample']:.0f}, forward "
+              f"{row['forward']['arcs_per_sample']:.0f} arcs/sample", file=sys.stderr, flush=True)
+        rows.append(row)
+        G.close()
+    ctx.close()
+    fits = []
+    for m in models:
+        for b in betas:
+            rs = [r for r in rows if r["model"] == m and r["beta"] == b]
+            x = np.log([r["n"] for r in rs])
+            fit = {"model": m, "beta": b,
+                   "theorem2": 0.5 if b >= 3 else (4 - b) / 2}
+            for search in ("balanced", "forward"):
+                y = np.log([r[search]["arcs_per_sample"] for r in rs])
+                fit[f"alpha_{search}"] = float(np.polyfit(x, y, 1)[0])
+            fits.append(fit)
+    out = {"metric": "exponent alpha of arcs visited per sampled path (arcs ~ n^alpha)",
+           "value": float(np.mean([f["alpha_balanced"] for f in fits])),
+           "unit": "exponent", "n_gpus": 1, "steps": 1, "warmup": 0, "ms_per_step": None,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None,
+           "dtype": "u128", "data": "synthetic",
+           "config": {"workload": f"random-graph models {models}, beta {betas}, mean degree "
+                                  f"{args.mean_degree}, n in {sizes}, {args.exp_samples} "
+                                  "samples each, balanced and forward search"},
+           "generation_s": gen_s, "fits": fits, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -382,6 +456,11 @@ def main():
                     help="serve: seconds after the last arrival before running queries are canceled")
     ap.add_argument("--exclude-grid", action="store_true",
                     help="serve: leave the 2000x2000 grid (and its queries) out")
+    ap.add_argument("--models", default="cl,cm,nr,grg", help="exponent: random-graph models")
+    ap.add_argument("--betas", default="2.5,3.5", help="exponent: power-law exponents")
+    ap.add_argument("--sizes", default="1e4,3e4,1e5,3e5,1e6", help="exponent: node counts")
+    ap.add_argument("--mean-degree", type=float, default=10.0, help="exponent: mean degree")
+    ap.add_argument("--exp-samples", type=int, default=1024, help="exponent: samples per graph")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM counters)")
     args = ap.parse_args()
@@ -420,6 +499,8 @@ def main():
         return bench_batch(args, torch, gg, kad)
     if args.workload == "serve":
         return bench_serve(args, torch, gg, kad)
+    if args.workload == "exponent":
+        return bench_exponent(args, torch, gg, kad)
     t0 = time.perf_counter()
     csr = gg.workload(args.workload)
     gen_s = time.perf_counter() - t0

@@ -25,7 +25,8 @@ __all__ = [
     "CSR", "csr_from_edges", "er_lcc", "chung_lu", "chung_lu_directed",
     "grid", "damaged_grid", "path_graph", "star_graph", "cycle_graph",
     "complete_graph", "complete_bipartite", "disjoint_union", "gnp",
-    "hub_layers", "batch_family_spec", "batch_graph", "serve_family_spec", "serve_graph", "serve_queries",
+    "hub_layers", "configuration_model", "norros_reittu", "generalized_random_graph",
+    "random_model", "batch_family_spec", "batch_graph", "serve_family_spec", "serve_graph", "serve_queries",
     "workload",
 ]
 
@@ -297,7 +298,7 @@ def _sample_cells(rng, ncells: int, p: float) -> np.ndarray:
     return np.concatenate(out)
 
 
-def _chung_lu_arcs(rng, wo, wi, in_order, wsum, directed):
+def _chung_lu_arcs(rng, wo, wi, in_order, wsum, directed, model="cl"):
     """Sample pairs (u, v) with independent probability min(1, wo_u wi_v / W).
 
     ``wo`` is descending by node id; ``in_order`` lists node ids by descending
@@ -316,7 +317,11 @@ def _chung_lu_arcs(rng, wo, wi, in_order, wsum, directed):
             b0, b1 = bi[b], bi[b + 1]
             if not directed and b0 < a0:
                 continue                       # undirected: only bucket pairs with b >= a
-            pmax = min(1.0, wo[a0] * wi[b0] / wsum)
+            if model == "cl":
+                pmax = min(1.0, wo[a0] * wi[b0] / wsum)
+            else:  # generalized random graph: x / (1 + x), increasing in x
+                x0 = wo[a0] * wi[b0] / wsum
+                pmax = x0 / (1.0 + x0)
             nb = b1 - b0
             cells = _sample_cells(rng, (a1 - a0) * nb, pmax)
             if cells.size == 0:
@@ -324,7 +329,11 @@ def _chung_lu_arcs(rng, wo, wi, in_order, wsum, directed):
             u = a0 + cells // nb
             vpos = b0 + cells % nb
             v = in_order[vpos]
-            p = np.minimum(1.0, wo[u] * wi[vpos] / wsum)
+            if model == "cl":
+                p = np.minimum(1.0, wo[u] * wi[vpos] / wsum)
+            else:
+                x = wo[u] * wi[vpos] / wsum
+                p = x / (1.0 + x)
             acc = rng.random(cells.size) * pmax < p
             if directed:
                 acc &= u != v
@@ -367,6 +376,79 @@ def chung_lu_directed(n: int, beta_out: float, beta_in: float, mean_deg: float,
                           name=f"dcl{n}_bo{beta_out}_bi{beta_in}_d{mean_deg}_s{seed}",
                           meta={"model": "chung-lu-directed", "beta_out": beta_out,
                                 "beta_in": beta_in, "mean_deg": mean_deg, "seed": seed})
+
+
+# ----------------------------------------------------------------------------
+# the other random-graph models of the paper's appendix on random graphs
+# ----------------------------------------------------------------------------
+#
+# All are undirected with n Pareto(beta) weights w_v (the quantiles of _pareto_profile)
+# scaled to mean weight mean_deg, and M = sum of the weights:
+#   * configuration model: node v gets round(w_v) (at least 1) half-edges, one more on a
+#     seeded random node if the total is odd, paired by a seeded permutation; self-loops
+#     and repeated edges are erased;
+#   * Norros-Reittu: {u, v} is an edge with probability 1 - exp(-w_u w_v / M), i.e. when a
+#     Poisson(w_u w_v / M) number of parallel edges is at least one.  Drawn exactly without
+#     evaluating exp: Poisson(M/2) ordered endpoint pairs, each endpoint independently with
+#     probability w/M, give every unordered pair a Poisson(w_u w_v / M) count;
+#   * generalized random graph: probability x/(1+x), x = w_u w_v / M (the Chung-Lu sampler
+#     with that function);
+#   * Chung-Lu (chung_lu above): probability min(1, x), with the weight scale tuned to the
+#     realised mean degree.
+
+
+def _scaled_weights(n: int, beta: float, mean_deg: float) -> np.ndarray:
+    c = _pareto_profile(n, beta)
+    return c * (mean_deg * n / math.fsum(c.tolist()))
+
+
+def configuration_model(n: int, beta: float, mean_deg: float, seed: int) -> CSR:
+    rng = np.random.default_rng(seed)
+    w = _scaled_weights(n, beta, mean_deg)
+    deg = np.maximum(1, np.rint(w)).astype(np.int64)
+    if int(deg.sum()) % 2 == 1:
+        deg[int(rng.integers(0, n))] += 1
+    stubs = np.repeat(np.arange(n, dtype=np.int64), deg)
+    stubs = stubs[rng.permutation(stubs.size)]
+    return csr_from_edges(n, stubs[0::2], stubs[1::2], False,
+                          name=f"cm{n}_b{beta}_d{mean_deg}_s{seed}",
+                          meta={"model": "configuration", "beta": beta, "mean_deg": mean_deg,
+                                "seed": seed})
+
+
+def norros_reittu(n: int, beta: float, mean_deg: float, seed: int) -> CSR:
+    rng = np.random.default_rng(seed)
+    w = _scaled_weights(n, beta, mean_deg)
+    cum = np.cumsum(w)
+    total = float(cum[-1])
+    pairs = int(rng.poisson(total / 2.0))
+    u = np.searchsorted(cum, rng.random(pairs) * total, side="right")
+    v = np.searchsorted(cum, rng.random(pairs) * total, side="right")
+    u = np.minimum(u, n - 1)
+    v = np.minimum(v, n - 1)
+    return csr_from_edges(n, u, v, False, name=f"nr{n}_b{beta}_d{mean_deg}_s{seed}",
+                          meta={"model": "norros-reittu", "beta": beta, "mean_deg": mean_deg,
+                                "seed": seed})
+
+
+def generalized_random_graph(n: int, beta: float, mean_deg: float, seed: int) -> CSR:
+    rng = np.random.default_rng(seed)
+    w = _scaled_weights(n, beta, mean_deg)
+    wsum = math.fsum(w.tolist())
+    s, d = _chung_lu_arcs(rng, w, w, np.arange(n, dtype=np.int64), wsum, False, model="grg")
+    return csr_from_edges(n, s, d, False, name=f"grg{n}_b{beta}_d{mean_deg}_s{seed}",
+                          meta={"model": "generalized-random-graph", "beta": beta,
+                                "mean_deg": mean_deg, "seed": seed})
+
+
+RANDOM_MODELS = {"cl": lambda n, b, d, s: chung_lu(n, b, d, s),
+                 "cm": configuration_model, "nr": norros_reittu,
+                 "grg": generalized_random_graph}
+
+
+def random_model(model: str, n: int, beta: float, mean_deg: float, seed: int) -> CSR:
+    """One of the appendix's random-graph models: "cl", "cm", "nr" or "grg"."""
+    return RANDOM_MODELS[model](n, beta, mean_deg, seed)
 
 
 # ----------------------------------------------------------------------------
