@@ -46,6 +46,10 @@ typedef enum {
 
 enum { KAD_MEM_HOST = 0, KAD_MEM_DEVICE = 1 };
 enum { KAD_ALL_NODES = 0, KAD_TOPK = 1 };
+/* what the betweenness is estimated for (kad_params.target): the nodes, or the edges
+ * (section 1: the method adapts to the centrality of edges; a sampled path hits every edge
+ * on it, and bc(e) = 1/(n(n-1)) sum over ordered pairs s != t of sigma_st(e)/sigma_st) */
+enum { KAD_TARGET_NODES = 0, KAD_TARGET_EDGES = 1 };
 enum { KAD_STOP_OMEGA = 0, KAD_STOP_RULE = 1, KAD_STOP_FIXED = 2 };
 /* sample schedules (kad_params.schedule) */
 enum {
@@ -122,6 +126,12 @@ typedef struct {
                               stopping check, and report [bc - eps, bc + eps] (kad_run only) */
   double c;                /* constant of the sample cap omega; 0 = 0.5 */
   double balance_eps;      /* epsilon of computeDelta (Algorithm 2); 0 = 0.001 */
+  uint32_t target;         /* KAD_TARGET_NODES (0) or KAD_TARGET_EDGES: the items of the run.
+                              With edges every per-item array has one entry per edge id
+                              (kad_graph_edge_ids), k counts edges, the union bounds run over
+                              the edges, and the cap omega uses floor(log2(max(VD-1,1))) + 1
+                              in place of floor(log2(max(VD-2,1))) + 1 (a path has at most
+                              VD - 1 edges).  kad_run only (the engine refuses it). */
 } kad_params;
 
 typedef struct {
@@ -156,6 +166,7 @@ typedef struct {
      returns KAD_ETOOSMALL with topk_len set to the number needed. */
   uint32_t topk_cap, topk_len;
   uint32_t *topk_node, *rank_lo, *rank_hi;
+  uint64_t items;          /* entries of the per-item arrays: n, or the number of edges */
 } kad_result;
 
 /* Run the adaptive algorithm (Algorithm 1) on the GPU: vertex diameter (host), omega,
@@ -260,6 +271,19 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
 kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                                   uint64_t first, uint64_t count, uint64_t *count_dev,
                                   uint64_t *arcs_dev, uint32_t *flags_dev, void *hip_stream);
+
+/* Edge hit counts of sample ids [first, first+count) of `phase`: count_out[e] (host, one
+ * entry per edge id) is incremented by the number of sampled paths that contain edge e. */
+kad_status kad_edge_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                               uint64_t first, uint64_t count, uint64_t *count_out,
+                               uint64_t *arcs_scanned, void *hip_stream);
+
+/* Edges of g: *count = arcs (directed) or arcs / 2 (undirected). */
+kad_status kad_graph_edge_count(const kad_graph *g, uint64_t *count);
+/* Edge id of every arc position (host uint32[arcs]): a directed graph's edge is its arc's
+ * position in the out-rows; an undirected edge {u, v} is the rank of its arc u -> v (u < v)
+ * in CSR order, and both of its arcs carry that id. */
+kad_status kad_graph_edge_ids(const kad_graph *g, uint32_t *eid);
 
 /* ---------------------------------------------------------------- host statistics */
 /* These run on the CPU only (no device needed); binary64, no FMA contraction. */

@@ -48,7 +48,8 @@ class _Params(C.Structure):
     _fields_ = [("epsilon", C.c_double), ("delta", C.c_double), ("mode", C.c_uint32),
                 ("k", C.c_uint32), ("seed", C.c_uint64), ("check_interval", C.c_uint64),
                 ("vd_override", C.c_uint32), ("c", C.c_double), ("balance_eps", C.c_double),
-                ("exact_vd_limit", C.c_double), ("threads", C.c_int32), ("forward", C.c_int32)]
+                ("exact_vd_limit", C.c_double), ("threads", C.c_int32), ("forward", C.c_int32),
+                ("edges", C.c_int32)]
 
 
 class _Result(C.Structure):
@@ -106,6 +107,17 @@ def lib():
         L.or_brandes.restype = C.c_int
         L.or_sigma_st.argtypes = [C.POINTER(_Graph), u32, u32, vp, u32]
         L.or_sigma_st.restype = C.c_int64
+        L.or_edge_count.argtypes = [C.POINTER(_Graph)]
+        L.or_edge_count.restype = u64
+        L.or_edge_ids.argtypes = [C.POINTER(_Graph), vp]
+        L.or_edge_ids.restype = C.c_int
+        L.or_edge_hits.argtypes = [C.POINTER(_Graph), u64, u32, u64, u64, C.c_int, C.c_int, vp,
+                                   vp]
+        L.or_edge_hits.restype = C.c_int
+        L.or_edge_brandes.argtypes = [C.POINTER(_Graph), vp]
+        L.or_edge_brandes.restype = C.c_int
+        L.or_omega_edges.argtypes = [dbl, dbl, u32, dbl]
+        L.or_omega_edges.restype = u64
         _lib = L
     return _lib
 
@@ -279,13 +291,16 @@ def rank_intervals(lower, upper):
 # ---------------------------------------------------------------- whole run
 
 def run(g, epsilon, delta, mode="all", k=0, seed=1, check_interval=0, vd_override=0, c=0.0,
-        balance_eps=0.0, exact_vd_limit=0.0, threads=0, search="balanced") -> dict:
-    """Algorithm 1 with the batched stopping check; returns a dict of results."""
+        balance_eps=0.0, exact_vd_limit=0.0, threads=0, search="balanced",
+        target="nodes") -> dict:
+    """Algorithm 1 with the batched stopping check; returns a dict of results (per-item
+    arrays: one entry per node, or per edge id with target="edges")."""
     g = as_graph(g)
-    n = g.n
+    edges = {"nodes": 0, "edges": 1}[target]
+    n = edge_count(g) if edges else g.n
     p = _Params(epsilon, delta, 1 if mode == "topk" else 0, k, seed, check_interval,
                 vd_override, c, balance_eps, exact_vd_limit, threads,
-                {"balanced": 0, "forward": 1}[search])
+                {"balanced": 0, "forward": 1}[search], edges)
     out = {name: np.zeros(n, dtype=np.uint64) for name in ("count", "count0")}
     for name in ("bc", "lower", "upper", "L_l", "L_u"):
         out[name] = np.zeros(n)
@@ -316,3 +331,43 @@ def sigma_st(g, s, t, words=64):
     if d < 0:
         return -1, 0
     return d, sum(int(buf[j]) << (64 * j) for j in range(words))
+
+
+# ---------------------------------------------------------------- edge betweenness
+
+def edge_count(g) -> int:
+    """Edges whose betweenness is estimated: arcs (directed) or arcs / 2 (undirected)."""
+    g = as_graph(g)
+    return int(lib().or_edge_count(C.byref(g.s)))
+
+
+def edge_ids(g) -> np.ndarray:
+    """Edge id of every arc position (directed: the position; undirected: the rank of the
+    edge's u < v arc, shared by both arcs)."""
+    g = as_graph(g)
+    eid = np.zeros(max(int(g.col.size), 1), dtype=np.uint32)
+    _check(lib().or_edge_ids(C.byref(g.s), _ptr(eid)))
+    return eid[:int(g.col.size)]
+
+
+def edge_hits(g, seed: int, phase: int, first: int, count: int, threads: int = 0,
+              search: str = "balanced"):
+    """(hits per edge id, arcs scanned) of sample ids [first, first+count)."""
+    g = as_graph(g)
+    cnt = np.zeros(max(edge_count(g), 1), dtype=np.uint64)
+    arcs = np.zeros(1, dtype=np.uint64)
+    _check(lib().or_edge_hits(C.byref(g.s), seed, phase, first, count, threads,
+                              {"balanced": 0, "forward": 1}[search], _ptr(cnt), _ptr(arcs)))
+    return cnt[:edge_count(g)], int(arcs[0])
+
+
+def edge_brandes(g) -> np.ndarray:
+    """Exact edge betweenness (ordered-pair normalisation, indexed by edge id)."""
+    g = as_graph(g)
+    ebc = np.zeros(max(edge_count(g), 1))
+    _check(lib().or_edge_brandes(C.byref(g.s), _ptr(ebc)))
+    return ebc[:edge_count(g)]
+
+
+def omega_edges(lam: float, delta: float, vd: int, c: float = 0.5) -> int:
+    return int(lib().or_omega_edges(lam, delta, vd, c))

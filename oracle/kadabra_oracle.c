@@ -679,6 +679,156 @@ static int add_hits(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t f
 }
 
 /* ------------------------------------------------------------------------- */
+/* Edge betweenness (section 1: the method adapts to the centrality of edges):  */
+/* bc(e) = 1/(n(n-1)) * sum over ordered pairs s != t of sigma_st(e)/sigma_st,   */
+/* with sigma_st(e) the shortest s-t paths through e; a sample hits every edge  */
+/* of its path.  Edge ids: a directed graph's edge is its arc's CSR position; an */
+/* undirected edge {u, v} is the rank of its arc u -> v (u < v) in CSR order,    */
+/* and both of its arcs map to that id.                                         */
+/* ------------------------------------------------------------------------- */
+uint64_t or_edge_count(const or_graph *g) { return g->directed ? g->arcs : g->arcs / 2; }
+
+/* position of the arc a -> b in a's out-row (rows are sorted), or UINT64_MAX */
+static uint64_t arc_pos(const or_graph *g, uint32_t a, uint32_t b) {
+  uint64_t lo = g->row[a], hi = g->row[a + 1];
+  while (lo < hi) {
+    uint64_t mid = (lo + hi) / 2;
+    if (g->col[mid] < b) lo = mid + 1;
+    else hi = mid;
+  }
+  return (lo < g->row[a + 1] && g->col[lo] == b) ? lo : UINT64_MAX;
+}
+
+int or_edge_ids(const or_graph *g, uint32_t *eid) {
+  if (g->directed) {
+    for (uint64_t e = 0; e < g->arcs; ++e) eid[e] = (uint32_t)e;
+    return OR_OK;
+  }
+  uint32_t next = 0;
+  for (uint32_t u = 0; u < g->n; ++u) {
+    for (uint32_t e = g->row[u]; e < g->row[u + 1]; ++e) {
+      uint32_t v = g->col[e];
+      if (v < u) continue;
+      uint64_t back = arc_pos(g, v, u);
+      if (back == UINT64_MAX) return OR_EINVAL; /* not symmetric */
+      eid[e] = next;
+      eid[back] = next;
+      next++;
+    }
+  }
+  return OR_OK;
+}
+
+/* hits of samples [first, first+count) on the edges of their paths: cnt[eid] += 1 */
+static int add_edge_hits(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t first,
+                         uint64_t count, int threads, int forward, const uint32_t *eid,
+                         uint64_t *cnt, uint64_t *arcs) {
+  if (count == 0) return OR_OK;
+  uint64_t cap = count * (uint64_t)(g->n < 64 ? g->n : 64) + 1;
+  uint64_t *off = (uint64_t *)malloc((count + 1) * sizeof(uint64_t));
+  uint64_t *ar = (uint64_t *)malloc(count * sizeof(uint64_t));
+  uint32_t *nodes = NULL;
+  int rc;
+  for (;;) {
+    nodes = (uint32_t *)malloc(cap * sizeof(uint32_t));
+    if (!off || !ar || !nodes) {
+      rc = OR_ENOMEM;
+      break;
+    }
+    rc = or_sample_paths_search(g, seed, phase, first, count, threads, forward, NULL, NULL, off,
+                                nodes, cap, ar, NULL);
+    if (rc != OR_ECAP) break;
+    free(nodes);
+    nodes = NULL;
+    cap *= 4;
+  }
+  if (rc == OR_OK) {
+    for (uint64_t k = 0; k < count && rc == OR_OK; ++k) {
+      *arcs += ar[k];
+      for (uint64_t j = off[k]; j + 1 < off[k + 1]; ++j) {
+        uint64_t pos = arc_pos(g, nodes[j], nodes[j + 1]);
+        if (pos == UINT64_MAX) {
+          rc = OR_EINVAL; /* cannot happen: consecutive path nodes are adjacent */
+          break;
+        }
+        cnt[eid[pos]] += 1;
+      }
+    }
+  }
+  free(off);
+  free(ar);
+  free(nodes);
+  return rc;
+}
+
+int or_edge_hits(const or_graph *g, uint64_t seed, uint32_t phase, uint64_t first,
+                 uint64_t count, int threads, int forward, uint64_t *cnt, uint64_t *arcs) {
+  uint32_t *eid = (uint32_t *)malloc((g->arcs ? g->arcs : 1) * sizeof(uint32_t));
+  if (!eid) return OR_ENOMEM;
+  int rc = or_edge_ids(g, eid);
+  uint64_t a = 0;
+  if (rc == OR_OK) rc = add_edge_hits(g, seed, phase, first, count, threads, forward, eid, cnt, &a);
+  if (arcs) *arcs = a;
+  free(eid);
+  return rc;
+}
+
+/* Exact edge betweenness by Brandes' dependencies: from each source s, an edge (v, w) of the
+ * shortest-path DAG carries sigma_sv / sigma_sw * (1 + delta_s(w)) of the pairs (s, t). */
+int or_edge_brandes(const or_graph *g, double *ebc) {
+  uint32_t n = g->n;
+  uint64_t me = or_edge_count(g);
+  uint32_t *eid = (uint32_t *)malloc((g->arcs ? g->arcs : 1) * 4);
+  uint32_t *dist = (uint32_t *)malloc((size_t)n * 4);
+  uint32_t *order = (uint32_t *)malloc((size_t)n * 4);
+  double *sig = (double *)malloc((size_t)n * 8);
+  double *dep = (double *)malloc((size_t)n * 8);
+  if (!eid || !dist || !order || !sig || !dep) {
+    free(eid); free(dist); free(order); free(sig); free(dep);
+    return OR_ENOMEM;
+  }
+  int rc = or_edge_ids(g, eid);
+  for (uint64_t e = 0; e < me; ++e) ebc[e] = 0.0;
+  for (uint32_t s = 0; s < n && rc == OR_OK; ++s) {
+    for (uint32_t v = 0; v < n; ++v) {
+      dist[v] = UNSEEN;
+      sig[v] = 0.0;
+      dep[v] = 0.0;
+    }
+    size_t head = 0, tail = 0;
+    dist[s] = 0;
+    sig[s] = 1.0;
+    order[tail++] = s;
+    while (head < tail) {
+      uint32_t u = order[head++];
+      for (uint32_t j = g->row[u]; j < g->row[u + 1]; ++j) {
+        uint32_t x = g->col[j];
+        if (dist[x] == UNSEEN) {
+          dist[x] = dist[u] + 1;
+          order[tail++] = x;
+        }
+        if (dist[x] == dist[u] + 1) sig[x] += sig[u];
+      }
+    }
+    for (size_t k = tail; k-- > 0;) {
+      uint32_t u = order[k];
+      for (uint32_t j = g->row[u]; j < g->row[u + 1]; ++j) {
+        uint32_t x = g->col[j];
+        if (dist[x] == dist[u] + 1) {
+          double c = sig[u] / sig[x] * (1.0 + dep[x]);
+          ebc[eid[j]] += c;
+          dep[u] += c;
+        }
+      }
+    }
+  }
+  double norm = 1.0 / ((double)n * (double)(n - 1));
+  for (uint64_t e = 0; e < me; ++e) ebc[e] *= norm;
+  free(eid); free(dist); free(order); free(sig); free(dep);
+  return rc;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Vertex diameter VD: the largest number of nodes on a shortest path.         */
 /* Exact (a BFS from every node) when n * arcs <= 1e9; otherwise an upper      */
 /* bound: a shortest path crosses strongly connected components along a path  */
@@ -865,6 +1015,17 @@ static uint32_t floor_log2_u32(uint32_t x) {
 
 uint64_t or_omega(double lambda, double delta, uint32_t vd, double c) {
   uint32_t base = vd > 3 ? vd - 2 : 1;
+  double j = (double)(floor_log2_u32(base) + 1);
+  double x = c / (lambda * lambda) * (j + log(2.0 / delta));
+  return (uint64_t)ceil(x);
+}
+
+/* The same cap for edge betweenness: a shortest path has at most VD - 1 edges, so the
+ * ranges "paths through edge e" shatter at most floor(log2(VD - 1)) + 1 paths (a path in
+ * a shattered set of k lies in 2^(k-1) distinct ranges, each one of its edges), where the
+ * node ranges give floor(log2(VD - 2)) + 1. */
+uint64_t or_omega_edges(double lambda, double delta, uint32_t vd, double c) {
+  uint32_t base = vd > 2 ? vd - 1 : 1;
   double j = (double)(floor_log2_u32(base) + 1);
   double x = c / (lambda * lambda) * (j + log(2.0 / delta));
   return (uint64_t)ceil(x);
@@ -1133,6 +1294,7 @@ typedef struct {
   double exact_vd_limit;   /* 0: 1e9 */
   int32_t threads;
   int32_t forward;         /* 1: forward BFS from s instead of the balanced search */
+  int32_t edges;           /* 1: the betweenness of edges (items = edge ids) */
 } or_params;
 
 typedef struct {
@@ -1140,17 +1302,31 @@ typedef struct {
   uint32_t vd, stop_rule; /* stop_rule 1: stopping condition, 0: tau reached omega */
   int32_t vd_exact;
   double C;
-  uint64_t *count; /* [n] main-phase hits */
-  double *bc, *lower, *upper; /* [n] */
-  double *L_l, *L_u; /* [n] */
-  uint64_t *count0; /* [n] pilot hits */
+  /* arrays of one entry per item: node, or edge id with p->edges */
+  uint64_t *count; /* main-phase hits */
+  double *bc, *lower, *upper;
+  double *L_l, *L_u;
+  uint64_t *count0; /* pilot hits */
 } or_result;
 
 int or_run(const or_graph *g, const or_params *p, or_result *r) {
   if (!g || !p || !r || g->n < 2) return OR_EINVAL;
   if (!(p->epsilon > 0 && p->epsilon < 1 && p->delta > 0 && p->delta < 1)) return OR_EINVAL;
-  if (p->mode == 1 && (p->k < 1 || p->k > g->n)) return OR_EINVAL;
-  uint32_t n = g->n;
+  /* the items whose betweenness is estimated: the nodes, or the edges */
+  const uint64_t items = p->edges ? or_edge_count(g) : g->n;
+  if (items < 1 || items > 0xFFFFFFFFull) return OR_EINVAL;
+  if (p->mode == 1 && (p->k < 1 || p->k > items)) return OR_EINVAL;
+  uint32_t n = (uint32_t)items;
+  uint32_t *eid = NULL;
+  if (p->edges) {
+    eid = (uint32_t *)malloc((g->arcs ? g->arcs : 1) * sizeof(uint32_t));
+    if (!eid) return OR_ENOMEM;
+    int rc0 = or_edge_ids(g, eid);
+    if (rc0) {
+      free(eid);
+      return rc0;
+    }
+  }
   double c = p->c > 0 ? p->c : 0.5;
   double eb = p->balance_eps > 0 ? p->balance_eps : 0.001;
   double lim = p->exact_vd_limit > 0 ? p->exact_vd_limit : 1e9;
@@ -1161,7 +1337,8 @@ int or_run(const or_graph *g, const or_params *p, or_result *r) {
   } else if ((rc = or_vertex_diameter(g, lim, &r->vd, &r->vd_exact))) {
     return rc;
   }
-  r->omega = or_omega(p->epsilon, p->delta, r->vd, c);
+  r->omega = p->edges ? or_omega_edges(p->epsilon, p->delta, r->vd, c)
+                      : or_omega(p->epsilon, p->delta, r->vd, c);
   r->alpha = or_alpha(r->omega);
   r->interval = p->check_interval ? p->check_interval : or_default_interval(r->omega);
 
@@ -1177,7 +1354,10 @@ int or_run(const or_graph *g, const or_params *p, or_result *r) {
 
   /* pilot: phase 0, ids 0..alpha-1 */
   r->pilot_arcs = 0;
-  if ((rc = add_hits(g, p->seed, 0, 0, r->alpha, p->threads, p->forward, cnt0, &r->pilot_arcs)))
+  if ((rc = p->edges ? add_edge_hits(g, p->seed, 0, 0, r->alpha, p->threads, p->forward, eid,
+                                     cnt0, &r->pilot_arcs)
+                    : add_hits(g, p->seed, 0, 0, r->alpha, p->threads, p->forward, cnt0,
+                               &r->pilot_arcs)))
     return rc;
   if (p->mode == 1) {
     if ((rc = or_topk_lambdas(n, p->k, cnt0, r->alpha, p->epsilon, lam_l, lam_u))) return rc;
@@ -1194,7 +1374,10 @@ int or_run(const or_graph *g, const or_params *p, or_result *r) {
   r->stop_rule = 0;
   for (;;) {
     uint64_t b = r->omega - tau < r->interval ? r->omega - tau : r->interval;
-    if ((rc = add_hits(g, p->seed, 1, tau, b, p->threads, p->forward, cnt, &r->arcs))) return rc;
+    if ((rc = p->edges ? add_edge_hits(g, p->seed, 1, tau, b, p->threads, p->forward, eid, cnt,
+                                       &r->arcs)
+                      : add_hits(g, p->seed, 1, tau, b, p->threads, p->forward, cnt, &r->arcs)))
+      return rc;
     tau += b;
     if (tau >= r->omega) break;
     int stop = p->mode == 1
@@ -1230,6 +1413,7 @@ int or_run(const or_graph *g, const or_params *p, or_result *r) {
   if (!r->count) free(cnt);
   free(lam_l);
   free(lam_u);
+  free(eid);
   return OR_OK;
 }
 

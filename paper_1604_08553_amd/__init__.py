@@ -15,7 +15,7 @@ import re
 import numpy as np
 
 __all__ = ["Context", "Graph", "run", "run_batch", "Server", "sample_paths", "hit_counts",
-           "hit_counts_noalloc",
+           "hit_counts_noalloc", "edge_hit_counts",
            "KadError", "lib",
            "library_path", "declared_symbols", "omega", "alpha", "default_interval",
            "vertex_diameter", "bound_f", "bound_g", "compute_delta", "topk_lambdas",
@@ -30,6 +30,7 @@ MEM_HOST, MEM_DEVICE = 0, 1
 STOP_OMEGA, STOP_RULE, STOP_FIXED = 0, 1, 2
 SCHEDULES = {"adaptive": 0, "rk": 1, "hoeffding": 2}
 SEARCHES = {"balanced": 0, "forward": 1}
+TARGETS = {"nodes": 0, "edges": 1}
 SAMPLE_OVERFLOW, SAMPLE_CAPACITY, SAMPLE_RNG = 1, 2, 4
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
@@ -48,7 +49,8 @@ class _Params(C.Structure):
     _fields_ = [("epsilon", C.c_double), ("delta", C.c_double), ("mode", C.c_uint32),
                 ("k", C.c_uint32), ("seed", C.c_uint64), ("check_interval", C.c_uint32),
                 ("kernel_batch", C.c_uint32), ("vd_override", C.c_uint32),
-                ("schedule", C.c_uint32), ("c", C.c_double), ("balance_eps", C.c_double)]
+                ("schedule", C.c_uint32), ("c", C.c_double), ("balance_eps", C.c_double),
+                ("target", C.c_uint32)]
 
 
 class _Result(C.Structure):
@@ -61,7 +63,8 @@ class _Result(C.Structure):
                 ("seconds_delta", C.c_double), ("seconds_main", C.c_double),
                 ("count", C.c_void_p), ("bc", C.c_void_p), ("lower", C.c_void_p),
                 ("upper", C.c_void_p), ("topk_cap", C.c_uint32), ("topk_len", C.c_uint32),
-                ("topk_node", C.c_void_p), ("rank_lo", C.c_void_p), ("rank_hi", C.c_void_p)]
+                ("topk_node", C.c_void_p), ("rank_lo", C.c_void_p), ("rank_hi", C.c_void_p),
+                ("items", C.c_uint64)]
 
 
 _lib = None
@@ -90,6 +93,9 @@ def lib():
         "kad_sample_paths": ([vp, vp, u64, u32, u64, u32, vp, vp, vp, vp, u64, vp, vp, vp], st),
         "kad_hit_counts": ([vp, vp, u64, u32, u64, u64, vp, vp, vp], st),
         "kad_hit_counts_noalloc": ([vp, vp, u64, u32, u64, u64, vp, vp, vp, vp], st),
+        "kad_edge_hit_counts": ([vp, vp, u64, u32, u64, u64, vp, vp, vp], st),
+        "kad_graph_edge_count": ([vp, vp], st),
+        "kad_graph_edge_ids": ([vp, vp], st),
         "kad_omega": ([dbl, dbl, u32, dbl], u64),
         "kad_alpha": ([u64], u64),
         "kad_fixed_samples": ([u32, dbl, dbl, u32, u32, dbl], u64),
@@ -242,6 +248,18 @@ class Graph:
         _check(lib().kad_graph_get_search(self.handle, C.byref(v)))
         return {b: a for a, b in SEARCHES.items()}[v.value]
 
+    def edge_count(self) -> int:
+        """Edges: arcs (directed) or arcs / 2 (undirected)."""
+        v = C.c_uint64()
+        _check(lib().kad_graph_edge_count(self.handle, C.byref(v)))
+        return v.value
+
+    def edge_ids(self) -> np.ndarray:
+        """Edge id of every arc position (kad_graph_edge_ids)."""
+        eid = np.zeros(max(self.arcs, 1), dtype=np.uint32)
+        _check(lib().kad_graph_edge_ids(self.handle, _p(eid)))
+        return eid[:self.arcs]
+
     def launch(self):
         b, e = C.c_uint32(), C.c_uint32()
         _check(lib().kad_graph_get_launch(self.handle, C.byref(b), C.byref(e)))
@@ -279,14 +297,14 @@ def _stream(stream):
 
 _SCALARS = ("tau", "omega", "alpha", "interval", "arcs_scanned", "pilot_arcs_scanned",
             "overflow_samples", "vd", "vd_exact", "stop_reason", "seconds", "C",
-            "seconds_setup", "seconds_pilot", "seconds_delta", "seconds_main")
+            "seconds_setup", "seconds_pilot", "seconds_delta", "seconds_main", "items")
 
 
 def _params(epsilon, delta, mode="all", k=0, seed=1, check_interval=0, kernel_batch=0,
-            vd_override=0, c=0.0, balance_eps=0.0, schedule="adaptive"):
+            vd_override=0, c=0.0, balance_eps=0.0, schedule="adaptive", target="nodes"):
     return _Params(epsilon, delta, TOPK if mode == "topk" else ALL_NODES, k, seed,
                    check_interval, kernel_batch, vd_override, SCHEDULES[schedule], c,
-                   balance_eps)
+                   balance_eps, TARGETS[target])
 
 
 def _result(n, topk, topk_cap=0, out=None):
@@ -323,15 +341,16 @@ def _collect(r, arrs, topk):
 def run(ctx: Context, graph: Graph, epsilon: float, delta: float, mode: str = "all", k: int = 0,
         seed: int = 1, check_interval: int = 0, kernel_batch: int = 0, vd_override: int = 0,
         c: float = 0.0, balance_eps: float = 0.0, topk_cap: int = 0, stream=None,
-        out: dict = None, schedule: str = "adaptive") -> dict:
+        out: dict = None, schedule: str = "adaptive", target: str = "nodes") -> dict:
     """The adaptive run (Algorithm 1), or a fixed schedule ("rk", "hoeffding").  Returns
-    scalars plus the per-node arrays.
+    scalars plus the per-item arrays (per node, or per edge id with target="edges").
 
     ``out`` may hold preallocated arrays "count" (uint64[n]), "bc", "lower", "upper"
     (float64[n]) to be filled in place (saves page-faulting fresh arrays per call)."""
     p = _params(epsilon, delta, mode, k, seed, check_interval, kernel_batch, vd_override, c,
-                balance_eps, schedule)
-    r, arrs = _result(graph.n, mode == "topk", topk_cap, out)
+                balance_eps, schedule, target)
+    items = graph.n if target == "nodes" else graph.edge_count()
+    r, arrs = _result(items, mode == "topk", topk_cap, out)
     _check(lib().kad_run(ctx.handle, graph.handle, C.byref(p), C.byref(r), _stream(stream)))
     return _collect(r, arrs, mode == "topk")
 
@@ -456,6 +475,16 @@ def hit_counts(ctx: Context, graph: Graph, seed: int, phase: int, first: int, co
     _check(lib().kad_hit_counts(ctx.handle, graph.handle, seed, phase, first, count, _p(cnt),
                                 C.byref(arcs), _stream(stream)))
     return cnt, arcs.value
+
+
+def edge_hit_counts(ctx: Context, graph: Graph, seed: int, phase: int, first: int, count: int,
+                    stream=None):
+    """(count per edge id, arcs scanned) of sample ids [first, first+count)."""
+    cnt = np.zeros(max(graph.edge_count(), 1), dtype=np.uint64)
+    arcs = C.c_uint64()
+    _check(lib().kad_edge_hit_counts(ctx.handle, graph.handle, seed, phase, first, count, _p(cnt),
+                                     C.byref(arcs), _stream(stream)))
+    return cnt[:graph.edge_count()], arcs.value
 
 
 def hit_counts_noalloc(ctx: Context, graph: Graph, seed: int, phase: int, first: int,

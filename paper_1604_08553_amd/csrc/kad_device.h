@@ -152,6 +152,15 @@ hipError_t launch_hit_batch(const uint32_t *path, const uint32_t *len, uint32_t 
                             uint32_t *tmp, uint64_t *ivmax, uint64_t *snap,
                             hipStream_t stream);
 
+// Edge betweenness: the paths of samples [0, nsamp) (node ids, `stride` apart) rewritten
+// as edge ids with a placeholder entry at each end (epath, estride >= stride + 1 apart;
+// elen[k] = len[k] + 1, 0 without a path): the node-hit reductions then count every edge
+// of every path.  eid: edge id per arc position (nullptr: the position is the id).
+hipError_t launch_edge_paths(const uint32_t *path, const uint32_t *len, uint32_t stride,
+                             uint32_t nsamp, const uint32_t *row, const uint32_t *col,
+                             const uint32_t *eid, uint32_t *epath, uint32_t *elen,
+                             uint32_t estride, hipStream_t stream);
+
 // Zero a device buffer with a kernel (no memset node when captured).
 hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream);
 // hist[c] += #{v < n : count[v] == c} for c < bins (hist zeroed by the caller)

@@ -1102,6 +1102,8 @@ kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *g
     if (st) return st;
     if (params[i].schedule != KAD_SCHEDULE_ADAPTIVE)
       return fail(KAD_EINVAL, "query %u: fixed schedules run through kad_run", i);
+    if (params[i].target != KAD_TARGET_NODES)
+      return fail(KAD_EINVAL, "query %u: edge betweenness runs through kad_run", i);
   }
   kad::CtxClaim claim(ctx);
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
@@ -1174,6 +1176,7 @@ kad_status kad_server_submit(kad_server *sv, const kad_graph *g, const kad_param
   if (st) return st;
   if (p->schedule != KAD_SCHEDULE_ADAPTIVE)
     return fail(KAD_EINVAL, "fixed schedules run through kad_run");
+  if (p->target != KAD_TARGET_NODES) return fail(KAD_EINVAL, "edge betweenness runs through kad_run");
   std::unique_ptr<kad::Query> q(new kad::Query());
   q->g = const_cast<kad_graph *>(g);
   q->p = *p;

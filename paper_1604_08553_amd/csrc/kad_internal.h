@@ -78,6 +78,8 @@ constexpr uint32_t DEFAULT_BATCH = 65536;
 struct OutSet {
   DevBuf<uint32_t> s, t, len, flags, nodes, path;
   DevBuf<uint32_t> fix_list;  // samples the sampler leaves to the wide-count kernel
+  DevBuf<uint32_t> epath, elen;  // edge betweenness: paths as edge ids (estride apart)
+  uint32_t estride = 0;
   DevBuf<uint64_t> arcs;
   PinBuf<uint32_t> h_flags, h_len, h_nodes, h_nwide;  // h_nwide: samples resampled wide
   PinBuf<uint64_t> h_arcs;
@@ -101,6 +103,8 @@ struct OutSet {
   kad_status ensure_entries(uint32_t cap, uint64_t path_entries, hipStream_t rs);
   // fix_count: the launch's counter of fix_list entries (null: no list kept)
   SampleOut view(uint32_t path_stride, uint32_t *fix_count = nullptr) const;
+  // room for `cap` samples' edge paths, `estride` entries apart
+  kad_status ensure_edges(uint32_t cap, uint32_t estride);
 };
 
 class Engine;
@@ -189,6 +193,12 @@ struct kad_graph {
   kad::LaunchShape shape;  // sampler launch shape (kad_graph_set_launch / kad_autotune)
   bool shape_set = false;
   uint32_t search = 0;     // KAD_SEARCH_BALANCED or KAD_SEARCH_FORWARD
+  // edge ids of an undirected graph's arcs (built on first use; directed graphs use the
+  // arc position itself)
+  std::mutex eid_mu;
+  bool eid_ready = false;
+  std::vector<uint32_t> eid;
+  uint32_t *d_eid = nullptr;
 };
 
 namespace kad {
@@ -216,6 +226,11 @@ kad_status context_engine(kad_ctx *ctx, Engine **out);
 
 // Parameter checks shared by every entry point that runs Algorithm 1.
 kad_status validate_params(const kad_graph *g, const kad_params *p);
+// Items of a run: the nodes, or the edges (arcs, or arcs / 2 when undirected).
+uint64_t run_items(const kad_graph *g, uint32_t target);
+// The graph's edge-id map on the device (nullptr for a directed graph: the arc position
+// is the id), built on first use.
+kad_status graph_edge_ids(kad_graph *g, const uint32_t **d_eid);
 
 GraphDev dev_view(const kad_graph *g);
 // The graph's vertex diameter by the library rule, computed once (thread-safe).

@@ -2612,6 +2612,59 @@ hipError_t noalloc_scratch(void **ptr) {
   return hipSuccess;
 }
 
+// Edge betweenness: every path rewritten as the ids of its edges, with one placeholder
+// entry before and after, so that the hit reductions -- which skip a path's first and last
+// entry -- count exactly the path's edges.  Step j of sample k (nodes a = path[j], b =
+// path[j + 1]) becomes epath[k * estride + 1 + j] = the id of the arc a -> b: its CSR
+// position (binary search in a's sorted row), mapped through eid when given (undirected
+// graphs: both arcs of an edge share one id).  elen[k] = len[k] + 1, or 0 without a path.
+__global__ __launch_bounds__(256) void edge_path_kernel(const uint32_t *__restrict__ path,
+                                                        const uint32_t *__restrict__ len,
+                                                        uint32_t stride, uint32_t nsamp,
+                                                        const uint32_t *__restrict__ row,
+                                                        const uint32_t *__restrict__ col,
+                                                        const uint32_t *__restrict__ eid,
+                                                        uint32_t *epath, uint32_t *elen,
+                                                        uint32_t estride) {
+  const uint32_t steps = stride - 1;
+  const uint64_t total = (uint64_t)nsamp * steps;
+  for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < total;
+       e += (uint64_t)gridDim.x * 256) {
+    const uint32_t k = (uint32_t)(e / steps), j = (uint32_t)(e % steps);
+    const uint32_t L = len[k];
+    uint32_t *ep = epath + (size_t)k * estride;
+    if (j == 0) {
+      elen[k] = L >= 2 ? L + 1 : 0u;
+      if (L >= 2) {
+        ep[0] = 0;
+        ep[L] = 0;
+      }
+    }
+    if (j + 1 < L) {
+      const uint32_t a = path[(size_t)k * stride + j], b = path[(size_t)k * stride + j + 1];
+      uint32_t lo = row[a], hi = row[a + 1];
+      while (lo < hi) {  // first position whose head is not below b (b is in the row)
+        const uint32_t mid = (lo + hi) >> 1;
+        if (col[mid] < b) lo = mid + 1; else hi = mid;
+      }
+      ep[1 + j] = eid ? eid[lo] : lo;
+    }
+  }
+}
+
+hipError_t launch_edge_paths(const uint32_t *path, const uint32_t *len, uint32_t stride,
+                             uint32_t nsamp, const uint32_t *row, const uint32_t *col,
+                             const uint32_t *eid, uint32_t *epath, uint32_t *elen,
+                             uint32_t estride, hipStream_t stream) {
+  if (nsamp == 0) return hipSuccess;
+  if (stride < 2 || estride < stride + 1) return hipErrorInvalidValue;
+  const uint64_t total = (uint64_t)nsamp * (stride - 1);
+  const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(edge_path_kernel, dim3(blocks), dim3(256), 0, stream, path, len, stride,
+                     nsamp, row, col, eid, epath, elen, estride);
+  return hipGetLastError();
+}
+
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream) {
   if (count == 0) return hipSuccess;
   const uint64_t blocks = std::min<uint64_t>((count + 255) / 256, 65536);

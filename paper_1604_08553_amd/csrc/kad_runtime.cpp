@@ -90,6 +90,17 @@ kad_status OutSet::ensure_entries(uint32_t want_cap, uint64_t path_entries, hipS
   return ensure(cap, 0, rs);  // events
 }
 
+kad_status OutSet::ensure_edges(uint32_t want_cap, uint32_t want_estride) {
+  if (epath.n < (size_t)want_cap * want_estride || elen.n < want_cap) {
+    epath.release();
+    elen.release();
+    HIP_TRY(epath.ensure((size_t)want_cap * want_estride));
+    HIP_TRY(elen.ensure(want_cap));
+  }
+  estride = want_estride;
+  return KAD_OK;
+}
+
 SampleOut OutSet::view(uint32_t path_stride, uint32_t *fix_count) const {
   SampleOut so;
   so.s = s.p;
@@ -370,11 +381,54 @@ void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, 
   }
 }
 
+uint64_t run_items(const kad_graph *g, uint32_t target) {
+  if (target == KAD_TARGET_EDGES) return g->directed ? g->arcs : g->arcs / 2;
+  return g->n;
+}
+
+kad_status graph_edge_ids(kad_graph *g, const uint32_t **d_eid) {
+  *d_eid = nullptr;
+  if (g->directed) return KAD_OK;
+  std::lock_guard<std::mutex> lk(g->eid_mu);
+  if (!g->eid_ready) {
+    std::vector<uint32_t> &eid = g->eid;
+    eid.assign(g->arcs, 0);
+    uint32_t next = 0;
+    for (uint32_t u = 0; u < g->n; ++u)
+      for (uint32_t e = g->row[u]; e < g->row[u + 1]; ++e) {
+        const uint32_t v = g->col[e];
+        if (v < u) continue;
+        const uint32_t *b = g->col.data() + g->row[v], *en = g->col.data() + g->row[v + 1];
+        const uint32_t back = (uint32_t)(std::lower_bound(b, en, u) - g->col.data());
+        eid[e] = next;
+        eid[back] = next;
+        next++;
+      }
+    HIP_TRY(hipSetDevice(g->ctx->device));
+    HIP_TRY(hipMalloc((void **)&g->d_eid, std::max<size_t>(g->arcs, 1) * 4));
+    if (g->arcs)
+      HIP_TRY(hipMemcpy(g->d_eid, eid.data(), (size_t)g->arcs * 4, hipMemcpyHostToDevice));
+    g->bytes += g->arcs * 4;
+    g->ctx->used_graphs += g->arcs * 4;
+    g->eid_ready = true;
+  }
+  *d_eid = g->d_eid;
+  return KAD_OK;
+}
+
 kad_status validate_params(const kad_graph *g, const kad_params *p) {
+  if (p->target != KAD_TARGET_NODES && p->target != KAD_TARGET_EDGES)
+    return fail(KAD_EINVAL, "target must be KAD_TARGET_NODES or KAD_TARGET_EDGES");
   if (!(p->epsilon > 0 && p->epsilon < 1)) return fail(KAD_EINVAL, "epsilon must be in (0,1)");
   if (!(p->delta > 0 && p->delta < 1)) return fail(KAD_EINVAL, "delta must be in (0,1)");
   if (p->mode != KAD_ALL_NODES && p->mode != KAD_TOPK) return fail(KAD_EINVAL, "bad mode");
-  if (p->mode == KAD_TOPK && (p->k < 1 || p->k > g->n)) return fail(KAD_EINVAL, "k must be in [1, n]");
+  const uint64_t items = run_items(g, p->target);
+  if (items == 0) return fail(KAD_EINVAL, "the graph has no edges");
+  if (items > (uint64_t)MAX_HIT_TILES_PUBLIC * HIT_TILE_IDS)
+    return fail(KAD_EINVAL, "runs over more than %u items are not supported",
+                MAX_HIT_TILES_PUBLIC * HIT_TILE_IDS);
+  if (p->mode == KAD_TOPK && (p->k < 1 || p->k > items))
+    return fail(KAD_EINVAL, "k must be in [1, items]");
   if (p->schedule > KAD_SCHEDULE_HOEFFDING) return fail(KAD_EINVAL, "unknown schedule");
   if (p->c < 0) return fail(KAD_EINVAL, "c must be positive (or 0 for the default)");
   if (!(p->balance_eps >= 0 && p->balance_eps < 0.5))
@@ -428,25 +482,30 @@ hipStream_t pick_stream(kad_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx
 // Size the slot state, the wide-count arena and both output sets for graph g (overflow
 // class ovc) and `batch` samples of path stride `stride`.
 kad_status ensure_capacity(kad_ctx *ctx, const kad_graph *g, int ovc, uint32_t batch,
-                           uint32_t stride) {
+                           uint32_t stride, uint64_t items = 0, bool edges = false) {
   const uint32_t n = g->n;
+  if (items == 0) items = n;  // the counters: one per node, or per edge
   kad_status st = kad::ensure_slots(ctx, n);
   if (st) return st;
   if ((st = kad::ensure_wide(ctx, g, ovc))) return st;
-  for (OutSet &o : ctx->outs)
+  for (OutSet &o : ctx->outs) {
     if ((st = o.ensure(batch, stride, ctx->rstream))) return st;
+    if (edges && (st = o.ensure_edges(o.cap, o.stride + 1))) return st;
+  }
   HIP_TRY(ctx->work.ensure(3));
   HIP_TRY(ctx->work2.ensure(3));
-  HIP_TRY(ctx->count.ensure(n));
-  HIP_TRY(ctx->h_count.ensure(n));
+  HIP_TRY(ctx->count.ensure(items));
+  HIP_TRY(ctx->h_count.ensure(items));
   // hit-reduction bins: room in every tile for all the hits of one reduction call
   // (fixed layout), or, when that would pass 1 GiB (long paths), one array sized by the
-  // hits with a counting pass first (compact layout)
-  const uint64_t tiles = (n + kad::HIT_TILE_IDS - 1) / kad::HIT_TILE_IDS;
+  // hits with a counting pass first (compact layout).  A path of len nodes has len - 2
+  // interior nodes and len - 1 edges.
+  const uint64_t tiles = (items + kad::HIT_TILE_IDS - 1) / kad::HIT_TILE_IDS;
   if (tiles > kad::MAX_HIT_TILES_PUBLIC)
-    return fail(KAD_EINVAL, "graphs above %u nodes are not supported by the hit reduction",
+    return fail(KAD_EINVAL, "more than %u counters are not supported by the hit reduction",
                 kad::MAX_HIT_TILES_PUBLIC * kad::HIT_TILE_IDS);
-  const uint64_t cap = (uint64_t)ctx->outs[0].cap * std::max<uint32_t>(ctx->outs[0].stride - 2, 1);
+  const uint32_t rstride = ctx->outs[0].stride + (edges ? 1 : 0);
+  const uint64_t cap = (uint64_t)ctx->outs[0].cap * std::max<uint32_t>(rstride - 2, 1);
   const bool compact = tiles * cap * 4 > (1ull << 30);
   const uint64_t want = compact ? cap : tiles * cap;
   if (cap > ctx->bins_cap || want > ctx->bins.n || compact != ctx->bins_compact) {
@@ -488,7 +547,8 @@ kad::HitScratch hit_scratch(kad_ctx *ctx) {
 kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                         uint64_t first, uint32_t count, uint32_t stride, int set,
                         hipStream_t stream, int ovc, uint32_t slot0 = 0, uint32_t *work = nullptr,
-                        hipEvent_t wide_after = nullptr) {
+                        hipEvent_t wide_after = nullptr, bool edges = false,
+                        const uint32_t *edge_ids = nullptr) {
   OutSet &o = ctx->outs[set];
   kad_status st = KAD_OK;
   uint32_t *wk = work ? work : ctx->work.p;  // sampler counter, fix-list length, fix counter
@@ -515,6 +575,9 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
     if (st) return st;
     HIP_TRY(hipMemcpyAsync(o.h_nwide.p, wk + 1, 4, hipMemcpyDeviceToHost, stream));
   }
+  if (edges)  // the paths as edge ids, for the edge-hit reductions
+    HIP_TRY(kad::launch_edge_paths(o.path.p, o.len.p, stride, count, g->d_row, g->d_col, edge_ids,
+                                   o.epath.p, o.elen.p, stride + 1, stream));
   // the reductions need only the paths: they wait for this event, not for the mirrors
   // (a set is launched into again only after the host has waited for its mirrors)
   HIP_TRY(hipEventRecord(o.sampled, stream));
@@ -760,6 +823,7 @@ kad_status kad_graph_destroy(kad_graph *g) {
     (void)hipFree(g->d_rrow);
     (void)hipFree(g->d_rcol);
   }
+  if (g->d_eid) (void)hipFree(g->d_eid);
   g->ctx->used_graphs -= std::min(g->ctx->used_graphs, g->bytes);
   delete g;
   return KAD_OK;
@@ -950,6 +1014,68 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
   return KAD_OK;
 }
 
+kad_status kad_edge_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
+                               uint64_t first, uint64_t count, uint64_t *count_out,
+                               uint64_t *arcs_scanned, void *hip_stream) {
+  if (!ctx || !g || !count_out) return fail(KAD_EINVAL, "NULL argument");
+  if (phase > 255) return fail(KAD_EINVAL, "phase must fit 8 bits");
+  const uint64_t items = kad::run_items(g, KAD_TARGET_EDGES);
+  if (items == 0) return fail(KAD_EINVAL, "the graph has no edges");
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
+  kad_graph *gm = const_cast<kad_graph *>(g);
+  uint32_t vd;
+  bool ex;
+  kad_status st = graph_vd(gm, &vd, &ex);
+  if (st) return st;
+  const uint32_t *edge_ids = nullptr;
+  if ((st = kad::graph_edge_ids(gm, &edge_ids))) return st;
+  const uint32_t stride = std::max<uint32_t>(vd, 2), rstride = stride + 1;
+  const int ovc = kad::overflow_class(g, vd, true);
+  const uint32_t batch = (uint32_t)std::min<uint64_t>(std::max<uint64_t>(count, 1), DEFAULT_BATCH);
+  if ((st = ensure_capacity(ctx, g, ovc, batch, stride, items, true))) return st;
+  hipStream_t stream = pick_stream(ctx, hip_stream);
+  HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)items * 8, stream));
+  uint64_t arcs = 0;
+  for (uint64_t done = 0; done < count;) {
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(batch, count - done);
+    if ((st = launch_batch(ctx, g, seed, phase, first + done, nb, stride, 0, stream, ovc, 0,
+                           nullptr, nullptr, true, edge_ids)))
+      return st;
+    HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].epath.p, ctx->outs[0].elen.p, rstride, nb,
+                                   (uint32_t)items, ctx->count.p, false, nullptr, nullptr,
+                                   hit_scratch(ctx), stream));
+    if ((st = finish_batch(ctx, 0, nb, nb))) return st;
+    for (uint32_t k = 0; k < nb; ++k) arcs += ctx->outs[0].h_arcs.p[k];
+    done += nb;
+  }
+  HIP_TRY(hipMemcpyAsync(ctx->h_count.p, ctx->count.p, (size_t)items * 8, hipMemcpyDeviceToHost,
+                         stream));
+  HIP_TRY(hipStreamSynchronize(stream));
+  for (uint64_t e = 0; e < items; ++e) count_out[e] += ctx->h_count.p[e];
+  if (arcs_scanned) *arcs_scanned = arcs;
+  return KAD_OK;
+}
+
+kad_status kad_graph_edge_count(const kad_graph *g, uint64_t *count) {
+  if (!g || !count) return fail(KAD_EINVAL, "NULL argument");
+  *count = kad::run_items(g, KAD_TARGET_EDGES);
+  return KAD_OK;
+}
+
+kad_status kad_graph_edge_ids(const kad_graph *g, uint32_t *eid) {
+  if (!g || (!eid && g->arcs)) return fail(KAD_EINVAL, "NULL argument");
+  if (g->directed) {
+    for (uint64_t e = 0; e < g->arcs; ++e) eid[e] = (uint32_t)e;
+    return KAD_OK;
+  }
+  const uint32_t *d = nullptr;
+  kad_status st = kad::graph_edge_ids(const_cast<kad_graph *>(g), &d);
+  if (st) return st;
+  memcpy(eid, g->eid.data(), (size_t)g->arcs * 4);
+  return KAD_OK;
+}
+
 // ---------------------------------------------------------------- hit counts, no allocation
 
 kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
@@ -1066,7 +1192,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   kad::CtxClaim claim(ctx);
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
   kad_graph *gm = const_cast<kad_graph *>(g);
-  const uint32_t n = g->n;
+  // the run's items -- the nodes, or the edges -- and every per-item array and counter below
+  const bool edges = p->target == KAD_TARGET_EDGES;
+  const uint32_t n = (uint32_t)kad::run_items(g, p->target);
+  const uint32_t *edge_ids = nullptr;
+  if (edges && (st = kad::graph_edge_ids(gm, &edge_ids))) return st;
   ctx->run_wide = 0;
 
   uint32_t vd;
@@ -1076,7 +1206,8 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   } else if ((st = graph_vd(gm, &vd, &vd_exact))) {
     return st;
   }
-  const uint64_t omega = kad::omega_of(p->epsilon, p->delta, vd, c);
+  const uint64_t omega = edges ? kad::omega_edges_of(p->epsilon, p->delta, vd, c)
+                               : kad::omega_of(p->epsilon, p->delta, vd, c);
   const uint64_t alpha = kad::alpha_of(omega);
   const uint64_t B = p->check_interval ? p->check_interval : kad::interval_of(omega);
   uint64_t K = p->kernel_batch ? p->kernel_batch : DEFAULT_BATCH;
@@ -1085,7 +1216,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   const uint32_t chunks_per_batch = (uint32_t)(K / B);
   const uint32_t stride = std::max<uint32_t>(vd, 2);
   const int ovc = kad::overflow_class(g, vd, p->vd_override == 0);
-  if ((st = ensure_capacity(ctx, g, ovc, (uint32_t)K, stride))) return st;
+  if ((st = ensure_capacity(ctx, g, ovc, (uint32_t)K, stride, n, edges))) return st;
+  // what the hit reductions read: the node paths, or the same paths as edge ids
+  const uint32_t rstride = edges ? stride + 1 : stride;
+  auto rpath = [&](const OutSet &o) -> const uint32_t * { return edges ? o.epath.p : o.path.p; };
+  auto rlen = [&](const OutSet &o) -> const uint32_t * { return edges ? o.elen.p : o.len.p; };
   hipStream_t stream = pick_stream(ctx, hip_stream);
   if ((st = run_timing_begin(ctx, stream))) return st;
   struct RunTimingEnd {  // also on early returns
@@ -1096,13 +1231,18 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
 
   if (p->schedule != KAD_SCHEDULE_ADAPTIVE) {
     // ---- a fixed number of main-phase samples, no pilot and no stopping check
-    const uint64_t tau_fixed = kad_fixed_samples(p->schedule, p->epsilon, p->delta, vd, n, c);
+    const uint64_t tau_fixed =
+        edges && p->schedule == KAD_SCHEDULE_RK
+            ? kad::omega_edges_of(p->epsilon, 2.0 * p->delta, vd, c)  // ln(1/delta): 2 delta
+            : kad_fixed_samples(p->schedule, p->epsilon, p->delta, vd, n, c);
     HIP_TRY(hipMemsetAsync(ctx->count.p, 0, (size_t)n * 8, stream));
     uint64_t arcs_f = 0;
     for (uint64_t done = 0; done < tau_fixed;) {
       const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, tau_fixed - done);
-      if ((st = launch_batch(ctx, g, p->seed, 1, done, nb, stride, 0, stream, ovc))) return st;
-      HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
+      if ((st = launch_batch(ctx, g, p->seed, 1, done, nb, stride, 0, stream, ovc, 0, nullptr,
+                             nullptr, edges, edge_ids)))
+        return st;
+      HIP_TRY(kad::launch_hit_reduce(rpath(ctx->outs[0]), rlen(ctx->outs[0]), rstride, nb, n,
                                      ctx->count.p, false, nullptr, nullptr, hit_scratch(ctx), stream));
       if ((st = finish_batch(ctx, 0, nb, nb))) return st;
       for (uint32_t k = 0; k < nb; ++k) arcs_f += ctx->outs[0].h_arcs.p[k];
@@ -1122,7 +1262,8 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     r->vd = vd;
     r->vd_exact = vd_exact ? 1u : 0u;
     r->stop_reason = KAD_STOP_FIXED;
-    r->n = n;
+    r->n = g->n;
+    r->items = n;
     r->C = 0.0;
     const uint64_t *cnt = ctx->h_count.p;
     std::vector<double> &bcs = ctx->h_bc, &los = ctx->h_lo, &his = ctx->h_hi;
@@ -1200,14 +1341,16 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       for (uint32_t k = 0; k < pilot_last; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
     }
     const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, alpha - done);
-    if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream, ovc))) return st;
+    if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream, ovc, 0, nullptr,
+                           nullptr, edges, edge_ids)))
+      return st;
     if (overlap) {
       HIP_TRY(hipStreamWaitEvent(b1_stream, ctx->outs[first_set].reduced, 0));
       if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, b1_stream, ovc,
-                             b1_slot0, ctx->work2.p, ctx->outs[0].copied)))
+                             b1_slot0, ctx->work2.p, ctx->outs[0].copied, edges, edge_ids)))
         return st;
     }
-    HIP_TRY(kad::launch_hit_reduce(ctx->outs[0].path.p, ctx->outs[0].len.p, stride, nb, n,
+    HIP_TRY(kad::launch_hit_reduce(rpath(ctx->outs[0]), rlen(ctx->outs[0]), rstride, nb, n,
                                    pcount, false, nullptr, nullptr, hit_scratch(ctx), stream));
     pilot_last = nb;
     done += nb;
@@ -1229,7 +1372,8 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   // sampled while the host runs computeDelta
   if (!overlap) {
     HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[first_set].reduced, 0));
-    if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream, ovc))) {
+    if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream, ovc, 0,
+                           nullptr, nullptr, edges, edge_ids))) {
       (void)hipEventDestroy(pilot_done);
       return st;
     }
@@ -1360,7 +1504,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       for (; queued < upto; ++queued) {
         const uint32_t q0 = queued * (uint32_t)B;
         const uint32_t cb = (uint32_t)std::min<uint64_t>(B, cur_nb - q0);
-        HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)q0 * stride, o.len.p + q0, stride, cb, n,
+        HIP_TRY(kad::launch_hit_reduce(rpath(o) + (size_t)q0 * rstride, rlen(o) + q0, rstride, cb, n,
                                        ctx->count.p, false, by_group ? ctx->group.p : nullptr,
                                        by_group ? ctx->gmax.p : nullptr, hit_scratch(ctx), rs));
         HIP_TRY(hipMemcpyAsync(snaps.p + (size_t)queued * snap,
@@ -1372,7 +1516,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       return KAD_OK;
     };
     if (batch_reduce) {  // every interval in three launches; all snapshots land together
-      HIP_TRY(kad::launch_hit_batch(o.path.p, o.len.p, stride, cur_nb, (uint32_t)B, n,
+      HIP_TRY(kad::launch_hit_batch(rpath(o), rlen(o), rstride, cur_nb, (uint32_t)B, n,
                                     ctx->count.p, ctx->group.p, ctx->gmax.p, (uint32_t)ngroups,
                                     ctx->ivtmp.p, ctx->ivmax.p, snaps.p, rs));
       for (uint32_t q = 0; q < nch; ++q) HIP_TRY(hipEventRecord(ctx->chunk_ev[q], rs));
@@ -1393,7 +1537,8 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       next_nb = (uint32_t)std::min<uint64_t>(round_up(want), omega - launched);
       const int nxt = 1 - cur;
       HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[nxt].reduced, 0));
-      kad_status s2 = launch_batch(ctx, g, p->seed, 1, launched, next_nb, stride, nxt, stream, ovc);
+      kad_status s2 = launch_batch(ctx, g, p->seed, 1, launched, next_nb, stride, nxt, stream, ovc,
+                                   0, nullptr, nullptr, edges, edge_ids);
       if (s2) return s2;
       launched += next_nb;
       return KAD_OK;
@@ -1419,7 +1564,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       // undo the reductions enqueued past the stopping point; the counts go home
       const uint32_t reduced_end = (uint32_t)std::min<uint64_t>((uint64_t)queued * B, cur_nb);
       if (used < reduced_end)
-        HIP_TRY(kad::launch_hit_reduce(o.path.p + (size_t)used * stride, o.len.p + used, stride,
+        HIP_TRY(kad::launch_hit_reduce(rpath(o) + (size_t)used * rstride, rlen(o) + used, rstride,
                                        reduced_end - used, n, ctx->count.p, true, nullptr, nullptr,
                                        hit_scratch(ctx), rs));
       if ((st = enqueue_count_copy())) return st;
@@ -1450,7 +1595,8 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   r->vd = vd;
   r->vd_exact = vd_exact ? 1u : 0u;
   r->stop_reason = rule ? KAD_STOP_RULE : KAD_STOP_OMEGA;
-  r->n = n;
+  r->n = g->n;
+  r->items = n;
   r->C = Cb;
   const uint64_t *cnt = ctx->h_count.p;
   // per-node outputs, written straight into the caller's arrays when given

@@ -115,6 +115,18 @@ uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c) {
   return (uint64_t)ceil(value);
 }
 
+// The cap for edge betweenness: a shortest path has at most VD - 1 edges, and a set of k
+// paths shattered by the ranges "paths through edge e" puts each of its paths in 2^(k-1)
+// ranges, i.e. on 2^(k-1) of its edges: floor(log2(VD - 1)) + 1 replaces floor(log2(VD - 2)) + 1.
+uint64_t omega_edges_of(double epsilon, double delta, uint32_t vd, double c) {
+  const uint32_t base = vd > 2 ? vd - 1 : 1u;
+  uint32_t fl = 0;
+  for (uint32_t x = base; x > 1; x >>= 1) ++fl;
+  const double bits = (double)(fl + 1);
+  const double value = c / (epsilon * epsilon) * (bits + log(2.0 / delta));
+  return (uint64_t)ceil(value);
+}
+
 uint64_t alpha_of(uint64_t omega) { return std::max<uint64_t>(1, omega / 100); }
 
 uint64_t interval_of(uint64_t omega) {

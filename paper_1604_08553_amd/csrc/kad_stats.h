@@ -15,6 +15,7 @@ void parallel_ranges(uint32_t n, const std::function<void(uint32_t, uint32_t, un
 unsigned parallel_threads(uint32_t n);
 
 uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c);
+uint64_t omega_edges_of(double epsilon, double delta, uint32_t vd, double c);
 uint64_t alpha_of(uint64_t omega);
 uint64_t interval_of(uint64_t omega);
 

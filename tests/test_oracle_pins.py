@@ -833,3 +833,113 @@ def test_forward_search_same_pairs_scans_more(oracle_lib):
     assert np.array_equal(B.s, F.s) and np.array_equal(B.t, F.t)
     assert np.array_equal(np.diff(B.path_off.astype(np.int64)), np.diff(F.path_off.astype(np.int64)))
     assert F.arcs.mean() > 3 * B.arcs.mean()
+
+
+# ----------------------------------------------------------------------------- edge betweenness
+#
+# Section 1: the method adapts to the centrality of edges.  bc(e) = 1/(n(n-1)) * sum over
+# ordered pairs s != t of sigma_st(e)/sigma_st; a sampled path hits every edge on it.
+
+
+def test_edge_brandes_matches_networkx(oracle_lib):
+    import networkx as nx
+    for g in _small_graphs() + [gg.gnp(40, 0.1, 1), gg.gnp(30, 0.08, 2, directed=True)]:
+        ebc = oracle_lib.edge_brandes(g)
+        eid = oracle_lib.edge_ids(g)
+        ref = nx.edge_betweenness_centrality(_nx(g), normalized=False)
+        scale = (1.0 if g.directed else 2.0) / (g.n * (g.n - 1))
+        src, dst = g.edges()
+        for pos in range(g.arcs):
+            u, v = int(src[pos]), int(dst[pos])
+            key = (u, v) if (g.directed or (u, v) in ref) else (v, u)
+            assert abs(ebc[eid[pos]] - ref[key] * scale) < 1e-12, (g.name, u, v)
+
+
+def test_edge_brandes_closed_forms(oracle_lib):
+    n = 9
+    ebc = oracle_lib.edge_brandes(gg.path_graph(n))    # edge {i, i+1} has id i
+    for i in range(n - 1):
+        assert abs(ebc[i] - 2 * (i + 1) * (n - 1 - i) / (n * (n - 1))) < 1e-14
+    assert np.allclose(oracle_lib.edge_brandes(gg.star_graph(n)), 2.0 / n, atol=1e-14)
+    # directed cycle: arc i -> i+1 lies on the one path of every pair whose forward distance
+    # passes it: sum over distances d of d pairs, i.e. n(n-1)/2 pairs
+    assert np.allclose(oracle_lib.edge_brandes(gg.cycle_graph(n, True)), 0.5, atol=1e-14)
+    # K_n: an edge carries only its own two ordered pairs
+    assert np.allclose(oracle_lib.edge_brandes(gg.complete_graph(7)), 2.0 / (7 * 6), atol=1e-14)
+
+
+def test_edge_ids_structure(oracle_lib):
+    g = gg.gnp(50, 0.1, 4)
+    eid = oracle_lib.edge_ids(g)
+    src, dst = g.edges()
+    m = oracle_lib.edge_count(g)
+    assert m == g.arcs // 2 and np.array_equal(np.bincount(eid, minlength=m), np.full(m, 2))
+    canon = {}
+    for pos in range(g.arcs):
+        canon.setdefault((min(src[pos], dst[pos]), max(src[pos], dst[pos])), set()).add(int(eid[pos]))
+    assert all(len(ids) == 1 for ids in canon.values())
+    # ids follow the order of the u < v arcs in CSR order
+    order = [int(eid[p]) for p in range(g.arcs) if src[p] < dst[p]]
+    assert order == list(range(m))
+    d = gg.gnp(30, 0.1, 5, True)
+    assert np.array_equal(oracle_lib.edge_ids(d), np.arange(d.arcs))
+
+
+def test_expected_edge_hits_equal_edge_betweenness(oracle_lib):
+    for g in [gg.gnp(30, 0.12, 7), gg.gnp(25, 0.12, 8, directed=True), gg.grid(5, 6)]:
+        N = 120000
+        cnt, _ = oracle_lib.edge_hits(g, 5, 1, 0, N, threads=4)
+        bt = cnt / N
+        bc = oracle_lib.edge_brandes(g)
+        sd = np.sqrt(np.maximum(bc * (1 - bc), 1e-12) / N)
+        assert np.all(np.abs(bt - bc) <= 5 * sd + 1e-9), np.max(np.abs(bt - bc) / sd)
+
+
+def test_edge_hits_are_path_edges(oracle_lib):
+    g = oracle_lib.Graph(gg.workload("er2000"))
+    S = oracle_lib.sample_paths(g, 3, 1, 0, 5000, threads=4)
+    cnt, arcs = oracle_lib.edge_hits(g, 3, 1, 0, 5000, threads=4)
+    eid = oracle_lib.edge_ids(g)
+    ref = np.zeros(oracle_lib.edge_count(g), dtype=np.uint64)
+    row, col = g.row.astype(np.int64), g.col
+    for k in range(5000):
+        p = [int(x) for x in S.path(k)]
+        for a, b in zip(p, p[1:]):
+            pos = row[a] + int(np.searchsorted(col[row[a]:row[a + 1]], b))
+            ref[eid[pos]] += 1
+    assert np.array_equal(cnt, ref) and arcs == int(S.arcs.sum())
+    assert int(cnt.sum()) == int(sum(max(len(S.path(k)) - 1, 0) for k in range(5000)))
+
+
+def test_omega_edges_is_omega_with_one_more_node(oracle_lib):
+    """floor(log2(VD - 1)) + 1 for edges is the nodes' floor(log2(VD' - 2)) + 1 at VD' = VD + 1."""
+    for lam in (0.03, 0.01, 0.002):
+        for vd in (2, 3, 4, 5, 8, 9, 17, 1000):
+            assert oracle_lib.omega_edges(lam, 0.1, vd) == oracle_lib.omega(lam, 0.1, vd + 1)
+
+
+def test_run_edges_invariants(oracle_lib):
+    g = oracle_lib.Graph(gg.workload("er2000"))
+    r1 = oracle_lib.run(g, 0.01, 0.1, seed=2, threads=1, target="edges")
+    r4 = oracle_lib.run(g, 0.01, 0.1, seed=2, threads=4, target="edges")
+    for key in ("count", "count0", "tau", "lower", "upper"):
+        assert np.array_equal(np.asarray(r1[key]), np.asarray(r4[key])), key
+    assert r1["omega"] == oracle_lib.omega_edges(0.01, 0.1, 8) and r1["vd"] == 8
+    assert len(r1["count"]) == oracle_lib.edge_count(g)
+    cnt, arcs = oracle_lib.edge_hits(g, 2, 1, 0, int(r1["tau"]), threads=4)
+    assert np.array_equal(cnt, r1["count"]) and arcs == r1["arcs"]
+
+
+@pytest.mark.slow
+def test_epsilon_guarantee_edges(oracle_lib):
+    """Theorem 1 over edges: every edge estimate within lambda in (nearly) every run."""
+    g = oracle_lib.Graph(gg.workload("er2000"))
+    bc = oracle_lib.edge_brandes(g)
+    runs, bad_eps, bad_cov = 50, 0, 0
+    for seed in range(1, runs + 1):
+        r = oracle_lib.run(g, 0.01, 0.1, seed=seed, threads=8, target="edges")
+        if np.max(np.abs(r["bc"] - bc)) > 0.01:
+            bad_eps += 1
+        if not np.all((r["lower"] <= bc) & (bc <= r["upper"])):
+            bad_cov += 1
+    assert bad_eps <= 0.1 * runs and bad_cov <= 0.1 * runs
