@@ -146,7 +146,8 @@ def _same_result(a, b):
 
 def bench_batch(args, torch, gg, kad):
     """256-graph family: engine (one step = one kad_run_batch of all queries) against
-    the same queries run one after another with kad_run."""
+    the same queries run one after another with kad_run, in its default launch mode
+    (recorded batch chains) and on the plain single-graph path."""
     ngraphs = 256
     t0 = time.perf_counter()
     csrs = [gg.batch_graph(i) for i in range(ngraphs)]
@@ -155,35 +156,51 @@ def bench_batch(args, torch, gg, kad):
           file=sys.stderr, flush=True)
     ctx = kad.Context(0)
     Gs = [kad.Graph(ctx, g) for g in csrs]
-    eps = 0.01
+    eps = args.epsilon
     kw = dict(epsilon=eps, delta=args.delta, seed=args.seed)
     params = [dict(kw) for _ in Gs]
     for w in range(args.warmup):
         kad.run_batch(ctx, Gs, params)
-        for G in Gs:
-            kad.run(ctx, G, **kw)
+        for mode in ("graph", "plain"):
+            ctx.set_exec(mode)
+            for G in Gs:
+                kad.run(ctx, G, **kw)
+        ctx.set_exec("graph")
         print(f"[bench] warmup {w} done", file=sys.stderr, flush=True)
-    # sequential single runs
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for s in range(args.steps):
-        single = [kad.run(ctx, G, **kw) for G in Gs]
-    torch.cuda.synchronize()
-    seq_s = (time.perf_counter() - t0) / args.steps
-    print(f"[bench] sequential kad_run: {seq_s:.3f} s per pass", file=sys.stderr, flush=True)
+    # sequential single runs: recorded batch chains, then the plain single-graph path
+    seq = {}
+    for mode in ("graph", "plain"):
+        ctx.set_exec(mode)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(args.steps):
+            runs_m = [kad.run(ctx, G, **kw) for G in Gs]
+        torch.cuda.synchronize()
+        seq[mode] = ((time.perf_counter() - t0) / args.steps, runs_m)
+        print(f"[bench] sequential kad_run ({mode}): {seq[mode][0]:.3f} s per pass",
+              file=sys.stderr, flush=True)
+    ctx.set_exec("graph")
+    seq_s, single = seq["graph"]
+    plain_s, plain = seq["plain"]
     # the engine
-    ctx.set_timing(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
         batch = kad.run_batch(ctx, Gs, params)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    step_s = elapsed / args.steps
+    # the engine's sampler launches timed by events, in one further step
+    ctx.set_timing(True)
+    t1 = time.perf_counter()
+    kad.run_batch(ctx, Gs, params)
+    torch.cuda.synchronize()
+    timed_elapsed = time.perf_counter() - t1
     tm = ctx.timing()
     ctx.set_timing(False)
-    step_s = elapsed / args.steps
     print(f"[bench] kad_run_batch: {step_s:.3f} s per step", file=sys.stderr, flush=True)
-    identical = all(_same_result(a, b) for a, b in zip(batch, single))
+    identical = all(_same_result(a, b) for a, b in zip(batch, single)) and \
+        all(_same_result(a, b) for a, b in zip(plain, single))
     paths = sum(r["alpha"] + r["tau"] for r in batch)
     arcs = sum(r["arcs_scanned"] + r["pilot_arcs_scanned"] for r in batch)
     alg = algorithmic_bytes(tm["arcs"], tm["nodes"], tm["hits"])
@@ -205,11 +222,14 @@ def bench_batch(args, torch, gg, kad):
         "time_to_epsilon_s": step_s,
         "sequential_time_to_epsilon_s": seq_s,
         "speedup_vs_sequential": seq_s / step_s,
+        "plain_sequential_time_to_epsilon_s": plain_s,
+        "speedup_vs_plain": plain_s / step_s,
         "results_identical_to_single_runs": identical,
-        "sampler": {"launches": tm["launches"], "samples": tm["samples"],
+        "sampler": {"note": "one further engine step with event timing",
+                    "launches": tm["launches"], "samples": tm["samples"],
                     "avg_launch_ms": avg_launch_s * 1e3,
                     "gteps_in_kernel": tm["arcs"] / max(tm["seconds"], 1e-12) / 1e9,
-                    "busy_fraction": tm["seconds"] / elapsed},
+                    "busy_fraction": tm["seconds"] / timed_elapsed},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "sampler_kernel (multi-segment)"},
@@ -218,6 +238,34 @@ def bench_batch(args, torch, gg, kad):
         G.close()
     ctx.close()
     print(json.dumps(out), flush=True)
+
+
+def time_modes(ctx, G, kw, ref, torch, kad, reps=3):
+    """Warm time to epsilon of one call in each of kad_run's launch modes -- recorded
+    batch chains, call by call, and the plain single-graph path -- after one untimed call,
+    and whether each result equals the headline's."""
+    import numpy as np
+    ref = {k: (np.copy(v) if hasattr(v, "shape") else v) for k, v in ref.items()}
+    out = {}
+    for mode in ("graph", "stream", "plain"):
+        ctx.set_exec(mode)
+        r = kad.run(ctx, G, **kw)
+        same = (r["tau"] == ref["tau"] and r["arcs_scanned"] == ref["arcs_scanned"]
+                and all(np.array_equal(r[k], ref[k]) for k in ("count", "lower", "upper")))
+        arrays = {k: r[k] for k in ("count", "bc", "lower", "upper")}
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            kad.run(ctx, G, out=arrays, **kw)
+        torch.cuda.synchronize()
+        t = (time.perf_counter() - t0) / reps
+        out[mode] = {"time_to_epsilon_s": t, "identical": bool(same)}
+        print(f"[bench] exec {mode}: {t * 1e3:.2f} ms per call, identical={same}",
+              file=sys.stderr, flush=True)
+    ctx.set_exec("graph")
+    out["graph_vs_plain_speedup"] = out["plain"]["time_to_epsilon_s"] / out["graph"]["time_to_epsilon_s"]
+    out["graph_vs_stream_speedup"] = out["stream"]["time_to_epsilon_s"] / out["graph"]["time_to_epsilon_s"]
+    return out
 
 
 def _pct(xs, q):
@@ -442,6 +490,10 @@ def main():
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-batch", type=int, default=65536)
     ap.add_argument("--check-interval", type=int, default=0)
+    ap.add_argument("--exec", default="graph", choices=["graph", "stream", "plain"],
+                    help="kad_run launch mode of the timed steps")
+    ap.add_argument("--no-modes", action="store_true",
+                    help="skip timing the call in every launch mode")
     ap.add_argument("--cpu-samples", type=int, default=150000,
                     help="oracle sampling-rate baseline: main-phase ids (--no-cpu-full-run)")
     ap.add_argument("--cpu-full-run", dest="cpu_full_run", action="store_true", default=None,
@@ -527,7 +579,7 @@ def main():
             first_call_s = r["seconds"]
         print(f"[bench] warmup {w}: tau={r['tau']} {r['seconds']:.3f} s", file=sys.stderr, flush=True)
 
-    ctx.set_timing(True)
+    ctx.set_exec(args.exec)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     runs = []
@@ -541,8 +593,18 @@ def main():
               f"{r['seconds']:.3f} s", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
+    exec_info = ctx.exec_info()
+    # the sampler's own launch time: the same call again with every sampler launch timed
+    # by HIP events on its stream (timing launches call by call)
+    ctx.set_timing(True)
+    timed_steps = max(1, min(args.steps, 5))
+    for s in range(timed_steps):
+        rt = kad.run(ctx, G, out=arrays, **kw)
+        assert rt["tau"] == runs[0]["tau"]
     tm = ctx.timing()
     ctx.set_timing(False)
+    print(f"[bench] event-timed pass: {tm['launches']} launches, {tm['seconds']:.4f} s",
+          file=sys.stderr, flush=True)
 
     paths = sum(r["alpha"] + r["tau"] for r in runs)
     arcs = sum(r["arcs_scanned"] + r["pilot_arcs_scanned"] for r in runs)
@@ -582,7 +644,10 @@ def main():
         "check_interval": r0["interval"], "stop": "rule" if r0["stop_reason"] else "omega",
         "phases_s": {k: sum(r[f"seconds_{k}"] for r in runs) / len(runs)
                      for k in ("setup", "pilot", "delta", "main")},
-        "sampler": {"launches": tm["launches"], "samples": tm["samples"],
+        "exec": {"mode": args.exec, "chains_recorded": exec_info["records"],
+                 "chain_replays": exec_info["replays"]},
+        "sampler": {"note": f"from {timed_steps} further calls with event timing",
+                    "launches": tm["launches"], "samples": tm["samples"],
                     "avg_launch_ms": avg_launch_s * 1e3,
                     "arcs_per_sample": tm["arcs"] / max(tm["samples"], 1),
                     "nodes_per_sample": tm["nodes"] / max(tm["samples"], 1),
@@ -593,6 +658,8 @@ def main():
                      "alg_bytes_per_launch": per_launch_bytes,
                      "hbm_bytes_per_launch": hbm},
     }
+    if not args.no_modes:
+        out["exec_modes"] = time_modes(ctx, G, kw, runs[0], torch, kad)
     # cold time to epsilon: a graph registered anew (upload, validation, transpose) and its
     # first run (vertex diameter, buffers) on the warm context
     G.close()

@@ -60,6 +60,21 @@ enum {
                                  with a union bound over the nodes, section 2) */
 };
 
+/* how kad_run launches its work (kad_ctx_set_exec); every mode gives the same result */
+enum {
+  KAD_EXEC_GRAPH = 0,  /* main-phase batches replay recorded hipGraphs: the sampling chain
+                          (sampler, wide-count fix, edge rewrite, host mirrors) and, in
+                          all-nodes runs, the batched reduction of the check intervals; the
+                          batch's sample range is read from a device descriptor, so one
+                          recording serves every batch of up to kernel_batch samples */
+  KAD_EXEC_STREAM = 1, /* the same chains launched call by call on the context's streams */
+  KAD_EXEC_PLAIN = 2   /* the plain single-graph path, kept as the baseline: no batching of
+                          check intervals, no persistent workgroups (one sample per
+                          workgroup, one launch per resident grid of samples), no pilot
+                          overlap and no recorded graphs; the host waits for every launch
+                          and checks after every interval */
+};
+
 /* per-sample flag bits reported by kad_sample_paths */
 enum {
   KAD_SAMPLE_OVERFLOW = 1u, /* a path count or the candidate-edge total reached 2^128 */
@@ -390,6 +405,15 @@ kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable);
  * searches, and hits (interior path nodes).  Any pointer may be NULL. */
 kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *samples,
                               double *seconds, uint64_t *arcs, uint64_t *nodes, uint64_t *hits);
+
+/* kad_run's launch mode (KAD_EXEC_*; default KAD_EXEC_GRAPH).  While timing is enabled
+ * KAD_EXEC_GRAPH launches call by call (the per-launch events sit inside the chain).
+ * The recorded chains are kept in the context and recorded again when the graph, the
+ * buffers or kernel_batch change.  KAD_EINVAL for an unknown mode. */
+kad_status kad_ctx_set_exec(kad_ctx *ctx, uint32_t mode);
+/* The mode, and how many chains kad_run has recorded and replayed in this context (any
+ * pointer may be NULL). */
+kad_status kad_ctx_get_exec(kad_ctx *ctx, uint32_t *mode, uint64_t *records, uint64_t *replays);
 
 const char *kad_last_error(void);
 

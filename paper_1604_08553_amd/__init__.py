@@ -123,6 +123,8 @@ def lib():
         "kad_autotune": ([vp, vp, u32, vp, vp, vp], st),
         "kad_ctx_set_timing": ([vp, i32], st),
         "kad_ctx_get_timing": ([vp, vp, vp, vp, vp, vp, vp], st),
+        "kad_ctx_set_exec": ([vp, u32], st),
+        "kad_ctx_get_exec": ([vp, vp, vp, vp], st),
         "kad_last_error": ([], C.c_char_p),
     }
     for name, (args, res) in sig.items():
@@ -157,6 +159,9 @@ def _u32(a):
 # ----------------------------------------------------------------------------- objects
 
 
+EXECS = {"graph": 0, "stream": 1, "plain": 2}
+
+
 class Context:
     """A HIP device with the library's working memory (``hbm_budget`` bytes, 0 = 90%
     of the free memory)."""
@@ -186,6 +191,17 @@ class Context:
 
     def set_timing(self, enable: bool = True):
         _check(lib().kad_ctx_set_timing(self.handle, 1 if enable else 0))
+
+    def set_exec(self, mode: str):
+        """How kad_run launches: "graph" (recorded batch chains, the default), "stream"
+        (call by call) or "plain" (the plain single-graph path); see kad_ctx_set_exec."""
+        _check(lib().kad_ctx_set_exec(self.handle, EXECS[mode]))
+
+    def exec_info(self) -> dict:
+        m, rec, rep = C.c_uint32(), C.c_uint64(), C.c_uint64()
+        _check(lib().kad_ctx_get_exec(self.handle, C.byref(m), C.byref(rec), C.byref(rep)))
+        name = {v: k for k, v in EXECS.items()}[m.value]
+        return {"mode": name, "records": rec.value, "replays": rep.value}
 
     def timing(self) -> dict:
         """Totals over the event-timed sampler launches (see kad_ctx_get_timing)."""

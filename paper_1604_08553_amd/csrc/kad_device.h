@@ -74,6 +74,20 @@ struct WideState {
   uint64_t *lbase;      // [slots * 2 * max_lev]
 };
 
+// The arguments of one batch in device memory.  A chain of launches recorded once into a
+// hipGraph reads them from here on every replay (kernels given a descriptor ignore the
+// corresponding arguments): the sampler and the wide-count fix take seed, phase, first,
+// count (and, over segments, nseg); the edge-path rewrite and the copies take count; the
+// batched hit reduction takes count and the number of check intervals niv.
+struct BatchDesc {
+  uint64_t seed;
+  uint64_t first;
+  uint32_t count;
+  uint32_t phase;
+  uint32_t niv;
+  uint32_t nseg;
+};
+
 struct SampleOut {
   uint32_t *s, *t, *len, *flags; // [count]
   uint32_t *nodes;               // [count] nodes reached by the two searches
@@ -90,16 +104,21 @@ struct SampleOut {
 
 // Sample ids [first, first + count) of `phase`, dynamically distributed over the
 // slot workgroups through *work (must be 0 at launch).
+// bd (device memory, may be null): the batch's arguments, read by the kernel in place of
+// seed, phase, first and count -- the launch is then valid for any batch of at most
+// `count` samples.
 hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed, uint32_t phase,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
-                          uint32_t grid, const LaunchShape &shape, hipStream_t stream);
+                          uint32_t grid, const LaunchShape &shape, hipStream_t stream,
+                          const BatchDesc *bd = nullptr);
 
 // Samples [0, count) of the launch, segment by segment (segs[] in device memory,
 // ascending `begin`, segs[0].begin == 0); st.n is the slot capacity (>= every
 // segment's n).
 hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const SlotState &st,
                                 uint32_t count, uint32_t *work, const SampleOut &out,
-                                uint32_t grid, const LaunchShape &shape, hipStream_t stream);
+                                uint32_t grid, const LaunchShape &shape, hipStream_t stream,
+                                const BatchDesc *bd = nullptr);
 
 // Sample again, with multi-limb path counts and no limit on the candidate edges but the
 // arena, the samples of the launch listed in list[0, *list_count) -- the sampler's fix
@@ -112,7 +131,8 @@ hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uin
                            const SampleSeg *segs, uint32_t nseg, const SlotState &st,
                            const WideState &ws, uint32_t count, bool all,
                            const uint32_t *list, const uint32_t *list_count, uint32_t *work,
-                           const SampleOut &out, hipStream_t stream);
+                           const SampleOut &out, hipStream_t stream,
+                           const BatchDesc *bd = nullptr);
 
 // Node tiles of the hit reduction: 8,192 ids each, at most this many tiles (graphs of
 // up to 2^25 nodes).
@@ -150,7 +170,7 @@ hipError_t launch_hit_batch(const uint32_t *path, const uint32_t *len, uint32_t 
                             uint32_t nsamp, uint32_t per_iv, uint32_t n, uint64_t *count,
                             const uint32_t *group, uint64_t *gmax, uint32_t ngroups,
                             uint32_t *tmp, uint64_t *ivmax, uint64_t *snap,
-                            hipStream_t stream);
+                            hipStream_t stream, const BatchDesc *bd = nullptr);
 
 // Edge betweenness: the paths of samples [0, nsamp) (node ids, `stride` apart) rewritten
 // as edge ids with a placeholder entry at each end (epath, estride >= stride + 1 apart;
@@ -159,7 +179,8 @@ hipError_t launch_hit_batch(const uint32_t *path, const uint32_t *len, uint32_t 
 hipError_t launch_edge_paths(const uint32_t *path, const uint32_t *len, uint32_t stride,
                              uint32_t nsamp, const uint32_t *row, const uint32_t *col,
                              const uint32_t *eid, uint32_t *epath, uint32_t *elen,
-                             uint32_t estride, hipStream_t stream);
+                             uint32_t estride, hipStream_t stream,
+                             const BatchDesc *bd = nullptr);
 
 // Zero a device buffer with a kernel (no memset node when captured).
 hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream);
@@ -171,11 +192,12 @@ hipError_t launch_group_map(const uint64_t *count, uint32_t n, const uint32_t *c
                             uint32_t *group, hipStream_t stream);
 // dst[i] = src[i], i < count, by a kernel on `stream`; either side may be pinned,
 // coherent host memory.  Used instead of runtime copies where a copy must not wait
-// behind kernels of other streams.
+// behind kernels of other streams, and inside recorded graphs.  With bd the kernel
+// copies bd->count entries (at most `count`, the launch's size).
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t count,
-                              hipStream_t stream);
+                              hipStream_t stream, const BatchDesc *bd = nullptr);
 hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t count,
-                              hipStream_t stream);
+                              hipStream_t stream, const BatchDesc *bd = nullptr);
 // p[i] = value for i < count.
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 

@@ -107,6 +107,27 @@ struct OutSet {
   kad_status ensure_edges(uint32_t cap, uint32_t estride);
 };
 
+// A chain of launches recorded once into a hipGraph and replayed; `key` lists everything
+// the recording bakes in (buffer addresses, sizes, launch shapes), and a replay with
+// another key records the chain again.
+struct BatchGraph {
+  std::vector<uint64_t> key;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  uint64_t records = 0, replays = 0;
+  BatchGraph() = default;
+  BatchGraph(const BatchGraph &) = delete;
+  BatchGraph &operator=(const BatchGraph &) = delete;
+  ~BatchGraph() { release(); }
+  void release() {
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    exec = nullptr;
+    graph = nullptr;
+    key.clear();
+  }
+};
+
 class Engine;
 void destroy_engine(Engine *e);
 
@@ -171,6 +192,16 @@ struct kad_ctx {
   kad::Engine *engine = nullptr;
   // device address of the fixed scratch array used by kad_hit_counts_noalloc
   void *noalloc = nullptr;
+  // how kad_run launches (KAD_EXEC_*); with KAD_EXEC_GRAPH its main-phase batches replay
+  // recorded chains: per output set the sampling chain (bgraph[set]) and the batched
+  // reduction (bgraph[2 + set]), reading the batch from d_bd[set] (copied from h_bd[set]
+  // by the sampling chain).  cstream: the stream chains are recorded on.
+  uint32_t exec = KAD_EXEC_GRAPH;
+  hipStream_t cstream = nullptr;
+  kad::BatchGraph bgraph[4];
+  kad::PinBuf<kad::BatchDesc> h_bd;
+  kad::DevBuf<kad::BatchDesc> d_bd;
+  kad::PinBuf<uint64_t> snaps;  // kad_run's check snapshots, one per check of a batch
   ~kad_ctx() {
     kad::destroy_engine(engine);
     for (auto e : chunk_ev) (void)hipEventDestroy(e);

@@ -984,13 +984,18 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
 // Occupancy targets: 5 waves per SIMD (VGPR-bound) for 128 and 256 threads; 64-thread
 // workgroups are LDS-bound at 4.
 template <int BLOCK, bool MULTI>
-__global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(GraphDev g0, SlotState st, uint64_t seed0,
-                                                        uint32_t phase0, uint64_t first0,
+__global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(GraphDev g0, SlotState st, uint64_t seed_a,
+                                                        uint32_t phase_a, uint64_t first_a,
                                                         const SampleSeg *__restrict__ segs,
-                                                        uint32_t nseg, uint32_t count,
+                                                        uint32_t nseg_a, uint32_t count_a,
                                                         uint32_t *work, SampleOut out,
-                                                        uint32_t small_exp) {
+                                                        uint32_t small_exp,
+                                                        const BatchDesc *__restrict__ bd) {
   constexpr int NWAVES = BLOCK / WAVE;
+  // a replayed launch takes its batch from the descriptor (uniform, scalar loads)
+  const uint64_t seed0 = bd ? bd->seed : seed_a, first0 = bd ? bd->first : first_a;
+  const uint32_t phase0 = bd ? bd->phase : phase_a, count = bd ? bd->count : count_a;
+  const uint32_t nseg = bd ? bd->nseg : nseg_a;
   __shared__ Lds<BLOCK> L;
   const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
   const size_t n = st.n;  // slot capacity
@@ -1590,7 +1595,10 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value) {
 // A copy by a kernel between device memory and pinned, coherent host memory (the GPU
 // reads or writes the host side over the bus); the stream's next event covers it.
 template <typename T>
-__global__ __launch_bounds__(256) void copy_kernel(T *dst, const T *src, uint64_t count) {
+__global__ __launch_bounds__(256) void copy_kernel(T *dst, const T *src, uint64_t count_a,
+                                                   const BatchDesc *__restrict__ bd,
+                                                   uint32_t per) {
+  const uint64_t count = bd ? (uint64_t)bd->count * per : count_a;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
     dst[i] = src[i];
@@ -1776,12 +1784,17 @@ enum : uint32_t { LV_LO = 0, LV_HI = 1, LV_STRIDE = 2, LV_WIDTH = 3 };
 // list == nullptr: every launch index below all_count.
 template <bool MULTI>
 __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *__restrict__ segs,
-                                                  uint32_t nseg, uint64_t seed0, uint32_t phase0,
-                                                  uint64_t first0, SlotState st, WideState ws,
+                                                  uint32_t nseg_a, uint64_t seed_a,
+                                                  uint32_t phase_a, uint64_t first_a,
+                                                  SlotState st, WideState ws,
                                                   const uint32_t *list,
-                                                  const uint32_t *list_count, uint32_t all_count,
-                                                  uint32_t *work, SampleOut out) {
+                                                  const uint32_t *list_count, uint32_t all_a,
+                                                  uint32_t *work, SampleOut out,
+                                                  const BatchDesc *__restrict__ bd) {
   __shared__ WideLds L;
+  const uint64_t seed0 = bd ? bd->seed : seed_a, first0 = bd ? bd->first : first_a;
+  const uint32_t phase0 = bd ? bd->phase : phase_a, all_count = bd ? bd->count : all_a;
+  const uint32_t nseg = bd ? bd->nseg : nseg_a;
   const uint32_t tid = threadIdx.x, wid = tid / WAVE, lane = lane_id();
   const size_t n = st.n;
   const size_t slot = blockIdx.x;
@@ -2359,19 +2372,19 @@ hipError_t launch_sampler_variant(int block, uint32_t grid, hipStream_t stream, 
                                   const SlotState &st, uint64_t seed, uint32_t phase,
                                   uint64_t first, const SampleSeg *segs, uint32_t nseg,
                                   uint32_t count, uint32_t *work, const SampleOut &out,
-                                  uint32_t small_exp) {
+                                  uint32_t small_exp, const BatchDesc *bd) {
   switch (block) {
     case 64:
       hipLaunchKernelGGL((sampler_kernel<64, MULTI>), dim3(grid), dim3(64), 0, stream, g, st,
-                         seed, phase, first, segs, nseg, count, work, out, small_exp);
+                         seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
       break;
     case 128:
       hipLaunchKernelGGL((sampler_kernel<128, MULTI>), dim3(grid), dim3(128), 0, stream, g, st,
-                         seed, phase, first, segs, nseg, count, work, out, small_exp);
+                         seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
       break;
     case 256:
       hipLaunchKernelGGL((sampler_kernel<256, MULTI>), dim3(grid), dim3(256), 0, stream, g, st,
-                         seed, phase, first, segs, nseg, count, work, out, small_exp);
+                         seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
       break;
     default:
       return hipErrorInvalidValue;
@@ -2381,38 +2394,40 @@ hipError_t launch_sampler_variant(int block, uint32_t grid, hipStream_t stream, 
 
 hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed, uint32_t phase,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
-                          uint32_t grid, const LaunchShape &shape, hipStream_t stream) {
+                          uint32_t grid, const LaunchShape &shape, hipStream_t stream,
+                          const BatchDesc *bd) {
   if (count == 0) return hipSuccess;
-  if (st.n < g.n || grid > st.slots) return hipErrorInvalidValue;
+  if (st.n < g.n || grid > st.slots || grid == 0) return hipErrorInvalidValue;
   return launch_sampler_variant<false>(shape.block, grid, stream, g, st, seed, phase, first,
-                                       nullptr, 0u, count, work, out, shape.small_exp);
+                                       nullptr, 0u, count, work, out, shape.small_exp, bd);
 }
 
 hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const SlotState &st,
                                 uint32_t count, uint32_t *work, const SampleOut &out,
-                                uint32_t grid, const LaunchShape &shape, hipStream_t stream) {
+                                uint32_t grid, const LaunchShape &shape, hipStream_t stream,
+                                const BatchDesc *bd) {
   if (count == 0) return hipSuccess;
-  if (nseg == 0 || grid > st.slots) return hipErrorInvalidValue;
+  if (nseg == 0 || grid > st.slots || grid == 0) return hipErrorInvalidValue;
   GraphDev none{};
   return launch_sampler_variant<true>(shape.block, grid, stream, none, st, 0ull, 0u, 0ull, segs,
-                                      nseg, count, work, out, shape.small_exp);
+                                      nseg, count, work, out, shape.small_exp, bd);
 }
 
 hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
                            const SampleSeg *segs, uint32_t nseg, const SlotState &st,
                            const WideState &ws, uint32_t count, bool all,
                            const uint32_t *list, const uint32_t *list_count, uint32_t *work,
-                           const SampleOut &out, hipStream_t stream) {
+                           const SampleOut &out, hipStream_t stream, const BatchDesc *bd) {
   if (count == 0) return hipSuccess;
   if (ws.slots == 0 || ws.slots > st.slots || !ws.arena || !work) return hipErrorInvalidValue;
   if (!all && (!list || !list_count)) return hipErrorInvalidValue;
   const uint32_t *lst = all ? nullptr : list;
   if (segs)
     hipLaunchKernelGGL(wide_kernel<true>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
-                       seed, phase, first, st, ws, lst, list_count, count, work, out);
+                       seed, phase, first, st, ws, lst, list_count, count, work, out, bd);
   else
     hipLaunchKernelGGL(wide_kernel<false>, dim3(ws.slots), dim3(WB), 0, stream, g, segs, nseg,
-                       seed, phase, first, st, ws, lst, list_count, count, work, out);
+                       seed, phase, first, st, ws, lst, list_count, count, work, out, bd);
   return hipGetLastError();
 }
 
@@ -2498,9 +2513,11 @@ hipError_t launch_hit_reduce(const uint32_t *path, const uint32_t *len, uint32_t
 // snapshot per interval (clearing the per-interval maxima).
 __global__ __launch_bounds__(HIT_BLOCK) void iv_count_kernel(const uint32_t *path,
                                                              const uint32_t *len,
-                                                             uint32_t stride, uint32_t nsamp,
+                                                             uint32_t stride, uint32_t nsamp_a,
                                                              uint32_t per_iv, uint32_t n,
-                                                             uint32_t *tmp) {
+                                                             uint32_t *tmp,
+                                                             const BatchDesc *__restrict__ bd) {
+  const uint32_t nsamp = bd ? bd->count : nsamp_a;
   const uint64_t entries = (uint64_t)nsamp * stride;
   for (uint64_t e = (uint64_t)blockIdx.x * HIT_BLOCK + threadIdx.x; e < entries;
        e += (uint64_t)gridDim.x * HIT_BLOCK) {
@@ -2511,11 +2528,13 @@ __global__ __launch_bounds__(HIT_BLOCK) void iv_count_kernel(const uint32_t *pat
   }
 }
 
-__global__ __launch_bounds__(HIT_BLOCK) void iv_prefix_kernel(uint32_t n, uint32_t niv,
+__global__ __launch_bounds__(HIT_BLOCK) void iv_prefix_kernel(uint32_t n, uint32_t niv_a,
                                                               uint32_t *tmp, uint64_t *count,
                                                               const uint32_t *group,
                                                               uint32_t ngroups,
-                                                              uint64_t *ivmax) {
+                                                              uint64_t *ivmax,
+                                                              const BatchDesc *__restrict__ bd) {
+  const uint32_t niv = bd ? bd->niv : niv_a;
   for (uint32_t v = blockIdx.x * HIT_BLOCK + threadIdx.x; v < n; v += gridDim.x * HIT_BLOCK) {
     uint64_t c = 0;
     bool hit = false;
@@ -2534,9 +2553,11 @@ __global__ __launch_bounds__(HIT_BLOCK) void iv_prefix_kernel(uint32_t n, uint32
   }
 }
 
-__global__ __launch_bounds__(HIT_BLOCK) void iv_snap_kernel(uint32_t niv, uint32_t ngroups,
+__global__ __launch_bounds__(HIT_BLOCK) void iv_snap_kernel(uint32_t niv_a, uint32_t ngroups,
                                                             uint64_t *ivmax, uint64_t *gmax,
-                                                            uint64_t *snap) {
+                                                            uint64_t *snap,
+                                                            const BatchDesc *__restrict__ bd) {
+  const uint32_t niv = bd ? bd->niv : niv_a;
   for (uint32_t g = blockIdx.x * HIT_BLOCK + threadIdx.x; g < ngroups;
        g += gridDim.x * HIT_BLOCK) {
     uint64_t m = gmax[g];
@@ -2554,20 +2575,20 @@ hipError_t launch_hit_batch(const uint32_t *path, const uint32_t *len, uint32_t 
                             uint32_t nsamp, uint32_t per_iv, uint32_t n, uint64_t *count,
                             const uint32_t *group, uint64_t *gmax, uint32_t ngroups,
                             uint32_t *tmp, uint64_t *ivmax, uint64_t *snap,
-                            hipStream_t stream) {
+                            hipStream_t stream, const BatchDesc *bd) {
   if (nsamp == 0) return hipSuccess;
   if (per_iv == 0 || !group || !gmax || !tmp || !ivmax || !snap) return hipErrorInvalidValue;
   const uint32_t niv = (nsamp + per_iv - 1) / per_iv;
   const uint64_t entries = (uint64_t)nsamp * stride;
   const uint32_t b1 = (uint32_t)std::min<uint64_t>((entries + HIT_BLOCK - 1) / HIT_BLOCK, 4096);
   hipLaunchKernelGGL(iv_count_kernel, dim3(b1), dim3(HIT_BLOCK), 0, stream, path, len, stride,
-                     nsamp, per_iv, n, tmp);
+                     nsamp, per_iv, n, tmp, bd);
   const uint32_t b2 = std::min<uint32_t>((n + HIT_BLOCK - 1) / HIT_BLOCK, 4096);
   hipLaunchKernelGGL(iv_prefix_kernel, dim3(b2), dim3(HIT_BLOCK), 0, stream, n, niv, tmp, count,
-                     group, ngroups, ivmax);
+                     group, ngroups, ivmax, bd);
   const uint32_t b3 = std::max<uint32_t>(1, std::min<uint32_t>((ngroups + HIT_BLOCK - 1) / HIT_BLOCK, 1024));
   hipLaunchKernelGGL(iv_snap_kernel, dim3(b3), dim3(HIT_BLOCK), 0, stream, niv, ngroups, ivmax,
-                     gmax, snap);
+                     gmax, snap, bd);
   return hipGetLastError();
 }
 
@@ -2625,8 +2646,10 @@ __global__ __launch_bounds__(256) void edge_path_kernel(const uint32_t *__restri
                                                         const uint32_t *__restrict__ col,
                                                         const uint32_t *__restrict__ eid,
                                                         uint32_t *epath, uint32_t *elen,
-                                                        uint32_t estride) {
+                                                        uint32_t estride,
+                                                        const BatchDesc *__restrict__ bd) {
   const uint32_t steps = stride - 1;
+  if (bd) nsamp = bd->count;
   const uint64_t total = (uint64_t)nsamp * steps;
   for (uint64_t e = (uint64_t)blockIdx.x * 256 + threadIdx.x; e < total;
        e += (uint64_t)gridDim.x * 256) {
@@ -2655,13 +2678,13 @@ __global__ __launch_bounds__(256) void edge_path_kernel(const uint32_t *__restri
 hipError_t launch_edge_paths(const uint32_t *path, const uint32_t *len, uint32_t stride,
                              uint32_t nsamp, const uint32_t *row, const uint32_t *col,
                              const uint32_t *eid, uint32_t *epath, uint32_t *elen,
-                             uint32_t estride, hipStream_t stream) {
+                             uint32_t estride, hipStream_t stream, const BatchDesc *bd) {
   if (nsamp == 0) return hipSuccess;
   if (stride < 2 || estride < stride + 1) return hipErrorInvalidValue;
   const uint64_t total = (uint64_t)nsamp * (stride - 1);
   const uint32_t blocks = (uint32_t)std::min<uint64_t>((total + 255) / 256, 4096);
   hipLaunchKernelGGL(edge_path_kernel, dim3(blocks), dim3(256), 0, stream, path, len, stride,
-                     nsamp, row, col, eid, epath, elen, estride);
+                     nsamp, row, col, eid, epath, elen, estride, bd);
   return hipGetLastError();
 }
 
@@ -2694,18 +2717,20 @@ hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream) {
 }
 
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t count,
-                              hipStream_t stream) {
+                              hipStream_t stream, const BatchDesc *bd) {
   if (count == 0) return hipSuccess;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 1024);
-  hipLaunchKernelGGL(copy_kernel<uint32_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count);
+  hipLaunchKernelGGL(copy_kernel<uint32_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count,
+                     bd, 1u);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t count,
-                              hipStream_t stream) {
+                              hipStream_t stream, const BatchDesc *bd) {
   if (count == 0) return hipSuccess;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 1024);
-  hipLaunchKernelGGL(copy_kernel<uint64_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count);
+  hipLaunchKernelGGL(copy_kernel<uint64_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count,
+                     bd, 1u);
   return hipGetLastError();
 }
 

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <memory>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "kad_internal.h"
@@ -591,6 +592,147 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
   return KAD_OK;
 }
 
+// ---------------------------------------------------------------- recorded batch chains
+// What a recorded chain bakes in, as words (addresses and sizes); see BatchGraph.
+struct Key {
+  std::vector<uint64_t> v;
+  template <typename T>
+  Key &operator<<(T x) {
+    if constexpr (std::is_pointer<T>::value) v.push_back((uint64_t)(uintptr_t)x);
+    else v.push_back((uint64_t)x);
+    return *this;
+  }
+  Key &operator<<(const kad::GraphDev &g) {
+    return *this << g.n << g.arcs << g.row << g.col << g.rrow << g.rcol << g.forward;
+  }
+  Key &operator<<(const kad::SlotState &t) {
+    return *this << t.slots << t.n << t.pi_cap << t.rec << t.visit << t.pi;
+  }
+  Key &operator<<(const kad::WideState &w) {
+    return *this << w.slots << w.max_lev << w.arena_limbs << w.arena << w.lv << w.lbase;
+  }
+  Key &operator<<(const kad::SampleOut &o) {
+    return *this << o.s << o.t << o.len << o.flags << o.nodes << o.arcs << o.path << o.stride
+                 << o.fix_list << o.fix_count;
+  }
+};
+
+// Record the launches `fn` makes on the stream it is given into bg, unless bg already
+// holds a recording with this key.
+kad_status record_chain(kad_ctx *ctx, kad::BatchGraph &bg, const Key &key,
+                        const std::function<kad_status(hipStream_t)> &fn) {
+  if (bg.exec && bg.key == key.v) return KAD_OK;
+  bg.release();
+  if (!ctx->cstream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cstream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(ctx->cstream, hipStreamCaptureModeThreadLocal));
+  const kad_status st = fn(ctx->cstream);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cstream, &gr);
+  if (st != KAD_OK || e != hipSuccess || !gr) {
+    if (gr) (void)hipGraphDestroy(gr);
+    if (st != KAD_OK) return st;
+    return fail(KAD_EDEVICE, "recording a batch chain failed: %s", hipGetErrorString(e));
+  }
+  bg.graph = gr;
+  const hipError_t ei = hipGraphInstantiate(&bg.exec, gr, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    bg.release();
+    return fail(KAD_EDEVICE, "instantiating a batch chain failed: %s", hipGetErrorString(ei));
+  }
+  bg.key = key.v;
+  bg.records++;
+  return KAD_OK;
+}
+
+// The main-phase batch [first, first + count) of output set `set`, as launch_batch makes
+// it (slots from 0, the context's work counters), by replaying the set's recorded sampling
+// chain for batches of up to `cap` samples.  niv: the batch's check intervals (read by the
+// reduction chain's descriptor, written by replay_reduce).
+kad_status replay_sampling(kad_ctx *ctx, const kad_graph *g, int set, uint64_t seed,
+                           uint32_t phase, uint64_t first, uint32_t count, uint32_t cap,
+                           uint32_t stride, hipStream_t stream, int ovc, bool edges,
+                           const uint32_t *edge_ids) {
+  if (count == 0 || count > cap) return fail(KAD_EINVAL, "internal: batch of %u > %u", count, cap);
+  if (ctx->w_slots == 0) return fail(KAD_EINVAL, "internal: wide-count arena not allocated");
+  OutSet &o = ctx->outs[set];
+  HIP_TRY(ctx->h_bd.ensure(4));
+  HIP_TRY(ctx->d_bd.ensure(4));
+  const kad::GraphDev gd = dev_view(g);
+  const kad::LaunchShape shape = kad::graph_shape(g);
+  const uint32_t grid = kad::launch_grid(ctx, shape, cap, 0);
+  const kad::SlotState sv = kad::slot_view(ctx, 0);
+  kad::WideState wv = kad::wide_view(ctx);
+  wv.slots = std::min(wv.slots, sv.slots);
+  uint32_t *wk = ctx->work.p;  // sampler counter, fix-list length, fix counter
+  const kad::SampleOut so_list = o.view(stride, wk + 1), so = o.view(stride);
+  kad::BatchDesc *hb = ctx->h_bd.p + set, *db = ctx->d_bd.p + set;
+  Key key;
+  key << 1 << set << gd << sv << wv << so_list << shape.block << shape.small_exp << grid << cap
+      << stride << ovc << edges << edge_ids << o.epath.p << o.elen.p << o.h_flags.p << o.h_arcs.p
+      << o.h_nwide.p << wk << hb << db;
+  kad_status st = record_chain(ctx, ctx->bgraph[set], key, [&](hipStream_t s) -> kad_status {
+    HIP_TRY(kad::launch_copy_u64(reinterpret_cast<uint64_t *>(db),
+                                 reinterpret_cast<const uint64_t *>(hb),
+                                 sizeof(kad::BatchDesc) / 8, s));
+    HIP_TRY(kad::launch_zero_u32(wk, 3, s));
+    if (ovc == 2) {
+      HIP_TRY(kad::launch_wide_fix(gd, 0, 0, 0, nullptr, 0, sv, wv, cap, true, nullptr, nullptr,
+                                   wk + 2, so, s, db));
+    } else {
+      HIP_TRY(kad::launch_sampler(gd, sv, 0, 0, 0, cap, wk, so_list, grid, shape, s, db));
+      HIP_TRY(kad::launch_wide_fix(gd, 0, 0, 0, nullptr, 0, sv, wv, cap, false, o.fix_list.p,
+                                   wk + 1, wk + 2, so, s, db));
+      HIP_TRY(kad::launch_copy_u32(o.h_nwide.p, wk + 1, 1, s));
+    }
+    if (edges)
+      HIP_TRY(kad::launch_edge_paths(o.path.p, o.len.p, stride, cap, g->d_row, g->d_col,
+                                     edge_ids, o.epath.p, o.elen.p, stride + 1, s, db));
+    HIP_TRY(kad::launch_copy_u32(o.h_flags.p, o.flags.p, cap, s, db));
+    HIP_TRY(kad::launch_copy_u64(o.h_arcs.p, o.arcs.p, cap, s, db));
+    return KAD_OK;
+  });
+  if (st) return st;
+  // the set's previous replay read this descriptor before its mirrors landed, and the
+  // host has waited for those
+  *hb = kad::BatchDesc{seed, first, count, phase, 0u, 0u};
+  HIP_TRY(hipGraphLaunch(ctx->bgraph[set].exec, stream));
+  ctx->bgraph[set].replays++;
+  if (ovc == 2) o.h_nwide.p[0] = count;
+  HIP_TRY(hipEventRecord(o.sampled, stream));
+  HIP_TRY(hipEventRecord(o.copied, stream));
+  return KAD_OK;
+}
+
+// Every check interval of a batch of `count` samples of output set `set` reduced
+// (launch_hit_batch) by replaying the set's recorded reduction chain for batches of up to
+// `cap` samples; the snapshots land in snaps.
+kad_status replay_reduce(kad_ctx *ctx, int set, const uint32_t *rpath, const uint32_t *rlen,
+                         uint32_t rstride, uint32_t count, uint32_t cap, uint32_t per_iv,
+                         uint32_t n, uint32_t ngroups, uint64_t *snaps, hipStream_t rs) {
+  if (count == 0 || count > cap) return fail(KAD_EINVAL, "internal: batch of %u > %u", count, cap);
+  HIP_TRY(ctx->h_bd.ensure(4));
+  HIP_TRY(ctx->d_bd.ensure(4));
+  kad::BatchDesc *hb = ctx->h_bd.p + 2 + set, *db = ctx->d_bd.p + 2 + set;
+  Key key;
+  key << 2 << set << rpath << rlen << rstride << cap << per_iv << n << ngroups << ctx->count.p
+      << ctx->group.p << ctx->gmax.p << ctx->ivtmp.p << ctx->ivmax.p << snaps << hb << db;
+  kad_status st = record_chain(ctx, ctx->bgraph[2 + set], key, [&](hipStream_t s) -> kad_status {
+    HIP_TRY(kad::launch_copy_u64(reinterpret_cast<uint64_t *>(db),
+                                 reinterpret_cast<const uint64_t *>(hb),
+                                 sizeof(kad::BatchDesc) / 8, s));
+    HIP_TRY(kad::launch_hit_batch(rpath, rlen, rstride, cap, per_iv, n, ctx->count.p,
+                                  ctx->group.p, ctx->gmax.p, ngroups, ctx->ivtmp.p,
+                                  ctx->ivmax.p, snaps, s, db));
+    return KAD_OK;
+  });
+  if (st) return st;
+  // the previous replay of this chain is complete: the host waited for its snapshots
+  *hb = kad::BatchDesc{0, 0, count, 0u, (count + per_iv - 1) / per_iv, 0u};
+  HIP_TRY(hipGraphLaunch(ctx->bgraph[2 + set].exec, rs));
+  ctx->bgraph[2 + set].replays++;
+  return KAD_OK;
+}
+
 // Wait for an event by polling: a run waits on many short GPU steps, and a blocking
 // wait was seen to wake several hundred microseconds late.  After 2 ms of polling the
 // wait blocks.
@@ -730,6 +872,8 @@ kad_status kad_ctx_destroy(kad_ctx *ctx) {
   if (ctx->stream) (void)hipStreamDestroy(ctx->stream);
   if (ctx->rstream) (void)hipStreamDestroy(ctx->rstream);
   if (ctx->pstream) (void)hipStreamDestroy(ctx->pstream);
+  for (kad::BatchGraph &b : ctx->bgraph) b.release();
+  if (ctx->cstream) (void)hipStreamDestroy(ctx->cstream);
   delete ctx;
   return KAD_OK;
 }
@@ -1222,6 +1366,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   auto rpath = [&](const OutSet &o) -> const uint32_t * { return edges ? o.epath.p : o.path.p; };
   auto rlen = [&](const OutSet &o) -> const uint32_t * { return edges ? o.elen.p : o.len.p; };
   hipStream_t stream = pick_stream(ctx, hip_stream);
+  // main-phase batches as recorded chains (not while timing: its events sit between the
+  // launches), or the plain single-graph path
+  const bool graph_mode = ctx->exec == KAD_EXEC_GRAPH && !ctx->timing;
+  const bool plain = ctx->exec == KAD_EXEC_PLAIN;
+  const uint32_t plain_grid = kad::launch_grid(ctx, kad::graph_shape(g), UINT32_MAX);
   if ((st = run_timing_begin(ctx, stream))) return st;
   struct RunTimingEnd {  // also on early returns
     kad_ctx *c;
@@ -1329,7 +1478,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   const uint32_t first_nb = (uint32_t)std::min<uint64_t>(
       omega, std::min<uint64_t>(K, std::max<uint64_t>(B, (omega / 2 + B - 1) / B * B)));
   const uint32_t b1_slot0 = (uint32_t)std::max<uint64_t>(alpha, 64);
-  const bool overlap = hip_stream == nullptr && ovc != 2 && alpha <= ctx->outs[0].cap &&
+  const bool overlap = !plain && hip_stream == nullptr && ovc != 2 && alpha <= ctx->outs[0].cap &&
                        (uint64_t)ctx->slots >= (uint64_t)b1_slot0 + kad::launch_grid(
                                                    ctx, kad::graph_shape(g), first_nb);
   hipStream_t b1_stream = overlap ? ctx->pstream : stream;
@@ -1340,7 +1489,9 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       if ((st = finish_batch(ctx, 0, pilot_last, pilot_last))) return st;
       for (uint32_t k = 0; k < pilot_last; ++k) pilot_arcs += ctx->outs[0].h_arcs.p[k];
     }
-    const uint32_t nb = (uint32_t)std::min<uint64_t>(ctx->outs[0].cap, alpha - done);
+    // (the plain path: at most one resident grid, one sample per workgroup)
+    const uint32_t nb = (uint32_t)std::min<uint64_t>(
+        std::min<uint64_t>(ctx->outs[0].cap, plain ? plain_grid : UINT32_MAX), alpha - done);
     if ((st = launch_batch(ctx, g, p->seed, 0, done, nb, stride, 0, stream, ovc, 0, nullptr,
                            nullptr, edges, edge_ids)))
       return st;
@@ -1370,10 +1521,13 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
 
   // ---- otherwise the first main-phase batch follows the pilot on the stream and is
   // sampled while the host runs computeDelta
-  if (!overlap) {
+  if (!overlap && !plain) {
     HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[first_set].reduced, 0));
-    if ((st = launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream, ovc, 0,
-                           nullptr, nullptr, edges, edge_ids))) {
+    st = graph_mode ? replay_sampling(ctx, g, first_set, p->seed, 1, 0, first_nb, (uint32_t)K,
+                                      stride, stream, ovc, edges, edge_ids)
+                    : launch_batch(ctx, g, p->seed, 1, 0, first_nb, stride, first_set, stream,
+                                   ovc, 0, nullptr, nullptr, edges, edge_ids);
+    if (st) {
       (void)hipEventDestroy(pilot_done);
       return st;
     }
@@ -1444,7 +1598,7 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
     }
     HIP_TRY(hipMemsetAsync(ctx->gmax.p, 0, ngroups * 8, rs));
   }
-  PinBuf<uint64_t> snaps;  // one snapshot per check of the current batch
+  PinBuf<uint64_t> &snaps = ctx->snaps;  // one snapshot per check of the current batch
   HIP_TRY(snaps.ensure(snap * chunks_per_batch));
   // All-nodes runs reduce a batch's check intervals together (launch_hit_batch) when the
   // per-interval hit counters fit 256 MiB; its scratch is cleared here, beside the pilot.
@@ -1494,6 +1648,40 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   int cur = first_set;
   uint32_t cur_nb = first_nb;
   double worst = 0.0;
+  if (plain) {
+    // the plain path: every check interval sampled by launches of at most one resident
+    // grid (one sample per workgroup), reduced, copied and checked before the next
+    HIP_TRY(wait_stream(ctx, rs));  // counters, groups and maxima set up
+    const OutSet &o = ctx->outs[0];
+    while (!stop) {
+      const uint32_t cb = (uint32_t)std::min<uint64_t>(B, omega - tau);
+      for (uint32_t d = 0; d < cb;) {
+        const uint32_t nb = std::min(plain_grid, cb - d);
+        if ((st = launch_batch(ctx, g, p->seed, 1, tau + d, nb, stride, 0, stream, ovc, 0,
+                               nullptr, nullptr, edges, edge_ids)))
+          return st;
+        HIP_TRY(kad::launch_hit_reduce(rpath(o), rlen(o), rstride, nb, n, ctx->count.p, false,
+                                       by_group ? ctx->group.p : nullptr,
+                                       by_group ? ctx->gmax.p : nullptr, hit_scratch(ctx),
+                                       stream));
+        if ((st = finish_batch(ctx, 0, nb, nb))) return st;
+        for (uint32_t k = 0; k < nb; ++k) arcs += o.h_arcs.p[k];
+        d += nb;
+      }
+      HIP_TRY(hipMemcpyAsync(snaps.p, by_group ? ctx->gmax.p : ctx->count.p, snap * 8,
+                             hipMemcpyDeviceToHost, stream));
+      HIP_TRY(wait_stream(ctx, stream));
+      tau += cb;
+      if (tau >= omega) {
+        stop = true;
+      } else if (cb == B && (by_group ? checker.check_group_max(snaps.p, tau, &worst)
+                                      : checker.check(snaps.p, tau))) {
+        stop = true;
+        rule = true;
+      }
+    }
+    if ((st = enqueue_count_copy())) return st;
+  }
   while (!stop) {
     if (cur_nb == 0) return fail(KAD_EINVAL, "internal: empty batch before the stopping point");
     const OutSet &o = ctx->outs[cur];
@@ -1516,9 +1704,16 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       return KAD_OK;
     };
     if (batch_reduce) {  // every interval in three launches; all snapshots land together
-      HIP_TRY(kad::launch_hit_batch(rpath(o), rlen(o), rstride, cur_nb, (uint32_t)B, n,
-                                    ctx->count.p, ctx->group.p, ctx->gmax.p, (uint32_t)ngroups,
-                                    ctx->ivtmp.p, ctx->ivmax.p, snaps.p, rs));
+      if (graph_mode) {
+        if ((st = replay_reduce(ctx, cur, rpath(o), rlen(o), rstride, cur_nb, (uint32_t)K,
+                                (uint32_t)B, n, (uint32_t)ngroups, snaps.p, rs)))
+          return st;
+      } else {
+        HIP_TRY(kad::launch_hit_batch(rpath(o), rlen(o), rstride, cur_nb, (uint32_t)B, n,
+                                      ctx->count.p, ctx->group.p, ctx->gmax.p,
+                                      (uint32_t)ngroups, ctx->ivtmp.p, ctx->ivmax.p, snaps.p,
+                                      rs));
+      }
       for (uint32_t q = 0; q < nch; ++q) HIP_TRY(hipEventRecord(ctx->chunk_ev[q], rs));
       HIP_TRY(hipEventRecord(ctx->outs[cur].reduced, rs));
       queued = nch;
@@ -1537,8 +1732,11 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
       next_nb = (uint32_t)std::min<uint64_t>(round_up(want), omega - launched);
       const int nxt = 1 - cur;
       HIP_TRY(hipStreamWaitEvent(stream, ctx->outs[nxt].reduced, 0));
-      kad_status s2 = launch_batch(ctx, g, p->seed, 1, launched, next_nb, stride, nxt, stream, ovc,
-                                   0, nullptr, nullptr, edges, edge_ids);
+      kad_status s2 =
+          graph_mode ? replay_sampling(ctx, g, nxt, p->seed, 1, launched, next_nb, (uint32_t)K,
+                                       stride, stream, ovc, edges, edge_ids)
+                     : launch_batch(ctx, g, p->seed, 1, launched, next_nb, stride, nxt, stream,
+                                    ovc, 0, nullptr, nullptr, edges, edge_ids);
       if (s2) return s2;
       launched += next_nb;
       return KAD_OK;
@@ -1755,6 +1953,28 @@ kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable) {
   ctx->timing = enable != 0;
   ctx->t_launches = ctx->t_samples = ctx->t_arcs = ctx->t_nodes = ctx->t_hits = 0;
   ctx->t_seconds = 0.0;
+  return KAD_OK;
+}
+
+kad_status kad_ctx_set_exec(kad_ctx *ctx, uint32_t mode) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  if (mode > KAD_EXEC_PLAIN) return fail(KAD_EINVAL, "unknown launch mode %u", mode);
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
+  ctx->exec = mode;
+  return KAD_OK;
+}
+
+kad_status kad_ctx_get_exec(kad_ctx *ctx, uint32_t *mode, uint64_t *records, uint64_t *replays) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  if (mode) *mode = ctx->exec;
+  uint64_t rec = 0, rep = 0;
+  for (const kad::BatchGraph &b : ctx->bgraph) {
+    rec += b.records;
+    rep += b.replays;
+  }
+  if (records) *records = rec;
+  if (replays) *replays = rep;
   return KAD_OK;
 }
 
