@@ -57,19 +57,19 @@ WORKLOAD_TEXT = {"cl1m": "undirected Chung-Lu, beta 2.3, mean degree 20",
                  "er2000": "G(2000, 8/1999) seed 1, largest component",
                  "dcl4m": "directed Chung-Lu, out beta 2.5, in beta 2.1, mean degree 15",
                  "grid2000": "2000x2000 grid, 5% of edges deleted"}
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sampler_cl1m_traffic.json")
-
-
-def measured_traffic(workload):
-    """HBM bytes per sampler dispatch from the committed counter passes, if they were
-    taken on this workload with the current kernel source; else None."""
-    if workload != "cl1m" or not os.path.exists(TRAFFIC_FILE):
+def measured_traffic(workload, kernel="sampler_kernel"):
+    """Bytes per dispatch of `kernel` below the L2 (FETCH_SIZE + WRITE_SIZE, scaled by a
+    plain copy) from the committed counter passes, if they were taken on this workload with
+    the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles",
+                        f"{kernel.replace('_kernel', '')}_{workload}_traffic.json")
+    if not os.path.exists(path):
         return None
     from paper_1604_08553_amd.profiling import kernel_source_sha256
-    rec = json.load(open(TRAFFIC_FILE))
+    rec = json.load(open(path))
     if rec.get("kernel_source_sha256") != kernel_source_sha256():
         return None
-    return rec["hbm_bytes_per_dispatch"]
+    return rec.get("l2_egress_bytes_per_dispatch", rec.get("hbm_bytes_per_dispatch"))
 
 
 def algorithmic_bytes(arcs, nodes, hits):
@@ -410,6 +410,62 @@ def _gen_model(spec):
     return spec, g
 
 
+def bench_wide(args, torch, gg, kad):
+    """The wide-count kernel on the 2000x2000 grid with 5% of edges deleted, where every
+    sample needs path counts of hundreds to thousands of bits: hit counts of a fixed range
+    of main-phase ids, timed end to end, then the same call with event timing for the
+    kernel's own launch time and roofline."""
+    g = gg.workload("grid2000")
+    ctx = kad.Context(0)
+    G = kad.Graph(ctx, g)
+    N = args.wide_samples
+    t0 = time.perf_counter()
+    kad.hit_counts(ctx, G, args.seed, 1, 0, 64)  # slots, arenas, vertex diameter
+    print(f"[bench] warm-up 64 samples {time.perf_counter() - t0:.2f} s, layout "
+          f"{ctx.wide_info()}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        counts, arcs = kad.hit_counts(ctx, G, args.seed, 1, 1000, N)
+    torch.cuda.synchronize()
+    step_s = (time.perf_counter() - t0) / args.steps
+    ctx.set_timing(True)
+    kad.hit_counts(ctx, G, args.seed, 1, 1000, N)
+    tm = ctx.timing()
+    ctx.set_timing(False)
+    alg = algorithmic_bytes(tm["arcs"], tm["nodes"], tm["hits"])
+    avg_launch_s = tm["seconds"] / max(tm["launches"], 1)
+    achieved = alg / max(tm["launches"], 1) / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    hbm = measured_traffic("grid2000", "wide_kernel")
+    traffic = hbm / avg_launch_s / 1e9 if hbm and avg_launch_s > 0 else None
+    out = {
+        "metric": "sampled shortest paths/sec",
+        "value": N / step_s,
+        "unit": "paths/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": 1,
+        "ms_per_step": step_s * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "multi-limb u64", "data": "synthetic",
+        "config": {"workload": f"{WORKLOAD_TEXT['grid2000']}: n={g.n}, {g.arcs} arcs; hit counts "
+                               f"of main-phase ids 1000..{1000 + N - 1}, seed {args.seed}"},
+        "wide_layout": ctx.wide_info(),
+        "gteps": arcs / step_s / 1e9,
+        "per_sample": {"arcs": tm["arcs"] / max(tm["samples"], 1),
+                       "nodes": tm["nodes"] / max(tm["samples"], 1)},
+        "sampler": {"note": "one further call with event timing", "launches": tm["launches"],
+                    "samples": tm["samples"], "avg_launch_ms": avg_launch_s * 1e3},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "wide_kernel",
+                     "alg_bytes_per_launch": alg / max(tm["launches"], 1),
+                     "l2_egress_bytes_per_launch": hbm,
+                     "note": "algorithmic bytes by the sampler's per-arc and per-node figures; "
+                             "the multi-limb counts add to them"},
+    }
+    G.close()
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
 def bench_exponent(args, torch, gg, kad):
     """Theorem 2 and Fig. 2: arcs visited per sampled path, balanced bidirectional search
     against the forward BFS from s, on the appendix's random-graph models as n grows."""
@@ -486,6 +542,8 @@ def main():
     ap.add_argument("--k", type=int, default=50, help="top-k: k")
     ap.add_argument("--autotune", action="store_true",
                     help="autotune the sampler launch shape before timing (always for dcl4m)")
+    ap.add_argument("--launch", default=None, metavar="BLOCK,SMALL",
+                    help="sampler launch shape to use instead of the autotuner's")
     ap.add_argument("--delta", type=float, default=0.1)
     ap.add_argument("--seed", type=int, default=1)
     ap.add_argument("--kernel-batch", type=int, default=65536)
@@ -513,16 +571,18 @@ def main():
     ap.add_argument("--sizes", default="1e4,3e4,1e5,3e5,1e6", help="exponent: node counts")
     ap.add_argument("--mean-degree", type=float, default=10.0, help="exponent: mean degree")
     ap.add_argument("--exp-samples", type=int, default=1024, help="exponent: samples per graph")
+    ap.add_argument("--wide-samples", type=int, default=1000,
+                    help="grid2000: samples per call of the wide-count kernel")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM counters)")
     args = ap.parse_args()
     if args.steps is None:
-        args.steps = 3 if args.workload == "dcl4m" else 10
+        args.steps = {"dcl4m": 3, "grid2000": 2}.get(args.workload, 10)
     if args.epsilon is None:
         args.epsilon = {"er2000": 0.01, "dcl4m": 0.0002}.get(args.workload, 0.005)
     if args.mode is None:
         args.mode = "topk" if args.workload == "dcl4m" else "all"
-    if args.workload == "dcl4m":
+    if args.workload == "dcl4m" and not args.launch:
         args.autotune = True
     if args.cpu_full_run is None:
         args.cpu_full_run = args.workload in ("cl1m", "er2000")
@@ -553,6 +613,8 @@ def main():
         return bench_serve(args, torch, gg, kad)
     if args.workload == "exponent":
         return bench_exponent(args, torch, gg, kad)
+    if args.workload == "grid2000":
+        return bench_wide(args, torch, gg, kad)
     t0 = time.perf_counter()
     csr = gg.workload(args.workload)
     gen_s = time.perf_counter() - t0
@@ -563,7 +625,11 @@ def main():
     ctx_create_s = time.perf_counter() - t0
     G = kad.Graph(ctx, csr)
     tuned = None
-    if args.autotune:
+    if args.launch:
+        block, small = (int(x) for x in args.launch.split(","))
+        G.set_launch(block, small)
+        tuned = {"block": block, "small_expansion": small, "seconds": None}
+    elif args.autotune:
         tuned = G.autotune(args.kernel_batch)
         print(f"[bench] autotune: {tuned}", file=sys.stderr, flush=True)
     kw = dict(epsilon=args.epsilon, delta=args.delta, seed=args.seed,
@@ -656,7 +722,7 @@ def main():
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel": "sampler_kernel",
                      "alg_bytes_per_launch": per_launch_bytes,
-                     "hbm_bytes_per_launch": hbm},
+                     "l2_egress_bytes_per_launch": hbm},
     }
     if not args.no_modes:
         out["exec_modes"] = time_modes(ctx, G, kw, runs[0], torch, kad)

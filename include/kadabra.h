@@ -406,6 +406,22 @@ kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable);
 kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *samples,
                               double *seconds, uint64_t *arcs, uint64_t *nodes, uint64_t *hits);
 
+/* Wide-count working memory, used by graphs whose path counts can pass 128 bits: the
+ * number of first-pass slots (workgroups sampling at once) and each one's arena in 64-bit
+ * limbs (0 = the library's choice: at most the sampler slots, three per compute unit, and
+ * as many as 80% of the memory left after the sampler slots allows, each with room for any
+ * sample of the graph when that bound is at most 2^25 limbs, else 2^25 limbs or more).
+ * Samples that outgrow a first-pass arena are sampled again, after the pass, by a second
+ * pass with fewer and larger arenas (the graph's bound, at most 2^27 limbs, or all of the
+ * first pass's memory) carved from the same memory; a sample that outgrows that too fails
+ * the call with KAD_EOVERFLOW.  Results never depend on this layout.  Frees the current
+ * arenas (laid out again on next use); KAD_EINVAL for 0 < limbs < 4096. */
+kad_status kad_ctx_set_wide(kad_ctx *ctx, uint32_t slots, uint64_t limbs);
+/* The current layout: first-pass slots and limbs per slot, second-pass slots and limbs per
+ * slot (0 when no arena is allocated, or when there is one pass).  Any pointer may be NULL. */
+kad_status kad_ctx_get_wide(kad_ctx *ctx, uint32_t *slots, uint64_t *limbs, uint32_t *slots2,
+                            uint64_t *limbs2);
+
 /* kad_run's launch mode (KAD_EXEC_*; default KAD_EXEC_GRAPH).  While timing is enabled
  * KAD_EXEC_GRAPH launches call by call (the per-launch events sit inside the chain).
  * The recorded chains are kept in the context and recorded again when the graph, the

@@ -124,6 +124,8 @@ def lib():
         "kad_ctx_set_timing": ([vp, i32], st),
         "kad_ctx_get_timing": ([vp, vp, vp, vp, vp, vp, vp], st),
         "kad_ctx_set_exec": ([vp, u32], st),
+        "kad_ctx_set_wide": ([vp, u32, u64], st),
+        "kad_ctx_get_wide": ([vp, vp, vp, vp, vp], st),
         "kad_ctx_get_exec": ([vp, vp, vp, vp], st),
         "kad_last_error": ([], C.c_char_p),
     }
@@ -196,6 +198,17 @@ class Context:
         """How kad_run launches: "graph" (recorded batch chains, the default), "stream"
         (call by call) or "plain" (the plain single-graph path); see kad_ctx_set_exec."""
         _check(lib().kad_ctx_set_exec(self.handle, EXECS[mode]))
+
+    def set_wide(self, slots: int = 0, limbs: int = 0):
+        """First-pass wide-count slots and arena limbs (0 = library choice); see
+        kad_ctx_set_wide."""
+        _check(lib().kad_ctx_set_wide(self.handle, slots, limbs))
+
+    def wide_info(self) -> dict:
+        a, c = C.c_uint32(), C.c_uint32()
+        b, d = C.c_uint64(), C.c_uint64()
+        _check(lib().kad_ctx_get_wide(self.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
+        return {"slots": a.value, "limbs": b.value, "slots2": c.value, "limbs2": d.value}
 
     def exec_info(self) -> dict:
         m, rec, rep = C.c_uint32(), C.c_uint64(), C.c_uint64()

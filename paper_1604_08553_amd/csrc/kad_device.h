@@ -124,9 +124,10 @@ hipError_t launch_sampler_multi(const SampleSeg *segs, uint32_t nseg, const Slot
 // arena, the samples of the launch listed in list[0, *list_count) -- the sampler's fix
 // list -- or, with `all` (list == nullptr), every sample of the launch (no sampler launch
 // before it).  The results are those of exact arithmetic; FLAG_CAPACITY remains only if
-// the arena or the level tables are too small, or the path outgrows the stride.  work:
-// a counter, zero at launch.  segs == nullptr: the single-graph launch (g, seed, phase,
-// first).  With an empty list the kernel's workgroups exit at once.
+// the arena or the level tables are too small, or the path outgrows the stride; with
+// out.fix_list set, such samples are also appended to it (for a launch with larger
+// arenas).  work: a counter, zero at launch.  segs == nullptr: the single-graph launch
+// (g, seed, phase, first).  With an empty list the kernel's workgroups exit at once.
 hipError_t launch_wide_fix(const GraphDev &g, uint64_t seed, uint32_t phase, uint64_t first,
                            const SampleSeg *segs, uint32_t nseg, const SlotState &st,
                            const WideState &ws, uint32_t count, bool all,

@@ -122,6 +122,7 @@ struct Piece {
 struct Tick {
   OutSet out;
   DevBuf<uint32_t> wlist;  // samples left by the sampler to the wide-count kernel
+  DevBuf<uint32_t> wlist2; // samples left by the first wide pass to the second
   DevBuf<SampleSeg> d_segs;
   PinBuf<SampleSeg> h_segs;
   DevBuf<GatherDesc> d_gat;
@@ -216,6 +217,8 @@ class Engine {
   void layout();
   SlotState lane_slots(const Lane &L, bool wide) const;
   WideState lane_wide(const Lane &L) const;
+  // the second wide pass's view of the lane's arena (slots 0 when the arena is small)
+  WideState lane_wide2(const Lane &L) const;
   static bool tick_complete(const Tick &t);
   // Double a buffer's capacity (at least to n) without freeing: the old storage is
   // released by release_graveyard() once no lane runs.
@@ -283,7 +286,7 @@ kad_status Engine::init() {
     HIP_TRY(hipMemsetAsync(L.bin_count.p, 0, POOL_TILES * 4, ctx_->rstream));
     HIP_TRY(hipMemsetAsync(L.tile_fill.p, 0, POOL_TILES * 4, ctx_->rstream));
     for (Tick &t : L.ticks) {
-      HIP_TRY(t.work.ensure(3));  // sampler counter, fix-list length, fix counter
+      HIP_TRY(t.work.ensure(WORK_WORDS));
       HIP_TRY(hipEventCreateWithFlags(&t.sampled, hipEventDisableTiming));
     }
   }
@@ -334,6 +337,19 @@ WideState Engine::lane_wide(const Lane &L) const {
   w.lv += (size_t)L.wslot0 * 2 * w.max_lev * 4;
   w.lbase += (size_t)L.wslot0 * 2 * w.max_lev;
   w.slots = L.nwslots;
+  return w;
+}
+
+WideState Engine::lane_wide2(const Lane &L) const {
+  WideState w = lane_wide(L);
+  if (ctx_->w_slots2 == 0 || L.nwslots == 0) {
+    w.slots = 0;
+    return w;
+  }
+  const uint64_t total = (uint64_t)L.nwslots * w.arena_limbs;
+  const uint64_t n2 = std::max<uint64_t>(1, total / ctx_->w_arena_limbs2);
+  w.slots = (uint32_t)n2;
+  w.arena_limbs = total / n2;
   return w;
 }
 
@@ -572,6 +588,7 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   HIP_TRY(t.d_gat.ensure(MAX_PIECES));
   HIP_TRY(t.h_gat.ensure(MAX_PIECES));
   HIP_TRY(t.wlist.ensure(TICK_SAMPLES));
+  HIP_TRY(t.wlist2.ensure(TICK_SAMPLES));
   if (L.bins.n == 0) {
     HIP_TRY(L.bins.ensure(TICK_PATH_BYTES / 4));
     L.bins_cap = TICK_PATH_BYTES / 4;
@@ -652,7 +669,7 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   static_assert(sizeof(SampleSeg) % 8 == 0 && sizeof(GatherDesc) % 8 == 0, "copied as words");
   HIP_TRY(launch_copy_u64((uint64_t *)t.d_segs.p, (const uint64_t *)t.h_segs.p,
                           (uint64_t)np * sizeof(SampleSeg) / 8, s));
-  HIP_TRY(launch_zero_u32(t.work.p, 3, s));
+  HIP_TRY(launch_zero_u32(t.work.p, WORK_WORDS, s));
   // launch shape of the graph with the most samples in this launch
   const kad_graph *major = nullptr;
   {
@@ -684,9 +701,21 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   // every sample of lane 1; in lane 0 the samples its sampler left (counts past 128 bits,
   // wide_only segments, more candidate edges than a slot holds)
   if (L.nwslots == 0) return fail(KAD_ENOMEM, "no wide-count slots for this launch");
+  // (with large arenas in two passes: the samples the lane's first pass cannot hold are
+  // sampled again by fewer slots with larger arenas in the lane's same memory)
+  const WideState w2 = lane_wide2(L);
+  SampleOut o1 = t.out.view(t.stride);
+  if (w2.slots) {
+    o1.fix_list = t.wlist2.p;
+    o1.fix_count = t.work.p + 3;
+  }
   HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, np, lane_slots(L, true),
                           lane_wide(L), t.total, wide_lane, t.wlist.p, t.work.p + 1,
-                          t.work.p + 2, t.out.view(t.stride), s));
+                          t.work.p + 2, o1, s));
+  if (w2.slots)
+    HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, np, lane_slots(L, true), w2,
+                            t.total, false, t.wlist2.p, t.work.p + 3, t.work.p + 4,
+                            t.out.view(t.stride), s));
   if (wide_lane)
     t.out.h_nwide.p[0] = t.total;
   else

@@ -73,11 +73,21 @@ struct PinBuf {
 
 constexpr uint32_t PI_CAP = 65536;  // candidate edges per slot (power of two)
 constexpr uint32_t DEFAULT_BATCH = 65536;
+// Counters of one sampler launch: [0] the sampler's sample counter, [1] its fix-list
+// length, then the wide-count passes' ([2] the first pass's counter, [3] the length of
+// its list for the second pass, [4] the second pass's counter).
+constexpr uint32_t WORK_WORDS = 5;
+// Wide-count arenas (limbs of 64 bits per slot) of graphs whose counts pass 128 bits: the
+// first pass's size when a sample may need more (256 MiB), and the second pass's (1 GiB)
+// unless the graph's worst case is smaller.
+constexpr uint64_t WIDE_TIER1_LIMBS = 1ull << 25;
+constexpr uint64_t WIDE_MAX_LIMBS = 1ull << 27;
 
 // Device outputs of one sampler launch, with pinned host mirrors of the small ones.
 struct OutSet {
   DevBuf<uint32_t> s, t, len, flags, nodes, path;
   DevBuf<uint32_t> fix_list;  // samples the sampler leaves to the wide-count kernel
+  DevBuf<uint32_t> fix_list2; // samples the first wide pass leaves to the second
   DevBuf<uint32_t> epath, elen;  // edge betweenness: paths as edge ids (estride apart)
   uint32_t estride = 0;
   DevBuf<uint64_t> arcs;
@@ -151,17 +161,20 @@ struct kad_ctx {
   // wide-count resampling (kad::WideState): samples whose counts pass 128 bits or whose
   // candidate edges outgrow a slot.  w_big: the arena sized for wide counts (graphs whose
   // counts can pass 128 bits), else for the candidate edges of 128-bit graphs only.
-  uint32_t w_slots = 0, w_max_lev = 0;
+  // Large arenas come in two passes over the same memory: w_slots slots of w_arena_limbs,
+  // then, for the samples that outgrow those, w_slots2 slots of w_arena_limbs2 (0: none).
+  uint32_t w_slots = 0, w_max_lev = 0, w_slots2 = 0;
   bool w_big = false;
   uint64_t run_wide = 0;  // samples resampled wide during the current kad_run
-  uint64_t w_arena_limbs = 0;
+  uint64_t w_arena_limbs = 0, w_arena_limbs2 = 0;
+  uint32_t w_user_slots = 0;  // kad_ctx_set_wide (0: the library's choice)
+  uint64_t w_user_limbs = 0;
   kad::DevBuf<uint64_t> w_arena, w_lbase;
   kad::DevBuf<uint32_t> w_lv;
   // per-launch outputs, double-buffered so the next batch can be sampled while the
   // host checks the current one
   kad::OutSet outs[2];
-  // work counters of a launch: [0] the sampler's, [1] its fix-list length, [2] the wide
-  // fix's; work2: the same for pstream launches
+  // counters of a launch (WORK_WORDS); work2: the same for pstream launches
   kad::DevBuf<uint32_t> work, work2, group;
   kad::DevBuf<uint64_t> count, gmax;
   hipEvent_t ev_s = nullptr, ev_rs = nullptr, ev_ps = nullptr;  // wait_stream's markers
@@ -270,6 +283,8 @@ kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact);
 kad_status ensure_slots(kad_ctx *ctx, uint32_t n);
 SlotState slot_view(const kad_ctx *ctx, uint32_t slot0 = 0);
 WideState wide_view(const kad_ctx *ctx);
+// The second wide pass's view of the same arena (slots 0 when there is none).
+WideState wide_view2(const kad_ctx *ctx);
 // Wide path counts: 0 = a graph whose path counts always fit 128 bits (VD and the
 // largest degree bound them), 1 = overflowed samples are resampled wide, 2 = a
 // high-diameter graph whose samples all go to the wide kernel.  vd_from_library:
@@ -283,12 +298,14 @@ kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc);
 bool wide_fits(const kad_ctx *ctx, const kad_graph *g, int ovc);
 // Launch the wide-count resampling of a launch of `count` samples whose outputs are
 // `out`: the samples of its fix list (list, *list_count), or with `all` every sample (no
-// sampler launch before); work: zero at launch.  segs == nullptr: single graph g.
+// sampler launch before); work: 3 counters, zero at launch.  With large arenas in two
+// passes, list2 (room for count entries) carries the samples the first pass leaves to the
+// second.  segs == nullptr: single graph g.  bd: as in launch_wide_fix.
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
                        bool all, const uint32_t *list, const uint32_t *list_count,
-                       uint32_t *work, const SampleOut &out, hipStream_t stream,
-                       uint32_t slot0 = 0);
+                       uint32_t *work, uint32_t *list2, const SampleOut &out,
+                       hipStream_t stream, uint32_t slot0 = 0, const BatchDesc *bd = nullptr);
 // The graph's launch shape (set or tuned, else a default by size), and the grid of a
 // launch of `count` samples with it.
 LaunchShape graph_shape(const kad_graph *g);

@@ -2319,6 +2319,10 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       out.arcs[k] = L.arcs;
       out.flags[k] = L.flags;
       out.nodes[k] = needed;
+      // a sample that outgrew this launch's arena is sampled again by a launch with
+      // larger arenas (when the caller keeps a list)
+      if ((L.flags & FLAG_CAPACITY) && out.fix_list)
+        out.fix_list[atomicAdd(out.fix_count, 1u)] = k;
     }
     // ---- restore the slot's all-zero state
     const uint32_t nv = L.nvis;

@@ -39,7 +39,7 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
   if (cap < want_cap || stride < want_stride) {
     const uint32_t c = std::max(want_cap, cap);
     const uint32_t st = std::max(want_stride, stride);
-    for (auto *b : {&s, &t, &len, &flags, &nodes, &path, &fix_list}) b->release();
+    for (auto *b : {&s, &t, &len, &flags, &nodes, &path, &fix_list, &fix_list2}) b->release();
     arcs.release();
     HIP_TRY(s.ensure(c));
     HIP_TRY(t.ensure(c));
@@ -47,6 +47,7 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
     HIP_TRY(flags.ensure(c));
     HIP_TRY(nodes.ensure(c));
     HIP_TRY(fix_list.ensure(c));
+    HIP_TRY(fix_list2.ensure(c));
     HIP_TRY(arcs.ensure(c));
     HIP_TRY(path.ensure((size_t)c * st));
     HIP_TRY(h_flags.ensure(c));
@@ -70,7 +71,7 @@ kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t r
 
 kad_status OutSet::ensure_entries(uint32_t want_cap, uint64_t path_entries, hipStream_t rs) {
   if (cap < want_cap || path.n < path_entries) {
-    for (auto *b : {&s, &t, &len, &flags, &nodes, &path, &fix_list}) b->release();
+    for (auto *b : {&s, &t, &len, &flags, &nodes, &path, &fix_list, &fix_list2}) b->release();
     arcs.release();
     HIP_TRY(s.ensure(want_cap));
     HIP_TRY(t.ensure(want_cap));
@@ -78,6 +79,7 @@ kad_status OutSet::ensure_entries(uint32_t want_cap, uint64_t path_entries, hipS
     HIP_TRY(flags.ensure(want_cap));
     HIP_TRY(nodes.ensure(want_cap));
     HIP_TRY(fix_list.ensure(want_cap));
+    HIP_TRY(fix_list2.ensure(want_cap));
     HIP_TRY(arcs.ensure(want_cap));
     HIP_TRY(path.ensure(path_entries));
     HIP_TRY(h_flags.ensure(want_cap));
@@ -154,6 +156,12 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   ctx->pi.release();
   ctx->slots = 0;
   ctx->slot_n = 0;
+  // the wide-count arena is laid out after the slots, from what they leave
+  ctx->w_arena.release();
+  ctx->w_lv.release();
+  ctx->w_lbase.release();
+  ctx->w_slots = ctx->w_slots2 = 0;
+  ctx->w_arena_limbs = ctx->w_arena_limbs2 = 0;
   const uint32_t want_slots =
       ctx->cus * (uint32_t)*std::max_element(ctx->blocks_per_cu, ctx->blocks_per_cu + 3);
   const uint64_t per_slot = (uint64_t)n * (4ull * REC_WORDS + 4) + (uint64_t)PI_CAP * 8;
@@ -177,17 +185,33 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   return KAD_OK;
 }
 
-// Limbs of one wide slot's arena for graph g: with counts that may pass 128 bits, as much
-// as the budget allows (up to 1 GiB); otherwise the counts of every node at three limbs,
-// every arc as a candidate-edge key, and the selection's scratch.
+// Limbs of one wide slot's arena for graph g: with counts that may pass 128 bits, at
+// least 2^20; otherwise the counts of every node at three limbs, every arc as a candidate
+// edge, and the selection's scratch.
 static uint64_t wide_limbs_needed(const kad_graph *g, int ovc) {
-  if (ovc != 0) return 1ull << 20;  // at least; the large arena takes what the budget gives
+  if (ovc != 0) return 1ull << 20;
   return std::min<uint64_t>(1ull << 27, 3ull * g->n + g->arcs + (1ull << 18));
 }
 
+// An arena that holds any sample of g: every node's count at the widest count's limbs
+// (a count is below maxdeg^(VD-1)) plus two, every arc as a candidate edge with the
+// product of two counts, and the selection's scratch (capped at 2^40).
+static uint64_t wide_limbs_worst(const kad_graph *g) {
+  const double vd = g->vd_known ? (double)g->vd : (double)g->n;
+  const double bits = std::max(vd - 1.0, 1.0) * std::log2(std::max<double>(g->maxdeg, 2.0));
+  const double L = std::ceil(bits / 64.0);
+  const double w = (double)g->n * (L + 2.0) + (double)g->arcs * (2.0 * L + 2.0) + 262144.0;
+  return (uint64_t)std::min(w, 1099511627776.0);
+}
+
 bool wide_fits(const kad_ctx *ctx, const kad_graph *g, int ovc) {
-  return ctx->w_slots > 0 && (ovc == 0 || ctx->w_big) &&
-         ctx->w_arena_limbs >= wide_limbs_needed(g, ovc);
+  if (ctx->w_slots == 0) return false;
+  if (ovc == 0) return ctx->w_arena_limbs >= wide_limbs_needed(g, 0);
+  if (!ctx->w_big) return false;
+  if (ctx->w_user_limbs) return true;  // the caller's layout (kad_ctx_set_wide)
+  const uint64_t worst = wide_limbs_worst(g);
+  return ctx->w_arena_limbs >= worst ||
+         (ctx->w_slots2 > 0 && ctx->w_arena_limbs2 >= std::min(worst, WIDE_MAX_LIMBS));
 }
 
 kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc) {
@@ -199,28 +223,59 @@ kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc) {
   ctx->w_arena.release();
   ctx->w_lv.release();
   ctx->w_lbase.release();
-  ctx->w_slots = 0;
-  ctx->w_arena_limbs = 0;
-  // the large arena: up to 64 workgroups, each with up to 1 GiB, in at most half of what
-  // the budget leaves after the graphs and the sampler slots; the small one: 16 workgroups
+  ctx->w_slots = ctx->w_slots2 = 0;
+  ctx->w_arena_limbs = ctx->w_arena_limbs2 = 0;
   const uint64_t left = ctx->budget > ctx->used_graphs + ctx->slot_bytes + (1024ull << 20)
                             ? ctx->budget - ctx->used_graphs - ctx->slot_bytes - (1024ull << 20)
                             : 0;
-  const uint32_t w_slots = std::min<uint32_t>(big ? 64 : 16, ctx->slots);
   const uint32_t max_lev = 16384;
-  const uint64_t tables = (uint64_t)w_slots * 2 * max_lev * (16 + 8);
-  uint64_t limbs = left / 2 > tables ? (left / 2 - tables) / (8ull * std::max(w_slots, 1u)) : 0;
-  limbs = std::min<uint64_t>(limbs, 1ull << 27);
-  if (!big) limbs = std::min(limbs, want);
-  if (w_slots == 0 || limbs < want)
-    return fail(KAD_ENOMEM, "no HBM left for the wide-count arena (%llu limbs per slot needed)",
-                (unsigned long long)want);
+  const uint64_t tables = 2ull * max_lev * (16 + 8);  // one slot's level tables
+  uint32_t w_slots = 0, w_slots2 = 0;
+  uint64_t limbs = 0, limbs2 = 0;
+  if (!big) {
+    // 128-bit graphs (candidate edges past a slot only): 16 slots, each with room for every
+    // node's count at three limbs and every arc as a candidate edge
+    w_slots = std::min<uint32_t>(16, ctx->slots);
+    limbs = want;
+    if (w_slots == 0 || left / 2 < (uint64_t)w_slots * (limbs * 8 + tables))
+      return fail(KAD_ENOMEM, "no HBM left for the wide-count arena (%llu limbs per slot needed)",
+                  (unsigned long long)want);
+  } else {
+    // Counts past 128 bits: at most as many slots as the sampler slots, as can be resident
+    // (three per CU) and as 80% of the memory left allows, each with an arena that holds
+    // any sample of the graph when that is at most WIDE_TIER1_LIMBS (or kad_ctx_set_wide's
+    // size), else of that size, grown to what the memory gives.  Samples that outgrow it
+    // are sampled again by a second pass: fewer slots with arenas of the worst case (at
+    // most WIDE_MAX_LIMBS, at least the whole first-pass memory) carved from the same memory.
+    const uint64_t A = left / 10 * 8;
+    const uint64_t worst = std::max(wide_limbs_worst(g), ovc == 0 ? want : (uint64_t)0);
+    const uint64_t target = ctx->w_user_limbs ? ctx->w_user_limbs : WIDE_TIER1_LIMBS;
+    const uint64_t lim1 = std::min(worst, target);
+    uint32_t most = std::min<uint32_t>(ctx->slots, 3 * ctx->cus);
+    if (ctx->w_user_slots) most = std::min(most, ctx->w_user_slots);
+    w_slots = (uint32_t)std::min<uint64_t>(most, A / (lim1 * 8 + tables));
+    if (w_slots == 0)
+      return fail(KAD_ENOMEM, "no HBM left for the wide-count arena (%llu limbs per slot needed)",
+                  (unsigned long long)lim1);
+    limbs = ctx->w_user_limbs
+                ? lim1
+                : std::min(worst, std::max(lim1, std::min<uint64_t>(
+                                                     WIDE_MAX_LIMBS,
+                                                     (A - (uint64_t)w_slots * tables) / 8 / w_slots)));
+    if (limbs < worst) {
+      const uint64_t total = (uint64_t)w_slots * limbs;
+      w_slots2 = (uint32_t)std::max<uint64_t>(1, total / std::min(worst, WIDE_MAX_LIMBS));
+      limbs2 = total / w_slots2;
+    }
+  }
   HIP_TRY(ctx->w_arena.ensure((size_t)w_slots * limbs));
   HIP_TRY(ctx->w_lv.ensure((size_t)w_slots * 2 * max_lev * 4));
   HIP_TRY(ctx->w_lbase.ensure((size_t)w_slots * 2 * max_lev));
   ctx->w_slots = w_slots;
+  ctx->w_slots2 = w_slots2;
   ctx->w_max_lev = max_lev;
   ctx->w_arena_limbs = limbs;
+  ctx->w_arena_limbs2 = limbs2;
   ctx->w_big = big;
   return KAD_OK;
 }
@@ -246,18 +301,37 @@ WideState wide_view(const kad_ctx *ctx) {
   return w;
 }
 
+WideState wide_view2(const kad_ctx *ctx) {
+  WideState w = wide_view(ctx);
+  w.slots = std::min(ctx->w_slots2, w.slots);
+  w.arena_limbs = ctx->w_arena_limbs2;
+  return w;
+}
+
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
                        bool all, const uint32_t *list, const uint32_t *list_count,
-                       uint32_t *work, const SampleOut &out, hipStream_t stream,
-                       uint32_t slot0) {
+                       uint32_t *work, uint32_t *list2, const SampleOut &out,
+                       hipStream_t stream, uint32_t slot0, const BatchDesc *bd) {
   if (count == 0) return KAD_OK;
   if (ctx->w_slots == 0) return fail(KAD_EINVAL, "internal: wide-count arena not allocated");
   const SlotState sv = slot_view(ctx, slot0);
   WideState wv = wide_view(ctx);
   wv.slots = std::min(wv.slots, sv.slots);  // the wide slots reuse these sampler slots
+  const bool two = ctx->w_slots2 > 0 && list2;
+  SampleOut o1 = out, o2 = out;  // the first pass lists the samples its arenas cannot hold
+  o1.fix_list = two ? list2 : nullptr;
+  o1.fix_count = two ? work + 1 : nullptr;
+  o2.fix_list = nullptr;
+  o2.fix_count = nullptr;
   HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, sv, wv, count, all, list,
-                          list_count, work, out, stream));
+                          list_count, work, o1, stream, bd));
+  if (two) {
+    WideState w2 = wide_view2(ctx);
+    w2.slots = std::min(w2.slots, sv.slots);
+    HIP_TRY(launch_wide_fix(g, seed, phase, first, segs, nseg, sv, w2, count, false, list2,
+                            work + 1, work + 2, o2, stream, bd));
+  }
   return KAD_OK;
 }
 
@@ -493,8 +567,8 @@ kad_status ensure_capacity(kad_ctx *ctx, const kad_graph *g, int ovc, uint32_t b
     if ((st = o.ensure(batch, stride, ctx->rstream))) return st;
     if (edges && (st = o.ensure_edges(o.cap, o.stride + 1))) return st;
   }
-  HIP_TRY(ctx->work.ensure(3));
-  HIP_TRY(ctx->work2.ensure(3));
+  HIP_TRY(ctx->work.ensure(kad::WORK_WORDS));
+  HIP_TRY(ctx->work2.ensure(kad::WORK_WORDS));
   HIP_TRY(ctx->count.ensure(items));
   HIP_TRY(ctx->h_count.ensure(items));
   // hit-reduction bins: room in every tile for all the hits of one reduction call
@@ -552,13 +626,13 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
                         const uint32_t *edge_ids = nullptr) {
   OutSet &o = ctx->outs[set];
   kad_status st = KAD_OK;
-  uint32_t *wk = work ? work : ctx->work.p;  // sampler counter, fix-list length, fix counter
+  uint32_t *wk = work ? work : ctx->work.p;  // the launch's counters (kad::WORK_WORDS)
   HIP_TRY(hipEventRecord(o.k0, stream));
-  HIP_TRY(kad::launch_zero_u32(wk, 3, stream));
+  HIP_TRY(kad::launch_zero_u32(wk, kad::WORK_WORDS, stream));
   if (ovc == 2) {
     if (wide_after) HIP_TRY(hipStreamWaitEvent(stream, wide_after, 0));
     st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, true, nullptr,
-                          nullptr, wk + 2, o.view(stride), stream, slot0);
+                          nullptr, wk + 2, o.fix_list2.p, o.view(stride), stream, slot0);
     if (st) return st;
     HIP_TRY(hipEventRecord(o.k1, stream));
     o.h_nwide.p[0] = count;
@@ -572,7 +646,8 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
     // holds) are sampled again by the wide-count kernel; an empty list costs one short launch
     if (wide_after) HIP_TRY(hipStreamWaitEvent(stream, wide_after, 0));
     st = kad::launch_wide(ctx, dev_view(g), seed, phase, first, nullptr, 0, count, false,
-                          o.fix_list.p, wk + 1, wk + 2, o.view(stride), stream, slot0);
+                          o.fix_list.p, wk + 1, wk + 2, o.fix_list2.p, o.view(stride), stream,
+                          slot0);
     if (st) return st;
     HIP_TRY(hipMemcpyAsync(o.h_nwide.p, wk + 1, 4, hipMemcpyDeviceToHost, stream));
   }
@@ -661,27 +736,29 @@ kad_status replay_sampling(kad_ctx *ctx, const kad_graph *g, int set, uint64_t s
   const kad::LaunchShape shape = kad::graph_shape(g);
   const uint32_t grid = kad::launch_grid(ctx, shape, cap, 0);
   const kad::SlotState sv = kad::slot_view(ctx, 0);
-  kad::WideState wv = kad::wide_view(ctx);
-  wv.slots = std::min(wv.slots, sv.slots);
-  uint32_t *wk = ctx->work.p;  // sampler counter, fix-list length, fix counter
+  const kad::WideState wv = kad::wide_view(ctx), wv2 = kad::wide_view2(ctx);
+  uint32_t *wk = ctx->work.p;  // the launch's counters (kad::WORK_WORDS)
   const kad::SampleOut so_list = o.view(stride, wk + 1), so = o.view(stride);
   kad::BatchDesc *hb = ctx->h_bd.p + set, *db = ctx->d_bd.p + set;
   Key key;
-  key << 1 << set << gd << sv << wv << so_list << shape.block << shape.small_exp << grid << cap
-      << stride << ovc << edges << edge_ids << o.epath.p << o.elen.p << o.h_flags.p << o.h_arcs.p
-      << o.h_nwide.p << wk << hb << db;
+  key << 1 << set << gd << sv << wv << wv2 << so_list << o.fix_list2.p << shape.block
+      << shape.small_exp << grid << cap << stride << ovc << edges << edge_ids << o.epath.p
+      << o.elen.p << o.h_flags.p << o.h_arcs.p << o.h_nwide.p << wk << hb << db;
   kad_status st = record_chain(ctx, ctx->bgraph[set], key, [&](hipStream_t s) -> kad_status {
     HIP_TRY(kad::launch_copy_u64(reinterpret_cast<uint64_t *>(db),
                                  reinterpret_cast<const uint64_t *>(hb),
                                  sizeof(kad::BatchDesc) / 8, s));
-    HIP_TRY(kad::launch_zero_u32(wk, 3, s));
+    HIP_TRY(kad::launch_zero_u32(wk, kad::WORK_WORDS, s));
+    kad_status ws;
     if (ovc == 2) {
-      HIP_TRY(kad::launch_wide_fix(gd, 0, 0, 0, nullptr, 0, sv, wv, cap, true, nullptr, nullptr,
-                                   wk + 2, so, s, db));
+      if ((ws = kad::launch_wide(ctx, gd, 0, 0, 0, nullptr, 0, cap, true, nullptr, nullptr,
+                                 wk + 2, o.fix_list2.p, so, s, 0, db)))
+        return ws;
     } else {
       HIP_TRY(kad::launch_sampler(gd, sv, 0, 0, 0, cap, wk, so_list, grid, shape, s, db));
-      HIP_TRY(kad::launch_wide_fix(gd, 0, 0, 0, nullptr, 0, sv, wv, cap, false, o.fix_list.p,
-                                   wk + 1, wk + 2, so, s, db));
+      if ((ws = kad::launch_wide(ctx, gd, 0, 0, 0, nullptr, 0, cap, false, o.fix_list.p, wk + 1,
+                                 wk + 2, o.fix_list2.p, so, s, 0, db)))
+        return ws;
       HIP_TRY(kad::launch_copy_u32(o.h_nwide.p, wk + 1, 1, s));
     }
     if (edges)
@@ -1284,6 +1361,9 @@ kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t see
   out.stride = stride;
   out.fix_list = reinterpret_cast<uint32_t *>(base + o_fix);
   out.fix_count = cnt + 1;
+  kad::SampleOut wout = out;  // the wide kernel's outputs: it keeps no list
+  wout.fix_list = nullptr;
+  wout.fix_count = nullptr;
   kad::SlotState sv;
   sv.slots = (uint32_t)G;
   sv.n = n;
@@ -1314,7 +1394,7 @@ kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t see
     HIP_TRY(kad::launch_sampler(gd, sv, seed, phase, first + done, nb, cnt, out,
                                 (uint32_t)std::min<uint64_t>(G, nb), shape, stream));
     HIP_TRY(kad::launch_wide_fix(gd, seed, phase, first + done, nullptr, 0, sv, wv, nb, false,
-                                 out.fix_list, cnt + 1, cnt + 2, out, stream));
+                                 out.fix_list, cnt + 1, cnt + 2, wout, stream));
     HIP_TRY(kad::launch_hit_add_atomic(out.path, out.len, stride, nb, n, count_dev, stream));
     HIP_TRY(kad::launch_sample_sums(out.arcs, out.flags, nb, arcs_dev, flags_dev, stream));
     done += nb;
@@ -1473,11 +1553,14 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   // whole check intervals.  When the slots allow it, it runs beside the pilot on its own
   // stream, slots and work counter (a pilot of alpha samples is one short launch whose
   // last samples would otherwise hold the GPU); its wide-count fix, which shares one
-  // arena, waits for the pilot's.
+  // arena, waits for the pilot's.  Its slots start past every slot the pilot may use:
+  // the pilot sampler's (at most alpha) and those of the pilot's wide-count passes, which
+  // run on sampler slots 0, 1, ... (at most w_slots).
   const int first_set = 1;
   const uint32_t first_nb = (uint32_t)std::min<uint64_t>(
       omega, std::min<uint64_t>(K, std::max<uint64_t>(B, (omega / 2 + B - 1) / B * B)));
-  const uint32_t b1_slot0 = (uint32_t)std::max<uint64_t>(alpha, 64);
+  const uint32_t b1_slot0 =
+      (uint32_t)std::max<uint64_t>(std::max<uint64_t>(alpha, 64), ctx->w_slots);
   const bool overlap = !plain && hip_stream == nullptr && ovc != 2 && alpha <= ctx->outs[0].cap &&
                        (uint64_t)ctx->slots >= (uint64_t)b1_slot0 + kad::launch_grid(
                                                    ctx, kad::graph_shape(g), first_nb);
@@ -1953,6 +2036,34 @@ kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable) {
   ctx->timing = enable != 0;
   ctx->t_launches = ctx->t_samples = ctx->t_arcs = ctx->t_nodes = ctx->t_hits = 0;
   ctx->t_seconds = 0.0;
+  return KAD_OK;
+}
+
+kad_status kad_ctx_set_wide(kad_ctx *ctx, uint32_t slots, uint64_t limbs) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  if (limbs != 0 && limbs < 4096) return fail(KAD_EINVAL, "a wide-count arena needs 4096 limbs or more");
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipDeviceSynchronize());  // no launch may still use the arena
+  ctx->w_user_slots = slots;
+  ctx->w_user_limbs = limbs;
+  ctx->w_arena.release();  // laid out again on next use
+  ctx->w_lv.release();
+  ctx->w_lbase.release();
+  ctx->w_slots = ctx->w_slots2 = 0;
+  ctx->w_arena_limbs = ctx->w_arena_limbs2 = 0;
+  ctx->w_big = false;
+  return KAD_OK;
+}
+
+kad_status kad_ctx_get_wide(kad_ctx *ctx, uint32_t *slots, uint64_t *limbs, uint32_t *slots2,
+                            uint64_t *limbs2) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  if (slots) *slots = ctx->w_slots;
+  if (limbs) *limbs = ctx->w_arena_limbs;
+  if (slots2) *slots2 = ctx->w_slots2;
+  if (limbs2) *limbs2 = ctx->w_arena_limbs2;
   return KAD_OK;
 }
 
