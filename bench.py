@@ -182,7 +182,16 @@ def bench_batch(args, torch, gg, kad):
     ctx.set_exec("graph")
     seq_s, single = seq["graph"]
     plain_s, plain = seq["plain"]
-    # the engine
+    # the engine: ticks launched call by call, then replayed as recorded chains (default)
+    ctx.set_exec("stream")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        batch_s = kad.run_batch(ctx, Gs, params)
+    torch.cuda.synchronize()
+    engine_stream_s = (time.perf_counter() - t0) / args.steps
+    ctx.set_exec("graph")
+    r0 = ctx.exec_info()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for s in range(args.steps):
@@ -190,6 +199,9 @@ def bench_batch(args, torch, gg, kad):
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t0
     step_s = elapsed / args.steps
+    r1 = ctx.exec_info()
+    print(f"[bench] kad_run_batch call by call: {engine_stream_s:.3f} s; replayed: {step_s:.3f} s",
+          file=sys.stderr, flush=True)
     # the engine's sampler launches timed by events, in one further step
     ctx.set_timing(True)
     t1 = time.perf_counter()
@@ -200,7 +212,8 @@ def bench_batch(args, torch, gg, kad):
     ctx.set_timing(False)
     print(f"[bench] kad_run_batch: {step_s:.3f} s per step", file=sys.stderr, flush=True)
     identical = all(_same_result(a, b) for a, b in zip(batch, single)) and \
-        all(_same_result(a, b) for a, b in zip(plain, single))
+        all(_same_result(a, b) for a, b in zip(plain, single)) and \
+        all(_same_result(a, b) for a, b in zip(batch_s, single))
     paths = sum(r["alpha"] + r["tau"] for r in batch)
     arcs = sum(r["arcs_scanned"] + r["pilot_arcs_scanned"] for r in batch)
     alg = algorithmic_bytes(tm["arcs"], tm["nodes"], tm["hits"])
@@ -224,6 +237,8 @@ def bench_batch(args, torch, gg, kad):
         "speedup_vs_sequential": seq_s / step_s,
         "plain_sequential_time_to_epsilon_s": plain_s,
         "speedup_vs_plain": plain_s / step_s,
+        "engine_call_by_call_time_to_epsilon_s": engine_stream_s,
+        "chain_replays_per_step": (r1["replays"] - r0["replays"]) / args.steps,
         "results_identical_to_single_runs": identical,
         "sampler": {"note": "one further engine step with event timing",
                     "launches": tm["launches"], "samples": tm["samples"],

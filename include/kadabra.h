@@ -422,13 +422,16 @@ kad_status kad_ctx_set_wide(kad_ctx *ctx, uint32_t slots, uint64_t limbs);
 kad_status kad_ctx_get_wide(kad_ctx *ctx, uint32_t *slots, uint64_t *limbs, uint32_t *slots2,
                             uint64_t *limbs2);
 
-/* kad_run's launch mode (KAD_EXEC_*; default KAD_EXEC_GRAPH).  While timing is enabled
+/* The launch mode (KAD_EXEC_*; default KAD_EXEC_GRAPH) of kad_run and of the engine
+ * (kad_run_batch, the server: KAD_EXEC_GRAPH replays each tick's sampling chain; the other
+ * two modes launch it call by call).  While timing is enabled
  * KAD_EXEC_GRAPH launches call by call (the per-launch events sit inside the chain).
  * The recorded chains are kept in the context and recorded again when the graph, the
  * buffers or kernel_batch change.  KAD_EINVAL for an unknown mode. */
 kad_status kad_ctx_set_exec(kad_ctx *ctx, uint32_t mode);
-/* The mode, and how many chains kad_run has recorded and replayed in this context (any
- * pointer may be NULL). */
+/* The mode, and how many chains this context has recorded and replayed (kad_run's batches
+ * and the engine's ticks, whose sampling chain -- segment table, sampler, wide-count passes,
+ * host mirrors -- is replayed the same way; any pointer may be NULL). */
 kad_status kad_ctx_get_exec(kad_ctx *ctx, uint32_t *mode, uint64_t *records, uint64_t *replays);
 
 const char *kad_last_error(void);

@@ -77,8 +77,9 @@ struct WideState {
 // The arguments of one batch in device memory.  A chain of launches recorded once into a
 // hipGraph reads them from here on every replay (kernels given a descriptor ignore the
 // corresponding arguments): the sampler and the wide-count fix take seed, phase, first,
-// count (and, over segments, nseg); the edge-path rewrite and the copies take count; the
-// batched hit reduction takes count and the number of check intervals niv.
+// count, over segments nseg, and (when nonzero) the path stride; the edge-path rewrite and
+// the copies take count (or nseg); the batched hit reduction takes count and the number of
+// check intervals niv.
 struct BatchDesc {
   uint64_t seed;
   uint64_t first;
@@ -86,6 +87,8 @@ struct BatchDesc {
   uint32_t phase;
   uint32_t niv;
   uint32_t nseg;
+  uint32_t stride;
+  uint32_t pad;
 };
 
 struct SampleOut {
@@ -194,11 +197,14 @@ hipError_t launch_group_map(const uint64_t *count, uint32_t n, const uint32_t *c
 // dst[i] = src[i], i < count, by a kernel on `stream`; either side may be pinned,
 // coherent host memory.  Used instead of runtime copies where a copy must not wait
 // behind kernels of other streams, and inside recorded graphs.  With bd the kernel
-// copies bd->count entries (at most `count`, the launch's size).
+// copies per * bd->count entries (per * bd->nseg with by_nseg; at most `count`, the
+// launch's size).
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t count,
-                              hipStream_t stream, const BatchDesc *bd = nullptr);
+                              hipStream_t stream, const BatchDesc *bd = nullptr,
+                              uint32_t per = 1, bool by_nseg = false);
 hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t count,
-                              hipStream_t stream, const BatchDesc *bd = nullptr);
+                              hipStream_t stream, const BatchDesc *bd = nullptr,
+                              uint32_t per = 1, bool by_nseg = false);
 // p[i] = value for i < count.
 hipError_t launch_fill_u32(uint32_t *p, uint64_t count, uint32_t value, hipStream_t stream);
 

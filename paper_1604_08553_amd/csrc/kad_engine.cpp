@@ -123,6 +123,11 @@ struct Tick {
   OutSet out;
   DevBuf<uint32_t> wlist;  // samples left by the sampler to the wide-count kernel
   DevBuf<uint32_t> wlist2; // samples left by the first wide pass to the second
+  // the recorded sampling chains of this tick's buffers, one per sampler block size
+  // (KAD_EXEC_GRAPH), and the descriptor they read
+  BatchGraph chains[3];
+  PinBuf<BatchDesc> h_bd;
+  DevBuf<BatchDesc> d_bd;
   DevBuf<SampleSeg> d_segs;
   PinBuf<SampleSeg> h_segs;
   DevBuf<GatherDesc> d_gat;
@@ -667,9 +672,6 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   // ---- sampler
   HIP_TRY(hipStreamWaitEvent(s, t.out.reduced, 0));
   static_assert(sizeof(SampleSeg) % 8 == 0 && sizeof(GatherDesc) % 8 == 0, "copied as words");
-  HIP_TRY(launch_copy_u64((uint64_t *)t.d_segs.p, (const uint64_t *)t.h_segs.p,
-                          (uint64_t)np * sizeof(SampleSeg) / 8, s));
-  HIP_TRY(launch_zero_u32(t.work.p, WORK_WORDS, s));
   // launch shape of the graph with the most samples in this launch
   const kad_graph *major = nullptr;
   {
@@ -685,46 +687,88 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   }
   const LaunchShape shape = graph_shape(major);
   const bool wide_lane = &L == &lanes_[1];
-  if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k0, s));
-  if (!wide_lane) {
-    int per_cu = 1;
-    for (int j = 0; j < 3; ++j)
-      if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx_->blocks_per_cu[j];
-    const uint32_t grid = (uint32_t)std::min<uint64_t>(
-        std::min<uint64_t>(L.nslots, (uint64_t)ctx_->cus * per_cu), t.total);
-    SampleOut so = t.out.view(t.stride);
-    so.fix_list = t.wlist.p;
-    so.fix_count = t.work.p + 1;
-    HIP_TRY(launch_sampler_multi(t.d_segs.p, np, lane_slots(L, false), t.total, t.work.p, so,
-                                 grid, shape, s));
-  }
-  // every sample of lane 1; in lane 0 the samples its sampler left (counts past 128 bits,
-  // wide_only segments, more candidate edges than a slot holds)
   if (L.nwslots == 0) return fail(KAD_ENOMEM, "no wide-count slots for this launch");
-  // (with large arenas in two passes: the samples the lane's first pass cannot hold are
-  // sampled again by fewer slots with larger arenas in the lane's same memory)
+  int per_cu = 1;
+  for (int j = 0; j < 3; ++j)
+    if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx_->blocks_per_cu[j];
+  const uint32_t resident =
+      (uint32_t)std::min<uint64_t>(L.nslots, (uint64_t)ctx_->cus * per_cu);
   const WideState w2 = lane_wide2(L);
-  SampleOut o1 = t.out.view(t.stride);
-  if (w2.slots) {
-    o1.fix_list = t.wlist2.p;
-    o1.fix_count = t.work.p + 3;
+  // The sampling chain: segment table to the device, counters cleared, the sampler (lane 0),
+  // the wide-count passes (every sample of lane 1; in lane 0 the samples its sampler left:
+  // counts past 128 bits, wide_only segments, more candidate edges than a slot holds; with
+  // large arenas in two passes, the samples the lane's first pass cannot hold are sampled
+  // again by fewer slots with larger arenas in the lane's same memory), the fix count to
+  // the host.  With bd (a replay) the segment count, the sample count and the stride come
+  // from the descriptor and the launches are sized for the largest tick.
+  auto chain = [&](hipStream_t cs, const BatchDesc *bd) -> kad_status {
+    const uint32_t nseg = bd ? MAX_PIECES : np, total = bd ? TICK_SAMPLES : t.total;
+    const uint32_t stride = bd ? 0u : t.stride;
+    if (bd)
+      HIP_TRY(launch_copy_u64(reinterpret_cast<uint64_t *>(t.d_bd.p),
+                              reinterpret_cast<const uint64_t *>(t.h_bd.p),
+                              sizeof(BatchDesc) / 8, cs));
+    HIP_TRY(launch_copy_u64((uint64_t *)t.d_segs.p, (const uint64_t *)t.h_segs.p,
+                            (uint64_t)nseg * sizeof(SampleSeg) / 8, cs, bd,
+                            sizeof(SampleSeg) / 8, true));
+    HIP_TRY(launch_zero_u32(t.work.p, WORK_WORDS, cs));
+    if (!bd && ctx_->timing) HIP_TRY(hipEventRecord(t.out.k0, cs));
+    if (!wide_lane) {
+      SampleOut so = t.out.view(stride);
+      so.fix_list = t.wlist.p;
+      so.fix_count = t.work.p + 1;
+      HIP_TRY(launch_sampler_multi(t.d_segs.p, nseg, lane_slots(L, false), total, t.work.p, so,
+                                   std::min(resident, total), shape, cs, bd));
+    }
+    SampleOut o1 = t.out.view(stride);
+    if (w2.slots) {
+      o1.fix_list = t.wlist2.p;
+      o1.fix_count = t.work.p + 3;
+    }
+    HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, nseg, lane_slots(L, true),
+                            lane_wide(L), total, wide_lane, t.wlist.p, t.work.p + 1,
+                            t.work.p + 2, o1, cs, bd));
+    if (w2.slots)
+      HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, nseg, lane_slots(L, true), w2,
+                              total, false, t.wlist2.p, t.work.p + 3, t.work.p + 4,
+                              t.out.view(stride), cs, bd));
+    if (!wide_lane) HIP_TRY(launch_copy_u32(t.out.h_nwide.p, t.work.p + 1, 1, cs));
+    if (bd) {  // the host mirrors, inside the chain
+      HIP_TRY(launch_copy_u32(t.out.h_flags.p, t.out.flags.p, TICK_SAMPLES, cs, bd));
+      HIP_TRY(launch_copy_u64(t.out.h_arcs.p, t.out.arcs.p, TICK_SAMPLES, cs, bd));
+    }
+    return KAD_OK;
+  };
+  const bool replay = ctx_->exec == KAD_EXEC_GRAPH && !ctx_->timing;
+  if (replay) {
+    HIP_TRY(t.h_bd.ensure(1));
+    HIP_TRY(t.d_bd.ensure(1));
+    BatchGraph &bg = t.chains[shape.block == 64 ? 0 : (shape.block == 128 ? 1 : 2)];
+    ChainKey key;
+    key << 3 << (int)(&L - lanes_) << shape.block << shape.small_exp << resident << wide_lane
+        << lane_slots(L, false) << lane_slots(L, true) << lane_wide(L) << w2
+        << t.out.view(0) << t.out.h_flags.p << t.out.h_arcs.p << t.out.h_nwide.p << t.d_segs.p
+        << t.h_segs.p << t.work.p << t.wlist.p << t.wlist2.p << t.h_bd.p << t.d_bd.p;
+    kad_status st = record_chain(ctx_, bg, key,
+                                 [&](hipStream_t cs) { return chain(cs, t.d_bd.p); });
+    if (st) return st;
+    // this tick's previous replay read its descriptor: the host has waited for its mirrors
+    t.h_bd.p[0] = BatchDesc{0, 0, t.total, 0u, 0u, np, t.stride, 0u};
+    HIP_TRY(hipGraphLaunch(bg.exec, s));
+    bg.replays++;
+    ctx_->chain_replays++;
+  } else {
+    kad_status st = chain(s, nullptr);
+    if (st) return st;
   }
-  HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, np, lane_slots(L, true),
-                          lane_wide(L), t.total, wide_lane, t.wlist.p, t.work.p + 1,
-                          t.work.p + 2, o1, s));
-  if (w2.slots)
-    HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, np, lane_slots(L, true), w2,
-                            t.total, false, t.wlist2.p, t.work.p + 3, t.work.p + 4,
-                            t.out.view(t.stride), s));
-  if (wide_lane)
-    t.out.h_nwide.p[0] = t.total;
-  else
-    HIP_TRY(launch_copy_u32(t.out.h_nwide.p, t.work.p + 1, 1, s));
-  if (ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
+  if (wide_lane) t.out.h_nwide.p[0] = t.total;
+  if (!replay && ctx_->timing) HIP_TRY(hipEventRecord(t.out.k1, s));
   HIP_TRY(hipEventRecord(t.sampled, s));
   // host copies by kernels: runtime copies were seen waiting for the other lane's kernels
-  HIP_TRY(launch_copy_u32(t.out.h_flags.p, t.out.flags.p, t.total, s));
-  HIP_TRY(launch_copy_u64(t.out.h_arcs.p, t.out.arcs.p, t.total, s));
+  if (!replay) {
+    HIP_TRY(launch_copy_u32(t.out.h_flags.p, t.out.flags.p, t.total, s));
+    HIP_TRY(launch_copy_u64(t.out.h_arcs.p, t.out.arcs.p, t.total, s));
+  }
   if (ctx_->timing) {
     HIP_TRY(launch_copy_u32(t.out.h_nodes.p, t.out.nodes.p, t.total, s));
     HIP_TRY(launch_copy_u32(t.out.h_len.p, t.out.len.p, t.total, s));
@@ -1010,6 +1054,7 @@ void fill_result(const kad::Query *q, kad_result *r, kad_status *ret) {
   r->vd_exact = q->vd_exact ? 1u : 0u;
   r->stop_reason = q->rule ? KAD_STOP_RULE : KAD_STOP_OMEGA;
   r->n = q->n;
+  r->items = q->n;  // the engine runs node betweenness only
   r->C = q->C;
   r->seconds = kad::secs(q->t_submit, q->t_done);
   r->seconds_setup = kad::secs(q->t_submit, q->t_admit);

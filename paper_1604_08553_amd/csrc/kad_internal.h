@@ -9,6 +9,7 @@
 #include <atomic>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/kadabra.h"
@@ -138,6 +139,30 @@ struct BatchGraph {
   }
 };
 
+// What a recorded chain bakes in, as words (addresses, sizes, launch shapes).
+struct ChainKey {
+  std::vector<uint64_t> v;
+  template <typename T>
+  ChainKey &operator<<(T x) {
+    if constexpr (std::is_pointer<T>::value) v.push_back((uint64_t)(uintptr_t)x);
+    else v.push_back((uint64_t)x);
+    return *this;
+  }
+  ChainKey &operator<<(const GraphDev &g) {
+    return *this << g.n << g.arcs << g.row << g.col << g.rrow << g.rcol << g.forward;
+  }
+  ChainKey &operator<<(const SlotState &t) {
+    return *this << t.slots << t.n << t.pi_cap << t.rec << t.visit << t.pi;
+  }
+  ChainKey &operator<<(const WideState &w) {
+    return *this << w.slots << w.max_lev << w.arena_limbs << w.arena << w.lv << w.lbase;
+  }
+  ChainKey &operator<<(const SampleOut &o) {
+    return *this << o.s << o.t << o.len << o.flags << o.nodes << o.arcs << o.path << o.stride
+                 << o.fix_list << o.fix_count;
+  }
+};
+
 class Engine;
 void destroy_engine(Engine *e);
 
@@ -215,6 +240,8 @@ struct kad_ctx {
   kad::PinBuf<kad::BatchDesc> h_bd;
   kad::DevBuf<kad::BatchDesc> d_bd;
   kad::PinBuf<uint64_t> snaps;  // kad_run's check snapshots, one per check of a batch
+  // chains recorded and replayed, by kad_run and by the engine's ticks
+  std::atomic<uint64_t> chain_records{0}, chain_replays{0};
   ~kad_ctx() {
     kad::destroy_engine(engine);
     for (auto e : chunk_ev) (void)hipEventDestroy(e);
@@ -264,6 +291,11 @@ class CtxClaim {
   kad_ctx *c_;
   bool ok_ = false;
 };
+
+// Record the launches `fn` makes on the stream it is given (the context's capture stream)
+// into bg as a hipGraph, unless bg already holds a recording with this key.
+kad_status record_chain(kad_ctx *ctx, BatchGraph &bg, const ChainKey &key,
+                        const std::function<kad_status(hipStream_t)> &fn);
 
 // The context's multi-query engine (created, with its counter pools, on first use).
 kad_status context_engine(kad_ctx *ctx, Engine **out);

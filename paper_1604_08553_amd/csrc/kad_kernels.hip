@@ -988,10 +988,12 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
                                                         uint32_t phase_a, uint64_t first_a,
                                                         const SampleSeg *__restrict__ segs,
                                                         uint32_t nseg_a, uint32_t count_a,
-                                                        uint32_t *work, SampleOut out,
+                                                        uint32_t *work, SampleOut out_a,
                                                         uint32_t small_exp,
                                                         const BatchDesc *__restrict__ bd) {
   constexpr int NWAVES = BLOCK / WAVE;
+  SampleOut out = out_a;
+  if (bd && bd->stride) out.stride = bd->stride;
   // a replayed launch takes its batch from the descriptor (uniform, scalar loads)
   const uint64_t seed0 = bd ? bd->seed : seed_a, first0 = bd ? bd->first : first_a;
   const uint32_t phase0 = bd ? bd->phase : phase_a, count = bd ? bd->count : count_a;
@@ -1597,8 +1599,8 @@ __global__ void fill_u32_kernel(uint32_t *p, uint64_t count, uint32_t value) {
 template <typename T>
 __global__ __launch_bounds__(256) void copy_kernel(T *dst, const T *src, uint64_t count_a,
                                                    const BatchDesc *__restrict__ bd,
-                                                   uint32_t per) {
-  const uint64_t count = bd ? (uint64_t)bd->count * per : count_a;
+                                                   uint32_t per, uint32_t by_nseg) {
+  const uint64_t count = bd ? (uint64_t)(by_nseg ? bd->nseg : bd->count) * per : count_a;
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride)
     dst[i] = src[i];
@@ -1789,9 +1791,11 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
                                                   SlotState st, WideState ws,
                                                   const uint32_t *list,
                                                   const uint32_t *list_count, uint32_t all_a,
-                                                  uint32_t *work, SampleOut out,
+                                                  uint32_t *work, SampleOut out_a,
                                                   const BatchDesc *__restrict__ bd) {
   __shared__ WideLds L;
+  SampleOut out = out_a;
+  if (bd && bd->stride) out.stride = bd->stride;
   const uint64_t seed0 = bd ? bd->seed : seed_a, first0 = bd ? bd->first : first_a;
   const uint32_t phase0 = bd ? bd->phase : phase_a, all_count = bd ? bd->count : all_a;
   const uint32_t nseg = bd ? bd->nseg : nseg_a;
@@ -2721,20 +2725,22 @@ hipError_t launch_zero_u32(uint32_t *p, uint64_t count, hipStream_t stream) {
 }
 
 hipError_t launch_copy_u32(uint32_t *dst, const uint32_t *src, uint64_t count,
-                              hipStream_t stream, const BatchDesc *bd) {
+                              hipStream_t stream, const BatchDesc *bd, uint32_t per,
+                              bool by_nseg) {
   if (count == 0) return hipSuccess;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 1024);
   hipLaunchKernelGGL(copy_kernel<uint32_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count,
-                     bd, 1u);
+                     bd, per, by_nseg ? 1u : 0u);
   return hipGetLastError();
 }
 
 hipError_t launch_copy_u64(uint64_t *dst, const uint64_t *src, uint64_t count,
-                              hipStream_t stream, const BatchDesc *bd) {
+                              hipStream_t stream, const BatchDesc *bd, uint32_t per,
+                              bool by_nseg) {
   if (count == 0) return hipSuccess;
   const uint32_t blocks = (uint32_t)std::min<uint64_t>((count + 255) / 256, 1024);
   hipLaunchKernelGGL(copy_kernel<uint64_t>, dim3(blocks), dim3(256), 0, stream, dst, src, count,
-                     bd, 1u);
+                     bd, per, by_nseg ? 1u : 0u);
   return hipGetLastError();
 }
 

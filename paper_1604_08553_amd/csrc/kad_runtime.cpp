@@ -511,6 +511,35 @@ kad_status validate_params(const kad_graph *g, const kad_params *p) {
   return KAD_OK;
 }
 
+
+// Record the launches `fn` makes on the stream it is given into bg, unless bg already
+// holds a recording with this key.
+kad_status record_chain(kad_ctx *ctx, BatchGraph &bg, const ChainKey &key,
+                        const std::function<kad_status(hipStream_t)> &fn) {
+  if (bg.exec && bg.key == key.v) return KAD_OK;
+  bg.release();
+  if (!ctx->cstream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cstream, hipStreamNonBlocking));
+  HIP_TRY(hipStreamBeginCapture(ctx->cstream, hipStreamCaptureModeThreadLocal));
+  const kad_status st = fn(ctx->cstream);
+  hipGraph_t gr = nullptr;
+  const hipError_t e = hipStreamEndCapture(ctx->cstream, &gr);
+  if (st != KAD_OK || e != hipSuccess || !gr) {
+    if (gr) (void)hipGraphDestroy(gr);
+    if (st != KAD_OK) return st;
+    return fail(KAD_EDEVICE, "recording a batch chain failed: %s", hipGetErrorString(e));
+  }
+  bg.graph = gr;
+  const hipError_t ei = hipGraphInstantiate(&bg.exec, gr, nullptr, nullptr, 0);
+  if (ei != hipSuccess) {
+    bg.release();
+    return fail(KAD_EDEVICE, "instantiating a batch chain failed: %s", hipGetErrorString(ei));
+  }
+  bg.key = key.v;
+  bg.records++;
+  ctx->chain_records++;
+  return KAD_OK;
+}
+
 }  // namespace kad
 
 namespace {
@@ -668,57 +697,6 @@ kad_status launch_batch(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_
 }
 
 // ---------------------------------------------------------------- recorded batch chains
-// What a recorded chain bakes in, as words (addresses and sizes); see BatchGraph.
-struct Key {
-  std::vector<uint64_t> v;
-  template <typename T>
-  Key &operator<<(T x) {
-    if constexpr (std::is_pointer<T>::value) v.push_back((uint64_t)(uintptr_t)x);
-    else v.push_back((uint64_t)x);
-    return *this;
-  }
-  Key &operator<<(const kad::GraphDev &g) {
-    return *this << g.n << g.arcs << g.row << g.col << g.rrow << g.rcol << g.forward;
-  }
-  Key &operator<<(const kad::SlotState &t) {
-    return *this << t.slots << t.n << t.pi_cap << t.rec << t.visit << t.pi;
-  }
-  Key &operator<<(const kad::WideState &w) {
-    return *this << w.slots << w.max_lev << w.arena_limbs << w.arena << w.lv << w.lbase;
-  }
-  Key &operator<<(const kad::SampleOut &o) {
-    return *this << o.s << o.t << o.len << o.flags << o.nodes << o.arcs << o.path << o.stride
-                 << o.fix_list << o.fix_count;
-  }
-};
-
-// Record the launches `fn` makes on the stream it is given into bg, unless bg already
-// holds a recording with this key.
-kad_status record_chain(kad_ctx *ctx, kad::BatchGraph &bg, const Key &key,
-                        const std::function<kad_status(hipStream_t)> &fn) {
-  if (bg.exec && bg.key == key.v) return KAD_OK;
-  bg.release();
-  if (!ctx->cstream) HIP_TRY(hipStreamCreateWithFlags(&ctx->cstream, hipStreamNonBlocking));
-  HIP_TRY(hipStreamBeginCapture(ctx->cstream, hipStreamCaptureModeThreadLocal));
-  const kad_status st = fn(ctx->cstream);
-  hipGraph_t gr = nullptr;
-  const hipError_t e = hipStreamEndCapture(ctx->cstream, &gr);
-  if (st != KAD_OK || e != hipSuccess || !gr) {
-    if (gr) (void)hipGraphDestroy(gr);
-    if (st != KAD_OK) return st;
-    return fail(KAD_EDEVICE, "recording a batch chain failed: %s", hipGetErrorString(e));
-  }
-  bg.graph = gr;
-  const hipError_t ei = hipGraphInstantiate(&bg.exec, gr, nullptr, nullptr, 0);
-  if (ei != hipSuccess) {
-    bg.release();
-    return fail(KAD_EDEVICE, "instantiating a batch chain failed: %s", hipGetErrorString(ei));
-  }
-  bg.key = key.v;
-  bg.records++;
-  return KAD_OK;
-}
-
 // The main-phase batch [first, first + count) of output set `set`, as launch_batch makes
 // it (slots from 0, the context's work counters), by replaying the set's recorded sampling
 // chain for batches of up to `cap` samples.  niv: the batch's check intervals (read by the
@@ -740,11 +718,11 @@ kad_status replay_sampling(kad_ctx *ctx, const kad_graph *g, int set, uint64_t s
   uint32_t *wk = ctx->work.p;  // the launch's counters (kad::WORK_WORDS)
   const kad::SampleOut so_list = o.view(stride, wk + 1), so = o.view(stride);
   kad::BatchDesc *hb = ctx->h_bd.p + set, *db = ctx->d_bd.p + set;
-  Key key;
+  kad::ChainKey key;
   key << 1 << set << gd << sv << wv << wv2 << so_list << o.fix_list2.p << shape.block
       << shape.small_exp << grid << cap << stride << ovc << edges << edge_ids << o.epath.p
       << o.elen.p << o.h_flags.p << o.h_arcs.p << o.h_nwide.p << wk << hb << db;
-  kad_status st = record_chain(ctx, ctx->bgraph[set], key, [&](hipStream_t s) -> kad_status {
+  kad_status st = kad::record_chain(ctx, ctx->bgraph[set], key, [&](hipStream_t s) -> kad_status {
     HIP_TRY(kad::launch_copy_u64(reinterpret_cast<uint64_t *>(db),
                                  reinterpret_cast<const uint64_t *>(hb),
                                  sizeof(kad::BatchDesc) / 8, s));
@@ -774,6 +752,7 @@ kad_status replay_sampling(kad_ctx *ctx, const kad_graph *g, int set, uint64_t s
   *hb = kad::BatchDesc{seed, first, count, phase, 0u, 0u};
   HIP_TRY(hipGraphLaunch(ctx->bgraph[set].exec, stream));
   ctx->bgraph[set].replays++;
+  ctx->chain_replays++;
   if (ovc == 2) o.h_nwide.p[0] = count;
   HIP_TRY(hipEventRecord(o.sampled, stream));
   HIP_TRY(hipEventRecord(o.copied, stream));
@@ -790,10 +769,10 @@ kad_status replay_reduce(kad_ctx *ctx, int set, const uint32_t *rpath, const uin
   HIP_TRY(ctx->h_bd.ensure(4));
   HIP_TRY(ctx->d_bd.ensure(4));
   kad::BatchDesc *hb = ctx->h_bd.p + 2 + set, *db = ctx->d_bd.p + 2 + set;
-  Key key;
+  kad::ChainKey key;
   key << 2 << set << rpath << rlen << rstride << cap << per_iv << n << ngroups << ctx->count.p
       << ctx->group.p << ctx->gmax.p << ctx->ivtmp.p << ctx->ivmax.p << snaps << hb << db;
-  kad_status st = record_chain(ctx, ctx->bgraph[2 + set], key, [&](hipStream_t s) -> kad_status {
+  kad_status st = kad::record_chain(ctx, ctx->bgraph[2 + set], key, [&](hipStream_t s) -> kad_status {
     HIP_TRY(kad::launch_copy_u64(reinterpret_cast<uint64_t *>(db),
                                  reinterpret_cast<const uint64_t *>(hb),
                                  sizeof(kad::BatchDesc) / 8, s));
@@ -807,6 +786,7 @@ kad_status replay_reduce(kad_ctx *ctx, int set, const uint32_t *rpath, const uin
   *hb = kad::BatchDesc{0, 0, count, 0u, (count + per_iv - 1) / per_iv, 0u};
   HIP_TRY(hipGraphLaunch(ctx->bgraph[2 + set].exec, rs));
   ctx->bgraph[2 + set].replays++;
+  ctx->chain_replays++;
   return KAD_OK;
 }
 
@@ -2079,13 +2059,8 @@ kad_status kad_ctx_set_exec(kad_ctx *ctx, uint32_t mode) {
 kad_status kad_ctx_get_exec(kad_ctx *ctx, uint32_t *mode, uint64_t *records, uint64_t *replays) {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (mode) *mode = ctx->exec;
-  uint64_t rec = 0, rep = 0;
-  for (const kad::BatchGraph &b : ctx->bgraph) {
-    rec += b.records;
-    rep += b.replays;
-  }
-  if (records) *records = rec;
-  if (replays) *replays = rep;
+  if (records) *records = ctx->chain_records.load();
+  if (replays) *replays = ctx->chain_replays.load();
   return KAD_OK;
 }
 

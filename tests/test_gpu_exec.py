@@ -161,3 +161,33 @@ def test_exec_mode_rejects_unknown(kad, ctx):
         kad._check(kad.lib().kad_ctx_set_exec(ctx.handle, 7))
     assert e.value.status == -1
     assert ctx.exec_info()["mode"] == "graph"
+
+
+def test_engine_ticks_replayed_equal_call_by_call(kad, ctx, graphs):
+    """The engine replays each tick's sampling chain (segment table, sampler, wide-count
+    passes, host mirrors) with the tick's size, segment count and stride read from a
+    descriptor; its results equal the call-by-call engine's and kad_run's, twice in a row."""
+    gs, Gs = graphs
+    mix = [("er2000", dict(epsilon=0.01, seed=21)),
+           ("cl30k", dict(epsilon=0.01, seed=22)),
+           ("dcl30k", dict(epsilon=0.02, seed=23, mode="topk", k=5)),
+           ("grid90", dict(epsilon=0.05, seed=24)),
+           ("grid140", dict(epsilon=0.1, seed=25)),
+           ("er2000", dict(epsilon=0.006, seed=26, kernel_batch=2048))]
+    graphs_ = [Gs[name] for name, _ in mix]
+    params = [dict(delta=0.1, **kw) for _, kw in mix]
+    ctx.set_exec("stream")
+    _say("engine call by call")
+    a = kad.run_batch(ctx, graphs_, params)
+    ctx.set_exec("graph")
+    r0 = ctx.exec_info()["replays"]
+    for rep in range(2):
+        _say("engine replayed", rep)
+        b = kad.run_batch(ctx, graphs_, params)
+        for (name, kw), x, y in zip(mix, a, b):
+            _same(y, x, f"engine replay {rep} {name} {kw}")
+    assert ctx.exec_info()["replays"] > r0
+    ctx.set_exec("stream")
+    for (name, kw), x in zip(mix[:2], a):
+        _same(kad.run(ctx, Gs[name], delta=0.1, **kw), x, f"kad_run {name}")
+    ctx.set_exec("graph")
