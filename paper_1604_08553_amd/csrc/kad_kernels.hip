@@ -1657,6 +1657,29 @@ __device__ int wide_cmp(const uint64_t *a, uint32_t aw, const uint64_t *b, uint3
   return 0;
 }
 
+// The same for a number whose limb j sits at a[j * pitch] (a level's counts are stored
+// limb-major: limb j of every node of the level side by side).
+__device__ uint32_t wide_len_s(const uint64_t *a, uint32_t pitch, uint32_t w) {
+  while (w > 0 && a[(size_t)(w - 1) * pitch] == 0) --w;
+  return w;
+}
+
+// acc[0, aw) += x[j * pitch], j < xw, xw <= aw (x limb-major, acc contiguous).
+__device__ void wide_add_s(uint64_t *acc, uint32_t aw, const uint64_t *x, uint32_t pitch,
+                           uint32_t xw) {
+  uint64_t c = 0;
+  for (uint32_t j = 0; j < aw; ++j) {
+    if (j >= xw && c == 0) break;
+    const uint64_t xv = j < xw ? x[(size_t)j * pitch] : 0;
+    const uint64_t s1 = acc[j] + xv;
+    const uint64_t c1 = s1 < xv ? 1u : 0u;
+    const uint64_t s2 = s1 + c;
+    const uint64_t c2 = s2 < c ? 1u : 0u;
+    acc[j] = s2;
+    c = c1 | c2;
+  }
+}
+
 // acc[0, aw) += x[0, xw), xw <= aw; returns the carry out of acc[aw - 1].
 __device__ uint64_t wide_add(uint64_t *acc, uint32_t aw, const uint64_t *x, uint32_t xw) {
   uint64_t c = 0;
@@ -1671,6 +1694,28 @@ __device__ uint64_t wide_add(uint64_t *acc, uint32_t aw, const uint64_t *x, uint
     c = c1 | c2;
   }
   return c;
+}
+
+// out[0, aw + bw) = a * b (schoolbook), a and b limb-major with pitches ap and bp.
+__device__ void wide_mul_s(const uint64_t *a, uint32_t ap, uint32_t aw, const uint64_t *b,
+                           uint32_t bp, uint32_t bw, uint64_t *out) {
+  for (uint32_t j = 0; j < aw + bw; ++j) out[j] = 0;
+  for (uint32_t x = 0; x < aw; ++x) {
+    const uint64_t ax = a[(size_t)x * ap];
+    if (ax == 0) continue;
+    uint64_t carry = 0;
+    for (uint32_t y = 0; y < bw; ++y) {
+      const uint64_t by = b[(size_t)y * bp];
+      const uint64_t lo = ax * by, hi = __umul64hi(ax, by);
+      uint64_t s = out[x + y] + lo;
+      uint64_t c = s < lo ? 1u : 0u;
+      s += carry;
+      c += s < carry ? 1u : 0u;
+      out[x + y] = s;
+      carry = hi + c;  // the 128-bit sum fits, so this does not wrap
+    }
+    out[x + bw] = carry;
+  }
 }
 
 // out[0, aw + bw) = a * b (schoolbook).
@@ -1735,22 +1780,25 @@ __device__ void uniform_below_wide(const uint64_t *bound, uint32_t bw, uint64_t 
 
 constexpr int WCHUNK = 2 * WB;  // frontier nodes staged per pass
 
-// acc[0, stride) (+)= the sum of the counts src[idx[q] * sl, + wl), q < np (np <= 4),
+// acc (+)= the sum of the counts of nodes idx[q], q < np (np <= 4), of the level before,
 // four limbs at a time in registers so that the loads of a chunk overlap; with first
-// the old contents of acc are ignored.  wl < stride, so the sum fits.
-__device__ void pull_add(uint64_t *__restrict__ acc, uint32_t stride,
-                         const uint64_t *__restrict__ src, uint32_t sl, uint32_t wl,
+// the old contents of acc are ignored.  Both levels are limb-major: limb j of acc at
+// acc[j * apitch] (j < stride), limb j of node q at src[j * spitch + q] (j < wl).
+// wl < stride, so the sum fits.
+__device__ void pull_add(uint64_t *__restrict__ acc, uint32_t apitch, uint32_t stride,
+                         const uint64_t *__restrict__ src, uint32_t spitch, uint32_t wl,
                          const uint32_t *idx, uint32_t np, bool first) {
   uint64_t carry = 0;  // carry into the next limb (at most np)
   for (uint32_t c0 = 0; c0 < stride; c0 += 4) {
     uint64_t v[4], x[4][4];
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[j] = (!first && c0 + j < stride) ? acc[c0 + j] : 0;
+    for (int j = 0; j < 4; ++j)
+      v[j] = (!first && c0 + j < stride) ? acc[(size_t)(c0 + j) * apitch] : 0;
 #pragma unroll
     for (int q = 0; q < 4; ++q)
 #pragma unroll
       for (int j = 0; j < 4; ++j)
-        x[q][j] = ((uint32_t)q < np && c0 + j < wl) ? src[(size_t)idx[q] * sl + c0 + j] : 0;
+        x[q][j] = ((uint32_t)q < np && c0 + j < wl) ? src[(size_t)(c0 + j) * spitch + idx[q]] : 0;
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       uint64_t sum = v[j] + carry;
@@ -1765,14 +1813,14 @@ __device__ void pull_add(uint64_t *__restrict__ acc, uint32_t stride,
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (c0 + j < stride) acc[c0 + j] = v[j];
+      if (c0 + j < stride) acc[(size_t)(c0 + j) * apitch] = v[j];
   }
 }
 
 struct WideLds {
   uint32_t k, seg, s, t, flags;
   uint32_t lvl[2];
-  uint32_t nvis, pi_count, maxw, maxw_all, sel, capf;
+  uint32_t nvis, pi_count, maxw, maxw_all, sel;
   uint32_t kcount, kfound;
   uint64_t deg[2], new_deg, arcs, top;
   uint64_t skey, kmask, kwant;  // the chosen candidate edge; the radix select's digits so far
@@ -1900,7 +1948,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       const uint32_t *pc = me == 0 ? g.rcol : g.col;
       const uint64_t dme = L.deg[me];
       const uint32_t nb = L.nvis;
-      const uint32_t wl = LV(me, l, LV_WIDTH), sl = LV(me, l, LV_STRIDE);
+      const uint32_t wl = LV(me, l, LV_WIDTH);
       const uint64_t bl = LB(me, l);
       const uint32_t stride = wl + 1;
       const uint64_t nbase = L.top;
@@ -1916,13 +1964,10 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
         L.pi_count = 0;
         L.new_deg = 0;
         L.maxw = 0;
-        L.capf = 0;
       }
       __syncthreads();
-      // ---- one pass over the frontier's arcs: meeting test, discovery, and the new
-      // node's count pulled from its predecessors on level l
-      uint32_t used_max = 0;
-      bool cap = false;
+      // ---- one pass over the frontier's arcs: the meeting test and the claims of the
+      // next level's nodes
       for (uint32_t cb = fb; cb < fe; cb += WCHUNK) {
         const uint32_t m = min((uint32_t)WCHUNK, fe - cb);
         uint32_t d[2] = {0, 0};
@@ -1968,33 +2013,11 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
             visit[p] = w;
             *pos_of(rec, w) = p;
             atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)(rp[w + 1] - rp[w]));
-            if (nbase + (uint64_t)(p - nb + 1) * stride > ws.arena_limbs) {
-              cap = true;
-            } else {
-              uint64_t *acc = arena + nbase + (size_t)(p - nb) * stride;
-              uint32_t idx[4], np = 0;
-              bool first = true;
-              const uint32_t pe = pr[w + 1];
-              for (uint32_t e2 = pr[w]; e2 < pe; ++e2) {
-                const uint32_t u2 = pc[e2];
-                if (ld_tag(tag_of(rec, u2)) == cur_tag) idx[np++] = *pos_of(rec, u2) - fb;
-                if (np == 4 || (e2 + 1 == pe && (np > 0 || first))) {
-                  pull_add(acc, stride, arena + bl, sl, wl, idx, np, first);
-                  first = false;
-                  np = 0;
-                }
-              }
-              if (first) pull_add(acc, stride, arena + bl, sl, wl, idx, 0, true);  // no predecessor
-              used_max = max(used_max, wide_len(acc, stride));
-            }
           }
         }
         __syncthreads();
       }
-      atomicMax(&L.maxw, used_max);
-      if (cap) atomicOr(&L.capf, 1u);
-      __syncthreads();
-      if (L.pi_count > 0) {  // the level just discovered is never used: no arena limit
+      if (L.pi_count > 0) {  // the level just discovered is never used: no counts for it
         met = true;
         m_side = me;
         m_fb = fb;
@@ -2004,10 +2027,35 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       }
       const uint32_t ne = L.nvis;
       if (ne == nb) break;  // the expanded side closed: s and t are disconnected
-      if (L.capf) {
+      // ---- the new level's counts, stored limb-major: limb j of the node at position p
+      // at arena[nbase + j * (ne - nb) + (p - nb)].  The thread of p pulls it from the
+      // node's predecessors on level l (limb j of its node q at arena[bl + j * (fe - fb)
+      // + q]), so consecutive threads write consecutive words and read nearby ones.
+      const uint32_t mnew = ne - nb, mcur = fe - fb;
+      if (nbase + (uint64_t)mnew * stride > ws.arena_limbs) {
         if (tid == 0) L.flags |= FLAG_CAPACITY;
         break;
       }
+      uint32_t used_max = 0;
+      for (uint32_t p = nb + tid; p < ne; p += WB) {
+        const uint32_t w = visit[p];
+        uint64_t *acc = arena + nbase + (p - nb);
+        uint32_t idx[4], np = 0;
+        bool first = true;
+        const uint32_t pe = pr[w + 1];
+        for (uint32_t e2 = pr[w]; e2 < pe; ++e2) {
+          const uint32_t u2 = pc[e2];
+          if (ld_tag(tag_of(rec, u2)) == cur_tag) idx[np++] = *pos_of(rec, u2) - fb;
+          if (np == 4 || (e2 + 1 == pe && (np > 0 || first))) {
+            pull_add(acc, mnew, stride, arena + bl, mcur, wl, idx, np, first);
+            first = false;
+            np = 0;
+          }
+        }
+        if (first) pull_add(acc, mnew, stride, arena + bl, mcur, wl, idx, 0, true);  // no predecessor
+        used_max = max(used_max, wide_len_s(acc, mnew, stride));
+      }
+      atomicMax(&L.maxw, used_max);
       __syncthreads();
       if (tid == 0) {
         const uint32_t wn = max(L.maxw, 1u);
@@ -2034,14 +2082,14 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       const uint32_t tw = max(pw, L.maxw_all) + 2;  // totals, draws, running sums
       constexpr uint32_t GROUPS = 16;  // block sums are combined in 16 groups of 16
       static_assert(WB == GROUPS * 16, "one block of candidate edges per thread");
-      const uint32_t so = LV(0, ls, LV_LO), ss = LV(0, ls, LV_STRIDE);
-      const uint32_t to = LV(1, lt, LV_LO), ts = LV(1, lt, LV_STRIDE);
+      const uint32_t so = LV(0, ls, LV_LO), sp = LV(0, ls, LV_HI) - so;  // limb pitches
+      const uint32_t to = LV(1, lt, LV_LO), tp = LV(1, lt, LV_HI) - to;
       const uint64_t sb = LB(0, ls), tb = LB(1, lt);
       // weight of candidate edge (v, w): sigma_s(v) sigma_t(w), pw limbs at dst
       auto weight = [&](uint64_t key, uint64_t *dst) {
         const uint32_t v = (uint32_t)(key >> 32), w = (uint32_t)key;
-        wide_mul(arena + sb + (size_t)(*pos_of(rec, v) - so) * ss, ws_,
-                 arena + tb + (size_t)(*pos_of(rec, w) - to) * ts, wt_, dst);
+        wide_mul_s(arena + sb + (*pos_of(rec, v) - so), sp, ws_,
+                   arena + tb + (*pos_of(rec, w) - to), tp, wt_, dst);
       };
       const uint64_t prod = L.top;  // the (unused) new level's place: free from here on
       uint64_t *bscr = nullptr;     // six numbers of tw limbs for the two backtracking walks
@@ -2283,21 +2331,22 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
         const uint32_t *brp = side == 0 ? g.rrow : g.row;
         const uint32_t *bcl = side == 0 ? g.rcol : g.col;
         for (uint32_t j = lev; j >= 1 && fl == 0; --j) {
-          const uint32_t xw = LV(side, j, LV_WIDTH);
-          const uint64_t *sx = arena + LB(side, j) +
-                               (size_t)(*pos_of(rec, x) - LV(side, j, LV_LO)) * LV(side, j, LV_STRIDE);
-          uniform_below_wide(sx, xw, seed, i,
+          const uint32_t xw = LV(side, j, LV_WIDTH), xlo = LV(side, j, LV_LO);
+          const uint64_t *sx = arena + LB(side, j) + (*pos_of(rec, x) - xlo);
+          const uint32_t xp = LV(side, j, LV_HI) - xlo;  // limb pitch of level j
+          for (uint32_t q = 0; q < xw; ++q) acc[q] = sx[(size_t)q * xp];  // sigma(x)
+          uniform_below_wide(acc, xw, seed, i,
                              stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j), r, tmp2, fl);
           const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1
           const uint32_t pwid = LV(side, j - 1, LV_WIDTH), plo = LV(side, j - 1, LV_LO);
-          const uint32_t pst = LV(side, j - 1, LV_STRIDE);
+          const uint32_t ppt = LV(side, j - 1, LV_HI) - plo;  // limb pitch of level j-1
           const uint64_t pb = LB(side, j - 1);
           for (uint32_t q = 0; q < tw; ++q) acc[q] = 0;
           uint32_t pick = 0xFFFFFFFFu;
           for (uint32_t e = brp[x]; e < brp[x + 1] && fl == 0; ++e) {
             const uint32_t u = bcl[e];
             if (ld_tag(tag_of(rec, u)) != want) continue;
-            (void)wide_add(acc, tw, arena + pb + (size_t)(*pos_of(rec, u) - plo) * pst, pwid);
+            wide_add_s(acc, tw, arena + pb + (*pos_of(rec, u) - plo), ppt, pwid);
             if (wide_cmp(acc, tw, r, xw) > 0) {
               pick = u;
               break;
