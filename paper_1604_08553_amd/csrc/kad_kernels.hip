@@ -1784,10 +1784,12 @@ constexpr int WCHUNK = 2 * WB;  // frontier nodes staged per pass
 // four limbs at a time in registers so that the loads of a chunk overlap; with first
 // the old contents of acc are ignored.  Both levels are limb-major: limb j of acc at
 // acc[j * apitch] (j < stride), limb j of node q at src[j * spitch + q] (j < wl).
-// wl < stride, so the sum fits.
-__device__ void pull_add(uint64_t *__restrict__ acc, uint32_t apitch, uint32_t stride,
-                         const uint64_t *__restrict__ src, uint32_t spitch, uint32_t wl,
-                         const uint32_t *idx, uint32_t np, bool first) {
+// wl < stride, so the sum fits.  Returns the width of acc afterwards (its highest nonzero
+// limb + 1).
+__device__ uint32_t pull_add(uint64_t *__restrict__ acc, uint32_t apitch, uint32_t stride,
+                             const uint64_t *__restrict__ src, uint32_t spitch, uint32_t wl,
+                             const uint32_t *idx, uint32_t np, bool first) {
+  uint32_t width = 0;
   uint64_t carry = 0;  // carry into the next limb (at most np)
   for (uint32_t c0 = 0; c0 < stride; c0 += 4) {
     uint64_t v[4], x[4][4];
@@ -1813,8 +1815,12 @@ __device__ void pull_add(uint64_t *__restrict__ acc, uint32_t apitch, uint32_t s
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j)
-      if (c0 + j < stride) acc[(size_t)(c0 + j) * apitch] = v[j];
+      if (c0 + j < stride) {
+        acc[(size_t)(c0 + j) * apitch] = v[j];
+        if (v[j] != 0) width = c0 + j + 1;
+      }
   }
+  return width;
 }
 
 struct WideLds {
@@ -1995,24 +2001,45 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
         if (2 * tid + 1 < m) L.c_pref[2 * tid + 1] = ex + d[0];
         if (tid == 0) L.c_pref[m] = tot;
         __syncthreads();
-        for (uint32_t e = tid; e < tot; e += WB) {
-          uint32_t lo = 0, hi = m;  // largest j with c_pref[j] <= e
-          while (hi - lo > 1) {
-            const uint32_t mid = (lo + hi) >> 1;
-            if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
+        // UA arcs per thread at a time: their row reads, tag loads and claims go out
+        // together rather than one arc's after another's
+        constexpr int UA = 4;
+        for (uint32_t e0 = tid; e0 < tot; e0 += WB * UA) {
+          uint32_t uu[UA], ww[UA], tg[UA], old[UA];
+#pragma unroll
+          for (int q = 0; q < UA; ++q) {
+            const uint32_t e = e0 + (uint32_t)q * WB;
+            uu[q] = 0xFFFFFFFFu;  // no arc
+            ww[q] = 0;
+            if (e < tot) {
+              uint32_t lo = 0, hi = m;  // largest j with c_pref[j] <= e
+              while (hi - lo > 1) {
+                const uint32_t mid = (lo + hi) >> 1;
+                if (L.c_pref[mid] <= e) lo = mid; else hi = mid;
+              }
+              uu[q] = L.c_node[lo];
+              ww[q] = cl[L.c_start[lo] + (e - L.c_pref[lo])];
+            }
           }
-          const uint32_t u = L.c_node[lo];
-          const uint32_t w = cl[L.c_start[lo] + (e - L.c_pref[lo])];
-          const uint32_t tg = ld_tag(tag_of(rec, w));
-          if (tg == other_tag) {
-            const uint32_t idx = atomicAdd(&L.pi_count, 1u);
-            const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
-            if (idx < st.pi_cap) gpi[idx] = key;
-          } else if (tg == 0 && cas_tag(tag_of(rec, w), 0u, next_tag) == 0u) {
-            const uint32_t p = atomicAdd(&L.nvis, 1u);
-            visit[p] = w;
-            *pos_of(rec, w) = p;
-            atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)(rp[w + 1] - rp[w]));
+#pragma unroll
+          for (int q = 0; q < UA; ++q)
+            tg[q] = uu[q] != 0xFFFFFFFFu ? ld_tag(tag_of(rec, ww[q])) : next_tag;  // next_tag: skip
+#pragma unroll
+          for (int q = 0; q < UA; ++q)
+            old[q] = tg[q] == 0 ? cas_tag(tag_of(rec, ww[q]), 0u, next_tag) : 1u;
+#pragma unroll
+          for (int q = 0; q < UA; ++q) {
+            const uint32_t u = uu[q], w = ww[q];
+            if (tg[q] == other_tag) {
+              const uint32_t idx = atomicAdd(&L.pi_count, 1u);
+              const uint64_t key = me == 0 ? (((uint64_t)u << 32) | w) : (((uint64_t)w << 32) | u);
+              if (idx < st.pi_cap) gpi[idx] = key;
+            } else if (tg[q] == 0 && old[q] == 0u) {  // this arc claimed w
+              const uint32_t p = atomicAdd(&L.nvis, 1u);
+              visit[p] = w;
+              *pos_of(rec, w) = p;
+              atomicAdd((unsigned long long *)&L.new_deg, (unsigned long long)(rp[w + 1] - rp[w]));
+            }
           }
         }
         __syncthreads();
@@ -2040,20 +2067,35 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       for (uint32_t p = nb + tid; p < ne; p += WB) {
         const uint32_t w = visit[p];
         uint64_t *acc = arena + nbase + (p - nb);
-        uint32_t idx[4], np = 0;
+        uint32_t idx[4], np = 0, width = 0;
         bool first = true;
         const uint32_t pe = pr[w + 1];
-        for (uint32_t e2 = pr[w]; e2 < pe; ++e2) {
-          const uint32_t u2 = pc[e2];
-          if (ld_tag(tag_of(rec, u2)) == cur_tag) idx[np++] = *pos_of(rec, u2) - fb;
-          if (np == 4 || (e2 + 1 == pe && (np > 0 || first))) {
-            pull_add(acc, mnew, stride, arena + bl, mcur, wl, idx, np, first);
-            first = false;
-            np = 0;
+        // the node's in-arcs eight at a time: their tails, then the tails' tags and
+        // positions (one load each: no claim changes them during this pass), all in flight
+        // together; predecessors on level l are added four at a time
+        constexpr int UP = 8;
+        for (uint32_t e0 = pr[w]; e0 < pe; e0 += UP) {
+          uint32_t uu[UP];
+          uint2 tp[UP];
+#pragma unroll
+          for (int q = 0; q < UP; ++q) uu[q] = e0 + q < pe ? pc[e0 + q] : 0xFFFFFFFFu;
+#pragma unroll
+          for (int q = 0; q < UP; ++q)
+            tp[q] = uu[q] != 0xFFFFFFFFu ? *reinterpret_cast<const uint2 *>(tag_of(rec, uu[q]))
+                                         : make_uint2(0u, 0u);
+#pragma unroll
+          for (int q = 0; q < UP; ++q) {
+            if (tp[q].x == cur_tag) idx[np++] = tp[q].y - fb;  // (cur_tag is never 0)
+            if (np == 4) {
+              width = pull_add(acc, mnew, stride, arena + bl, mcur, wl, idx, np, first);
+              first = false;
+              np = 0;
+            }
           }
         }
-        if (first) pull_add(acc, mnew, stride, arena + bl, mcur, wl, idx, 0, true);  // no predecessor
-        used_max = max(used_max, wide_len_s(acc, mnew, stride));
+        if (np > 0 || first)  // the rest (or, with no predecessor, zeros)
+          width = pull_add(acc, mnew, stride, arena + bl, mcur, wl, idx, np, first);
+        used_max = max(used_max, width);
       }
       atomicMax(&L.maxw, used_max);
       __syncthreads();
