@@ -408,7 +408,7 @@ kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *sample
 
 /* Wide-count working memory, used by graphs whose path counts can pass 128 bits: the
  * number of first-pass slots (workgroups sampling at once) and each one's arena in 64-bit
- * limbs (0 = the library's choice: at most the sampler slots, three per compute unit, and
+ * limbs (0 = the library's choice: at most the sampler slots, as many as can be resident, and
  * as many as 80% of the memory left after the sampler slots allows, each with room for any
  * sample of the graph when that bound is at most 2^25 limbs, else 2^25 limbs or more).
  * Samples that outgrow a first-pass arena are sampled again, after the pass, by a second

@@ -244,5 +244,7 @@ hipError_t noalloc_scratch(void **ptr);
 
 // Sampler workgroups of `block` threads resident per CU (occupancy query).
 int sampler_blocks_per_cu(int block);
+// Wide-count workgroups resident per CU (occupancy query).
+int wide_blocks_per_cu();
 
 }  // namespace kad

@@ -177,6 +177,7 @@ struct kad_ctx {
   uint64_t used_graphs = 0;
   uint32_t cus = 0;
   int blocks_per_cu[3] = {1, 1, 1};  // resident sampler workgroups per CU, per SAMPLER_BLOCKS
+  int wide_per_cu = 1;               // resident wide-count workgroups per CU
   std::atomic<bool> busy{false};  // one user at a time (a call, or a server's engine)
   // per-slot working state
   uint32_t slot_n = 0, slots = 0;

@@ -1639,7 +1639,7 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc *__restric
 // A level is expanded in one arc-parallel pass: the thread that claims a new node
 // pulls its count from the node's predecessors on the (complete) level before, so no
 // two threads write the same count.
-constexpr int WB = 256;
+constexpr int WB = 512;
 constexpr int WNW = WB / WAVE;
 
 // Limb arrays: 64-bit limbs, least significant first.
@@ -2122,7 +2122,7 @@ __global__ __launch_bounds__(WB) void wide_kernel(GraphDev g0, const SampleSeg *
       const uint32_t ws_ = LV(0, ls, LV_WIDTH), wt_ = LV(1, lt, LV_WIDTH);
       const uint32_t pw = ws_ + wt_;
       const uint32_t tw = max(pw, L.maxw_all) + 2;  // totals, draws, running sums
-      constexpr uint32_t GROUPS = 16;  // block sums are combined in 16 groups of 16
+      constexpr uint32_t GROUPS = WB / 16;  // block sums are combined in groups of 16
       static_assert(WB == GROUPS * 16, "one block of candidate edges per thread");
       const uint32_t so = LV(0, ls, LV_LO), sp = LV(0, ls, LV_HI) - so;  // limb pitches
       const uint32_t to = LV(1, lt, LV_LO), tp = LV(1, lt, LV_HI) - to;
@@ -2841,6 +2841,14 @@ hipError_t launch_gather(const GatherDesc *d, uint32_t nd, uint32_t blocks, uint
   hipLaunchKernelGGL(gather_kernel, dim3(blocks), dim3(256), 0, stream, d, nd, count_pool,
                      gmax_pool, snap);
   return hipGetLastError();
+}
+
+int wide_blocks_per_cu() {
+  int blocks = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, wide_kernel<false>, WB, 0) !=
+      hipSuccess)
+    return 1;
+  return blocks > 0 ? blocks : 1;
 }
 
 int sampler_blocks_per_cu(int block) {

@@ -242,7 +242,7 @@ kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc) {
                   (unsigned long long)want);
   } else {
     // Counts past 128 bits: at most as many slots as the sampler slots, as can be resident
-    // (three per CU) and as 80% of the memory left allows, each with an arena that holds
+    // and as 80% of the memory left allows, each with an arena that holds
     // any sample of the graph when that is at most WIDE_TIER1_LIMBS (or kad_ctx_set_wide's
     // size), else of that size, grown to what the memory gives.  Samples that outgrow it
     // are sampled again by a second pass: fewer slots with arenas of the worst case (at
@@ -251,7 +251,7 @@ kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc) {
     const uint64_t worst = std::max(wide_limbs_worst(g), ovc == 0 ? want : (uint64_t)0);
     const uint64_t target = ctx->w_user_limbs ? ctx->w_user_limbs : WIDE_TIER1_LIMBS;
     const uint64_t lim1 = std::min(worst, target);
-    uint32_t most = std::min<uint32_t>(ctx->slots, 3 * ctx->cus);
+    uint32_t most = std::min<uint32_t>(ctx->slots, (uint32_t)ctx->wide_per_cu * ctx->cus);
     if (ctx->w_user_slots) most = std::min(most, ctx->w_user_slots);
     w_slots = (uint32_t)std::min<uint64_t>(most, A / (lim1 * 8 + tables));
     if (w_slots == 0)
@@ -907,6 +907,7 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   c->cus = (uint32_t)prop.multiProcessorCount;
   for (int j = 0; j < 3; ++j) c->blocks_per_cu[j] = kad::sampler_blocks_per_cu(kad::SAMPLER_BLOCKS[j]);
+  c->wide_per_cu = kad::wide_blocks_per_cu();
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
   c->budget = hbm_budget_bytes ? hbm_budget_bytes : (uint64_t)(0.9 * (double)free_b);
