@@ -123,9 +123,9 @@ struct Tick {
   OutSet out;
   DevBuf<uint32_t> wlist;  // samples left by the sampler to the wide-count kernel
   DevBuf<uint32_t> wlist2; // samples left by the first wide pass to the second
-  // the recorded sampling chains of this tick's buffers, one per sampler block size
-  // (KAD_EXEC_GRAPH), and the descriptor they read
-  BatchGraph chains[3];
+  // the recorded sampling chains of this tick's buffers, one per sampler block size and
+  // wide-lane share (KAD_EXEC_GRAPH), and the descriptor they read
+  BatchGraph chains[6];
   PinBuf<BatchDesc> h_bd;
   DevBuf<BatchDesc> d_bd;
   DevBuf<SampleSeg> d_segs;
@@ -693,6 +693,12 @@ kad_status Engine::launch(Lane &L, Tick &t) {
     if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx_->blocks_per_cu[j];
   const uint32_t resident =
       (uint32_t)std::min<uint64_t>(L.nslots, (uint64_t)ctx_->cus * per_cu);
+  // While lane 0 has work, the wide lane's launches take at most a quarter of the CUs: a
+  // wide-count workgroup fills a CU's registers, and lane 1's long high-diameter queries
+  // would otherwise hold most of the GPU away from every other query.
+  WideState w1 = lane_wide(L);
+  const bool capped = wide_lane && lanes_[0].busy();
+  if (capped) w1.slots = std::min(w1.slots, std::max<uint32_t>(1, ctx_->cus / 4));
   const WideState w2 = lane_wide2(L);
   // The sampling chain: segment table to the device, counters cleared, the sampler (lane 0),
   // the wide-count passes (every sample of lane 1; in lane 0 the samples its sampler left:
@@ -726,7 +732,7 @@ kad_status Engine::launch(Lane &L, Tick &t) {
       o1.fix_count = t.work.p + 3;
     }
     HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, nseg, lane_slots(L, true),
-                            lane_wide(L), total, wide_lane, t.wlist.p, t.work.p + 1,
+                            w1, total, wide_lane, t.wlist.p, t.work.p + 1,
                             t.work.p + 2, o1, cs, bd));
     if (w2.slots)
       HIP_TRY(launch_wide_fix(GraphDev{}, 0, 0, 0, t.d_segs.p, nseg, lane_slots(L, true), w2,
@@ -743,10 +749,11 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   if (replay) {
     HIP_TRY(t.h_bd.ensure(1));
     HIP_TRY(t.d_bd.ensure(1));
-    BatchGraph &bg = t.chains[shape.block == 64 ? 0 : (shape.block == 128 ? 1 : 2)];
+    BatchGraph &bg =
+        t.chains[2 * (shape.block == 64 ? 0 : (shape.block == 128 ? 1 : 2)) + (capped ? 1 : 0)];
     ChainKey key;
     key << 3 << (int)(&L - lanes_) << shape.block << shape.small_exp << resident << wide_lane
-        << lane_slots(L, false) << lane_slots(L, true) << lane_wide(L) << w2
+        << lane_slots(L, false) << lane_slots(L, true) << w1 << w2
         << t.out.view(0) << t.out.h_flags.p << t.out.h_arcs.p << t.out.h_nwide.p << t.d_segs.p
         << t.h_segs.p << t.work.p << t.wlist.p << t.wlist2.p << t.h_bd.p << t.d_bd.p;
     kad_status st = record_chain(ctx_, bg, key,
