@@ -180,6 +180,115 @@ uint32_t bfs_farthest(const uint32_t *rp, const uint32_t *cl, uint32_t src,
   return far;
 }
 
+// Level-synchronous BFS from src over rows (rp, cl) through the nodes whose mark is
+// `from`, marking each reached node `to` (mark[src] must already be `to`); a large level
+// is split over the worker threads, which claim nodes by compare-and-swap on the mark.
+// Returns src's eccentricity within those nodes; with root, also the reached node of
+// largest degree (the first in id order among equals).
+struct BfsScratch {  // reused across the BFS calls of one bound (many components are tiny)
+  std::vector<uint32_t> cur, next, lbest, ldeg;
+  std::vector<std::vector<uint32_t>> local;
+};
+
+uint32_t bfs_levels(const uint32_t *rp, const uint32_t *cl, uint32_t src, uint32_t *mark,
+                    uint32_t from, uint32_t to, uint32_t *root, BfsScratch &sc) {
+  constexpr size_t PAR_MIN = 8192;  // frontier nodes below which a level runs on one thread
+  std::vector<uint32_t> &cur = sc.cur, &next = sc.next;
+  cur.assign(1, src);
+  uint32_t best = src, best_deg = rp[src + 1] - rp[src], ecc = 0;
+  auto better = [](uint32_t d, uint32_t v, uint32_t bd, uint32_t bv) {
+    return d > bd || (d == bd && v < bv);
+  };
+  const unsigned nw = (unsigned)workers().size();
+  sc.local.resize(nw);
+  sc.lbest.resize(nw);
+  sc.ldeg.resize(nw);
+  std::vector<std::vector<uint32_t>> &local = sc.local;
+  std::vector<uint32_t> &lbest = sc.lbest, &ldeg = sc.ldeg;
+  for (;;) {
+    next.clear();
+    if (cur.size() < PAR_MIN || nw == 1) {
+      for (const uint32_t u : cur)
+        for (uint32_t e = rp[u]; e < rp[u + 1]; ++e) {
+          const uint32_t x = cl[e];
+          if (mark[x] != from) continue;
+          mark[x] = to;
+          next.push_back(x);
+          const uint32_t d = rp[x + 1] - rp[x];
+          if (root && better(d, x, best_deg, best)) {
+            best = x;
+            best_deg = d;
+          }
+        }
+    } else {
+      const unsigned nt = (unsigned)std::min<size_t>(nw, cur.size() / (PAR_MIN / 8));
+      workers().run(nt, [&](unsigned w) {
+        std::vector<uint32_t> &out = local[w];
+        out.clear();
+        uint32_t b = UINT32_MAX, bd = 0;
+        const size_t lo = cur.size() * w / nt, hi = cur.size() * (w + 1) / nt;
+        for (size_t q = lo; q < hi; ++q) {
+          const uint32_t u = cur[q];
+          for (uint32_t e = rp[u]; e < rp[u + 1]; ++e) {
+            const uint32_t x = cl[e];
+            uint32_t expect = from;
+            if (__atomic_load_n(&mark[x], __ATOMIC_RELAXED) != from ||
+                !__atomic_compare_exchange_n(&mark[x], &expect, to, false, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED))
+              continue;
+            out.push_back(x);
+            const uint32_t d = rp[x + 1] - rp[x];
+            if (b == UINT32_MAX || better(d, x, bd, b)) {
+              b = x;
+              bd = d;
+            }
+          }
+        }
+        lbest[w] = b;
+        ldeg[w] = bd;
+      });
+      for (unsigned w = 0; w < nt; ++w) {
+        next.insert(next.end(), local[w].begin(), local[w].end());
+        if (root && lbest[w] != UINT32_MAX && better(ldeg[w], lbest[w], best_deg, best)) {
+          best = lbest[w];
+          best_deg = ldeg[w];
+        }
+      }
+    }
+    if (next.empty()) break;
+    ++ecc;
+    cur.swap(next);
+  }
+  if (root) *root = best;
+  return ecc;
+}
+
+// Undirected graphs: the strongly connected components are the connected components and
+// no arc joins two of them, so the bound below is the largest 2 ecc(r_C) + 1 over the
+// components C (r_C: C's node of largest degree, the first in id order among equals; an
+// isolated node gives 1).  One BFS labels a component and finds r_C, a second measures
+// ecc(r_C).
+uint32_t vd_undirected(uint32_t n, const uint32_t *row, const uint32_t *col) {
+  std::vector<uint32_t> mark(n, 0);  // 0 unseen, 1 labelled, 2 measured
+  BfsScratch sc;
+  uint64_t answer = 0;
+  for (uint32_t v = 0; v < n; ++v) {
+    if (mark[v] != 0) continue;
+    if (row[v + 1] == row[v]) {
+      mark[v] = 2;
+      answer = std::max<uint64_t>(answer, 1);
+      continue;
+    }
+    uint32_t root = v;
+    mark[v] = 1;
+    (void)bfs_levels(row, col, v, mark.data(), 0, 1, &root, sc);
+    mark[root] = 2;
+    const uint32_t ecc = bfs_levels(row, col, root, mark.data(), 1, 2, nullptr, sc);
+    answer = std::max<uint64_t>(answer, 2ull * ecc + 1);
+  }
+  return (uint32_t)std::min<uint64_t>(answer, UINT32_MAX);
+}
+
 // Strongly connected components by Tarjan's algorithm (iterative).  Components are
 // numbered in the order Tarjan completes them, which is a reverse topological order
 // of the condensation: every arc u->x between components has comp[u] > comp[x].
@@ -255,6 +364,11 @@ int vertex_diameter(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32
     return 0;
   }
   // bound over the condensation: weight(C) = ecc_out_C(r) + ecc_in_C(r) + 1
+  if (rrow == row && rcol == col) {  // undirected: the same bound, component by component
+    *vd = vd_undirected(n, row, col);
+    *exact = false;
+    return 0;
+  }
   std::vector<uint32_t> comp;
   const uint32_t nc = tarjan_scc(n, row, col, comp);
   std::vector<uint32_t> root(nc, UINT32_MAX);
