@@ -65,6 +65,9 @@ def test_vertex_diameter_matches_oracle(klib, oracle_lib):
     for g in _graphs():
         for limit in (1e9, 0.0):
             assert kad.vertex_diameter(g, limit) == oracle_lib.vertex_diameter(g, limit), (g.name, limit)
+    # levels of thousands of nodes: the bound's BFS runs them on several threads
+    for g in (gg.chung_lu(200_000, 2.3, 8.0, 11), gg.damaged_grid(300, 300, 0.05, 2)):
+        assert kad.vertex_diameter(g, 0.0) == oracle_lib.vertex_diameter(g, 0.0), g.name
 
 
 def test_f_g_bitwise_equal_to_oracle(klib, oracle_lib):
