@@ -137,6 +137,34 @@ def cpu_baseline(csr, samples, seed):
                       f"same graph ({dt:.1f} s)"}
 
 
+def cpu_baseline_family(csrs, kw, gpu_results, stride=16):
+    """The oracle's whole adaptive runs on every stride-th query of a batch (all host
+    threads, one after another): their sampling rate and time to epsilon, scaled to the
+    whole batch by sampled paths, and whether each result equals the GPU's."""
+    import numpy as np
+    import oracle
+    threads = host_threads()
+    picks = list(range(0, len(csrs), stride))
+    t0 = time.perf_counter()
+    paths, parity = 0, True
+    for i in picks:
+        r = oracle.run(csrs[i], threads=threads, **kw)
+        g = gpu_results[i]
+        paths += r["alpha"] + r["tau"]
+        parity &= bool(r["tau"] == g["tau"] and np.array_equal(r["count"], g["count"])
+                       and np.array_equal(r["lower"], g["lower"])
+                       and np.array_equal(r["upper"], g["upper"]))
+    dt = time.perf_counter() - t0
+    total = sum(r["alpha"] + r["tau"] for r in gpu_results)
+    return {"value": paths / dt, "unit": "sampled shortest paths/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(), "parity": parity,
+            "time_to_epsilon_whole_batch_s_estimate": dt * total / max(paths, 1),
+            "sample": f"the oracle's whole runs of queries {picks[0]}, {picks[0] + stride}, ... "
+                      f"({len(picks)} of {len(csrs)}; {paths} samples, {dt:.1f} s), all host "
+                      "threads, results compared with the GPU's; the whole-batch time is "
+                      "scaled by sampled paths"}
+
+
 def _same_result(a, b):
     import numpy as np
     return (a["tau"] == b["tau"] and a["stop_reason"] == b["stop_reason"]
@@ -249,6 +277,10 @@ def bench_batch(args, torch, gg, kad):
                      "frac": achieved / HBM_PEAK_GBS, "traffic": None,
                      "kernel": "sampler_kernel (multi-segment)"},
     }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline_family(csrs, kw, batch)
+        print(f"[bench] cpu baseline: {out['cpu_baseline']['value']:.0f} paths/s, parity "
+              f"{out['cpu_baseline']['parity']}", file=sys.stderr, flush=True)
     for G in Gs:
         G.close()
     ctx.close()
@@ -451,6 +483,16 @@ def bench_wide(args, torch, gg, kad):
     alg = algorithmic_bytes(tm["arcs"], tm["nodes"], tm["hits"])
     avg_launch_s = tm["seconds"] / max(tm["launches"], 1)
     achieved = alg / max(tm["launches"], 1) / avg_launch_s / 1e9 if avg_launch_s > 0 else 0.0
+    run_info = None
+    if args.grid_run_eps > 0:  # one whole adaptive run (all nodes) on the grid
+        t0 = time.perf_counter()
+        r = kad.run(ctx, G, epsilon=args.grid_run_eps, delta=args.delta, seed=args.seed)
+        run_info = {"epsilon": args.grid_run_eps, "delta": args.delta,
+                    "time_to_epsilon_s": time.perf_counter() - t0, "tau": r["tau"],
+                    "omega": r["omega"], "vd": r["vd"],
+                    "stop": "rule" if r["stop_reason"] else "omega"}
+        print(f"[bench] grid2000 run at epsilon {args.grid_run_eps}: {run_info}", file=sys.stderr,
+              flush=True)
     hbm = measured_traffic("grid2000", "wide_kernel")
     traffic = hbm / avg_launch_s / 1e9 if hbm and avg_launch_s > 0 else None
     out = {
@@ -464,6 +506,7 @@ def bench_wide(args, torch, gg, kad):
         "config": {"workload": f"{WORKLOAD_TEXT['grid2000']}: n={g.n}, {g.arcs} arcs; hit counts "
                                f"of main-phase ids 1000..{1000 + N - 1}, seed {args.seed}"},
         "wide_layout": ctx.wide_info(),
+        "run": run_info,
         "gteps": arcs / step_s / 1e9,
         "per_sample": {"arcs": tm["arcs"] / max(tm["samples"], 1),
                        "nodes": tm["nodes"] / max(tm["samples"], 1)},
@@ -588,6 +631,8 @@ def main():
     ap.add_argument("--exp-samples", type=int, default=1024, help="exponent: samples per graph")
     ap.add_argument("--wide-samples", type=int, default=1000,
                     help="grid2000: samples per call of the wide-count kernel")
+    ap.add_argument("--grid-run-eps", type=float, default=0.02,
+                    help="grid2000: epsilon of one whole run after the timed calls (0: none)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB (scale for HBM counters)")
     args = ap.parse_args()
