@@ -467,8 +467,11 @@ def bench_wide(args, torch, gg, kad):
     G = kad.Graph(ctx, g)
     N = args.wide_samples
     t0 = time.perf_counter()
-    kad.hit_counts(ctx, G, args.seed, 1, 0, 64)  # slots, arenas, vertex diameter
-    print(f"[bench] warm-up 64 samples {time.perf_counter() - t0:.2f} s, layout "
+    # warm-up: the timed call itself (slots, arenas, vertex diameter), so that every wide
+    # dispatch of the run has one shape and a counter pass's mean per dispatch is the
+    # timed launch's
+    kad.hit_counts(ctx, G, args.seed, 1, 1000, N)
+    print(f"[bench] warm-up {N} samples {time.perf_counter() - t0:.2f} s, layout "
           f"{ctx.wide_info()}", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
