@@ -611,6 +611,9 @@ def main():
     ap.add_argument("--check-interval", type=int, default=0)
     ap.add_argument("--exec", default="graph", choices=["graph", "stream", "plain"],
                     help="kad_run launch mode of the timed steps")
+    ap.add_argument("--table", type=int, default=0,
+                    help="sampler slot layout (kad_ctx_set_table): 0 library choice, 1 one "
+                         "record per node, 6..24 hash tables of 2^k records")
     ap.add_argument("--no-modes", action="store_true",
                     help="skip timing the call in every launch mode")
     ap.add_argument("--cpu-samples", type=int, default=150000,
@@ -686,6 +689,8 @@ def main():
     t0 = time.perf_counter()
     ctx = kad.Context(0)
     ctx_create_s = time.perf_counter() - t0
+    if args.table:
+        ctx.set_table(args.table)
     G = kad.Graph(ctx, csr)
     tuned = None
     if args.launch:
@@ -775,6 +780,7 @@ def main():
                      for k in ("setup", "pilot", "delta", "main")},
         "exec": {"mode": args.exec, "chains_recorded": exec_info["records"],
                  "chain_replays": exec_info["replays"]},
+        "slot_layout": ctx.table_info(),
         "sampler": {"note": f"from {timed_steps} further calls with event timing",
                     "launches": tm["launches"], "samples": tm["samples"],
                     "avg_launch_ms": avg_launch_s * 1e3,

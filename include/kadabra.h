@@ -422,6 +422,26 @@ kad_status kad_ctx_set_wide(kad_ctx *ctx, uint32_t slots, uint64_t limbs);
 kad_status kad_ctx_get_wide(kad_ctx *ctx, uint32_t *slots, uint64_t *limbs, uint32_t *slots2,
                             uint64_t *limbs2);
 
+/* Sampler slot layout (section 4's searches keep, per sample, a tag and a 128-bit path
+ * count for every node they reach).  log2_records = 0: the library's choice -- one
+ * record per node of the largest graph seen, unless the memory budget then holds fewer
+ * than 4 slots per CU and the graph has more than 2^16 nodes (about 10^7 nodes and more
+ * at full budget); then a hash table of 2^16 records per slot.  1: always one record per
+ * node.  6 to 24: always tables of 2^log2_records records.  With tables, memory per slot
+ * no longer grows with the graph (32 B, 8 B of lists per record), the wide-count kernel
+ * gets slots of its own with one record per node, and a sample whose reached nodes do
+ * not fit its table (a node that finds no free record within 32 probes) is sampled again
+ * by the wide-count kernel; a sample takes about 0.75x as long to draw with tables where
+ * one record per node also fits.  Results never depend on the layout.  Frees nothing at
+ * once: the slots are laid out again on next use.  KAD_EINVAL for another value;
+ * KAD_EBUSY while the context is in use. */
+kad_status kad_ctx_set_table(kad_ctx *ctx, uint32_t log2_records);
+/* The current layout: log2 of the records per sampler slot (0: one record per node, or no
+ * slots yet), the sampler slots and the slots the wide-count kernel can use (0 before the
+ * first call that samples).  Any pointer may be NULL. */
+kad_status kad_ctx_get_table(kad_ctx *ctx, uint32_t *log2_records, uint32_t *slots,
+                             uint32_t *wide_slots);
+
 /* The launch mode (KAD_EXEC_*; default KAD_EXEC_GRAPH) of kad_run and of the engine
  * (kad_run_batch, the server: KAD_EXEC_GRAPH replays each tick's sampling chain; the other
  * two modes launch it call by call).  While timing is enabled

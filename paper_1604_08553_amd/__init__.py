@@ -126,6 +126,8 @@ def lib():
         "kad_ctx_set_exec": ([vp, u32], st),
         "kad_ctx_set_wide": ([vp, u32, u64], st),
         "kad_ctx_get_wide": ([vp, vp, vp, vp, vp], st),
+        "kad_ctx_set_table": ([vp, u32], st),
+        "kad_ctx_get_table": ([vp, vp, vp, vp], st),
         "kad_ctx_get_exec": ([vp, vp, vp, vp], st),
         "kad_last_error": ([], C.c_char_p),
     }
@@ -209,6 +211,16 @@ class Context:
         b, d = C.c_uint64(), C.c_uint64()
         _check(lib().kad_ctx_get_wide(self.handle, C.byref(a), C.byref(b), C.byref(c), C.byref(d)))
         return {"slots": a.value, "limbs": b.value, "slots2": c.value, "limbs2": d.value}
+
+    def set_table(self, log2_records: int = 0):
+        """Sampler slot layout: 0 = library choice, 1 = one record per node, 6..24 = hash
+        tables of 2^log2_records records per slot; see kad_ctx_set_table."""
+        _check(lib().kad_ctx_set_table(self.handle, log2_records))
+
+    def table_info(self) -> dict:
+        b, s_, w = C.c_uint32(), C.c_uint32(), C.c_uint32()
+        _check(lib().kad_ctx_get_table(self.handle, C.byref(b), C.byref(s_), C.byref(w)))
+        return {"log2_records": b.value, "slots": s_.value, "wide_slots": w.value}
 
     def exec_info(self) -> dict:
         m, rec, rep = C.c_uint32(), C.c_uint64(), C.c_uint64()

@@ -34,7 +34,9 @@ struct GraphDev {
 // n node records of REC_WORDS words -- tag, wide-count position, 128-bit path count
 // (low, high) -- all zero between samples, an n-entry list of the nodes reached (the
 // frontiers are contiguous segments of it) and a candidate-edge buffer of pi_cap
-// entries.
+// entries.  With hbits > 0 (sampler slots only) the n = 2^hbits records of a slot are a
+// hash table keyed by node id (word 1 holds id + 1 instead of the wide-count position)
+// and vh[j] is the record index of the reached node visit[j].
 constexpr uint32_t REC_WORDS = 8;
 struct SlotState {
   uint32_t slots;
@@ -43,6 +45,8 @@ struct SlotState {
   uint32_t *rec;       // [slots * n * REC_WORDS]
   uint32_t *visit;     // [slots * n]
   uint64_t *pi;        // [slots * pi_cap]
+  uint32_t hbits = 0;  // 0: record v at index v; else log2 of the table size (= n)
+  uint32_t *vh = nullptr;  // hashed: [slots * n]
 };
 
 // One segment of a multi-query launch: sample ids [first, first + count) of
@@ -243,7 +247,8 @@ constexpr int NOALLOC_MAX_DEVICES = 64;
 hipError_t noalloc_scratch(void **ptr);
 
 // Sampler workgroups of `block` threads resident per CU (occupancy query).
-int sampler_blocks_per_cu(int block);
+// Resident sampler workgroups per CU for a workgroup size and slot layout (tables or not).
+int sampler_blocks_per_cu(int block, bool tables);
 // Wide-count workgroups resident per CU (occupancy query).
 int wide_blocks_per_cu();
 

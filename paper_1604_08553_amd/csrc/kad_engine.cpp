@@ -302,12 +302,15 @@ kad_status Engine::init() {
 }
 
 // Lane 1 takes 3/4 of the wide-count slots; lane 0 keeps the rest of them for its
-// overflowed samples and the sampler slots past all of them.  Without enough slots,
-// lane 0 alone serves everything.
+// overflowed samples and the sampler slots past all of them (all of them when the
+// wide-count kernel has slots of its own).  Without enough slots, lane 0 alone serves
+// everything.
 void Engine::layout() {
-  const uint32_t W = ctx_->w_slots ? std::min(ctx_->w_slots, ctx_->slots) : 0, S = ctx_->slots;
+  const uint32_t W = ctx_->w_slots ? std::min(ctx_->w_slots, wide_slot_count(ctx_)) : 0,
+                 S = ctx_->slots;
+  const uint32_t skip = ctx_->slot_hbits ? 0u : W;  // sampler slots the wide passes use
   Lane &a = lanes_[0], &b = lanes_[1];
-  split_ = W >= 4 && S >= W + 64;
+  split_ = W >= 4 && S >= skip + 64;
   if (split_) {
     b.wslot0 = 0;
     b.nwslots = W * 3 / 4;
@@ -315,8 +318,8 @@ void Engine::layout() {
     b.nslots = 0;
     a.wslot0 = b.nwslots;
     a.nwslots = W - b.nwslots;
-    a.slot0 = W;
-    a.nslots = S - W;
+    a.slot0 = skip;
+    a.nslots = S - skip;
   } else {
     a.wslot0 = 0;
     a.nwslots = W;
@@ -327,11 +330,7 @@ void Engine::layout() {
 }
 
 SlotState Engine::lane_slots(const Lane &L, bool wide) const {
-  SlotState st = slot_view(ctx_);
-  const size_t off = wide ? L.wslot0 : L.slot0, n = st.n;
-  st.rec += off * n * REC_WORDS;
-  st.visit += off * n;
-  st.pi += off * (size_t)st.pi_cap;
+  SlotState st = wide ? wide_slot_view(ctx_, L.wslot0) : slot_view(ctx_, L.slot0);
   st.slots = wide ? L.nwslots : L.nslots;
   return st;
 }
@@ -690,7 +689,7 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   if (L.nwslots == 0) return fail(KAD_ENOMEM, "no wide-count slots for this launch");
   int per_cu = 1;
   for (int j = 0; j < 3; ++j)
-    if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx_->blocks_per_cu[j];
+    if (SAMPLER_BLOCKS[j] == shape.block) per_cu = sampler_per_cu(ctx_, shape.block);
   const uint32_t resident =
       (uint32_t)std::min<uint64_t>(L.nslots, (uint64_t)ctx_->cus * per_cu);
   // While lane 0 has work, the wide lane's launches take at most a quarter of the CUs: a

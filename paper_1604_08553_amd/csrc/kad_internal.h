@@ -83,6 +83,19 @@ constexpr uint32_t WORK_WORDS = 5;
 // unless the graph's worst case is smaller.
 constexpr uint64_t WIDE_TIER1_LIMBS = 1ull << 25;
 constexpr uint64_t WIDE_MAX_LIMBS = 1ull << 27;
+// Sampler slot tables (kad_ctx_set_table): the sizes a caller may ask for, and the size the
+// library takes when one record per node would leave fewer than TABLE_AUTO_PER_CU slots
+// per CU.  A sample runs about 0.75x as fast with tables (probes, fewer resident
+// workgroups), and below about four samples in flight per CU the dense layout loses more
+// than that.  2^16 records hold the nodes one sample reaches before the two searches
+// meet on the large power-law workloads (their largest sample over 10^5 draws reaches
+// about 6K on a 10^6-node undirected graph, 21K on a 4*10^6-node directed one) with
+// the table at most a third full.
+constexpr uint32_t TABLE_MIN_BITS = 6, TABLE_MAX_BITS = 24, TABLE_AUTO_BITS = 16;
+constexpr uint32_t TABLE_AUTO_PER_CU = 4;
+// The wide-count kernel's own slots when the sampler's are tables: at most this share
+// of the slot memory.
+constexpr double WIDE_POOL_SHARE = 1.0 / 3.0;
 
 // Device outputs of one sampler launch, with pinned host mirrors of the small ones.
 struct OutSet {
@@ -152,7 +165,7 @@ struct ChainKey {
     return *this << g.n << g.arcs << g.row << g.col << g.rrow << g.rcol << g.forward;
   }
   ChainKey &operator<<(const SlotState &t) {
-    return *this << t.slots << t.n << t.pi_cap << t.rec << t.visit << t.pi;
+    return *this << t.slots << t.n << t.pi_cap << t.rec << t.visit << t.pi << t.hbits << t.vh;
   }
   ChainKey &operator<<(const WideState &w) {
     return *this << w.slots << w.max_lev << w.arena_limbs << w.arena << w.lv << w.lbase;
@@ -177,13 +190,24 @@ struct kad_ctx {
   uint64_t used_graphs = 0;
   uint32_t cus = 0;
   int blocks_per_cu[3] = {1, 1, 1};  // resident sampler workgroups per CU, per SAMPLER_BLOCKS
+  int blocks_per_cu_tab[3] = {1, 1, 1};  // the same with slot tables
   int wide_per_cu = 1;               // resident wide-count workgroups per CU
   std::atomic<bool> busy{false};  // one user at a time (a call, or a server's engine)
-  // per-slot working state
+  // per-slot working state.  slot_hbits = 0: every slot holds one record per node of the
+  // largest graph seen (slot_n), and the wide-count kernel uses the first sampler slots.
+  // slot_hbits > 0: sampler slots hold tables of 2^slot_hbits records whatever the graph
+  // (SlotState::hbits); the wide-count kernel then has wpool slots of its own with one
+  // record per node (slot_n = their node capacity).
   uint32_t slot_n = 0, slots = 0;
   uint64_t slot_bytes = 0;
   kad::DevBuf<uint32_t> rec, visit;  // node records (REC_WORDS words each), reached lists
   kad::DevBuf<uint64_t> pi;
+  uint32_t slot_hbits = 0;
+  uint32_t table_knob = 0;  // kad_ctx_set_table: 0 the library's choice, 1 dense, else log2 size
+  kad::DevBuf<uint32_t> vh;  // tables: the record index of each reached-list entry
+  uint32_t wpool = 0;
+  kad::DevBuf<uint32_t> wrec, wvisit;
+  kad::DevBuf<uint64_t> wpi;
   // wide-count resampling (kad::WideState): samples whose counts pass 128 bits or whose
   // candidate edges outgrow a slot.  w_big: the arena sized for wide counts (graphs whose
   // counts can pass 128 bits), else for the candidate edges of 128-bit graphs only.
@@ -315,6 +339,12 @@ kad_status graph_vd(kad_graph *g, uint32_t *vd, bool *exact);
 // Slot state for graphs of up to n nodes (reallocates, and synchronises, when it grows).
 kad_status ensure_slots(kad_ctx *ctx, uint32_t n);
 SlotState slot_view(const kad_ctx *ctx, uint32_t slot0 = 0);
+// The dense slots the wide-count kernel runs on: the sampler slots, or with slot tables
+// the wide-count pool.
+SlotState wide_slot_view(const kad_ctx *ctx, uint32_t slot0 = 0);
+uint32_t wide_slot_count(const kad_ctx *ctx);
+// Resident sampler workgroups per CU of this workgroup size in the context's slot layout.
+int sampler_per_cu(const kad_ctx *ctx, int block);
 WideState wide_view(const kad_ctx *ctx);
 // The second wide pass's view of the same arena (slots 0 when there is none).
 WideState wide_view2(const kad_ctx *ctx);
@@ -333,7 +363,9 @@ bool wide_fits(const kad_ctx *ctx, const kad_graph *g, int ovc);
 // `out`: the samples of its fix list (list, *list_count), or with `all` every sample (no
 // sampler launch before); work: 3 counters, zero at launch.  With large arenas in two
 // passes, list2 (room for count entries) carries the samples the first pass leaves to the
-// second.  segs == nullptr: single graph g.  bd: as in launch_wide_fix.
+// second.  segs == nullptr: single graph g.  bd: as in launch_wide_fix.  slot0: the first
+// sampler slot it may use (one record per node); with slot tables the passes take the
+// wide-count pool from its first slot.
 kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t phase,
                        uint64_t first, const SampleSeg *segs, uint32_t nseg, uint32_t count,
                        bool all, const uint32_t *list, const uint32_t *list_count,

@@ -214,6 +214,76 @@ __device__ __forceinline__ uint64_t add_u64(uint64_t *p, uint64_t x) {
   return __hip_atomic_fetch_add(p, x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
 }
 
+// ------------------------------------------------------------------ slot tables
+// A sampler slot keeps its records in one of two layouts (SlotState::hbits):
+//   dense  -- node v's record at index v, one record per node of the graph;
+//   hashed -- a table of 2^hbits records.  Node v sits at the first index of
+//             home(v), home(v) + 1, ... (mod the table size) whose word 1 holds v + 1,
+//             at most MAX_PROBE steps from home(v).  One 64-bit compare-and-swap on
+//             words 0-1 (tag, key) places a node and claims it at once.  A node that
+//             cannot be placed within MAX_PROBE steps gives its sample FLAG_CAPACITY:
+//             the wide-count kernel, whose records are dense, samples it again.  So a
+//             lookup that meets neither its key nor an empty record within MAX_PROBE
+//             steps knows the node has no record.
+// Entries are never removed while a sample runs; its reset clears every record it placed
+// (the reached list keeps each node's index beside its id).
+constexpr uint32_t MAX_PROBE = 32;
+constexpr uint32_t NO_REC = 0xFFFFFFFFu;
+
+struct Recs {
+  uint32_t *rec;
+  uint32_t hbits;  // hashed layouts only: log2 of the table size
+  __device__ __forceinline__ uint32_t home(uint32_t v) const {
+    return (v * 2654435761u) >> (32 - hbits);
+  }
+  __device__ __forceinline__ uint32_t mask() const { return (1u << hbits) - 1u; }
+  __device__ __forceinline__ uint64_t *word(uint32_t idx) const {
+    return reinterpret_cast<uint64_t *>(rec + (size_t)REC_WORDS * idx);
+  }
+};
+__device__ __forceinline__ uint64_t rec_word(uint32_t v, uint32_t tag) {
+  return ((uint64_t)(v + 1u) << 32) | tag;
+}
+__device__ __forceinline__ uint64_t ld_word(const uint64_t *p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+__device__ __forceinline__ uint64_t cas_word(uint64_t *p, uint64_t expect, uint64_t want) {
+  __hip_atomic_compare_exchange_strong(p, &expect, want, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+  return expect;  // the word found (0 on success)
+}
+// v's word and index (0 and NO_REC: no record).
+__device__ __forceinline__ uint64_t rec_find(const Recs &R, uint32_t v, uint32_t &h) {
+  const uint32_t key = v + 1u, m = R.mask();
+  h = R.home(v);
+  for (uint32_t p = 0; p < MAX_PROBE; ++p, h = (h + 1u) & m) {
+    const uint64_t x = ld_word(R.word(h));
+    const uint32_t k = (uint32_t)(x >> 32);
+    if (k == key) return x;
+    if (k == 0) break;
+  }
+  h = NO_REC;
+  return 0;
+}
+// Record index of node v in a table (NO_REC: none).  Out of line: its probe loop, inlined
+// into the 128-bit arithmetic of the callers, would take their registers.
+__device__ __noinline__ uint32_t rec_index(uint32_t *rec, uint32_t hbits, uint32_t v) {
+  uint32_t h;
+  (void)rec_find(Recs{rec, hbits}, v, h);
+  return h;
+}
+// The 128-bit count of node v, which has a record (zero, and FLAG_CAPACITY in fl, if not).
+template <bool HASHED>
+__device__ __forceinline__ u128 node_sig(const Recs &R, uint32_t v, uint32_t &fl) {
+  if (!HASHED) return ld_sig(R.rec, v);
+  const uint32_t h = rec_index(R.rec, R.hbits, v);
+  if (h == NO_REC) {
+    fl |= FLAG_CAPACITY;
+    return u128{0, 0};
+  }
+  return ld_sig(R.rec, h);
+}
+
 __device__ __forceinline__ uint32_t filter_bit(uint32_t w) {
   return (w * 2654435761u) >> (32 - FILTER_LOG2);
 }
@@ -449,18 +519,22 @@ enum class Scan { Touch, Discover, Both };
 // Short rows take the chunk slots from the front, long rows from the back, and below
 // them (touch scans only) the long rows that are searched for the other frontier's om
 // nodes visit[ob, ob + om) rather than read (touch_by_search).
-template <int BLOCK, Scan MODE>
+// HASHED: the slot's records form a table of 2^hbits (see Recs); vh[j] is the record
+// index of visit[j].
+template <int BLOCK, Scan MODE, bool HASHED>
 __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, uint32_t me,
                                               uint32_t fb, uint32_t fe, uint32_t *rec,
-                                              uint32_t *visit, uint64_t *gpi,
-                                              uint32_t pi_cap, uint32_t other_tag,
-                                              uint32_t next_tag, bool &ovf, uint32_t &wk,
-                                              bool exact, bool first, uint32_t ob = 0,
-                                              uint32_t om = 0) {
+                                              uint32_t hbits, uint32_t *visit, uint32_t *vh,
+                                              uint64_t *gpi, uint32_t pi_cap,
+                                              uint32_t other_tag, uint32_t next_tag,
+                                              bool &ovf, uint32_t &wk, bool exact, bool first,
+                                              uint32_t ob = 0, uint32_t om = 0) {
+  const Recs R{rec, hbits};
   constexpr int CHUNK = 2 * BLOCK;
   // arcs per lane per window or piece: a window costs a few dependent round trips
   // whatever its size; wider touch windows than 8 run out of registers
-  constexpr int U = MODE == Scan::Touch ? 8 : (MODE == Scan::Discover ? 4 : 2);
+  // (hashed records: four, the probes' indices and words take the registers)
+  constexpr int U = MODE == Scan::Touch ? (HASHED ? 4 : 8) : (MODE == Scan::Discover ? 4 : 2);
   constexpr uint32_t WIN = BLOCK * U;
   constexpr uint32_t PIECE = WAVE * U;
   constexpr uint32_t NWAVES = BLOCK / WAVE;
@@ -495,6 +569,34 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
 #pragma unroll
         for (int q = 0; q < U; ++q)
           if ((pass >> q) & 1u) hitm |= fset_has<4 * CHUNK>(L.fset, ww[q]) ? 1u << q : 0u;
+      } else if (HASHED) {
+        // every round of probes goes out together: first the home records, then the next
+        // record of each arc whose probe met another node (rare at the tables' fill)
+        uint64_t x[U];
+        uint32_t h[U], open = pass;  // open bit q: arc q not yet resolved
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          h[q] = R.home(ww[q]);
+          x[q] = (open >> q) & 1u ? ld_word(R.word(h[q])) : 0ull;
+        }
+        for (uint32_t p = 0;; ++p) {
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            const uint32_t k = (uint32_t)(x[q] >> 32);
+            if (k == 0 || k == ww[q] + 1u) open &= ~(1u << q);
+          }
+          if (open == 0 || p + 1 == MAX_PROBE) break;
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            if ((open >> q) & 1u) {
+              h[q] = (h[q] + 1u) & R.mask();
+              x[q] = ld_word(R.word(h[q]));
+            }
+          }
+        }
+#pragma unroll
+        for (int q = 0; q < U; ++q)
+          hitm |= (uint32_t)(x[q] >> 32) == ww[q] + 1u && (uint32_t)x[q] == other_tag ? 1u << q : 0u;
       } else {
         uint32_t tg[U];
 #pragma unroll
@@ -521,14 +623,52 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
       // Claims: one compare-and-swap per arc returns the head's tag as it was (0 if
       // unseen, then this arc claimed it; next_tag if another arc of this level did;
       // other_tag if the head is in the other side's frontier).
-      uint32_t tg[U], dm = 0;  // dm bit q: this lane's arc of group q claimed its head
+      // HASHED: the claim places the head in the table (at[q]: its record index); the
+      // home probes of all arcs go out together, a probe that meets another node
+      // continues alone, and a head that finds no room within MAX_PROBE steps leaves the
+      // sample to the wide-count kernel
+      uint32_t tg[U], at[U], dm = 0;  // dm bit q: this lane's arc of group q claimed its head
+      if (HASHED) {
+        // every round of compare-and-swaps goes out together: first at the home records,
+        // then at the next record of each head whose attempt met another node
+        uint64_t x[U];
+        uint32_t open = vm;  // open bit q: head q neither placed nor found yet
 #pragma unroll
-      for (int q = 0; q < U; ++q) {
-        tg[q] = 0;
-        if ((vm >> q) & 1u) {
-          const uint32_t old = cas_tag(tag_of(rec, ww[q]), 0u, next_tag);
-          dm |= old == 0 ? 1u << q : 0u;
-          tg[q] = old == 0 ? next_tag : old;
+        for (int q = 0; q < U; ++q) {
+          at[q] = R.home(ww[q]);
+          x[q] = (open >> q) & 1u ? cas_word(R.word(at[q]), 0, rec_word(ww[q], next_tag)) : 0ull;
+        }
+        for (uint32_t p = 0;; ++p) {
+#pragma unroll
+          for (int q = 0; q < U; ++q)
+            if (x[q] == 0 || (uint32_t)(x[q] >> 32) == ww[q] + 1u) open &= ~(1u << q);
+          if (open == 0 || p + 1 == MAX_PROBE) break;
+#pragma unroll
+          for (int q = 0; q < U; ++q) {
+            if ((open >> q) & 1u) {
+              at[q] = (at[q] + 1u) & R.mask();
+              x[q] = cas_word(R.word(at[q]), 0, rec_word(ww[q], next_tag));
+            }
+          }
+        }
+        if (open) atomicOr(&L.flags, FLAG_CAPACITY);  // no room within MAX_PROBE records
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          tg[q] = 0;
+          if (((vm & ~open) >> q) & 1u) {
+            dm |= x[q] == 0 ? 1u << q : 0u;
+            tg[q] = x[q] == 0 ? next_tag : (uint32_t)x[q];
+          }
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < U; ++q) {
+          tg[q] = 0;
+          if ((vm >> q) & 1u) {
+            const uint32_t old = cas_tag(tag_of(rec, ww[q]), 0u, next_tag);
+            dm |= old == 0 ? 1u << q : 0u;
+            tg[q] = old == 0 ? next_tag : old;
+          }
         }
       }
       // sigma(w) += sigma(u) on the low words, the appends of the claimed heads and
@@ -538,7 +678,8 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
 #pragma unroll
       for (int q = 0; q < U; ++q) {
         old_lo[q] = 0;
-        if (tg[q] == next_tag) old_lo[q] = add_u64(sig_of(rec, ww[q]), L.c_sig_lo[owner(q)]);
+        if (tg[q] == next_tag)
+          old_lo[q] = add_u64(sig_of(rec, HASHED ? at[q] : ww[q]), L.c_sig_lo[owner(q)]);
       }
       if (MODE == Scan::Both) {
 #pragma unroll
@@ -560,7 +701,10 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
         const bool disc = (dm >> q) & 1u;
         uint32_t rank = 0;
         const uint32_t base = wave_reserve(disc, &L.nvis, rank);
-        if (disc) visit[base + rank] = ww[q];
+        if (disc) {
+          visit[base + rank] = ww[q];
+          if (HASHED) vh[base + rank] = at[q];
+        }
       }
       if (__ballot(dm != 0)) {  // uniform: some lane of this wave discovered a node
         uint64_t dg = 0;
@@ -578,7 +722,7 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
           const uint64_t add = xhi + ((old_lo[q] + xlo < old_lo[q]) ? 1u : 0u);
           ovf |= add < xhi;
           if (add != 0) {
-            const uint64_t oh = add_u64(sig_of(rec, ww[q]) + 1, add);
+            const uint64_t oh = add_u64(sig_of(rec, HASHED ? at[q] : ww[q]) + 1, add);
             ovf |= oh + add < oh;
           }
         }
@@ -606,7 +750,7 @@ __device__ __forceinline__ void scan_frontier(Lds<BLOCK> &L, const GraphDev &g, 
           u[q] = visit[cb + j];
           st[q] = rp[u[q]];
           d[q] = rp[u[q] + 1] - st[q];
-          if (MODE != Scan::Touch) su[q] = ld_sig(rec, u[q]);
+          if (MODE != Scan::Touch) su[q] = ld_sig(rec, HASHED ? vh[cb + j] : u[q]);
         }
       }
     }
@@ -857,8 +1001,11 @@ constexpr uint32_t pow2floor(uint32_t x) { return x <= 1 ? 1u : 2u * pow2floor(x
 //                entries found in x's row by binary search; prefix sums are then
 //                taken in ascending id.  Used when the list is much shorter than the
 //                row (x a hub).
+// HASHED: records in a table of 2^hbits (see Recs), vh[j] the record index of visit[j].
+template <bool HASHED>
 __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint32_t lev,
-                          const uint32_t *rec, const uint32_t *visit,
+                          uint32_t *rec, uint32_t hbits, const uint32_t *visit,
+                          const uint32_t *vh,
                           const uint32_t (*seg_lo)[MAXLEV], const uint32_t (*seg_hi)[MAXLEV],
                           MatchScratch &M, uint64_t seed, uint64_t i, uint32_t phase,
                           uint32_t *path, uint32_t ls, uint32_t base, uint32_t endpoint,
@@ -867,6 +1014,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
   const uint32_t *rp = side == 0 ? g.rrow : g.row;
   const uint32_t *cl = side == 0 ? g.rcol : g.col;
   const uint64_t lanes_below = (1ULL << lane) - 1ULL;
+  const Recs R{rec, hbits};
   uint32_t x = start;
   for (uint32_t j = lev; j >= 1; --j) {
     // A level of one node holds x's only predecessor, whatever the draw (the draw is
@@ -878,7 +1026,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
       continue;
     }
     const uint32_t beg = rp[x], end = rp[x + 1];  // in flight during the draw
-    const u128 bound = ld_sig(rec, x);
+    const u128 bound = node_sig<HASHED>(R, x, flags);
     const u128 r = uniform_below(bound, seed, i, stream_word(phase, side == 0 ? P_BACK_S : P_BACK_T, j),
                                  flags);
     const uint32_t want = (side == 0 ? 0u : TAG_T) | j;  // level j-1, stored as (j-1)+1
@@ -916,7 +1064,7 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
           if (match) {
             const uint32_t pos = nm + (uint32_t)__popcll(mk & lanes_below);
             if (pos < (uint32_t)MATCH_CAP) {
-              const u128 sv = ld_sig(rec, cand);
+              const u128 sv = ld_sig(rec, HASHED ? vh[q] : cand);
               M.id[pos] = cand;
               M.lo[pos] = sv.lo;
               M.hi[pos] = sv.hi;
@@ -953,7 +1101,13 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
         u128 val{0, 0};
         if (idx < end) {
           u = cl[idx];
-          if (ld_tag(tag_of(rec, u)) == want) val = ld_sig(rec, u);
+          if (HASHED) {
+            uint32_t h;
+            const uint64_t xw = rec_find(R, u, h);
+            if (h != NO_REC && (uint32_t)xw == want) val = ld_sig(rec, h);
+          } else if (ld_tag(tag_of(rec, u)) == want) {
+            val = ld_sig(rec, u);
+          }
         }
         bool dummy = false;
         u128 inc = wave_incl_u128(val, dummy);
@@ -981,10 +1135,13 @@ __device__ void backtrack(const GraphDev &g, uint32_t side, uint32_t start, uint
 // begin <= k; graph, seed, phase and id come from there.
 // A level expansion of at most small_exp arcs takes one combined scan; larger ones
 // take a touch scan and, if the searches did not meet, a discovery scan.
+// HASHED: the slots' records are tables of 2^st.hbits (see Recs) instead of one record
+// per node.
 // Occupancy targets: 5 waves per SIMD (VGPR-bound) for 128 and 256 threads; 64-thread
-// workgroups are LDS-bound at 4.
-template <int BLOCK, bool MULTI>
-__global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(GraphDev g0, SlotState st, uint64_t seed_a,
+// workgroups are LDS-bound at 4.  With tables 4: the probes' state takes the registers
+// that a fifth wave would leave (it would spill).
+template <int BLOCK, bool MULTI, bool HASHED>
+__global__ __launch_bounds__(BLOCK, (BLOCK == 64 || HASHED) ? 4 : 5) void sampler_kernel(GraphDev g0, SlotState st, uint64_t seed_a,
                                                         uint32_t phase_a, uint64_t first_a,
                                                         const SampleSeg *__restrict__ segs,
                                                         uint32_t nseg_a, uint32_t count_a,
@@ -1004,7 +1161,10 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
   const size_t slot = blockIdx.x;
   uint32_t *rec = st.rec + slot * n * REC_WORDS;
   uint32_t *visit = st.visit + slot * n;
+  uint32_t *vh = HASHED ? st.vh + slot * n : nullptr;
   uint64_t *gpi = st.pi + slot * st.pi_cap;
+  const uint32_t hbits = HASHED ? st.hbits : 0u;
+  const Recs R{rec, hbits};
 
   for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
   for (uint32_t j = tid; j < 3u * Lds<BLOCK>::MASK_WORDS; j += BLOCK) (&L.wmask[0][0])[j] = 0;
@@ -1080,12 +1240,21 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
       const uint32_t t = tp + (tp >= s ? 1u : 0u);
       L.s = s;
       L.t = t;
-      *tag_of(rec, s) = 1u;
-      *tag_of(rec, t) = TAG_T | 1u;
-      sig_of(rec, s)[0] = 1;
-      sig_of(rec, s)[1] = 0;
-      sig_of(rec, t)[0] = 1;
-      sig_of(rec, t)[1] = 0;
+      // the table is empty: s takes its home record, t its own or the next one
+      const uint32_t hs = HASHED ? R.home(s) : s;
+      const uint32_t ht = HASHED ? (R.home(t) == hs ? (hs + 1u) & R.mask() : R.home(t)) : t;
+      *tag_of(rec, hs) = 1u;
+      *tag_of(rec, ht) = TAG_T | 1u;
+      if (HASHED) {
+        *pos_of(rec, hs) = s + 1u;
+        *pos_of(rec, ht) = t + 1u;
+        vh[0] = hs;
+        vh[1] = ht;
+      }
+      sig_of(rec, hs)[0] = 1;
+      sig_of(rec, hs)[1] = 0;
+      sig_of(rec, ht)[0] = 1;
+      sig_of(rec, ht)[1] = 0;
       visit[0] = s;
       visit[1] = t;
       L.fb[0] = 0; L.fe[0] = 1;
@@ -1110,6 +1279,8 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
     bool met = false;
     uint32_t needed = 0;
     for (;;) {
+      // a head found no room in the table: the wide-count kernel samples this pair
+      if (HASHED && (L.flags & FLAG_CAPACITY)) break;
       // ties expand the s side; the forward search expands it always
       const uint32_t me = (g.forward || L.deg[0] <= L.deg[1]) ? 0u : 1u;
       const uint32_t ot = 1u - me;
@@ -1133,8 +1304,9 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
         // claims are never read if the two searches touched; they are reset anyway)
         __syncthreads();
         bool ovf_next = false;  // counts of the next level matter only if there is one
-        scan_frontier<BLOCK, Scan::Both>(L, g, me, fb, fe, rec, visit, gpi, st.pi_cap, other_tag,
-                                  next_tag, ovf_next, wk, false, lme == 0);
+        scan_frontier<BLOCK, Scan::Both, HASHED>(L, g, me, fb, fe, rec, hbits, visit, vh, gpi,
+                                                 st.pi_cap, other_tag, next_tag, ovf_next, wk,
+                                                 false, lme == 0);
         if (L.pi_count > 0) {
           met = true;
           break;
@@ -1155,16 +1327,18 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           if (exact) fset_insert<FSET_SLOTS>(L.fset, v);
         }
         __syncthreads();
-        scan_frontier<BLOCK, Scan::Touch>(L, g, me, fb, fe, rec, visit, gpi, st.pi_cap, other_tag,
-                                   next_tag, ovf, wk, exact, lme == 0, ob, oe - ob);
+        scan_frontier<BLOCK, Scan::Touch, HASHED>(L, g, me, fb, fe, rec, hbits, visit, vh, gpi,
+                                                  st.pi_cap, other_tag, next_tag, ovf, wk, exact,
+                                                  lme == 0, ob, oe - ob);
         for (uint32_t j = tid; j < (uint32_t)FILTER_WORDS; j += BLOCK) L.filter[j] = 0;
         const uint32_t P = L.pi_count;  // final: the scan ends with a barrier
         if (P > 0) {
           met = true;
           break;
         }
-        scan_frontier<BLOCK, Scan::Discover>(L, g, me, fb, fe, rec, visit, gpi, st.pi_cap,
-                                      other_tag, next_tag, ovf, wk, false, lme == 0);
+        scan_frontier<BLOCK, Scan::Discover, HASHED>(L, g, me, fb, fe, rec, hbits, visit, vh,
+                                                     gpi, st.pi_cap, other_tag, next_tag, ovf,
+                                                     wk, false, lme == 0);
       }
       // final: every scan ends with a barrier; tid 0 writes other fields below
       const uint32_t ne = L.nvis;
@@ -1208,7 +1382,14 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           u128 wt{0, 0};
           if (tid < P) {
             key = L.pi[tid];
-            wt = mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), wov);
+            if (HASHED) {
+              uint32_t nfl = 0;  // an endpoint without a record (never, for consistent tables)
+              wt = mul128(node_sig<true>(R, (uint32_t)(key >> 32), nfl),
+                          node_sig<true>(R, (uint32_t)key, nfl), wov);
+              if (nfl) atomicOr(&L.flags, nfl);
+            } else {
+              wt = mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), wov);
+            }
             L.c_sig_lo[tid] = wt.lo;
             L.c_sig_hi[tid] = wt.hi;
           }
@@ -1269,9 +1450,19 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           };
           bool wov = false;
           u128 acc{0, 0};
-          for (uint32_t j = tid; j < P; j += BLOCK) {
-            const uint64_t key = key_at(j);
-            acc = add128(acc, mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), wov), wov);
+          if (HASHED) {
+            uint32_t nfl = 0;  // an endpoint without a record (never, for consistent tables)
+            for (uint32_t j = tid; j < P; j += BLOCK) {
+              const uint64_t key = key_at(j);
+              acc = add128(acc, mul128(node_sig<true>(R, (uint32_t)(key >> 32), nfl),
+                                       node_sig<true>(R, (uint32_t)key, nfl), wov), wov);
+            }
+            if (nfl) atomicOr(&L.flags, nfl);
+          } else {
+            for (uint32_t j = tid; j < P; j += BLOCK) {
+              const uint64_t key = key_at(j);
+              acc = add128(acc, mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), wov), wov);
+            }
           }
           u128 total;
           (void)block_incl_u128(L, acc, total, wov);
@@ -1301,7 +1492,13 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
               uint64_t key = 0;
               if (j < P) {
                 key = key_at(j);
-                wt = mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), dm);
+                if (HASHED) {
+                  uint32_t nfl = 0;  // checked by the first pass over the same keys
+                  wt = mul128(node_sig<true>(R, (uint32_t)(key >> 32), nfl),
+                              node_sig<true>(R, (uint32_t)key, nfl), dm);
+                } else {
+                  wt = mul128(ld_sig(rec, (uint32_t)(key >> 32)), ld_sig(rec, (uint32_t)key), dm);
+                }
               }
               u128 chunk_total;
               u128 inc = block_incl_u128(L, wt, chunk_total, dm);
@@ -1329,13 +1526,13 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
           MatchScratch *mscr = reinterpret_cast<MatchScratch *>(L.pi);
           if (wid == 0) {
             if (lane == 0) path[ls] = v + base;
-            backtrack(g, 0, v, ls, rec, visit, L.seg_lo, L.seg_hi, mscr[0], seed, i,
-                      phase, path, ls, base, L.s, fl);
+            backtrack<HASHED>(g, 0, v, ls, rec, hbits, visit, vh, L.seg_lo, L.seg_hi, mscr[0],
+                              seed, i, phase, path, ls, base, L.s, fl);
           }
           if (wid == (NWAVES >= 2 ? 1u : 0u)) {
             if (lane == 0) path[ls + 1] = w + base;
-            backtrack(g, 1, w, lt, rec, visit, L.seg_lo, L.seg_hi, mscr[1], seed, i,
-                      phase, path, ls, base, L.t, fl);
+            backtrack<HASHED>(g, 1, w, lt, rec, hbits, visit, vh, L.seg_lo, L.seg_hi, mscr[1],
+                              seed, i, phase, path, ls, base, L.t, fl);
           }
           if (win >= P) fl |= FLAG_CAPACITY;
           if (fl && lane == 0) atomicOr(&L.flags, fl);
@@ -1360,7 +1557,7 @@ __global__ __launch_bounds__(BLOCK, BLOCK == 64 ? 4 : 5) void sampler_kernel(Gra
     // ---- restore the slot's all-zero state for the next sample
     const uint32_t nv = L.nvis;
     for (uint32_t j = tid; j < nv; j += BLOCK) {
-      uint4 *r4 = reinterpret_cast<uint4 *>(tag_of(rec, visit[j]));
+      uint4 *r4 = reinterpret_cast<uint4 *>(tag_of(rec, HASHED ? vh[j] : visit[j]));
       r4[0] = make_uint4(0, 0, 0, 0);  // tag, position, count low
       r4[1] = make_uint4(0, 0, 0, 0);  // count high (and the unused words)
     }
@@ -2466,24 +2663,24 @@ static __device__ __align__(256) uint64_t scratch[NOALLOC_SCRATCH_BYTES / 8];
 
 }  // namespace
 
-template <bool MULTI>
-hipError_t launch_sampler_variant(int block, uint32_t grid, hipStream_t stream, const GraphDev &g,
-                                  const SlotState &st, uint64_t seed, uint32_t phase,
-                                  uint64_t first, const SampleSeg *segs, uint32_t nseg,
-                                  uint32_t count, uint32_t *work, const SampleOut &out,
-                                  uint32_t small_exp, const BatchDesc *bd) {
+template <bool MULTI, bool HASHED>
+hipError_t launch_sampler_shape(int block, uint32_t grid, hipStream_t stream, const GraphDev &g,
+                                const SlotState &st, uint64_t seed, uint32_t phase,
+                                uint64_t first, const SampleSeg *segs, uint32_t nseg,
+                                uint32_t count, uint32_t *work, const SampleOut &out,
+                                uint32_t small_exp, const BatchDesc *bd) {
   switch (block) {
     case 64:
-      hipLaunchKernelGGL((sampler_kernel<64, MULTI>), dim3(grid), dim3(64), 0, stream, g, st,
-                         seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
+      hipLaunchKernelGGL((sampler_kernel<64, MULTI, HASHED>), dim3(grid), dim3(64), 0, stream, g,
+                         st, seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
       break;
     case 128:
-      hipLaunchKernelGGL((sampler_kernel<128, MULTI>), dim3(grid), dim3(128), 0, stream, g, st,
-                         seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
+      hipLaunchKernelGGL((sampler_kernel<128, MULTI, HASHED>), dim3(grid), dim3(128), 0, stream,
+                         g, st, seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
       break;
     case 256:
-      hipLaunchKernelGGL((sampler_kernel<256, MULTI>), dim3(grid), dim3(256), 0, stream, g, st,
-                         seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
+      hipLaunchKernelGGL((sampler_kernel<256, MULTI, HASHED>), dim3(grid), dim3(256), 0, stream,
+                         g, st, seed, phase, first, segs, nseg, count, work, out, small_exp, bd);
       break;
     default:
       return hipErrorInvalidValue;
@@ -2491,12 +2688,28 @@ hipError_t launch_sampler_variant(int block, uint32_t grid, hipStream_t stream, 
   return hipGetLastError();
 }
 
+// Slot tables (st.hbits in [1, 31]: hashed records) or one record per node (0).
+template <bool MULTI>
+hipError_t launch_sampler_variant(int block, uint32_t grid, hipStream_t stream, const GraphDev &g,
+                                  const SlotState &st, uint64_t seed, uint32_t phase,
+                                  uint64_t first, const SampleSeg *segs, uint32_t nseg,
+                                  uint32_t count, uint32_t *work, const SampleOut &out,
+                                  uint32_t small_exp, const BatchDesc *bd) {
+  if (st.hbits > 31 || (st.hbits != 0 && (!st.vh || st.n != (1u << st.hbits))))
+    return hipErrorInvalidValue;
+  if (st.hbits)
+    return launch_sampler_shape<MULTI, true>(block, grid, stream, g, st, seed, phase, first,
+                                             segs, nseg, count, work, out, small_exp, bd);
+  return launch_sampler_shape<MULTI, false>(block, grid, stream, g, st, seed, phase, first, segs,
+                                            nseg, count, work, out, small_exp, bd);
+}
+
 hipError_t launch_sampler(const GraphDev &g, const SlotState &st, uint64_t seed, uint32_t phase,
                           uint64_t first, uint32_t count, uint32_t *work, const SampleOut &out,
                           uint32_t grid, const LaunchShape &shape, hipStream_t stream,
                           const BatchDesc *bd) {
   if (count == 0) return hipSuccess;
-  if (st.n < g.n || grid > st.slots || grid == 0) return hipErrorInvalidValue;
+  if ((st.hbits == 0 && st.n < g.n) || grid > st.slots || grid == 0) return hipErrorInvalidValue;
   return launch_sampler_variant<false>(shape.block, grid, stream, g, st, seed, phase, first,
                                        nullptr, 0u, count, work, out, shape.small_exp, bd);
 }
@@ -2851,16 +3064,27 @@ int wide_blocks_per_cu() {
   return blocks > 0 ? blocks : 1;
 }
 
-int sampler_blocks_per_cu(int block) {
-  int blocks = 0;
-  hipError_t e = hipErrorInvalidValue;
-  if (block == 64)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<64, false>, 64, 0);
-  else if (block == 128)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<128, false>, 128, 0);
-  else if (block == 256)
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&blocks, sampler_kernel<256, false>, 256, 0);
-  if (e != hipSuccess) return 1;
+template <int BLOCK>
+static int sampler_blocks(int &blocks, bool tables) {
+  // the fewer of the two variants (one graph, several) a launch of this layout may use
+  int b[2] = {0, 0};
+  hipError_t e = tables
+      ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], sampler_kernel<BLOCK, false, true>, BLOCK, 0)
+      : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[0], sampler_kernel<BLOCK, false, false>, BLOCK, 0);
+  if (e == hipSuccess)
+    e = tables
+        ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], sampler_kernel<BLOCK, true, true>, BLOCK, 0)
+        : hipOccupancyMaxActiveBlocksPerMultiprocessor(&b[1], sampler_kernel<BLOCK, true, false>, BLOCK, 0);
+  blocks = std::min(b[0], b[1]);
+  return e == hipSuccess ? 0 : 1;
+}
+
+int sampler_blocks_per_cu(int block, bool tables) {
+  int blocks = 0, bad = 1;
+  if (block == 64) bad = sampler_blocks<64>(blocks, tables);
+  else if (block == 128) bad = sampler_blocks<128>(blocks, tables);
+  else if (block == 256) bad = sampler_blocks<256>(blocks, tables);
+  if (bad) return 1;
   return blocks > 0 ? blocks : 1;
 }
 

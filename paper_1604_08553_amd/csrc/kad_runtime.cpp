@@ -153,9 +153,14 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   HIP_TRY(hipDeviceSynchronize());  // no launch may still use the old state
   ctx->rec.release();
   ctx->visit.release();
+  ctx->vh.release();
   ctx->pi.release();
-  ctx->slots = 0;
+  ctx->wrec.release();
+  ctx->wvisit.release();
+  ctx->wpi.release();
+  ctx->slots = ctx->wpool = 0;
   ctx->slot_n = 0;
+  ctx->slot_hbits = 0;
   // the wide-count arena is laid out after the slots, from what they leave
   ctx->w_arena.release();
   ctx->w_lv.release();
@@ -164,24 +169,54 @@ kad_status ensure_slots(kad_ctx *ctx, uint32_t n) {
   ctx->w_arena_limbs = ctx->w_arena_limbs2 = 0;
   const uint32_t want_slots =
       ctx->cus * (uint32_t)*std::max_element(ctx->blocks_per_cu, ctx->blocks_per_cu + 3);
-  const uint64_t per_slot = (uint64_t)n * (4ull * REC_WORDS + 4) + (uint64_t)PI_CAP * 8;
+  const uint32_t want_tab =
+      ctx->cus * (uint32_t)*std::max_element(ctx->blocks_per_cu_tab, ctx->blocks_per_cu_tab + 3);
+  const uint64_t dense_slot = (uint64_t)n * (4ull * REC_WORDS + 4) + (uint64_t)PI_CAP * 8;
   // slots take at most 70% of what the budget leaves after the graphs and 1 GiB (the
   // wide-count arenas, the engine's pools and the run buffers use the rest)
   const uint64_t avail = ctx->budget > ctx->used_graphs + (1024ull << 20)
                              ? (uint64_t)(0.7 * (double)(ctx->budget - ctx->used_graphs - (1024ull << 20)))
                              : 0;
-  const uint64_t slots = std::min<uint64_t>(want_slots, avail / per_slot);
+  // one record per node, unless that leaves fewer than TABLE_AUTO_PER_CU slots per CU (and
+  // the graph is larger than a table) or the caller chose tables
+  uint32_t hbits = 0;
+  if (ctx->table_knob >= TABLE_MIN_BITS)
+    hbits = ctx->table_knob;
+  else if (ctx->table_knob == 0 && avail / dense_slot < (uint64_t)TABLE_AUTO_PER_CU * ctx->cus &&
+           n > (1u << TABLE_AUTO_BITS))
+    hbits = TABLE_AUTO_BITS;
+  uint64_t slots = 0, wpool = 0, table_slot = 0;
+  if (hbits == 0) {
+    slots = std::min<uint64_t>(want_slots, avail / dense_slot);
+  } else {
+    // the wide-count kernel's dense slots first (as many as it can run resident, within
+    // their share), then the tables: records, reached list, record indices, candidates
+    const uint64_t H = 1ull << hbits;
+    table_slot = H * (4ull * REC_WORDS + 8) + (uint64_t)PI_CAP * 8;
+    wpool = std::min<uint64_t>(std::max<uint32_t>(16, (uint32_t)ctx->wide_per_cu * ctx->cus),
+                               (uint64_t)(WIDE_POOL_SHARE * (double)avail) / dense_slot);
+    slots = wpool ? std::min<uint64_t>(want_tab, (avail - wpool * dense_slot) / table_slot) : 0;
+  }
   if (slots == 0)
     return fail(KAD_ENOMEM, "HBM budget too small for one sampler slot of a %u-node graph", n);
-  HIP_TRY(ctx->rec.ensure((size_t)slots * n * REC_WORDS));
-  HIP_TRY(ctx->visit.ensure((size_t)slots * n));
+  const uint64_t cap = hbits ? (1ull << hbits) : n;  // records per sampler slot
+  HIP_TRY(ctx->rec.ensure((size_t)(slots * cap * REC_WORDS)));
+  HIP_TRY(ctx->visit.ensure((size_t)(slots * cap)));
   HIP_TRY(ctx->pi.ensure((size_t)slots * PI_CAP));
-  HIP_TRY(hipMemsetAsync(ctx->rec.p, 0, (size_t)slots * n * 4 * REC_WORDS, ctx->stream));
+  HIP_TRY(hipMemsetAsync(ctx->rec.p, 0, (size_t)(slots * cap * 4 * REC_WORDS), ctx->stream));
+  if (hbits) {
+    HIP_TRY(ctx->vh.ensure((size_t)(slots * cap)));
+    HIP_TRY(ctx->wrec.ensure((size_t)(wpool * n * REC_WORDS)));
+    HIP_TRY(ctx->wvisit.ensure((size_t)(wpool * n)));
+    HIP_TRY(ctx->wpi.ensure((size_t)(wpool * PI_CAP)));
+    HIP_TRY(hipMemsetAsync(ctx->wrec.p, 0, (size_t)(wpool * n * 4 * REC_WORDS), ctx->stream));
+  }
   HIP_TRY(hipStreamSynchronize(ctx->stream));
   ctx->slots = (uint32_t)slots;
   ctx->slot_n = n;
-  ctx->slot_bytes = slots * per_slot;
-  ctx->w_slots = std::min<uint32_t>(ctx->w_slots, ctx->slots);
+  ctx->slot_hbits = hbits;
+  ctx->wpool = (uint32_t)wpool;
+  ctx->slot_bytes = hbits ? slots * table_slot + wpool * dense_slot : slots * dense_slot;
   return KAD_OK;
 }
 
@@ -235,7 +270,7 @@ kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc) {
   if (!big) {
     // 128-bit graphs (candidate edges past a slot only): 16 slots, each with room for every
     // node's count at three limbs and every arc as a candidate edge
-    w_slots = std::min<uint32_t>(16, ctx->slots);
+    w_slots = std::min<uint32_t>(16, wide_slot_count(ctx));
     limbs = want;
     if (w_slots == 0 || left / 2 < (uint64_t)w_slots * (limbs * 8 + tables))
       return fail(KAD_ENOMEM, "no HBM left for the wide-count arena (%llu limbs per slot needed)",
@@ -251,7 +286,7 @@ kad_status ensure_wide(kad_ctx *ctx, const kad_graph *g, int ovc) {
     const uint64_t worst = std::max(wide_limbs_worst(g), ovc == 0 ? want : (uint64_t)0);
     const uint64_t target = ctx->w_user_limbs ? ctx->w_user_limbs : WIDE_TIER1_LIMBS;
     const uint64_t lim1 = std::min(worst, target);
-    uint32_t most = std::min<uint32_t>(ctx->slots, (uint32_t)ctx->wide_per_cu * ctx->cus);
+    uint32_t most = std::min<uint32_t>(wide_slot_count(ctx), (uint32_t)ctx->wide_per_cu * ctx->cus);
     if (ctx->w_user_slots) most = std::min(most, ctx->w_user_slots);
     w_slots = (uint32_t)std::min<uint64_t>(most, A / (lim1 * 8 + tables));
     if (w_slots == 0)
@@ -292,7 +327,7 @@ int overflow_class(const kad_graph *g, uint32_t vd, bool vd_from_library) {
 
 WideState wide_view(const kad_ctx *ctx) {
   WideState w;
-  w.slots = std::min(ctx->w_slots, ctx->slots);
+  w.slots = std::min(ctx->w_slots, wide_slot_count(ctx));
   w.max_lev = ctx->w_max_lev;
   w.arena_limbs = ctx->w_arena_limbs;
   w.arena = ctx->w_arena.p;
@@ -315,9 +350,11 @@ kad_status launch_wide(kad_ctx *ctx, const GraphDev &g, uint64_t seed, uint32_t 
                        hipStream_t stream, uint32_t slot0, const BatchDesc *bd) {
   if (count == 0) return KAD_OK;
   if (ctx->w_slots == 0) return fail(KAD_EINVAL, "internal: wide-count arena not allocated");
-  const SlotState sv = slot_view(ctx, slot0);
+  // with slot tables the wide-count kernel has a pool of its own, which the wide passes of
+  // one run take in turn (each waits for the previous one: they share the arena)
+  const SlotState sv = wide_slot_view(ctx, ctx->slot_hbits ? 0u : slot0);
   WideState wv = wide_view(ctx);
-  wv.slots = std::min(wv.slots, sv.slots);  // the wide slots reuse these sampler slots
+  wv.slots = std::min(wv.slots, sv.slots);  // one dense slot per wide-count workgroup
   const bool two = ctx->w_slots2 > 0 && list2;
   SampleOut o1 = out, o2 = out;  // the first pass lists the samples its arenas cannot hold
   o1.fix_list = two ? list2 : nullptr;
@@ -343,7 +380,7 @@ LaunchShape graph_shape(const kad_graph *g) {
 uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t count, uint32_t slot0) {
   int per_cu = 1;
   for (int j = 0; j < 3; ++j)
-    if (SAMPLER_BLOCKS[j] == shape.block) per_cu = ctx->blocks_per_cu[j];
+    if (SAMPLER_BLOCKS[j] == shape.block) per_cu = sampler_per_cu(ctx, shape.block);
   const uint64_t resident = (uint64_t)ctx->cus * (uint64_t)per_cu;
   const uint64_t slots = ctx->slots > slot0 ? ctx->slots - slot0 : 0;
   return (uint32_t)std::min<uint64_t>(std::min<uint64_t>(slots, resident), count);
@@ -351,13 +388,39 @@ uint32_t launch_grid(const kad_ctx *ctx, const LaunchShape &shape, uint64_t coun
 
 SlotState slot_view(const kad_ctx *ctx, uint32_t slot0) {
   SlotState st;
-  const size_t n = ctx->slot_n;
+  const size_t n = ctx->slot_hbits ? (size_t)1 << ctx->slot_hbits : ctx->slot_n;
   st.slots = ctx->slots > slot0 ? ctx->slots - slot0 : 0;
-  st.n = ctx->slot_n;
+  st.n = (uint32_t)n;
   st.pi_cap = PI_CAP;
   st.rec = ctx->rec.p + (size_t)slot0 * n * REC_WORDS;
   st.visit = ctx->visit.p + (size_t)slot0 * n;
   st.pi = ctx->pi.p + (size_t)slot0 * PI_CAP;
+  st.hbits = ctx->slot_hbits;
+  st.vh = ctx->slot_hbits ? ctx->vh.p + (size_t)slot0 * n : nullptr;
+  return st;
+}
+
+int sampler_per_cu(const kad_ctx *ctx, int block) {
+  for (int j = 0; j < 3; ++j)
+    if (SAMPLER_BLOCKS[j] == block)
+      return ctx->slot_hbits ? ctx->blocks_per_cu_tab[j] : ctx->blocks_per_cu[j];
+  return 1;
+}
+
+uint32_t wide_slot_count(const kad_ctx *ctx) {
+  return ctx->slot_hbits ? ctx->wpool : ctx->slots;
+}
+
+SlotState wide_slot_view(const kad_ctx *ctx, uint32_t slot0) {
+  if (!ctx->slot_hbits) return slot_view(ctx, slot0);
+  SlotState st;
+  const size_t n = ctx->slot_n;
+  st.slots = ctx->wpool > slot0 ? ctx->wpool - slot0 : 0;
+  st.n = ctx->slot_n;
+  st.pi_cap = PI_CAP;
+  st.rec = ctx->wrec.p + (size_t)slot0 * n * REC_WORDS;
+  st.visit = ctx->wvisit.p + (size_t)slot0 * n;
+  st.pi = ctx->wpi.p + (size_t)slot0 * PI_CAP;
   return st;
 }
 
@@ -713,13 +776,13 @@ kad_status replay_sampling(kad_ctx *ctx, const kad_graph *g, int set, uint64_t s
   const kad::GraphDev gd = dev_view(g);
   const kad::LaunchShape shape = kad::graph_shape(g);
   const uint32_t grid = kad::launch_grid(ctx, shape, cap, 0);
-  const kad::SlotState sv = kad::slot_view(ctx, 0);
+  const kad::SlotState sv = kad::slot_view(ctx, 0), wsv = kad::wide_slot_view(ctx, 0);
   const kad::WideState wv = kad::wide_view(ctx), wv2 = kad::wide_view2(ctx);
   uint32_t *wk = ctx->work.p;  // the launch's counters (kad::WORK_WORDS)
   const kad::SampleOut so_list = o.view(stride, wk + 1), so = o.view(stride);
   kad::BatchDesc *hb = ctx->h_bd.p + set, *db = ctx->d_bd.p + set;
   kad::ChainKey key;
-  key << 1 << set << gd << sv << wv << wv2 << so_list << o.fix_list2.p << shape.block
+  key << 1 << set << gd << sv << wsv << wv << wv2 << so_list << o.fix_list2.p << shape.block
       << shape.small_exp << grid << cap << stride << ovc << edges << edge_ids << o.epath.p
       << o.elen.p << o.h_flags.p << o.h_arcs.p << o.h_nwide.p << wk << hb << db;
   kad_status st = kad::record_chain(ctx, ctx->bgraph[set], key, [&](hipStream_t s) -> kad_status {
@@ -906,7 +969,10 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, hip_device));
   c->cus = (uint32_t)prop.multiProcessorCount;
-  for (int j = 0; j < 3; ++j) c->blocks_per_cu[j] = kad::sampler_blocks_per_cu(kad::SAMPLER_BLOCKS[j]);
+  for (int j = 0; j < 3; ++j) {
+    c->blocks_per_cu[j] = kad::sampler_blocks_per_cu(kad::SAMPLER_BLOCKS[j], false);
+    c->blocks_per_cu_tab[j] = kad::sampler_blocks_per_cu(kad::SAMPLER_BLOCKS[j], true);
+  }
   c->wide_per_cu = kad::wide_blocks_per_cu();
   size_t free_b = 0, total_b = 0;
   HIP_TRY(hipMemGetInfo(&free_b, &total_b));
@@ -1535,13 +1601,14 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   // stream, slots and work counter (a pilot of alpha samples is one short launch whose
   // last samples would otherwise hold the GPU); its wide-count fix, which shares one
   // arena, waits for the pilot's.  Its slots start past every slot the pilot may use:
-  // the pilot sampler's (at most alpha) and those of the pilot's wide-count passes, which
+  // the pilot sampler's (at most alpha) and, when the wide-count kernel shares the
+  // sampler slots (one record per node), those of the pilot's wide-count passes, which
   // run on sampler slots 0, 1, ... (at most w_slots).
   const int first_set = 1;
   const uint32_t first_nb = (uint32_t)std::min<uint64_t>(
       omega, std::min<uint64_t>(K, std::max<uint64_t>(B, (omega / 2 + B - 1) / B * B)));
-  const uint32_t b1_slot0 =
-      (uint32_t)std::max<uint64_t>(std::max<uint64_t>(alpha, 64), ctx->w_slots);
+  const uint32_t b1_slot0 = (uint32_t)std::max<uint64_t>(
+      std::max<uint64_t>(alpha, 64), ctx->slot_hbits ? 0u : ctx->w_slots);
   const bool overlap = !plain && hip_stream == nullptr && ovc != 2 && alpha <= ctx->outs[0].cap &&
                        (uint64_t)ctx->slots >= (uint64_t)b1_slot0 + kad::launch_grid(
                                                    ctx, kad::graph_shape(g), first_nb);
@@ -2045,6 +2112,30 @@ kad_status kad_ctx_get_wide(kad_ctx *ctx, uint32_t *slots, uint64_t *limbs, uint
   if (limbs) *limbs = ctx->w_arena_limbs;
   if (slots2) *slots2 = ctx->w_slots2;
   if (limbs2) *limbs2 = ctx->w_arena_limbs2;
+  return KAD_OK;
+}
+
+kad_status kad_ctx_set_table(kad_ctx *ctx, uint32_t log2_records) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  if (log2_records > 1 && (log2_records < kad::TABLE_MIN_BITS || log2_records > kad::TABLE_MAX_BITS))
+    return fail(KAD_EINVAL, "slot tables hold 2^%u to 2^%u records", kad::TABLE_MIN_BITS,
+                kad::TABLE_MAX_BITS);
+  kad::CtxClaim claim(ctx);
+  if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
+  HIP_TRY(hipSetDevice(ctx->device));
+  HIP_TRY(hipDeviceSynchronize());  // no launch may still use the slots
+  ctx->table_knob = log2_records;
+  ctx->slots = 0;  // laid out again (and the wide-count arena after them) on next use
+  ctx->slot_n = 0;
+  return KAD_OK;
+}
+
+kad_status kad_ctx_get_table(kad_ctx *ctx, uint32_t *log2_records, uint32_t *slots,
+                             uint32_t *wide_slots) {
+  if (!ctx) return fail(KAD_EINVAL, "NULL context");
+  if (log2_records) *log2_records = ctx->slots ? ctx->slot_hbits : 0;
+  if (slots) *slots = ctx->slots;
+  if (wide_slots) *wide_slots = ctx->slots ? kad::wide_slot_count(ctx) : 0;
   return KAD_OK;
 }
 
