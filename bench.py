@@ -776,8 +776,13 @@ def main():
         "time_to_epsilon_s": elapsed / args.steps,
         "tau": r0["tau"], "omega": r0["omega"], "alpha": r0["alpha"], "vd": r0["vd"],
         "check_interval": r0["interval"], "stop": "rule" if r0["stop_reason"] else "omega",
-        "phases_s": {k: sum(r[f"seconds_{k}"] for r in runs) / len(runs)
-                     for k in ("setup", "pilot", "delta", "main")},
+        "phases_s": dict({k: sum(r[f"seconds_{k}"] for r in runs) / len(runs)
+                          for k in ("setup", "pilot", "delta", "main")},
+                         outputs=sum(r["seconds"] - sum(r[f"seconds_{k}"] for k in
+                                                        ("setup", "pilot", "delta", "main"))
+                                     for r in runs) / len(runs),
+                         note="outputs: the final counts copied to the host (n x 8 bytes) "
+                              "and the per-node intervals computed there in binary64"),
         "exec": {"mode": args.exec, "chains_recorded": exec_info["records"],
                  "chain_replays": exec_info["replays"]},
         "slot_layout": ctx.table_info(),
