@@ -1376,7 +1376,10 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 64 || HASHED) ? 4 : 5) void sample
         bool arena = false;  // the sort used the filter's words (cleared again below)
         if (P <= (uint32_t)BLOCK) {
           // one candidate per thread, no sort: a candidate's prefix in canonical order is
-          // the sum of the weights of the smaller keys (keys are distinct)
+          // the sum of the weights of the smaller keys (keys are distinct).  Each thread
+          // sums every weight itself and takes the draw itself (a pure function of the
+          // sample), so one barrier publishes the weights and the one after the pick its
+          // winner.
           bool wov = false;
           uint64_t key = 0;
           u128 wt{0, 0};
@@ -1392,37 +1395,32 @@ __global__ __launch_bounds__(BLOCK, (BLOCK == 64 || HASHED) ? 4 : 5) void sample
             }
             L.c_sig_lo[tid] = wt.lo;
             L.c_sig_hi[tid] = wt.hi;
+            if (wov) atomicOr(&L.ovf_any, 2u);
           }
-          u128 total;
-          (void)block_incl_u128(L, wt, total, wov);  // its barriers publish the weights
-          if (wov) atomicOr(&L.ovf_any, 2u);
-          if (tid == BLOCK - 1) {  // the draw (pure; void if a count overflowed) overlaps
-            uint32_t fl = 0;       // the prefix sums of the other threads
-            const u128 r = uniform_below(total, seed, i, stream_word(phase, P_EDGE, 0), fl);
-            L.r_lo = r.lo;
-            L.r_hi = r.hi;
-            L.rfl = fl;
+          if (tid == 0) {
             L.win = 0xFFFFFFFFu;
             L.wkey = L.pi[0];
           }
-          u128 pre{0, 0};
-          if (tid < P) {
-            bool dm = false;  // partial sums of a total that fits do not overflow
-#pragma unroll 4
-            for (uint32_t j = 0; j < P; ++j)
-              if (L.pi[j] < key) pre = add128(pre, u128{L.c_sig_lo[j], L.c_sig_hi[j]}, dm);
-          }
           __syncthreads();
-          const uint32_t fl = (L.ovf_any & 2u) ? (uint32_t)FLAG_OVERFLOW : L.rfl;
-          if (fl == 0 && tid < P) {
-            const u128 r{L.r_lo, L.r_hi};
-            bool dm = false;
-            if (!lt128(r, pre) && lt128(r, add128(pre, wt, dm))) {
-              L.win = tid;
-              L.wkey = key;
+          if (tid < P) {
+            u128 pre{0, 0}, total{0, 0};
+            bool dm = false, tov = false;  // a total that fits has partial sums that fit
+#pragma unroll 4
+            for (uint32_t j = 0; j < P; ++j) {
+              const u128 x{L.c_sig_lo[j], L.c_sig_hi[j]};
+              if (L.pi[j] < key) pre = add128(pre, x, dm);
+              total = add128(total, x, tov);
             }
+            uint32_t fl = (tov || (L.ovf_any & 2u)) ? (uint32_t)FLAG_OVERFLOW : 0u;
+            if (fl == 0) {
+              const u128 r = uniform_below(total, seed, i, stream_word(phase, P_EDGE, 0), fl);
+              if (fl == 0 && !lt128(r, pre) && lt128(r, add128(pre, wt, dm))) {
+                L.win = tid;
+                L.wkey = key;
+              }
+            }
+            if (tid == 0) L.flags |= fl;  // every thread found the same flags
           }
-          if (tid == 0) L.flags |= fl;
         } else {
           // sort, then prefix sums chunk by chunk.  Up to SORT_CAP keys are sorted in the
           // LDS words the searches no longer need, more in the slot's candidate buffer.
