@@ -165,6 +165,40 @@ def cpu_baseline_family(csrs, kw, gpu_results, stride=16):
                       "scaled by sampled paths"}
 
 
+def cpu_baseline_serve(csrs, Gs, ctx, stream, grid_id, kad, per_graph=2000, grid_samples=4):
+    """The oracle's sampling rate over the resident graphs: on each, main-phase ids
+    0..per_graph-1 under the seed of the graph's first query (grid_samples ids on the grid,
+    whose samples reach about 1.35M nodes with counts of hundreds of bits), all host
+    threads; the GPU's paths for the same ids (kad_sample_paths) compared with them."""
+    import numpy as np
+    import oracle
+    threads = host_threads()
+    seeds = {}
+    for q in stream:
+        seeds.setdefault(q["graph"], q["seed"])
+    total, arcs, dt, parity = 0, 0, 0.0, True
+    for i, g in csrs.items():
+        cnt = grid_samples if i == grid_id else per_graph
+        seed = seeds.get(i, 1)
+        t0 = time.perf_counter()
+        S = oracle.sample_paths(g, seed, 1, 0, cnt, threads=threads)
+        dt += time.perf_counter() - t0
+        total += cnt
+        arcs += int(S.arcs.sum())
+        A = kad.sample_paths(ctx, Gs[i], seed, 1, 0, cnt)
+        parity &= bool((A["flags"] == 0).all() and np.array_equal(A["s"], S.s)
+                       and np.array_equal(A["t"], S.t) and np.array_equal(A["arcs"], S.arcs)
+                       and np.array_equal(A["path_off"], S.path_off)
+                       and np.array_equal(A["nodes"], S.nodes))
+    return {"value": total / dt, "unit": "sampled shortest paths/s", "cores": threads,
+            "kind": "oracle", "cpu_model": cpu_model(), "gteps": arcs / dt / 1e9,
+            "parity": parity,
+            "sample": f"oracle sample_paths on each of the {len(csrs)} resident graphs: main-phase "
+                      f"ids 0..{per_graph - 1} under the seed of its first query ({grid_samples} "
+                      f"on the grid); {total} samples, {dt:.1f} s, all host threads; the GPU's "
+                      "paths for the same ids compared"}
+
+
 def _same_result(a, b):
     import numpy as np
     return (a["tau"] == b["tau"] and a["stop_reason"] == b["stop_reason"]
@@ -401,6 +435,11 @@ def bench_serve(args, torch, gg, kad):
     st = srv.stats()
     print("[bench] closing the server (waits for launches in flight)", file=sys.stderr, flush=True)
     srv.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline_serve(csrs, Gs, ctx, stream, grid_id, kad)
+        print(f"[bench] cpu baseline: {cpu['value']:.0f} paths/s, parity {cpu['parity']}",
+              file=sys.stderr, flush=True)
     elapsed = cut - start
     lat = [r["seconds"] for _, r in done]
     lower = lat + [age for _, age in unfinished]
@@ -436,6 +475,8 @@ def bench_serve(args, torch, gg, kad):
                      "grid": cls(lambda q: q["graph"] == grid_id),
                      "not_grid": cls(lambda q: q["graph"] != grid_id)},
     }
+    if cpu is not None:
+        out["cpu_baseline"] = cpu
     for q, age in sorted(unfinished, key=lambda x: -x[1])[:12]:
         print(f"[bench] unfinished: graph {q['graph']} (n={csrs[q['graph']].n}) {q['mode']} "
               f"k={q['k']} eps={q['epsilon']:.4f} age {age:.1f} s", file=sys.stderr, flush=True)

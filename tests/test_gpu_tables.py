@@ -184,3 +184,24 @@ def test_table_knob_rejects(kad):
             ctx.set_table(bad)
         assert e.value.status == -1
     ctx.close()
+
+
+@pytest.mark.parametrize("bits", [12, 6])
+def test_forward_search_and_edges_with_tables(kad, orc, graphs, bits):
+    """The plain BFS from s (the forward search) and edge hits with slot tables."""
+    g = graphs["cl30k"]
+    ctx = _ctx(kad, bits)
+    G = kad.Graph(ctx, g)
+    G.set_search("forward")
+    _say("forward search, tables", bits)
+    A = kad.sample_paths(ctx, G, 5, 1, 0, 1500)
+    B = orc.sample_paths(g, 5, 1, 0, 1500, threads=16, search="forward")
+    assert (A["flags"] == 0).all()
+    assert np.array_equal(A["arcs"], B.arcs) and np.array_equal(A["nodes"], B.nodes)
+    G.set_search("balanced")
+    _say("edge hits, tables", bits)
+    a, arcs = kad.edge_hit_counts(ctx, G, 4, 1, 50, 3000)
+    b, barcs = orc.edge_hits(g, 4, 1, 50, 3000, threads=16)
+    assert np.array_equal(a, b) and arcs == barcs
+    G.close()
+    ctx.close()
