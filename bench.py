@@ -477,6 +477,18 @@ def bench_serve(args, torch, gg, kad):
     }
     if cpu is not None:
         out["cpu_baseline"] = cpu
+
+    def phases(rs):
+        """Mean seconds per phase of a query: queued, pilot (admission to the pilot's counts),
+        computeDelta, main phase, outputs (stopping to the result)."""
+        if not rs:
+            return None
+        keys = ("setup", "pilot", "delta", "main")
+        m = {k: sum(r[f"seconds_{k}"] for r in rs) / len(rs) for k in keys}
+        m["outputs"] = sum(r["seconds"] - sum(r[f"seconds_{k}"] for k in keys) for r in rs) / len(rs)
+        return m
+    ng = sorted((r for q, r in done if q["graph"] != grid_id), key=lambda r: r["seconds"])
+    out["not_grid_phases_s"] = {"all": phases(ng), "slowest_5pct": phases(ng[-max(1, len(ng) // 20):])}
     for q, age in sorted(unfinished, key=lambda x: -x[1])[:12]:
         print(f"[bench] unfinished: graph {q['graph']} (n={csrs[q['graph']].n}) {q['mode']} "
               f"k={q['k']} eps={q['epsilon']:.4f} age {age:.1f} s", file=sys.stderr, flush=True)
@@ -484,7 +496,9 @@ def bench_serve(args, torch, gg, kad):
     for q, r in slow:
         print(f"[bench] slowest: graph {q['graph']} (n={csrs[q['graph']].n}) {q['mode']} "
               f"k={q['k']} eps={q['epsilon']:.4f} {r['seconds']:.2f} s tau={r['tau']} "
-              f"omega={r['omega']} queued {r['seconds_setup']:.2f} s", file=sys.stderr, flush=True)
+              f"omega={r['omega']} queued {r['seconds_setup']:.2f} pilot {r['seconds_pilot']:.2f} "
+              f"delta {r['seconds_delta']:.2f} main {r['seconds_main']:.2f} s", file=sys.stderr,
+              flush=True)
     for G in Gs.values():
         G.close()
     ctx.close()

@@ -144,6 +144,7 @@ struct Tick {
   std::vector<uint32_t> layer_blocks; // and the gather's workgroups
   std::vector<uint64_t> layer_snap;   // and its snapshot entries
   uint32_t total = 0, stride = 2, layers = 0;
+  uint32_t wide_wgs = 0;  // wide-count workgroups of the lane-1 launch (each fills a CU)
   uint64_t id = 0;
   bool in_flight = false;
   ~Tick() {
@@ -162,6 +163,13 @@ struct Lane {
   uint32_t slot0 = 0, nslots = 0;   // sampler slots
   uint32_t wslot0 = 0, nwslots = 0; // wide-count slots (arena and slot arrays of that index)
   bool busy() const { return ticks[0].in_flight || ticks[1].in_flight; }
+  // wide-count workgroups of the launches in flight
+  uint32_t wide_in_flight() const {
+    uint32_t w = 0;
+    for (const Tick &t : ticks)
+      if (t.in_flight) w = std::max(w, t.wide_wgs);
+    return w;
+  }
   HitScratch scratch() const {
     HitScratch h;
     h.bins = bins.p;
@@ -191,6 +199,9 @@ class Engine {
   }
   kad_status init();
   void enqueue(Query *q) { queue_.push_back(q); }
+  // A server's queries arrive at any time: the wide lane then always leaves three quarters
+  // of the CUs to lane 0, not only while lane 0 has work.
+  void set_serving(bool on) { serving_ = on; }
   bool busy() const {
     return !queue_.empty() || !active_.empty() || lanes_[0].busy() || lanes_[1].busy();
   }
@@ -267,6 +278,7 @@ class Engine {
   std::vector<Query *> active_;
   std::vector<Query *> done_;
   size_t rr_ = 0;
+  bool serving_ = false;
   std::atomic<uint64_t> ticks_launched_{0}, samples_launched_{0};
 };
 
@@ -690,13 +702,20 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   int per_cu = 1;
   for (int j = 0; j < 3; ++j)
     if (SAMPLER_BLOCKS[j] == shape.block) per_cu = sampler_per_cu(ctx_, shape.block);
-  const uint32_t resident =
-      (uint32_t)std::min<uint64_t>(L.nslots, (uint64_t)ctx_->cus * per_cu);
-  // While lane 0 has work, the wide lane's launches take at most a quarter of the CUs: a
-  // wide-count workgroup fills a CU's registers, and lane 1's long high-diameter queries
-  // would otherwise hold most of the GPU away from every other query.
+  // Lane 1's wide-count workgroups in flight each fill a CU for as long as their samples
+  // take (hundreds of ms on a high-diameter graph); lane 0's sampler grid takes only the
+  // CUs they leave, so that all its workgroups are resident at once: one that waited for
+  // a CU would hold its sample ids, and so the tick, until the wide kernel finished.
+  const uint32_t held =
+      wide_lane ? 0u : (lanes_[1].wide_in_flight() + ctx_->wide_per_cu - 1) / ctx_->wide_per_cu;
+  const bool shared = held > 0;
+  const uint32_t free_cus = held < ctx_->cus ? ctx_->cus - held : 1u;
+  const uint32_t resident = (uint32_t)std::min<uint64_t>(L.nslots, (uint64_t)free_cus * per_cu);
+  // While lane 0 has work (and always in a server), the wide lane's launches take at most
+  // a quarter of the CUs: a wide-count workgroup fills a CU's registers, and lane 1's long
+  // high-diameter queries would otherwise hold most of the GPU away from every other query.
   WideState w1 = lane_wide(L);
-  const bool capped = wide_lane && lanes_[0].busy();
+  const bool capped = wide_lane && (lanes_[0].busy() || serving_);
   if (capped) w1.slots = std::min(w1.slots, std::max<uint32_t>(1, ctx_->cus / 4));
   const WideState w2 = lane_wide2(L);
   // The sampling chain: segment table to the device, counters cleared, the sampler (lane 0),
@@ -748,8 +767,10 @@ kad_status Engine::launch(Lane &L, Tick &t) {
   if (replay) {
     HIP_TRY(t.h_bd.ensure(1));
     HIP_TRY(t.d_bd.ensure(1));
-    BatchGraph &bg =
-        t.chains[2 * (shape.block == 64 ? 0 : (shape.block == 128 ? 1 : 2)) + (capped ? 1 : 0)];
+    // per block size, one chain for each lane-1 share (capped or not) and each lane-0 grid
+    // (the whole GPU, or beside wide-count workgroups)
+    BatchGraph &bg = t.chains[2 * (shape.block == 64 ? 0 : (shape.block == 128 ? 1 : 2)) +
+                              (capped || shared ? 1 : 0)];
     ChainKey key;
     key << 3 << (int)(&L - lanes_) << shape.block << shape.small_exp << resident << wide_lane
         << lane_slots(L, false) << lane_slots(L, true) << w1 << w2
@@ -799,6 +820,7 @@ kad_status Engine::launch(Lane &L, Tick &t) {
     }
     HIP_TRY(hipEventRecord(t.layer_ev[ly], rs));
   }
+  t.wide_wgs = wide_lane ? w1.slots : 0u;
   t.in_flight = true;
   ticks_launched_++;
   samples_launched_ += t.total;
@@ -1238,6 +1260,7 @@ kad_status kad_server_create(kad_ctx *ctx, kad_server **out) {
   sv->ctx = ctx;
   kad_status st = kad::context_engine(ctx, &sv->eng);
   if (st) return st;
+  sv->eng->set_serving(true);
   (void)sv->eng->take_done();
   sv->launches0 = sv->eng->ticks_launched();
   sv->samples0 = sv->eng->samples_launched();
@@ -1341,6 +1364,7 @@ kad_status kad_server_destroy(kad_server *sv) {
   }
   if (sv->th.joinable()) sv->th.join();
   kad_ctx *ctx = sv->ctx;
+  if (sv->eng) sv->eng->set_serving(false);
   if (sv->fatal) {  // the engine may still point at this server's queries
     kad::destroy_engine(ctx->engine);
     ctx->engine = nullptr;
