@@ -353,6 +353,16 @@ kad_status kad_compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cma
 kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha,
                             double epsilon, double *lambda_l, double *lambda_u);
 
+/* The top-k output (section 5): the nodes v whose rank interval reaches the top k --
+ * rank_lo(v) = 1 + #{w != v: lower(w) >= upper(v)} <= k -- ordered by count descending, id
+ * ascending, with rank_lo and rank_hi(v) = #{w: upper(w) > lower(v)}.  count, lower and upper
+ * are host arrays of n entries; node, rank_lo and rank_hi have room for cap entries (any may
+ * be NULL).  *len receives the selection's size; KAD_ETOOSMALL when it exceeds cap (nothing
+ * written), KAD_EINVAL for k outside [1, n]. */
+kad_status kad_topk_select(uint32_t n, uint32_t k, const uint64_t *count, const double *lower,
+                           const double *upper, uint32_t cap, uint32_t *node, uint32_t *rank_lo,
+                           uint32_t *rank_hi, uint32_t *len);
+
 /* Stopping conditions: all-nodes (every f <= eps and g <= eps) and top-k (Algorithm 3).
  * Return 1 (stop), 0 (continue) or a negative kad_status. */
 int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *count, uint64_t tau,

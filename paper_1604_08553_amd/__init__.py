@@ -107,6 +107,7 @@ def lib():
         "kad_compute_delta_hist": ([u32, vp, u64, u64, u64, dbl, dbl, dbl, dbl, vp, vp, vp, vp,
                                     vp], st),
         "kad_topk_lambdas": ([u32, u32, vp, u64, dbl, vp, vp], st),
+        "kad_topk_select": ([u32, u32, vp, vp, vp, u32, vp, vp, vp, vp], st),
         "kad_have_to_stop": ([u32, u32, u32, vp, u64, u64, dbl, vp, vp], st),
         "kad_run_batch": ([vp, u32, vp, vp, vp, vp], st),
         "kad_server_create": ([vp, vp], st),
@@ -608,6 +609,21 @@ def topk_lambdas(count0, k, alpha_, epsilon):
     ll, lu = np.zeros(n), np.zeros(n)
     _check(lib().kad_topk_lambdas(n, k, _p(count0), alpha_, epsilon, _p(ll), _p(lu)))
     return ll, lu
+
+
+def topk_select(count, lower, upper, k):
+    """The top-k output: nodes whose rank interval reaches the top k, by count descending
+    (id ascending), with rank_lo and rank_hi; see kad_topk_select."""
+    count = np.ascontiguousarray(count, dtype=np.uint64)
+    lo = np.ascontiguousarray(lower, dtype=np.float64)
+    hi = np.ascontiguousarray(upper, dtype=np.float64)
+    n = count.size
+    node, rlo, rhi = (np.zeros(n, dtype=np.uint32) for _ in range(3))
+    ln = C.c_uint32()
+    _check(lib().kad_topk_select(n, k, _p(count), _p(lo), _p(hi), n, _p(node), _p(rlo), _p(rhi),
+                                 C.byref(ln)))
+    m = ln.value
+    return node[:m].copy(), rlo[:m].copy(), rhi[:m].copy()
 
 
 def have_to_stop(count, tau, omega_, epsilon, L_l, L_u, mode="all", k=0) -> bool:

@@ -522,13 +522,22 @@ kad_status Engine::build(int li, Tick &t) {
       t.queries.push_back(q);
     }
   };
+  // With more than one query of the lane under way, none takes more than a quarter of a
+  // tick: a tick lasts until its last sample, so one query's large batch would hold every
+  // other query's next round trip (its check, then its next batch) for all that time.
   const size_t na = active_.size();
+  uint32_t under_way = 0;
+  for (const Query *q : active_)
+    if (q->lane == li && q->status == KAD_OK && (q->st == QState::Pilot || q->st == QState::Main))
+      ++under_way;
+  const uint64_t per_query = under_way > 1 ? TICK_SAMPLES / 4 : TICK_SAMPLES;
   for (size_t j = 0; j < na; ++j) {
     Query *q = active_[(rr_ + j) % na];
     if (q->lane != li || q->status != KAD_OK || q->st == QState::Final) continue;
     if (q->st == QState::Pilot) {
       if (q->pilot_launched >= q->alpha) continue;  // waiting for computeDelta
-      const uint32_t cnt = room(q, std::min<uint64_t>(q->alpha - q->pilot_launched, TICK_SAMPLES / 2));
+      const uint32_t cnt = room(q, std::min<uint64_t>(q->alpha - q->pilot_launched,
+                                                      std::min<uint64_t>(TICK_SAMPLES / 2, per_query)));
       if (cnt == 0) continue;
       const bool last = q->pilot_launched + cnt == q->alpha;
       add(q, 0, last ? Kind::PilotLast : Kind::Pilot, cnt, q->pilot_launched);
@@ -555,6 +564,7 @@ kad_status Engine::build(int li, Tick &t) {
       }
       want = (uint64_t)std::min<double>(std::ceil(w / (double)q->B), (double)(q->K / q->B)) * q->B;
     }
+    want = std::min(want, per_query);  // at least one interval is still added
     const Kind kind = q->p.mode == KAD_TOPK ? Kind::MainFull : Kind::Main;
     for (uint32_t L = 0; L < MAX_LAYERS && want > 0 && q->launched < q->omega; ++L) {
       const uint32_t cnt = (uint32_t)std::min<uint64_t>(q->B, q->omega - q->launched);

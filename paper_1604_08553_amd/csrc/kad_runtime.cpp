@@ -500,23 +500,61 @@ void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t 
   });
 }
 
+// The nodes whose rank interval can reach the top k, with their rank intervals
+// (rank_lo = 1 + #{w != v: lo(w) >= hi(v)}, rank_hi = #{w: hi(w) > lo(v)}), ordered by count
+// descending, id ascending.  Without sorting all n bounds: rank_lo(v) <= k needs hi(v) above
+// the (k+1)-th largest lower bound (else the k+1 largest lower bounds all reach hi(v)), and
+// then every lower bound that reaches hi(v) is among the k largest; rank_hi of a selected
+// node counts upper bounds above the selection's smallest lower bound only.
 void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
                  std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,
                  std::vector<uint32_t> &rhi_sel) {
-  std::vector<uint32_t> rlo(n), rhi(n);
-  rank_intervals(n, lo, hi, rlo.data(), rhi.data());
   sel.clear();
+  rlo_sel.clear();
+  rhi_sel.clear();
+  if (n == 0) return;
+  const uint32_t m = (uint32_t)std::min<uint64_t>(n, (uint64_t)k + 1);
+  std::vector<double> top(lo, lo + n);
+  std::nth_element(top.begin(), top.begin() + (m - 1), top.end(), std::greater<double>());
+  top.resize(m);
+  std::sort(top.begin(), top.end(), std::greater<double>());  // the m largest, descending
+  const bool everyone = (uint64_t)k + 1 > n;  // all lower bounds are in `top`
+  const double floor_lo = top[m - 1];
+  std::vector<uint32_t> rl;
+  for (uint32_t v = 0; v < n; ++v) {
+    if (!everyone && !(hi[v] > floor_lo)) continue;
+    // #{w: lo(w) >= hi(v)}: the prefix of `top` that is >= hi(v)
+    size_t ge = std::upper_bound(top.begin(), top.end(), hi[v], std::greater<double>()) -
+                top.begin();
+    if (lo[v] >= hi[v]) --ge;
+    if (1 + ge <= k) {
+      sel.push_back(v);
+      rl.push_back((uint32_t)(1 + ge));
+    }
+  }
+  if (sel.empty()) return;
+  double t = lo[sel[0]];
+  for (uint32_t v : sel) t = std::min(t, lo[v]);
+  std::vector<double> up;
   for (uint32_t v = 0; v < n; ++v)
-    if (rlo[v] <= k) sel.push_back(v);
-  std::sort(sel.begin(), sel.end(), [cnt](uint32_t a, uint32_t b) {
-    return cnt[a] != cnt[b] ? cnt[a] > cnt[b] : a < b;
+    if (hi[v] > t) up.push_back(hi[v]);
+  std::sort(up.begin(), up.end());
+  std::vector<uint32_t> idx(sel.size());
+  for (uint32_t q = 0; q < idx.size(); ++q) idx[q] = q;
+  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+    const uint32_t x = sel[a], y = sel[b];
+    return cnt[x] != cnt[y] ? cnt[x] > cnt[y] : x < y;
   });
+  std::vector<uint32_t> sorted(sel.size());
   rlo_sel.resize(sel.size());
   rhi_sel.resize(sel.size());
-  for (size_t q = 0; q < sel.size(); ++q) {
-    rlo_sel[q] = rlo[sel[q]];
-    rhi_sel[q] = rhi[sel[q]];
+  for (size_t q = 0; q < idx.size(); ++q) {
+    const uint32_t v = sel[idx[q]];
+    sorted[q] = v;
+    rlo_sel[q] = rl[idx[q]];
+    rhi_sel[q] = (uint32_t)(up.end() - std::upper_bound(up.begin(), up.end(), lo[v]));
   }
+  sel.swap(sorted);
 }
 
 uint64_t run_items(const kad_graph *g, uint32_t target) {
@@ -1176,6 +1214,23 @@ kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint
   if (!n || k < 1 || k > n || !count0 || !lambda_l || !lambda_u || !alpha)
     return fail(KAD_EINVAL, "bad argument");
   kad::topk_lambdas(n, k, count0, alpha, epsilon, lambda_l, lambda_u);
+  return KAD_OK;
+}
+
+kad_status kad_topk_select(uint32_t n, uint32_t k, const uint64_t *count, const double *lower,
+                           const double *upper, uint32_t cap, uint32_t *node, uint32_t *rank_lo,
+                           uint32_t *rank_hi, uint32_t *len) {
+  if (!n || k < 1 || k > n || !count || !lower || !upper || !len)
+    return fail(KAD_EINVAL, "bad argument");
+  std::vector<uint32_t> sel, rlo, rhi;
+  kad::topk_select(n, k, count, lower, upper, sel, rlo, rhi);
+  *len = (uint32_t)sel.size();
+  if (sel.size() > cap) return fail(KAD_ETOOSMALL, "the selection has %zu entries", sel.size());
+  for (size_t q = 0; q < sel.size(); ++q) {
+    if (node) node[q] = sel[q];
+    if (rank_lo) rank_lo[q] = rlo[q];
+    if (rank_hi) rank_hi[q] = rhi[q];
+  }
   return KAD_OK;
 }
 

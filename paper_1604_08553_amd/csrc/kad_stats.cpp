@@ -661,9 +661,19 @@ void compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cmax, uint64_
 // ------------------------------------------------------------------ top-k half-widths
 
 namespace {
-// nodes by count descending, id ascending
+// nodes by count descending, id ascending.  Pilot counts are at most alpha: placed by a
+// counting pass (ids ascending within a count), O(n + largest count) instead of a sort.
 void estimate_order(uint32_t n, const uint64_t *count, std::vector<uint32_t> &ord) {
   ord.resize(n);
+  uint64_t cmax = 0;
+  for (uint32_t v = 0; v < n; ++v) cmax = std::max(cmax, count[v]);
+  if (cmax < (1ull << 26)) {
+    std::vector<uint32_t> pos(cmax + 2, 0);  // bucket cmax - c holds count c
+    for (uint32_t v = 0; v < n; ++v) pos[cmax - count[v] + 1]++;
+    for (uint64_t b = 1; b <= cmax + 1; ++b) pos[b] += pos[b - 1];
+    for (uint32_t v = 0; v < n; ++v) ord[pos[cmax - count[v]]++] = v;
+    return;
+  }
   for (uint32_t v = 0; v < n; ++v) ord[v] = v;
   std::sort(ord.begin(), ord.end(), [count](uint32_t a, uint32_t b) {
     return count[a] != count[b] ? count[a] > count[b] : a < b;

@@ -175,3 +175,43 @@ def test_fixed_schedule_sample_counts(klib):
         assert 2 * n * math.exp(-2 * k * eps * eps) <= delta
         assert 2 * n * math.exp(-2 * (k - 1) * eps * eps) > delta
     assert kad.fixed_samples("adaptive", 0.01, 0.1, 8, 100) == 0
+
+
+def _bounds(n, seed, zero_frac=0.05, wide_frac=0.02):
+    """Intervals like a run's: counts with many ties, bounds around count/tau, some of zero
+    width and some very wide."""
+    rng = np.random.default_rng(seed)
+    count = rng.geometric(0.05, n).astype(np.uint64) - 1
+    tau = 5000.0
+    b = count / tau
+    w = rng.uniform(0.0, 0.004, n)
+    w[rng.random(n) < zero_frac] = 0.0
+    w[rng.random(n) < wide_frac] *= 50
+    lo = b - w * rng.uniform(0.5, 1.5, n)
+    hi = b + w * rng.uniform(0.5, 1.5, n)
+    return count, lo, hi
+
+
+def test_topk_select_matches_oracle_rank_intervals(klib, oracle_lib):
+    """kad_topk_select (which sorts only the bounds near the top) against the definition:
+    every node's rank interval from the oracle, the nodes with rank_lo <= k, by count
+    descending then id."""
+    for seed in range(8):
+        for n in (1, 2, 50, 3000):
+            count, lo, hi = _bounds(n, seed)
+            rlo, rhi = oracle_lib.rank_intervals(lo, hi)
+            for k in sorted({1, 2, 10, 100, n}):
+                if k > n:
+                    continue
+                want = sorted(np.nonzero(rlo <= k)[0].tolist(), key=lambda v: (-int(count[v]), v))
+                node, a_lo, a_hi = kad.topk_select(count, lo, hi, k)
+                assert node.tolist() == want, (seed, n, k)
+                assert a_lo.tolist() == [int(rlo[v]) for v in want], (seed, n, k)
+                assert a_hi.tolist() == [int(rhi[v]) for v in want], (seed, n, k)
+
+
+def test_topk_select_rejects_bad_k(klib):
+    count, lo, hi = _bounds(10, 0)
+    for k in (0, 11):
+        with pytest.raises(kad.KadError):
+            kad.topk_select(count, lo, hi, k)
