@@ -16,8 +16,8 @@
 // reduction serves all queries of a layer.  Snapshots are the per-group maxima of
 // the counts (all-nodes task; group = nodes with equal (L_l, L_u), kept current by
 // the reduction itself) or the counts (top-k task).  A query's main phase starts once
-// its computeDelta has run (its groups are then known); until then other queries
-// keep the device busy.
+// its computeDelta has run (its groups are then known); that runs as a task beside the
+// engine thread, and until it is done other queries keep the device busy.
 //
 // While tick t runs on the GPU the host evaluates tick t-1's checks.  A query that
 // stops has samples past its stopping point in flight: their hits are subtracted
@@ -34,6 +34,7 @@
 #include <cmath>
 #include <condition_variable>
 #include <deque>
+#include <future>
 #include <map>
 #include <memory>
 #include <thread>
@@ -106,6 +107,10 @@ struct Query {
   std::vector<uint32_t> topk, rlo, rhi;
   // times
   clk::time_point t_submit, t_admit, t_pilot, t_delta, t_final, t_done;
+  // computeDelta and the stopping check's setup, run beside the engine thread once the
+  // pilot's counts are in; declared last: destroying it first waits for the task, which
+  // writes the fields above
+  std::future<void> delta_task;
   ~Query() {
     if (final_ev) (void)hipEventDestroy(final_ev);
   }
@@ -222,6 +227,9 @@ class Engine {
  private:
   kad_status prepare(Query *q);
   kad_status admit();
+  // Queries whose computeDelta task has finished: their group ids into the pool; they
+  // enter the main phase.
+  kad_status delta_done();
   kad_status build(int li, Tick &t);
   kad_status launch(Lane &L, Tick &t);
   kad_status process(Lane &L, Tick &t, Tick &other);
@@ -279,6 +287,7 @@ class Engine {
   std::vector<Query *> done_;
   size_t rr_ = 0;
   bool serving_ = false;
+  bool delta_pending_ = false;  // a computeDelta task is still running
   std::atomic<uint64_t> ticks_launched_{0}, samples_launched_{0};
 };
 
@@ -904,32 +913,26 @@ kad_status Engine::process(Lane &L, Tick &t, Tick &other) {
       if (pc.kind == Kind::Pilot || pc.kind == Kind::PilotLast) {
         q->pilot_arcs += arcs;
         if (pc.kind == Kind::Pilot) continue;
-        // ---- computeDelta (Algorithm 2) on the pilot counts
+        // ---- computeDelta (Algorithm 2) on the pilot counts, beside the engine thread: on
+        // a graph of millions of nodes it takes tens of ms, and every other query would wait
         const uint32_t n = q->n;
         q->count0.assign(t.h_snap.p + pc.snap, t.h_snap.p + pc.snap + n);
-        q->lam_l.assign(n, q->p.epsilon);
-        q->lam_u.assign(n, q->p.epsilon);
-        q->L_l.resize(n);
-        q->L_u.resize(n);
         q->t_pilot = clk::now();
-        if (q->p.mode == KAD_TOPK)
-          topk_lambdas(n, q->p.k, q->count0.data(), q->alpha, q->p.epsilon, q->lam_l.data(),
-                       q->lam_u.data());
-        Groups groups;
-        compute_delta(n, q->count0.data(), q->alpha, q->omega, q->lam_l.data(), q->lam_u.data(),
-                      q->p.delta, q->eb, q->L_l.data(), q->L_u.data(), &q->C, &groups);
-        q->checker.reset(new StopChecker(n, q->p.mode, q->p.k, q->p.epsilon, q->omega,
-                                         q->L_l.data(), q->L_u.data(), std::move(groups)));
-        // group ids into the pool; the group maxima start at 0 with the counters
-        const auto &go = q->checker->group_of();
-        const uint32_t base = (uint32_t)q->base();
-        uint32_t *stage = group_stage_.p + base;  // the query's own pinned range
-        for (uint32_t v = 0; v < n; ++v) stage[v] = go[v] + base;
-        HIP_TRY(launch_copy_u32(group_pool_.p + base, stage, n, rs));
-        HIP_TRY(launch_zero_u32((uint32_t *)(gmax_pool_.p + base), 2ull * q->checker->groups(), rs));
-        q->delta_ready = true;
-        q->st = QState::Main;
-        q->t_delta = clk::now();
+        q->delta_task = std::async(std::launch::async, [q, n] {
+          q->lam_l.assign(n, q->p.epsilon);
+          q->lam_u.assign(n, q->p.epsilon);
+          q->L_l.resize(n);
+          q->L_u.resize(n);
+          if (q->p.mode == KAD_TOPK)
+            topk_lambdas(n, q->p.k, q->count0.data(), q->alpha, q->p.epsilon, q->lam_l.data(),
+                         q->lam_u.data());
+          Groups groups;
+          compute_delta(n, q->count0.data(), q->alpha, q->omega, q->lam_l.data(),
+                        q->lam_u.data(), q->p.delta, q->eb, q->L_l.data(), q->L_u.data(), &q->C,
+                        &groups);
+          q->checker.reset(new StopChecker(n, q->p.mode, q->p.k, q->p.epsilon, q->omega,
+                                           q->L_l.data(), q->L_u.data(), std::move(groups)));
+        });
         continue;
       }
       // ---- a main-phase check point (every B samples, or omega)
@@ -1028,9 +1031,34 @@ kad_status Engine::finalize(bool block) {
   return KAD_OK;
 }
 
+kad_status Engine::delta_done() {
+  delta_pending_ = false;
+  for (Query *q : active_) {
+    if (!q->delta_task.valid() || q->status != KAD_OK || q->st != QState::Pilot) continue;
+    if (q->delta_task.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
+      delta_pending_ = true;
+      continue;
+    }
+    q->delta_task.get();
+    // group ids into the pool; the group maxima start at 0 with the counters
+    hipStream_t rs = lanes_[q->lane].rs;
+    const auto &go = q->checker->group_of();
+    const uint32_t n = q->n, base = (uint32_t)q->base();
+    uint32_t *stage = group_stage_.p + base;  // the query's own pinned range
+    for (uint32_t v = 0; v < n; ++v) stage[v] = go[v] + base;
+    HIP_TRY(launch_copy_u32(group_pool_.p + base, stage, n, rs));
+    HIP_TRY(launch_zero_u32((uint32_t *)(gmax_pool_.p + base), 2ull * q->checker->groups(), rs));
+    q->delta_ready = true;
+    q->st = QState::Main;
+    q->t_delta = clk::now();
+  }
+  return KAD_OK;
+}
+
 kad_status Engine::step() {
   kad_status st = admit();
   if (st) return st;
+  if ((st = delta_done())) return st;
   bool acted = false;
   for (int li = 0; li < 2; ++li) {
     Lane &L = lanes_[li];
@@ -1057,7 +1085,7 @@ kad_status Engine::step() {
   const bool idle = !lanes_[0].busy() && !lanes_[1].busy();
   if (idle && (!grave_dev_.empty() || !grave_host_.empty())) release_graveyard();
   st = finalize(idle);
-  if (!acted && !idle) std::this_thread::sleep_for(std::chrono::microseconds(200));
+  if (!acted && (!idle || delta_pending_)) std::this_thread::sleep_for(std::chrono::microseconds(200));
   return st;
 }
 

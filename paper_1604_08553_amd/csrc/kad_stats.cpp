@@ -597,12 +597,23 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
       S.mult[m.a] += 1.0;
       S.mult[m.b] += 1.0;
     }
-    if (groups) {  // group = distinct (il, iu) pair
+    if (groups) {  // group = distinct (il, iu) pair, numbered by first appearance
       std::map<std::pair<uint32_t, uint32_t>, uint32_t> ids;
+      struct GMemo {  // most nodes repeat an earlier pair: a direct-mapped memo before the map
+        uint32_t a, b, g;
+        bool used;
+      };
+      std::vector<GMemo> gm(4096, GMemo{0, 0, 0, false});
       groups->of.resize(n);
       for (uint32_t v = 0; v < n; ++v) {
-        auto it = ids.emplace(std::make_pair(il[v], iu[v]), (uint32_t)ids.size()).first;
-        groups->of[v] = it->second;
+        GMemo &m = gm[((il[v] * 0x9E3779B1u) ^ (iu[v] * 0x85EBCA6Bu)) >> 20];
+        if (!(m.used && m.a == il[v] && m.b == iu[v])) {
+          const auto key = std::make_pair(il[v], iu[v]);
+          auto it = ids.find(key);
+          if (it == ids.end()) it = ids.emplace(key, (uint32_t)ids.size()).first;
+          m = GMemo{il[v], iu[v], it->second, true};
+        }
+        groups->of[v] = m.g;
       }
       groups->L_l.assign(ids.size(), 0.0);
       groups->L_u.assign(ids.size(), 0.0);
