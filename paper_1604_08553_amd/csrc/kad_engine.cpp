@@ -111,6 +111,9 @@ struct Query {
   // pilot's counts are in; declared last: destroying it first waits for the task, which
   // writes the fields above
   std::future<void> delta_task;
+  // the per-node outputs (Theorem 1 intervals, the top-k selection), computed beside the
+  // engine thread once the final counts have landed
+  std::future<void> out_task;
   ~Query() {
     if (final_ev) (void)hipEventDestroy(final_ev);
   }
@@ -288,6 +291,7 @@ class Engine {
   size_t rr_ = 0;
   bool serving_ = false;
   bool delta_pending_ = false;  // a computeDelta task is still running
+  bool out_pending_ = false;    // an outputs task is still running
   std::atomic<uint64_t> ticks_launched_{0}, samples_launched_{0};
 };
 
@@ -990,6 +994,23 @@ kad_status Engine::finalize(bool block) {
       ++j;
       continue;
     }
+    if (q->out_task.valid()) {  // outputs under way: done once the task is
+      if (!block && q->out_task.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
+        out_pending_ = true;
+        ++j;
+        continue;
+      }
+      q->out_task.get();
+      release_tiles(q);
+      q->checker.reset();
+      q->count0.clear();
+      q->count0.shrink_to_fit();
+      q->st = QState::Done;
+      q->t_done = clk::now();
+      done_.push_back(q);
+      active_.erase(active_.begin() + j);
+      continue;
+    }
     if (block) {
       HIP_TRY(hipEventSynchronize(q->final_ev));
     } else {
@@ -1013,11 +1034,19 @@ kad_status Engine::finalize(bool block) {
       q->o_bc = pickd(d ? d->bc : nullptr, q->bc);
       q->o_lo = pickd(d ? d->lower : nullptr, q->lo);
       q->o_hi = pickd(d ? d->upper : nullptr, q->hi);
-      memcpy(q->o_count, final_pool_.p + q->base(), (size_t)n * 8);
-      node_outputs(n, q->o_count, q->tau, q->omega, q->rule, q->p.epsilon, q->L_l.data(),
-                   q->L_u.data(), q->checker->group_of(), q->o_bc, q->o_lo, q->o_hi);
-      if (q->p.mode == KAD_TOPK)
-        topk_select(n, q->p.k, q->o_count, q->o_lo, q->o_hi, q->topk, q->rlo, q->rhi);
+      // O(n) on graphs of millions of nodes: beside the engine thread (the query's counter
+      // tiles, which the task reads, are released once it is done)
+      const uint64_t *fin = final_pool_.p + q->base();
+      q->out_task = std::async(std::launch::async, [q, n, fin] {
+        memcpy(q->o_count, fin, (size_t)n * 8);
+        node_outputs(n, q->o_count, q->tau, q->omega, q->rule, q->p.epsilon, q->L_l.data(),
+                     q->L_u.data(), q->checker->group_of(), q->o_bc, q->o_lo, q->o_hi);
+        if (q->p.mode == KAD_TOPK)
+          topk_select(n, q->p.k, q->o_count, q->o_lo, q->o_hi, q->topk, q->rlo, q->rhi);
+      });
+      out_pending_ = true;
+      ++j;
+      continue;
     }
     release_tiles(q);
     q->checker.reset();
@@ -1084,8 +1113,10 @@ kad_status Engine::step() {
   // block on a stopped query's counters only when nothing else can move
   const bool idle = !lanes_[0].busy() && !lanes_[1].busy();
   if (idle && (!grave_dev_.empty() || !grave_host_.empty())) release_graveyard();
+  out_pending_ = false;
   st = finalize(idle);
-  if (!acted && (!idle || delta_pending_)) std::this_thread::sleep_for(std::chrono::microseconds(200));
+  if (!acted && (!idle || delta_pending_ || out_pending_))
+    std::this_thread::sleep_for(std::chrono::microseconds(200));
   return st;
 }
 
