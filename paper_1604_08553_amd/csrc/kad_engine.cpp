@@ -994,6 +994,16 @@ kad_status Engine::finalize(bool block) {
       ++j;
       continue;
     }
+    // a query canceled or failed while its computeDelta task ran: the task reads count0 and
+    // writes the checker, which are released below
+    if (q->delta_task.valid()) {
+      if (!block && q->delta_task.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
+        out_pending_ = true;
+        ++j;
+        continue;
+      }
+      q->delta_task.get();
+    }
     if (q->out_task.valid()) {  // outputs under way: done once the task is
       if (!block && q->out_task.wait_for(std::chrono::seconds(0)) != std::future_status::ready) {
         out_pending_ = true;

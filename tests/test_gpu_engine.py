@@ -186,3 +186,29 @@ def test_server_cancel(kad, ctx):
         _same(srv.wait(t2, timeout=120.0), b)
     heavy.close()
     light.close()
+
+
+def test_server_cancel_during_compute_delta(kad, ctx):
+    """Queries canceled at several moments, some while their computeDelta task (top-k on a
+    300K-node graph) runs beside the engine thread: each one either completes with the
+    result of its single run or reports KAD_ECANCELED, and the server keeps serving."""
+    g = gg.chung_lu(300_000, 2.3, 8.0, 51)
+    G = kad.Graph(ctx, g)
+    light = kad.Graph(ctx, gg.workload("er2000"))
+    kw = [dict(epsilon=0.02, delta=0.1, seed=60 + i, mode="topk", k=10) for i in range(6)]
+    ref = [kad.run(ctx, G, **p) for p in kw]
+    b = kad.run(ctx, light, epsilon=0.01, delta=0.1, seed=3)
+    with kad.Server(ctx) as srv:
+        for delay in (0.0, 0.002, 0.005, 0.01, 0.02, 0.05):
+            _say("cancel after", delay)
+            ts = [srv.submit(G, **p) for p in kw]
+            time.sleep(delay)
+            srv.cancel()
+            for t, r in zip(ts, ref):
+                try:
+                    _same(srv.wait(t, timeout=120.0), r)
+                except kad.KadError as e:
+                    assert e.status == -8
+        _same(srv.wait(srv.submit(light, epsilon=0.01, delta=0.1, seed=3), timeout=120.0), b)
+    G.close()
+    light.close()
