@@ -289,37 +289,44 @@ uint32_t vd_undirected(uint32_t n, const uint32_t *row, const uint32_t *col) {
   return (uint32_t)std::min<uint64_t>(answer, UINT32_MAX);
 }
 
-// Strongly connected components by Tarjan's algorithm (iterative).  Components are
-// numbered in the order Tarjan completes them, which is a reverse topological order
-// of the condensation: every arc u->x between components has comp[u] > comp[x].
-uint32_t tarjan_scc(uint32_t n, const uint32_t *row, const uint32_t *col,
+// Strongly connected components by Tarjan's algorithm (iterative), with one component
+// known beforehand contracted into a single node: the nodes with mark[v] == gmark form a
+// strongly connected component represented by g, and gout lists the heads of its arcs that
+// leave it.  An arc into that component leads to g, and its other nodes are not visited
+// (they take g's number on return).  Contracting a strongly connected component leaves
+// the condensation as it was, so components are still numbered in the order Tarjan
+// completes them, a reverse topological order of the condensation: every arc u->x
+// between components has comp[u] > comp[x].
+uint32_t tarjan_scc(uint32_t n, const uint32_t *row, const uint32_t *col, const uint32_t *mark,
+                    uint32_t gmark, uint32_t g, const std::vector<uint32_t> &gout,
                     std::vector<uint32_t> &comp) {
-  std::vector<uint32_t> index(n, UINT32_MAX), low(n, 0), stack, call, edge;
+  std::vector<uint32_t> index(n, UINT32_MAX), low(n, 0), stack, call;
+  std::vector<std::pair<const uint32_t *, const uint32_t *>> next;  // arcs left, per call
   std::vector<uint8_t> on_stack(n, 0);
   comp.assign(n, UINT32_MAX);
   uint32_t next_index = 0, ncomp = 0;
-  stack.reserve(n);
+  auto open = [&](uint32_t u) {
+    index[u] = low[u] = next_index++;
+    stack.push_back(u);
+    on_stack[u] = 1;
+    call.push_back(u);
+    if (u == g)
+      next.emplace_back(gout.data(), gout.data() + gout.size());
+    else
+      next.emplace_back(col + row[u], col + row[u + 1]);
+  };
   for (uint32_t root = 0; root < n; ++root) {
-    if (index[root] != UINT32_MAX) continue;
-    call.push_back(root);
-    edge.push_back(row[root]);
-    index[root] = low[root] = next_index++;
-    stack.push_back(root);
-    on_stack[root] = 1;
+    if (index[root] != UINT32_MAX || (mark[root] == gmark && root != g)) continue;
+    open(root);
     while (!call.empty()) {
       const uint32_t u = call.back();
-      uint32_t &e = edge.back();
-      if (e < row[u + 1]) {
-        const uint32_t x = col[e++];
-        if (index[x] == UINT32_MAX) {
-          index[x] = low[x] = next_index++;
-          stack.push_back(x);
-          on_stack[x] = 1;
-          call.push_back(x);
-          edge.push_back(row[x]);
-        } else if (on_stack[x]) {
+      if (next.back().first != next.back().second) {
+        uint32_t x = *next.back().first++;
+        if (mark[x] == gmark) x = g;
+        if (index[x] == UINT32_MAX)
+          open(x);
+        else if (on_stack[x])
           low[u] = std::min(low[u], index[x]);
-        }
         continue;
       }
       if (low[u] == index[u]) {
@@ -333,11 +340,114 @@ uint32_t tarjan_scc(uint32_t n, const uint32_t *row, const uint32_t *col,
         ++ncomp;
       }
       call.pop_back();
-      edge.pop_back();
+      next.pop_back();
       if (!call.empty()) low[call.back()] = std::min(low[call.back()], low[u]);
     }
   }
+  for (uint32_t v = 0; v < n; ++v)
+    if (mark[v] == gmark) comp[v] = comp[g];
   return ncomp;
+}
+
+// Directed graphs: the bound over the condensation, weight(C) = ecc_out_C(r_C) +
+// ecc_in_C(r_C) + 1 (r_C: C's node of largest total degree, the first in id order among
+// equals), summed along the heaviest chain of components.  The node p of largest total
+// degree in the whole graph is r_C of its own component G, which in a sparse power-law
+// graph is the giant one; G and its weight come from three BFS from p, run level by level
+// on the worker threads, and Tarjan's algorithm then walks only the rest:
+//  1. forward over all nodes: the nodes p reaches;
+//  2. backward through those nodes only: the ones that also reach p, which is G (every
+//     node on a path from a node of G to p is in G).  A shortest path between two nodes
+//     of G never leaves G, so this BFS's depth is ecc_in_G(p);
+//  3. forward through G: ecc_out_G(p).
+uint32_t vd_directed(uint32_t n, const uint32_t *row, const uint32_t *col, const uint32_t *rrow,
+                     const uint32_t *rcol) {
+  auto degree = [&](uint32_t v) {
+    return (uint64_t)(row[v + 1] - row[v]) + (rrow[v + 1] - rrow[v]);
+  };
+  uint32_t p = 0;
+  for (uint32_t v = 1; v < n; ++v)
+    if (degree(v) > degree(p)) p = v;
+  constexpr uint32_t IN_G = 3;  // marks: 0 unseen, 1 reached from p, 2 and 3 in G
+  std::vector<uint32_t> mark(n, 0);
+  BfsScratch sc;
+  mark[p] = 1;
+  (void)bfs_levels(row, col, p, mark.data(), 0, 1, nullptr, sc);
+  mark[p] = 2;
+  const uint32_t ecc_in = bfs_levels(rrow, rcol, p, mark.data(), 1, 2, nullptr, sc);
+  mark[p] = IN_G;
+  const uint32_t ecc_out = bfs_levels(row, col, p, mark.data(), 2, IN_G, nullptr, sc);
+  // heads of the arcs that leave G, gathered over ranges of tails on the worker threads
+  std::vector<std::vector<uint32_t>> part(workers().size());
+  parallel_ranges(n, [&](uint32_t lo, uint32_t hi, unsigned w) {
+    std::vector<uint32_t> &out = part[w];
+    out.clear();
+    for (uint32_t v = lo; v < hi; ++v) {
+      if (mark[v] != IN_G) continue;
+      for (uint32_t e = row[v]; e < row[v + 1]; ++e)
+        if (mark[col[e]] != IN_G) out.push_back(col[e]);
+    }
+  });
+  std::vector<uint32_t> gout;
+  for (auto &pv : part) gout.insert(gout.end(), pv.begin(), pv.end());
+
+  std::vector<uint32_t> comp;
+  const uint32_t nc = tarjan_scc(n, row, col, mark.data(), IN_G, p, gout, comp);
+  const uint32_t cg = comp[p];
+  std::vector<uint32_t> root(nc, UINT32_MAX);
+  for (uint32_t v = 0; v < n; ++v) {
+    const uint32_t c = comp[v];
+    if (root[c] == UINT32_MAX || degree(v) > degree(root[c])) root[c] = v;
+  }
+  // members of each component, ids ascending (a counting pass; most components of a
+  // sparse directed graph are single nodes)
+  std::vector<uint32_t> mstart(nc + 1, 0), member(n);
+  for (uint32_t v = 0; v < n; ++v) mstart[comp[v] + 1]++;
+  for (uint32_t c = 0; c < nc; ++c) mstart[c + 1] += mstart[c];
+  {
+    std::vector<uint32_t> fill(mstart.begin(), mstart.end() - 1);
+    for (uint32_t v = 0; v < n; ++v) member[fill[comp[v]]++] = v;
+  }
+  std::vector<uint32_t> dist(n, UINT32_MAX), queue(n);
+  std::vector<uint64_t> weight(nc);
+  for (uint32_t c = 0; c < nc; ++c) {
+    if (c == cg) {  // r_G is p: no node has a larger degree, none before p an equal one
+      weight[c] = (uint64_t)ecc_out + ecc_in + 1;
+    } else if (mstart[c + 1] - mstart[c] == 1) {  // a single node: both eccentricities 0
+      weight[c] = 1;
+    } else {
+      weight[c] = (uint64_t)bfs_farthest(row, col, root[c], &comp, c, dist, queue) +
+                  bfs_farthest(rrow, rcol, root[c], &comp, c, dist, queue) + 1;
+    }
+  }
+  // Tarjan numbering is reverse topological: process components from the highest id
+  // (sources) down; heaviest[c] = weight[c] + max over arcs into c.
+  std::vector<uint64_t> heaviest(nc, 0);
+  uint64_t answer = 0;
+  auto best_into = [&](uint32_t c, uint32_t lo, uint32_t hi) {
+    uint64_t best = 0;
+    for (uint32_t i = lo; i < hi; ++i)
+      for (uint32_t v = member[i], e = rrow[v]; e < rrow[v + 1]; ++e) {
+        const uint32_t c2 = comp[rcol[e]];
+        if (c2 != c) best = std::max(best, heaviest[c2]);
+      }
+    return best;
+  };
+  for (uint32_t c = nc; c-- > 0;) {
+    uint64_t in_best = 0;
+    if (c == cg) {  // G's members over the worker threads (their arcs are most of the graph)
+      std::vector<uint64_t> part_best(workers().size(), 0);
+      parallel_ranges(mstart[c + 1] - mstart[c], [&](uint32_t lo, uint32_t hi, unsigned w) {
+        part_best[w] = best_into(c, mstart[c] + lo, mstart[c] + hi);
+      });
+      in_best = *std::max_element(part_best.begin(), part_best.end());
+    } else {
+      in_best = best_into(c, mstart[c], mstart[c + 1]);
+    }
+    heaviest[c] = in_best + weight[c];
+    answer = std::max(answer, heaviest[c]);
+  }
+  return (uint32_t)std::min<uint64_t>(answer, UINT32_MAX);
 }
 
 }  // namespace
@@ -369,41 +479,7 @@ int vertex_diameter(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32
     *exact = false;
     return 0;
   }
-  std::vector<uint32_t> comp;
-  const uint32_t nc = tarjan_scc(n, row, col, comp);
-  std::vector<uint32_t> root(nc, UINT32_MAX);
-  std::vector<uint64_t> root_deg(nc, 0);
-  for (uint32_t v = 0; v < n; ++v) {
-    const uint64_t d = (uint64_t)(row[v + 1] - row[v]) + (rrow[v + 1] - rrow[v]);
-    const uint32_t c = comp[v];
-    if (root[c] == UINT32_MAX || d > root_deg[c]) {
-      root[c] = v;
-      root_deg[c] = d;
-    }
-  }
-  std::vector<uint32_t> dist(n, UINT32_MAX), queue(n);
-  std::vector<uint64_t> weight(nc);
-  for (uint32_t c = 0; c < nc; ++c) {
-    weight[c] = (uint64_t)bfs_farthest(row, col, root[c], &comp, c, dist, queue) +
-                bfs_farthest(rrow, rcol, root[c], &comp, c, dist, queue) + 1;
-  }
-  // Tarjan numbering is reverse topological: process components from the highest id
-  // (sources) down; heaviest[c] = weight[c] + max over arcs into c.
-  std::vector<uint64_t> heaviest(nc, 0);
-  std::vector<std::vector<uint32_t>> members(nc);
-  for (uint32_t v = 0; v < n; ++v) members[comp[v]].push_back(v);
-  uint64_t answer = 0;
-  for (uint32_t c = nc; c-- > 0;) {
-    uint64_t in_best = 0;
-    for (uint32_t v : members[c])
-      for (uint32_t e = rrow[v]; e < rrow[v + 1]; ++e) {
-        const uint32_t c2 = comp[rcol[e]];
-        if (c2 != c) in_best = std::max(in_best, heaviest[c2]);
-      }
-    heaviest[c] = in_best + weight[c];
-    answer = std::max(answer, heaviest[c]);
-  }
-  *vd = (uint32_t)std::min<uint64_t>(answer, UINT32_MAX);
+  *vd = vd_directed(n, row, col, rrow, rcol);
   *exact = false;
   return 0;
 }

@@ -61,12 +61,56 @@ def _graphs():
     return out
 
 
+def _cycle_chains():
+    """Directed graphs of several strongly connected components in chains, where the node
+    of largest degree sits in a single-node component, in a small one between a larger
+    upstream and a downstream one, or in a DAG, and random chains of cycles with a hub."""
+    out = []
+    # hub 0 points at every node of two cycles, A (1..5) and B (6..12), and A -> B
+    src = [0] * 12 + list(range(1, 6)) + list(range(6, 13)) + [3]
+    dst = list(range(1, 13)) + [2, 3, 4, 5, 1] + [7, 8, 9, 10, 11, 12, 6] + [9]
+    out.append(gg.csr_from_edges(13, src, dst, True, "hub_into_cycles"))
+    # cycle U (0..19) -> two-node hub {20, 21} with many arcs -> cycle D (22..29)
+    src = list(range(20)) + list(range(20)) + [20, 21] + [20] * 8 + list(range(22, 30))
+    dst = [(i + 1) % 20 for i in range(20)] + [20 + (i % 2) for i in range(20)] + [21, 20] \
+        + list(range(22, 30)) + [22 + (i + 1) % 8 for i in range(8)]
+    out.append(gg.csr_from_edges(30, src, dst, True, "cycle_hub_cycle"))
+    rng = np.random.default_rng(5)
+    n = 60
+    u, v = rng.integers(0, n, 300), rng.integers(0, n, 300)
+    out.append(gg.csr_from_edges(n, np.minimum(u, v), np.maximum(u, v), True, "dag60"))
+    for seed in range(6):
+        rng = np.random.default_rng(100 + seed)
+        sizes = rng.integers(1, 9, 12)
+        start = np.concatenate([[0], np.cumsum(sizes)])
+        n = int(start[-1]) + 1
+        hub = int(rng.integers(0, n))
+        src, dst = [], []
+        for b in range(len(sizes)):
+            members = np.arange(start[b], start[b + 1])
+            src += list(members)
+            dst += list(np.roll(members, -1))
+        for _ in range(40):  # arcs between blocks, lower block to higher
+            a, b = sorted(rng.choice(len(sizes), 2, replace=False))
+            src.append(int(rng.integers(start[a], start[a + 1])))
+            dst.append(int(rng.integers(start[b], start[b + 1])))
+        others = [x for x in range(n) if x != hub]
+        for x in rng.choice(others, 25, replace=False):  # hub degree above every other
+            if rng.random() < 0.5:
+                src.append(hub); dst.append(int(x))
+            else:
+                src.append(int(x)); dst.append(hub)
+        out.append(gg.csr_from_edges(n, src, dst, True, f"cycle_chain{seed}"))
+    return out
+
+
 def test_vertex_diameter_matches_oracle(klib, oracle_lib):
-    for g in _graphs():
+    for g in _graphs() + _cycle_chains():
         for limit in (1e9, 0.0):
             assert kad.vertex_diameter(g, limit) == oracle_lib.vertex_diameter(g, limit), (g.name, limit)
     # levels of thousands of nodes: the bound's BFS runs them on several threads
-    for g in (gg.chung_lu(200_000, 2.3, 8.0, 11), gg.damaged_grid(300, 300, 0.05, 2)):
+    for g in (gg.chung_lu(200_000, 2.3, 8.0, 11), gg.damaged_grid(300, 300, 0.05, 2),
+              gg.chung_lu_directed(200_000, 2.5, 2.1, 8.0, 12)):
         assert kad.vertex_diameter(g, 0.0) == oracle_lib.vertex_diameter(g, 0.0), g.name
 
 
