@@ -267,11 +267,20 @@ uint32_t bfs_levels(const uint32_t *rp, const uint32_t *cl, uint32_t src, uint32
 // no arc joins two of them, so the bound below is the largest 2 ecc(r_C) + 1 over the
 // components C (r_C: C's node of largest degree, the first in id order among equals; an
 // isolated node gives 1).  One BFS labels a component and finds r_C, a second measures
-// ecc(r_C).
+// ecc(r_C).  The node of largest degree in the whole graph (the first in id order among
+// equals) is r_C of its own component, the giant one of a sparse power-law graph, so that
+// component goes first and takes a single BFS from it.
 uint32_t vd_undirected(uint32_t n, const uint32_t *row, const uint32_t *col) {
   std::vector<uint32_t> mark(n, 0);  // 0 unseen, 1 labelled, 2 measured
   BfsScratch sc;
   uint64_t answer = 0;
+  uint32_t p = 0;
+  for (uint32_t v = 1; v < n; ++v)
+    if (row[v + 1] - row[v] > row[p + 1] - row[p]) p = v;
+  if (row[p + 1] > row[p]) {
+    mark[p] = 2;
+    answer = 2ull * bfs_levels(row, col, p, mark.data(), 0, 2, nullptr, sc) + 1;
+  }
   for (uint32_t v = 0; v < n; ++v) {
     if (mark[v] != 0) continue;
     if (row[v + 1] == row[v]) {
