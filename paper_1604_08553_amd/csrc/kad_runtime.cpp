@@ -654,32 +654,96 @@ using kad::DEFAULT_BATCH;
 using kad::dev_view;
 using kad::graph_vd;
 
-// Rows sorted strictly ascending, heads in range, no self-loops.
+// Rows sorted strictly ascending, heads in range, no self-loops.  The row pointers are
+// checked first, so that no row is read before its bounds are known to lie within the
+// arcs; the rows before the first bad pointer are then checked in ranges on the worker
+// threads.  The error reported is that of the first bad node.
 kad_status check_rows(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32_t *col,
                       const char *what) {
   if (row[0] != 0 || row[n] != arcs) return fail(KAD_EINVAL, "%s: row_ptr[0] must be 0 and row_ptr[n] = arcs", what);
-  for (uint32_t v = 0; v < n; ++v) {
-    if (row[v + 1] < row[v]) return fail(KAD_EINVAL, "%s: row_ptr decreases at node %u", what, v);
-    for (uint32_t e = row[v]; e < row[v + 1]; ++e) {
-      const uint32_t x = col[e];
-      if (x >= n) return fail(KAD_EINVAL, "%s: node %u has out-of-range neighbour %u", what, v, x);
-      if (x == v) return fail(KAD_EINVAL, "%s: self-loop at node %u", what, v);
-      if (e > row[v] && col[e - 1] >= x)
-        return fail(KAD_EINVAL, "%s: row %u is not strictly ascending", what, v);
+  uint32_t d = n;  // the first node whose row pointer decreases or passes the arcs
+  for (uint32_t v = 0; v < n; ++v)
+    if (row[v + 1] < row[v] || row[v + 1] > arcs) {
+      d = v;
+      break;
     }
+  // per range: the first bad row (kind 1 head out of range, 2 self-loop, 3 not ascending)
+  struct Bad { uint32_t v = UINT32_MAX, kind = 0, x = 0; };
+  std::vector<Bad> bad(kad::worker_count());
+  kad::parallel_ranges(d, [&](uint32_t lo, uint32_t hi, unsigned w) {
+    Bad b;
+    for (uint32_t v = lo; v < hi && b.kind == 0; ++v)
+      for (uint32_t e = row[v]; e < row[v + 1]; ++e) {
+        const uint32_t x = col[e];
+        const uint32_t k = x >= n ? 1u : x == v ? 2u : (e > row[v] && col[e - 1] >= x) ? 3u : 0u;
+        if (k) {
+          b = {v, k, x};
+          break;
+        }
+      }
+    bad[w] = b;
+  });
+  const Bad b = *std::min_element(bad.begin(), bad.end(),
+                                  [](const Bad &a, const Bad &c) { return a.v < c.v; });
+  switch (b.kind) {
+    case 1: return fail(KAD_EINVAL, "%s: node %u has out-of-range neighbour %u", what, b.v, b.x);
+    case 2: return fail(KAD_EINVAL, "%s: self-loop at node %u", what, b.v);
+    case 3: return fail(KAD_EINVAL, "%s: row %u is not strictly ascending", what, b.v);
+    default: break;
+  }
+  if (d < n) {
+    if (row[d + 1] < row[d]) return fail(KAD_EINVAL, "%s: row_ptr decreases at node %u", what, d);
+    return fail(KAD_EINVAL, "%s: row_ptr[%u] passes the arc count", what, d + 1);
   }
   return KAD_OK;
 }
 
+// The in-rows of (row, col): for each node x, the tails of the arcs into x, ascending.
+// The tails are split into K chunks of about equal arc counts, one per worker thread;
+// each chunk counts its heads, a prefix over (head, chunk) gives every chunk its place in
+// each in-row, and each chunk then writes its arcs in tail order, so every in-row comes
+// out ascending.  The per-chunk counts take 4 n bytes per chunk (K is cut to keep them
+// within 1 GiB).
 void transpose(uint32_t n, const std::vector<uint32_t> &row, const std::vector<uint32_t> &col,
                std::vector<uint32_t> &trow, std::vector<uint32_t> &tcol) {
+  const uint64_t m = col.size();
+  const uint64_t by_mem = std::max<uint64_t>(1, (1ull << 28) / std::max<uint32_t>(n, 1));
+  const unsigned K = (unsigned)std::min<uint64_t>(
+      {(uint64_t)kad::parallel_threads((uint32_t)std::min<uint64_t>(m, UINT32_MAX)),
+       (uint64_t)kad::worker_count(), by_mem});
+  std::vector<uint32_t> cut(K + 1);  // chunk k: tails [cut[k], cut[k + 1])
+  for (unsigned k = 0; k < K; ++k)
+    cut[k] = (uint32_t)(std::lower_bound(row.begin(), row.end(), (uint32_t)(m * k / K)) - row.begin());
+  cut[K] = n;
+  std::unique_ptr<uint32_t[]> cnt(new uint32_t[(size_t)K * n]);  // [chunk][head]
+  kad::parallel_tasks(K, [&](unsigned k) {
+    uint32_t *c = cnt.get() + (size_t)k * n;
+    std::fill(c, c + n, 0u);
+    for (uint32_t e = row[cut[k]]; e < row[cut[k + 1]]; ++e) c[col[e]]++;
+  });
   trow.assign((size_t)n + 1, 0);
-  for (uint32_t x : col) trow[x + 1]++;
-  for (uint32_t v = 0; v < n; ++v) trow[v + 1] += trow[v];
-  tcol.resize(col.size());
-  std::vector<uint32_t> fill(trow.begin(), trow.end() - 1);
-  for (uint32_t v = 0; v < n; ++v)
-    for (uint32_t e = row[v]; e < row[v + 1]; ++e) tcol[fill[col[e]]++] = v;  // v ascending
+  kad::parallel_ranges(n, [&](uint32_t lo, uint32_t hi, unsigned) {
+    for (uint32_t x = lo; x < hi; ++x) {
+      uint32_t s = 0;
+      for (unsigned k = 0; k < K; ++k) {
+        uint32_t &c = cnt[(size_t)k * n + x];
+        const uint32_t t = c;
+        c = s;  // chunk k's first place in in-row x, counted from the row's start
+        s += t;
+      }
+      trow[x + 1] = s;
+    }
+  });
+  for (uint32_t x = 0; x < n; ++x) trow[x + 1] += trow[x];
+  tcol.resize(m);
+  kad::parallel_tasks(K, [&](unsigned k) {
+    uint32_t *c = cnt.get() + (size_t)k * n;
+    for (uint32_t v = cut[k]; v < cut[k + 1]; ++v)
+      for (uint32_t e = row[v]; e < row[v + 1]; ++e) {
+        const uint32_t x = col[e];
+        tcol[trow[x] + c[x]++] = v;
+      }
+  });
 }
 
 hipStream_t pick_stream(kad_ctx *ctx, void *s) { return s ? (hipStream_t)s : ctx->stream; }

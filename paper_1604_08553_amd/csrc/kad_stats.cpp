@@ -103,6 +103,19 @@ void parallel_ranges(uint32_t n, const std::function<void(uint32_t, uint32_t, un
   });
 }
 
+unsigned worker_count() { return workers().size(); }
+
+void parallel_tasks(unsigned tasks, const std::function<void(unsigned)> &f) {
+  const unsigned nw = workers().size();
+  for (unsigned b = 0; b < tasks; b += nw) {
+    const unsigned k = std::min(nw, tasks - b);
+    if (k == 1)
+      f(b);
+    else
+      workers().run(k, [&](unsigned w) { f(b + w); });
+  }
+}
+
 // ------------------------------------------------------------------ schedule
 
 uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c) {

@@ -13,6 +13,9 @@ namespace kad {
 // small n).  Used for per-node loops whose iterations are independent.
 void parallel_ranges(uint32_t n, const std::function<void(uint32_t, uint32_t, unsigned)> &f);
 unsigned parallel_threads(uint32_t n);
+// Run f(0), ..., f(tasks - 1) on the same worker threads, one task per thread at a time.
+void parallel_tasks(unsigned tasks, const std::function<void(unsigned)> &f);
+unsigned worker_count();
 
 uint64_t omega_of(double epsilon, double delta, uint32_t vd, double c);
 uint64_t omega_edges_of(double epsilon, double delta, uint32_t vd, double c);
