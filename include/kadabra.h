@@ -41,8 +41,12 @@ typedef enum {
   KAD_ETOOSMALL = -5, /* an output buffer is too small; the needed size is reported */
   KAD_EOVERFLOW = -6, /* a result does not fit the library's fixed-width arithmetic */
   KAD_ERNG = -7,      /* a bounded random draw was rejected 64 times (probability < 2^-64) */
-  KAD_ECANCELED = -8  /* a served query was dropped before it started */
+  KAD_ECANCELED = -8, /* a served query was dropped before it started */
+  KAD_EINTERNAL = -9  /* an unexpected host-side failure (the message says what) */
 } kad_status;
+/* No C++ exception leaves the library: every call that returns a kad_status turns one
+ * into a status (host memory or threads exhausted: KAD_ENOMEM, anything else:
+ * KAD_EINTERNAL) with a message from kad_last_error(). */
 
 enum { KAD_MEM_HOST = 0, KAD_MEM_DEVICE = 1 };
 enum { KAD_ALL_NODES = 0, KAD_TOPK = 1 };

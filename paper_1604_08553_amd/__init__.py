@@ -35,7 +35,7 @@ SAMPLE_OVERFLOW, SAMPLE_CAPACITY, SAMPLE_RNG = 1, 2, 4
 
 _STATUS = {0: "ok", -1: "invalid argument", -2: "out of memory", -3: "device error",
            -4: "busy", -5: "buffer too small", -6: "overflow", -7: "random draw rejected",
-           -8: "canceled"}
+           -8: "canceled", -9: "internal error"}
 EBUSY = -4
 
 

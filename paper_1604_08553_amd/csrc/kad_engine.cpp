@@ -1143,6 +1143,13 @@ kad_status context_engine(kad_ctx *ctx, Engine **out) {
 
 void destroy_engine(Engine *e) { delete e; }
 
+// Let a query's host tasks end (computeDelta reads its pilot counts; the outputs task reads
+// the engine's final-count pool), so that the engine may be destroyed.
+void wait_tasks(Query *q) {
+  if (q->delta_task.valid()) q->delta_task.wait();
+  if (q->out_task.valid()) q->out_task.wait();
+}
+
 }  // namespace kad
 
 // ---------------------------------------------------------------- C ABI
@@ -1234,8 +1241,12 @@ void server_loop(kad_server *sv) {
       cancel = sv->cancel_req != sv->cancel_done;
       sv->cancel_done = sv->cancel_req;
     }
-    if (cancel) st = sv->eng->cancel_all();
-    if (!st && sv->eng->busy()) st = sv->eng->step();
+    try {
+      if (cancel) st = sv->eng->cancel_all();
+      if (!st && sv->eng->busy()) st = sv->eng->step();
+    } catch (...) {
+      st = kad::status_of_exception();
+    }
     std::vector<kad::Query *> done = sv->eng->take_done();
     if (st || !done.empty()) {
       std::lock_guard<std::mutex> lk(sv->mu);
@@ -1272,7 +1283,7 @@ kad_status server_take(kad_server *sv, uint64_t ticket, kad_result *r, std::uniq
 extern "C" {
 
 kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *graphs,
-                         const kad_params *params, kad_result *results, kad_status *status) {
+                         const kad_params *params, kad_result *results, kad_status *status) try {
   using kad::fail;
   if (!ctx || (count && (!graphs || !params || !results)))
     return fail(KAD_EINVAL, "NULL argument");
@@ -1303,14 +1314,20 @@ kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *g
     qs[i]->t_submit = now;
     eng.enqueue(qs[i].get());
   }
-  while (eng.busy()) {
-    if ((st = eng.step())) {
-      // the engine may still point at this call's queries: start over next time
-      std::string msg = kad_last_error();
-      kad::destroy_engine(ctx->engine);
-      ctx->engine = nullptr;
-      return fail(st, "%s", msg.c_str());
-    }
+  // on a failure the engine may still point at this call's queries, and their host tasks
+  // at its pools: those end first, and the next call starts with a new engine
+  auto drop_engine = [&](kad_status why) {
+    std::string msg = kad_last_error();
+    for (auto &q : qs) kad::wait_tasks(q.get());
+    kad::destroy_engine(ctx->engine);
+    ctx->engine = nullptr;
+    return fail(why, "%s", msg.c_str());
+  };
+  try {
+    while (eng.busy())
+      if ((st = eng.step())) return drop_engine(st);
+  } catch (...) {
+    return drop_engine(kad::status_of_exception());
   }
   (void)eng.take_done();  // every query of this call is done
   kad_status first = KAD_OK;
@@ -1327,9 +1344,11 @@ kad_status kad_run_batch(kad_ctx *ctx, uint32_t count, const kad_graph *const *g
   }
   if (first != KAD_OK) return fail(first, "%s", first_msg.c_str());
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_server_create(kad_ctx *ctx, kad_server **out) {
+kad_status kad_server_create(kad_ctx *ctx, kad_server **out) try {
   using kad::fail;
   if (!ctx || !out) return fail(KAD_EINVAL, "NULL argument");
   *out = nullptr;
@@ -1347,10 +1366,12 @@ kad_status kad_server_create(kad_ctx *ctx, kad_server **out) {
   claim.release_to_owner();  // released by kad_server_destroy
   *out = sv.release();
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_server_submit(kad_server *sv, const kad_graph *g, const kad_params *p,
-                             uint64_t *ticket) {
+                             uint64_t *ticket) try {
   using kad::fail;
   if (!sv || !g || !p || !ticket) return fail(KAD_EINVAL, "NULL argument");
   if (g->ctx != sv->ctx) return fail(KAD_EINVAL, "the graph belongs to another context");
@@ -1371,9 +1392,11 @@ kad_status kad_server_submit(kad_server *sv, const kad_graph *g, const kad_param
   sv->queries[q->ticket] = std::move(q);
   sv->cv_work.notify_one();
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_server_poll(kad_server *sv, uint64_t ticket, kad_result *r) {
+kad_status kad_server_poll(kad_server *sv, uint64_t ticket, kad_result *r) try {
   using kad::fail;
   if (!sv || !r) return fail(KAD_EINVAL, "NULL argument");
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -1383,9 +1406,11 @@ kad_status kad_server_poll(kad_server *sv, uint64_t ticket, kad_result *r) {
     return fail(KAD_EBUSY, "query %llu is running", (unsigned long long)ticket);
   }
   return server_take(sv, ticket, r, lk);
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_server_wait(kad_server *sv, uint64_t ticket, kad_result *r, double timeout_s) {
+kad_status kad_server_wait(kad_server *sv, uint64_t ticket, kad_result *r, double timeout_s) try {
   using kad::fail;
   if (!sv || !r) return fail(KAD_EINVAL, "NULL argument");
   std::unique_lock<std::mutex> lk(sv->mu);
@@ -1402,19 +1427,23 @@ kad_status kad_server_wait(kad_server *sv, uint64_t ticket, kad_result *r, doubl
     return fail(KAD_ECANCELED, "query %llu was dropped by kad_server_destroy", (unsigned long long)ticket);
   if (!sv->finished.count(ticket)) return fail(sv->fatal, "server stopped: %s", sv->fatal_msg.c_str());
   return server_take(sv, ticket, r, lk);
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_server_stats(kad_server *sv, uint64_t *completed, uint64_t *launches,
-                            uint64_t *samples) {
+                            uint64_t *samples) try {
   if (!sv) return kad::fail(KAD_EINVAL, "NULL server");
   std::lock_guard<std::mutex> lk(sv->mu);
   if (completed) *completed = sv->completed;
   if (launches) *launches = sv->eng->ticks_launched() - sv->launches0;
   if (samples) *samples = sv->eng->samples_launched() - sv->samples0;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_server_cancel(kad_server *sv) {
+kad_status kad_server_cancel(kad_server *sv) try {
   if (!sv) return kad::fail(KAD_EINVAL, "NULL server");
   std::lock_guard<std::mutex> lk(sv->mu);
   for (kad::Query *q : sv->incoming) {  // not yet seen by the engine
@@ -1428,9 +1457,11 @@ kad_status kad_server_cancel(kad_server *sv) {
   sv->cv_work.notify_one();
   sv->cv_done.notify_all();
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_server_destroy(kad_server *sv) {
+kad_status kad_server_destroy(kad_server *sv) try {
   if (!sv) return KAD_OK;
   {
     std::lock_guard<std::mutex> lk(sv->mu);
@@ -1445,12 +1476,15 @@ kad_status kad_server_destroy(kad_server *sv) {
   kad_ctx *ctx = sv->ctx;
   if (sv->eng) sv->eng->set_serving(false);
   if (sv->fatal) {  // the engine may still point at this server's queries
+    for (auto &kv : sv->queries) kad::wait_tasks(kv.second.get());
     kad::destroy_engine(ctx->engine);
     ctx->engine = nullptr;
   }
   delete sv;
   ctx->busy.store(false);
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 }  // extern "C"

@@ -18,6 +18,10 @@
 namespace kad {
 
 kad_status fail(kad_status st, const char *fmt, ...);
+// The status of the exception being handled, for the catch (...) handlers of the C entry
+// points (no exception may cross the C boundary): host memory or threads exhausted give
+// KAD_ENOMEM, anything else KAD_EINTERNAL, with the message set as fail() sets it.
+kad_status status_of_exception();
 
 #define HIP_TRY(expr)                                                                   \
   do {                                                                                  \

@@ -15,6 +15,7 @@
 #include <chrono>
 #include <memory>
 #include <string>
+#include <system_error>
 #include <type_traits>
 #include <vector>
 
@@ -33,6 +34,20 @@ kad_status fail(kad_status st, const char *fmt, ...) {
   va_end(ap);
   g_error = buf;
   return st;
+}
+
+kad_status status_of_exception() {
+  try {
+    throw;
+  } catch (const std::bad_alloc &) {
+    return fail(KAD_ENOMEM, "host memory exhausted");
+  } catch (const std::system_error &e) {
+    return fail(KAD_ENOMEM, "host resources exhausted: %s", e.what());
+  } catch (const std::exception &e) {
+    return fail(KAD_EINTERNAL, "internal error: %s", e.what());
+  } catch (...) {
+    return fail(KAD_EINTERNAL, "internal error");
+  }
 }
 
 kad_status OutSet::ensure(uint32_t want_cap, uint32_t want_stride, hipStream_t rs) {
@@ -1055,7 +1070,7 @@ extern "C" {
 
 const char *kad_last_error(void) { return kad::g_error.c_str(); }
 
-kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **out) {
+kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **out) try {
   if (!out) return fail(KAD_EINVAL, "out is NULL");
   *out = nullptr;
   int ndev = 0;
@@ -1084,9 +1099,11 @@ kad_status kad_ctx_create(int hip_device, uint64_t hbm_budget_bytes, kad_ctx **o
   HIP_TRY(kad::noalloc_scratch(&c->noalloc));
   *out = c.release();
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_ctx_destroy(kad_ctx *ctx) {
+kad_status kad_ctx_destroy(kad_ctx *ctx) try {
   if (!ctx) return KAD_OK;
   (void)hipSetDevice(ctx->device);
   kad::destroy_engine(ctx->engine);  // waits for its work on the context's streams
@@ -1102,12 +1119,14 @@ kad_status kad_ctx_destroy(kad_ctx *ctx) {
   if (ctx->cstream) (void)hipStreamDestroy(ctx->cstream);
   delete ctx;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_graph_create(kad_ctx *ctx, uint32_t n, uint64_t arcs, int directed,
                             const uint32_t *row_ptr, const uint32_t *col,
                             const uint32_t *rrow_ptr, const uint32_t *rcol, int mem,
-                            kad_graph **out) {
+                            kad_graph **out) try {
   if (!ctx || !out || !row_ptr || (!col && arcs)) return fail(KAD_EINVAL, "NULL argument");
   *out = nullptr;
   if (n < 2) return fail(KAD_EINVAL, "a graph needs at least 2 nodes");
@@ -1180,9 +1199,11 @@ kad_status kad_graph_create(kad_ctx *ctx, uint32_t n, uint64_t arcs, int directe
   ctx->used_graphs += g->bytes;
   *out = g.release();
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_graph_destroy(kad_graph *g) {
+kad_status kad_graph_destroy(kad_graph *g) try {
   if (!g) return KAD_OK;
   (void)hipSetDevice(g->ctx->device);
   if (g->owns_fwd) {
@@ -1197,6 +1218,8 @@ kad_status kad_graph_destroy(kad_graph *g) {
   g->ctx->used_graphs -= std::min(g->ctx->used_graphs, g->bytes);
   delete g;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 // ---------------------------------------------------------------- host statistics
@@ -1219,7 +1242,7 @@ uint64_t kad_default_interval(uint64_t omega) { return kad::interval_of(omega); 
 kad_status kad_vertex_diameter(uint32_t n, uint64_t arcs, int directed, const uint32_t *row_ptr,
                                const uint32_t *col, const uint32_t *rrow_ptr,
                                const uint32_t *rcol, double exact_limit, uint32_t *vd,
-                               uint32_t *exact) {
+                               uint32_t *exact) try {
   if (!vd || !exact || !row_ptr || (arcs && !col)) return fail(KAD_EINVAL, "NULL argument");
   if (directed && (!rrow_ptr || !rcol)) return fail(KAD_EINVAL, "directed graph needs in-rows");
   bool ex = false;
@@ -1228,6 +1251,8 @@ kad_status kad_vertex_diameter(uint32_t n, uint64_t arcs, int directed, const ui
     return fail(KAD_EINVAL, "bad graph");
   *exact = ex ? 1u : 0u;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 double kad_bound_f(double btilde, double L, double omega, double tau) {
@@ -1239,19 +1264,21 @@ double kad_bound_g(double btilde, double L, double omega, double tau) {
 
 kad_status kad_compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t omega,
                              const double *lambda_l, const double *lambda_u, double delta,
-                             double balance_eps, double *L_l, double *L_u, double *C) {
+                             double balance_eps, double *L_l, double *L_u, double *C) try {
   if (!n || !count0 || !lambda_l || !lambda_u || !L_l || !L_u || !alpha)
     return fail(KAD_EINVAL, "bad argument");
   if (!(delta > 0 && delta < 1) || !(balance_eps > 0 && balance_eps < 0.5))
     return fail(KAD_EINVAL, "delta must be in (0,1) and balance_eps in (0,0.5)");
   kad::compute_delta(n, count0, alpha, omega, lambda_l, lambda_u, delta, balance_eps, L_l, L_u, C);
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cmax, uint64_t alpha,
                                   uint64_t omega, double lambda_l, double lambda_u, double delta,
                                   double balance_eps, uint32_t *group_of_count, double *L_l,
-                                  double *L_u, uint32_t *ngroups, double *C) {
+                                  double *L_u, uint32_t *ngroups, double *C) try {
   if (!n || !hist || !alpha || !group_of_count || !L_l || !L_u || !ngroups)
     return fail(KAD_EINVAL, "bad argument");
   if (!(delta > 0 && delta < 1) || !(balance_eps > 0 && balance_eps < 0.5))
@@ -1271,19 +1298,23 @@ kad_status kad_compute_delta_hist(uint32_t n, const uint64_t *hist, uint64_t cma
   }
   *ngroups = (uint32_t)groups.L_l.size();
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha,
-                            double epsilon, double *lambda_l, double *lambda_u) {
+                            double epsilon, double *lambda_l, double *lambda_u) try {
   if (!n || k < 1 || k > n || !count0 || !lambda_l || !lambda_u || !alpha)
     return fail(KAD_EINVAL, "bad argument");
   kad::topk_lambdas(n, k, count0, alpha, epsilon, lambda_l, lambda_u);
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_topk_select(uint32_t n, uint32_t k, const uint64_t *count, const double *lower,
                            const double *upper, uint32_t cap, uint32_t *node, uint32_t *rank_lo,
-                           uint32_t *rank_hi, uint32_t *len) {
+                           uint32_t *rank_hi, uint32_t *len) try {
   if (!n || k < 1 || k > n || !count || !lower || !upper || !len)
     return fail(KAD_EINVAL, "bad argument");
   std::vector<uint32_t> sel, rlo, rhi;
@@ -1296,6 +1327,8 @@ kad_status kad_topk_select(uint32_t n, uint32_t k, const uint64_t *count, const 
     if (rank_hi) rank_hi[q] = rhi[q];
   }
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *count, uint64_t tau,
@@ -1313,7 +1346,7 @@ int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *coun
 kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                             uint64_t first, uint32_t count, uint32_t *s, uint32_t *t,
                             uint64_t *path_off, uint32_t *path_nodes, uint64_t path_cap,
-                            uint64_t *arcs_scanned, uint32_t *flags, void *hip_stream) {
+                            uint64_t *arcs_scanned, uint32_t *flags, void *hip_stream) try {
   if (!ctx || !g) return fail(KAD_EINVAL, "NULL context or graph");
   if (path_nodes && !path_off) return fail(KAD_EINVAL, "path_nodes needs path_off");
   if (phase > 255) return fail(KAD_EINVAL, "phase must fit 8 bits");
@@ -1365,11 +1398,13 @@ kad_status kad_sample_paths(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uin
   if (path_off) path_off[count] = off;
   if (short_buf) return fail(KAD_ETOOSMALL, "path_nodes needs %llu entries", (unsigned long long)off);
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                           uint64_t first, uint64_t count, uint64_t *count_out,
-                          uint64_t *arcs_scanned, void *hip_stream) {
+                          uint64_t *arcs_scanned, void *hip_stream) try {
   if (!ctx || !g || !count_out) return fail(KAD_EINVAL, "NULL argument");
   kad::CtxClaim claim(ctx);
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
@@ -1399,11 +1434,13 @@ kad_status kad_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint3
   for (uint32_t v = 0; v < g->n; ++v) count_out[v] += ctx->h_count.p[v];
   if (arcs_scanned) *arcs_scanned = arcs;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_edge_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                                uint64_t first, uint64_t count, uint64_t *count_out,
-                               uint64_t *arcs_scanned, void *hip_stream) {
+                               uint64_t *arcs_scanned, void *hip_stream) try {
   if (!ctx || !g || !count_out) return fail(KAD_EINVAL, "NULL argument");
   if (phase > 255) return fail(KAD_EINVAL, "phase must fit 8 bits");
   const uint64_t items = kad::run_items(g, KAD_TARGET_EDGES);
@@ -1442,15 +1479,19 @@ kad_status kad_edge_hit_counts(kad_ctx *ctx, const kad_graph *g, uint64_t seed, 
   for (uint64_t e = 0; e < items; ++e) count_out[e] += ctx->h_count.p[e];
   if (arcs_scanned) *arcs_scanned = arcs;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_graph_edge_count(const kad_graph *g, uint64_t *count) {
+kad_status kad_graph_edge_count(const kad_graph *g, uint64_t *count) try {
   if (!g || !count) return fail(KAD_EINVAL, "NULL argument");
   *count = kad::run_items(g, KAD_TARGET_EDGES);
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_graph_edge_ids(const kad_graph *g, uint32_t *eid) {
+kad_status kad_graph_edge_ids(const kad_graph *g, uint32_t *eid) try {
   if (!g || (!eid && g->arcs)) return fail(KAD_EINVAL, "NULL argument");
   if (g->directed) {
     for (uint64_t e = 0; e < g->arcs; ++e) eid[e] = (uint32_t)e;
@@ -1461,13 +1502,15 @@ kad_status kad_graph_edge_ids(const kad_graph *g, uint32_t *eid) {
   if (st) return st;
   memcpy(eid, g->eid.data(), (size_t)g->arcs * 4);
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 // ---------------------------------------------------------------- hit counts, no allocation
 
 kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t seed, uint32_t phase,
                                   uint64_t first, uint64_t count, uint64_t *count_dev,
-                                  uint64_t *arcs_dev, uint32_t *flags_dev, void *hip_stream) {
+                                  uint64_t *arcs_dev, uint32_t *flags_dev, void *hip_stream) try {
   if (!ctx || !g || !count_dev || !arcs_dev || !flags_dev) return fail(KAD_EINVAL, "NULL argument");
   if (phase > 255) return fail(KAD_EINVAL, "phase must fit 8 bits");
   if (!ctx->noalloc) return fail(KAD_EDEVICE, "the fixed scratch of this device is not set up");
@@ -1566,12 +1609,14 @@ kad_status kad_hit_counts_noalloc(kad_ctx *ctx, const kad_graph *g, uint64_t see
     done += nb;
   }
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 // ---------------------------------------------------------------- the adaptive run
 
 kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_result *r,
-                   void *hip_stream) {
+                   void *hip_stream) try {
   using clock = std::chrono::steady_clock;
   const auto t0 = clock::now();
   if (!ctx || !g || !p || !r) return fail(KAD_EINVAL, "NULL argument");
@@ -2102,11 +2147,13 @@ kad_status kad_run(kad_ctx *ctx, const kad_graph *g, const kad_params *p, kad_re
   r->seconds_delta = secs(t_pilot, t_delta);
   r->seconds_main = secs(t_delta, t_main);
   return ret;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 // ---------------------------------------------------------------- launch shape
 
-kad_status kad_graph_set_launch(kad_graph *g, uint32_t block, uint32_t small_expansion) {
+kad_status kad_graph_set_launch(kad_graph *g, uint32_t block, uint32_t small_expansion) try {
   if (!g) return fail(KAD_EINVAL, "NULL graph");
   if (block == 0 && small_expansion == 0) {
     g->shape_set = false;
@@ -2119,32 +2166,40 @@ kad_status kad_graph_set_launch(kad_graph *g, uint32_t block, uint32_t small_exp
   g->shape.small_exp = small_expansion;
   g->shape_set = true;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_graph_set_search(kad_graph *g, uint32_t search) {
+kad_status kad_graph_set_search(kad_graph *g, uint32_t search) try {
   if (!g) return fail(KAD_EINVAL, "NULL graph");
   if (search != KAD_SEARCH_BALANCED && search != KAD_SEARCH_FORWARD)
     return fail(KAD_EINVAL, "search must be KAD_SEARCH_BALANCED or KAD_SEARCH_FORWARD");
   g->search = search;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_graph_get_search(const kad_graph *g, uint32_t *search) {
+kad_status kad_graph_get_search(const kad_graph *g, uint32_t *search) try {
   if (!g || !search) return fail(KAD_EINVAL, "NULL argument");
   *search = g->search;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_graph_get_launch(const kad_graph *g, uint32_t *block, uint32_t *small_expansion) {
+kad_status kad_graph_get_launch(const kad_graph *g, uint32_t *block, uint32_t *small_expansion) try {
   if (!g) return fail(KAD_EINVAL, "NULL graph");
   const kad::LaunchShape sh = kad::graph_shape(g);
   if (block) *block = (uint32_t)sh.block;
   if (small_expansion) *small_expansion = sh.small_exp;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *block,
-                        uint32_t *small_expansion, double *seconds) {
+                        uint32_t *small_expansion, double *seconds) try {
   if (!ctx || !g) return fail(KAD_EINVAL, "NULL argument");
   if (samples == 0) samples = DEFAULT_BATCH;
   kad::CtxClaim claim(ctx);
@@ -2194,19 +2249,23 @@ kad_status kad_autotune(kad_ctx *ctx, kad_graph *g, uint32_t samples, uint32_t *
   if (small_expansion) *small_expansion = best.small_exp;
   if (seconds) *seconds = best_s;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 // ---------------------------------------------------------------- timing (bench support)
 
-kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable) {
+kad_status kad_ctx_set_timing(kad_ctx *ctx, int enable) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   ctx->timing = enable != 0;
   ctx->t_launches = ctx->t_samples = ctx->t_arcs = ctx->t_nodes = ctx->t_hits = 0;
   ctx->t_seconds = 0.0;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_ctx_set_wide(kad_ctx *ctx, uint32_t slots, uint64_t limbs) {
+kad_status kad_ctx_set_wide(kad_ctx *ctx, uint32_t slots, uint64_t limbs) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (limbs != 0 && limbs < 4096) return fail(KAD_EINVAL, "a wide-count arena needs 4096 limbs or more");
   kad::CtxClaim claim(ctx);
@@ -2222,19 +2281,23 @@ kad_status kad_ctx_set_wide(kad_ctx *ctx, uint32_t slots, uint64_t limbs) {
   ctx->w_arena_limbs = ctx->w_arena_limbs2 = 0;
   ctx->w_big = false;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_ctx_get_wide(kad_ctx *ctx, uint32_t *slots, uint64_t *limbs, uint32_t *slots2,
-                            uint64_t *limbs2) {
+                            uint64_t *limbs2) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (slots) *slots = ctx->w_slots;
   if (limbs) *limbs = ctx->w_arena_limbs;
   if (slots2) *slots2 = ctx->w_slots2;
   if (limbs2) *limbs2 = ctx->w_arena_limbs2;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_ctx_set_table(kad_ctx *ctx, uint32_t log2_records) {
+kad_status kad_ctx_set_table(kad_ctx *ctx, uint32_t log2_records) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (log2_records > 1 && (log2_records < kad::TABLE_MIN_BITS || log2_records > kad::TABLE_MAX_BITS))
     return fail(KAD_EINVAL, "slot tables hold 2^%u to 2^%u records", kad::TABLE_MIN_BITS,
@@ -2247,36 +2310,44 @@ kad_status kad_ctx_set_table(kad_ctx *ctx, uint32_t log2_records) {
   ctx->slots = 0;  // laid out again (and the wide-count arena after them) on next use
   ctx->slot_n = 0;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_ctx_get_table(kad_ctx *ctx, uint32_t *log2_records, uint32_t *slots,
-                             uint32_t *wide_slots) {
+                             uint32_t *wide_slots) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (log2_records) *log2_records = ctx->slots ? ctx->slot_hbits : 0;
   if (slots) *slots = ctx->slots;
   if (wide_slots) *wide_slots = ctx->slots ? kad::wide_slot_count(ctx) : 0;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_ctx_set_exec(kad_ctx *ctx, uint32_t mode) {
+kad_status kad_ctx_set_exec(kad_ctx *ctx, uint32_t mode) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (mode > KAD_EXEC_PLAIN) return fail(KAD_EINVAL, "unknown launch mode %u", mode);
   kad::CtxClaim claim(ctx);
   if (!claim.ok()) return fail(KAD_EBUSY, "the context is in use (another call or a server)");
   ctx->exec = mode;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
-kad_status kad_ctx_get_exec(kad_ctx *ctx, uint32_t *mode, uint64_t *records, uint64_t *replays) {
+kad_status kad_ctx_get_exec(kad_ctx *ctx, uint32_t *mode, uint64_t *records, uint64_t *replays) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (mode) *mode = ctx->exec;
   if (records) *records = ctx->chain_records.load();
   if (replays) *replays = ctx->chain_replays.load();
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *samples,
-                              double *seconds, uint64_t *arcs, uint64_t *nodes, uint64_t *hits) {
+                              double *seconds, uint64_t *arcs, uint64_t *nodes, uint64_t *hits) try {
   if (!ctx) return fail(KAD_EINVAL, "NULL context");
   if (launches) *launches = ctx->t_launches;
   if (samples) *samples = ctx->t_samples;
@@ -2285,6 +2356,8 @@ kad_status kad_ctx_get_timing(kad_ctx *ctx, uint64_t *launches, uint64_t *sample
   if (nodes) *nodes = ctx->t_nodes;
   if (hits) *hits = ctx->t_hits;
   return KAD_OK;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 }  // extern "C"

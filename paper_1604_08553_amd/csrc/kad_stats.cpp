@@ -11,8 +11,10 @@
 
 #include <algorithm>
 #include <condition_variable>
+#include <exception>
 #include <map>
 #include <mutex>
+#include <system_error>
 #include <thread>
 #include <utility>
 #include <vector>
@@ -26,11 +28,19 @@ unsigned parallel_threads(uint32_t n) {
 
 namespace {
 // Persistent workers for parallel_ranges (starting threads per call cost about as much as
-// the loops they ran).  One job at a time; the calling thread takes share 0.
+// the loops they ran).  One job at a time; the calling thread takes share 0.  A share that
+// throws does not end its thread: run() rethrows the first exception once every share is
+// done.  Threads that cannot be started leave a smaller pool.
 class WorkerPool {
  public:
   explicit WorkerPool(unsigned n) {
-    for (unsigned i = 1; i < n; ++i) th_.emplace_back([this, i] { loop(i); });
+    for (unsigned i = 1; i < n; ++i) {
+      try {
+        th_.emplace_back([this, i] { loop(i); });
+      } catch (const std::system_error &) {
+        break;
+      }
+    }
   }
   ~WorkerPool() {
     {
@@ -52,10 +62,19 @@ class WorkerPool {
       ++gen_;
     }
     cv_.notify_all();
-    job(0);
+    std::exception_ptr err;
+    try {
+      job(0);
+    } catch (...) {
+      err = std::current_exception();
+    }
     std::unique_lock<std::mutex> lk(m_);
     done_.wait(lk, [&] { return left_ == 0; });
     job_ = nullptr;
+    if (!err) err = err_;
+    err_ = nullptr;
+    lk.unlock();
+    if (err) std::rethrow_exception(err);
   }
 
  private:
@@ -71,8 +90,14 @@ class WorkerPool {
         if (i >= nt_) continue;
         job = job_;
       }
-      (*job)(i);
+      std::exception_ptr e;
+      try {
+        (*job)(i);
+      } catch (...) {
+        e = std::current_exception();
+      }
       std::lock_guard<std::mutex> lk(m_);
+      if (e && !err_) err_ = e;
       if (--left_ == 0) done_.notify_one();
     }
   }
@@ -80,6 +105,7 @@ class WorkerPool {
   std::mutex m_, run_m_;
   std::condition_variable cv_, done_;
   const std::function<void(unsigned)> *job_ = nullptr;
+  std::exception_ptr err_;  // the first exception of a worker's share in the current job
   unsigned nt_ = 0, left_ = 0;
   uint64_t gen_ = 0;
   bool quit_ = false;

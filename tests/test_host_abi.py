@@ -2,6 +2,9 @@
 host-side binary64 statistics agree with the oracle (no device calls)."""
 import ctypes
 import os
+import subprocess
+import sys
+import textwrap
 
 import numpy as np
 import pytest
@@ -259,3 +262,47 @@ def test_topk_select_rejects_bad_k(klib):
     for k in (0, 11):
         with pytest.raises(kad.KadError):
             kad.topk_select(count, lo, hi, k)
+
+
+def test_host_memory_exhaustion_is_a_status(klib):
+    """A host allocation that fails inside the library comes back as KAD_ENOMEM: the call
+    returns, the process lives on, and the same call succeeds once memory is there again.
+    A child process caps its own address space just above what it uses, then asks for the
+    vertex-diameter bound of a 3M-node directed cycle (vectors of 12 MB each)."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    code = textwrap.dedent(f"""
+        import resource, sys
+        import numpy as np
+        sys.path.insert(0, {root!r})
+        import paper_1604_08553_amd as kad
+        kad.lib()
+        n = 3_000_000
+
+        class Cycle:
+            pass
+        g = Cycle()
+        g.n, g.directed = n, True
+        g.row = np.arange(n + 1, dtype=np.uint32)
+        g.col = ((np.arange(n) + 1) % n).astype(np.uint32)
+        g.rrow = g.row
+        g.rcol = ((np.arange(n) + n - 1) % n).astype(np.uint32)
+        want = kad.vertex_diameter(g, 0.0)
+
+        def vm_bytes():
+            for line in open("/proc/self/status"):
+                if line.startswith("VmSize:"):
+                    return int(line.split()[1]) * 1024
+        soft, hard = resource.getrlimit(resource.RLIMIT_AS)
+        resource.setrlimit(resource.RLIMIT_AS, (vm_bytes() + (4 << 20), hard))
+        try:
+            kad.vertex_diameter(g, 0.0)
+            print("NO ERROR")
+        except kad.KadError as e:
+            print("STATUS", e.status, e)
+        resource.setrlimit(resource.RLIMIT_AS, (soft, hard))
+        print("AGAIN", kad.vertex_diameter(g, 0.0) == want, want)
+    """)
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=300)
+    assert r.returncode == 0, r.stdout + r.stderr
+    assert "STATUS -2 out of memory" in r.stdout, r.stdout + r.stderr
+    assert "AGAIN True" in r.stdout, r.stdout
