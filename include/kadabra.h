@@ -320,7 +320,9 @@ uint64_t kad_fixed_samples(uint32_t schedule, double epsilon, double delta, uint
 uint64_t kad_default_interval(uint64_t omega);
 
 /* Vertex diameter (largest number of nodes on a shortest path) of a host CSR (same layout
- * rules as kad_graph_create; rrow/rcol required for directed graphs).  Exact by a BFS from
+ * rules as kad_graph_create; rrow/rcol required for directed graphs).  The rows (and
+ * in-rows) are checked as kad_graph_create checks them, KAD_EINVAL if malformed; the
+ * in-rows are not compared with the transpose, nor an undirected graph for symmetry.  Exact by a BFS from
  * every node when n*arcs <= exact_limit; otherwise the bound: heaviest path of the
  * strongly-connected-component DAG where component C weighs ecc_out_C(r) + ecc_in_C(r) + 1,
  * r = C's node of largest in+out degree (lowest id on ties). */

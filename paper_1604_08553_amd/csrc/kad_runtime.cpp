@@ -1245,6 +1245,11 @@ kad_status kad_vertex_diameter(uint32_t n, uint64_t arcs, int directed, const ui
                                uint32_t *exact) try {
   if (!vd || !exact || !row_ptr || (arcs && !col)) return fail(KAD_EINVAL, "NULL argument");
   if (directed && (!rrow_ptr || !rcol)) return fail(KAD_EINVAL, "directed graph needs in-rows");
+  if (n == 0) return fail(KAD_EINVAL, "a graph needs at least one node");
+  if (arcs >= (1ull << 32)) return fail(KAD_EINVAL, "arcs must be below 2^32");
+  kad_status st = check_rows(n, arcs, row_ptr, col, "out-rows");
+  if (!st && directed) st = check_rows(n, arcs, rrow_ptr, rcol, "in-rows");
+  if (st) return st;
   bool ex = false;
   if (kad::vertex_diameter(n, arcs, row_ptr, col, directed ? rrow_ptr : row_ptr,
                            directed ? rcol : col, exact_limit, vd, &ex))

@@ -306,3 +306,43 @@ def test_host_memory_exhaustion_is_a_status(klib):
     assert r.returncode == 0, r.stdout + r.stderr
     assert "STATUS -2 out of memory" in r.stdout, r.stdout + r.stderr
     assert "AGAIN True" in r.stdout, r.stdout
+
+
+def test_vertex_diameter_rejects_malformed_rows(klib):
+    """The host bound checks its CSR as graph registration does (rows on worker threads,
+    the first bad node reported) instead of reading out of bounds: heads out of range,
+    self-loops, rows not ascending, row pointers that decrease or pass the arc count."""
+    g = gg.chung_lu_directed(300_000, 2.5, 2.1, 5.0, 9)  # several worker ranges
+    n, row, col = g.n, g.row.astype(np.int64), g.col.astype(np.int64)
+    deg = np.diff(row)
+    v = int(np.flatnonzero(deg >= 3)[len(np.flatnonzero(deg >= 3)) // 2])
+    e = int(row[v])
+
+    class G:
+        directed = True
+
+    def call(r, c, rr=g.rrow, rc=g.rcol):
+        h = G()
+        h.n, h.row, h.col, h.rrow, h.rcol = n, r, c, rr, rc
+        return kad.vertex_diameter(h, 0.0)
+
+    def rejects(text, *a):
+        with pytest.raises(kad.KadError) as err:
+            call(*a)
+        assert err.value.status == -1 and text in str(err.value), str(err.value)
+
+    assert call(row, col) == kad.vertex_diameter(g, 0.0)
+    c = col.copy(); c[e + 1] = n + 5; c[-1] = n + 9  # two bad heads: the first is reported
+    rejects(f"out-rows: node {v} has out-of-range neighbour {n + 5}", row, c)
+    c = col.copy(); c[e + 1], c[e + 2] = col[e + 2], col[e + 1]
+    rejects(f"out-rows: row {v} is not strictly ascending", row, c)
+    first_head = np.where(deg > 0, col[np.minimum(row[:-1], len(col) - 1)], -1)
+    w = int(np.flatnonzero(first_head > np.arange(n))[0])
+    c = col.copy(); c[row[w]] = w
+    rejects(f"out-rows: self-loop at node {w}", row, c)
+    r = row.copy(); r[v + 1] = r[v] - 1
+    rejects(f"out-rows: row_ptr decreases at node {v}", r, col)
+    r = row.copy(); r[v + 1] = len(col) + 100  # above the arcs, then back down
+    rejects(f"out-rows: row_ptr[{v + 1}] passes the arc count", r, col)
+    rc = g.rcol.astype(np.int64); rc[5] = n
+    rejects("in-rows: node", row, col, g.rrow, rc)
