@@ -1337,13 +1337,15 @@ kad_status kad_topk_select(uint32_t n, uint32_t k, const uint64_t *count, const 
 }
 
 int kad_have_to_stop(uint32_t n, uint32_t mode, uint32_t k, const uint64_t *count, uint64_t tau,
-                     uint64_t omega, double epsilon, const double *L_l, const double *L_u) {
+                     uint64_t omega, double epsilon, const double *L_l, const double *L_u) try {
   if (!n || !count || !L_l || !L_u || tau == 0) return fail(KAD_EINVAL, "bad argument");
   if (mode != KAD_ALL_NODES && mode != KAD_TOPK) return fail(KAD_EINVAL, "bad mode");
   if (mode == KAD_TOPK && (k < 1 || k > n)) return fail(KAD_EINVAL, "k out of range");
   // the same grouped evaluation that kad_run uses at every check
   kad::StopChecker checker(n, mode, k, epsilon, omega, L_l, L_u);
   return checker.check(count, tau) ? 1 : 0;
+} catch (...) {
+  return kad::status_of_exception();
 }
 
 // ---------------------------------------------------------------- sampling primitives
