@@ -515,12 +515,41 @@ void node_outputs_pilot(uint32_t n, const uint64_t *cnt, uint64_t tau, uint64_t 
   });
 }
 
+// Sort x ascending on the worker threads: chunks sorted at once, then merged in pairs.
+static void parallel_sort(std::vector<double> &x) {
+  const size_t N = x.size();
+  const unsigned K = std::min<unsigned>(kad::worker_count(), (unsigned)std::max<size_t>(1, N >> 16));
+  if (K <= 1) {
+    std::sort(x.begin(), x.end());
+    return;
+  }
+  std::vector<size_t> cut(K + 1);
+  for (unsigned c = 0; c <= K; ++c) cut[c] = N * c / K;
+  kad::parallel_tasks(K, [&](unsigned c) { std::sort(x.begin() + cut[c], x.begin() + cut[c + 1]); });
+  std::vector<double> tmp(N);
+  std::vector<double> *src = &x, *dst = &tmp;
+  for (unsigned w = 1; w < K; w *= 2) {  // runs of w chunks merged into runs of 2w
+    const unsigned pairs = (K + 2 * w - 1) / (2 * w);
+    kad::parallel_tasks(pairs, [&](unsigned p) {
+      const size_t a = cut[std::min(K, 2 * w * p)], b = cut[std::min(K, 2 * w * p + w)],
+                   e = cut[std::min(K, 2 * w * (p + 1))];
+      std::merge(src->begin() + a, src->begin() + b, src->begin() + b, src->begin() + e,
+                 dst->begin() + a);
+    });
+    std::swap(src, dst);
+  }
+  if (src != &x) x.swap(tmp);
+}
+
 // The nodes whose rank interval can reach the top k, with their rank intervals
 // (rank_lo = 1 + #{w != v: lo(w) >= hi(v)}, rank_hi = #{w: hi(w) > lo(v)}), ordered by count
 // descending, id ascending.  Without sorting all n bounds: rank_lo(v) <= k needs hi(v) above
 // the (k+1)-th largest lower bound (else the k+1 largest lower bounds all reach hi(v)), and
 // then every lower bound that reaches hi(v) is among the k largest; rank_hi of a selected
-// node counts upper bounds above the selection's smallest lower bound only.
+// node counts upper bounds above the selection's smallest lower bound only.  Loose bounds
+// can select every node, so the output order comes from a counting sort by count when the
+// counts are small (the selection is in id order and the sort is stable), and the rank_hi
+// searches and the sort of the upper bounds run on the worker threads.
 void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, const double *hi,
                  std::vector<uint32_t> &sel, std::vector<uint32_t> &rlo_sel,
                  std::vector<uint32_t> &rhi_sel) {
@@ -548,27 +577,42 @@ void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, 
     }
   }
   if (sel.empty()) return;
+  const uint32_t S = (uint32_t)sel.size();
   double t = lo[sel[0]];
-  for (uint32_t v : sel) t = std::min(t, lo[v]);
+  uint64_t cmax = 0;
+  for (uint32_t v : sel) {
+    t = std::min(t, lo[v]);
+    cmax = std::max(cmax, cnt[v]);
+  }
   std::vector<double> up;
   for (uint32_t v = 0; v < n; ++v)
     if (hi[v] > t) up.push_back(hi[v]);
-  std::sort(up.begin(), up.end());
-  std::vector<uint32_t> idx(sel.size());
-  for (uint32_t q = 0; q < idx.size(); ++q) idx[q] = q;
-  std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
-    const uint32_t x = sel[a], y = sel[b];
-    return cnt[x] != cnt[y] ? cnt[x] > cnt[y] : x < y;
-  });
-  std::vector<uint32_t> sorted(sel.size());
-  rlo_sel.resize(sel.size());
-  rhi_sel.resize(sel.size());
-  for (size_t q = 0; q < idx.size(); ++q) {
-    const uint32_t v = sel[idx[q]];
-    sorted[q] = v;
-    rlo_sel[q] = rl[idx[q]];
-    rhi_sel[q] = (uint32_t)(up.end() - std::upper_bound(up.begin(), up.end(), lo[v]));
+  parallel_sort(up);
+  // idx[q]: the position in sel of the q-th node in output order
+  std::vector<uint32_t> idx(S);
+  if (cmax <= 4ull * S + 1024) {
+    std::vector<uint32_t> pos(cmax + 2, 0);  // bucket cmax - c holds count c
+    for (uint32_t q = 0; q < S; ++q) pos[cmax - cnt[sel[q]] + 1]++;
+    for (uint64_t b = 1; b <= cmax + 1; ++b) pos[b] += pos[b - 1];
+    for (uint32_t q = 0; q < S; ++q) idx[pos[cmax - cnt[sel[q]]]++] = q;
+  } else {
+    for (uint32_t q = 0; q < S; ++q) idx[q] = q;
+    std::sort(idx.begin(), idx.end(), [&](uint32_t a, uint32_t b) {
+      const uint32_t x = sel[a], y = sel[b];
+      return cnt[x] != cnt[y] ? cnt[x] > cnt[y] : x < y;
+    });
   }
+  std::vector<uint32_t> sorted(S);
+  rlo_sel.resize(S);
+  rhi_sel.resize(S);
+  kad::parallel_ranges(S, [&](uint32_t qb, uint32_t qe, unsigned) {
+    for (uint32_t q = qb; q < qe; ++q) {
+      const uint32_t v = sel[idx[q]];
+      sorted[q] = v;
+      rlo_sel[q] = rl[idx[q]];
+      rhi_sel[q] = (uint32_t)(up.end() - std::upper_bound(up.begin(), up.end(), lo[v]));
+    }
+  });
   sel.swap(sorted);
 }
 
