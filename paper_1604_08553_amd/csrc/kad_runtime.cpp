@@ -558,35 +558,77 @@ void topk_select(uint32_t n, uint32_t k, const uint64_t *cnt, const double *lo, 
   rhi_sel.clear();
   if (n == 0) return;
   const uint32_t m = (uint32_t)std::min<uint64_t>(n, (uint64_t)k + 1);
-  std::vector<double> top(lo, lo + n);
+  // The loops over the nodes run in ranges on the worker threads, each range's results
+  // written at its offset in arrays sized by a counting pass (the selection stays in id
+  // order).  parallel_ranges splits n the same way every time, so the passes agree.
+  const unsigned nw = kad::worker_count();
+  // the m largest lower bounds: each range's m largest, then the m largest of those
+  std::vector<std::vector<double>> ptop(nw);
+  kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+    std::vector<double> &pt = ptop[w];
+    pt.assign(lo + vb, lo + ve);
+    if (pt.size() > m) {
+      std::nth_element(pt.begin(), pt.begin() + (m - 1), pt.end(), std::greater<double>());
+      pt.resize(m);
+    }
+  });
+  std::vector<double> top;
+  for (auto &pt : ptop) top.insert(top.end(), pt.begin(), pt.end());
   std::nth_element(top.begin(), top.begin() + (m - 1), top.end(), std::greater<double>());
   top.resize(m);
   std::sort(top.begin(), top.end(), std::greater<double>());  // the m largest, descending
   const bool everyone = (uint64_t)k + 1 > n;  // all lower bounds are in `top`
   const double floor_lo = top[m - 1];
-  std::vector<uint32_t> rl;
-  for (uint32_t v = 0; v < n; ++v) {
-    if (!everyone && !(hi[v] > floor_lo)) continue;
+  // rank_lo(v) - 1 = #{w != v: lo(w) >= hi(v)} when it is below k, else 0
+  auto rank_lo_of = [&](uint32_t v) -> uint32_t {
+    if (!everyone && !(hi[v] > floor_lo)) return 0;
     // #{w: lo(w) >= hi(v)}: the prefix of `top` that is >= hi(v)
     size_t ge = std::upper_bound(top.begin(), top.end(), hi[v], std::greater<double>()) -
                 top.begin();
     if (lo[v] >= hi[v]) --ge;
-    if (1 + ge <= k) {
-      sel.push_back(v);
-      rl.push_back((uint32_t)(1 + ge));
+    return 1 + ge <= k ? (uint32_t)(1 + ge) : 0u;
+  };
+  std::vector<uint32_t> at(nw + 1, 0);
+  kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+    uint32_t c = 0;
+    for (uint32_t v = vb; v < ve; ++v) c += rank_lo_of(v) != 0;
+    at[w + 1] = c;
+  });
+  for (unsigned w = 0; w < nw; ++w) at[w + 1] += at[w];
+  const uint32_t S = at[nw];
+  if (S == 0) return;
+  sel.resize(S);
+  std::vector<uint32_t> rl(S);
+  kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+    uint32_t o = at[w];
+    for (uint32_t v = vb; v < ve; ++v) {
+      const uint32_t r = rank_lo_of(v);
+      if (r) {
+        sel[o] = v;
+        rl[o++] = r;
+      }
     }
-  }
-  if (sel.empty()) return;
-  const uint32_t S = (uint32_t)sel.size();
+  });
   double t = lo[sel[0]];
   uint64_t cmax = 0;
   for (uint32_t v : sel) {
     t = std::min(t, lo[v]);
     cmax = std::max(cmax, cnt[v]);
   }
-  std::vector<double> up;
-  for (uint32_t v = 0; v < n; ++v)
-    if (hi[v] > t) up.push_back(hi[v]);
+  // the upper bounds above t, gathered the same way
+  std::vector<uint32_t> ua(nw + 1, 0);
+  kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+    uint32_t c = 0;
+    for (uint32_t v = vb; v < ve; ++v) c += hi[v] > t;
+    ua[w + 1] = c;
+  });
+  for (unsigned w = 0; w < nw; ++w) ua[w + 1] += ua[w];
+  std::vector<double> up(ua[nw]);
+  kad::parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+    uint32_t o = ua[w];
+    for (uint32_t v = vb; v < ve; ++v)
+      if (hi[v] > t) up[o++] = hi[v];
+  });
   parallel_sort(up);
   // idx[q]: the position in sel of the q-th node in output order
   std::vector<uint32_t> idx(S);
