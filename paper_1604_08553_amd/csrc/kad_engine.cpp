@@ -922,7 +922,9 @@ kad_status Engine::process(Lane &L, Tick &t, Tick &other) {
         const uint32_t n = q->n;
         q->count0.assign(t.h_snap.p + pc.snap, t.h_snap.p + pc.snap + n);
         q->t_pilot = clk::now();
-        q->delta_task = std::async(std::launch::async, [q, n] {
+        // the query's own range of the pinned group staging area, filled by the task
+        uint32_t *stage = group_stage_.p + q->base();
+        q->delta_task = std::async(std::launch::async, [q, n, stage] {
           q->lam_l.assign(n, q->p.epsilon);
           q->lam_u.assign(n, q->p.epsilon);
           q->L_l.resize(n);
@@ -936,6 +938,12 @@ kad_status Engine::process(Lane &L, Tick &t, Tick &other) {
                         &groups);
           q->checker.reset(new StopChecker(n, q->p.mode, q->p.k, q->p.epsilon, q->omega,
                                            q->L_l.data(), q->L_u.data(), std::move(groups)));
+          // group ids as pool ids, staged for the device copy
+          const auto &go = q->checker->group_of();
+          const uint32_t base = (uint32_t)q->base();
+          parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+            for (uint32_t v = vb; v < ve; ++v) stage[v] = go[v] + base;
+          });
         });
         continue;
       }
@@ -1079,13 +1087,11 @@ kad_status Engine::delta_done() {
       continue;
     }
     q->delta_task.get();
-    // group ids into the pool; the group maxima start at 0 with the counters
+    // group ids into the pool (staged by the task); the group maxima start at 0 with the
+    // counters
     hipStream_t rs = lanes_[q->lane].rs;
-    const auto &go = q->checker->group_of();
     const uint32_t n = q->n, base = (uint32_t)q->base();
-    uint32_t *stage = group_stage_.p + base;  // the query's own pinned range
-    for (uint32_t v = 0; v < n; ++v) stage[v] = go[v] + base;
-    HIP_TRY(launch_copy_u32(group_pool_.p + base, stage, n, rs));
+    HIP_TRY(launch_copy_u32(group_pool_.p + base, group_stage_.p + base, n, rs));
     HIP_TRY(launch_zero_u32((uint32_t *)(gmax_pool_.p + base), 2ull * q->checker->groups(), rs));
     q->delta_ready = true;
     q->st = QState::Main;
