@@ -909,17 +909,54 @@ bool StopChecker::check_group_max(const uint64_t *gmax, uint64_t tau, double *wo
   return stop;
 }
 
-bool StopChecker::check(const uint64_t *count, uint64_t tau) {
-  const double T = (double)tau, W = (double)omega_;
+// gmax_[g], seen_[g]: the largest count in group g and whether g has a node, over the
+// nodes (those not marked in in_top_ when skip_top).  Ranges of nodes run on the worker
+// threads and their maxima are merged (the result does not depend on the order); many
+// groups or few nodes take one pass.
+void StopChecker::group_maxima(const uint64_t *count, bool skip_top) {
+  const size_t G = gmax_.size();
   std::fill(gmax_.begin(), gmax_.end(), 0);
-  std::vector<uint8_t> &seen = seen_;
-  seen.assign(gmax_.size(), 0);
-  if (mode_ == 0) {
+  seen_.assign(G, 0);
+  if (G > 4096 || parallel_threads(n_) == 1) {
     for (uint32_t v = 0; v < n_; ++v) {
+      if (skip_top && in_top_[v]) continue;
       const uint32_t g = group_[v];
-      seen[g] = 1;
+      seen_[g] = 1;
       gmax_[g] = std::max(gmax_[g], count[v]);
     }
+    return;
+  }
+  const unsigned nw = workers().size();
+  pgmax_.resize(nw);
+  pseen_.resize(nw);
+  pused_.assign(nw, 0);
+  parallel_ranges(n_, [&](uint32_t vb, uint32_t ve, unsigned w) {
+    std::vector<uint64_t> &gm = pgmax_[w];
+    std::vector<uint8_t> &sn = pseen_[w];
+    gm.assign(G, 0);
+    sn.assign(G, 0);
+    pused_[w] = 1;
+    for (uint32_t v = vb; v < ve; ++v) {
+      if (skip_top && in_top_[v]) continue;
+      const uint32_t g = group_[v];
+      sn[g] = 1;
+      gm[g] = std::max(gm[g], count[v]);
+    }
+  });
+  for (unsigned w = 0; w < nw; ++w) {
+    if (!pused_[w]) continue;
+    for (size_t g = 0; g < G; ++g) {
+      seen_[g] |= pseen_[w][g];
+      gmax_[g] = std::max(gmax_[g], pgmax_[w][g]);
+    }
+  }
+}
+
+bool StopChecker::check(const uint64_t *count, uint64_t tau) {
+  const double T = (double)tau, W = (double)omega_;
+  std::vector<uint8_t> &seen = seen_;
+  if (mode_ == 0) {
+    group_maxima(count, false);
     for (size_t g = 0; g < gmax_.size(); ++g) {
       if (!seen[g]) continue;
       const double bt = (double)gmax_[g] / T;
@@ -933,9 +970,23 @@ bool StopChecker::check(const uint64_t *count, uint64_t tau) {
   const uint32_t head = std::min(n_, k_ + 1);
   // Counts never decrease between checks, so the k+1 largest now all have a count of
   // at least the (k+1)-th largest of the previous check: select among those only.
-  order_.clear();
-  for (uint32_t v = 0; v < n_; ++v)
-    if (count[v] >= head_floor_) order_.push_back(v);
+  // (the candidates in id order: a counting pass and a writing pass over ranges of nodes)
+  {
+    const unsigned nw = workers().size();
+    std::vector<uint32_t> at(nw + 1, 0);
+    parallel_ranges(n_, [&](uint32_t vb, uint32_t ve, unsigned w) {
+      uint32_t c = 0;
+      for (uint32_t v = vb; v < ve; ++v) c += count[v] >= head_floor_;
+      at[w + 1] = c;
+    });
+    for (unsigned w = 0; w < nw; ++w) at[w + 1] += at[w];
+    order_.resize(at[nw]);
+    parallel_ranges(n_, [&](uint32_t vb, uint32_t ve, unsigned w) {
+      uint32_t o = at[w];
+      for (uint32_t v = vb; v < ve; ++v)
+        if (count[v] >= head_floor_) order_[o++] = v;
+    });
+  }
   if (order_.size() < head) {  // cannot happen for non-decreasing counts; select among all
     order_.resize(n_);
     for (uint32_t v = 0; v < n_; ++v) order_[v] = v;
@@ -959,12 +1010,7 @@ bool StopChecker::check(const uint64_t *count, uint64_t tau) {
   const uint32_t vk = order_[k_ - 1];
   const double kth_low = bt(vk) - fv(vk);
   for (uint32_t i = 0; i < k_; ++i) in_top_[order_[i]] = 1;
-  for (uint32_t v = 0; v < n_; ++v) {
-    if (in_top_[v]) continue;
-    const uint32_t g = group_[v];
-    seen[g] = 1;
-    gmax_[g] = std::max(gmax_[g], count[v]);
-  }
+  group_maxima(count, true);
   for (uint32_t i = 0; i < k_; ++i) in_top_[order_[i]] = 0;
   for (size_t g = 0; g < gmax_.size(); ++g) {
     if (!seen[g]) continue;

@@ -84,6 +84,11 @@ class StopChecker {
   std::vector<uint32_t> order_;      // scratch for the top-k order
   std::vector<uint8_t> in_top_, seen_;
   uint64_t head_floor_ = 0;          // (k+1)-th largest count at the last top-k check
+  // per worker range: largest count and presence per group, and whether the range ran
+  std::vector<std::vector<uint64_t>> pgmax_;
+  std::vector<std::vector<uint8_t>> pseen_;
+  std::vector<uint8_t> pused_;
+  void group_maxima(const uint64_t *count, bool skip_top);
 };
 
 // Rank intervals of the top-k output: rank_lo = 1 + #{w != v: lower(w) >= upper(v)},

@@ -206,6 +206,34 @@ def test_grouped_stop_check_equals_plain_oracle(klib, oracle_lib):
     assert decisions > 0
 
 
+def test_grouped_stop_check_equals_plain_oracle_large(klib, oracle_lib):
+    """The same at 200,000 nodes, where the check's node loops run in ranges on the
+    worker threads (candidates gathered in id order, group maxima merged)."""
+    rng = np.random.default_rng(4)
+    n, alpha, om = 200_000, 2000, 300_000
+    decisions = 0
+    for trial in range(2):
+        c0 = _pilot(n, alpha, 200 + trial)
+        lam = 0.004 if trial == 0 else 0.002
+        for mode, k in (("all", 0), ("topk", 5)):
+            if mode == "topk":
+                ll, lu = oracle_lib.topk_lambdas(c0, k, alpha, lam)
+            else:
+                ll = lu = np.full(n, lam)
+            Ll, Lu, _ = oracle_lib.compute_delta(c0, alpha, om, ll, lu, 0.1)
+            p = (c0.astype(np.float64) + 0.5) / (alpha + 1)
+            for tau in np.unique(np.geomspace(5000, om, 6).astype(np.int64)):
+                cnt = rng.binomial(int(tau), np.minimum(p, 1.0)).astype(np.uint64)
+                a = kad.have_to_stop(cnt, int(tau), om, lam, Ll, Lu, mode=mode, k=k)
+                if mode == "topk":
+                    b = oracle_lib.stop_topk(cnt, k, int(tau), om, lam, Ll, Lu)
+                else:
+                    b = oracle_lib.stop_all(cnt, int(tau), om, lam, Ll, Lu)
+                assert a == b, (trial, mode, k, tau)
+                decisions += a
+    assert decisions > 0
+
+
 def test_fixed_schedule_sample_counts(klib):
     """RK: the printed RK iteration counts of the appendix tables (delta = 0.1) are
     c/eps^2 (floor(log2(VD-2)) + 1 + ln(1/delta)) for some vertex diameter; Hoeffding:
