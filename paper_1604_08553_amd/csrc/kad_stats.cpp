@@ -994,6 +994,24 @@ bool StopChecker::check(const uint64_t *count, uint64_t tau) {
   auto cmp = [count](uint32_t a, uint32_t b) {
     return count[a] != count[b] ? count[a] > count[b] : a < b;
   };
+  if (order_.size() > 65536 && order_.size() > 8ull * head) {
+    // many candidates (the first check): the head largest of each range of them on the
+    // worker threads, then of those -- the order is total, so the set is the same
+    const uint32_t C = (uint32_t)order_.size();
+    const unsigned nw = workers().size();
+    std::vector<uint32_t> rb(nw, C), kept(nw, 0);
+    parallel_ranges(C, [&](uint32_t b, uint32_t e, unsigned w) {
+      rb[w] = b;
+      kept[w] = std::min(head, e - b);
+      if (e - b > head)
+        std::nth_element(order_.begin() + b, order_.begin() + b + (head - 1),
+                         order_.begin() + e, cmp);
+    });
+    uint32_t o = 0;
+    for (unsigned w = 0; w < nw; ++w)
+      for (uint32_t i = 0; i < kept[w]; ++i) order_[o++] = order_[rb[w] + i];
+    order_.resize(o);
+  }
   std::nth_element(order_.begin(), order_.begin() + (head - 1), order_.end(), cmp);
   std::sort(order_.begin(), order_.begin() + head, cmp);
   head_floor_ = count[order_[head - 1]];

@@ -208,14 +208,16 @@ def test_grouped_stop_check_equals_plain_oracle(klib, oracle_lib):
 
 def test_grouped_stop_check_equals_plain_oracle_large(klib, oracle_lib):
     """The same at 200,000 nodes, where the check's node loops run in ranges on the
-    worker threads (candidates gathered in id order, group maxima merged)."""
+    worker threads (candidates gathered in id order, group maxima merged, the first
+    check's k+1 largest chosen per range), with k small and large (many tied counts at
+    the boundary of the k+1 largest)."""
     rng = np.random.default_rng(4)
     n, alpha, om = 200_000, 2000, 300_000
     decisions = 0
     for trial in range(2):
         c0 = _pilot(n, alpha, 200 + trial)
         lam = 0.004 if trial == 0 else 0.002
-        for mode, k in (("all", 0), ("topk", 5)):
+        for mode, k in (("all", 0), ("topk", 5), ("topk", 60)):
             if mode == "topk":
                 ll, lu = oracle_lib.topk_lambdas(c0, k, alpha, lam)
             else:
@@ -232,6 +234,27 @@ def test_grouped_stop_check_equals_plain_oracle_large(klib, oracle_lib):
                 assert a == b, (trial, mode, k, tau)
                 decisions += a
     assert decisions > 0
+    # five heavy nodes far apart: the top-k rule stops on their separation while other
+    # nodes are still unconverged, so the decision rests on which nodes form the top k
+    om = 3_000_000
+    separated = 0
+    for seed in range(2):
+        rng = np.random.default_rng(50 + seed)
+        c0 = _pilot(n, alpha, 300 + seed)
+        heavy = rng.choice(n, 5, replace=False)
+        ph = np.array([0.30, 0.24, 0.18, 0.13, 0.09])
+        c0[heavy] = (ph * alpha).astype(np.uint64)
+        lam = 0.005
+        ll, lu = oracle_lib.topk_lambdas(c0, 5, alpha, lam)
+        Ll, Lu, _ = oracle_lib.compute_delta(c0, alpha, om, ll, lu, 0.1)
+        p = (c0.astype(np.float64) + 0.5) / (alpha + 1)
+        p[heavy] = ph
+        for tau in np.unique(np.geomspace(2000, om, 12).astype(np.int64)):
+            cnt = rng.binomial(int(tau), np.minimum(p, 1.0)).astype(np.uint64)
+            a = kad.have_to_stop(cnt, int(tau), om, lam, Ll, Lu, mode="topk", k=5)
+            assert a == oracle_lib.stop_topk(cnt, 5, int(tau), om, lam, Ll, Lu), (seed, tau)
+            separated += a and not oracle_lib.stop_all(cnt, int(tau), om, lam, Ll, Lu)
+    assert separated > 0
 
 
 def test_fixed_schedule_sample_counts(klib):
