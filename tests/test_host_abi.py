@@ -308,6 +308,28 @@ def test_topk_select_matches_oracle_rank_intervals(klib, oracle_lib):
                 assert a_hi.tolist() == [int(rhi[v]) for v in want], (seed, n, k)
 
 
+def test_topk_select_large_against_definition(klib):
+    """At 300,000 nodes, where the selection, the rank searches and the sort of the upper
+    bounds run on the worker threads: against the definition written with numpy sorts
+    (rank_lo = 1 + #{w != v: lo(w) >= hi(v)}, rank_hi = #{w: hi(w) > lo(v)}), including
+    bounds loose enough that every node is selected."""
+    n = 300_000
+    for seed, (loose, k) in enumerate(((False, 10), (False, 100), (True, 100))):
+        count, lo, hi = _bounds(n, 40 + seed)
+        if loose:  # every interval reaches the top k
+            lo, hi = lo - 1.0, hi + 1.0
+        lo_sorted, hi_sorted = np.sort(lo), np.sort(hi)
+        rlo = 1 + (n - np.searchsorted(lo_sorted, hi, side="left")) - (lo >= hi)
+        rhi = n - np.searchsorted(hi_sorted, lo, side="right")
+        sel = np.nonzero(rlo <= k)[0]
+        want = sel[np.lexsort((sel, -count[sel].astype(np.int64)))]
+        node, a_lo, a_hi = kad.topk_select(count, lo, hi, k)
+        assert np.array_equal(node, want), (seed, len(node), len(want))
+        assert np.array_equal(a_lo, rlo[want]) and np.array_equal(a_hi, rhi[want]), seed
+        if loose:
+            assert len(node) == n
+
+
 def test_topk_select_rejects_bad_k(klib):
     count, lo, hi = _bounds(10, 0)
     for k in (0, 11):
