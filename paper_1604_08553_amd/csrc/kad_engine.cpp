@@ -1225,7 +1225,7 @@ struct kad_server {
 
 namespace {
 
-void server_loop(kad_server *sv) {
+static void server_rounds(kad_server *sv) {
   (void)hipSetDevice(sv->ctx->device);
   for (;;) {
     {
@@ -1267,6 +1267,21 @@ void server_loop(kad_server *sv) {
       sv->cv_done.notify_all();
     }
     if (st) break;  // device error: every unfinished query reports it
+  }
+}
+
+// The server's thread: rounds until destroyed.  A host failure outside the engine's steps
+// (memory, in the server's own bookkeeping) stops it like a device error does: every
+// unfinished query reports it, and no exception ends the process.
+void server_loop(kad_server *sv) {
+  try {
+    server_rounds(sv);
+  } catch (...) {
+    const kad_status st = kad::status_of_exception();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->fatal = st;
+    sv->fatal_msg = kad_last_error();
+    sv->cv_done.notify_all();
   }
 }
 
