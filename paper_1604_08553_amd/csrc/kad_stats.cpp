@@ -505,18 +505,15 @@ int vertex_diameter(uint32_t n, uint64_t arcs, const uint32_t *row, const uint32
                     bool *exact) {
   if (n == 0 || !row || !rrow || (arcs && (!col || !rcol))) return -1;
   if ((double)n * (double)arcs <= exact_limit) {
-    // exact: the largest BFS eccentricity over all sources, plus one node
-    unsigned nt = std::max(1u, std::min(16u, std::thread::hardware_concurrency()));
+    // exact: the largest BFS eccentricity over all sources, plus one node (sources dealt
+    // out over the worker threads)
+    const unsigned nt = worker_count();
     std::vector<uint32_t> best(nt, 0);
-    std::vector<std::thread> pool;
-    for (unsigned w = 0; w < nt; ++w) {
-      pool.emplace_back([&, w]() {
-        std::vector<uint32_t> dist(n, UINT32_MAX), queue(n);
-        for (uint32_t s = w; s < n; s += nt)
-          best[w] = std::max(best[w], bfs_farthest(row, col, s, nullptr, 0, dist, queue));
-      });
-    }
-    for (auto &t : pool) t.join();
+    parallel_tasks(nt, [&](unsigned w) {
+      std::vector<uint32_t> dist(n, UINT32_MAX), queue(n);
+      for (uint32_t s = w; s < n; s += nt)
+        best[w] = std::max(best[w], bfs_farthest(row, col, s, nullptr, 0, dist, queue));
+    });
     *vd = *std::max_element(best.begin(), best.end()) + 1;
     *exact = true;
     return 0;
