@@ -812,35 +812,72 @@ void estimate_order(uint32_t n, const uint64_t *count, std::vector<uint32_t> &or
   });
 }
 double clamp_unit(double x, double eps) { return std::min(1.0, std::max(eps, x)); }
+
+// The first m nodes in the order of count descending, id ascending.  For small m each
+// range of nodes on the worker threads keeps its m first and the m first of those are
+// taken (the order is total, so they are the same nodes); otherwise the full order.
+void head_by_count(uint32_t n, const uint64_t *count, uint32_t m, std::vector<uint32_t> &head) {
+  auto cmp = [count](uint32_t a, uint32_t b) {
+    return count[a] != count[b] ? count[a] > count[b] : a < b;
+  };
+  if ((uint64_t)m * 8 > n || parallel_threads(n) == 1) {
+    estimate_order(n, count, head);
+    head.resize(m);
+    return;
+  }
+  std::vector<std::vector<uint32_t>> part(workers().size());
+  parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+    std::vector<uint32_t> &p = part[w];
+    p.resize(ve - vb);
+    for (uint32_t v = vb; v < ve; ++v) p[v - vb] = v;
+    if (p.size() > m) {
+      std::nth_element(p.begin(), p.begin() + (m - 1), p.end(), cmp);
+      p.resize(m);
+    }
+  });
+  head.clear();
+  for (auto &p : part) head.insert(head.end(), p.begin(), p.end());
+  std::nth_element(head.begin(), head.begin() + (m - 1), head.end(), cmp);
+  head.resize(m);
+  std::sort(head.begin(), head.end(), cmp);
+}
 }  // namespace
 
+// Section 5's half-widths: the k nodes of largest pilot count get theirs from the gaps to
+// their neighbours in that order (eps where two of the first k+1 lie within 2 eps); every
+// other node has lambda_L = 1 and lambda_U from the gap below the k-th node's lower end.
+// Only the first k+1 positions of the order matter, so only they are found; the others'
+// values depend on their own count alone and are written on the worker threads.
 void topk_lambdas(uint32_t n, uint32_t k, const uint64_t *count0, uint64_t alpha, double eps,
                   double *lam_l, double *lam_u) {
-  std::vector<uint32_t> ord;
-  estimate_order(n, count0, ord);
+  const uint32_t m = (uint32_t)std::min<uint64_t>(n, (uint64_t)k + 1);
+  std::vector<uint32_t> ord;  // positions 0..m-1 of the order
+  head_by_count(n, count0, m, ord);
   const double A = (double)alpha;
   auto b0 = [&](uint32_t pos) { return (double)count0[ord[pos]] / A; };
-  std::vector<uint8_t> tie(n, 0);
+  std::vector<uint8_t> tie(m, 0);
   for (uint32_t i = 0; i < k; ++i)
     if (i + 1 < n && b0(i) - b0(i + 1) < 2.0 * eps) tie[i] = tie[i + 1] = 1;
+  std::vector<double> top_l(k), top_u(k);
   for (uint32_t i = 0; i < k; ++i) {
-    const uint32_t v = ord[i];
     double up = i == 0 ? 1.0 : (b0(i - 1) - b0(i)) / 2.0;
     double dn = i + 1 < n ? (b0(i) - b0(i + 1)) / 2.0 : 1.0;
     if (tie[i]) up = dn = eps;
-    lam_u[v] = clamp_unit(up, eps);
-    lam_l[v] = clamp_unit(dn, eps);
+    top_u[i] = clamp_unit(up, eps);
+    top_l[i] = clamp_unit(dn, eps);
   }
-  const double kth_low = b0(k - 1) - lam_l[ord[k - 1]];
-  for (uint32_t i = k; i < n; ++i) {
-    const uint32_t v = ord[i];
-    if (tie[i]) {
-      lam_l[v] = lam_u[v] = eps;
-    } else {
+  const double kth_low = b0(k - 1) - top_l[k - 1];
+  parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+    for (uint32_t v = vb; v < ve; ++v) {
       lam_l[v] = 1.0;
-      lam_u[v] = clamp_unit(kth_low - b0(i), eps);
+      lam_u[v] = clamp_unit(kth_low - (double)count0[v] / A, eps);
     }
+  });
+  for (uint32_t i = 0; i < k; ++i) {
+    lam_l[ord[i]] = top_l[i];
+    lam_u[ord[i]] = top_u[i];
   }
+  if (k < n && tie[k]) lam_l[ord[k]] = lam_u[ord[k]] = eps;
 }
 
 // ------------------------------------------------------------------ stopping conditions

@@ -178,6 +178,20 @@ def test_topk_lambdas_match_oracle(klib, oracle_lib):
                 assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (seed, k, lam)
 
 
+def test_topk_lambdas_match_oracle_large(klib, oracle_lib):
+    """At 200,000 nodes the library finds only the k+1 largest pilot counts (per range on
+    the worker threads) and writes every other node's half-widths from its own count; the
+    oracle orders all nodes.  Small pilot counts tie at the boundary of the k+1 largest."""
+    n, alpha = 200_000, 300
+    for seed in range(2):
+        c0 = _pilot(n, alpha, 70 + seed, zero_frac=0.3)
+        for k in (1, 10, 100, 30_000):  # the last takes the full order
+            for lam in (0.0005, 0.002, 0.05):
+                a = kad.topk_lambdas(c0, k, alpha, lam)
+                b = oracle_lib.topk_lambdas(c0, k, alpha, lam)
+                assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]), (seed, k, lam)
+
+
 def test_grouped_stop_check_equals_plain_oracle(klib, oracle_lib):
     """The library groups nodes by (L_l, L_u) and tests only each group's largest count;
     the oracle tests every node.  Sweep tau across the decision boundary."""
