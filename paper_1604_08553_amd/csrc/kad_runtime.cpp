@@ -1015,7 +1015,7 @@ kad_status replay_sampling(kad_ctx *ctx, const kad_graph *g, int set, uint64_t s
   if (st) return st;
   // the set's previous replay read this descriptor before its mirrors landed, and the
   // host has waited for those
-  *hb = kad::BatchDesc{seed, first, count, phase, 0u, 0u};
+  *hb = kad::BatchDesc{seed, first, count, phase, 0u, 0u, 0u, 0u};  // stride 0: the launch's own
   HIP_TRY(hipGraphLaunch(ctx->bgraph[set].exec, stream));
   ctx->bgraph[set].replays++;
   ctx->chain_replays++;
@@ -1049,7 +1049,7 @@ kad_status replay_reduce(kad_ctx *ctx, int set, const uint32_t *rpath, const uin
   });
   if (st) return st;
   // the previous replay of this chain is complete: the host waited for its snapshots
-  *hb = kad::BatchDesc{0, 0, count, 0u, (count + per_iv - 1) / per_iv, 0u};
+  *hb = kad::BatchDesc{0, 0, count, 0u, (count + per_iv - 1) / per_iv, 0u, 0u, 0u};
   HIP_TRY(hipGraphLaunch(ctx->bgraph[2 + set].exec, rs));
   ctx->bgraph[2 + set].replays++;
   ctx->chain_replays++;
