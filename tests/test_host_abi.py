@@ -149,6 +149,22 @@ def test_compute_delta_matches_oracle(klib, oracle_lib):
         assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
 
 
+def test_compute_delta_matches_oracle_large(klib, oracle_lib):
+    """At 300,000 nodes, where the uniform path builds its count histogram and writes the
+    per-node values over ranges on the worker threads: bit for bit with the oracle, for
+    uniform half-widths and for the top-k ones (the per-node path)."""
+    n, alpha, om = 300_000, 2999, 299_790
+    c0 = _pilot(n, alpha, 11)
+    lam = np.full(n, 0.004)
+    a = kad.compute_delta(c0, alpha, om, lam, lam, 0.1, 0.001)
+    b = oracle_lib.compute_delta(c0, alpha, om, lam, lam, 0.1, 0.001)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+    ll, lu = oracle_lib.topk_lambdas(c0, 20, alpha, 0.002)
+    a = kad.compute_delta(c0, alpha, om, ll, lu, 0.1, 0.001)
+    b = oracle_lib.compute_delta(c0, alpha, om, ll, lu, 0.1, 0.001)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1]) and a[2] == b[2]
+
+
 def test_compute_delta_hist_matches_oracle(klib, oracle_lib):
     """The all-nodes run solves computeDelta from the histogram of the pilot counts; the
     L value of each node (through its count's group) and C equal the oracle's per-node
