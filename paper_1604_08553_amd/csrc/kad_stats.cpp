@@ -13,6 +13,7 @@
 #include <condition_variable>
 #include <exception>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <system_error>
 #include <thread>
@@ -673,6 +674,7 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
   const bool uniform = std::all_of(t_uniform.begin(), t_uniform.end(), [](uint8_t x) { return x; });
   const uint64_t cmax = *std::max_element(t_cmax.begin(), t_cmax.end());
   std::vector<uint32_t> il, iu;        // general path: per-node value indices
+  std::vector<std::pair<uint32_t, uint32_t>> gpairs_out;  // general path: group -> (il, iu)
   std::vector<uint32_t> ca, cb, cgrp;  // uniform path: per-count value indices and group
   if (uniform && cmax < (1u << 24)) {
     std::vector<std::vector<uint32_t>> th(nt, std::vector<uint32_t>(cmax + 1, 0));
@@ -689,8 +691,11 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
       groups->L_u.assign(ngrp, 0.0);
     }
   } else {
-    // most nodes repeat an earlier (count0, lambda_l, lambda_u): a direct-mapped memo
-    // of that triple skips recomputing the same two constants
+    // Most nodes repeat an earlier (count0, lambda_l, lambda_u): a direct-mapped memo of
+    // that triple skips recomputing the same two constants.  Ranges of nodes on the worker
+    // threads number their distinct constants (and groups) in order of first appearance;
+    // merged in range order, the numbering is the one a single pass over the nodes gives,
+    // and the multiplicities are whole counts.
     il.resize(n);
     iu.resize(n);
     struct Memo {
@@ -698,46 +703,103 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
       uint32_t a, b;
       bool used;
     };
-    std::vector<Memo> memo(4096, Memo{0, 0, 0, 0, 0, false});
-    for (uint32_t v = 0; v < n; ++v) {
-      uint64_t bl, bu;
-      memcpy(&bl, &lam_l[v], 8);
-      memcpy(&bu, &lam_u[v], 8);
-      const uint64_t h = (count0[v] * 0x9E3779B97F4A7C15ULL) ^ (bl * 0xC2B2AE3D27D4EB4FULL) ^
-                         (bu * 0x165667B19E3779F9ULL);
-      Memo &m = memo[(h >> 40) & 4095];
-      if (!(m.used && m.c0 == count0[v] && m.ll == bl && m.lu == bu)) {
-        const double b0 = (double)count0[v] / (double)alpha;
-        const double cl = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
-        const double cu = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
-        m = Memo{count0[v], bl, bu, S.index.find_or_add(cl), S.index.find_or_add(cu), true};
-        if (S.mult.size() < S.index.values.size()) S.mult.resize(S.index.values.size(), 0.0);
+    const unsigned nw = workers().size();
+    std::vector<std::unique_ptr<ValueIndex>> loc(nw);
+    std::vector<std::vector<uint64_t>> lmult(nw);
+    std::vector<uint8_t> ran(nw, 0);
+    parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+      ran[w] = 1;
+      loc[w].reset(new ValueIndex(1024));
+      ValueIndex &X = *loc[w];
+      std::vector<uint64_t> &lm = lmult[w];
+      lm.clear();
+      std::vector<Memo> memo(4096, Memo{0, 0, 0, 0, 0, false});
+      for (uint32_t v = vb; v < ve; ++v) {
+        uint64_t bl, bu;
+        memcpy(&bl, &lam_l[v], 8);
+        memcpy(&bu, &lam_u[v], 8);
+        const uint64_t h = (count0[v] * 0x9E3779B97F4A7C15ULL) ^ (bl * 0xC2B2AE3D27D4EB4FULL) ^
+                           (bu * 0x165667B19E3779F9ULL);
+        Memo &m = memo[(h >> 40) & 4095];
+        if (!(m.used && m.c0 == count0[v] && m.ll == bl && m.lu == bu)) {
+          const double b0 = (double)count0[v] / (double)alpha;
+          const double cl = 2.0 * b0 * (double)omega / (lam_l[v] * lam_l[v]);
+          const double cu = 2.0 * b0 * (double)omega / (lam_u[v] * lam_u[v]);
+          m = Memo{count0[v], bl, bu, X.find_or_add(cl), X.find_or_add(cu), true};
+          if (lm.size() < X.values.size()) lm.resize(X.values.size(), 0);
+        }
+        il[v] = m.a;
+        iu[v] = m.b;
+        lm[m.a]++;
+        lm[m.b]++;
       }
-      il[v] = m.a;
-      iu[v] = m.b;
-      S.mult[m.a] += 1.0;
-      S.mult[m.b] += 1.0;
+    });
+    std::vector<std::vector<uint32_t>> remap(nw);
+    for (unsigned w = 0; w < nw; ++w) {
+      if (!ran[w]) continue;
+      const std::vector<double> &vals = loc[w]->values;
+      remap[w].resize(vals.size());
+      for (size_t q = 0; q < vals.size(); ++q) {
+        const uint32_t g = S.index.find_or_add(vals[q]);
+        if (S.mult.size() < S.index.values.size()) S.mult.resize(S.index.values.size(), 0.0);
+        S.mult[g] += (double)lmult[w][q];
+        remap[w][q] = g;
+      }
     }
+    parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+      const std::vector<uint32_t> &r = remap[w];
+      for (uint32_t v = vb; v < ve; ++v) {
+        il[v] = r[il[v]];
+        iu[v] = r[iu[v]];
+      }
+    });
     if (groups) {  // group = distinct (il, iu) pair, numbered by first appearance
-      std::map<std::pair<uint32_t, uint32_t>, uint32_t> ids;
       struct GMemo {  // most nodes repeat an earlier pair: a direct-mapped memo before the map
         uint32_t a, b, g;
         bool used;
       };
-      std::vector<GMemo> gm(4096, GMemo{0, 0, 0, false});
+      std::vector<std::vector<std::pair<uint32_t, uint32_t>>> lpairs(nw);
       groups->of.resize(n);
-      for (uint32_t v = 0; v < n; ++v) {
-        GMemo &m = gm[((il[v] * 0x9E3779B1u) ^ (iu[v] * 0x85EBCA6Bu)) >> 20];
-        if (!(m.used && m.a == il[v] && m.b == iu[v])) {
-          const auto key = std::make_pair(il[v], iu[v]);
-          auto it = ids.find(key);
-          if (it == ids.end()) it = ids.emplace(key, (uint32_t)ids.size()).first;
-          m = GMemo{il[v], iu[v], it->second, true};
+      parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+        std::map<std::pair<uint32_t, uint32_t>, uint32_t> ids;
+        std::vector<std::pair<uint32_t, uint32_t>> &lp = lpairs[w];
+        lp.clear();
+        std::vector<GMemo> gm(4096, GMemo{0, 0, 0, false});
+        for (uint32_t v = vb; v < ve; ++v) {
+          GMemo &m = gm[((il[v] * 0x9E3779B1u) ^ (iu[v] * 0x85EBCA6Bu)) >> 20];
+          if (!(m.used && m.a == il[v] && m.b == iu[v])) {
+            const auto key = std::make_pair(il[v], iu[v]);
+            auto it = ids.find(key);
+            if (it == ids.end()) {
+              it = ids.emplace(key, (uint32_t)lp.size()).first;
+              lp.push_back(key);
+            }
+            m = GMemo{il[v], iu[v], it->second, true};
+          }
+          groups->of[v] = m.g;
         }
-        groups->of[v] = m.g;
+      });
+      std::map<std::pair<uint32_t, uint32_t>, uint32_t> gids;
+      std::vector<std::pair<uint32_t, uint32_t>> gpairs;  // group id -> (il, iu)
+      std::vector<std::vector<uint32_t>> gremap(nw);
+      for (unsigned w = 0; w < nw; ++w) {
+        if (!ran[w]) continue;
+        for (const auto &key : lpairs[w]) {
+          auto it = gids.find(key);
+          if (it == gids.end()) {
+            it = gids.emplace(key, (uint32_t)gpairs.size()).first;
+            gpairs.push_back(key);
+          }
+          gremap[w].push_back(it->second);
+        }
       }
-      groups->L_l.assign(ids.size(), 0.0);
-      groups->L_u.assign(ids.size(), 0.0);
+      parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned w) {
+        const std::vector<uint32_t> &r = gremap[w];
+        for (uint32_t v = vb; v < ve; ++v) groups->of[v] = r[groups->of[v]];
+      });
+      groups->L_l.assign(gpairs.size(), 0.0);
+      groups->L_u.assign(gpairs.size(), 0.0);
+      gpairs_out = std::move(gpairs);
     }
   }
   std::vector<double> Lq;
@@ -759,14 +821,16 @@ void compute_delta(uint32_t n, const uint64_t *count0, uint64_t alpha, uint64_t 
       }
     });
   } else {
-    for (uint32_t v = 0; v < n; ++v) {
-      L_l[v] = Lq[il[v]];
-      L_u[v] = Lq[iu[v]];
-    }
-    if (groups)
-      for (uint32_t v = 0; v < n; ++v) {
-        groups->L_l[groups->of[v]] = L_l[v];
-        groups->L_u[groups->of[v]] = L_u[v];
+    parallel_ranges(n, [&](uint32_t vb, uint32_t ve, unsigned) {
+      for (uint32_t v = vb; v < ve; ++v) {
+        L_l[v] = Lq[il[v]];
+        L_u[v] = Lq[iu[v]];
+      }
+    });
+    if (groups)  // every node of a group has its pair's values
+      for (size_t g = 0; g < gpairs_out.size(); ++g) {
+        groups->L_l[g] = Lq[gpairs_out[g].first];
+        groups->L_u[g] = Lq[gpairs_out[g].second];
       }
   }
 }
